@@ -1,0 +1,290 @@
+/*
+ * caddelag.h - C ABI of the MI355X (gfx950) commute-time anomaly-detection
+ * library (libcaddelag.so).
+ *
+ * The calls follow the problem statements of the paper's algorithms:
+ *   cdl_build_graph      - the fully connected Gaussian-kernel graph of one
+ *                          snapshot (Section "Climate Data"; Background:
+ *                          symmetric A, no self-edges, volume V_G).
+ *   cdl_graph_from_weights - the same, for a caller-supplied weight matrix.
+ *   cdl_build_chain      - ChainProduct of Algorithm 2: the normalised
+ *                          matrix S = D^{-1/2} A D^{-1/2} and its repeated
+ *                          squares (eq. inverse-chain).
+ *   cdl_solve_embedding  - CommuteTimeEmbedding of Algorithm 3: k random
+ *                          right-hand sides y = B^T W^{1/2} q (Algorithm 1),
+ *                          each solved with the chain as preconditioner
+ *                          (EstimateSolution of Algorithm 2, batched over the
+ *                          k columns) to an FP64 residual tolerance.
+ *   cdl_anomaly_scores   - Algorithm 4: commute times c = V_G ||z_i - z_j||^2
+ *                          (eq. 1) of two snapshots, node scores
+ *                          F_i = sum_j omega_ij |c_t(i,j) - c_{t+1}(i,j)| and
+ *                          the top-K nodes.
+ *   cdl_score_sequence   - Algorithm 4 over consecutive pairs of a sequence
+ *                          of snapshots with uneven node sets.
+ *
+ * Conventions
+ * -----------
+ * Memory.  Pointers documented as "device" point to GPU memory owned by the
+ *   caller; "host" pointers point to CPU memory.  The library never allocates
+ *   or frees device memory: every scratch buffer is a caller-supplied
+ *   workspace whose size is returned by cdl_workspace_bytes().  Workspaces
+ *   must be 256-byte aligned.
+ * Layout.  n x n matrices (weights W, chain levels) use the library's padded
+ *   square layout: cdl_ld(n) rows of cdl_ld(n) elements, row-major, with
+ *   cdl_ld(n) = n rounded up to a multiple of 256; entries in padding rows and
+ *   columns are zero (the library writes them so).  Node series X, the
+ *   embedding Z and the scores F use plain row-major layouts described per
+ *   call.
+ * Streams.  Every call enqueues its GPU work on the context's stream (set at
+ *   creation or with cdl_ctx_set_stream) in stream order.  A call that returns
+ *   host values (marked "syncs") synchronises that stream before returning.
+ * Errors.  Every call returns a cdl_status; no exception or abort crosses the
+ *   boundary.  cdl_last_error() returns a message for the last failing call on
+ *   the context.  On an error, output buffers hold unspecified values, except
+ *   CDL_E_NOCONV, which leaves the last iterate in Z and fills the info struct.
+ * Threads.  A context must not be used by two host threads at once.
+ */
+#ifndef CADDELAG_H
+#define CADDELAG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cdl_ctx cdl_ctx;
+
+typedef enum {
+    CDL_OK = 0,
+    CDL_E_ARG = 1,          /* invalid argument: size, pointer, alignment, enum */
+    CDL_E_WORKSPACE = 2,    /* workspace smaller than cdl_workspace_bytes() */
+    CDL_E_NONFINITE = 3,    /* NaN or Inf in an input or an intermediate */
+    CDL_E_GRAPH = 4,        /* invalid graph: node of zero degree, negative or
+                               asymmetric weights, fewer than two nodes */
+    CDL_E_DIVERGED = 5,     /* chain does not contract (spectral radius of the
+                               normalised, deflated matrix is >= 1) */
+    CDL_E_NOCONV = 6,       /* solve did not reach tol within max_iter */
+    CDL_E_HIP = 7,          /* HIP runtime error */
+    CDL_E_UNSUPPORTED = 8   /* valid request this build does not implement */
+} cdl_status;
+
+typedef enum { CDL_FP64 = 0, CDL_FP32 = 1, CDL_BF16 = 2, CDL_FP16 = 3 } cdl_prec;
+typedef enum { CDL_RICHARDSON = 0, CDL_PCG = 1 } cdl_solver;
+typedef enum {
+    CDL_SCORE_UNWEIGHTED = 0,  /* omega_ij = 1 */
+    CDL_SCORE_DELTA_A = 1      /* omega_ij = |A_{t+1}(i,j) - A_t(i,j)| (CAD edge score) */
+} cdl_score_mode;
+
+#define CDL_MAX_DEPTH 14
+#define CDL_MAX_TOPK 256
+#define CDL_GRAPH_STATS 4      /* device doubles: vol, sigma, deg_min, deg_max */
+
+typedef struct {
+    int depth;                 /* number of stored levels S~, S~^2, ..., S~^{2^(depth-1)} */
+    int lazy;                  /* 1: levels are of (I + S)/2 (lazy walk) */
+    cdl_prec prec;             /* element type of the stored levels */
+    double rho_hat;            /* upper estimate of the spectral radius of S~ */
+    double fro[CDL_MAX_DEPTH + 1]; /* Frobenius norm of each stored level */
+} cdl_chain_info;
+
+typedef struct {
+    int iterations;            /* preconditioner applications performed */
+    int converged;             /* 1 if max relative residual <= tol */
+    double rel_residual;       /* final max_r ||y_r - L z_r|| / ||y_r|| (FP64) */
+    double history[64];        /* max relative residual after each iteration */
+} cdl_solve_info;
+
+/* One snapshot of a sequence, for cdl_score_sequence. */
+typedef struct {
+    const double *X;           /* device, n x T row-major node series (row stride ldx) */
+    int64_t n, T, ldx;
+    const int32_t *gid;        /* device, n strictly increasing global node ids < 2^20 */
+    const int32_t *gid_host;   /* host copy of gid (used to plan common-node maps) */
+} cdl_snapshot;
+
+typedef struct {
+    int64_t k;                 /* random projections per snapshot */
+    uint64_t seed;             /* projection seed (same for every snapshot) */
+    double sigma;              /* > 0: fixed kernel bandwidth; <= 0: per-snapshot median rule */
+    cdl_prec prec;             /* chain element type */
+    int depth;                 /* > 0: fixed chain depth; 0: adaptive */
+    int depth_max;
+    double chain_eps;          /* adaptive-depth truncation target (<= 0: default per prec) */
+    cdl_solver solver;
+    double tol;                /* relative FP64 residual target of each solve */
+    int max_iter;
+    cdl_score_mode mode;
+    int32_t top_k;
+} cdl_seq_params;
+
+typedef struct {
+    int32_t pairs;             /* number of scored pairs (n_snap - 1) */
+    int32_t max_iterations;    /* largest iteration count over the solves */
+    double max_rel_residual;   /* largest final residual over the solves */
+} cdl_seq_info;
+
+/* ---- context --------------------------------------------------------- */
+
+/* Create a context on HIP device `device` using HIP stream `stream` (a
+ * hipStream_t; NULL = the default stream).  Loads nothing, allocates no
+ * device memory. */
+cdl_status cdl_ctx_create(int device, void *stream, cdl_ctx **out);
+cdl_status cdl_ctx_destroy(cdl_ctx *ctx);
+cdl_status cdl_ctx_set_stream(cdl_ctx *ctx, void *stream);
+const char *cdl_status_string(cdl_status s);
+const char *cdl_last_error(const cdl_ctx *ctx);
+/* Library version string, e.g. "caddelag-gfx950 1.0". */
+const char *cdl_version(void);
+
+/* ---- sizes ------------------------------------------------------------- */
+
+/* Padded leading dimension (and row count) of the library's n x n layout. */
+int64_t cdl_ld(int64_t n);
+/* Bytes of an n x n matrix of `prec` elements in the padded layout. */
+size_t cdl_matrix_bytes(int64_t n, cdl_prec prec);
+/* Workspace sizes for one snapshot of n nodes with series of length T, k
+ * projections and at most depth_max chain levels of element type prec:
+ *   graph: for cdl_build_graph / cdl_graph_from_weights;
+ *   chain: storage of the chain levels (kept between build_chain and every
+ *          solve that uses it);
+ *   solve: for cdl_solve_embedding;
+ *   score: for cdl_anomaly_scores with up to n common nodes.
+ * Any output pointer may be NULL. */
+cdl_status cdl_workspace_bytes(int64_t n, int64_t T, int64_t k, int depth_max,
+                               cdl_prec prec, size_t *graph, size_t *chain,
+                               size_t *solve, size_t *score);
+
+/* ---- graph --------------------------------------------------------------- */
+
+/* Gaussian-kernel graph of one snapshot (Section "Climate Data"; Background).
+ *   X       device, n x T FP64 node series, row i at X + i*ldx (ldx >= T).
+ *   sigma   > 0: kernel bandwidth to use; <= 0: the lower median of the
+ *           n(n-1)/2 pair distances ||x_i - x_j|| (element of 0-based rank
+ *           floor((N-1)/2) of the sorted distances).
+ *   W       device output, padded n x n FP64: W_ij = exp(-||x_i-x_j||^2 / sigma^2)
+ *           for i != j, W_ii = 0.
+ *   deg     device output, n FP64 degrees deg_i = sum_j W_ij.
+ *   stats   device output, CDL_GRAPH_STATS FP64: vol = sum_i deg_i, sigma used,
+ *           min and max degree.
+ *   ws      device workspace of ws_bytes >= graph size from cdl_workspace_bytes.
+ * Async.  Errors: CDL_E_ARG (n < 2, T < 1, ldx < T, NULL), CDL_E_WORKSPACE.
+ * Non-finite X or a zero degree are reported by cdl_check_graph(). */
+cdl_status cdl_build_graph(cdl_ctx *ctx, const double *X, int64_t n, int64_t T,
+                           int64_t ldx, double sigma, double *W, double *deg,
+                           double *stats, void *ws, size_t ws_bytes);
+
+/* Copy a caller weight matrix into the padded layout and compute degrees.
+ *   Win     device, n x n FP64 symmetric weights, row stride ldw (>= n); the
+ *           diagonal is ignored (no self-edges).
+ *   W, deg, stats, ws as for cdl_build_graph (stats[1] = 0).
+ * Syncs: validates symmetry (exact), non-negativity, finiteness and positive
+ * degrees; CDL_E_GRAPH / CDL_E_NONFINITE on failure. */
+cdl_status cdl_graph_from_weights(cdl_ctx *ctx, const double *Win, int64_t n,
+                                  int64_t ldw, double *W, double *deg,
+                                  double *stats, void *ws, size_t ws_bytes);
+
+/* Syncs.  Checks a built graph: CDL_E_NONFINITE if any weight or degree is
+ * not finite, CDL_E_GRAPH if the minimum degree is not positive.  Optionally
+ * returns stats to the host (host_stats may be NULL). */
+cdl_status cdl_check_graph(cdl_ctx *ctx, const double *deg, const double *stats,
+                           int64_t n, double *host_stats);
+
+/* ---- chain (Algorithm 2, ChainProduct) ------------------------------------ */
+
+/* Levels S~_0 = S - u u^T (S = D^{-1/2} W D^{-1/2}, u = D^{1/2} 1 / sqrt(vol);
+ * lazy: S = (I + D^{-1/2} W D^{-1/2}) / 2) and S~_{l+1} = S~_l^2, stored in
+ * element type prec (FP32 accumulation; FP64 for CDL_FP64).
+ *   W, deg, stats  from cdl_build_graph / cdl_graph_from_weights.
+ *   depth   > 0: exactly this many levels (<= depth_max); 0: adaptive.
+ *   chain_eps  adaptive rule.  > 0: square until the truncation bound
+ *           fro(S~_l)^2 / (1 - rho_hat) <= chain_eps (then depth = l+1) or
+ *           depth_max levels are stored.  <= 0: autotune - before each
+ *           squaring, compare the modelled time of one more squaring plus the
+ *           refinement iterations it saves against stopping now (model: MFMA
+ *           and HBM rates of the level type, a 1e-8 residual target, k = 256
+ *           columns, contraction max(truncation bound, rounding floor of the
+ *           level type)) and square only while that is cheaper.
+ *   chain   device buffer of chain_bytes >= chain size from cdl_workspace_bytes.
+ *   info    host output.
+ * Syncs (reads back the level norms).  Errors: CDL_E_ARG, CDL_E_WORKSPACE,
+ * CDL_E_DIVERGED (rho_hat >= 1: e.g. a bipartite graph without lazy),
+ * CDL_E_NONFINITE. */
+cdl_status cdl_build_chain(cdl_ctx *ctx, const double *W, const double *deg,
+                           const double *stats, int64_t n, cdl_prec prec,
+                           int depth, int depth_max, double chain_eps, int lazy,
+                           void *chain, size_t chain_bytes, cdl_chain_info *info);
+
+/* ---- embedding (Algorithm 3 with Algorithm 1's right-hand sides) ---------- */
+
+/* Z = L^+ Y for the k columns y_r = (1/sqrt(k)) B^T W^{1/2} q_r (L = D - W;
+ * B the signed edge-node incidence with each edge's head at the endpoint of
+ * lower global id; q_r(edge) = +-1 from the counter-based generator below).
+ *   gid     device, n int32 global node ids < 2^20 (NULL = 0..n-1).  Signs
+ *           depend only on (seed, r, global ids), so snapshots of a sequence
+ *           share random numbers on common edges.
+ *   k       number of projections (k <= 0: ceil(ln(n / eps_rp)), Algorithm 1).
+ *   seed    sign word of edge {lo, hi} (global ids, lo < hi) and block
+ *           beta = r / 64 is mix(mix(seed) ^ (beta << 40 | lo << 20 | hi)),
+ *           mix = the SplitMix64 output function; bit (r mod 64) set = -1.
+ *   solver  CDL_RICHARDSON: x <- x + P1 (y - L x) (EstimateSolution with
+ *           P2 y = P1 L y); CDL_PCG: preconditioned conjugate gradients per
+ *           column with the same P1.  Residuals and inner products in FP64.
+ *   tol     stop when max_r ||y_r - L x_r|| / ||y_r|| <= tol (tol <= 0: run
+ *           exactly max_iter preconditioner applications).
+ *   Z       device output, n x k FP64 row-major (row i = z_i), columns
+ *           centred (1^T z_r = 0).
+ *   info    host output (may be NULL).
+ * Syncs once per iteration (residual norms).  Errors: CDL_E_ARG,
+ * CDL_E_WORKSPACE, CDL_E_NOCONV (Z holds the last iterate), CDL_E_NONFINITE. */
+cdl_status cdl_solve_embedding(cdl_ctx *ctx, const double *W, const double *deg,
+                               const double *stats, const int32_t *gid, int64_t n,
+                               const void *chain, const cdl_chain_info *chain_info,
+                               int64_t k, double eps_rp, uint64_t seed,
+                               cdl_solver solver, double tol, int max_iter,
+                               double *Z, void *ws, size_t ws_bytes,
+                               cdl_solve_info *info);
+
+/* ---- scores (Algorithm 4) -------------------------------------------------- */
+
+/* F_c = sum_{c'} omega |c_0(a,b) - c_1(a',b')| over the m common nodes, where
+ * common node c is row map0[c] of snapshot 0 and row map1[c] of snapshot 1,
+ * c_t = vol_t ||z_i - z_j||^2, omega = 1 or |W1(a',b') - W0(a,b)|.
+ *   Z0, Z1      device, n0 x k and n1 x k FP64 row-major embeddings.
+ *   W0, W1      device, padded weight matrices (only read for DELTA_A; may be
+ *               NULL for UNWEIGHTED).
+ *   stats0/1    device graph stats (vol read from element 0).
+ *   map0, map1  device, m int32 row indices (NULL = identity; then m = n0 = n1).
+ *   F           device output, m FP64.
+ *   top_k       number of top nodes (0..CDL_MAX_TOPK, <= m).
+ *   top_idx     device output, top_k int32 common-node indices sorted by
+ *               descending F, ties by ascending index.
+ * Async.  Errors: CDL_E_ARG, CDL_E_WORKSPACE. */
+cdl_status cdl_anomaly_scores(cdl_ctx *ctx, const double *Z0, const double *W0,
+                              const double *stats0, int64_t n0,
+                              const double *Z1, const double *W1,
+                              const double *stats1, int64_t n1, int64_t k,
+                              const int32_t *map0, const int32_t *map1, int64_t m,
+                              cdl_score_mode mode, double *F, int32_t top_k,
+                              int32_t *top_idx, void *ws, size_t ws_bytes);
+
+/* Whole sequence: for every snapshot, graph + chain + embedding; for every
+ * consecutive pair (t, t+1), scores over the common global ids.
+ *   F[t]        device output for pair t: m_t FP64, m_t = |V_t ∩ V_{t+1}|, in
+ *               ascending global-id order.
+ *   top_idx[t]  device output for pair t: top_k int32 indices into F[t].
+ *   ws          device workspace of cdl_sequence_workspace_bytes().
+ * Syncs.  Errors as for the per-snapshot calls. */
+cdl_status cdl_sequence_workspace_bytes(int32_t n_snap, const cdl_snapshot *snaps,
+                                        const cdl_seq_params *p, size_t *bytes);
+cdl_status cdl_score_sequence(cdl_ctx *ctx, int32_t n_snap, const cdl_snapshot *snaps,
+                              const cdl_seq_params *p, double *const *F,
+                              int32_t *const *top_idx, void *ws, size_t ws_bytes,
+                              cdl_seq_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CADDELAG_H */

@@ -1,0 +1,32 @@
+"""MI355X (gfx950) commute-time anomaly detection for dense graph sequences.
+
+The hot path - Gaussian-kernel graph, inverse-chain squarings, chain-
+preconditioned FP64-refined multi-RHS Laplacian solve, fused all-pairs node
+scores - runs in hand-written HIP kernels behind the C ABI of
+include/caddelag.h (libcaddelag.so, built in-tree).  This package is the thin
+torch binding: it allocates device buffers and passes pointers and streams.
+Importing it loads the library and fails if it has not been built.
+"""
+
+from . import _lib
+
+_lib.load()
+
+from .api import (  # noqa: E402,F401
+    Chain,
+    Context,
+    Graph,
+    SeqParams,
+    anomaly_scores,
+    build_chain,
+    build_graph,
+    check_graph,
+    graph_from_weights,
+    ld,
+    level,
+    level_scale,
+    score_sequence,
+    solve_embedding,
+    workspace_bytes,
+)
+from ._lib import CdlError  # noqa: E402,F401

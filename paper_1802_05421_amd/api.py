@@ -1,0 +1,293 @@
+"""Thin torch-facing binding of libcaddelag (same call names as the C ABI).
+
+Every step runs in the library's HIP kernels; this module only allocates
+device buffers with torch, passes raw pointers and the current HIP stream,
+and turns status codes into exceptions.  There is no CPU or PyTorch compute
+fallback: if the library is missing, importing the package fails.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import torch
+
+from . import _lib as L
+
+_ctx_cache = {}
+
+
+def _lib():
+    return L.load()
+
+
+def _check(status: int, ctx=None):
+    if status != 0:
+        msg = _lib().cdl_last_error(ctx).decode() if ctx else ""
+        raise L.CdlError(status, msg)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A library context bound to one device and (by default) torch's current stream."""
+
+    def __init__(self, device: int = 0, stream: Optional[torch.cuda.Stream] = None):
+        self.device = device
+        s = stream if stream is not None else torch.cuda.current_stream(device)
+        self._stream = s
+        h = C.c_void_p()
+        _check(_lib().cdl_ctx_create(device, C.c_void_p(s.cuda_stream), C.byref(h)))
+        self.h = h
+
+    def sync_stream(self):
+        """Follow torch's current stream of the device."""
+        s = torch.cuda.current_stream(self.device)
+        if s.cuda_stream != self._stream.cuda_stream:
+            _check(_lib().cdl_ctx_set_stream(self.h, C.c_void_p(s.cuda_stream)), self.h)
+            self._stream = s
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None) and L._lib is not None:
+                L._lib.cdl_ctx_destroy(self.h)
+        except Exception:
+            pass
+
+
+def context(device: int = 0) -> Context:
+    c = _ctx_cache.get(device)
+    if c is None:
+        c = Context(device)
+        _ctx_cache[device] = c
+    c.sync_stream()
+    return c
+
+
+def ld(n: int) -> int:
+    return int(_lib().cdl_ld(n))
+
+
+def workspace_bytes(n: int, T: int, k: int, depth_max: int = 14, prec: str = "bf16"):
+    g, c, s, sc = C.c_size_t(), C.c_size_t(), C.c_size_t(), C.c_size_t()
+    _check(_lib().cdl_workspace_bytes(n, T, k, depth_max, L.PREC[prec], C.byref(g), C.byref(c),
+                                      C.byref(s), C.byref(sc)))
+    return dict(graph=g.value, chain=c.value, solve=s.value, score=sc.value)
+
+
+def _ws(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+
+
+@dataclass
+class Graph:
+    W: torch.Tensor          # (ld, ld) float64, padded
+    deg: torch.Tensor        # (n,) float64
+    stats: torch.Tensor      # (4,) float64: vol, sigma, deg_min, deg_max
+    n: int
+
+    def host_stats(self):
+        s = self.stats.cpu().tolist()
+        return dict(vol=s[0], sigma=s[1], deg_min=s[2], deg_max=s[3])
+
+
+@dataclass
+class Chain:
+    buf: torch.Tensor
+    info: L.ChainInfo
+    n: int
+
+    @property
+    def depth(self) -> int:
+        return self.info.depth
+
+    @property
+    def fro(self) -> List[float]:
+        return [self.info.fro[i] for i in range(self.info.depth)]
+
+
+def build_graph(X: torch.Tensor, sigma: Optional[float] = None, ws: Optional[torch.Tensor] = None,
+                out: Optional[Graph] = None, check: bool = True) -> Graph:
+    """Gaussian-kernel graph of one snapshot; X is (n, T) float64 on the GPU."""
+    if X.dtype != torch.float64 or not X.is_cuda or X.dim() != 2 or X.stride(1) != 1:
+        raise ValueError("X must be a CUDA float64 matrix with unit column stride")
+    ctx = context(X.device.index)
+    n, T = X.shape
+    m = ld(n)
+    if out is None:
+        out = Graph(W=torch.empty((m, m), dtype=torch.float64, device=X.device),
+                    deg=torch.empty(n, dtype=torch.float64, device=X.device),
+                    stats=torch.empty(L.CDL_GRAPH_STATS, dtype=torch.float64, device=X.device), n=n)
+    need = workspace_bytes(n, T, 1, 1, "fp64")["graph"]
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, X.device)
+    _check(_lib().cdl_build_graph(ctx.h, _ptr(X), n, T, X.stride(0),
+                                  float(sigma) if sigma else 0.0, _ptr(out.W), _ptr(out.deg),
+                                  _ptr(out.stats), _ptr(ws), ws.numel()), ctx.h)
+    if check:
+        check_graph(out)
+    return out
+
+
+def check_graph(g: Graph) -> dict:
+    ctx = context(g.W.device.index)
+    h = (C.c_double * L.CDL_GRAPH_STATS)()
+    _check(_lib().cdl_check_graph(ctx.h, _ptr(g.deg), _ptr(g.stats), g.n, h), ctx.h)
+    return dict(vol=h[0], sigma=h[1], deg_min=h[2], deg_max=h[3])
+
+
+def graph_from_weights(Win: torch.Tensor) -> Graph:
+    if Win.dtype != torch.float64 or not Win.is_cuda or Win.dim() != 2 or Win.stride(1) != 1:
+        raise ValueError("weights must be a CUDA float64 matrix with unit column stride")
+    ctx = context(Win.device.index)
+    n = Win.shape[0]
+    m = ld(n)
+    g = Graph(W=torch.empty((m, m), dtype=torch.float64, device=Win.device),
+              deg=torch.empty(n, dtype=torch.float64, device=Win.device),
+              stats=torch.empty(L.CDL_GRAPH_STATS, dtype=torch.float64, device=Win.device), n=n)
+    ws = _ws(256, Win.device)
+    _check(_lib().cdl_graph_from_weights(ctx.h, _ptr(Win), n, Win.stride(0), _ptr(g.W),
+                                         _ptr(g.deg), _ptr(g.stats), _ptr(ws), ws.numel()), ctx.h)
+    return g
+
+
+def build_chain(g: Graph, prec: str = "bf16", depth: int = 0, depth_max: int = 14,
+                chain_eps: float = 0.0, lazy: bool = False,
+                buf: Optional[torch.Tensor] = None) -> Chain:
+    ctx = context(g.W.device.index)
+    need = workspace_bytes(g.n, 1, 1, depth_max, prec)["chain"]
+    if buf is None or buf.numel() < need:
+        buf = _ws(need, g.W.device)
+    info = L.ChainInfo()
+    _check(_lib().cdl_build_chain(ctx.h, _ptr(g.W), _ptr(g.deg), _ptr(g.stats), g.n,
+                                  L.PREC[prec], depth, depth_max, chain_eps, int(lazy),
+                                  _ptr(buf), buf.numel(), C.byref(info)), ctx.h)
+    return Chain(buf=buf, info=info, n=g.n)
+
+
+def level(chain: Chain, l: int) -> torch.Tensor:
+    """View of stored chain level l as an (ld, ld) tensor (for inspection)."""
+    prec = {0: torch.float64, 1: torch.float32, 2: torch.bfloat16, 3: torch.float16}[chain.info.prec]
+    m = ld(chain.n)
+    esz = torch.tensor([], dtype=prec).element_size()
+    al = lambda x: (x + 255) // 256 * 256
+    tiles = (m // (256 if chain.info.prec in (2, 3) else 128))
+    off = 3 * al(m * 8) + al(max(m, tiles * (tiles + 1) // 2) * 8)
+    lb = m * m * esz
+    raw = chain.buf[off + l * lb: off + (l + 1) * lb]
+    return raw.view(prec).view(m, m)
+
+
+def level_scale(chain: Chain) -> float:
+    if chain.info.prec != 3:
+        return 1.0
+    s = 1.0
+    while s * 2 <= chain.n:
+        s *= 2
+    return s
+
+
+def solve_embedding(g: Graph, chain: Chain, k: int, seed: int, tol: float = 1e-8,
+                    max_iter: int = 30, gid: Optional[torch.Tensor] = None,
+                    solver: str = "richardson", eps_rp: float = 0.0,
+                    ws: Optional[torch.Tensor] = None, Z: Optional[torch.Tensor] = None,
+                    raise_noconv: bool = True):
+    """Embedding Z (n, k) float64 with L Z = Y to relative residual tol."""
+    ctx = context(g.W.device.index)
+    kk = k if k > 0 else int(math.ceil(math.log(g.n / eps_rp)))
+    need = workspace_bytes(g.n, 1, kk, max(chain.info.depth, 1), L.PREC_NAME[chain.info.prec])["solve"]
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, g.W.device)
+    if Z is None:
+        Z = torch.empty((g.n, kk), dtype=torch.float64, device=g.W.device)
+    if gid is not None and (gid.dtype != torch.int32 or not gid.is_cuda):
+        raise ValueError("gid must be a CUDA int32 vector")
+    info = L.SolveInfo()
+    st = _lib().cdl_solve_embedding(ctx.h, _ptr(g.W), _ptr(g.deg), _ptr(g.stats), _ptr(gid), g.n,
+                                    _ptr(chain.buf), C.byref(chain.info), kk, float(eps_rp),
+                                    C.c_uint64(seed), L.SOLVER[solver], float(tol), max_iter,
+                                    _ptr(Z), _ptr(ws), ws.numel(), C.byref(info))
+    if st != 0 and not (st == 6 and not raise_noconv):
+        _check(st, ctx.h)
+    return Z, info
+
+
+def anomaly_scores(Z0: torch.Tensor, g0: Graph, Z1: torch.Tensor, g1: Graph,
+                   mode: str = "unweighted", top_k: int = 50,
+                   map0: Optional[torch.Tensor] = None, map1: Optional[torch.Tensor] = None,
+                   ws: Optional[torch.Tensor] = None, F: Optional[torch.Tensor] = None,
+                   top: Optional[torch.Tensor] = None):
+    ctx = context(Z0.device.index)
+    k = Z0.shape[1]
+    m = map0.numel() if map0 is not None else g0.n
+    need = workspace_bytes(max(m, 2), 1, k, 1, "fp64")["score"]
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, Z0.device)
+    if F is None:
+        F = torch.empty(m, dtype=torch.float64, device=Z0.device)
+    if top is None:
+        top = torch.empty(max(top_k, 1), dtype=torch.int32, device=Z0.device)
+    weighted = mode == "delta_a"
+    _check(_lib().cdl_anomaly_scores(ctx.h, _ptr(Z0), _ptr(g0.W) if weighted else None,
+                                     _ptr(g0.stats), g0.n, _ptr(Z1),
+                                     _ptr(g1.W) if weighted else None, _ptr(g1.stats), g1.n, k,
+                                     _ptr(map0), _ptr(map1), m, L.MODE[mode], _ptr(F), top_k,
+                                     _ptr(top), _ptr(ws), ws.numel()), ctx.h)
+    return F, top[:top_k]
+
+
+@dataclass
+class SeqParams:
+    k: int = 128
+    seed: int = 7
+    sigma: float = 0.0
+    prec: str = "bf16"
+    depth: int = 0
+    depth_max: int = 14
+    chain_eps: float = 0.0
+    solver: str = "richardson"
+    tol: float = 1e-8
+    max_iter: int = 30
+    mode: str = "unweighted"
+    top_k: int = 50
+
+
+def score_sequence(Xs: Sequence[torch.Tensor], gids: Sequence[torch.Tensor], p: SeqParams,
+                   ws: Optional[torch.Tensor] = None):
+    """Scores of every consecutive pair of snapshots (common global ids)."""
+    dev = Xs[0].device
+    ctx = context(dev.index)
+    n_snap = len(Xs)
+    gid_host = [g.cpu().to(torch.int32).contiguous() for g in gids]
+    gid_dev = [g.to(device=dev, dtype=torch.int32).contiguous() for g in gids]
+    snaps = (L.Snapshot * n_snap)()
+    for t, X in enumerate(Xs):
+        snaps[t].X = X.data_ptr()
+        snaps[t].n, snaps[t].T = X.shape
+        snaps[t].ldx = X.stride(0)
+        snaps[t].gid = gid_dev[t].data_ptr()
+        snaps[t].gid_host = gid_host[t].data_ptr()
+    q = L.SeqParams(k=p.k, seed=p.seed, sigma=p.sigma, prec=L.PREC[p.prec], depth=p.depth,
+                    depth_max=p.depth_max, chain_eps=p.chain_eps, solver=L.SOLVER[p.solver],
+                    tol=p.tol, max_iter=p.max_iter, mode=L.MODE[p.mode], top_k=p.top_k)
+    nb = C.c_size_t()
+    _check(_lib().cdl_sequence_workspace_bytes(n_snap, snaps, C.byref(q), C.byref(nb)))
+    if ws is None or ws.numel() < nb.value:
+        ws = _ws(nb.value, dev)
+    Fs, tops = [], []
+    for t in range(n_snap - 1):
+        a = set(gid_host[t].tolist())
+        m = sum(1 for v in gid_host[t + 1].tolist() if v in a)
+        Fs.append(torch.empty(m, dtype=torch.float64, device=dev))
+        tops.append(torch.empty(max(1, min(p.top_k, m)), dtype=torch.int32, device=dev))
+    Fp = (C.c_void_p * (n_snap - 1))(*[f.data_ptr() for f in Fs])
+    Tp = (C.c_void_p * (n_snap - 1))(*[t.data_ptr() for t in tops])
+    info = L.SeqInfo()
+    _check(_lib().cdl_score_sequence(ctx.h, n_snap, snaps, C.byref(q), Fp, Tp, _ptr(ws),
+                                     ws.numel(), C.byref(info)), ctx.h)
+    return Fs, [t[:min(p.top_k, f.numel())] for t, f in zip(tops, Fs)], info

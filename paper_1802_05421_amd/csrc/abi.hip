@@ -1,0 +1,637 @@
+// C ABI of libcaddelag: argument validation, workspace planning and the host
+// orchestration of the kernels for each call of include/caddelag.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "caddelag.h"
+#include "kernels.h"
+
+struct cdl_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+};
+
+namespace {
+
+using namespace cdl;
+
+constexpr size_t kAlign = 256;
+size_t al(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+size_t esize(int prec) { return prec == 0 ? 8 : prec == 1 ? 4 : 2; }
+
+// Bump allocator over a caller workspace (base == nullptr: size only).
+struct Arena {
+    char *base;
+    size_t off = 0;
+    explicit Arena(void *b) : base((char *)b) {}
+    template <typename T> T *take(size_t count) {
+        T *p = base ? (T *)(base + off) : nullptr;
+        off += al(count * sizeof(T));
+        return p;
+    }
+};
+
+struct GraphWs {
+    int *flags;
+    SelectState *sel;
+    double *sqn, *Xp;
+};
+GraphWs plan_graph(Arena &a, int64_t n, int64_t T) {
+    const int64_t ld = pad_n(n), Tp = pad_t(T);
+    GraphWs w;
+    w.flags = a.take<int>(64);
+    w.sel = a.take<SelectState>(1);
+    w.sqn = a.take<double>(ld);
+    w.Xp = a.take<double>((size_t)ld * Tp);
+    return w;
+}
+
+struct ChainBuf {
+    double *dmn, *dm, *u, *fro;
+    char *levels;
+    size_t level_bytes;
+};
+ChainBuf plan_chain(Arena &a, int64_t n, int prec, int depth_max) {
+    const int64_t ld = pad_n(n);
+    ChainBuf c;
+    c.dmn = a.take<double>(ld);
+    c.dm = a.take<double>(ld);
+    c.u = a.take<double>(ld);
+    c.fro = a.take<double>(std::max<int64_t>(ld, square_tiles(prec, ld)));
+    c.level_bytes = (size_t)ld * ld * esize(prec);
+    c.levels = a.take<char>(c.level_bytes * depth_max);
+    return c;
+}
+
+struct SolveWs {
+    double *Yt, *Xt, *Rt, *V64, *npart, *mpart, *scal, *mean;
+    void *Vlo[2];
+};
+SolveWs plan_solve(Arena &a, int64_t n, int64_t k, int prec) {
+    const int64_t ld = pad_n(n), kp = pad_k(k);
+    const size_t panel = (size_t)kp * ld;
+    SolveWs w;
+    w.Yt = a.take<double>(panel);
+    w.Xt = a.take<double>(panel);
+    w.Rt = a.take<double>(panel);
+    w.V64 = a.take<double>(panel);
+    w.Vlo[0] = a.take<char>(panel * esize(prec));
+    w.Vlo[1] = a.take<char>(panel * esize(prec));
+    w.npart = a.take<double>((size_t)residual_parts(ld) * kp);
+    w.mpart = a.take<double>(residual_tiles(ld, kp));
+    w.scal = a.take<double>(kp + 2);
+    w.mean = a.take<double>(kp);
+    return w;
+}
+
+struct ScoreWs {
+    double *Zh, *Zhe, *sq, *part;
+    void *topk;
+};
+ScoreWs plan_score(Arena &a, int64_t m, int64_t k) {
+    const int64_t mp = pad_n(m), kp = pad_k(k);
+    ScoreWs w;
+    w.Zh = a.take<double>((size_t)mp * 2 * kp);
+    w.Zhe = a.take<double>((size_t)mp * 2 * kp);
+    w.sq = a.take<double>(mp);
+    w.part = a.take<double>((size_t)score_tiles_1d(mp) * mp);
+    const int64_t cap = topk_scratch_elems(m, CDL_MAX_TOPK);
+    w.topk = a.take<char>((size_t)cap * (2 * sizeof(double) + 2 * sizeof(int32_t)));
+    return w;
+}
+
+cdl_status fail(cdl_ctx *c, cdl_status s, const std::string &msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+#define HIPCHK(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(ctx, CDL_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+bool valid_prec(int p) { return p >= 0 && p <= 3; }
+
+// ---- depth model ----------------------------------------------------------
+
+double peak_flops(int prec) {
+    switch (prec) {
+    case 0: return 78.6e12;
+    case 1: return 157.3e12;
+    default: return 2.5e15;
+    }
+}
+double unit_roundoff(int prec) {
+    switch (prec) {
+    case 0: return std::ldexp(1.0, -53);
+    case 1: return std::ldexp(1.0, -24);
+    case 2: return std::ldexp(1.0, -8);
+    default: return std::ldexp(1.0, -11);
+    }
+}
+double iters_for(double c, double tol) {
+    if (!(c < 1.0)) return 1e30;
+    if (c <= 0.0) return 1.0;
+    return std::max(1.0, std::ceil(std::log(tol) / std::log(c)));
+}
+// Should level l (Frobenius norm f, spectral estimate rho) be squared again?
+bool model_wants_square(int prec, int64_t n, int l, double f, double rho) {
+    const double k = 256.0, tol = 1e-8, nn = (double)n;
+    const double t_sq = nn * nn * nn / (peak_flops(prec) * 0.5);
+    const double t_res = 2.0 * nn * nn * k / (78.6e12 * 0.6);
+    const double t_ap = std::max(2.0 * nn * nn * k / (peak_flops(prec) * 0.4),
+                                 nn * nn * esize(prec) / 5.0e12);
+    if (!(rho < 1.0 - 1e-9)) return true;   // not contracting yet: keep testing
+    const double floor_ = unit_roundoff(prec) * 8.0 * std::max(rho, 1e-3);
+    const double p1 = std::ldexp(1.0, l + 1), p2 = std::ldexp(1.0, l + 2);
+    const double tr_now = std::min(f * f, std::pow(rho, p1)) / (1.0 - rho);
+    const double tr_next = std::min(f * f * f * f, std::pow(rho, p2)) / (1.0 - rho);
+    const double c_now = std::max(tr_now, floor_), c_next = std::max(tr_next, floor_);
+    const double cost_now = iters_for(c_now, tol) * (t_res + (l + 1) * t_ap);
+    const double cost_next = t_sq + iters_for(c_next, tol) * (t_res + (l + 2) * t_ap);
+    return cost_next < cost_now;
+}
+
+} // namespace
+
+extern "C" {
+
+const char *cdl_version(void) { return "caddelag-gfx950 1.0"; }
+
+const char *cdl_status_string(cdl_status s) {
+    switch (s) {
+    case CDL_OK: return "ok";
+    case CDL_E_ARG: return "invalid argument";
+    case CDL_E_WORKSPACE: return "workspace too small";
+    case CDL_E_NONFINITE: return "non-finite value";
+    case CDL_E_GRAPH: return "invalid graph";
+    case CDL_E_DIVERGED: return "chain does not contract";
+    case CDL_E_NOCONV: return "solve did not converge";
+    case CDL_E_HIP: return "HIP runtime error";
+    case CDL_E_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char *cdl_last_error(const cdl_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+cdl_status cdl_ctx_create(int device, void *stream, cdl_ctx **out) {
+    if (!out) return CDL_E_ARG;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return CDL_E_ARG;
+    cdl_ctx *c = new (std::nothrow) cdl_ctx;
+    if (!c) return CDL_E_HIP;
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    *out = c;
+    return CDL_OK;
+}
+
+cdl_status cdl_ctx_destroy(cdl_ctx *ctx) {
+    delete ctx;
+    return CDL_OK;
+}
+
+cdl_status cdl_ctx_set_stream(cdl_ctx *ctx, void *stream) {
+    if (!ctx) return CDL_E_ARG;
+    ctx->stream = (hipStream_t)stream;
+    return CDL_OK;
+}
+
+int64_t cdl_ld(int64_t n) { return n > 0 ? pad_n(n) : 0; }
+
+size_t cdl_matrix_bytes(int64_t n, cdl_prec prec) {
+    if (n <= 0 || !valid_prec(prec)) return 0;
+    const size_t ld = (size_t)pad_n(n);
+    return ld * ld * esize(prec);
+}
+
+cdl_status cdl_workspace_bytes(int64_t n, int64_t T, int64_t k, int depth_max, cdl_prec prec,
+                               size_t *graph, size_t *chain, size_t *solve, size_t *score) {
+    if (n < 2 || n > (1 << 20) || T < 1 || k < 1 || depth_max < 1 ||
+        depth_max > CDL_MAX_DEPTH || !valid_prec(prec))
+        return CDL_E_ARG;
+    if (graph) { Arena a(nullptr); plan_graph(a, n, T); *graph = a.off; }
+    if (chain) { Arena a(nullptr); plan_chain(a, n, prec, depth_max); *chain = a.off; }
+    if (solve) { Arena a(nullptr); plan_solve(a, n, k, prec); *solve = a.off; }
+    if (score) { Arena a(nullptr); plan_score(a, n, k); *score = a.off; }
+    return CDL_OK;
+}
+
+// ---- graph -------------------------------------------------------------------
+
+cdl_status cdl_build_graph(cdl_ctx *ctx, const double *X, int64_t n, int64_t T, int64_t ldx,
+                           double sigma, double *W, double *deg, double *stats, void *ws,
+                           size_t ws_bytes) {
+    if (!ctx) return CDL_E_ARG;
+    if (n < 2 || n > (1 << 20)) return fail(ctx, CDL_E_ARG, "n must be in [2, 2^20]");
+    if (T < 1 || ldx < T) return fail(ctx, CDL_E_ARG, "need T >= 1 and ldx >= T");
+    if (!X || !W || !deg || !stats || !ws) return fail(ctx, CDL_E_ARG, "null pointer");
+    if (!aligned(X, 8) || !aligned(W, 16) || !aligned(deg, 8) || !aligned(stats, 8) ||
+        !aligned(ws, kAlign))
+        return fail(ctx, CDL_E_ARG, "misaligned pointer");
+    if (!std::isfinite(sigma)) return fail(ctx, CDL_E_ARG, "sigma must be finite");
+    Arena need(nullptr);
+    plan_graph(need, n, T);
+    if (ws_bytes < need.off) return fail(ctx, CDL_E_WORKSPACE, "graph workspace too small");
+    Arena a(ws);
+    GraphWs w = plan_graph(a, n, T);
+    const int64_t ld = pad_n(n), Tp = pad_t(T);
+    hipStream_t s = ctx->stream;
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(launch_fill_zero(w.flags, 256, s));
+    HIPCHK(launch_pad_series(X, n, T, ldx, w.Xp, ld, Tp, w.sqn, w.flags, s));
+    HIPCHK(launch_gram_dist(w.Xp, Tp, w.sqn, n, ld, W, s));
+    if (sigma > 0.0)
+        HIPCHK(launch_set_sigma(sigma, stats, s));
+    else
+        HIPCHK(launch_select_median(W, ld, n, w.sel, stats, s));
+    HIPCHK(launch_exp_degree(W, ld, n, stats, deg, s));
+    HIPCHK(launch_graph_stats(deg, n, stats, s));
+    return CDL_OK;
+}
+
+cdl_status cdl_check_graph(cdl_ctx *ctx, const double *deg, const double *stats, int64_t n,
+                           double *host_stats) {
+    if (!ctx) return CDL_E_ARG;
+    if (!deg || !stats || n < 2) return fail(ctx, CDL_E_ARG, "bad arguments");
+    double h[CDL_GRAPH_STATS];
+    HIPCHK(hipMemcpyAsync(h, stats, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (host_stats) std::memcpy(host_stats, h, sizeof(h));
+    for (double v : h)
+        if (!std::isfinite(v)) return fail(ctx, CDL_E_NONFINITE, "non-finite weights or degrees");
+    if (!(h[2] > 0.0)) return fail(ctx, CDL_E_GRAPH, "a node has zero degree");
+    return CDL_OK;
+}
+
+cdl_status cdl_graph_from_weights(cdl_ctx *ctx, const double *Win, int64_t n, int64_t ldw,
+                                  double *W, double *deg, double *stats, void *ws,
+                                  size_t ws_bytes) {
+    if (!ctx) return CDL_E_ARG;
+    if (n < 2 || n > (1 << 20) || ldw < n) return fail(ctx, CDL_E_ARG, "bad n or ldw");
+    if (!Win || !W || !deg || !stats || !ws) return fail(ctx, CDL_E_ARG, "null pointer");
+    if (!aligned(Win, 8) || !aligned(W, 16) || !aligned(ws, kAlign))
+        return fail(ctx, CDL_E_ARG, "misaligned pointer");
+    if (ws_bytes < 256) return fail(ctx, CDL_E_WORKSPACE, "graph workspace too small");
+    hipStream_t s = ctx->stream;
+    int *flags = (int *)ws;
+    const int64_t ld = pad_n(n);
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(launch_fill_zero(flags, 256, s));
+    HIPCHK(launch_import_weights(Win, ldw, n, W, ld, deg, flags, s));
+    HIPCHK(launch_set_sigma(0.0, stats, s));
+    HIPCHK(launch_graph_stats(deg, n, stats, s));
+    int hf = 0;
+    HIPCHK(hipMemcpyAsync(&hf, flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hf & 1) return fail(ctx, CDL_E_NONFINITE, "non-finite weight");
+    if (hf & 2) return fail(ctx, CDL_E_GRAPH, "negative weight");
+    if (hf & 4) return fail(ctx, CDL_E_GRAPH, "asymmetric weights");
+    return cdl_check_graph(ctx, deg, stats, n, nullptr);
+}
+
+// ---- chain ---------------------------------------------------------------------
+
+static double host_sum(const std::vector<double> &v) {
+    double s = 0.0;
+    for (double x : v) s += x;
+    return s;
+}
+
+cdl_status cdl_build_chain(cdl_ctx *ctx, const double *W, const double *deg, const double *stats,
+                           int64_t n, cdl_prec prec, int depth, int depth_max, double chain_eps,
+                           int lazy, void *chain, size_t chain_bytes, cdl_chain_info *info) {
+    if (!ctx) return CDL_E_ARG;
+    if (n < 2 || n > (1 << 20)) return fail(ctx, CDL_E_ARG, "bad n");
+    if (!valid_prec(prec)) return fail(ctx, CDL_E_ARG, "bad precision");
+    if (depth_max < 1 || depth_max > CDL_MAX_DEPTH || depth < 0 || depth > depth_max)
+        return fail(ctx, CDL_E_ARG, "need 0 <= depth <= depth_max <= 14, depth_max >= 1");
+    if (!W || !deg || !stats || !chain || !info) return fail(ctx, CDL_E_ARG, "null pointer");
+    if (!aligned(W, 16) || !aligned(chain, kAlign)) return fail(ctx, CDL_E_ARG, "misaligned pointer");
+    Arena need(nullptr);
+    plan_chain(need, n, prec, depth_max);
+    if (chain_bytes < need.off) return fail(ctx, CDL_E_WORKSPACE, "chain buffer too small");
+    Arena a(chain);
+    ChainBuf c = plan_chain(a, n, prec, depth_max);
+    const int64_t ld = pad_n(n);
+    hipStream_t s = ctx->stream;
+    HIPCHK(hipSetDevice(ctx->device));
+    std::memset(info, 0, sizeof(*info));
+    info->lazy = lazy ? 1 : 0;
+    info->prec = prec;
+
+    HIPCHK(launch_chain_prep(deg, stats, n, ld, info->lazy, c.dmn, c.dm, c.u, s));
+    HIPCHK(launch_normalize(prec, W, ld, n, c.dmn, c.u, info->lazy, c.levels, c.fro, s));
+    std::vector<double> part(ld);
+    HIPCHK(hipMemcpyAsync(part.data(), c.fro, ld * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    double f = std::sqrt(host_sum(part));
+    if (!std::isfinite(f)) return fail(ctx, CDL_E_NONFINITE, "non-finite chain level");
+    info->fro[0] = f;
+    int l = 0;
+    double rho = f;
+    while (true) {
+        rho = std::pow(f, 1.0 / std::ldexp(1.0, l));
+        bool more;
+        if (depth > 0)
+            more = l + 1 < depth;
+        else if (chain_eps > 0.0)
+            more = l + 1 < depth_max && !(rho < 1.0 && f * f / (1.0 - rho) <= chain_eps);
+        else
+            more = l + 1 < depth_max && model_wants_square(prec, n, l, f, rho);
+        if (!more) break;
+        const int ntl = square_tiles(prec, ld);
+        HIPCHK(launch_square(prec, c.levels + c.level_bytes * l, c.levels + c.level_bytes * (l + 1),
+                             ld, n, c.fro, s));
+        part.resize(ntl);
+        HIPCHK(hipMemcpyAsync(part.data(), c.fro, ntl * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        const double fprev = f;
+        f = std::sqrt(host_sum(part));
+        if (!std::isfinite(f)) return fail(ctx, CDL_E_NONFINITE, "non-finite chain level");
+        ++l;
+        info->fro[l] = f;
+        if (f >= 0.999 && f >= 0.999 * fprev && l >= 1 && (depth == 0 || l + 1 == depth)) {
+            info->depth = l + 1;
+            info->rho_hat = std::pow(f, 1.0 / std::ldexp(1.0, l));
+            return fail(ctx, CDL_E_DIVERGED,
+                        "chain levels do not decay (spectral radius >= 1; bipartite graph? try lazy)");
+        }
+    }
+    info->depth = l + 1;
+    info->rho_hat = rho;
+    return CDL_OK;
+}
+
+// ---- embedding -------------------------------------------------------------------
+
+cdl_status cdl_solve_embedding(cdl_ctx *ctx, const double *W, const double *deg,
+                               const double *stats, const int32_t *gid, int64_t n,
+                               const void *chain, const cdl_chain_info *ci, int64_t k,
+                               double eps_rp, uint64_t seed, cdl_solver solver, double tol,
+                               int max_iter, double *Z, void *ws, size_t ws_bytes,
+                               cdl_solve_info *info) {
+    if (!ctx) return CDL_E_ARG;
+    if (n < 2 || n > (1 << 20)) return fail(ctx, CDL_E_ARG, "bad n");
+    if (!W || !deg || !stats || !chain || !ci || !Z || !ws) return fail(ctx, CDL_E_ARG, "null pointer");
+    if (!aligned(W, 16) || !aligned(chain, kAlign) || !aligned(ws, kAlign) || !aligned(Z, 8))
+        return fail(ctx, CDL_E_ARG, "misaligned pointer");
+    if (k <= 0) {
+        if (!(eps_rp > 0.0 && eps_rp < 1.0)) return fail(ctx, CDL_E_ARG, "need 0 < eps_rp < 1 when k <= 0");
+        k = (int64_t)std::ceil(std::log((double)n / eps_rp));
+    }
+    if (k > (int64_t)1 << 20) return fail(ctx, CDL_E_ARG, "k too large");
+    if (ci->depth < 1 || ci->depth > CDL_MAX_DEPTH || !valid_prec(ci->prec))
+        return fail(ctx, CDL_E_ARG, "invalid chain info");
+    if (max_iter < 1 || max_iter > 64) return fail(ctx, CDL_E_ARG, "max_iter must be in [1, 64]");
+    if (solver != CDL_RICHARDSON && solver != CDL_PCG) return fail(ctx, CDL_E_ARG, "bad solver");
+    if (solver == CDL_PCG) return fail(ctx, CDL_E_UNSUPPORTED, "PCG not available in this build");
+    Arena need(nullptr);
+    plan_solve(need, n, k, ci->prec);
+    if (ws_bytes < need.off) return fail(ctx, CDL_E_WORKSPACE, "solve workspace too small");
+    Arena a(ws);
+    SolveWs w = plan_solve(a, n, k, ci->prec);
+    Arena ac((void *)chain);
+    ChainBuf c = plan_chain(ac, n, ci->prec, ci->depth);
+    const int prec = ci->prec;
+    const int64_t ld = pad_n(n), kp = pad_k(k);
+    const size_t panel = (size_t)kp * ld;
+    hipStream_t s = ctx->stream;
+    HIPCHK(hipSetDevice(ctx->device));
+    if (info) std::memset(info, 0, sizeof(*info));
+
+    HIPCHK(launch_fill_zero(w.Yt, panel * sizeof(double), s));
+    HIPCHK(launch_fill_zero(w.Xt, panel * sizeof(double), s));
+    HIPCHK(launch_rhs(W, ld, n, gid, k, kp, seed, w.Yt, s));
+    const int nparts = residual_parts(ld), ntiles = residual_tiles(ld, kp);
+    HIPCHK(launch_residual_k(w.Xt, W, w.Yt, deg, c.dm, ld, n, kp, k, 1, w.Rt, w.npart, w.mpart, s));
+    HIPCHK(launch_col_norms2(w.npart, nparts, kp, w.mpart, ntiles, w.scal, s));
+    std::vector<double> ynorm(kp), rnorm(kp);
+    HIPCHK(hipMemcpyAsync(ynorm.data(), w.scal, kp * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int64_t r = 0; r < k; ++r)
+        if (!std::isfinite(ynorm[r])) return fail(ctx, CDL_E_NONFINITE, "non-finite right-hand side");
+
+    double rel = 1.0;
+    int it = 0;
+    bool conv = false;
+    while (it < max_iter) {
+        // X += P1 R: V = D^{-1/2} R (scaled), V <- (I + S~_l) V, X += D^{-1/2} V.
+        HIPCHK(launch_prep_v2(prec, w.Rt, c.dm, ld, kp, w.scal + kp, w.V64, w.Vlo[0], s));
+        for (int l = 0; l < ci->depth; ++l) {
+            const bool last = l + 1 == ci->depth;
+            HIPCHK(launch_apply(prec, w.Vlo[l & 1], c.levels + c.level_bytes * l, w.Vlo[(l + 1) & 1],
+                                w.V64, ld, n, kp, w.Xt, c.dm, last ? w.scal + kp + 1 : nullptr, s));
+        }
+        ++it;
+        HIPCHK(launch_residual_k(w.Xt, W, w.Yt, deg, c.dm, ld, n, kp, k, 0, w.Rt, w.npart,
+                                 w.mpart, s));
+        HIPCHK(launch_col_norms2(w.npart, nparts, kp, w.mpart, ntiles, w.scal, s));
+        HIPCHK(hipMemcpyAsync(rnorm.data(), w.scal, kp * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        rel = 0.0;
+        for (int64_t r = 0; r < k; ++r) {
+            if (!std::isfinite(rnorm[r])) return fail(ctx, CDL_E_NONFINITE, "non-finite residual");
+            if (ynorm[r] > 0.0) rel = std::max(rel, rnorm[r] / ynorm[r]);
+        }
+        if (info && it <= 64) info->history[it - 1] = rel;
+        if (tol > 0.0 && rel <= tol) {
+            conv = true;
+            break;
+        }
+    }
+    HIPCHK(launch_finalize_z2(w.Xt, ld, n, kp, k, w.mean, Z, s));
+    if (info) {
+        info->iterations = it;
+        info->converged = conv || tol <= 0.0;
+        info->rel_residual = rel;
+    }
+    if (tol > 0.0 && !conv) {
+        char buf[160];
+        std::snprintf(buf, sizeof(buf), "residual %.3e > tol %.3e after %d iterations", rel, tol, it);
+        return fail(ctx, CDL_E_NOCONV, buf);
+    }
+    return CDL_OK;
+}
+
+// ---- scores -----------------------------------------------------------------------
+
+static cdl_status check_map(cdl_ctx *ctx, const int32_t *map, int64_t m, int64_t n) {
+    if (!map) return m == n ? CDL_OK : fail(ctx, CDL_E_ARG, "identity map needs m == n");
+    std::vector<int32_t> h(m);
+    HIPCHK(hipMemcpyAsync(h.data(), map, m * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (int32_t v : h)
+        if (v < 0 || v >= n) return fail(ctx, CDL_E_ARG, "map entry out of range");
+    return CDL_OK;
+}
+
+cdl_status cdl_anomaly_scores(cdl_ctx *ctx, const double *Z0, const double *W0,
+                              const double *stats0, int64_t n0, const double *Z1,
+                              const double *W1, const double *stats1, int64_t n1, int64_t k,
+                              const int32_t *map0, const int32_t *map1, int64_t m,
+                              cdl_score_mode mode, double *F, int32_t top_k, int32_t *top_idx,
+                              void *ws, size_t ws_bytes) {
+    if (!ctx) return CDL_E_ARG;
+    if (n0 < 2 || n1 < 2 || m < 1 || m > std::min(n0, n1) || k < 1)
+        return fail(ctx, CDL_E_ARG, "bad sizes");
+    if (!Z0 || !Z1 || !stats0 || !stats1 || !F || !ws) return fail(ctx, CDL_E_ARG, "null pointer");
+    if (mode != CDL_SCORE_UNWEIGHTED && mode != CDL_SCORE_DELTA_A) return fail(ctx, CDL_E_ARG, "bad mode");
+    if (mode == CDL_SCORE_DELTA_A && (!W0 || !W1)) return fail(ctx, CDL_E_ARG, "weighted mode needs W0, W1");
+    if (top_k < 0 || top_k > CDL_MAX_TOPK || top_k > m || (top_k > 0 && !top_idx))
+        return fail(ctx, CDL_E_ARG, "bad top_k");
+    if (!aligned(ws, kAlign) || !aligned(Z0, 8) || !aligned(Z1, 8)) return fail(ctx, CDL_E_ARG, "misaligned pointer");
+    if ((map0 == nullptr) != (map1 == nullptr)) return fail(ctx, CDL_E_ARG, "give both maps or neither");
+    Arena need(nullptr);
+    plan_score(need, m, k);
+    if (ws_bytes < need.off) return fail(ctx, CDL_E_WORKSPACE, "score workspace too small");
+    HIPCHK(hipSetDevice(ctx->device));
+    cdl_status st = check_map(ctx, map0, m, n0);
+    if (st != CDL_OK) return st;
+    st = check_map(ctx, map1, m, n1);
+    if (st != CDL_OK) return st;
+    Arena a(ws);
+    ScoreWs w = plan_score(a, m, k);
+    const int64_t mp = pad_n(m), kp = pad_k(k);
+    hipStream_t s = ctx->stream;
+    HIPCHK(launch_build_zhat(Z0, Z1, map0, map1, m, mp, k, kp, stats0, stats1, w.Zh, w.Zhe, w.sq, s));
+    HIPCHK(launch_score(w.Zh, w.Zhe, kp, w.sq, m, mp, W0, pad_n(n0), W1, pad_n(n1), map0, map1,
+                        mode == CDL_SCORE_DELTA_A, w.part, s));
+    HIPCHK(launch_score_reduce(w.part, score_tiles_1d(mp), m, mp, F, s));
+    if (top_k > 0) HIPCHK(launch_topk(F, m, top_k, w.topk, top_idx, s));
+    return CDL_OK;
+}
+
+// ---- sequence ------------------------------------------------------------------------
+
+} // extern "C"
+
+namespace {
+struct SeqPlan {
+    int64_t nmax = 0, Tmax = 0, mmax = 0;
+};
+SeqPlan seq_plan(int32_t n_snap, const cdl_snapshot *sn) {
+    SeqPlan p;
+    for (int t = 0; t < n_snap; ++t) {
+        p.nmax = std::max(p.nmax, sn[t].n);
+        p.Tmax = std::max(p.Tmax, sn[t].T);
+    }
+    p.mmax = p.nmax;
+    return p;
+}
+size_t seq_bytes(const SeqPlan &p, const cdl_seq_params *q) {
+    const int dmax = q->depth > 0 ? q->depth : q->depth_max;
+    size_t g = 0, c = 0, so = 0, sc = 0;
+    cdl_workspace_bytes(p.nmax, p.Tmax, q->k, dmax, q->prec, &g, &c, &so, &sc);
+    const size_t ld = (size_t)pad_n(p.nmax);
+    size_t tot = 0;
+    tot += 2 * al(ld * ld * sizeof(double));                    // W ping-pong
+    tot += 2 * al(ld * sizeof(double));                          // deg
+    tot += 2 * al(CDL_GRAPH_STATS * sizeof(double));             // stats
+    tot += 2 * al((size_t)p.nmax * q->k * sizeof(double));       // Z ping-pong
+    tot += 2 * al((size_t)p.mmax * sizeof(int32_t));             // maps
+    tot += g + c + so + sc;
+    return tot;
+}
+} // namespace
+
+extern "C" {
+
+cdl_status cdl_sequence_workspace_bytes(int32_t n_snap, const cdl_snapshot *snaps,
+                                        const cdl_seq_params *p, size_t *bytes) {
+    if (n_snap < 2 || !snaps || !p || !bytes || p->k < 1) return CDL_E_ARG;
+    for (int t = 0; t < n_snap; ++t)
+        if (snaps[t].n < 2 || snaps[t].T < 1) return CDL_E_ARG;
+    *bytes = seq_bytes(seq_plan(n_snap, snaps), p);
+    return CDL_OK;
+}
+
+cdl_status cdl_score_sequence(cdl_ctx *ctx, int32_t n_snap, const cdl_snapshot *sn,
+                              const cdl_seq_params *q, double *const *F, int32_t *const *top_idx,
+                              void *ws, size_t ws_bytes, cdl_seq_info *info) {
+    if (!ctx) return CDL_E_ARG;
+    if (n_snap < 2 || !sn || !q || !F || !ws) return fail(ctx, CDL_E_ARG, "bad arguments");
+    for (int t = 0; t < n_snap; ++t) {
+        if (!sn[t].X || !sn[t].gid || !sn[t].gid_host || sn[t].n < 2)
+            return fail(ctx, CDL_E_ARG, "bad snapshot");
+        for (int64_t i = 1; i < sn[t].n; ++i)
+            if (sn[t].gid_host[i] <= sn[t].gid_host[i - 1])
+                return fail(ctx, CDL_E_ARG, "global ids must be strictly increasing");
+        if (sn[t].gid_host[sn[t].n - 1] >= (1 << 20) || sn[t].gid_host[0] < 0)
+            return fail(ctx, CDL_E_ARG, "global ids must be in [0, 2^20)");
+    }
+    const SeqPlan plan = seq_plan(n_snap, sn);
+    if (ws_bytes < seq_bytes(plan, q)) return fail(ctx, CDL_E_WORKSPACE, "sequence workspace too small");
+    const int dmax = q->depth > 0 ? q->depth : q->depth_max;
+    size_t gB = 0, cB = 0, soB = 0, scB = 0;
+    cdl_workspace_bytes(plan.nmax, plan.Tmax, q->k, dmax, q->prec, &gB, &cB, &soB, &scB);
+    Arena a(ws);
+    const size_t ld = (size_t)pad_n(plan.nmax);
+    double *Wb[2] = {a.take<double>(ld * ld), a.take<double>(ld * ld)};
+    double *degb[2] = {a.take<double>(ld), a.take<double>(ld)};
+    double *stb[2] = {a.take<double>(CDL_GRAPH_STATS), a.take<double>(CDL_GRAPH_STATS)};
+    double *Zb[2] = {a.take<double>((size_t)plan.nmax * q->k), a.take<double>((size_t)plan.nmax * q->k)};
+    int32_t *mapb[2] = {a.take<int32_t>(plan.mmax), a.take<int32_t>(plan.mmax)};
+    char *gws = a.take<char>(gB), *cws = a.take<char>(cB), *sows = a.take<char>(soB), *scws = a.take<char>(scB);
+    if (info) std::memset(info, 0, sizeof(*info));
+    hipStream_t s = ctx->stream;
+    for (int t = 0; t < n_snap; ++t) {
+        const int b = t & 1;
+        const cdl_snapshot &x = sn[t];
+        cdl_status st = cdl_build_graph(ctx, x.X, x.n, x.T, x.ldx, q->sigma, Wb[b], degb[b], stb[b], gws, gB);
+        if (st == CDL_OK) st = cdl_check_graph(ctx, degb[b], stb[b], x.n, nullptr);
+        cdl_chain_info ci;
+        if (st == CDL_OK)
+            st = cdl_build_chain(ctx, Wb[b], degb[b], stb[b], x.n, q->prec, q->depth, dmax, q->chain_eps,
+                                 0, cws, cB, &ci);
+        cdl_solve_info si;
+        if (st == CDL_OK)
+            st = cdl_solve_embedding(ctx, Wb[b], degb[b], stb[b], x.gid, x.n, cws, &ci, q->k, 0.0, q->seed,
+                                     q->solver, q->tol, q->max_iter, Zb[b], sows, soB, &si);
+        if (st != CDL_OK) {
+            ctx->err = "snapshot " + std::to_string(t) + ": " + ctx->err;
+            return st;
+        }
+        if (info) {
+            info->max_iterations = std::max(info->max_iterations, si.iterations);
+            info->max_rel_residual = std::max(info->max_rel_residual, si.rel_residual);
+        }
+        if (t == 0) continue;
+        // common nodes of (t-1, t) in ascending global id order
+        const cdl_snapshot &y = sn[t - 1];
+        std::vector<int32_t> m0, m1;
+        int64_t i = 0, j = 0;
+        while (i < y.n && j < x.n) {
+            if (y.gid_host[i] == x.gid_host[j]) { m0.push_back((int32_t)i); m1.push_back((int32_t)j); ++i; ++j; }
+            else if (y.gid_host[i] < x.gid_host[j]) ++i;
+            else ++j;
+        }
+        const int64_t m = (int64_t)m0.size();
+        if (m < 2) return fail(ctx, CDL_E_GRAPH, "consecutive snapshots share fewer than two nodes");
+        HIPCHK(hipMemcpyAsync(mapb[0], m0.data(), m * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(mapb[1], m1.data(), m * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        const int pb = b ^ 1;
+        const int32_t K = top_idx ? std::min<int32_t>(q->top_k, (int32_t)m) : 0;
+        st = cdl_anomaly_scores(ctx, Zb[pb], Wb[pb], stb[pb], y.n, Zb[b], Wb[b], stb[b], x.n, q->k,
+                                mapb[0], mapb[1], m, q->mode, F[t - 1], K,
+                                top_idx ? top_idx[t - 1] : nullptr, scws, scB);
+        if (st != CDL_OK) return st;
+        HIPCHK(hipStreamSynchronize(s));   // host maps are reused next pair
+        if (info) info->pairs += 1;
+    }
+    return CDL_OK;
+}
+
+} // extern "C"

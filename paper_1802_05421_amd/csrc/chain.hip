@@ -1,0 +1,271 @@
+// Inverse chain (eq. inverse-chain; Algorithm 2, ChainProduct) on MFMA.
+//
+//   chain_prep  dmn = D^{-1/2}, dm = (cD)^{-1/2} (c = 2 for the lazy walk),
+//               u = D^{1/2} 1 / sqrt(vol)
+//   normalize   S~_0 = D^{-1/2} W D^{-1/2} - u u^T  (lazy: (I + S)/2 - u u^T),
+//               computed in FP64, rounded to the storage type; removing the
+//               eigenvalue-1 mode u makes every power decay (the chain only
+//               ever multiplies vectors orthogonal to u, where S~ = S)
+//   square      S~_{l+1} = S~_l S~_l^T (= S~_l^2, S~ symmetric): upper
+//               triangular output tiles with mirrored stores, FP32
+//               accumulation (FP64 for FP64 levels), per-tile Frobenius sums
+//   apply       V <- V + S~_l V for the k columns at once (one level of
+//               P1 = D^{-1/2} prod_l (I + S~^{2^l}) D^{-1/2}); V kept in FP64,
+//               the MFMA operand is V rounded to the storage type; on the
+//               last level X += dm * V.
+//
+// FP16 levels hold scale * S~ (scale = a power of two near n) so entries of
+// order 1/n stay in FP16's normal range; the squaring and the application
+// divide the scale back out.
+#include "common.h"
+#include "gemm.h"
+#include "kernels.h"
+
+namespace cdl {
+
+__device__ inline double block_sum256c(double v, double *red) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+float level_scale(int prec, int64_t n) {
+    if (prec != 3) return 1.0f;
+    float s = 1.0f;
+    while (s * 2.0f <= (float)n) s *= 2.0f;
+    return s;
+}
+
+__global__ void k_chain_prep(const double *deg, const double *stats, int64_t n, int64_t ld,
+                             int lazy, double *dmn, double *dm, double *u) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ld) return;
+    if (i < n) {
+        const double d = deg[i], vol = stats[0];
+        dmn[i] = 1.0 / sqrt(d);
+        dm[i] = 1.0 / sqrt(lazy ? 2.0 * d : d);
+        u[i] = sqrt(d / vol);
+    } else {
+        dmn[i] = dm[i] = u[i] = 0.0;
+    }
+}
+
+hipError_t launch_chain_prep(const double *deg, const double *stats, int64_t n, int64_t ld,
+                             int lazy, double *dmn, double *dm, double *u, hipStream_t s) {
+    hipLaunchKernelGGL(k_chain_prep, dim3((unsigned)cdiv(ld, 256)), dim3(256), 0, s, deg,
+                       stats, n, ld, lazy, dmn, dm, u);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_normalize(const double *W, int64_t ld, int64_t n,
+                                                   const double *dmn, const double *u, int lazy,
+                                                   double scale, T *S0, double *fro_part) {
+    __shared__ double red[4];
+    const int64_t i = blockIdx.x;
+    double s = 0.0;
+    const double di = i < n ? dmn[i] : 0.0, ui = i < n ? u[i] : 0.0;
+    for (int64_t j = threadIdx.x; j < ld; j += 256) {
+        double v = 0.0;
+        if (i < n && j < n) {
+            v = W[i * ld + j] * (di * dmn[j]);   // symmetric rounding: (i,j) == (j,i)
+            if (lazy) v = 0.5 * ((i == j ? 1.0 : 0.0) + v);
+            v -= ui * u[j];
+        }
+        T t = cvtd<T>(v * scale);
+        S0[i * ld + j] = t;
+        double tv = tod<T>(t) / scale;
+        s += tv * tv;
+    }
+    s = block_sum256c(s, red);
+    if (threadIdx.x == 0) fro_part[i] = s;
+}
+
+hipError_t launch_normalize(int prec, const double *W, int64_t ld, int64_t n,
+                            const double *dmn, const double *u, int lazy, void *S0,
+                            double *fro_part, hipStream_t s) {
+    const double sc = level_scale(prec, n);
+    dim3 g((unsigned)ld), b(256);
+    switch (prec) {
+    case 0: hipLaunchKernelGGL(k_normalize<double>, g, b, 0, s, W, ld, n, dmn, u, lazy, sc, (double *)S0, fro_part); break;
+    case 1: hipLaunchKernelGGL(k_normalize<float>, g, b, 0, s, W, ld, n, dmn, u, lazy, sc, (float *)S0, fro_part); break;
+    case 2: hipLaunchKernelGGL(k_normalize<__bf16>, g, b, 0, s, W, ld, n, dmn, u, lazy, sc, (__bf16 *)S0, fro_part); break;
+    case 3: hipLaunchKernelGGL(k_normalize<_Float16>, g, b, 0, s, W, ld, n, dmn, u, lazy, sc, (_Float16 *)S0, fro_part); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Symmetric squaring.
+
+template <typename T> struct SqCfg;
+template <> struct SqCfg<__bf16> { using Core = GemmCore<MfmaBF16, 256, 256, 64, 2, 4>; static constexpr int TILE = 256; };
+template <> struct SqCfg<_Float16> { using Core = GemmCore<MfmaF16, 256, 256, 64, 2, 4>; static constexpr int TILE = 256; };
+template <> struct SqCfg<float> { using Core = GemmCore<MfmaF32, 128, 128, 32, 2, 2>; static constexpr int TILE = 128; };
+template <> struct SqCfg<double> { using Core = GemmCore<MfmaF64, 128, 128, 16, 2, 2>; static constexpr int TILE = 128; };
+
+template <typename T> constexpr size_t sq_smem() {
+    using C = typename SqCfg<T>::Core;
+    constexpr int TL = SqCfg<T>::TILE;
+    constexpr size_t stage = (size_t)TL * (TL + 16 / sizeof(T)) * sizeof(T);
+    return C::SMEM > stage ? C::SMEM : stage;
+}
+
+template <typename T>
+__global__ __launch_bounds__(SqCfg<T>::Core::NT) void k_square(const T *S, T *S2, int64_t ld, int64_t kend,
+                                                int nt, float inv_scale, double *fro_part) {
+    using Core = typename SqCfg<T>::Core;
+    constexpr int TL = SqCfg<T>::TILE;
+    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+    T *smem = (T *)smem_raw;
+    __shared__ double red[Core::NT / 64];
+    const int total = nt * (nt + 1) / 2;
+    const int id = xcd_remap(blockIdx.x, total);
+    int I, J;
+    sym_tile<8>(id, nt, I, J);
+    const int64_t m0 = (int64_t)I * TL, n0 = (int64_t)J * TL;
+    Core g;
+    g.run(S, ld, S, ld, m0, n0, kend, smem);
+    double fro = 0.0;
+    auto f = [&](int, int, typename Core::MF::Acc acc) -> T {
+        T t = (T)(acc * inv_scale);
+        double tv = tod<T>(t) * (double)inv_scale;
+        fro += tv * tv;
+        return t;
+    };
+    stage_and_store(g, smem, f, S2, ld, m0, n0, I != J);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) fro += __shfl_xor(fro, o);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = fro;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int q = 0; q < Core::NT / 64; ++q) t += red[q];
+        fro_part[id] = (I != J ? 2.0 : 1.0) * t;
+    }
+}
+
+int square_tiles(int prec, int64_t ld) {
+    int TL = (prec == 2 || prec == 3) ? 256 : 128;
+    int nt = (int)(ld / TL);
+    return nt * (nt + 1) / 2;
+}
+
+template <typename T>
+static hipError_t sq_launch(const void *S, void *S2, int64_t ld, int64_t n, float inv_scale,
+                            double *fro_part, hipStream_t s) {
+    constexpr int TL = SqCfg<T>::TILE;
+    constexpr size_t smem = sq_smem<T>();
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_square<T>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const int nt = (int)(ld / TL);
+    const int total = nt * (nt + 1) / 2;
+    constexpr int BK = (int)(64 * 2 / sizeof(T)) < 16 ? 16 : (int)(64 * 2 / sizeof(T));
+    const int64_t kend = (n + 63) / 64 * 64;   // multiple of every BK used (64/32/16)
+    (void)BK;
+    hipLaunchKernelGGL(k_square<T>, dim3(total), dim3(SqCfg<T>::Core::NT), smem, s, (const T *)S, (T *)S2, ld,
+                       kend, nt, inv_scale, fro_part);
+    return hipGetLastError();
+}
+
+hipError_t launch_square(int prec, const void *S, void *S2, int64_t ld, int64_t n,
+                         double *fro_part, hipStream_t s) {
+    const float inv = 1.0f / level_scale(prec, n);
+    switch (prec) {
+    case 0: return sq_launch<double>(S, S2, ld, n, inv, fro_part, s);
+    case 1: return sq_launch<float>(S, S2, ld, n, inv, fro_part, s);
+    case 2: return sq_launch<__bf16>(S, S2, ld, n, inv, fro_part, s);
+    case 3: return sq_launch<_Float16>(S, S2, ld, n, inv, fro_part, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Chain application: C[r][i] = sum_j Vin[r][j] S~[i][j]  (= (S~ V)_{i r}).
+
+template <typename T> struct ApBK { static constexpr int v = 64 * 2 / (int)sizeof(T) < 16 ? 16 : 64 * 2 / (int)sizeof(T); };
+
+template <typename T, int BM>
+__global__ __launch_bounds__(BM) void k_apply(const T *Vin, const T *S, T *Vout, double *V64,
+                                              int64_t ld, int64_t kend, int mt, int nt,
+                                              float inv_scale, double *Xt, const double *dm,
+                                              const double *inv_vs) {
+    using Mf = typename MfmaOf<T>::type;
+    using Core = GemmCore<Mf, BM, 64, ApBK<T>::v, BM / 64, 1>;
+    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+    T *smem = (T *)smem_raw;
+    int I, J;
+    rect_tile<4>(xcd_remap(blockIdx.x, mt * nt), mt, nt, I, J);
+    const int64_t m0 = (int64_t)I * BM, n0 = (int64_t)J * 64;
+    Core g;
+    g.run(Vin, ld, S, ld, m0, n0, kend, smem);
+    const double ivs = inv_vs ? *inv_vs : 0.0;
+#pragma unroll
+    for (int a = 0; a < Core::WTM; ++a)
+#pragma unroll
+        for (int b = 0; b < Core::WTN; ++b)
+#pragma unroll
+            for (int r = 0; r < Mf::R; ++r) {
+                const int64_t row = m0 + Core::row_of(a, r), col = n0 + Core::col_of(b);
+                const int64_t o = row * ld + col;
+                double v = V64[o] + (double)g.acc[a][b][r] * (double)inv_scale;
+                V64[o] = v;
+                Vout[o] = cvtd<T>(v);
+                if (inv_vs) Xt[o] += dm[col] * v * ivs;
+            }
+}
+
+template <typename T, int BM>
+static hipError_t ap_launch(const void *Vin, const void *S, void *Vout, double *V64, int64_t ld,
+                            int64_t n, int64_t kpad, float inv_scale, double *Xt,
+                            const double *dm, const double *inv_vs, hipStream_t s) {
+    using Mf = typename MfmaOf<T>::type;
+    using Core = GemmCore<Mf, BM, 64, ApBK<T>::v, BM / 64, 1>;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_apply<T, BM>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)Core::SMEM);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const int mt = (int)(kpad / BM), nt = (int)(ld / 64);
+    const int64_t kend = (n + 63) / 64 * 64;
+    hipLaunchKernelGGL((k_apply<T, BM>), dim3(mt * nt), dim3(BM), Core::SMEM, s, (const T *)Vin,
+                       (const T *)S, (T *)Vout, V64, ld, kend, mt, nt, inv_scale, Xt, dm, inv_vs);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t ap_dispatch(const void *Vin, const void *S, void *Vout, double *V64,
+                              int64_t ld, int64_t n, int64_t kpad, float inv_scale, double *Xt,
+                              const double *dm, const double *inv_vs, hipStream_t s) {
+    if (kpad % 256 == 0) return ap_launch<T, 256>(Vin, S, Vout, V64, ld, n, kpad, inv_scale, Xt, dm, inv_vs, s);
+    if (kpad % 128 == 0) return ap_launch<T, 128>(Vin, S, Vout, V64, ld, n, kpad, inv_scale, Xt, dm, inv_vs, s);
+    return ap_launch<T, 64>(Vin, S, Vout, V64, ld, n, kpad, inv_scale, Xt, dm, inv_vs, s);
+}
+
+hipError_t launch_apply(int prec, const void *Vin, const void *S, void *Vout, double *V64,
+                        int64_t ld, int64_t n, int64_t kpad, double *Xt, const double *dm,
+                        const double *inv_vs, hipStream_t s) {
+    const float inv = 1.0f / level_scale(prec, n);
+    switch (prec) {
+    case 0: return ap_dispatch<double>(Vin, S, Vout, V64, ld, n, kpad, inv, Xt, dm, inv_vs, s);
+    case 1: return ap_dispatch<float>(Vin, S, Vout, V64, ld, n, kpad, inv, Xt, dm, inv_vs, s);
+    case 2: return ap_dispatch<__bf16>(Vin, S, Vout, V64, ld, n, kpad, inv, Xt, dm, inv_vs, s);
+    case 3: return ap_dispatch<_Float16>(Vin, S, Vout, V64, ld, n, kpad, inv, Xt, dm, inv_vs, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+} // namespace cdl

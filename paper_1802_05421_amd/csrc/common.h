@@ -1,0 +1,159 @@
+// Shared definitions for the gfx950 kernels of libcaddelag.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+typedef __attribute__((__vector_size__(4 * sizeof(double)))) double f64x4;
+
+namespace cdl {
+
+// n x n matrices are stored with ld = n rounded up to kPadN rows and columns.
+constexpr int kPadN = 256;
+// Vectors of k projections are padded to a multiple of kPadK columns.
+constexpr int kPadK = 64;
+constexpr int kNumXcd = 8;
+
+inline int64_t ld_of(int64_t n) { return (n + kPadN - 1) / kPadN * kPadN; }
+inline int64_t kpad_of(int64_t k) { return (k + kPadK - 1) / kPadK * kPadK; }
+
+__host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------------------
+// MFMA families.  Operand layout (checked on gfx950 hardware): for an
+// instruction computing an M x M tile over KI reduction steps, lane l holds
+// E consecutive reduction elements k = E*(l / M) .. +E-1 of row (l % M) of
+// both operands (A row-major along k; B given as its transpose, also
+// row-major along k).  Accumulator element r of lane l is (crow, ccol).
+
+struct MfmaBF16 {
+    using T = __bf16;
+    using Frag = bf16x8;
+    using Acc = float;
+    using AccV = f32x16;
+    static constexpr int M = 32, KI = 16, E = 8, R = 16;
+    __device__ static inline AccV mma(const Frag &a, const Frag &b, const AccV &c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    }
+    __device__ static inline int crow(int lane, int r) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
+    __device__ static inline int ccol(int lane) { return lane & 31; }
+};
+
+struct MfmaF16 {
+    using T = _Float16;
+    using Frag = f16x8;
+    using Acc = float;
+    using AccV = f32x16;
+    static constexpr int M = 32, KI = 16, E = 8, R = 16;
+    __device__ static inline AccV mma(const Frag &a, const Frag &b, const AccV &c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+    }
+    __device__ static inline int crow(int lane, int r) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
+    __device__ static inline int ccol(int lane) { return lane & 31; }
+};
+
+struct MfmaF32 {
+    using T = float;
+    using Frag = float;
+    using Acc = float;
+    using AccV = f32x16;
+    static constexpr int M = 32, KI = 2, E = 1, R = 16;
+    __device__ static inline AccV mma(const Frag &a, const Frag &b, const AccV &c) {
+        return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static inline int crow(int lane, int r) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
+    __device__ static inline int ccol(int lane) { return lane & 31; }
+};
+
+struct MfmaF64 {
+    using T = double;
+    using Frag = double;
+    using Acc = double;
+    using AccV = f64x4;
+    static constexpr int M = 16, KI = 4, E = 1, R = 4;
+    __device__ static inline AccV mma(const Frag &a, const Frag &b, const AccV &c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static inline int crow(int lane, int r) { return (lane >> 4) + 4 * r; }
+    __device__ static inline int ccol(int lane) { return lane & 15; }
+};
+
+template <typename T> struct MfmaOf;
+template <> struct MfmaOf<__bf16> { using type = MfmaBF16; };
+template <> struct MfmaOf<_Float16> { using type = MfmaF16; };
+template <> struct MfmaOf<float> { using type = MfmaF32; };
+template <> struct MfmaOf<double> { using type = MfmaF64; };
+
+// Conversions from float/double accumulators to storage types (round to
+// nearest even).
+template <typename T> __device__ inline T cvt(float x);
+template <> __device__ inline __bf16 cvt<__bf16>(float x) { return (__bf16)x; }
+template <> __device__ inline _Float16 cvt<_Float16>(float x) { return (_Float16)x; }
+template <> __device__ inline float cvt<float>(float x) { return x; }
+template <> __device__ inline double cvt<double>(float x) { return (double)x; }
+
+template <typename T> __device__ inline T cvtd(double x);
+template <> __device__ inline __bf16 cvtd<__bf16>(double x) { return (__bf16)(float)x; }
+template <> __device__ inline _Float16 cvtd<_Float16>(double x) { return (_Float16)(float)x; }
+template <> __device__ inline float cvtd<float>(double x) { return (float)x; }
+template <> __device__ inline double cvtd<double>(double x) { return x; }
+
+template <typename T> __device__ inline double tod(T x) { return (double)(float)x; }
+template <> __device__ inline double tod<double>(double x) { return x; }
+
+// ---------------------------------------------------------------------------
+// Workgroup -> tile maps.  Workgroups are dispatched round-robin over the 8
+// XCDs, each with its own L2; remapping so that consecutive logical tiles
+// land on the same XCD lets neighbouring tiles share operand panels in L2.
+
+__device__ inline int xcd_remap(int w, int total) {
+    int x = w % kNumXcd, j = w / kNumXcd;
+    int base = total / kNumXcd, rem = total % kNumXcd;
+    return x * base + (x < rem ? x : rem) + j;
+}
+
+// Upper-triangular tile (I <= J) of an nt x nt tile grid, grouped in bands
+// of G tile rows: band g enumerates the G x G diagonal triangle column by
+// column, then the rectangular part column by column, so that a run of
+// consecutive ids covers a compact G-row block.
+template <int G>
+__device__ inline void sym_tile(int id, int nt, int &I, int &J) {
+    int g0 = 0;
+    while (true) {
+        int h = nt - g0 < G ? nt - g0 : G;
+        int tri = h * (h + 1) / 2;
+        int cnt = tri + (nt - g0 - h) * h;
+        if (id < cnt) {
+            if (id < tri) {
+                int c = 0;
+                while ((c + 1) * (c + 2) / 2 <= id) ++c;
+                J = g0 + c;
+                I = g0 + (id - c * (c + 1) / 2);
+            } else {
+                int q = id - tri;
+                J = g0 + h + q / h;
+                I = g0 + q % h;
+            }
+            return;
+        }
+        id -= cnt;
+        g0 += G;
+    }
+}
+
+// Rectangular mt x nt tile grid in column bands of G tile columns.
+template <int G>
+__device__ inline void rect_tile(int id, int mt, int nt, int &I, int &J) {
+    int band = id / (G * mt);
+    int j0 = band * G;
+    int w = nt - j0 < G ? nt - j0 : G;
+    int q = id - band * G * mt;
+    I = q / w;
+    J = j0 + q % w;
+}
+
+} // namespace cdl

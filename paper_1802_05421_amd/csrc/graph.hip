@@ -1,0 +1,322 @@
+// Graph construction for one snapshot (Section "Climate Data": fully
+// connected graph with Gaussian-kernel weights of the distance between node
+// series; Background: symmetric A, no self-edges, volume V_G = sum_i D(i,i)).
+//
+//   pad_series   copy X into a zero-padded FP64 panel, row norms ||x_i||^2
+//   gram_dist    D2_ij = ||x_i||^2 + ||x_j||^2 - 2 x_i.x_j on FP64 MFMA,
+//                upper-triangular tiles written with their mirror
+//   select       exact lower median of D2 over i < j by 6 radix passes over
+//                the IEEE-754 bit patterns (order-preserving for D2 >= 0)
+//   exp_degree   W = exp(-D2 / sigma^2) in place, W_ii = 0, deg = row sums
+//   graph_stats  vol = sum deg, min and max degree (fixed-order reductions)
+#include "common.h"
+#include "gemm.h"
+#include "kernels.h"
+
+namespace cdl {
+
+int64_t pad_n(int64_t n) { return ld_of(n); }
+int64_t pad_k(int64_t k) { return kpad_of(k); }
+int64_t pad_t(int64_t T) { return (T + 15) / 16 * 16; }
+
+// Deterministic sum over a 64-lane wave (xor butterfly, same order everywhere).
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Deterministic sum over a 256-thread block; result valid in every thread.
+__device__ inline double block_sum256(double v, double *red) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// ---------------------------------------------------------------------------
+
+__global__ void k_fill_zero(uint4 *p, size_t n16) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n16; i += stride) p[i] = make_uint4(0, 0, 0, 0);
+}
+
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return hipSuccess;
+    if (bytes % 16 || ((uintptr_t)p) % 16) return hipErrorInvalidValue;
+    size_t n16 = bytes / 16;
+    int grid = (int)(n16 / 256 + 1 < 8192 ? n16 / 256 + 1 : 8192);
+    hipLaunchKernelGGL(k_fill_zero, dim3(grid), dim3(256), 0, s, (uint4 *)p, n16);
+    return hipGetLastError();
+}
+
+// One wave per (padded) row.
+__global__ void k_pad_series(const double *X, int64_t n, int64_t T, int64_t ldx,
+                             double *Xp, int64_t Tp, double *sqn, int *flags) {
+    const int64_t i = blockIdx.x;
+    const int lane = threadIdx.x;
+    double s = 0.0;
+    int bad = 0;
+    for (int64_t t = lane; t < Tp; t += 64) {
+        double v = (i < n && t < T) ? X[i * ldx + t] : 0.0;
+        if (!isfinite(v)) bad = 1;
+        Xp[i * Tp + t] = v;
+        s += v * v;
+    }
+    s = wave_sum(s);
+    if (lane == 0) sqn[i] = s;
+    if (bad) atomicOr(flags, 1);
+}
+
+hipError_t launch_pad_series(const double *X, int64_t n, int64_t T, int64_t ldx,
+                             double *Xp, int64_t rows, int64_t Tp, double *sqn,
+                             int *flags, hipStream_t s) {
+    hipLaunchKernelGGL(k_pad_series, dim3((unsigned)rows), dim3(64), 0, s, X, n, T, ldx, Xp,
+                       Tp, sqn, flags);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Squared distances from the Gram matrix of the series (FP64 MFMA).
+
+using GramCore = GemmCore<MfmaF64, 128, 128, 16, 2, 2>;
+constexpr size_t kGramSmem = 128 * (128 + 2) * sizeof(double);
+static_assert(kGramSmem >= GramCore::SMEM, "staging must cover the operand ring");
+
+__global__ __launch_bounds__(256) void k_gram_dist(const double *Xp, int64_t Tp,
+                                                   const double *sqn, int64_t n, int64_t ld,
+                                                   double *D2, int nt) {
+    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+    double *smem = (double *)smem_raw;
+    const int total = nt * (nt + 1) / 2;
+    int I, J;
+    sym_tile<8>(xcd_remap(blockIdx.x, total), nt, I, J);
+    const int64_t m0 = (int64_t)I * 128, n0 = (int64_t)J * 128;
+    GramCore g;
+    g.run(Xp, Tp, Xp, Tp, m0, n0, Tp, smem);
+    auto f = [&](int r, int c, double acc) -> double {
+        const int64_t a = m0 + r, b = n0 + c;
+        if (a >= n || b >= n || a == b) return 0.0;
+        double d = sqn[a] + sqn[b] - 2.0 * acc;
+        return d < 0.0 ? 0.0 : d;
+    };
+    stage_and_store(g, smem, f, D2, ld, m0, n0, I != J);
+}
+
+hipError_t launch_gram_dist(const double *Xp, int64_t Tp, const double *sqn, int64_t n,
+                            int64_t ld, double *D2, hipStream_t s) {
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_gram_dist,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)kGramSmem);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const int nt = (int)(ld / 128);
+    const int total = nt * (nt + 1) / 2;
+    hipLaunchKernelGGL(k_gram_dist, dim3(total), dim3(256), kGramSmem, s, Xp, Tp, sqn, n, ld,
+                       D2, nt);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Exact selection of the element of rank floor((N-1)/2), N = n(n-1)/2, among
+// D2_ij (i < j).  D2 >= 0, so its bit pattern orders like its value.
+
+__global__ void k_select_init(SelectState *st, int64_t n) {
+    for (int b = threadIdx.x; b < 4096; b += blockDim.x) st->hist[b] = 0;
+    if (threadIdx.x == 0) {
+        unsigned long long N = (unsigned long long)n * (unsigned long long)(n - 1) / 2ull;
+        st->prefix = 0ull;
+        st->rank = (N - 1ull) / 2ull;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_select_hist(const double *D2, int64_t ld, int64_t n,
+                                                     SelectState *st, int shift, int width) {
+    __shared__ unsigned int h[4096];
+    for (int b = threadIdx.x; b < 4096; b += 256) h[b] = 0;
+    __syncthreads();
+    const unsigned long long prefix = st->prefix;
+    const int top = shift + width;
+    const unsigned long long hi_mask = top >= 64 ? 0ull : ~((1ull << top) - 1ull);
+    const unsigned long long dmask = (1ull << width) - 1ull;
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+        const unsigned long long *row = (const unsigned long long *)(D2 + i * ld);
+        for (int64_t j = i + 1 + threadIdx.x; j < n; j += 256) {
+            unsigned long long key = row[j];
+            if ((key & hi_mask) == prefix) atomicAdd(&h[(key >> shift) & dmask], 1u);
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < 4096; b += 256)
+        if (h[b]) atomicAdd(&st->hist[b], h[b]);
+}
+
+// Pick the bin holding the wanted rank; on the last pass the prefix is the
+// full key: write sigma = sqrt(D2 value) into stats[1].
+__global__ __launch_bounds__(256) void k_select_pick(SelectState *st, int shift, int last,
+                                                     double *stats) {
+    __shared__ unsigned long long part[256];
+    const int t = threadIdx.x;
+    unsigned long long c[16], s = 0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        c[q] = st->hist[t * 16 + q];
+        s += c[q];
+    }
+    part[t] = s;
+    __syncthreads();
+    if (t == 0) {
+        unsigned long long acc = 0;
+        for (int q = 0; q < 256; ++q) {
+            unsigned long long v = part[q];
+            part[q] = acc;   // exclusive prefix
+            acc += v;
+        }
+    }
+    __syncthreads();
+    const unsigned long long rank = st->rank;
+    unsigned long long before = part[t];
+    bool mine = false;
+    int bin = 0;
+    unsigned long long newrank = 0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        if (!mine && rank >= before && rank < before + c[q]) {
+            mine = true;
+            bin = t * 16 + q;
+            newrank = rank - before;
+        }
+        before += c[q];
+    }
+    __syncthreads();
+    if (mine) {
+        unsigned long long p = st->prefix | ((unsigned long long)bin << shift);
+        st->prefix = p;
+        st->rank = newrank;
+        if (last) stats[1] = sqrt(__longlong_as_double((long long)p));
+    }
+    __syncthreads();
+    for (int b = t; b < 4096; b += 256) st->hist[b] = 0;
+}
+
+hipError_t launch_select_median(const double *D2, int64_t ld, int64_t n, SelectState *st,
+                                double *stats, hipStream_t s) {
+    hipLaunchKernelGGL(k_select_init, dim3(1), dim3(256), 0, s, st, n);
+    // 63 value bits (the sign bit is 0): five 12-bit digits, then 3 bits.
+    const int shifts[6] = {51, 39, 27, 15, 3, 0};
+    const int widths[6] = {12, 12, 12, 12, 12, 3};
+    int grid = (int)(n < 2048 ? n : 2048);
+    for (int p = 0; p < 6; ++p) {
+        hipLaunchKernelGGL(k_select_hist, dim3(grid), dim3(256), 0, s, D2, ld, n, st, shifts[p],
+                           widths[p]);
+        hipLaunchKernelGGL(k_select_pick, dim3(1), dim3(256), 0, s, st, shifts[p], p == 5 ? 1 : 0,
+                           stats);
+    }
+    return hipGetLastError();
+}
+
+__global__ void k_set_sigma(double sigma, double *stats) { stats[1] = sigma; }
+
+hipError_t launch_set_sigma(double sigma, double *stats, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_sigma, dim3(1), dim3(1), 0, s, sigma, stats);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_exp_degree(double *W, int64_t ld, int64_t n,
+                                                    const double *stats, double *deg) {
+    __shared__ double red[4];
+    const int64_t i = blockIdx.x;
+    const double sigma = stats[1];
+    const double s2 = sigma * sigma;
+    double s = 0.0;
+    double *row = W + i * ld;
+    for (int64_t j = threadIdx.x; j < ld; j += 256) {
+        double v = 0.0;
+        if (i < n && j < n && i != j) v = exp(-row[j] / s2);
+        row[j] = v;
+        s += v;
+    }
+    s = block_sum256(s, red);
+    if (threadIdx.x == 0 && i < n) deg[i] = s;
+}
+
+hipError_t launch_exp_degree(double *W, int64_t ld, int64_t n, const double *stats,
+                             double *deg, hipStream_t s) {
+    hipLaunchKernelGGL(k_exp_degree, dim3((unsigned)ld), dim3(256), 0, s, W, ld, n, stats, deg);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_graph_stats(const double *deg, int64_t n,
+                                                     double *stats) {
+    __shared__ double red[4];
+    __shared__ double rmin[256], rmax[256];
+    double s = 0.0, lo = INFINITY, hi = -INFINITY;
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        double d = deg[i];
+        s += d;
+        lo = fmin(lo, d);
+        hi = fmax(hi, d);
+        if (isnan(d)) lo = hi = d;
+    }
+    rmin[threadIdx.x] = lo;
+    rmax[threadIdx.x] = hi;
+    s = block_sum256(s, red);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = rmin[0], b = rmax[0];
+        for (int q = 1; q < 256; ++q) {
+            a = (isnan(rmin[q]) || isnan(a)) ? NAN : fmin(a, rmin[q]);
+            b = (isnan(rmax[q]) || isnan(b)) ? NAN : fmax(b, rmax[q]);
+        }
+        stats[0] = s;
+        stats[2] = a;
+        stats[3] = b;
+    }
+}
+
+hipError_t launch_graph_stats(const double *deg, int64_t n, double *stats, hipStream_t s) {
+    hipLaunchKernelGGL(k_graph_stats, dim3(1), dim3(256), 0, s, deg, n, stats);
+    return hipGetLastError();
+}
+
+// Caller-supplied weights: copy into the padded layout, zero the diagonal,
+// row sums, and flag non-finite (1), negative (2) or asymmetric (4) input.
+__global__ __launch_bounds__(256) void k_import_weights(const double *Win, int64_t ldw,
+                                                        int64_t n, double *W, int64_t ld,
+                                                        double *deg, int *flags) {
+    __shared__ double red[4];
+    const int64_t i = blockIdx.x;
+    double s = 0.0;
+    int f = 0;
+    for (int64_t j = threadIdx.x; j < ld; j += 256) {
+        double v = 0.0;
+        if (i < n && j < n && i != j) {
+            v = Win[i * ldw + j];
+            if (!isfinite(v)) f |= 1;
+            if (v < 0.0) f |= 2;
+            if (v != Win[j * ldw + i]) f |= 4;
+        }
+        W[i * ld + j] = v;
+        s += v;
+    }
+    s = block_sum256(s, red);
+    if (threadIdx.x == 0 && i < n) deg[i] = s;
+    if (f) atomicOr(flags, f);
+}
+
+hipError_t launch_import_weights(const double *Win, int64_t ldw, int64_t n, double *W,
+                                 int64_t ld, double *deg, int *flags, hipStream_t s) {
+    hipLaunchKernelGGL(k_import_weights, dim3((unsigned)ld), dim3(256), 0, s, Win, ldw, n, W,
+                       ld, deg, flags);
+    return hipGetLastError();
+}
+
+} // namespace cdl

@@ -1,0 +1,238 @@
+// Node anomaly scores (Algorithm 4 with the CAD edge score of the Background
+// section), without materialising any n x n commute-time matrix.
+//
+//   build_zhat  Zh = [sqrt(vol0) Z0 | sqrt(vol1) Z1] over the common nodes,
+//               Zhe = Zh with the second half negated, sq_c = Zh_c . Zhe_c
+//   score       G = Zh Zhe^T on FP64 MFMA (upper-triangular tiles); per pair
+//               dc_ab = sq_a + sq_b - 2 G_ab = c_0(a,b) - c_1(a,b) (eq. 1 in
+//               embedding form), weighted by |W1 - W0| on request; |dc| is
+//               summed per row and, for off-diagonal tiles, per column into
+//               one partial per (tile, node)
+//   reduce      F_a = sum over tiles of the partials (fixed order)
+//   topk        bitonic sort of chunks in LDS, keep the best K per chunk,
+//               repeat on the candidates (order: value desc, index asc)
+#include "common.h"
+#include "gemm.h"
+#include "kernels.h"
+
+namespace cdl {
+
+// One wave per common node.
+__global__ void k_build_zhat(const double *Z0, const double *Z1, const int32_t *map0,
+                             const int32_t *map1, int64_t m, int64_t k, int64_t kpad,
+                             const double *stats0, const double *stats1, double *Zh,
+                             double *Zhe, double *sq) {
+    const int64_t c = blockIdx.x;
+    const int lane = threadIdx.x;
+    const double s0 = sqrt(stats0[0]), s1 = sqrt(stats1[0]);
+    const int64_t ldz = 2 * kpad;
+    double acc = 0.0;
+    int64_t a = -1, b = -1;
+    if (c < m) {
+        a = map0 ? map0[c] : c;
+        b = map1 ? map1[c] : c;
+    }
+    for (int64_t r = lane; r < kpad; r += 64) {
+        double x0 = 0.0, x1 = 0.0;
+        if (c < m && r < k) {
+            x0 = s0 * Z0[a * k + r];
+            x1 = s1 * Z1[b * k + r];
+        }
+        Zh[c * ldz + r] = x0;
+        Zh[c * ldz + kpad + r] = x1;
+        Zhe[c * ldz + r] = x0;
+        Zhe[c * ldz + kpad + r] = -x1;
+        acc += x0 * x0 - x1 * x1;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
+    if (lane == 0) sq[c] = acc;
+}
+
+hipError_t launch_build_zhat(const double *Z0, const double *Z1, const int32_t *map0,
+                             const int32_t *map1, int64_t m, int64_t mpad, int64_t k,
+                             int64_t kpad, const double *stats0, const double *stats1,
+                             double *Zh, double *Zhe, double *sq, hipStream_t s) {
+    hipLaunchKernelGGL(k_build_zhat, dim3((unsigned)mpad), dim3(64), 0, s, Z0, Z1, map0, map1,
+                       m, k, kpad, stats0, stats1, Zh, Zhe, sq);
+    return hipGetLastError();
+}
+
+using ScoreCore = GemmCore<MfmaF64, 128, 128, 16, 2, 2>;
+
+__global__ __launch_bounds__(256) void k_score(const double *Zh, const double *Zhe,
+                                               int64_t ldz, const double *sq, int64_t m,
+                                               int64_t mpad, const double *W0, int64_t ld0,
+                                               const double *W1, int64_t ld1,
+                                               const int32_t *map0, const int32_t *map1,
+                                               int weighted, int nt, double *part) {
+    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+    double *smem = (double *)smem_raw;
+    __shared__ double srow[2][128], scol[2][128];
+    const int total = nt * (nt + 1) / 2;
+    int I, J;
+    sym_tile<8>(xcd_remap(blockIdx.x, total), nt, I, J);
+    const int64_t m0 = (int64_t)I * 128, n0 = (int64_t)J * 128;
+    ScoreCore g;
+    g.run(Zh, ldz, Zhe, ldz, m0, n0, ldz, smem);
+
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int wm = wid % 2, wn = wid / 2;
+    double cs[ScoreCore::WTN];
+#pragma unroll
+    for (int b = 0; b < ScoreCore::WTN; ++b) cs[b] = 0.0;
+#pragma unroll
+    for (int a = 0; a < ScoreCore::WTM; ++a)
+#pragma unroll
+        for (int rr = 0; rr < MfmaF64::R; ++rr) {
+            const int lr = ScoreCore::row_of(a, rr);
+            const int64_t ga = m0 + lr;
+            double rs = 0.0;
+#pragma unroll
+            for (int b = 0; b < ScoreCore::WTN; ++b) {
+                const int64_t gb = n0 + ScoreCore::col_of(b);
+                double v = 0.0;
+                if (ga < m && gb < m && ga != gb) {
+                    v = fabs(sq[ga] + sq[gb] - 2.0 * g.acc[a][b][rr]);
+                    if (weighted) {
+                        const int64_t a0 = map0 ? map0[ga] : ga, b0 = map0 ? map0[gb] : gb;
+                        const int64_t a1 = map1 ? map1[ga] : ga, b1 = map1 ? map1[gb] : gb;
+                        v *= fabs(W1[a1 * ld1 + b1] - W0[a0 * ld0 + b0]);
+                    }
+                }
+                rs += v;
+                cs[b] += v;
+            }
+#pragma unroll
+            for (int off = 1; off < 16; off <<= 1) rs += __shfl_xor(rs, off);
+            if ((lane & 15) == 0) srow[wn][lr] = rs;
+        }
+#pragma unroll
+    for (int b = 0; b < ScoreCore::WTN; ++b) {
+        double v = cs[b];
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        if (lane < 16) scol[wm][ScoreCore::col_of(b)] = v;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < 128; t += 256) {
+        part[(int64_t)J * mpad + m0 + t] = srow[0][t] + srow[1][t];
+        if (I != J) part[(int64_t)I * mpad + n0 + t] = scol[0][t] + scol[1][t];
+    }
+}
+
+int score_tiles_1d(int64_t mpad) { return (int)(mpad / 128); }
+
+hipError_t launch_score(const double *Zh, const double *Zhe, int64_t kpad, const double *sq,
+                        int64_t m, int64_t mpad, const double *W0, int64_t ld0,
+                        const double *W1, int64_t ld1, const int32_t *map0,
+                        const int32_t *map1, int weighted, double *part, hipStream_t s) {
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_score,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)ScoreCore::SMEM);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const int nt = (int)(mpad / 128);
+    const int total = nt * (nt + 1) / 2;
+    hipLaunchKernelGGL(k_score, dim3(total), dim3(256), ScoreCore::SMEM, s, Zh, Zhe, 2 * kpad,
+                       sq, m, mpad, W0, ld0, W1, ld1, map0, map1, weighted, nt, part);
+    return hipGetLastError();
+}
+
+__global__ void k_score_reduce(const double *part, int nparts, int64_t m, int64_t mpad,
+                               double *F) {
+    int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= m) return;
+    double s = 0.0;
+    for (int t = 0; t < nparts; ++t) s += part[(int64_t)t * mpad + a];
+    F[a] = s;
+}
+
+hipError_t launch_score_reduce(const double *part, int nparts, int64_t m, int64_t mpad,
+                               double *F, hipStream_t s) {
+    hipLaunchKernelGGL(k_score_reduce, dim3((unsigned)cdiv(m, 256)), dim3(256), 0, s, part,
+                       nparts, m, mpad, F);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Top-K.
+
+constexpr int kChunk = 2048;
+
+__device__ inline bool before(double va, int ia, double vb, int ib) {
+    return va > vb || (va == vb && ia < ib);
+}
+
+// Sort chunk blockIdx.x of (val, idx) pairs; idx_in == nullptr means idx is
+// the position.  Writes the first K of each chunk.
+__global__ __launch_bounds__(256) void k_topk_chunk(const double *val_in, const int32_t *idx_in,
+                                                    int64_t count, int K, double *val_out,
+                                                    int32_t *idx_out) {
+    __shared__ double sv[kChunk];
+    __shared__ int32_t si[kChunk];
+    const int64_t base = (int64_t)blockIdx.x * kChunk;
+    for (int t = threadIdx.x; t < kChunk; t += 256) {
+        const int64_t p = base + t;
+        if (p < count) {
+            sv[t] = val_in[p];
+            si[t] = idx_in ? idx_in[p] : (int32_t)p;
+        } else {
+            sv[t] = -INFINITY;
+            si[t] = 0x7fffffff;
+        }
+    }
+    __syncthreads();
+    for (int size = 2; size <= kChunk; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = threadIdx.x; t < kChunk / 2; t += 256) {
+                const int lo = 2 * t - (t & (stride - 1));
+                const int hi = lo + stride;
+                const bool desc = (lo & size) == 0;   // first half of each run: best first
+                const bool swap = desc ? before(sv[hi], si[hi], sv[lo], si[lo])
+                                       : before(sv[lo], si[lo], sv[hi], si[hi]);
+                if (swap) {
+                    double tv = sv[lo]; sv[lo] = sv[hi]; sv[hi] = tv;
+                    int32_t ti = si[lo]; si[lo] = si[hi]; si[hi] = ti;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int t = threadIdx.x; t < K; t += 256) {
+        val_out[(int64_t)blockIdx.x * K + t] = sv[t];
+        idx_out[(int64_t)blockIdx.x * K + t] = si[t];
+    }
+}
+
+int64_t topk_scratch_elems(int64_t m, int K) { return cdiv(m, kChunk) * (int64_t)K; }
+
+hipError_t launch_topk(const double *F, int64_t m, int K, void *scratch, int32_t *out,
+                       hipStream_t s) {
+    if (K <= 0) return hipSuccess;
+    const int64_t cap = topk_scratch_elems(m, K);
+    double *v[2] = {(double *)scratch, (double *)scratch + cap};
+    int32_t *ix[2] = {(int32_t *)((double *)scratch + 2 * cap), (int32_t *)((double *)scratch + 2 * cap) + cap};
+    const double *vin = F;
+    const int32_t *iin = nullptr;
+    int64_t count = m;
+    int side = 0;
+    while (true) {
+        const int64_t blocks = cdiv(count, kChunk);
+        hipLaunchKernelGGL(k_topk_chunk, dim3((unsigned)blocks), dim3(256), 0, s, vin, iin, count,
+                           K, v[side], ix[side]);
+        if (blocks == 1) break;
+        vin = v[side];
+        iin = ix[side];
+        count = blocks * K;
+        side ^= 1;
+    }
+    hipError_t e = hipMemcpyAsync(out, ix[side], sizeof(int32_t) * K, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+} // namespace cdl

@@ -1,0 +1,277 @@
+// Embedding solve (Algorithm 3 with Algorithm 1's right-hand sides; the
+// refinement is EstimateSolution of Algorithm 2 with P2 y = P1 L y, batched
+// over the k columns).
+//
+//   rhs         Y = B^T W^{1/2} Q^T / sqrt(k) with counter-based SplitMix64
+//               signs, one row of Y per wave (lane = neighbour j), FP64
+//               accumulation, deterministic butterfly reduction
+//   residual    R = Y - (deg * X - W X) on FP64 MFMA, per-column partial
+//               sums of R^2 and the tile maximum of |D^{-1/2} R|
+//   col_norms   ||R_r|| (fixed-order sums) and a power-of-two scale for the
+//               next preconditioner operand
+//   prep_v      V = scale * D^{-1/2} R in FP64 and rounded to the chain type
+//   finalize_z  centre the columns of X and transpose it into Z (n x k)
+//
+// Vectors of k columns are stored transposed: row r of a kpad x ld panel
+// holds column r over all (padded) nodes.
+#include "common.h"
+#include "gemm.h"
+#include "kernels.h"
+
+namespace cdl {
+
+// SplitMix64 output function (Steele, Lea & Flood, OOPSLA 2014).
+__device__ inline uint64_t splitmix64_mix(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+static uint64_t splitmix64_mix_host(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// Row i of Y for projection block beta = blockIdx.y (64 columns).  The sign
+// of edge {i, j} in column r is B(e, i) * q_r(e): bit r of the sign word,
+// complemented when i is the tail (higher global id).
+__global__ __launch_bounds__(256) void k_rhs(const double *W, int64_t ld, int64_t n,
+                                             const int32_t *gid, int64_t k, uint64_t mseed,
+                                             double inv_sqrt_k, double *Yt) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const uint64_t beta = blockIdx.y;
+    if (i >= n) return;
+    const uint64_t gi = gid ? (uint64_t)(uint32_t)gid[i] : (uint64_t)i;
+    double acc[64];
+#pragma unroll
+    for (int r = 0; r < 64; ++r) acc[r] = 0.0;
+    const double *row = W + i * ld;
+    for (int64_t j = lane; j < n; j += 64) {
+        const uint64_t gj = gid ? (uint64_t)(uint32_t)gid[j] : (uint64_t)j;
+        const uint64_t lo = gi < gj ? gi : gj, hi = gi < gj ? gj : gi;
+        uint64_t h = splitmix64_mix(mseed ^ ((beta << 40) | (lo << 20) | hi));
+        if (gi > gj) h = ~h;
+        const double w = sqrt(row[j]) * inv_sqrt_k;
+        const uint32_t hl = (uint32_t)h, hh = (uint32_t)(h >> 32);
+        const int whi = __double2hiint(w), wlo = __double2loint(w);
+#pragma unroll
+        for (int r = 0; r < 32; ++r)
+            acc[r] += __hiloint2double(whi | (int)((hl << (31 - r)) & 0x80000000u), wlo);
+#pragma unroll
+        for (int r = 0; r < 32; ++r)
+            acc[32 + r] += __hiloint2double(whi | (int)((hh << (31 - r)) & 0x80000000u), wlo);
+    }
+    // Butterfly transpose-reduction: afterwards lane l holds column l summed
+    // over all 64 lanes.
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) {
+        const bool up = (lane & s) != 0;
+#pragma unroll
+        for (int q = 0; q < s; ++q) {
+            const double send = up ? acc[q] : acc[q + s];
+            const double keep = up ? acc[q + s] : acc[q];
+            acc[q] = keep + __shfl_xor(send, s);
+        }
+    }
+    const int64_t r = (int64_t)beta * 64 + lane;
+    Yt[r * ld + i] = r < k ? acc[0] : 0.0;
+}
+
+hipError_t launch_rhs(const double *W, int64_t ld, int64_t n, const int32_t *gid, int64_t k,
+                      int64_t kpad, uint64_t seed, double *Yt, hipStream_t s) {
+    const uint64_t mseed = splitmix64_mix_host(seed);
+    dim3 grid((unsigned)cdiv(n, 4), (unsigned)(kpad / 64));
+    hipLaunchKernelGGL(k_rhs, grid, dim3(256), 0, s, W, ld, n, gid, k, mseed,
+                       1.0 / sqrt((double)k), Yt);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// FP64 residual R = Y - deg * X + W X:  C[r][i] = sum_j Xt[r][j] W[i][j].
+
+template <int BM>
+__global__ __launch_bounds__(BM) void k_residual(const double *Xt, const double *W,
+                                                 const double *Yt, const double *deg,
+                                                 const double *dm, int64_t ld, int64_t n,
+                                                 int64_t k, int64_t kpad, int64_t kend, int mt,
+                                                 int nt, double *Rt, double *npart,
+                                                 double *mpart) {
+    using Core = GemmCore<MfmaF64, BM, 64, 16, BM / 64, 1>;
+    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+    double *smem = (double *)smem_raw;
+    __shared__ double wmax[BM / 64];
+    const int id = xcd_remap(blockIdx.x, mt * nt);
+    int I, J;
+    rect_tile<4>(id, mt, nt, I, J);
+    const int64_t m0 = (int64_t)I * BM, n0 = (int64_t)J * 64;
+    Core g;
+    g.run(Xt, ld, W, ld, m0, n0, kend, smem);
+    const int lane = threadIdx.x & 63;
+    double vmax = 0.0;
+#pragma unroll
+    for (int a = 0; a < Core::WTM; ++a)
+#pragma unroll
+        for (int rr = 0; rr < MfmaF64::R; ++rr) {
+            const int64_t row = m0 + Core::row_of(a, rr);
+            double ss = 0.0;
+#pragma unroll
+            for (int b = 0; b < Core::WTN; ++b) {
+                const int64_t col = n0 + Core::col_of(b);
+                const int64_t o = row * ld + col;
+                double R = 0.0;
+                if (row < k && col < n) R = Yt[o] - deg[col] * Xt[o] + g.acc[a][b][rr];
+                Rt[o] = R;
+                ss += R * R;
+                vmax = fmax(vmax, fabs(dm[col] * R));
+            }
+            // sum over the 16 lanes holding the same row
+#pragma unroll
+            for (int off = 1; off < 16; off <<= 1) ss += __shfl_xor(ss, off);
+            if ((lane & 15) == 0) npart[(int64_t)J * kpad + row] = ss;
+        }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, off));
+    if (lane == 0) wmax[threadIdx.x >> 6] = vmax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = wmax[0];
+        for (int q = 1; q < BM / 64; ++q) m = fmax(m, wmax[q]);
+        mpart[id] = m;
+    }
+}
+
+int residual_parts(int64_t ld) { return (int)(ld / 64); }
+
+template <int BM>
+static hipError_t res_launch(const double *Xt, const double *W, const double *Yt,
+                             const double *deg, const double *dm, int64_t ld, int64_t n,
+                             int64_t kpad, int64_t k, int64_t kend, double *Rt, double *npart,
+                             double *mpart, hipStream_t s) {
+    using Core = GemmCore<MfmaF64, BM, 64, 16, BM / 64, 1>;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_residual<BM>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)Core::SMEM);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const int mt = (int)(kpad / BM), nt = (int)(ld / 64);
+    hipLaunchKernelGGL(k_residual<BM>, dim3(mt * nt), dim3(BM), Core::SMEM, s, Xt, W, Yt, deg,
+                       dm, ld, n, k, kpad, kend, mt, nt, Rt, npart, mpart);
+    return hipGetLastError();
+}
+
+// skip_gemm != 0 computes R = Y - deg * X only (used when X = 0).
+hipError_t launch_residual_k(const double *Xt, const double *W, const double *Yt,
+                             const double *deg, const double *dm, int64_t ld, int64_t n,
+                             int64_t kpad, int64_t k, int skip_gemm, double *Rt, double *npart,
+                             double *mpart, hipStream_t s) {
+    const int64_t kend = skip_gemm ? 0 : (n + 63) / 64 * 64;
+    if (kpad % 256 == 0) return res_launch<256>(Xt, W, Yt, deg, dm, ld, n, kpad, k, kend, Rt, npart, mpart, s);
+    if (kpad % 128 == 0) return res_launch<128>(Xt, W, Yt, deg, dm, ld, n, kpad, k, kend, Rt, npart, mpart, s);
+    return res_launch<64>(Xt, W, Yt, deg, dm, ld, n, kpad, k, kend, Rt, npart, mpart, s);
+}
+
+int residual_tiles(int64_t ld, int64_t kpad) {
+    int BM = kpad % 256 == 0 ? 256 : (kpad % 128 == 0 ? 128 : 64);
+    return (int)(kpad / BM) * (int)(ld / 64);
+}
+
+// out[r] = ||R_r|| for r < kpad; out[kpad] = scale, out[kpad+1] = 1/scale
+// with scale a power of two bringing max |D^{-1/2} R| into [0.5, 1).
+__global__ __launch_bounds__(256) void k_col_norms(const double *npart, int nparts,
+                                                   int64_t kpad, const double *mpart,
+                                                   int ntiles, double *out) {
+    for (int64_t r = threadIdx.x; r < kpad; r += 256) {
+        double s = 0.0;
+        for (int p = 0; p < nparts; ++p) s += npart[(int64_t)p * kpad + r];
+        out[r] = sqrt(s);
+    }
+    if (threadIdx.x == 0) {
+        double m = 0.0;
+        for (int t = 0; t < ntiles; ++t) m = fmax(m, mpart[t]);
+        double sc = 1.0;
+        if (m > 0.0 && isfinite(m)) sc = ldexp(1.0, -ilogb(m) - 1);
+        out[kpad] = sc;
+        out[kpad + 1] = 1.0 / sc;
+    }
+}
+
+hipError_t launch_col_norms2(const double *npart, int nparts, int64_t kpad, const double *mpart,
+                             int ntiles, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_col_norms, dim3(1), dim3(256), 0, s, npart, nparts, kpad, mpart, ntiles,
+                       out);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_prep_v(const double *Rt, const double *dm, int64_t ld, int64_t total,
+                         const double *scal, double scale_lo, double *V64, T *Vlo) {
+    const double sc = *scal;
+    for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < total;
+         o += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t col = o % ld;
+        const double v = sc * dm[col] * Rt[o];
+        V64[o] = v;
+        Vlo[o] = cvtd<T>(v * scale_lo);
+    }
+}
+
+hipError_t launch_prep_v2(int prec, const double *Rt, const double *dm, int64_t ld, int64_t kpad,
+                          const double *scal, double *V64, void *Vlo, hipStream_t s) {
+    const int64_t total = kpad * ld;
+    const int grid = (int)(cdiv(total, 256) < 16384 ? cdiv(total, 256) : 16384);
+    switch (prec) {
+    case 0: hipLaunchKernelGGL(k_prep_v<double>, dim3(grid), dim3(256), 0, s, Rt, dm, ld, total, scal, 1.0, V64, (double *)Vlo); break;
+    case 1: hipLaunchKernelGGL(k_prep_v<float>, dim3(grid), dim3(256), 0, s, Rt, dm, ld, total, scal, 1.0, V64, (float *)Vlo); break;
+    case 2: hipLaunchKernelGGL(k_prep_v<__bf16>, dim3(grid), dim3(256), 0, s, Rt, dm, ld, total, scal, 1.0, V64, (__bf16 *)Vlo); break;
+    case 3: hipLaunchKernelGGL(k_prep_v<_Float16>, dim3(grid), dim3(256), 0, s, Rt, dm, ld, total, scal, 1.0, V64, (_Float16 *)Vlo); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_col_mean(const double *Xt, int64_t ld, int64_t n,
+                                                  double *mean) {
+    __shared__ double red[4];
+    const int64_t r = blockIdx.x;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) s += Xt[r * ld + i];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) mean[r] = ((red[0] + red[1]) + (red[2] + red[3])) / (double)n;
+}
+
+// Z[i][r] = Xt[r][i] - mean[r] through a 32 x 32 LDS tile.
+__global__ __launch_bounds__(256) void k_transpose_z(const double *Xt, int64_t ld, int64_t n,
+                                                     int64_t k, const double *mean, double *Z) {
+    __shared__ double t[32][33];
+    const int64_t i0 = (int64_t)blockIdx.x * 32, r0 = (int64_t)blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    for (int q = ty; q < 32; q += 8) {
+        const int64_t r = r0 + q, i = i0 + tx;
+        t[q][tx] = (r < k && i < n) ? Xt[r * ld + i] - mean[r] : 0.0;
+    }
+    __syncthreads();
+    for (int q = ty; q < 32; q += 8) {
+        const int64_t i = i0 + q, r = r0 + tx;
+        if (i < n && r < k) Z[i * k + r] = t[tx][q];
+    }
+}
+
+hipError_t launch_finalize_z2(const double *Xt, int64_t ld, int64_t n, int64_t kpad, int64_t k,
+                              double *mean, double *Z, hipStream_t s) {
+    hipLaunchKernelGGL(k_col_mean, dim3((unsigned)kpad), dim3(256), 0, s, Xt, ld, n, mean);
+    hipLaunchKernelGGL(k_transpose_z, dim3((unsigned)cdiv(n, 32), (unsigned)cdiv(k, 32)),
+                       dim3(256), 0, s, Xt, ld, n, k, mean, Z);
+    return hipGetLastError();
+}
+
+} // namespace cdl
