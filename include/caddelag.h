@@ -138,6 +138,22 @@ const char *cdl_last_error(const cdl_ctx *ctx);
 /* Library version string, e.g. "caddelag-gfx950 1.0". */
 const char *cdl_version(void);
 
+/* ---- per-kernel timing ------------------------------------------------- */
+
+/* enable != 0: every kernel launch of later calls on this context is
+ * bracketed by HIP events recorded on the context's stream (a few
+ * microseconds of overhead per launch); totals accumulate per kernel name
+ * ("gram_dist", "select_median", "exp_degree", "normalize", "square",
+ * "apply", "rhs", "residual", "score", "topk", ...). */
+cdl_status cdl_ctx_set_timing(cdl_ctx *ctx, int enable);
+/* Syncs.  Entry idx (0-based, in first-seen order) of the totals: kernel
+ * name (valid until the next reset), launches and summed milliseconds.
+ * CDL_E_ARG past the last entry. */
+cdl_status cdl_timing_read(cdl_ctx *ctx, int32_t idx, const char **name, int64_t *launches,
+                           double *total_ms);
+/* Syncs.  Clears the totals. */
+cdl_status cdl_timing_reset(cdl_ctx *ctx);
+
 /* ---- sizes ------------------------------------------------------------- */
 
 /* Padded leading dimension (and row count) of the library's n x n layout. */

@@ -26,6 +26,8 @@ from .api import (  # noqa: E402,F401
     level,
     level_scale,
     score_sequence,
+    set_timing,
+    timing,
     solve_embedding,
     workspace_bytes,
 )

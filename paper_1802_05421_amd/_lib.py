@@ -76,6 +76,10 @@ def load():
         "cdl_status_string": (C.c_char_p, [I]),
         "cdl_last_error": (C.c_char_p, [P]),
         "cdl_version": (C.c_char_p, []),
+        "cdl_ctx_set_timing": (I, [P, I]),
+        "cdl_timing_read": (I, [P, C.c_int32, C.POINTER(C.c_char_p), C.POINTER(i64),
+                                C.POINTER(d)]),
+        "cdl_timing_reset": (I, [P]),
         "cdl_ld": (i64, [i64]),
         "cdl_matrix_bytes": (sz, [i64, I]),
         "cdl_workspace_bytes": (I, [i64, i64, i64, I, I, C.POINTER(sz), C.POINTER(sz),

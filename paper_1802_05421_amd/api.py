@@ -60,6 +60,25 @@ class Context:
             pass
 
 
+def set_timing(enable: bool, device: int = 0):
+    """Per-kernel HIP-event timing on the context's stream (see include/caddelag.h)."""
+    ctx = context(device)
+    _check(_lib().cdl_ctx_set_timing(ctx.h, int(enable)), ctx.h)
+
+
+def timing(device: int = 0, reset: bool = False) -> dict:
+    """{kernel name: (launches, total ms)} accumulated since the last reset."""
+    ctx = context(device)
+    out, i = {}, 0
+    nm, cnt, ms = C.c_char_p(), C.c_int64(), C.c_double()
+    while _lib().cdl_timing_read(ctx.h, i, C.byref(nm), C.byref(cnt), C.byref(ms)) == 0:
+        out[nm.value.decode()] = (cnt.value, ms.value)
+        i += 1
+    if reset:
+        _check(_lib().cdl_timing_reset(ctx.h), ctx.h)
+    return out
+
+
 def context(device: int = 0) -> Context:
     c = _ctx_cache.get(device)
     if c is None:

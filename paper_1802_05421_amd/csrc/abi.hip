@@ -6,17 +6,89 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
 #include "caddelag.h"
 #include "kernels.h"
 
+struct cdl_timer_rec {
+    const char *name;
+    hipEvent_t a, b;
+};
+
 struct cdl_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
+    // Optional per-kernel timing: HIP events recorded on `stream` around each
+    // kernel launch, resolved when the totals are read.
+    bool timing = false;
+    std::vector<cdl_timer_rec> pending;
+    std::vector<hipEvent_t> pool;
+    std::map<std::string, std::pair<int64_t, double>> totals;
+    std::vector<std::string> names;   // stable order for cdl_timing_read
 };
+
+namespace {
+hipEvent_t take_event(cdl_ctx *c) {
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Brackets one kernel launch (or a fixed group of launches) with events.
+struct Timed {
+    cdl_ctx *c;
+    const char *name;
+    hipEvent_t a = nullptr;
+    Timed(cdl_ctx *ctx, const char *nm) : c(ctx), name(nm) {
+        if (c->timing && (a = take_event(c)) && hipEventRecord(a, c->stream) != hipSuccess) {
+            c->pool.push_back(a);
+            a = nullptr;
+        }
+    }
+    ~Timed() {
+        if (!a) return;
+        hipEvent_t b = take_event(c);
+        if (!b) {
+            c->pool.push_back(a);
+            return;
+        }
+        if (hipEventRecord(b, c->stream) != hipSuccess) {
+            c->pool.push_back(a);
+            c->pool.push_back(b);
+            return;
+        }
+        c->pending.push_back({name, a, b});
+    }
+};
+
+void resolve_timers(cdl_ctx *c) {
+    if (c->pending.empty()) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto &r : c->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) ms = 0.f;
+        auto it = c->totals.find(r.name);
+        if (it == c->totals.end()) {
+            c->names.push_back(r.name);
+            it = c->totals.emplace(r.name, std::make_pair((int64_t)0, 0.0)).first;
+        }
+        it->second.first += 1;
+        it->second.second += ms;
+        c->pool.push_back(r.a);
+        c->pool.push_back(r.b);
+    }
+    c->pending.clear();
+}
+} // namespace
 
 namespace {
 
@@ -199,7 +271,41 @@ cdl_status cdl_ctx_create(int device, void *stream, cdl_ctx **out) {
 }
 
 cdl_status cdl_ctx_destroy(cdl_ctx *ctx) {
+    if (!ctx) return CDL_OK;
+    if (!ctx->pending.empty()) (void)hipStreamSynchronize(ctx->stream);
+    for (auto &r : ctx->pending) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
     delete ctx;
+    return CDL_OK;
+}
+
+cdl_status cdl_ctx_set_timing(cdl_ctx *ctx, int enable) {
+    if (!ctx) return CDL_E_ARG;
+    ctx->timing = enable != 0;
+    return CDL_OK;
+}
+
+cdl_status cdl_timing_reset(cdl_ctx *ctx) {
+    if (!ctx) return CDL_E_ARG;
+    resolve_timers(ctx);
+    ctx->totals.clear();
+    ctx->names.clear();
+    return CDL_OK;
+}
+
+cdl_status cdl_timing_read(cdl_ctx *ctx, int32_t idx, const char **name, int64_t *launches,
+                           double *total_ms) {
+    if (!ctx || !name || !launches || !total_ms) return CDL_E_ARG;
+    resolve_timers(ctx);
+    if (idx < 0 || idx >= (int32_t)ctx->names.size()) return CDL_E_ARG;
+    const std::string &nm = ctx->names[idx];
+    const auto &v = ctx->totals[nm];
+    *name = nm.c_str();
+    *launches = v.first;
+    *total_ms = v.second;
     return CDL_OK;
 }
 
@@ -250,15 +356,15 @@ cdl_status cdl_build_graph(cdl_ctx *ctx, const double *X, int64_t n, int64_t T, 
     const int64_t ld = pad_n(n), Tp = pad_t(T);
     hipStream_t s = ctx->stream;
     HIPCHK(hipSetDevice(ctx->device));
-    HIPCHK(launch_fill_zero(w.flags, 256, s));
-    HIPCHK(launch_pad_series(X, n, T, ldx, w.Xp, ld, Tp, w.sqn, w.flags, s));
-    HIPCHK(launch_gram_dist(w.Xp, Tp, w.sqn, n, ld, W, s));
+    { Timed t_(ctx, "fill_zero"); HIPCHK(launch_fill_zero(w.flags, 256, s)); }
+    { Timed t_(ctx, "pad_series"); HIPCHK(launch_pad_series(X, n, T, ldx, w.Xp, ld, Tp, w.sqn, w.flags, s)); }
+    { Timed t_(ctx, "gram_dist"); HIPCHK(launch_gram_dist(w.Xp, Tp, w.sqn, n, ld, W, s)); }
     if (sigma > 0.0)
-        HIPCHK(launch_set_sigma(sigma, stats, s));
+        { Timed t_(ctx, "set_sigma"); HIPCHK(launch_set_sigma(sigma, stats, s)); }
     else
-        HIPCHK(launch_select_median(W, ld, n, w.sel, stats, s));
-    HIPCHK(launch_exp_degree(W, ld, n, stats, deg, s));
-    HIPCHK(launch_graph_stats(deg, n, stats, s));
+        { Timed t_(ctx, "select_median"); HIPCHK(launch_select_median(W, ld, n, w.sel, stats, s)); }
+    { Timed t_(ctx, "exp_degree"); HIPCHK(launch_exp_degree(W, ld, n, stats, deg, s)); }
+    { Timed t_(ctx, "graph_stats"); HIPCHK(launch_graph_stats(deg, n, stats, s)); }
     return CDL_OK;
 }
 
@@ -289,10 +395,10 @@ cdl_status cdl_graph_from_weights(cdl_ctx *ctx, const double *Win, int64_t n, in
     int *flags = (int *)ws;
     const int64_t ld = pad_n(n);
     HIPCHK(hipSetDevice(ctx->device));
-    HIPCHK(launch_fill_zero(flags, 256, s));
-    HIPCHK(launch_import_weights(Win, ldw, n, W, ld, deg, flags, s));
-    HIPCHK(launch_set_sigma(0.0, stats, s));
-    HIPCHK(launch_graph_stats(deg, n, stats, s));
+    { Timed t_(ctx, "fill_zero"); HIPCHK(launch_fill_zero(flags, 256, s)); }
+    { Timed t_(ctx, "import_weights"); HIPCHK(launch_import_weights(Win, ldw, n, W, ld, deg, flags, s)); }
+    { Timed t_(ctx, "set_sigma"); HIPCHK(launch_set_sigma(0.0, stats, s)); }
+    { Timed t_(ctx, "graph_stats"); HIPCHK(launch_graph_stats(deg, n, stats, s)); }
     int hf = 0;
     HIPCHK(hipMemcpyAsync(&hf, flags, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -332,8 +438,8 @@ cdl_status cdl_build_chain(cdl_ctx *ctx, const double *W, const double *deg, con
     info->lazy = lazy ? 1 : 0;
     info->prec = prec;
 
-    HIPCHK(launch_chain_prep(deg, stats, n, ld, info->lazy, c.dmn, c.dm, c.u, s));
-    HIPCHK(launch_normalize(prec, W, ld, n, c.dmn, c.u, info->lazy, c.levels, c.fro, s));
+    { Timed t_(ctx, "chain_prep"); HIPCHK(launch_chain_prep(deg, stats, n, ld, info->lazy, c.dmn, c.dm, c.u, s)); }
+    { Timed t_(ctx, "normalize"); HIPCHK(launch_normalize(prec, W, ld, n, c.dmn, c.u, info->lazy, c.levels, c.fro, s)); }
     std::vector<double> part(ld);
     HIPCHK(hipMemcpyAsync(part.data(), c.fro, ld * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -353,8 +459,8 @@ cdl_status cdl_build_chain(cdl_ctx *ctx, const double *W, const double *deg, con
             more = l + 1 < depth_max && model_wants_square(prec, n, l, f, rho);
         if (!more) break;
         const int ntl = square_tiles(prec, ld);
-        HIPCHK(launch_square(prec, c.levels + c.level_bytes * l, c.levels + c.level_bytes * (l + 1),
-                             ld, n, c.fro, s));
+        { Timed t_(ctx, "square"); HIPCHK(launch_square(prec, c.levels + c.level_bytes * l, c.levels + c.level_bytes * (l + 1),
+                             ld, n, c.fro, s)); }
         part.resize(ntl);
         HIPCHK(hipMemcpyAsync(part.data(), c.fro, ntl * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -412,12 +518,12 @@ cdl_status cdl_solve_embedding(cdl_ctx *ctx, const double *W, const double *deg,
     HIPCHK(hipSetDevice(ctx->device));
     if (info) std::memset(info, 0, sizeof(*info));
 
-    HIPCHK(launch_fill_zero(w.Yt, panel * sizeof(double), s));
-    HIPCHK(launch_fill_zero(w.Xt, panel * sizeof(double), s));
-    HIPCHK(launch_rhs(W, ld, n, gid, k, kp, seed, w.Yt, s));
+    { Timed t_(ctx, "fill_zero"); HIPCHK(launch_fill_zero(w.Yt, panel * sizeof(double), s)); }
+    { Timed t_(ctx, "fill_zero"); HIPCHK(launch_fill_zero(w.Xt, panel * sizeof(double), s)); }
+    { Timed t_(ctx, "rhs"); HIPCHK(launch_rhs(W, ld, n, gid, k, kp, seed, w.Yt, s)); }
     const int nparts = residual_parts(ld), ntiles = residual_tiles(ld, kp);
-    HIPCHK(launch_residual_k(w.Xt, W, w.Yt, deg, c.dm, ld, n, kp, k, 1, w.Rt, w.npart, w.mpart, s));
-    HIPCHK(launch_col_norms2(w.npart, nparts, kp, w.mpart, ntiles, w.scal, s));
+    { Timed t_(ctx, "residual_init"); HIPCHK(launch_residual_k(w.Xt, W, w.Yt, deg, c.dm, ld, n, kp, k, 1, w.Rt, w.npart, w.mpart, s)); }
+    { Timed t_(ctx, "col_norms"); HIPCHK(launch_col_norms2(w.npart, nparts, kp, w.mpart, ntiles, w.scal, s)); }
     std::vector<double> ynorm(kp), rnorm(kp);
     HIPCHK(hipMemcpyAsync(ynorm.data(), w.scal, kp * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -429,16 +535,16 @@ cdl_status cdl_solve_embedding(cdl_ctx *ctx, const double *W, const double *deg,
     bool conv = false;
     while (it < max_iter) {
         // X += P1 R: V = D^{-1/2} R (scaled), V <- (I + S~_l) V, X += D^{-1/2} V.
-        HIPCHK(launch_prep_v2(prec, w.Rt, c.dm, ld, kp, w.scal + kp, w.V64, w.Vlo[0], s));
+        { Timed t_(ctx, "prep_v"); HIPCHK(launch_prep_v2(prec, w.Rt, c.dm, ld, kp, w.scal + kp, w.V64, w.Vlo[0], s)); }
         for (int l = 0; l < ci->depth; ++l) {
             const bool last = l + 1 == ci->depth;
-            HIPCHK(launch_apply(prec, w.Vlo[l & 1], c.levels + c.level_bytes * l, w.Vlo[(l + 1) & 1],
-                                w.V64, ld, n, kp, w.Xt, c.dm, last ? w.scal + kp + 1 : nullptr, s));
+            { Timed t_(ctx, "apply"); HIPCHK(launch_apply(prec, w.Vlo[l & 1], c.levels + c.level_bytes * l, w.Vlo[(l + 1) & 1],
+                                w.V64, ld, n, kp, w.Xt, c.dm, last ? w.scal + kp + 1 : nullptr, s)); }
         }
         ++it;
-        HIPCHK(launch_residual_k(w.Xt, W, w.Yt, deg, c.dm, ld, n, kp, k, 0, w.Rt, w.npart,
-                                 w.mpart, s));
-        HIPCHK(launch_col_norms2(w.npart, nparts, kp, w.mpart, ntiles, w.scal, s));
+        { Timed t_(ctx, "residual"); HIPCHK(launch_residual_k(w.Xt, W, w.Yt, deg, c.dm, ld, n, kp, k, 0, w.Rt, w.npart,
+                                 w.mpart, s)); }
+        { Timed t_(ctx, "col_norms"); HIPCHK(launch_col_norms2(w.npart, nparts, kp, w.mpart, ntiles, w.scal, s)); }
         HIPCHK(hipMemcpyAsync(rnorm.data(), w.scal, kp * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         rel = 0.0;
@@ -452,7 +558,7 @@ cdl_status cdl_solve_embedding(cdl_ctx *ctx, const double *W, const double *deg,
             break;
         }
     }
-    HIPCHK(launch_finalize_z2(w.Xt, ld, n, kp, k, w.mean, Z, s));
+    { Timed t_(ctx, "finalize_z"); HIPCHK(launch_finalize_z2(w.Xt, ld, n, kp, k, w.mean, Z, s)); }
     if (info) {
         info->iterations = it;
         info->converged = conv || tol <= 0.0;
@@ -506,11 +612,11 @@ cdl_status cdl_anomaly_scores(cdl_ctx *ctx, const double *Z0, const double *W0,
     ScoreWs w = plan_score(a, m, k);
     const int64_t mp = pad_n(m), kp = pad_k(k);
     hipStream_t s = ctx->stream;
-    HIPCHK(launch_build_zhat(Z0, Z1, map0, map1, m, mp, k, kp, stats0, stats1, w.Zh, w.Zhe, w.sq, s));
-    HIPCHK(launch_score(w.Zh, w.Zhe, kp, w.sq, m, mp, W0, pad_n(n0), W1, pad_n(n1), map0, map1,
-                        mode == CDL_SCORE_DELTA_A, w.part, s));
-    HIPCHK(launch_score_reduce(w.part, score_tiles_1d(mp), m, mp, F, s));
-    if (top_k > 0) HIPCHK(launch_topk(F, m, top_k, w.topk, top_idx, s));
+    { Timed t_(ctx, "build_zhat"); HIPCHK(launch_build_zhat(Z0, Z1, map0, map1, m, mp, k, kp, stats0, stats1, w.Zh, w.Zhe, w.sq, s)); }
+    { Timed t_(ctx, "score"); HIPCHK(launch_score(w.Zh, w.Zhe, kp, w.sq, m, mp, W0, pad_n(n0), W1, pad_n(n1), map0, map1,
+                        mode == CDL_SCORE_DELTA_A, w.part, s)); }
+    { Timed t_(ctx, "score_reduce"); HIPCHK(launch_score_reduce(w.part, score_tiles_1d(mp), m, mp, F, s)); }
+    if (top_k > 0) { Timed t_(ctx, "topk"); HIPCHK(launch_topk(F, m, top_k, w.topk, top_idx, s)); }
     return CDL_OK;
 }
 
