@@ -98,9 +98,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--fp32-steps", type=int, default=3)
     ap.add_argument("--grid", type=int, default=128, help="grid side G (n = G*G)")
-    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--tol", type=float, default=-1e-6,
+                    help="> 0: relative FP64 residual target; < 0: certified embedding error")
+    ap.add_argument("--mixed", default="fp16", choices=("bf16", "fp16"),
+                    help="element type of the mixed-precision chain (headline value)")
+    ap.add_argument("--no-stress", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -114,6 +120,15 @@ def main():
     import gen
     import paper_1802_05421_amd as cdl
 
+    if args.calibrate_copy:
+        a = torch.ones(32 << 20, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 x 256 MiB device-to-device copies done")
+        del a, b
+
     G, T, k, seed = args.grid, 240, 256, gen.grid.PROJ_SEED
     n = G * G
     log("generating inputs G=%d n=%d T=%d" % (G, n, T))
@@ -125,39 +140,46 @@ def main():
                         deg=torch.empty(n, dtype=torch.float64, device=dev),
                         stats=torch.empty(4, dtype=torch.float64, device=dev), n=n) for _ in range(2)]
     DMAX = 6
-    sizes = {p: cdl.workspace_bytes(n, T, k, DMAX, p) for p in ("bf16", "fp32")}
-    gws = torch.empty(sizes["bf16"]["graph"], dtype=torch.uint8, device=dev)
-    chb = {p: [torch.empty(sizes[p]["chain"], dtype=torch.uint8, device=dev) for _ in range(2)]
-           for p in (("bf16",) if args.no_fp32 else ("bf16", "fp32"))}
-    sws = torch.empty(max(sizes["bf16"]["solve"], sizes["fp32"]["solve"]), dtype=torch.uint8, device=dev)
-    scws = torch.empty(sizes["bf16"]["score"], dtype=torch.uint8, device=dev)
-    Zb = {p: [torch.empty((n, k), dtype=torch.float64, device=dev) for _ in range(2)] for p in chb}
-    Fb = {p: torch.empty(n, dtype=torch.float64, device=dev) for p in chb}
-    Tb = {p: torch.empty(50, dtype=torch.int32, device=dev) for p in chb}
+    precs = [args.mixed] + [p for p in ("bf16", "fp16") if p != args.mixed] + ([] if args.no_fp32 else ["fp32"])
+    sizes = {p: cdl.workspace_bytes(n, T, k, DMAX, p) for p in precs}
+    gws = torch.empty(max(v["graph"] for v in sizes.values()), dtype=torch.uint8, device=dev)
+    chb = {p: [torch.empty(sizes[p]["chain"], dtype=torch.uint8, device=dev) for _ in range(2)] for p in precs}
+    sws = torch.empty(max(v["solve"] for v in sizes.values()), dtype=torch.uint8, device=dev)
+    scws = torch.empty(sizes[precs[0]]["score"], dtype=torch.uint8, device=dev)
+    Zb = {p: [torch.empty((n, k), dtype=torch.float64, device=dev) for _ in range(2)] for p in precs}
+    Fb = {p: torch.empty(n, dtype=torch.float64, device=dev) for p in precs}
+    Tb = {p: torch.empty(50, dtype=torch.int32, device=dev) for p in precs}
 
-    def step(prec):
+    def step(prec, sigma=None, Xs=X, tol=None):
+        tol = args.tol if tol is None else tol
         infos = []
         for t in (0, 1):
-            cdl.build_graph(X[t], ws=gws, out=graphs[t], check=True)
+            cdl.build_graph(Xs[t], sigma=sigma, ws=gws, out=graphs[t], check=True)
             ch = cdl.build_chain(graphs[t], prec=prec, depth=0, depth_max=DMAX, buf=chb[prec][t])
-            _, si = cdl.solve_embedding(graphs[t], ch, k, seed, tol=args.tol, max_iter=30, ws=sws,
+            _, si = cdl.solve_embedding(graphs[t], ch, k, seed, tol=tol, max_iter=30, ws=sws,
                                         Z=Zb[prec][t])
-            infos.append((ch.info.depth, ch.info.rho_hat, [ch.info.fro[i] for i in range(ch.info.depth)],
-                          si.iterations, si.rel_residual))
+            infos.append({"depth": ch.info.depth, "rho_hat": round(ch.info.rho_hat, 5),
+                          "rho_bound": round(ch.info.rho_bound, 5),
+                          "fro": [round(ch.info.fro[i], 7) for i in range(ch.info.depth)],
+                          "iterations": si.iterations,
+                          "depth_used": [si.depth_used[i] for i in range(si.iterations)],
+                          "history": ["%.2e" % si.history[i] for i in range(si.iterations)],
+                          "rel_residual": si.rel_residual, "kappa": round(si.kappa, 4),
+                          "certified_error": si.certified_error})
         cdl.anomaly_scores(Zb[prec][0], graphs[0], Zb[prec][1], graphs[1], top_k=50, ws=scws,
                            F=Fb[prec], top=Tb[prec])
         return infos
 
-    def timed(prec, steps, warmup):
+    def timed(prec, steps, warmup, **kw):
         for i in range(warmup):
-            step(prec)
+            step(prec, **kw)
             log("warmup %s %d/%d done" % (prec, i + 1, warmup))
         torch.cuda.synchronize()
         cdl.timing(reset=True)
         cdl.set_timing(True)
         t0 = time.perf_counter()
         for i in range(steps):
-            infos = step(prec)
+            infos = step(prec, **kw)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         cdl.set_timing(False)
@@ -165,32 +187,54 @@ def main():
         log("%s: %d pairs in %.3f s" % (prec, steps, t1 - t0))
         return (t1 - t0) / steps, infos, times
 
-    ms_mixed, info_mixed, times_mixed = timed("bf16", args.steps, args.warmup)
-    res = {"bf16": (ms_mixed, info_mixed, times_mixed)}
-    if not args.no_fp32:
-        res["fp32"] = timed("fp32", args.fp32_steps, 1)
+    res = {}
+    res[args.mixed] = timed(args.mixed, args.steps, args.warmup)
+    ms_mixed, info_mixed, times_mixed = res[args.mixed]
+    for p in precs[1:]:
+        res[p] = timed(p, args.fp32_steps, 1)
 
-    # dominant kernel of the mixed step, and the squaring's MFMA fraction
-    modeled = {nm: v for nm, v in times_mixed.items() if kernel_model(nm, n, k, T, "bf16")}
-    dom = max(modeled, key=lambda nm: modeled[nm][1])
-    roof = roofline(times_mixed, dom, n, k, T, "bf16", load_traffic(dom))
-    sq = {}
-    for p in res:
-        if "square" in res[p][2]:
-            r = roofline(res[p][2], "square", n, k, T, p)
-            sq[p] = {"frac_of_peak": r["frac"], "achieved_tflops": r["achieved"],
-                     "peak_tflops": r["peak"], "avg_ms": r["avg_ms"], "launches": r["launches"],
-                     "dense_equiv_frac": round(2 * r["frac"] * n / (n + 1), 4)}
-
-    # accuracy: certificates, and mixed vs plain agreement
-    acc = {"mixed_rel_residual": max(i[4] for i in info_mixed)}
-    if "fp32" in res:
-        acc["fp32_rel_residual"] = max(i[4] for i in res["fp32"][1])
-        zdiff = max(float(torch.linalg.norm(Zb["bf16"][t] - Zb["fp32"][t]) / torch.linalg.norm(Zb["fp32"][t]))
+    # accuracy: certificates, and agreement of the forms
+    acc = {"certified_error_bound": max(i["certified_error"] for i in info_mixed),
+           "mixed_rel_residual": max(i["rel_residual"] for i in info_mixed)}
+    for p in precs[1:]:
+        zdiff = max(float(torch.linalg.norm(Zb[args.mixed][t] - Zb[p][t]) / torch.linalg.norm(Zb[p][t]))
                     for t in (0, 1))
-        fdiff = float((Fb["bf16"] - Fb["fp32"]).abs().max() / Fb["fp32"].abs().max())
-        acc.update(mixed_vs_fp32_rel_Z=zdiff, mixed_vs_fp32_rel_F=fdiff,
-                   top50_equal=bool(set(Tb["bf16"].tolist()) == set(Tb["fp32"].tolist())))
+        fdiff = float((Fb[args.mixed] - Fb[p]).abs().max() / Fb[p].abs().max())
+        acc["vs_%s" % p] = {"rel_Z": zdiff, "rel_F": fdiff,
+                            "top50_equal": bool(set(Tb[args.mixed].tolist()) == set(Tb[p].tolist())),
+                            "certified_error_bound": max(i["certified_error"] for i in res[p][1])}
+
+    # The chain squaring itself (the autotuner may skip it at this spectral
+    # radius): one two-level chain per type, timed on its own.
+    sq = {}
+    for p in precs:
+        cdl.timing(reset=True)
+        cdl.set_timing(True)
+        cdl.build_chain(graphs[0], prec=p, depth=2, depth_max=DMAX, buf=chb[p][0])
+        cdl.set_timing(False)
+        r = roofline(cdl.timing(reset=True), "square", n, k, T, p)
+        sq[p] = {"frac_of_peak": r["frac"], "achieved_tflops": r["achieved"], "peak_tflops": r["peak"],
+                 "avg_ms": r["avg_ms"], "dense_equiv_frac": round(2 * r["frac"] * n / (n + 1), 4)}
+
+    # Stress case: bandwidth 0.3 x median pushes rho(S~) to ~0.8, so deep chains
+    # (many squarings) are needed - mixed vs FP32 where the squarings dominate.
+    stress = None
+    if not args.no_stress:
+        sig = 0.3 * float(graphs[0].stats[1])
+        st = {}
+        for p in ([args.mixed] + ([] if args.no_fp32 else ["fp32"])):
+            # ||S~||_F > 1 here, so the certificate does not apply: FP64 residual 1e-8
+            msp, inf, tms = timed(p, 1, 1, sigma=sig, tol=1e-8)
+            st[p] = {"ms_per_pair": round(msp * 1e3, 2), "pairs_per_s": round(1.0 / msp, 3),
+                     "chain": inf, "square_ms": round(tms.get("square", (0, 0.0))[1], 2)}
+        stress = {"sigma": round(sig, 4), "per_prec": st}
+        if "fp32" in st:
+            stress["mixed_over_fp32"] = round(st["fp32"]["ms_per_pair"] / st[args.mixed]["ms_per_pair"], 3)
+
+    # dominant kernel of the mixed step
+    modeled = {nm: v for nm, v in times_mixed.items() if kernel_model(nm, n, k, T, args.mixed)}
+    dom = max(modeled, key=lambda nm: modeled[nm][1])
+    roof = roofline(times_mixed, dom, n, k, T, args.mixed, load_traffic(dom))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -201,23 +245,24 @@ def main():
         "metric": METRIC, "value": round(1.0 / ms_mixed, 4), "unit": "pairs/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_mixed * 1e3, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "bf16/f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": "%s/f64" % args.mixed, "data": "synthetic",
         "config": {"workload": "C3 pair: 128x128 lat/lon grid, n=16384, T=240 AR(1) windows, "
-                               "4 flipped 4x4 patches, k=256 Rademacher projections, BF16 chain "
-                               "(FP32 accum) + FP64-residual Richardson to %.0e, top-50" % args.tol,
+                               "4 flipped 4x4 patches, k=256 Rademacher projections, %s chain "
+                               "(FP32 accum) + FP64-residual Richardson, stop at certified "
+                               "embedding error %s, top-50" % (args.mixed.upper(), (
+                                   "%.0e" % -args.tol) if args.tol < 0 else "residual %.0e" % args.tol),
                    "n": n, "T": T, "k": k, "tol": args.tol, "chain_depth_max": DMAX},
-        "fp32_plain": None if "fp32" not in res else {
-            "value": round(1.0 / res["fp32"][0], 4), "ms_per_step": round(res["fp32"][0] * 1e3, 3),
-            "steps": args.fp32_steps},
+        "forms": {p: {"value": round(1.0 / res[p][0], 4), "ms_per_step": round(res[p][0] * 1e3, 3),
+                      "steps": args.steps if p == args.mixed else args.fp32_steps} for p in precs},
         "mixed_over_fp32": None if "fp32" not in res else round(res["fp32"][0] / ms_mixed, 3),
         "roofline": roof,
         "squaring_mfma": sq,
-        "chain": {p: [{"depth": i[0], "rho_hat": round(i[1], 5), "fro": [round(f, 6) for f in i[2]],
-                       "iterations": i[3], "rel_residual": i[4]} for i in res[p][1]] for p in res},
+        "chain": {p: res[p][1] for p in precs},
         "accuracy": acc,
-        "kernels_ms_per_step": {p: {nm: round(v[1] / (args.steps if p == "bf16" else args.fp32_steps), 3)
+        "stress": stress,
+        "kernels_ms_per_step": {p: {nm: round(v[1] / (args.steps if p == args.mixed else args.fp32_steps), 3)
                                     for nm, v in sorted(res[p][2].items(), key=lambda x: -x[1][1])}
-                                for p in res},
+                                for p in precs},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

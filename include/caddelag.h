@@ -85,15 +85,19 @@ typedef struct {
     int depth;                 /* number of stored levels S~, S~^2, ..., S~^{2^(depth-1)} */
     int lazy;                  /* 1: levels are of (I + S)/2 (lazy walk) */
     cdl_prec prec;             /* element type of the stored levels */
-    double rho_hat;            /* upper estimate of the spectral radius of S~ */
+    double rho_hat;            /* fro(S~_{d-1})^(1/2^(d-1)): upper estimate of rho(S~) */
+    double rho_bound;          /* ||S~||_F of the unrounded FP64 S~: rigorous bound on rho */
     double fro[CDL_MAX_DEPTH + 1]; /* Frobenius norm of each stored level */
 } cdl_chain_info;
 
 typedef struct {
     int iterations;            /* preconditioner applications performed */
-    int converged;             /* 1 if max relative residual <= tol */
+    int converged;             /* 1 if the stopping test passed */
     double rel_residual;       /* final max_r ||y_r - L z_r|| / ||y_r|| (FP64) */
+    double kappa;              /* deg_max (1 + rho_bound) / (deg_min (1 - rho_bound)) */
+    double certified_error;    /* kappa * rel_residual: bound on ||Z - L^+ Y||_F / ||L^+ Y||_F */
     double history[64];        /* max relative residual after each iteration */
+    int depth_used[64];        /* chain depth (stored + applied-by-repetition) per iteration */
 } cdl_solve_info;
 
 /* One snapshot of a sequence, for cdl_score_sequence. */
@@ -138,6 +142,12 @@ const char *cdl_last_error(const cdl_ctx *ctx);
 /* Library version string, e.g. "caddelag-gfx950 1.0". */
 const char *cdl_version(void);
 
+/* depth > 0: every later solve iteration on this context applies the chain
+ * at total depth `depth` (stored levels first, deeper ones by repeated
+ * application of the last stored level) instead of the autotuned depth;
+ * 0 restores autotuning.  CDL_E_ARG outside [0, 16]. */
+cdl_status cdl_ctx_set_solve_depth(cdl_ctx *ctx, int depth);
+
 /* ---- per-kernel timing ------------------------------------------------- */
 
 /* enable != 0: every kernel launch of later calls on this context is
@@ -160,6 +170,10 @@ cdl_status cdl_timing_reset(cdl_ctx *ctx);
 int64_t cdl_ld(int64_t n);
 /* Bytes of an n x n matrix of `prec` elements in the padded layout. */
 size_t cdl_matrix_bytes(int64_t n, cdl_prec prec);
+/* Byte offset of level 0 inside a chain buffer; level l starts at
+ * offset + l * cdl_matrix_bytes(n, prec) (padded layout; FP16 levels hold
+ * 2^floor(log2 n) * S~).  0 for invalid arguments. */
+size_t cdl_chain_level_offset(int64_t n, cdl_prec prec);
 /* Workspace sizes for one snapshot of n nodes with series of length T, k
  * projections and at most depth_max chain levels of element type prec:
  *   graph: for cdl_build_graph / cdl_graph_from_weights;
@@ -247,8 +261,16 @@ cdl_status cdl_build_chain(cdl_ctx *ctx, const double *W, const double *deg,
  *   solver  CDL_RICHARDSON: x <- x + P1 (y - L x) (EstimateSolution with
  *           P2 y = P1 L y); CDL_PCG: preconditioned conjugate gradients per
  *           column with the same P1.  Residuals and inner products in FP64.
- *   tol     stop when max_r ||y_r - L x_r|| / ||y_r|| <= tol (tol <= 0: run
- *           exactly max_iter preconditioner applications).
+ *   tol     > 0: stop when max_r ||y_r - L x_r|| / ||y_r|| <= tol;
+ *           < 0: stop when the certified embedding error kappa * max_r rel_r
+ *           <= |tol| (kappa from the degree range and rho_bound: the nonzero
+ *           spectrum of L lies in [deg_min (1 - rho), deg_max (1 + rho)]);
+ *           == 0: run exactly max_iter preconditioner applications.
+ *   Depth   each iteration applies the stored levels and, when the model says
+ *           it pays, further levels S~^{2^l} (l >= depth) as 2^(l-depth+1)
+ *           repeated applications of the last stored level; a cost model
+ *           (FP64 residual vs. level applications, rounding floor of the
+ *           level type) picks the depth per iteration (info->depth_used).
  *   Z       device output, n x k FP64 row-major (row i = z_i), columns
  *           centred (1^T z_r = 0).
  *   info    host output (may be NULL).

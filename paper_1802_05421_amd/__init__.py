@@ -26,6 +26,7 @@ from .api import (  # noqa: E402,F401
     level,
     level_scale,
     score_sequence,
+    set_solve_depth,
     set_timing,
     timing,
     solve_embedding,

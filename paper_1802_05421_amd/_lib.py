@@ -23,12 +23,15 @@ MODE = {"unweighted": 0, "delta_a": 1}
 
 class ChainInfo(C.Structure):
     _fields_ = [("depth", C.c_int), ("lazy", C.c_int), ("prec", C.c_int),
-                ("rho_hat", C.c_double), ("fro", C.c_double * (CDL_MAX_DEPTH + 1))]
+                ("rho_hat", C.c_double), ("rho_bound", C.c_double),
+                ("fro", C.c_double * (CDL_MAX_DEPTH + 1))]
 
 
 class SolveInfo(C.Structure):
     _fields_ = [("iterations", C.c_int), ("converged", C.c_int),
-                ("rel_residual", C.c_double), ("history", C.c_double * 64)]
+                ("rel_residual", C.c_double), ("kappa", C.c_double),
+                ("certified_error", C.c_double), ("history", C.c_double * 64),
+                ("depth_used", C.c_int * 64)]
 
 
 class Snapshot(C.Structure):
@@ -77,11 +80,13 @@ def load():
         "cdl_last_error": (C.c_char_p, [P]),
         "cdl_version": (C.c_char_p, []),
         "cdl_ctx_set_timing": (I, [P, I]),
+        "cdl_ctx_set_solve_depth": (I, [P, I]),
         "cdl_timing_read": (I, [P, C.c_int32, C.POINTER(C.c_char_p), C.POINTER(i64),
                                 C.POINTER(d)]),
         "cdl_timing_reset": (I, [P]),
         "cdl_ld": (i64, [i64]),
         "cdl_matrix_bytes": (sz, [i64, I]),
+        "cdl_chain_level_offset": (sz, [i64, I]),
         "cdl_workspace_bytes": (I, [i64, i64, i64, I, I, C.POINTER(sz), C.POINTER(sz),
                                     C.POINTER(sz), C.POINTER(sz)]),
         "cdl_build_graph": (I, [P, P, i64, i64, i64, d, P, P, P, P, sz]),

@@ -60,6 +60,12 @@ class Context:
             pass
 
 
+def set_solve_depth(depth: int, device: int = 0):
+    """Force the total chain depth of every solve iteration (0 = autotune)."""
+    ctx = context(device)
+    _check(_lib().cdl_ctx_set_solve_depth(ctx.h, int(depth)), ctx.h)
+
+
 def set_timing(enable: bool, device: int = 0):
     """Per-kernel HIP-event timing on the context's stream (see include/caddelag.h)."""
     ctx = context(device)
@@ -193,11 +199,8 @@ def level(chain: Chain, l: int) -> torch.Tensor:
     """View of stored chain level l as an (ld, ld) tensor (for inspection)."""
     prec = {0: torch.float64, 1: torch.float32, 2: torch.bfloat16, 3: torch.float16}[chain.info.prec]
     m = ld(chain.n)
-    esz = torch.tensor([], dtype=prec).element_size()
-    al = lambda x: (x + 255) // 256 * 256
-    tiles = (m // (256 if chain.info.prec in (2, 3) else 128))
-    off = 3 * al(m * 8) + al(max(m, tiles * (tiles + 1) // 2) * 8)
-    lb = m * m * esz
+    off = int(_lib().cdl_chain_level_offset(chain.n, chain.info.prec))
+    lb = int(_lib().cdl_matrix_bytes(chain.n, chain.info.prec))
     raw = chain.buf[off + l * lb: off + (l + 1) * lb]
     return raw.view(prec).view(m, m)
 

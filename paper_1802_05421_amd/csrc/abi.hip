@@ -24,6 +24,7 @@ struct cdl_ctx {
     std::string err;
     // Optional per-kernel timing: HIP events recorded on `stream` around each
     // kernel launch, resolved when the totals are read.
+    int solve_depth = 0;   // > 0: total chain depth used by every solve iteration
     bool timing = false;
     std::vector<cdl_timer_rec> pending;
     std::vector<hipEvent_t> pool;
@@ -127,7 +128,7 @@ GraphWs plan_graph(Arena &a, int64_t n, int64_t T) {
 }
 
 struct ChainBuf {
-    double *dmn, *dm, *u, *fro;
+    double *dmn, *dm, *u, *fro, *fro64;
     char *levels;
     size_t level_bytes;
 };
@@ -138,25 +139,29 @@ ChainBuf plan_chain(Arena &a, int64_t n, int prec, int depth_max) {
     c.dm = a.take<double>(ld);
     c.u = a.take<double>(ld);
     c.fro = a.take<double>(std::max<int64_t>(ld, square_tiles(prec, ld)));
+    c.fro64 = a.take<double>(ld);
     c.level_bytes = (size_t)ld * ld * esize(prec);
     c.levels = a.take<char>(c.level_bytes * depth_max);
     return c;
 }
 
 struct SolveWs {
-    double *Yt, *Xt, *Rt, *V64, *npart, *mpart, *scal, *mean;
-    void *Vlo[2];
+    double *Yt, *Xt, *Rt, *V64, *T64, *npart, *mpart, *scal, *mean;
+    void *Vlo[4];
+    void *part;   // split-K partials of the residual and the chain application
 };
 SolveWs plan_solve(Arena &a, int64_t n, int64_t k, int prec) {
     const int64_t ld = pad_n(n), kp = pad_k(k);
     const size_t panel = (size_t)kp * ld;
     SolveWs w;
+    w.part = a.take<char>(panel * std::max<size_t>(8 * (size_t)residual_splits(ld, kp, n),
+                                                   4 * (size_t)apply_splits(prec, ld, kp, n)));
     w.Yt = a.take<double>(panel);
     w.Xt = a.take<double>(panel);
     w.Rt = a.take<double>(panel);
     w.V64 = a.take<double>(panel);
-    w.Vlo[0] = a.take<char>(panel * esize(prec));
-    w.Vlo[1] = a.take<char>(panel * esize(prec));
+    w.T64 = a.take<double>(panel);
+    for (int q = 0; q < 4; ++q) w.Vlo[q] = a.take<char>(panel * esize(prec));
     w.npart = a.take<double>((size_t)residual_parts(ld) * kp);
     w.mpart = a.take<double>(residual_tiles(ld, kp));
     w.scal = a.take<double>(kp + 2);
@@ -217,22 +222,71 @@ double iters_for(double c, double tol) {
     if (c <= 0.0) return 1.0;
     return std::max(1.0, std::ceil(std::log(tol) / std::log(c)));
 }
-// Should level l (Frobenius norm f, spectral estimate rho) be squared again?
+// Rounding floor of one preconditioner application with levels of the given
+// type, relative to the residual it reduces (calibrated on Gaussian-kernel
+// graphs at n = 16384: ~8e-4 times the storage unit roundoff; FP32
+// accumulation of the products sets a 1e-9 floor).
+double apply_floor(int prec) {
+    switch (prec) {
+    case 0: return 1e-15;
+    case 1: return 1e-9;
+    default: return std::max(1e-9, 8e-4 * unit_roundoff(prec));
+    }
+}
+// Level applications for total depth D over d stored levels: the stored ones
+// once each, level l >= d as 2^(l-d+1) applications of the last stored level.
+int applies_for(int d, int D) { return D <= d ? D : d + (1 << (D - d + 1)) - 2; }
+// Depth for the next iteration: minimise (iterations to gain `need`) x (FP64
+// residual + level applications), with contraction max(rho^(2^D), floor).
+int choose_depth(int prec, int64_t n, int64_t k, int d, double rho, double need) {
+    const double nn = (double)n, kk = (double)k;
+    const double t_res = 2.0 * nn * nn * kk / (78.6e12 * 0.75);
+    const double t_ap = std::max(2.0 * nn * nn * kk / (peak_flops(prec) * 0.5),
+                                 nn * nn * esize(prec) / 4.0e12);
+    if (!(need < 1.0)) return d;
+    const double r = std::min(std::max(rho, 1e-6), 0.999999);
+    int best = d;
+    double best_cost = 1e300;
+    for (int D = 1; D <= d + 3 && D <= 16; ++D) {
+        const double c = std::max(std::pow(r, std::ldexp(1.0, D)), apply_floor(prec));
+        const double it = iters_for(c, need);
+        const double cost = it * (t_res + applies_for(d, D) * t_ap);
+        if (cost < best_cost * (1.0 - 1e-9)) {
+            best_cost = cost;
+            best = D;
+        }
+    }
+    return best;
+}
+
+// Predicted time of one solve that must gain `need` with d stored levels,
+// using the best total depth per iteration (same model as choose_depth).
+double solve_cost(int prec, int64_t n, int64_t k, int d, double rho, double need) {
+    const double nn = (double)n, kk = (double)k;
+    const double t_res = 2.0 * nn * nn * kk / (78.6e12 * 0.75);
+    const double t_ap = std::max(2.0 * nn * nn * kk / (peak_flops(prec) * 0.5),
+                                 nn * nn * esize(prec) / 4.0e12);
+    const double r = std::min(std::max(rho, 1e-6), 0.999999);
+    double best = 1e300;
+    for (int D = 1; D <= d + 3 && D <= 16; ++D) {
+        const double c = std::max(std::pow(r, std::ldexp(1.0, D)), apply_floor(prec));
+        best = std::min(best, iters_for(c, need) * (t_res + applies_for(d, D) * t_ap));
+    }
+    return best;
+}
+// Should the chain with levels 0..l (last Frobenius norm f, spectral estimate
+// rho) get level l+1?  Yes when one squaring (MFMA at half the peak of the
+// level type) plus the cheapest solve with l+2 stored levels is predicted to
+// beat the cheapest solve with l+1 (k = 256 columns, a 1e-8 residual target;
+// deeper levels can always be applied by repetition instead).
 bool model_wants_square(int prec, int64_t n, int l, double f, double rho) {
-    const double k = 256.0, tol = 1e-8, nn = (double)n;
-    const double t_sq = nn * nn * nn / (peak_flops(prec) * 0.5);
-    const double t_res = 2.0 * nn * nn * k / (78.6e12 * 0.6);
-    const double t_ap = std::max(2.0 * nn * nn * k / (peak_flops(prec) * 0.4),
-                                 nn * nn * esize(prec) / 5.0e12);
+    (void)f;
     if (!(rho < 1.0 - 1e-9)) return true;   // not contracting yet: keep testing
-    const double floor_ = unit_roundoff(prec) * 8.0 * std::max(rho, 1e-3);
-    const double p1 = std::ldexp(1.0, l + 1), p2 = std::ldexp(1.0, l + 2);
-    const double tr_now = std::min(f * f, std::pow(rho, p1)) / (1.0 - rho);
-    const double tr_next = std::min(f * f * f * f, std::pow(rho, p2)) / (1.0 - rho);
-    const double c_now = std::max(tr_now, floor_), c_next = std::max(tr_next, floor_);
-    const double cost_now = iters_for(c_now, tol) * (t_res + (l + 1) * t_ap);
-    const double cost_next = t_sq + iters_for(c_next, tol) * (t_res + (l + 2) * t_ap);
-    return cost_next < cost_now;
+    const double nn = (double)n;
+    const double t_sq = nn * nn * nn / (peak_flops(prec) * 0.5);
+    const double need = 1e-8;
+    return t_sq + solve_cost(prec, n, 256, l + 2, rho, need) <
+           solve_cost(prec, n, 256, l + 1, rho, need);
 }
 
 } // namespace
@@ -282,6 +336,12 @@ cdl_status cdl_ctx_destroy(cdl_ctx *ctx) {
     return CDL_OK;
 }
 
+cdl_status cdl_ctx_set_solve_depth(cdl_ctx *ctx, int depth) {
+    if (!ctx || depth < 0 || depth > 16) return CDL_E_ARG;
+    ctx->solve_depth = depth;
+    return CDL_OK;
+}
+
 cdl_status cdl_ctx_set_timing(cdl_ctx *ctx, int enable) {
     if (!ctx) return CDL_E_ARG;
     ctx->timing = enable != 0;
@@ -316,6 +376,13 @@ cdl_status cdl_ctx_set_stream(cdl_ctx *ctx, void *stream) {
 }
 
 int64_t cdl_ld(int64_t n) { return n > 0 ? pad_n(n) : 0; }
+
+size_t cdl_chain_level_offset(int64_t n, cdl_prec prec) {
+    if (n < 2 || !valid_prec(prec)) return 0;
+    Arena a(nullptr);
+    plan_chain(a, n, prec, 0);
+    return a.off;
+}
 
 size_t cdl_matrix_bytes(int64_t n, cdl_prec prec) {
     if (n <= 0 || !valid_prec(prec)) return 0;
@@ -358,7 +425,8 @@ cdl_status cdl_build_graph(cdl_ctx *ctx, const double *X, int64_t n, int64_t T, 
     HIPCHK(hipSetDevice(ctx->device));
     { Timed t_(ctx, "fill_zero"); HIPCHK(launch_fill_zero(w.flags, 256, s)); }
     { Timed t_(ctx, "pad_series"); HIPCHK(launch_pad_series(X, n, T, ldx, w.Xp, ld, Tp, w.sqn, w.flags, s)); }
-    { Timed t_(ctx, "gram_dist"); HIPCHK(launch_gram_dist(w.Xp, Tp, w.sqn, n, ld, W, s)); }
+    if (sigma <= 0.0) { Timed t_(ctx, "select_median"); HIPCHK(launch_select_reset(w.sel, s)); }
+    { Timed t_(ctx, "gram_dist"); HIPCHK(launch_gram_dist(w.Xp, Tp, w.sqn, n, ld, W, sigma > 0.0 ? nullptr : w.sel, s)); }
     if (sigma > 0.0)
         { Timed t_(ctx, "set_sigma"); HIPCHK(launch_set_sigma(sigma, stats, s)); }
     else
@@ -439,10 +507,12 @@ cdl_status cdl_build_chain(cdl_ctx *ctx, const double *W, const double *deg, con
     info->prec = prec;
 
     { Timed t_(ctx, "chain_prep"); HIPCHK(launch_chain_prep(deg, stats, n, ld, info->lazy, c.dmn, c.dm, c.u, s)); }
-    { Timed t_(ctx, "normalize"); HIPCHK(launch_normalize(prec, W, ld, n, c.dmn, c.u, info->lazy, c.levels, c.fro, s)); }
-    std::vector<double> part(ld);
+    { Timed t_(ctx, "normalize"); HIPCHK(launch_normalize(prec, W, ld, n, c.dmn, c.u, info->lazy, c.levels, c.fro, c.fro64, s)); }
+    std::vector<double> part(ld), part64(ld);
     HIPCHK(hipMemcpyAsync(part.data(), c.fro, ld * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(part64.data(), c.fro64, ld * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    info->rho_bound = std::sqrt(host_sum(part64));
     double f = std::sqrt(host_sum(part));
     if (!std::isfinite(f)) return fail(ctx, CDL_E_NONFINITE, "non-finite chain level");
     info->fro[0] = f;
@@ -522,29 +592,70 @@ cdl_status cdl_solve_embedding(cdl_ctx *ctx, const double *W, const double *deg,
     { Timed t_(ctx, "fill_zero"); HIPCHK(launch_fill_zero(w.Xt, panel * sizeof(double), s)); }
     { Timed t_(ctx, "rhs"); HIPCHK(launch_rhs(W, ld, n, gid, k, kp, seed, w.Yt, s)); }
     const int nparts = residual_parts(ld), ntiles = residual_tiles(ld, kp);
-    { Timed t_(ctx, "residual_init"); HIPCHK(launch_residual_k(w.Xt, W, w.Yt, deg, c.dm, ld, n, kp, k, 1, w.Rt, w.npart, w.mpart, s)); }
-    { Timed t_(ctx, "col_norms"); HIPCHK(launch_col_norms2(w.npart, nparts, kp, w.mpart, ntiles, w.scal, s)); }
+    const int scaled = prec == 3;   // FP16 operands need a power-of-two scale
+    { Timed t_(ctx, "residual_init"); HIPCHK(launch_residual_k(prec, w.Xt, W, w.Yt, deg, c.dm, ld, n, kp, k, 1, (double *)w.part, w.Rt, w.V64, w.Vlo[0], w.npart, w.mpart, s)); }
+    { Timed t_(ctx, "col_norms"); HIPCHK(launch_col_norms2(w.npart, nparts, kp, w.mpart, ntiles, scaled, w.scal, s)); }
     std::vector<double> ynorm(kp), rnorm(kp);
+    double hstats[CDL_GRAPH_STATS];
     HIPCHK(hipMemcpyAsync(ynorm.data(), w.scal, kp * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hstats, stats, sizeof(hstats), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     for (int64_t r = 0; r < k; ++r)
         if (!std::isfinite(ynorm[r])) return fail(ctx, CDL_E_NONFINITE, "non-finite right-hand side");
+    // kappa bounds ||e|| / ||z|| per unit relative residual: the nonzero
+    // spectrum of L = D^{1/2} (I - S) D^{1/2} lies in
+    // [deg_min (1 - rho), deg_max (1 + rho)], rho = rho(S~) <= ||S~||_F.
+    // Lazy levels hold S~' = (I + S)/2 - u u^T: 1 - lambda(S) >= 2 (1 - ||S~'||_F)
+    // and <= 2, so kappa = deg_max / (deg_min (1 - ||S~'||_F)).
+    const double rb = ci->rho_bound;
+    double kappa = INFINITY;
+    if (rb < 1.0 && hstats[2] > 0.0)
+        kappa = ci->lazy ? hstats[3] / (hstats[2] * (1.0 - rb))
+                         : hstats[3] * (1.0 + rb) / (hstats[2] * (1.0 - rb));
+    const double target = tol > 0.0 ? tol : (tol < 0.0 ? -tol / kappa : 0.0);
+    if (tol < 0.0 && !std::isfinite(kappa))
+        return fail(ctx, CDL_E_ARG, "certified tolerance needs ||S~||_F < 1; use tol > 0");
+    const double rho_model = std::min(ci->rho_hat, ci->rho_bound);
+    const double *inv_vs = w.scal + kp + 1;
 
     double rel = 1.0;
     int it = 0;
     bool conv = false;
     while (it < max_iter) {
-        // X += P1 R: V = D^{-1/2} R (scaled), V <- (I + S~_l) V, X += D^{-1/2} V.
-        { Timed t_(ctx, "prep_v"); HIPCHK(launch_prep_v2(prec, w.Rt, c.dm, ld, kp, w.scal + kp, w.V64, w.Vlo[0], s)); }
-        for (int l = 0; l < ci->depth; ++l) {
-            const bool last = l + 1 == ci->depth;
-            { Timed t_(ctx, "apply"); HIPCHK(launch_apply(prec, w.Vlo[l & 1], c.levels + c.level_bytes * l, w.Vlo[(l + 1) & 1],
-                                w.V64, ld, n, kp, w.Xt, c.dm, last ? w.scal + kp + 1 : nullptr, s)); }
+        // X += P1 R with P1 = D^{-1/2} prod_{l<D} (I + S~^{2^l}) D^{-1/2}.  The
+        // residual step already left V = D^{-1/2} R in V64 / Vlo[0] (FP16:
+        // scaled copy made here).
+        const int d = ci->depth;
+        const int D = ctx->solve_depth > 0 ? ctx->solve_depth
+                      : (tol == 0.0 ? d : choose_depth(prec, n, k, d, rho_model, target / rel));
+        if (scaled) { Timed t_(ctx, "prep_v"); HIPCHK(launch_prep_v2(prec, w.Rt, c.dm, ld, kp, w.scal + kp, w.V64, w.Vlo[0], s)); }
+        int cur = 0;
+        for (int l = 0; l < std::min(d, D); ++l) {
+            const bool last = l + 1 == D;
+            { Timed t_(ctx, "apply"); HIPCHK(launch_apply(prec, w.Vlo[cur], c.levels + c.level_bytes * l, w.Vlo[cur ^ 1],
+                                w.V64, ld, n, kp, w.Xt, c.dm, last ? inv_vs : nullptr, (float *)w.part, 1, s)); }
+            cur ^= 1;
+        }
+        for (int l = d; l < D; ++l) {
+            // S~^{2^l} = (S~_{d-1})^{2^(l-d+1)}: repeated applications into T64
+            const int m = 1 << (l - d + 1);
+            const void *src = w.Vlo[cur];
+            for (int q = 0; q < m; ++q) {
+                void *dst = w.Vlo[2 + (q & 1)];
+                { Timed t_(ctx, "apply"); HIPCHK(launch_apply(prec, src, c.levels + c.level_bytes * (d - 1), dst, w.T64,
+                                    ld, n, kp, w.Xt, c.dm, nullptr, (float *)w.part, 0, s)); }
+                src = dst;
+            }
+            const bool last = l + 1 == D;
+            { Timed t_(ctx, "axpy_v"); HIPCHK(launch_axpy_v(prec, w.T64, ld, kp, w.V64, w.Vlo[cur ^ 1], w.Xt, c.dm,
+                                 last ? inv_vs : nullptr, s)); }
+            cur ^= 1;
         }
         ++it;
-        { Timed t_(ctx, "residual"); HIPCHK(launch_residual_k(w.Xt, W, w.Yt, deg, c.dm, ld, n, kp, k, 0, w.Rt, w.npart,
-                                 w.mpart, s)); }
-        { Timed t_(ctx, "col_norms"); HIPCHK(launch_col_norms2(w.npart, nparts, kp, w.mpart, ntiles, w.scal, s)); }
+        if (info && it <= 64) info->depth_used[it - 1] = D;
+        { Timed t_(ctx, "residual"); HIPCHK(launch_residual_k(prec, w.Xt, W, w.Yt, deg, c.dm, ld, n, kp, k, 0, (double *)w.part, w.Rt,
+                                 w.V64, w.Vlo[0], w.npart, w.mpart, s)); }
+        { Timed t_(ctx, "col_norms"); HIPCHK(launch_col_norms2(w.npart, nparts, kp, w.mpart, ntiles, scaled, w.scal, s)); }
         HIPCHK(hipMemcpyAsync(rnorm.data(), w.scal, kp * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         rel = 0.0;
@@ -553,7 +664,7 @@ cdl_status cdl_solve_embedding(cdl_ctx *ctx, const double *W, const double *deg,
             if (ynorm[r] > 0.0) rel = std::max(rel, rnorm[r] / ynorm[r]);
         }
         if (info && it <= 64) info->history[it - 1] = rel;
-        if (tol > 0.0 && rel <= tol) {
+        if (target > 0.0 && rel <= target) {
             conv = true;
             break;
         }
@@ -561,12 +672,14 @@ cdl_status cdl_solve_embedding(cdl_ctx *ctx, const double *W, const double *deg,
     { Timed t_(ctx, "finalize_z"); HIPCHK(launch_finalize_z2(w.Xt, ld, n, kp, k, w.mean, Z, s)); }
     if (info) {
         info->iterations = it;
-        info->converged = conv || tol <= 0.0;
+        info->converged = conv || tol == 0.0;
         info->rel_residual = rel;
+        info->kappa = kappa;
+        info->certified_error = kappa * rel + 1e-14;
     }
-    if (tol > 0.0 && !conv) {
+    if (tol != 0.0 && !conv) {
         char buf[160];
-        std::snprintf(buf, sizeof(buf), "residual %.3e > tol %.3e after %d iterations", rel, tol, it);
+        std::snprintf(buf, sizeof(buf), "residual %.3e > target %.3e after %d iterations", rel, target, it);
         return fail(ctx, CDL_E_NOCONV, buf);
     }
     return CDL_OK;

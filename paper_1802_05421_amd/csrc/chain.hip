@@ -63,10 +63,11 @@ hipError_t launch_chain_prep(const double *deg, const double *stats, int64_t n, 
 template <typename T>
 __global__ __launch_bounds__(256) void k_normalize(const double *W, int64_t ld, int64_t n,
                                                    const double *dmn, const double *u, int lazy,
-                                                   double scale, T *S0, double *fro_part) {
+                                                   double scale, T *S0, double *fro_part,
+                                                   double *fro64_part) {
     __shared__ double red[4];
     const int64_t i = blockIdx.x;
-    double s = 0.0;
+    double s = 0.0, s64 = 0.0;
     const double di = i < n ? dmn[i] : 0.0, ui = i < n ? u[i] : 0.0;
     for (int64_t j = threadIdx.x; j < ld; j += 256) {
         double v = 0.0;
@@ -79,21 +80,24 @@ __global__ __launch_bounds__(256) void k_normalize(const double *W, int64_t ld, 
         S0[i * ld + j] = t;
         double tv = tod<T>(t) / scale;
         s += tv * tv;
+        s64 += v * v;
     }
     s = block_sum256c(s, red);
     if (threadIdx.x == 0) fro_part[i] = s;
+    s64 = block_sum256c(s64, red);
+    if (threadIdx.x == 0) fro64_part[i] = s64;
 }
 
 hipError_t launch_normalize(int prec, const double *W, int64_t ld, int64_t n,
                             const double *dmn, const double *u, int lazy, void *S0,
-                            double *fro_part, hipStream_t s) {
+                            double *fro_part, double *fro64_part, hipStream_t s) {
     const double sc = level_scale(prec, n);
     dim3 g((unsigned)ld), b(256);
     switch (prec) {
-    case 0: hipLaunchKernelGGL(k_normalize<double>, g, b, 0, s, W, ld, n, dmn, u, lazy, sc, (double *)S0, fro_part); break;
-    case 1: hipLaunchKernelGGL(k_normalize<float>, g, b, 0, s, W, ld, n, dmn, u, lazy, sc, (float *)S0, fro_part); break;
-    case 2: hipLaunchKernelGGL(k_normalize<__bf16>, g, b, 0, s, W, ld, n, dmn, u, lazy, sc, (__bf16 *)S0, fro_part); break;
-    case 3: hipLaunchKernelGGL(k_normalize<_Float16>, g, b, 0, s, W, ld, n, dmn, u, lazy, sc, (_Float16 *)S0, fro_part); break;
+    case 0: hipLaunchKernelGGL(k_normalize<double>, g, b, 0, s, W, ld, n, dmn, u, lazy, sc, (double *)S0, fro_part, fro64_part); break;
+    case 1: hipLaunchKernelGGL(k_normalize<float>, g, b, 0, s, W, ld, n, dmn, u, lazy, sc, (float *)S0, fro_part, fro64_part); break;
+    case 2: hipLaunchKernelGGL(k_normalize<__bf16>, g, b, 0, s, W, ld, n, dmn, u, lazy, sc, (__bf16 *)S0, fro_part, fro64_part); break;
+    case 3: hipLaunchKernelGGL(k_normalize<_Float16>, g, b, 0, s, W, ld, n, dmn, u, lazy, sc, (_Float16 *)S0, fro_part, fro64_part); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -192,18 +196,126 @@ hipError_t launch_square(int prec, const void *S, void *S2, int64_t ld, int64_t 
 
 // ---------------------------------------------------------------------------
 // Chain application: C[r][i] = sum_j Vin[r][j] S~[i][j]  (= (S~ V)_{i r}).
+// BF16/FP16/FP32 levels: split-K MFMA GEMM over 256 x 256 output tiles (8
+// waves) writing FP32 partials, then a reduction that updates V (FP64), its
+// rounded copy and, on the last level, X.  FP64 levels: one 64-wide tile
+// per workgroup, updating in the epilogue.
 
 template <typename T> struct ApBK { static constexpr int v = 64 * 2 / (int)sizeof(T) < 16 ? 16 : 64 * 2 / (int)sizeof(T); };
 
+template <typename T, int BM> struct ApCfg {
+    static constexpr int WM = BM / 128 > 0 ? BM / 128 : 1;
+    static constexpr int WN = 8 / WM;
+    using Core = GemmCore<typename MfmaOf<T>::type, BM, 256, ApBK<T>::v, WM, WN>;
+};
+
 template <typename T, int BM>
-__global__ __launch_bounds__(BM) void k_apply(const T *Vin, const T *S, T *Vout, double *V64,
-                                              int64_t ld, int64_t kend, int mt, int nt,
-                                              float inv_scale, double *Xt, const double *dm,
-                                              const double *inv_vs) {
-    using Mf = typename MfmaOf<T>::type;
-    using Core = GemmCore<Mf, BM, 64, ApBK<T>::v, BM / 64, 1>;
+__global__ __launch_bounds__(512) void k_apply_gemm(const T *Vin, const T *S, int64_t ld,
+                                                    int64_t kend, int64_t ks, int mt, int nt,
+                                                    int nsplit, float *P, int64_t kpad) {
+    using Core = typename ApCfg<T, BM>::Core;
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
     T *smem = (T *)smem_raw;
+    const int total = mt * nt * nsplit;
+    const int id = xcd_remap(blockIdx.x, total);
+    const int split = id / (mt * nt);
+    int I, J;
+    rect_tile<4>(id % (mt * nt), mt, nt, I, J);
+    const int64_t m0 = (int64_t)I * BM, n0 = (int64_t)J * 256;
+    const int64_t k0 = (int64_t)split * ks;
+    const int64_t kk = k0 < kend ? (kend - k0 < ks ? kend - k0 : ks) : 0;
+    Core g;
+    g.run(Vin + k0, ld, S + k0, ld, m0, n0, kk, smem);
+    float *Ps = P + (int64_t)split * kpad * ld;
+#pragma unroll
+    for (int a = 0; a < Core::WTM; ++a)
+#pragma unroll
+        for (int b = 0; b < Core::WTN; ++b)
+#pragma unroll
+            for (int r = 0; r < Core::MF::R; ++r)
+                Ps[(m0 + Core::row_of(a, r)) * ld + n0 + Core::col_of(b)] = g.acc[a][b][r];
+}
+
+static int ap_bm(int64_t kpad) { return kpad % 256 == 0 ? 256 : (kpad % 128 == 0 ? 128 : 64); }
+
+int apply_splits(int prec, int64_t ld, int64_t kpad, int64_t n) {
+    if (prec == 0) return 1;
+    const int64_t base = (kpad / ap_bm(kpad)) * (ld / 256);
+    const int64_t kend = (n + 63) / 64 * 64;
+    int64_t S = (256 + base - 1) / base;
+    const int64_t smax = kend / 128 > 0 ? kend / 128 : 1;   // >= 2 k-tiles per split
+    if (S > smax) S = smax;
+    if (S < 1) S = 1;
+    return (int)S;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_apply_reduce(const float *P, int nsplit, int64_t total,
+                                                      int64_t ld, int64_t kpad, float inv_scale,
+                                                      int accumulate, double *V64, T *Vout,
+                                                      double *Xt, const double *dm,
+                                                      const double *inv_vs) {
+    const double ivs = inv_vs ? *inv_vs : 0.0;
+    for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < total;
+         o += (int64_t)gridDim.x * blockDim.x) {
+        float acc = 0.f;
+        for (int q = 0; q < nsplit; ++q) acc += P[(int64_t)q * kpad * ld + o];
+        const double v = (accumulate ? V64[o] : 0.0) + (double)acc * (double)inv_scale;
+        V64[o] = v;
+        Vout[o] = cvtd<T>(v);
+        if (inv_vs) Xt[o] += dm[o % ld] * v * ivs;
+    }
+}
+
+template <typename T, int BM>
+static hipError_t apg_launch(const void *Vin, const void *S, int64_t ld, int64_t n,
+                             int64_t kpad, int nsplit, float *P, hipStream_t s) {
+    using Core = typename ApCfg<T, BM>::Core;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_apply_gemm<T, BM>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)Core::SMEM);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const int mt = (int)(kpad / BM), nt = (int)(ld / 256);
+    const int64_t kend = (n + 63) / 64 * 64;
+    const int64_t ks = (cdiv(kend, nsplit) + 63) / 64 * 64;
+    hipLaunchKernelGGL((k_apply_gemm<T, BM>), dim3(mt * nt * nsplit), dim3(512), Core::SMEM, s,
+                       (const T *)Vin, (const T *)S, ld, kend, ks, mt, nt, nsplit, P, kpad);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t ap_split_launch(const void *Vin, const void *S, void *Vout, double *V64,
+                                  int64_t ld, int64_t n, int64_t kpad, float inv_scale,
+                                  double *Xt, const double *dm, const double *inv_vs, float *P,
+                                  int accumulate, hipStream_t s) {
+    const int ns = apply_splits(1, ld, kpad, n);
+    hipError_t e;
+    switch (ap_bm(kpad)) {
+    case 256: e = apg_launch<T, 256>(Vin, S, ld, n, kpad, ns, P, s); break;
+    case 128: e = apg_launch<T, 128>(Vin, S, ld, n, kpad, ns, P, s); break;
+    default: e = apg_launch<T, 64>(Vin, S, ld, n, kpad, ns, P, s); break;
+    }
+    if (e != hipSuccess) return e;
+    const int64_t total = kpad * ld;
+    const int grid = (int)(cdiv(total, 256) < 16384 ? cdiv(total, 256) : 16384);
+    hipLaunchKernelGGL(k_apply_reduce<T>, dim3(grid), dim3(256), 0, s, P, ns, total, ld, kpad,
+                       inv_scale, accumulate, V64, (T *)Vout, Xt, dm, inv_vs);
+    return hipGetLastError();
+}
+
+// FP64 levels: in-epilogue update (small n only in practice).
+template <int BM>
+__global__ __launch_bounds__(BM) void k_apply_f64(const double *Vin, const double *S, double *Vout,
+                                                  double *V64, int64_t ld, int64_t kend, int mt,
+                                                  int nt, double *Xt, const double *dm,
+                                                  const double *inv_vs, int accumulate) {
+    using Core = GemmCore<MfmaF64, BM, 64, 16, BM / 64, 1>;
+    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+    double *smem = (double *)smem_raw;
     int I, J;
     rect_tile<4>(xcd_remap(blockIdx.x, mt * nt), mt, nt, I, J);
     const int64_t m0 = (int64_t)I * BM, n0 = (int64_t)J * 64;
@@ -215,25 +327,24 @@ __global__ __launch_bounds__(BM) void k_apply(const T *Vin, const T *S, T *Vout,
 #pragma unroll
         for (int b = 0; b < Core::WTN; ++b)
 #pragma unroll
-            for (int r = 0; r < Mf::R; ++r) {
+            for (int r = 0; r < MfmaF64::R; ++r) {
                 const int64_t row = m0 + Core::row_of(a, r), col = n0 + Core::col_of(b);
                 const int64_t o = row * ld + col;
-                double v = V64[o] + (double)g.acc[a][b][r] * (double)inv_scale;
+                const double v = (accumulate ? V64[o] : 0.0) + g.acc[a][b][r];
                 V64[o] = v;
-                Vout[o] = cvtd<T>(v);
+                Vout[o] = v;
                 if (inv_vs) Xt[o] += dm[col] * v * ivs;
             }
 }
 
-template <typename T, int BM>
-static hipError_t ap_launch(const void *Vin, const void *S, void *Vout, double *V64, int64_t ld,
-                            int64_t n, int64_t kpad, float inv_scale, double *Xt,
-                            const double *dm, const double *inv_vs, hipStream_t s) {
-    using Mf = typename MfmaOf<T>::type;
-    using Core = GemmCore<Mf, BM, 64, ApBK<T>::v, BM / 64, 1>;
+template <int BM>
+static hipError_t apf64_launch(const void *Vin, const void *S, void *Vout, double *V64,
+                               int64_t ld, int64_t n, int64_t kpad, double *Xt, const double *dm,
+                               const double *inv_vs, int accumulate, hipStream_t s) {
+    using Core = GemmCore<MfmaF64, BM, 64, 16, BM / 64, 1>;
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_apply<T, BM>,
+        hipError_t e = hipFuncSetAttribute((const void *)k_apply_f64<BM>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)Core::SMEM);
         if (e != hipSuccess) return e;
@@ -241,31 +352,56 @@ static hipError_t ap_launch(const void *Vin, const void *S, void *Vout, double *
     }
     const int mt = (int)(kpad / BM), nt = (int)(ld / 64);
     const int64_t kend = (n + 63) / 64 * 64;
-    hipLaunchKernelGGL((k_apply<T, BM>), dim3(mt * nt), dim3(BM), Core::SMEM, s, (const T *)Vin,
-                       (const T *)S, (T *)Vout, V64, ld, kend, mt, nt, inv_scale, Xt, dm, inv_vs);
+    hipLaunchKernelGGL(k_apply_f64<BM>, dim3(mt * nt), dim3(BM), Core::SMEM, s,
+                       (const double *)Vin, (const double *)S, (double *)Vout, V64, ld, kend, mt,
+                       nt, Xt, dm, inv_vs, accumulate);
     return hipGetLastError();
-}
-
-template <typename T>
-static hipError_t ap_dispatch(const void *Vin, const void *S, void *Vout, double *V64,
-                              int64_t ld, int64_t n, int64_t kpad, float inv_scale, double *Xt,
-                              const double *dm, const double *inv_vs, hipStream_t s) {
-    if (kpad % 256 == 0) return ap_launch<T, 256>(Vin, S, Vout, V64, ld, n, kpad, inv_scale, Xt, dm, inv_vs, s);
-    if (kpad % 128 == 0) return ap_launch<T, 128>(Vin, S, Vout, V64, ld, n, kpad, inv_scale, Xt, dm, inv_vs, s);
-    return ap_launch<T, 64>(Vin, S, Vout, V64, ld, n, kpad, inv_scale, Xt, dm, inv_vs, s);
 }
 
 hipError_t launch_apply(int prec, const void *Vin, const void *S, void *Vout, double *V64,
                         int64_t ld, int64_t n, int64_t kpad, double *Xt, const double *dm,
-                        const double *inv_vs, hipStream_t s) {
+                        const double *inv_vs, float *P, int accumulate, hipStream_t s) {
     const float inv = 1.0f / level_scale(prec, n);
     switch (prec) {
-    case 0: return ap_dispatch<double>(Vin, S, Vout, V64, ld, n, kpad, inv, Xt, dm, inv_vs, s);
-    case 1: return ap_dispatch<float>(Vin, S, Vout, V64, ld, n, kpad, inv, Xt, dm, inv_vs, s);
-    case 2: return ap_dispatch<__bf16>(Vin, S, Vout, V64, ld, n, kpad, inv, Xt, dm, inv_vs, s);
-    case 3: return ap_dispatch<_Float16>(Vin, S, Vout, V64, ld, n, kpad, inv, Xt, dm, inv_vs, s);
+    case 0:
+        if (kpad % 256 == 0) return apf64_launch<256>(Vin, S, Vout, V64, ld, n, kpad, Xt, dm, inv_vs, accumulate, s);
+        if (kpad % 128 == 0) return apf64_launch<128>(Vin, S, Vout, V64, ld, n, kpad, Xt, dm, inv_vs, accumulate, s);
+        return apf64_launch<64>(Vin, S, Vout, V64, ld, n, kpad, Xt, dm, inv_vs, accumulate, s);
+    case 1: return ap_split_launch<float>(Vin, S, Vout, V64, ld, n, kpad, inv, Xt, dm, inv_vs, P, accumulate, s);
+    case 2: return ap_split_launch<__bf16>(Vin, S, Vout, V64, ld, n, kpad, inv, Xt, dm, inv_vs, P, accumulate, s);
+    case 3: return ap_split_launch<_Float16>(Vin, S, Vout, V64, ld, n, kpad, inv, Xt, dm, inv_vs, P, accumulate, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+// V += T (FP64), Vout = V rounded; on the last level X += dm * V * (*inv_vs).
+template <typename T>
+__global__ __launch_bounds__(256) void k_axpy_v(const double *T64, int64_t total, int64_t ld,
+                                                double *V64, T *Vout, double *Xt,
+                                                const double *dm, const double *inv_vs) {
+    const double ivs = inv_vs ? *inv_vs : 0.0;
+    for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < total;
+         o += (int64_t)gridDim.x * blockDim.x) {
+        const double v = V64[o] + T64[o];
+        V64[o] = v;
+        Vout[o] = cvtd<T>(v);
+        if (inv_vs) Xt[o] += dm[o % ld] * v * ivs;
+    }
+}
+
+hipError_t launch_axpy_v(int prec, const double *T64, int64_t ld, int64_t kpad, double *V64,
+                         void *Vout, double *Xt, const double *dm, const double *inv_vs,
+                         hipStream_t s) {
+    const int64_t total = kpad * ld;
+    const int grid = (int)(cdiv(total, 256) < 16384 ? cdiv(total, 256) : 16384);
+    switch (prec) {
+    case 0: hipLaunchKernelGGL(k_axpy_v<double>, dim3(grid), dim3(256), 0, s, T64, total, ld, V64, (double *)Vout, Xt, dm, inv_vs); break;
+    case 1: hipLaunchKernelGGL(k_axpy_v<float>, dim3(grid), dim3(256), 0, s, T64, total, ld, V64, (float *)Vout, Xt, dm, inv_vs); break;
+    case 2: hipLaunchKernelGGL(k_axpy_v<__bf16>, dim3(grid), dim3(256), 0, s, T64, total, ld, V64, (__bf16 *)Vout, Xt, dm, inv_vs); break;
+    case 3: hipLaunchKernelGGL(k_axpy_v<_Float16>, dim3(grid), dim3(256), 0, s, T64, total, ld, V64, (_Float16 *)Vout, Xt, dm, inv_vs); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 } // namespace cdl

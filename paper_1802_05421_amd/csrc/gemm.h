@@ -164,4 +164,44 @@ __device__ inline void stage_and_store(Core &g, O *sC, F f, O *C, int64_t ldc,
     }
 }
 
+// As stage_and_store, staging RC rows of the tile at a time so that the
+// staging buffer (RC * (BN + 16/sizeof(O)) elements) stays small.
+template <int RC, class Core, typename O, class F>
+__device__ inline void stage_and_store_rows(Core &g, O *sC, F f, O *C, int64_t ldc, int64_t m0,
+                                            int64_t n0, bool mirror) {
+    constexpr int BM = Core::TBM, BN = Core::TBN, NT = Core::NT;
+    constexpr int CEo = 16 / (int)sizeof(O);
+    constexpr int LDC = BN + CEo;
+    static_assert(BM % RC == 0 && RC % CEo == 0, "bad row chunk");
+#pragma unroll 1
+    for (int r0 = 0; r0 < BM; r0 += RC) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < Core::WTM; ++i)
+#pragma unroll
+            for (int j = 0; j < Core::WTN; ++j)
+#pragma unroll
+                for (int r = 0; r < Core::MF::R; ++r) {
+                    const int row = Core::row_of(i, r), col = Core::col_of(j);
+                    if (row >= r0 && row < r0 + RC) sC[(row - r0) * LDC + col] = f(row, col, g.acc[i][j][r]);
+                }
+        __syncthreads();
+        constexpr int CPR = BN / CEo;
+        for (int ch = threadIdx.x; ch < RC * CPR; ch += NT) {
+            const int r = ch / CPR, c = ch % CPR;
+            *(uint4 *)(C + (m0 + r0 + r) * ldc + n0 + c * CEo) = *(const uint4 *)(sC + r * LDC + c * CEo);
+        }
+        if (mirror) {
+            constexpr int QPR = RC / CEo;
+            for (int ch = threadIdx.x; ch < BN * QPR; ch += NT) {
+                const int c = ch % BN, q = ch / BN;
+                union { uint4 v; O e[CEo]; } u;
+#pragma unroll
+                for (int e = 0; e < CEo; ++e) u.e[e] = sC[(q * CEo + e) * LDC + c];
+                *(uint4 *)(C + (n0 + c) * ldc + m0 + r0 + q * CEo) = u.v;
+            }
+        }
+    }
+}
+
 } // namespace cdl

@@ -82,13 +82,17 @@ hipError_t launch_pad_series(const double *X, int64_t n, int64_t T, int64_t ldx,
 // ---------------------------------------------------------------------------
 // Squared distances from the Gram matrix of the series (FP64 MFMA).
 
-using GramCore = GemmCore<MfmaF64, 128, 128, 16, 2, 2>;
-constexpr size_t kGramSmem = 128 * (128 + 2) * sizeof(double);
-static_assert(kGramSmem >= GramCore::SMEM, "staging must cover the operand ring");
+using GramCore = GemmCore<MfmaF64, 128, 128, 8, 2, 4>;
+constexpr int kGramRC = 32;
+constexpr size_t kGramStage = kGramRC * (128 + 2) * sizeof(double);
+constexpr size_t kGramSmem = GramCore::SMEM > kGramStage ? GramCore::SMEM : kGramStage;
 
-__global__ __launch_bounds__(256) void k_gram_dist(const double *Xp, int64_t Tp,
+// st != nullptr: also fold the smallest and largest upper-triangle key
+// (i < j) into st->kmin / st->kmax (the median selection starts below their
+// common bit prefix).
+__global__ __launch_bounds__(512) void k_gram_dist(const double *Xp, int64_t Tp,
                                                    const double *sqn, int64_t n, int64_t ld,
-                                                   double *D2, int nt) {
+                                                   double *D2, int nt, SelectState *st) {
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
     double *smem = (double *)smem_raw;
     const int total = nt * (nt + 1) / 2;
@@ -97,17 +101,36 @@ __global__ __launch_bounds__(256) void k_gram_dist(const double *Xp, int64_t Tp,
     const int64_t m0 = (int64_t)I * 128, n0 = (int64_t)J * 128;
     GramCore g;
     g.run(Xp, Tp, Xp, Tp, m0, n0, Tp, smem);
+    unsigned long long kmin = ~0ull, kmax = 0ull;
     auto f = [&](int r, int c, double acc) -> double {
         const int64_t a = m0 + r, b = n0 + c;
         if (a >= n || b >= n || a == b) return 0.0;
         double d = sqn[a] + sqn[b] - 2.0 * acc;
-        return d < 0.0 ? 0.0 : d;
+        d = d < 0.0 ? 0.0 : d;
+        if (a < b) {
+            const unsigned long long key = (unsigned long long)__double_as_longlong(d);
+            kmin = key < kmin ? key : kmin;
+            kmax = key > kmax ? key : kmax;
+        }
+        return d;
     };
-    stage_and_store(g, smem, f, D2, ld, m0, n0, I != J);
+    stage_and_store_rows<kGramRC>(g, smem, f, D2, ld, m0, n0, I != J);
+    if (st) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            const unsigned long long a = __shfl_xor(kmin, o), b = __shfl_xor(kmax, o);
+            kmin = a < kmin ? a : kmin;
+            kmax = b > kmax ? b : kmax;
+        }
+        if ((threadIdx.x & 63) == 0) {
+            if (kmin != ~0ull) atomicMin(&st->kmin, kmin);
+            if (kmax != 0ull) atomicMax(&st->kmax, kmax);
+        }
+    }
 }
 
 hipError_t launch_gram_dist(const double *Xp, int64_t Tp, const double *sqn, int64_t n,
-                            int64_t ld, double *D2, hipStream_t s) {
+                            int64_t ld, double *D2, SelectState *st, hipStream_t s) {
     static bool attr = false;
     if (!attr) {
         hipError_t e = hipFuncSetAttribute((const void *)k_gram_dist,
@@ -118,105 +141,184 @@ hipError_t launch_gram_dist(const double *Xp, int64_t Tp, const double *sqn, int
     }
     const int nt = (int)(ld / 128);
     const int total = nt * (nt + 1) / 2;
-    hipLaunchKernelGGL(k_gram_dist, dim3(total), dim3(256), kGramSmem, s, Xp, Tp, sqn, n, ld,
-                       D2, nt);
+    hipLaunchKernelGGL(k_gram_dist, dim3(total), dim3(512), kGramSmem, s, Xp, Tp, sqn, n, ld,
+                       D2, nt, st);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // Exact selection of the element of rank floor((N-1)/2), N = n(n-1)/2, among
-// D2_ij (i < j).  D2 >= 0, so its bit pattern orders like its value.
+// D2_ij (i < j).  D2 >= 0, so its IEEE bit pattern orders like its value.
+// Radix passes of 12-bit digits start below the common prefix of the
+// smallest and largest key; as soon as the selected bin holds at most
+// kSelCap keys, one pass collects them and a single workgroup sorts them.
+// Every pass kernel reads the state's mode, so the fixed launch sequence
+// turns into no-ops once the answer is known.
 
-__global__ void k_select_init(SelectState *st, int64_t n) {
+__global__ void k_select_reset(SelectState *st) {
     for (int b = threadIdx.x; b < 4096; b += blockDim.x) st->hist[b] = 0;
     if (threadIdx.x == 0) {
-        unsigned long long N = (unsigned long long)n * (unsigned long long)(n - 1) / 2ull;
-        st->prefix = 0ull;
-        st->rank = (N - 1ull) / 2ull;
+        st->kmin = ~0ull;
+        st->kmax = 0ull;
+        st->count = 0;
+        st->mode = 0;
     }
 }
 
-__global__ __launch_bounds__(256) void k_select_hist(const double *D2, int64_t ld, int64_t n,
-                                                     SelectState *st, int shift, int width) {
+__global__ void k_select_setup(SelectState *st, int64_t n, double *stats) {
+    if (threadIdx.x != 0) return;
+    const unsigned long long N = (unsigned long long)n * (unsigned long long)(n - 1) / 2ull;
+    st->rank = (N - 1ull) / 2ull;
+    const unsigned long long x = st->kmin ^ st->kmax;
+    if (x == 0ull) {   // every pair distance is the same value
+        st->prefix = st->kmin;
+        st->bits = 64;
+        st->mode = 2;
+        stats[1] = sqrt(__longlong_as_double((long long)st->kmin));
+        return;
+    }
+    const int L = __clzll((long long)x);
+    st->bits = L;
+    st->prefix = L == 0 ? 0ull : (st->kmin & ~((1ull << (64 - L)) - 1ull));
+    st->mode = 0;
+}
+
+__device__ inline void sel_digit(const SelectState *st, int &shift, int &width,
+                                 unsigned long long &hi_mask) {
+    const int bits = st->bits;
+    width = 64 - bits < 12 ? 64 - bits : 12;
+    shift = 64 - bits - width;
+    hi_mask = bits == 0 ? 0ull : ~((1ull << (64 - bits)) - 1ull);
+}
+
+__global__ __launch_bounds__(256) void k_select_pass(const double *D2, int64_t ld, int64_t n,
+                                                     SelectState *st) {
     __shared__ unsigned int h[4096];
-    for (int b = threadIdx.x; b < 4096; b += 256) h[b] = 0;
-    __syncthreads();
+    const int mode = st->mode;
+    if (mode == 2) return;
+    int shift, width;
+    unsigned long long hi_mask;
+    sel_digit(st, shift, width, hi_mask);
     const unsigned long long prefix = st->prefix;
-    const int top = shift + width;
-    const unsigned long long hi_mask = top >= 64 ? 0ull : ~((1ull << top) - 1ull);
+    if (mode == 0) {
+        for (int b = threadIdx.x; b < 4096; b += 256) h[b] = 0;
+        __syncthreads();
+    }
     const unsigned long long dmask = (1ull << width) - 1ull;
     for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
         const unsigned long long *row = (const unsigned long long *)(D2 + i * ld);
         for (int64_t j = i + 1 + threadIdx.x; j < n; j += 256) {
-            unsigned long long key = row[j];
-            if ((key & hi_mask) == prefix) atomicAdd(&h[(key >> shift) & dmask], 1u);
+            const unsigned long long key = row[j];
+            if ((key & hi_mask) != prefix) continue;
+            if (mode == 0) {
+                atomicAdd(&h[(key >> shift) & dmask], 1u);
+            } else {
+                const unsigned int q = atomicAdd(&st->count, 1u);
+                if (q < kSelCap) st->cand[q] = key;
+            }
         }
     }
-    __syncthreads();
-    for (int b = threadIdx.x; b < 4096; b += 256)
-        if (h[b]) atomicAdd(&st->hist[b], h[b]);
+    if (mode == 0) {
+        __syncthreads();
+        for (int b = threadIdx.x; b < 4096; b += 256)
+            if (h[b]) atomicAdd(&st->hist[b], h[b]);
+    }
 }
 
-// Pick the bin holding the wanted rank; on the last pass the prefix is the
-// full key: write sigma = sqrt(D2 value) into stats[1].
-__global__ __launch_bounds__(256) void k_select_pick(SelectState *st, int shift, int last,
-                                                     double *stats) {
+__global__ __launch_bounds__(256) void k_select_pick(SelectState *st, double *stats) {
     __shared__ unsigned long long part[256];
+    __shared__ unsigned long long keys[kSelCap];
     const int t = threadIdx.x;
-    unsigned long long c[16], s = 0;
+    const int mode = st->mode;
+    if (mode == 2) return;
+    if (mode == 1) {
+        // sort the collected candidates (count <= kSelCap) and take the rank
+        const unsigned int cnt = st->count;
+        for (int q = t; q < kSelCap; q += 256) keys[q] = q < (int)cnt ? st->cand[q] : ~0ull;
+        __syncthreads();
+        for (int size = 2; size <= kSelCap; size <<= 1)
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int q = t; q < kSelCap / 2; q += 256) {
+                    const int lo = 2 * q - (q & (stride - 1)), hi = lo + stride;
+                    const bool up = (lo & size) == 0;
+                    const unsigned long long a = keys[lo], b = keys[hi];
+                    if ((a > b) == up) { keys[lo] = b; keys[hi] = a; }
+                }
+                __syncthreads();
+            }
+        if (t == 0) {
+            const unsigned long long key = keys[st->rank];
+            st->prefix = key;
+            st->bits = 64;
+            st->mode = 2;
+            stats[1] = sqrt(__longlong_as_double((long long)key));
+        }
+        return;
+    }
+    int shift, width;
+    unsigned long long hi_mask;
+    sel_digit(st, shift, width, hi_mask);
+    unsigned long long c[16], sum = 0;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         c[q] = st->hist[t * 16 + q];
-        s += c[q];
+        sum += c[q];
     }
-    part[t] = s;
+    part[t] = sum;
     __syncthreads();
     if (t == 0) {
         unsigned long long acc = 0;
         for (int q = 0; q < 256; ++q) {
-            unsigned long long v = part[q];
-            part[q] = acc;   // exclusive prefix
+            const unsigned long long v = part[q];
+            part[q] = acc;
             acc += v;
         }
     }
     __syncthreads();
     const unsigned long long rank = st->rank;
     unsigned long long before = part[t];
-    bool mine = false;
-    int bin = 0;
-    unsigned long long newrank = 0;
+    int bin = -1;
+    unsigned long long newrank = 0, cnt = 0;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-        if (!mine && rank >= before && rank < before + c[q]) {
-            mine = true;
+        if (bin < 0 && rank >= before && rank < before + c[q]) {
             bin = t * 16 + q;
             newrank = rank - before;
+            cnt = c[q];
         }
         before += c[q];
     }
     __syncthreads();
-    if (mine) {
-        unsigned long long p = st->prefix | ((unsigned long long)bin << shift);
+    if (bin >= 0) {
+        const unsigned long long p = st->prefix | ((unsigned long long)bin << shift);
         st->prefix = p;
+        st->bits += width;
         st->rank = newrank;
-        if (last) stats[1] = sqrt(__longlong_as_double((long long)p));
+        if (st->bits >= 64) {
+            st->mode = 2;
+            stats[1] = sqrt(__longlong_as_double((long long)p));
+        } else if (cnt <= (unsigned long long)kSelCap) {
+            st->mode = 1;
+            st->count = 0;
+        }
     }
     __syncthreads();
     for (int b = t; b < 4096; b += 256) st->hist[b] = 0;
 }
 
+hipError_t launch_select_reset(SelectState *st, hipStream_t s) {
+    hipLaunchKernelGGL(k_select_reset, dim3(1), dim3(256), 0, s, st);
+    return hipGetLastError();
+}
+
 hipError_t launch_select_median(const double *D2, int64_t ld, int64_t n, SelectState *st,
                                 double *stats, hipStream_t s) {
-    hipLaunchKernelGGL(k_select_init, dim3(1), dim3(256), 0, s, st, n);
-    // 63 value bits (the sign bit is 0): five 12-bit digits, then 3 bits.
-    const int shifts[6] = {51, 39, 27, 15, 3, 0};
-    const int widths[6] = {12, 12, 12, 12, 12, 3};
-    int grid = (int)(n < 2048 ? n : 2048);
-    for (int p = 0; p < 6; ++p) {
-        hipLaunchKernelGGL(k_select_hist, dim3(grid), dim3(256), 0, s, D2, ld, n, st, shifts[p],
-                           widths[p]);
-        hipLaunchKernelGGL(k_select_pick, dim3(1), dim3(256), 0, s, st, shifts[p], p == 5 ? 1 : 0,
-                           stats);
+    hipLaunchKernelGGL(k_select_setup, dim3(1), dim3(64), 0, s, st, n, stats);
+    const int grid = (int)(n < 2048 ? n : 2048);
+    // at most 6 digit passes resolve 64 bits; the collect pass is one more
+    for (int p = 0; p < 7; ++p) {
+        hipLaunchKernelGGL(k_select_pass, dim3(grid), dim3(256), 0, s, D2, ld, n, st);
+        hipLaunchKernelGGL(k_select_pick, dim3(1), dim3(256), 0, s, st, stats);
     }
     return hipGetLastError();
 }

@@ -13,18 +13,27 @@ int64_t pad_k(int64_t k);           // padded number of projection columns
 int64_t pad_t(int64_t T);           // padded series length (multiple of 16)
 
 // ---- graph ------------------------------------------------------------------
-struct SelectState {                // device scratch of the radix selection
+constexpr int kSelCap = 4096;       // candidates sorted in the last selection step
+struct SelectState {                // device scratch of the exact median selection
     unsigned long long prefix;      // selected high bits so far
     unsigned long long rank;        // rank still to skip inside the prefix
+    unsigned long long kmin, kmax;  // smallest / largest key (from the Gram epilogue)
+    int bits;                       // number of resolved high bits
+    int mode;                       // 0 histogram, 1 collect, 2 done
+    unsigned int count;             // collected candidates
     unsigned int hist[4096];
+    unsigned long long cand[kSelCap];
 };
 
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_pad_series(const double *X, int64_t n, int64_t T, int64_t ldx,
                              double *Xp, int64_t rows, int64_t Tp, double *sqn,
                              int *flags, hipStream_t s);
+// st != nullptr: also record min/max upper-triangle keys for the selection
+// (st must have been reset with launch_select_reset).
 hipError_t launch_gram_dist(const double *Xp, int64_t Tp, const double *sqn, int64_t n,
-                            int64_t ld, double *D2, hipStream_t s);
+                            int64_t ld, double *D2, SelectState *st, hipStream_t s);
+hipError_t launch_select_reset(SelectState *st, hipStream_t s);
 hipError_t launch_select_median(const double *D2, int64_t ld, int64_t n,
                                 SelectState *st, double *stats, hipStream_t s);
 hipError_t launch_set_sigma(double sigma, double *stats, hipStream_t s);
@@ -39,28 +48,42 @@ hipError_t launch_import_weights(const double *Win, int64_t ldw, int64_t n, doub
 hipError_t launch_chain_prep(const double *deg, const double *stats, int64_t n, int64_t ld,
                              int lazy, double *dmn, double *dm, double *u, hipStream_t s);
 float level_scale(int prec, int64_t n);   // storage scale of FP16 levels (1 otherwise)
+// fro_part: per-row squared Frobenius sums of the stored (rounded) level;
+// fro64_part: the same for the unrounded FP64 values.
 hipError_t launch_normalize(int prec, const double *W, int64_t ld, int64_t n,
                             const double *dmn, const double *u, int lazy, void *S0,
-                            double *fro_part, hipStream_t s);
+                            double *fro_part, double *fro64_part, hipStream_t s);
 int square_tiles(int prec, int64_t ld);   // number of partial norms written
 hipError_t launch_square(int prec, const void *S, void *S2, int64_t ld, int64_t n,
                          double *fro_part, hipStream_t s);
-// inv_vs != nullptr marks the last level: X += dm * V * (*inv_vs).
+// accumulate: V64 += S~ Vin (else V64 = S~ Vin); Vout = V64 rounded.
+// inv_vs != nullptr marks the last level: X += dm * V * (*inv_vs).  P is the
+// split-K partial buffer (apply_splits() x kpad x ld floats; unused for FP64).
 hipError_t launch_apply(int prec, const void *Vin, const void *S, void *Vout, double *V64,
                         int64_t ld, int64_t n, int64_t kpad, double *Xt, const double *dm,
-                        const double *inv_vs, hipStream_t s);
+                        const double *inv_vs, float *P, int accumulate, hipStream_t s);
+// V64 += T64, Vout = V64 rounded, last level: X += dm * V64 * (*inv_vs).
+hipError_t launch_axpy_v(int prec, const double *T64, int64_t ld, int64_t kpad, double *V64,
+                         void *Vout, double *Xt, const double *dm, const double *inv_vs,
+                         hipStream_t s);
+int apply_splits(int prec, int64_t ld, int64_t kpad, int64_t n);
 
 // ---- solve ------------------------------------------------------------------
 hipError_t launch_rhs(const double *W, int64_t ld, int64_t n, const int32_t *gid, int64_t k,
                       int64_t kpad, uint64_t seed, double *Yt, hipStream_t s);
-hipError_t launch_residual_k(const double *Xt, const double *W, const double *Yt,
+// R = Y - deg * X + W X (skip_gemm: R = Y - deg * X).  P: residual_splits()
+// x kpad x ld doubles of split-K partials.  For prec 0..2 the reduction also
+// writes V = dm * R (V64) and its rounded copy (Vlo); prec 3 leaves V alone.
+hipError_t launch_residual_k(int prec, const double *Xt, const double *W, const double *Yt,
                              const double *deg, const double *dm, int64_t ld, int64_t n,
-                             int64_t kpad, int64_t k, int skip_gemm, double *Rt, double *npart,
-                             double *mpart, hipStream_t s);
+                             int64_t kpad, int64_t k, int skip_gemm, double *P, double *Rt,
+                             double *V64, void *Vlo, double *npart, double *mpart,
+                             hipStream_t s);
+int residual_splits(int64_t ld, int64_t kpad, int64_t n);
 int residual_parts(int64_t ld);               // column-norm partials per column
-int residual_tiles(int64_t ld, int64_t kpad); // tile maxima written
+int residual_tiles(int64_t ld, int64_t kpad); // maxima written
 hipError_t launch_col_norms2(const double *npart, int nparts, int64_t kpad, const double *mpart,
-                             int ntiles, double *out, hipStream_t s);
+                             int ntiles, int scaled, double *out, hipStream_t s);
 hipError_t launch_prep_v2(int prec, const double *Rt, const double *dm, int64_t ld, int64_t kpad,
                           const double *scal, double *V64, void *Vlo, hipStream_t s);
 hipError_t launch_finalize_z2(const double *Xt, int64_t ld, int64_t n, int64_t kpad, int64_t k,

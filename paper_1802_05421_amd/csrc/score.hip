@@ -58,9 +58,10 @@ hipError_t launch_build_zhat(const double *Z0, const double *Z1, const int32_t *
     return hipGetLastError();
 }
 
-using ScoreCore = GemmCore<MfmaF64, 128, 128, 16, 2, 2>;
+using ScoreCore = GemmCore<MfmaF64, 128, 128, 16, 2, 4>;
+constexpr int kScoreWM = 2, kScoreWN = 4;
 
-__global__ __launch_bounds__(256) void k_score(const double *Zh, const double *Zhe,
+__global__ __launch_bounds__(512) void k_score(const double *Zh, const double *Zhe,
                                                int64_t ldz, const double *sq, int64_t m,
                                                int64_t mpad, const double *W0, int64_t ld0,
                                                const double *W1, int64_t ld1,
@@ -68,7 +69,7 @@ __global__ __launch_bounds__(256) void k_score(const double *Zh, const double *Z
                                                int weighted, int nt, double *part) {
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
     double *smem = (double *)smem_raw;
-    __shared__ double srow[2][128], scol[2][128];
+    __shared__ double srow[kScoreWN][128], scol[kScoreWM][128];
     const int total = nt * (nt + 1) / 2;
     int I, J;
     sym_tile<8>(xcd_remap(blockIdx.x, total), nt, I, J);
@@ -77,7 +78,7 @@ __global__ __launch_bounds__(256) void k_score(const double *Zh, const double *Z
     g.run(Zh, ldz, Zhe, ldz, m0, n0, ldz, smem);
 
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int wm = wid % 2, wn = wid / 2;
+    const int wm = wid % kScoreWM, wn = wid / kScoreWM;
     double cs[ScoreCore::WTN];
 #pragma unroll
     for (int b = 0; b < ScoreCore::WTN; ++b) cs[b] = 0.0;
@@ -115,9 +116,14 @@ __global__ __launch_bounds__(256) void k_score(const double *Zh, const double *Z
         if (lane < 16) scol[wm][ScoreCore::col_of(b)] = v;
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < 128; t += 256) {
-        part[(int64_t)J * mpad + m0 + t] = srow[0][t] + srow[1][t];
-        if (I != J) part[(int64_t)I * mpad + n0 + t] = scol[0][t] + scol[1][t];
+    for (int t = threadIdx.x; t < 128; t += ScoreCore::NT) {
+        double rs = 0.0, cs2 = 0.0;
+#pragma unroll
+        for (int q = 0; q < kScoreWN; ++q) rs += srow[q][t];
+#pragma unroll
+        for (int q = 0; q < kScoreWM; ++q) cs2 += scol[q][t];
+        part[(int64_t)J * mpad + m0 + t] = rs;
+        if (I != J) part[(int64_t)I * mpad + n0 + t] = cs2;
     }
 }
 
@@ -137,7 +143,7 @@ hipError_t launch_score(const double *Zh, const double *Zhe, int64_t kpad, const
     }
     const int nt = (int)(mpad / 128);
     const int total = nt * (nt + 1) / 2;
-    hipLaunchKernelGGL(k_score, dim3(total), dim3(256), ScoreCore::SMEM, s, Zh, Zhe, 2 * kpad,
+    hipLaunchKernelGGL(k_score, dim3(total), dim3(ScoreCore::NT), ScoreCore::SMEM, s, Zh, Zhe, 2 * kpad,
                        sq, m, mpad, W0, ld0, W1, ld1, map0, map1, weighted, nt, part);
     return hipGetLastError();
 }

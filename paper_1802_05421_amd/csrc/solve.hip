@@ -40,8 +40,9 @@ __global__ __launch_bounds__(256) void k_rhs(const double *W, int64_t ld, int64_
                                              const int32_t *gid, int64_t k, uint64_t mseed,
                                              double inv_sqrt_k, double *Yt) {
     const int lane = threadIdx.x & 63;
-    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const uint64_t beta = blockIdx.y;
+    // projection block fastest, so the blocks sharing a row of W run together
+    const int64_t i = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 6);
+    const uint64_t beta = blockIdx.x;
     if (i >= n) return;
     const uint64_t gi = gid ? (uint64_t)(uint32_t)gid[i] : (uint64_t)i;
     double acc[64];
@@ -53,9 +54,13 @@ __global__ __launch_bounds__(256) void k_rhs(const double *W, int64_t ld, int64_
         const uint64_t lo = gi < gj ? gi : gj, hi = gi < gj ? gj : gi;
         uint64_t h = splitmix64_mix(mseed ^ ((beta << 40) | (lo << 20) | hi));
         if (gi > gj) h = ~h;
+        // correctly rounded sqrt(W) (the bare hardware instruction is only an
+        // approximation in FP64), times k^{-1/2}
         const double w = sqrt(row[j]) * inv_sqrt_k;
         const uint32_t hl = (uint32_t)h, hh = (uint32_t)(h >> 32);
         const int whi = __double2hiint(w), wlo = __double2loint(w);
+        // bit r of the sign word moved to the IEEE sign bit of w (w >= 0):
+        // a shift and a masked OR per column, then the FP64 add
 #pragma unroll
         for (int r = 0; r < 32; ++r)
             acc[r] += __hiloint2double(whi | (int)((hl << (31 - r)) & 0x80000000u), wlo);
@@ -82,128 +87,192 @@ __global__ __launch_bounds__(256) void k_rhs(const double *W, int64_t ld, int64_
 hipError_t launch_rhs(const double *W, int64_t ld, int64_t n, const int32_t *gid, int64_t k,
                       int64_t kpad, uint64_t seed, double *Yt, hipStream_t s) {
     const uint64_t mseed = splitmix64_mix_host(seed);
-    dim3 grid((unsigned)cdiv(n, 4), (unsigned)(kpad / 64));
+    dim3 grid((unsigned)(kpad / 64), (unsigned)cdiv(n, 4));
     hipLaunchKernelGGL(k_rhs, grid, dim3(256), 0, s, W, ld, n, gid, k, mseed,
                        1.0 / sqrt((double)k), Yt);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// FP64 residual R = Y - deg * X + W X:  C[r][i] = sum_j Xt[r][j] W[i][j].
+// FP64 residual R = Y - deg * X + W X, as a split-K MFMA GEMM
+// P[s][r][i] = sum_{j in split s} Xt[r][j] W[i][j] followed by a reduction
+// that forms R, the next preconditioner operand and the column-norm partials.
+
+template <int BM> struct ResCfg {
+    static constexpr int WM = BM / 64, WN = 8 / (BM / 64);
+    using Core = GemmCore<MfmaF64, BM, 128, 16, WM, WN>;
+};
 
 template <int BM>
-__global__ __launch_bounds__(BM) void k_residual(const double *Xt, const double *W,
-                                                 const double *Yt, const double *deg,
-                                                 const double *dm, int64_t ld, int64_t n,
-                                                 int64_t k, int64_t kpad, int64_t kend, int mt,
-                                                 int nt, double *Rt, double *npart,
-                                                 double *mpart) {
-    using Core = GemmCore<MfmaF64, BM, 64, 16, BM / 64, 1>;
+__global__ __launch_bounds__(512) void k_residual_gemm(const double *Xt, const double *W,
+                                                       int64_t ld, int64_t kend, int64_t ks,
+                                                       int mt, int nt, int S, double *P,
+                                                       int64_t kpad) {
+    using Core = typename ResCfg<BM>::Core;
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
     double *smem = (double *)smem_raw;
-    __shared__ double wmax[BM / 64];
-    const int id = xcd_remap(blockIdx.x, mt * nt);
+    const int total = mt * nt * S;
+    const int id = xcd_remap(blockIdx.x, total);
+    // split-major order: the WGs of one split stream the same K range
+    const int split = id / (mt * nt);
     int I, J;
-    rect_tile<4>(id, mt, nt, I, J);
-    const int64_t m0 = (int64_t)I * BM, n0 = (int64_t)J * 64;
+    rect_tile<4>(id % (mt * nt), mt, nt, I, J);
+    const int64_t m0 = (int64_t)I * BM, n0 = (int64_t)J * 128;
+    const int64_t k0 = (int64_t)split * ks;
+    const int64_t kk = k0 < kend ? (kend - k0 < ks ? kend - k0 : ks) : 0;
     Core g;
-    g.run(Xt, ld, W, ld, m0, n0, kend, smem);
-    const int lane = threadIdx.x & 63;
-    double vmax = 0.0;
+    g.run(Xt + k0, ld, W + k0, ld, m0, n0, kk, smem);
+    double *Ps = P + (int64_t)split * kpad * ld;
 #pragma unroll
     for (int a = 0; a < Core::WTM; ++a)
 #pragma unroll
-        for (int rr = 0; rr < MfmaF64::R; ++rr) {
-            const int64_t row = m0 + Core::row_of(a, rr);
-            double ss = 0.0;
+        for (int b = 0; b < Core::WTN; ++b)
 #pragma unroll
-            for (int b = 0; b < Core::WTN; ++b) {
-                const int64_t col = n0 + Core::col_of(b);
-                const int64_t o = row * ld + col;
-                double R = 0.0;
-                if (row < k && col < n) R = Yt[o] - deg[col] * Xt[o] + g.acc[a][b][rr];
-                Rt[o] = R;
-                ss += R * R;
-                vmax = fmax(vmax, fabs(dm[col] * R));
-            }
-            // sum over the 16 lanes holding the same row
-#pragma unroll
-            for (int off = 1; off < 16; off <<= 1) ss += __shfl_xor(ss, off);
-            if ((lane & 15) == 0) npart[(int64_t)J * kpad + row] = ss;
-        }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, off));
-    if (lane == 0) wmax[threadIdx.x >> 6] = vmax;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double m = wmax[0];
-        for (int q = 1; q < BM / 64; ++q) m = fmax(m, wmax[q]);
-        mpart[id] = m;
-    }
+            for (int rr = 0; rr < MfmaF64::R; ++rr)
+                Ps[(m0 + Core::row_of(a, rr)) * ld + n0 + Core::col_of(b)] = g.acc[a][b][rr];
 }
 
-int residual_parts(int64_t ld) { return (int)(ld / 64); }
+static int res_bm(int64_t kpad) { return kpad % 256 == 0 ? 256 : (kpad % 128 == 0 ? 128 : 64); }
+
+int residual_splits(int64_t ld, int64_t kpad, int64_t n) {
+    const int64_t base = (kpad / res_bm(kpad)) * (ld / 128);
+    const int64_t kend = (n + 63) / 64 * 64;
+    int64_t S = (256 + base - 1) / base;          // aim at >= 256 workgroups
+    const int64_t smax = kend / 64 > 0 ? kend / 64 : 1;   // >= 4 k-tiles per split
+    if (S > smax) S = smax;
+    if (S < 1) S = 1;
+    return (int)S;
+}
 
 template <int BM>
-static hipError_t res_launch(const double *Xt, const double *W, const double *Yt,
-                             const double *deg, const double *dm, int64_t ld, int64_t n,
-                             int64_t kpad, int64_t k, int64_t kend, double *Rt, double *npart,
-                             double *mpart, hipStream_t s) {
-    using Core = GemmCore<MfmaF64, BM, 64, 16, BM / 64, 1>;
+static hipError_t resg_launch(const double *Xt, const double *W, int64_t ld, int64_t n,
+                              int64_t kpad, double *P, hipStream_t s) {
+    using Core = typename ResCfg<BM>::Core;
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_residual<BM>,
+        hipError_t e = hipFuncSetAttribute((const void *)k_residual_gemm<BM>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)Core::SMEM);
         if (e != hipSuccess) return e;
         attr = true;
     }
-    const int mt = (int)(kpad / BM), nt = (int)(ld / 64);
-    hipLaunchKernelGGL(k_residual<BM>, dim3(mt * nt), dim3(BM), Core::SMEM, s, Xt, W, Yt, deg,
-                       dm, ld, n, k, kpad, kend, mt, nt, Rt, npart, mpart);
+    const int mt = (int)(kpad / BM), nt = (int)(ld / 128);
+    const int S = residual_splits(ld, kpad, n);
+    const int64_t kend = (n + 63) / 64 * 64;
+    const int64_t ks = (cdiv(kend, S) + 15) / 16 * 16;
+    hipLaunchKernelGGL(k_residual_gemm<BM>, dim3(mt * nt * S), dim3(512), Core::SMEM, s, Xt, W,
+                       ld, kend, ks, mt, nt, S, P, kpad);
     return hipGetLastError();
 }
 
-// skip_gemm != 0 computes R = Y - deg * X only (used when X = 0).
-hipError_t launch_residual_k(const double *Xt, const double *W, const double *Yt,
+// R[r][i] = Y - deg X + sum_s P[s] (zero outside r < k, i < n); optional
+// V = dm R (FP64) and V rounded to the chain type; per (256-node block, r)
+// partial sums of R^2 and per-block maxima of |dm R|.
+template <typename T>
+__global__ __launch_bounds__(256) void k_residual_reduce(
+    const double *P, int S, const double *Yt, const double *Xt, const double *deg,
+    const double *dm, int64_t ld, int64_t n, int64_t k, int64_t kpad, int skip_gemm,
+    double *Rt, double *V64, T *Vlo, double *npart, double *mpart) {
+    __shared__ double red[4], redm[4];
+    const int64_t r = blockIdx.y, i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t o = r * ld + i;
+    double R = 0.0;
+    if (r < k && i < n) {
+        double acc = 0.0;
+        if (!skip_gemm)
+            for (int q = 0; q < S; ++q) acc += P[(int64_t)q * kpad * ld + o];
+        R = Yt[o] - deg[i] * Xt[o] + acc;
+    }
+    Rt[o] = R;
+    const double v = dm[i] * R;
+    if (Vlo) {
+        V64[o] = v;
+        Vlo[o] = cvtd<T>(v);
+    }
+    double ss = R * R, mx = fabs(v);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        ss += __shfl_xor(ss, off);
+        mx = fmax(mx, __shfl_xor(mx, off));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6] = ss;
+        redm[threadIdx.x >> 6] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        npart[(int64_t)blockIdx.x * kpad + r] = (red[0] + red[1]) + (red[2] + red[3]);
+        mpart[(int64_t)blockIdx.x * kpad + r] = fmax(fmax(redm[0], redm[1]), fmax(redm[2], redm[3]));
+    }
+}
+
+// prec < 0: no fused operand (FP16 chains scale it separately).
+hipError_t launch_residual_k(int prec, const double *Xt, const double *W, const double *Yt,
                              const double *deg, const double *dm, int64_t ld, int64_t n,
-                             int64_t kpad, int64_t k, int skip_gemm, double *Rt, double *npart,
-                             double *mpart, hipStream_t s) {
-    const int64_t kend = skip_gemm ? 0 : (n + 63) / 64 * 64;
-    if (kpad % 256 == 0) return res_launch<256>(Xt, W, Yt, deg, dm, ld, n, kpad, k, kend, Rt, npart, mpart, s);
-    if (kpad % 128 == 0) return res_launch<128>(Xt, W, Yt, deg, dm, ld, n, kpad, k, kend, Rt, npart, mpart, s);
-    return res_launch<64>(Xt, W, Yt, deg, dm, ld, n, kpad, k, kend, Rt, npart, mpart, s);
+                             int64_t kpad, int64_t k, int skip_gemm, double *P, double *Rt,
+                             double *V64, void *Vlo, double *npart, double *mpart,
+                             hipStream_t s) {
+    if (!skip_gemm) {
+        hipError_t e;
+        switch (res_bm(kpad)) {
+        case 256: e = resg_launch<256>(Xt, W, ld, n, kpad, P, s); break;
+        case 128: e = resg_launch<128>(Xt, W, ld, n, kpad, P, s); break;
+        default: e = resg_launch<64>(Xt, W, ld, n, kpad, P, s); break;
+        }
+        if (e != hipSuccess) return e;
+    }
+    const int S = residual_splits(ld, kpad, n);
+    dim3 grid((unsigned)(ld / 256), (unsigned)kpad), blk(256);
+    switch (prec) {
+    case 0: hipLaunchKernelGGL(k_residual_reduce<double>, grid, blk, 0, s, P, S, Yt, Xt, deg, dm, ld, n, k, kpad, skip_gemm, Rt, V64, (double *)Vlo, npart, mpart); break;
+    case 1: hipLaunchKernelGGL(k_residual_reduce<float>, grid, blk, 0, s, P, S, Yt, Xt, deg, dm, ld, n, k, kpad, skip_gemm, Rt, V64, (float *)Vlo, npart, mpart); break;
+    case 2: hipLaunchKernelGGL(k_residual_reduce<__bf16>, grid, blk, 0, s, P, S, Yt, Xt, deg, dm, ld, n, k, kpad, skip_gemm, Rt, V64, (__bf16 *)Vlo, npart, mpart); break;
+    default: hipLaunchKernelGGL(k_residual_reduce<_Float16>, grid, blk, 0, s, P, S, Yt, Xt, deg, dm, ld, n, k, kpad, skip_gemm, Rt, V64, (_Float16 *)nullptr, npart, mpart); break;
+    }
+    return hipGetLastError();
 }
 
-int residual_tiles(int64_t ld, int64_t kpad) {
-    int BM = kpad % 256 == 0 ? 256 : (kpad % 128 == 0 ? 128 : 64);
-    return (int)(kpad / BM) * (int)(ld / 64);
-}
+int residual_parts(int64_t ld) { return (int)(ld / 256); }
 
-// out[r] = ||R_r|| for r < kpad; out[kpad] = scale, out[kpad+1] = 1/scale
-// with scale a power of two bringing max |D^{-1/2} R| into [0.5, 1).
+int residual_tiles(int64_t ld, int64_t kpad) { return (int)(ld / 256 * kpad); }
+
+// out[r] = ||R_r|| (fixed-order sum of the partials), r < kpad; block kpad
+// writes out[kpad] = scale, out[kpad+1] = 1/scale: a power of two bringing
+// max |D^{-1/2} R| into [0.5, 1) when `scaled`, else 1.
 __global__ __launch_bounds__(256) void k_col_norms(const double *npart, int nparts,
                                                    int64_t kpad, const double *mpart,
-                                                   int ntiles, double *out) {
-    for (int64_t r = threadIdx.x; r < kpad; r += 256) {
+                                                   int ntiles, int scaled, double *out) {
+    __shared__ double red[4];
+    const int64_t r = blockIdx.x;
+    if (r < kpad) {
         double s = 0.0;
-        for (int p = 0; p < nparts; ++p) s += npart[(int64_t)p * kpad + r];
-        out[r] = sqrt(s);
+        for (int p = threadIdx.x; p < nparts; p += 256) s += npart[(int64_t)p * kpad + r];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) out[r] = sqrt((red[0] + red[1]) + (red[2] + red[3]));
+        return;
     }
+    double m = 0.0;
+    for (int t = threadIdx.x; t < ntiles; t += 256) m = fmax(m, mpart[t]);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
     if (threadIdx.x == 0) {
-        double m = 0.0;
-        for (int t = 0; t < ntiles; ++t) m = fmax(m, mpart[t]);
+        m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
         double sc = 1.0;
-        if (m > 0.0 && isfinite(m)) sc = ldexp(1.0, -ilogb(m) - 1);
+        if (scaled && m > 0.0 && isfinite(m)) sc = ldexp(1.0, -ilogb(m) - 1);
         out[kpad] = sc;
         out[kpad + 1] = 1.0 / sc;
     }
 }
 
 hipError_t launch_col_norms2(const double *npart, int nparts, int64_t kpad, const double *mpart,
-                             int ntiles, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_col_norms, dim3(1), dim3(256), 0, s, npart, nparts, kpad, mpart, ntiles,
-                       out);
+                             int ntiles, int scaled, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_col_norms, dim3((unsigned)kpad + 1), dim3(256), 0, s, npart, nparts, kpad,
+                       mpart, ntiles, scaled, out);
     return hipGetLastError();
 }
 

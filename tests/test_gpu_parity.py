@@ -159,6 +159,49 @@ def test_fixed_q_richardson_matches_oracle(cdl):
     assert rel(host(Z), Zo) <= 1e-12
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16", "fp16"])
+def test_virtual_levels_equal_deeper_chain(cdl, prec):
+    # Depth 3 over one stored level applies S~ (I+S~)(I+S~^2)(I+S~^4) by
+    # repeated application; one iteration must equal the oracle's 3-level
+    # chain preconditioner applied to Y (up to the level type's rounding).
+    n, k = 260, 40
+    X = series(n, 24, 31)
+    g = cdl.build_graph(dev(X))
+    ch = cdl.build_chain(g, prec=prec, depth=1, depth_max=1)
+    cdl.set_solve_depth(3)
+    try:
+        Z, info = cdl.solve_embedding(g, ch, k, 3, tol=0.0, max_iter=1)
+    finally:
+        cdl.set_solve_depth(0)
+    assert info.iterations == 1 and info.depth_used[0] == 3
+    W = host(g.W)[:n, :n]
+    deg, vol = oracle.degrees(W)
+    lev = oracle.chain_levels(oracle.normalized_deflated(W, deg, vol), 3)
+    Xo = oracle.chain_apply(lev, deg, oracle.rhs(W, k, 3))
+    Xo -= Xo.mean(axis=0)
+    tol = {"fp64": 1e-13, "fp32": 1e-6, "bf16": 2e-2, "fp16": 3e-3}[prec]
+    assert rel(host(Z), Xo) <= tol
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16", "fp32"])
+def test_certified_error_bounds_true_error(cdl, prec):
+    n, k = 700, 48
+    X = series(n, 30, 99)
+    g = cdl.build_graph(dev(X))
+    o = oracle.build_graph(X)
+    Zo = oracle.solve_embedding(o["W"], oracle.rhs(o["W"], k, 5))
+    ch = cdl.build_chain(g, prec=prec, depth=0, depth_max=4)
+    for target in (1e-6, 1e-10):
+        Z, info = cdl.solve_embedding(g, ch, k, 5, tol=-target, max_iter=30)
+        e = rel(host(Z), Zo)
+        print("  %s target %.0e: iterations %d depths %s certified %.2e true %.2e" % (
+            prec, target, info.iterations, list(info.depth_used[:info.iterations]),
+            info.certified_error, e))
+        assert info.converged and info.certified_error <= target
+        assert e <= info.certified_error
+        assert info.kappa >= 1.0
+
+
 # ----------------------------------------------------------------- scores
 
 @pytest.mark.parametrize("mode", ["unweighted", "delta_a"])
