@@ -239,8 +239,10 @@ cdl_status cdl_check_graph(cdl_ctx *ctx, const double *deg, const double *stats,
  *   chain   device buffer of chain_bytes >= chain size from cdl_workspace_bytes.
  *   info    host output.
  * Syncs (reads back the level norms).  Errors: CDL_E_ARG, CDL_E_WORKSPACE,
- * CDL_E_DIVERGED (rho_hat >= 1: e.g. a bipartite graph without lazy),
- * CDL_E_NONFINITE. */
+ * CDL_E_DIVERGED (a level with fro >= 0.999 that did not shrink - an
+ * eigenvalue of modulus one, e.g. a bipartite graph without lazy - or, in
+ * adaptive mode, rho_hat >= 1 after all of depth_max >= 3 levels),
+ * CDL_E_NONFINITE.  On CDL_E_DIVERGED info holds the levels built so far. */
 cdl_status cdl_build_chain(cdl_ctx *ctx, const double *W, const double *deg,
                            const double *stats, int64_t n, cdl_prec prec,
                            int depth, int depth_max, double chain_eps, int lazy,

@@ -539,7 +539,9 @@ cdl_status cdl_build_chain(cdl_ctx *ctx, const double *W, const double *deg, con
         if (!std::isfinite(f)) return fail(ctx, CDL_E_NONFINITE, "non-finite chain level");
         ++l;
         info->fro[l] = f;
-        if (f >= 0.999 && f >= 0.999 * fprev && l >= 1 && (depth == 0 || l + 1 == depth)) {
+        // A level whose norm stays >= 1 and no longer shrinks: an eigenvalue of
+        // modulus one (a bipartite component) survives every squaring.
+        if (f >= 0.999 && f >= 0.999 * fprev && (depth == 0 || l + 1 == depth)) {
             info->depth = l + 1;
             info->rho_hat = std::pow(f, 1.0 / std::ldexp(1.0, l));
             return fail(ctx, CDL_E_DIVERGED,
@@ -548,6 +550,12 @@ cdl_status cdl_build_chain(cdl_ctx *ctx, const double *W, const double *deg, con
     }
     info->depth = l + 1;
     info->rho_hat = rho;
+    // fro(S~^{2^l})^(1/2^l) bounds rho(S~) from above and tends to it.  When
+    // the automatic builder used every allowed level (three or more) and the
+    // bound is still >= 1, no contraction was shown.
+    if (depth == 0 && l >= 2 && !(rho < 1.0))
+        return fail(ctx, CDL_E_DIVERGED,
+                    "no contraction shown within depth_max levels (bipartite graph? try lazy)");
     return CDL_OK;
 }
 

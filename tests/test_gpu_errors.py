@@ -1,0 +1,277 @@
+"""Failure handling of the GPU path: every documented status code.
+
+Each failure is decided on the host (argument and size checks before any
+launch, read-back of graph statistics, residual norms or level norms), so
+every kernel that runs here still exits normally.  Graphs without a unique
+solution or a contracting chain (bipartite, disconnected) are the method's
+degenerate cases: the lazy chain of the Background section handles the
+bipartite ones.
+"""
+
+import ctypes as C
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+E_ARG, E_WORKSPACE, E_NONFINITE, E_GRAPH, E_DIVERGED, E_NOCONV, E_UNSUPPORTED = 1, 2, 3, 4, 5, 6, 8
+
+
+@pytest.fixture(scope="module")
+def cdl():
+    import paper_1802_05421_amd as cdl
+    return cdl
+
+
+@pytest.fixture(scope="module")
+def L(cdl):
+    from paper_1802_05421_amd import _lib
+    return _lib.load()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def p(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def series(n, T, seed):
+    return np.random.default_rng(seed).standard_normal((n, T))
+
+
+def complete_bipartite(a, b):
+    W = np.zeros((a + b, a + b))
+    W[:a, a:] = 1.0
+    W[a:, :a] = 1.0
+    return W
+
+
+def cycle(n):
+    W = np.zeros((n, n))
+    for i in range(n):
+        W[i, (i + 1) % n] = W[(i + 1) % n, i] = 1.0 + 0.01 * (i % 3)
+    return W
+
+
+def raises(cdl, code, fn, *a, **kw):
+    with pytest.raises(cdl.CdlError) as e:
+        fn(*a, **kw)
+    assert e.value.status == code, str(e.value)
+    return e.value
+
+
+# ---------------------------------------------------------------- graph
+
+def test_nonfinite_series_is_reported(cdl):
+    X = series(300, 20, 1)
+    X[17, 4] = np.nan
+    print("case: NaN in X, median bandwidth", flush=True)
+    raises(cdl, E_NONFINITE, cdl.build_graph, dev(X))
+    print("case: NaN in X, given bandwidth", flush=True)
+    raises(cdl, E_NONFINITE, cdl.build_graph, dev(X), sigma=3.0)
+
+
+def test_isolated_node_is_reported(cdl):
+    # exp(-D2 / sigma^2) underflows to 0 for a far-away node: degree 0
+    X = series(200, 10, 2)
+    X[5] += 1e6
+    e = raises(cdl, E_GRAPH, cdl.build_graph, dev(X), sigma=1.0)
+    assert "zero degree" in str(e)
+
+
+def test_weight_validation(cdl):
+    n = 70
+    A = np.random.default_rng(4).uniform(0.1, 1.0, (n, n))
+    A = np.triu(A, 1) + np.triu(A, 1).T
+    asym = A.copy(); asym[3, 9] += 1e-12
+    neg = A.copy(); neg[3, 9] = neg[9, 3] = -0.5
+    nan = A.copy(); nan[2, 8] = nan[8, 2] = np.nan
+    iso = A.copy(); iso[11, :] = 0.0; iso[:, 11] = 0.0
+    raises(cdl, E_GRAPH, cdl.graph_from_weights, dev(asym))
+    raises(cdl, E_GRAPH, cdl.graph_from_weights, dev(neg))
+    raises(cdl, E_NONFINITE, cdl.graph_from_weights, dev(nan))
+    raises(cdl, E_GRAPH, cdl.graph_from_weights, dev(iso))
+    cdl.graph_from_weights(dev(A))                       # the valid one passes
+
+
+# ---------------------------------------------------------------- chain
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_bipartite_graph_diverges_without_lazy(cdl, prec):
+    # K_{40,25}: S has eigenvalue -1, so S~^{2^l} keeps an eigenvalue 1.
+    # (In BF16/FP16 levels that eigenvalue is only known to about 1e-3, so
+    # the detection is exact in FP32/FP64 only.)
+    g = cdl.graph_from_weights(dev(complete_bipartite(40, 25)))
+    raises(cdl, E_DIVERGED, cdl.build_chain, g, prec=prec, depth=0, depth_max=6)
+    raises(cdl, E_DIVERGED, cdl.build_chain, g, prec=prec, depth=3, depth_max=6)
+    # even cycle: slowly decaying levels, never below one
+    g2 = cdl.graph_from_weights(dev(cycle(64)))
+    raises(cdl, E_DIVERGED, cdl.build_chain, g2, prec=prec, depth=0, depth_max=6)
+
+
+@pytest.mark.parametrize("W", [complete_bipartite(40, 25), cycle(64)], ids=["K40_25", "C64"])
+def test_bipartite_graph_with_lazy_chain_matches_oracle(cdl, W):
+    n, k, seed = W.shape[0], 24, 5
+    g = cdl.graph_from_weights(dev(W))
+    ch = cdl.build_chain(g, prec="fp32", depth=0, depth_max=14, lazy=True)
+    assert ch.info.lazy == 1 and ch.info.rho_hat < 1.0
+    Z, info = cdl.solve_embedding(g, ch, k, seed, tol=1e-12, max_iter=64)
+    Zo = oracle.solve_embedding(W, oracle.rhs(W, k, seed))
+    e = np.linalg.norm(host(Z) - Zo) / np.linalg.norm(Zo)
+    print("lazy n=%d depth %d iterations %d e_Z %.2e" % (n, ch.depth, info.iterations, e))
+    assert info.converged and e <= 1e-9
+
+
+def test_lazy_chain_on_gaussian_graph_matches_oracle(cdl):
+    X = series(300, 24, 9)
+    g = cdl.build_graph(dev(X))
+    k, seed = 40, 3
+    o = oracle.build_graph(X)
+    Zo = oracle.solve_embedding(o["W"], oracle.rhs(o["W"], k, seed), o["deg"])
+    for prec in ("fp64", "bf16"):
+        ch = cdl.build_chain(g, prec=prec, depth=0, depth_max=10, lazy=True)
+        Z, info = cdl.solve_embedding(g, ch, k, seed, tol=1e-12, max_iter=64)
+        e = np.linalg.norm(host(Z) - Zo) / np.linalg.norm(Zo)
+        assert e <= 1e-9
+        # the identity half of a lazy level puts ||S~'||_F above one: no
+        # certified stop from the Frobenius bound
+        assert ch.info.rho_bound >= 1.0
+        raises(cdl, E_ARG, cdl.solve_embedding, g, ch, k, seed, tol=-1e-8)
+
+
+# ---------------------------------------------------------------- solve
+
+def test_iteration_limit_reports_noconv(cdl):
+    X = series(300, 24, 7)
+    g = cdl.build_graph(dev(X))
+    ch = cdl.build_chain(g, prec="bf16", depth=1, depth_max=4)
+    raises(cdl, E_NOCONV, cdl.solve_embedding, g, ch, 16, 1, tol=1e-14, max_iter=1)
+    Z, info = cdl.solve_embedding(g, ch, 16, 1, tol=1e-14, max_iter=1, raise_noconv=False)
+    assert info.iterations == 1 and not info.converged
+    assert np.all(np.isfinite(host(Z)))
+    # tol == 0: exactly max_iter applications, reported as converged
+    Z, info = cdl.solve_embedding(g, ch, 16, 1, tol=0.0, max_iter=3)
+    assert info.iterations == 3 and info.converged
+
+
+def test_pcg_is_reported_unsupported(cdl):
+    X = series(100, 8, 8)
+    g = cdl.build_graph(dev(X))
+    ch = cdl.build_chain(g, prec="fp32", depth=2, depth_max=4)
+    raises(cdl, E_UNSUPPORTED, cdl.solve_embedding, g, ch, 8, 1, solver="pcg")
+
+
+def test_certified_tolerance_needs_a_contracting_bound(cdl):
+    # A narrow bandwidth (0.4 x the median distance) leaves many mid-sized
+    # eigenvalues: ||S~||_F > 1 although rho(S~) is about 0.33.  The certified
+    # stop is refused, the residual stop still converges.
+    X = series(300, 24, 13)
+    o = oracle.build_graph(X)
+    sigma = 0.4 * o["sigma"]
+    g = cdl.build_graph(dev(X), sigma=sigma)
+    ch = cdl.build_chain(g, prec="fp64", depth=0, depth_max=14)
+    assert ch.info.rho_bound >= 1.0 and ch.info.rho_hat < 1.0
+    raises(cdl, E_ARG, cdl.solve_embedding, g, ch, 8, 1, tol=-1e-6)
+    Z, info = cdl.solve_embedding(g, ch, 8, 1, tol=1e-12, max_iter=64)
+    W = oracle.build_graph(X, sigma=sigma)["W"]
+    Zo = oracle.solve_embedding(W, oracle.rhs(W, 8, 1))
+    assert np.linalg.norm(host(Z) - Zo) / np.linalg.norm(Zo) <= 1e-9
+
+
+# ---------------------------------------------------------------- C ABI checks
+
+def test_undersized_buffers_are_refused_before_any_launch(cdl, L):
+    n, T, k = 300, 16, 32
+    ctx = cdl.api.context().h
+    X = dev(series(n, T, 3))
+    m = cdl.ld(n)
+    W = torch.empty((m, m), dtype=torch.float64, device="cuda")
+    deg = torch.empty(n, dtype=torch.float64, device="cuda")
+    st = torch.empty(4, dtype=torch.float64, device="cuda")
+    sz = cdl.workspace_bytes(n, T, k, 4, "bf16")
+    small = torch.empty(sz["graph"] - 256, dtype=torch.uint8, device="cuda")
+    assert L.cdl_build_graph(ctx, p(X), n, T, T, 0.0, p(W), p(deg), p(st), p(small),
+                             small.numel()) == E_WORKSPACE
+    g = cdl.build_graph(X)
+    chb = torch.empty(sz["chain"] - 256, dtype=torch.uint8, device="cuda")
+    from paper_1802_05421_amd import _lib
+    info = _lib.ChainInfo()
+    assert L.cdl_build_chain(ctx, p(g.W), p(g.deg), p(g.stats), n, 2, 0, 4, 0.0, 0, p(chb),
+                             chb.numel(), C.byref(info)) == E_WORKSPACE
+    ch = cdl.build_chain(g, prec="bf16", depth_max=4)
+    Z = torch.empty((n, k), dtype=torch.float64, device="cuda")
+    sws = torch.empty(sz["solve"] - 256, dtype=torch.uint8, device="cuda")
+    si = _lib.SolveInfo()
+    assert L.cdl_solve_embedding(ctx, p(g.W), p(g.deg), p(g.stats), None, n, p(ch.buf),
+                                 C.byref(ch.info), k, 0.0, 1, 0, 1e-8, 10, p(Z), p(sws),
+                                 sws.numel(), C.byref(si)) == E_WORKSPACE
+    Z, _ = cdl.solve_embedding(g, ch, k, 1, tol=1e-8)
+    F = torch.empty(n, dtype=torch.float64, device="cuda")
+    top = torch.empty(50, dtype=torch.int32, device="cuda")
+    scw = torch.empty(sz["score"] - 256, dtype=torch.uint8, device="cuda")
+    assert L.cdl_anomaly_scores(ctx, p(Z), None, p(g.stats), n, p(Z), None, p(g.stats), n, k,
+                                None, None, n, 0, p(F), 50, p(top), p(scw),
+                                scw.numel()) == E_WORKSPACE
+    assert "too small" in L.cdl_last_error(ctx).decode()
+
+
+def test_bad_arguments_are_refused(cdl, L):
+    n, T, k = 300, 16, 32
+    ctx = cdl.api.context().h
+    X = dev(series(n, T, 3))
+    g = cdl.build_graph(X)
+    ch = cdl.build_chain(g, prec="fp32", depth_max=4)
+    Z, _ = cdl.solve_embedding(g, ch, k, 1, tol=1e-8)
+    sz = cdl.workspace_bytes(n, T, k, 4, "fp32")
+    ws = torch.empty(max(sz.values()), dtype=torch.uint8, device="cuda")
+    m = cdl.ld(n)
+    W = torch.empty((m, m), dtype=torch.float64, device="cuda")
+    # n < 2, T = 0, ldx < T, NaN bandwidth, misaligned W
+    for args in [(1, T, T, 0.0, W), (n, 0, T, 0.0, W), (n, T, T - 1, 0.0, W),
+                 (n, T, T, float("nan"), W)]:
+        nn, TT, ldx, sig, WW = args
+        assert L.cdl_build_graph(ctx, p(X), nn, TT, ldx, sig, p(WW), p(g.deg), p(g.stats),
+                                 p(ws), ws.numel()) == E_ARG
+    assert L.cdl_build_graph(ctx, p(X), n, T, T, 0.0, C.c_void_p(W.data_ptr() + 8), p(g.deg),
+                             p(g.stats), p(ws), ws.numel()) == E_ARG
+    from paper_1802_05421_amd import _lib
+    info = _lib.ChainInfo()
+    for prec, depth, dmax in [(9, 0, 4), (1, 5, 4), (1, 0, 0), (1, 0, 15), (1, -1, 4)]:
+        assert L.cdl_build_chain(ctx, p(g.W), p(g.deg), p(g.stats), n, prec, depth, dmax, 0.0,
+                                 0, p(ws), ws.numel(), C.byref(info)) == E_ARG
+    si = _lib.SolveInfo()
+    for kk, eps, it, solver in [(0, 0.0, 10, 0), (k, 0.0, 0, 0), (k, 0.0, 65, 0), (k, 0.0, 10, 5)]:
+        assert L.cdl_solve_embedding(ctx, p(g.W), p(g.deg), p(g.stats), None, n, p(ch.buf),
+                                     C.byref(ch.info), kk, eps, 1, solver, 1e-8, it, p(Z), p(ws),
+                                     ws.numel(), C.byref(si)) == E_ARG
+    F = torch.empty(n, dtype=torch.float64, device="cuda")
+    top = torch.empty(64, dtype=torch.int32, device="cuda")
+    bad_map = dev(np.array([0, 1, n], dtype=np.int32))
+    ok_map = dev(np.array([0, 1, 2], dtype=np.int32))
+    cases = [
+        (None, None, n, 0, n + 1),        # top_k > m
+        (None, None, n, 7, 10),           # bad mode
+        (None, None, n, 1, 10),           # weighted without W
+        (bad_map, ok_map, 3, 0, 2),       # map entry out of range
+        (ok_map, None, 3, 0, 2),          # one map only
+        (None, None, n - 1, 0, 2),        # identity maps need m == n
+    ]
+    for m0, m1, mm, mode, tk in cases:
+        assert L.cdl_anomaly_scores(ctx, p(Z), None, p(g.stats), n, p(Z), None, p(g.stats), n,
+                                    k, None if m0 is None else p(m0),
+                                    None if m1 is None else p(m1), mm, mode, p(F), tk, p(top),
+                                    p(ws), ws.numel()) == E_ARG
+    # the context still works after every refusal
+    F2, t2 = cdl.anomaly_scores(Z, g, Z, g, top_k=5)
+    assert np.all(np.isfinite(host(F2)))

@@ -1,0 +1,118 @@
+"""Snapshot sequences with node churn (Section "Climate Data": consecutive
+time windows; the node sets of consecutive graphs only partly overlap).
+
+Each consecutive pair is scored over its common global ids, in ascending id
+order, with right-hand-side signs keyed by global ids (so common edges share
+their random numbers).  The oracle runs the same definitions per snapshot.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cdl():
+    import paper_1802_05421_amd as cdl
+    return cdl
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def seq_oracle(seq, k, seed, weighted):
+    snaps = []
+    for X, gid in zip(seq.X, seq.gid):
+        g = oracle.build_graph(X)
+        Z = oracle.solve_embedding(g["W"], oracle.rhs(g["W"], k, seed, gid), g["deg"])
+        snaps.append((g, Z))
+    out = []
+    for t in range(len(snaps) - 1):
+        common, i0, i1 = np.intersect1d(seq.gid[t], seq.gid[t + 1], assume_unique=True,
+                                        return_indices=True)
+        (g0, Z0), (g1, Z1) = snaps[t], snaps[t + 1]
+        F = oracle.scores(Z0, g0["vol"], Z1, g1["vol"],
+                          g0["W"] if weighted else None, g1["W"] if weighted else None,
+                          map0=i0, map1=i1)
+        out.append((common, F, oracle.top_k(F, 50)))
+    return out
+
+
+def small_sequence():
+    return gen.make_sequence(G=40, T=60, n_snap=4, stride=20, n_min=450, n_max=1100,
+                             patch_size=3, onsets=(2,))
+
+
+@pytest.mark.parametrize("prec,mode", [("fp32", "unweighted"), ("bf16", "delta_a"),
+                                       ("fp16", "unweighted")])
+def test_sequence_matches_oracle(cdl, prec, mode):
+    seq = small_sequence()
+    k, seed = 48, gen.grid.PROJ_SEED
+    print("sequence sizes", [len(g) for g in seq.gid], prec, mode, flush=True)
+    p = cdl.SeqParams(k=k, seed=seed, prec=prec, tol=1e-11, max_iter=40, mode=mode, top_k=50)
+    Fs, tops, info = cdl.score_sequence([dev(X) for X in seq.X],
+                                        [torch.from_numpy(g) for g in seq.gid], p)
+    want = seq_oracle(seq, k, seed, mode == "delta_a")
+    assert info.pairs == len(seq.X) - 1 and info.max_rel_residual <= 1e-11
+    for t, (common, Fo, to) in enumerate(want):
+        F = host(Fs[t])
+        assert F.shape == Fo.shape == (len(common),)
+        ef = np.abs(F - Fo).max() / np.abs(Fo).max()
+        srt = np.sort(Fo)[::-1]
+        gap = (srt[49] - srt[50]) / np.abs(Fo).max()
+        print("  pair %d: m=%d e_F %.2e gap %.2e" % (t, len(common), ef, gap))
+        assert ef <= 1e-8
+        got = host(tops[t])
+        assert np.all(np.diff(F[got]) <= 0)
+        if gap > 2 * ef:
+            assert set(got.tolist()) == set(to.tolist())
+
+
+def test_sequence_pair_equals_single_pair_calls(cdl):
+    # The sequence driver is the per-snapshot calls plus the common-id maps.
+    seq = small_sequence()
+    k, seed = 32, 3
+    p = cdl.SeqParams(k=k, seed=seed, prec="fp32", depth=3, depth_max=3, tol=0.0, max_iter=6,
+                      top_k=20)
+    Fs, tops, _ = cdl.score_sequence([dev(X) for X in seq.X[:2]],
+                                     [torch.from_numpy(g) for g in seq.gid[:2]], p)
+    gs, Zs = [], []
+    for t in (0, 1):
+        g = cdl.build_graph(dev(seq.X[t]))
+        ch = cdl.build_chain(g, prec="fp32", depth=3, depth_max=3)
+        Z, _ = cdl.solve_embedding(g, ch, k, seed, tol=0.0, max_iter=6,
+                                   gid=dev(seq.gid[t].astype(np.int32)))
+        gs.append(g)
+        Zs.append(Z)
+    common, i0, i1 = np.intersect1d(seq.gid[0], seq.gid[1], assume_unique=True,
+                                    return_indices=True)
+    F, top = cdl.anomaly_scores(Zs[0], gs[0], Zs[1], gs[1], top_k=20,
+                                map0=dev(i0.astype(np.int32)), map1=dev(i1.astype(np.int32)))
+    np.testing.assert_array_equal(host(Fs[0]), host(F))
+    np.testing.assert_array_equal(host(tops[0]), host(top))
+
+
+def test_sequence_input_errors(cdl):
+    X = np.random.default_rng(1).standard_normal((100, 8))
+    p = cdl.SeqParams(k=8, seed=1, prec="fp32", tol=1e-8)
+    with pytest.raises(cdl.CdlError) as e:      # ids not increasing
+        cdl.score_sequence([dev(X), dev(X)],
+                           [torch.arange(100, dtype=torch.int32).flip(0),
+                            torch.arange(100, dtype=torch.int32)], p)
+    assert e.value.status == 1
+    with pytest.raises(cdl.CdlError) as e:      # fewer than two common nodes
+        cdl.score_sequence([dev(X), dev(X)],
+                           [torch.arange(100, dtype=torch.int32),
+                            torch.arange(99, 199, dtype=torch.int32)], p)
+    assert e.value.status == 4
