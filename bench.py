@@ -3,13 +3,14 @@
 
 One step = one graph pair end to end: for each of the two snapshots build the
 Gaussian-kernel graph (distances, median bandwidth, weights, degrees), build
-the inverse chain (normalise, deflate, square), solve the k right-hand sides
-to an FP64 relative residual of 1e-8; then score all node pairs and take the
-top 50.  Inputs (the two n x T windows) are resident in HBM before timing.
+the inverse chain (normalise, deflate, square while the cost model says it
+pays), solve the k right-hand sides until the certified embedding error is
+below 1e-6 (FP64 residuals); then score all node pairs and take the top 50.
+Inputs (the two n x T windows) are resident in HBM before timing.
 
-Workload: 128 x 128 grid (n = 16384), T = 240, k = 256, chain in BF16 with
-FP32 accumulation (the mixed form), refined in FP64; the same pair is also
-timed with an FP32 chain (the plain form).  Prints one JSON line.
+Workload: 128 x 128 grid (n = 16384), T = 240, k = 256, chain levels in FP16
+(BF16 selectable) with FP32 accumulation (the mixed form), refined in FP64;
+the same pair is also timed with BF16 and FP32 chains.  Prints one JSON line.
 """
 
 from __future__ import annotations
@@ -239,7 +240,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle stages on bounded samples of the same pair")
-        cpu = cpu_baseline(pair, k, seed, graphs)
+        cpu = cpu_baseline(pair, k, seed)
 
     out = {
         "metric": METRIC, "value": round(1.0 / ms_mixed, 4), "unit": "pairs/s",
@@ -268,7 +269,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(pair, k, seed, graphs, rows=1024, score_rows=64):
+def cpu_baseline(pair, k, seed, rows=1024, score_rows=64):
     """The oracle, as it stands, timed on a bounded sample of the same pair.
 
     Per snapshot: direct-difference distances, weights and right-hand sides
@@ -292,7 +293,7 @@ def cpu_baseline(pair, k, seed, graphs, rows=1024, score_rows=64):
     np.partition(pool, (N - 1) // 2)
     st["bandwidth"] = time.perf_counter() - t
     del pool
-    sigma = float(graphs[0].stats[1])
+    sigma = float(np.sqrt(np.median(D2r[D2r > 0])))   # the sample's own bandwidth
     t = time.perf_counter()
     Wr = np.exp(-D2r / (sigma * sigma))
     Wr[np.arange(rows), rr] = 0.0
@@ -304,7 +305,7 @@ def cpu_baseline(pair, k, seed, graphs, rows=1024, score_rows=64):
     st["rhs"] = (time.perf_counter() - t) * n / rows
     log("cpu: rhs sample done")
     h = n // 2
-    Wh = graphs[0].W[:h, :h].cpu().numpy()
+    Wh = oracle.gaussian_weights(oracle.sq_distances(pair.X0[:h]), sigma)   # untimed set-up
     Yh = np.random.default_rng(1).standard_normal((h, k))
     Yh -= Yh.mean(axis=0)
     t = time.perf_counter()

@@ -4,7 +4,8 @@
 //
 //   rhs         Y = B^T W^{1/2} Q^T / sqrt(k) with counter-based SplitMix64
 //               signs, one row of Y per wave (lane = neighbour j), FP64
-//               accumulation, deterministic butterfly reduction
+//               accumulation of EXEC-masked adds, deterministic butterfly
+//               reduction
 //   residual    R = Y - (deg * X - W X) on FP64 MFMA, per-column partial
 //               sums of R^2 and the tile maximum of |D^{-1/2} R|
 //   col_norms   ||R_r|| (fixed-order sums) and a power-of-two scale for the
@@ -33,9 +34,57 @@ static uint64_t splitmix64_mix_host(uint64_t z) {
     return z ^ (z >> 31);
 }
 
-// Row i of Y for projection block beta = blockIdx.y (64 columns).  The sign
-// of edge {i, j} in column r is B(e, i) * q_r(e): bit r of the sign word,
-// complemented when i is the tail (higher global id).
+// acc_q += w on the lanes whose next bit of h (most significant first) is
+// set, for eight bits; h is shifted left by eight.  Doubling h moves its top
+// bit into the carry mask of that lane; the FP64 add then runs with EXEC
+// restricted to the carry mask: two VALU instructions per column instead of
+// the three a per-lane sign insertion needs.  EXEC is saved and restored
+// inside the block, so inactive lanes (loop tails) stay inactive.
+__device__ __forceinline__ void masked_add8(uint32_t &h, double w, double &a0, double &a1,
+                                            double &a2, double &a3, double &a4, double &a5,
+                                            double &a6, double &a7) {
+    uint64_t sv, m0, m1, m2, m3, m4, m5, m6, m7;
+    asm volatile(
+        "s_mov_b64 %[sv], exec\n\t"
+        "v_add_co_u32 %[h], %[m0], %[h], %[h]\n\t"
+        "v_add_co_u32 %[h], %[m1], %[h], %[h]\n\t"
+        "v_add_co_u32 %[h], %[m2], %[h], %[h]\n\t"
+        "v_add_co_u32 %[h], %[m3], %[h], %[h]\n\t"
+        "v_add_co_u32 %[h], %[m4], %[h], %[h]\n\t"
+        "v_add_co_u32 %[h], %[m5], %[h], %[h]\n\t"
+        "v_add_co_u32 %[h], %[m6], %[h], %[h]\n\t"
+        "v_add_co_u32 %[h], %[m7], %[h], %[h]\n\t"
+        "s_and_b64 exec, %[sv], %[m0]\n\t"
+        "v_add_f64 %[a0], %[a0], %[w]\n\t"
+        "s_and_b64 exec, %[sv], %[m1]\n\t"
+        "v_add_f64 %[a1], %[a1], %[w]\n\t"
+        "s_and_b64 exec, %[sv], %[m2]\n\t"
+        "v_add_f64 %[a2], %[a2], %[w]\n\t"
+        "s_and_b64 exec, %[sv], %[m3]\n\t"
+        "v_add_f64 %[a3], %[a3], %[w]\n\t"
+        "s_and_b64 exec, %[sv], %[m4]\n\t"
+        "v_add_f64 %[a4], %[a4], %[w]\n\t"
+        "s_and_b64 exec, %[sv], %[m5]\n\t"
+        "v_add_f64 %[a5], %[a5], %[w]\n\t"
+        "s_and_b64 exec, %[sv], %[m6]\n\t"
+        "v_add_f64 %[a6], %[a6], %[w]\n\t"
+        "s_and_b64 exec, %[sv], %[m7]\n\t"
+        "v_add_f64 %[a7], %[a7], %[w]\n\t"
+        "s_mov_b64 exec, %[sv]"
+        : [h] "+v"(h), [a0] "+v"(a0), [a1] "+v"(a1), [a2] "+v"(a2), [a3] "+v"(a3),
+          [a4] "+v"(a4), [a5] "+v"(a5), [a6] "+v"(a6), [a7] "+v"(a7), [sv] "=&s"(sv),
+          [m0] "=&s"(m0), [m1] "=&s"(m1), [m2] "=&s"(m2), [m3] "=&s"(m3), [m4] "=&s"(m4),
+          [m5] "=&s"(m5), [m6] "=&s"(m6), [m7] "=&s"(m7)
+        : [w] "v"(w)
+        : "scc");
+}
+
+// Row i of Y for projection block beta = blockIdx.x (64 columns).  The sign
+// of edge {i, j} in column r is B(e, i) * q_r(e) = 1 - 2 b, b = bit r of the
+// sign word, complemented when i is the tail (higher global id).  So
+// sum_j s_j w_j = T - 2 M_r with T = sum_j w_j and M_r the sum over the j
+// whose bit is set: only non-negative terms are accumulated (FP64), and the
+// one subtraction at the end loses about log2(T / |y|) ~ 7 bits of the 53.
 __global__ __launch_bounds__(256) void k_rhs(const double *W, int64_t ld, int64_t n,
                                              const int32_t *gid, int64_t k, uint64_t mseed,
                                              double inv_sqrt_k, double *Yt) {
@@ -48,6 +97,7 @@ __global__ __launch_bounds__(256) void k_rhs(const double *W, int64_t ld, int64_
     double acc[64];
 #pragma unroll
     for (int r = 0; r < 64; ++r) acc[r] = 0.0;
+    double tsum = 0.0;
     const double *row = W + i * ld;
     for (int64_t j = lane; j < n; j += 64) {
         const uint64_t gj = gid ? (uint64_t)(uint32_t)gid[j] : (uint64_t)j;
@@ -55,19 +105,21 @@ __global__ __launch_bounds__(256) void k_rhs(const double *W, int64_t ld, int64_
         uint64_t h = splitmix64_mix(mseed ^ ((beta << 40) | (lo << 20) | hi));
         if (gi > gj) h = ~h;
         // correctly rounded sqrt(W) (the bare hardware instruction is only an
-        // approximation in FP64), times k^{-1/2}
-        const double w = sqrt(row[j]) * inv_sqrt_k;
-        const uint32_t hl = (uint32_t)h, hh = (uint32_t)(h >> 32);
-        const int whi = __double2hiint(w), wlo = __double2loint(w);
-        // bit r of the sign word moved to the IEEE sign bit of w (w >= 0):
-        // a shift and a masked OR per column, then the FP64 add
-#pragma unroll
-        for (int r = 0; r < 32; ++r)
-            acc[r] += __hiloint2double(whi | (int)((hl << (31 - r)) & 0x80000000u), wlo);
-#pragma unroll
-        for (int r = 0; r < 32; ++r)
-            acc[32 + r] += __hiloint2double(whi | (int)((hh << (31 - r)) & 0x80000000u), wlo);
+        // approximation in FP64)
+        const double w = sqrt(row[j]);
+        tsum += w;
+        uint32_t hh = (uint32_t)(h >> 32), hl = (uint32_t)h;
+        masked_add8(hh, w, acc[63], acc[62], acc[61], acc[60], acc[59], acc[58], acc[57], acc[56]);
+        masked_add8(hh, w, acc[55], acc[54], acc[53], acc[52], acc[51], acc[50], acc[49], acc[48]);
+        masked_add8(hh, w, acc[47], acc[46], acc[45], acc[44], acc[43], acc[42], acc[41], acc[40]);
+        masked_add8(hh, w, acc[39], acc[38], acc[37], acc[36], acc[35], acc[34], acc[33], acc[32]);
+        masked_add8(hl, w, acc[31], acc[30], acc[29], acc[28], acc[27], acc[26], acc[25], acc[24]);
+        masked_add8(hl, w, acc[23], acc[22], acc[21], acc[20], acc[19], acc[18], acc[17], acc[16]);
+        masked_add8(hl, w, acc[15], acc[14], acc[13], acc[12], acc[11], acc[10], acc[9], acc[8]);
+        masked_add8(hl, w, acc[7], acc[6], acc[5], acc[4], acc[3], acc[2], acc[1], acc[0]);
     }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) tsum += __shfl_xor(tsum, o);
     // Butterfly transpose-reduction: afterwards lane l holds column l summed
     // over all 64 lanes.
 #pragma unroll
@@ -81,7 +133,7 @@ __global__ __launch_bounds__(256) void k_rhs(const double *W, int64_t ld, int64_
         }
     }
     const int64_t r = (int64_t)beta * 64 + lane;
-    Yt[r * ld + i] = r < k ? acc[0] : 0.0;
+    Yt[r * ld + i] = r < k ? (tsum - 2.0 * acc[0]) * inv_sqrt_k : 0.0;
 }
 
 hipError_t launch_rhs(const double *W, int64_t ld, int64_t n, const int32_t *gid, int64_t k,
