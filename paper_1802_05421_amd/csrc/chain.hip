@@ -107,8 +107,8 @@ hipError_t launch_normalize(int prec, const double *W, int64_t ld, int64_t n,
 // Symmetric squaring.
 
 template <typename T> struct SqCfg;
-template <> struct SqCfg<__bf16> { using Core = GemmCore<MfmaBF16, 256, 256, 64, 2, 4>; static constexpr int TILE = 256; };
-template <> struct SqCfg<_Float16> { using Core = GemmCore<MfmaF16, 256, 256, 64, 2, 4>; static constexpr int TILE = 256; };
+template <> struct SqCfg<__bf16> { using Core = DmaCore<MfmaBF16, 256, 256, 2, 4>; static constexpr int TILE = 256; };
+template <> struct SqCfg<_Float16> { using Core = DmaCore<MfmaF16, 256, 256, 2, 4>; static constexpr int TILE = 256; };
 template <> struct SqCfg<float> { using Core = GemmCore<MfmaF32, 128, 128, 32, 2, 2>; static constexpr int TILE = 128; };
 template <> struct SqCfg<double> { using Core = GemmCore<MfmaF64, 128, 128, 16, 2, 2>; static constexpr int TILE = 128; };
 
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(SqCfg<T>::Core::NT) void k_square(const T *S, T *S2
     T *smem = (T *)smem_raw;
     __shared__ double red[Core::NT / 64];
     const int total = nt * (nt + 1) / 2;
-    const int id = xcd_remap(blockIdx.x, total);
+    const int id = TL == 256 ? round_remap(blockIdx.x, total) : xcd_remap(blockIdx.x, total);
     int I, J;
     sym_tile<8>(id, nt, I, J);
     const int64_t m0 = (int64_t)I * TL, n0 = (int64_t)J * TL;

@@ -116,6 +116,19 @@ __device__ inline int xcd_remap(int w, int total) {
     return x * base + (x < rem ? x : rem) + j;
 }
 
+// For one-workgroup-per-CU kernels: workgroups run in rounds of kNumCu (one
+// per CU); within a full round XCD x takes the CPX = kNumCu / kNumXcd
+// consecutive logical tiles [CPX x, CPX x + CPX).  Each round thus covers a
+// compact run of logical tiles chip-wide (operand panels shared across XCDs
+// through the memory-attached cache) and each XCD a compact sub-run (shared
+// in its L2).  The last, partial round keeps the dispatch order.
+constexpr int kNumCu = 256;
+__device__ inline int round_remap(int w, int total) {
+    constexpr int cpx = kNumCu / kNumXcd;
+    const int r = w / kNumCu, x = w % kNumXcd, j = (w / kNumXcd) % cpx;
+    return (r + 1) * kNumCu <= total ? r * kNumCu + x * cpx + j : w;
+}
+
 // Upper-triangular tile (I <= J) of an nt x nt tile grid, grouped in bands
 // of G tile rows: band g enumerates the G x G diagonal triangle column by
 // column, then the rectangular part column by column, so that a run of
