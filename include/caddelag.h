@@ -261,8 +261,12 @@ cdl_status cdl_build_chain(cdl_ctx *ctx, const double *W, const double *deg,
  *           beta = r / 64 is mix(mix(seed) ^ (beta << 40 | lo << 20 | hi)),
  *           mix = the SplitMix64 output function; bit (r mod 64) set = -1.
  *   solver  CDL_RICHARDSON: x <- x + P1 (y - L x) (EstimateSolution with
- *           P2 y = P1 L y); CDL_PCG: preconditioned conjugate gradients per
- *           column with the same P1.  Residuals and inner products in FP64.
+ *           P2 y = P1 L y); CDL_PCG: conjugate gradients preconditioned by
+ *           the same P1, one recurrence per column (flexible beta =
+ *           z_{j+1} . (r_{j+1} - r_j) / z_j . r_j), x0 = 0; the residual is
+ *           the recursively updated one.  Residuals and inner products in
+ *           FP64.  An iteration is one application of P1 followed by one
+ *           product with L.
  *   tol     > 0: stop when max_r ||y_r - L x_r|| / ||y_r|| <= tol;
  *           < 0: stop when the certified embedding error kappa * max_r rel_r
  *           <= |tol| (kappa from the degree range and rho_bound: the nonzero

@@ -147,6 +147,7 @@ ChainBuf plan_chain(Arena &a, int64_t n, int prec, int depth_max) {
 
 struct SolveWs {
     double *Yt, *Xt, *Rt, *V64, *T64, *npart, *mpart, *scal, *mean;
+    double *Pt, *Qt, *Zt, *pcg, *dots;   // conjugate-gradient state
     void *Vlo[4];
     void *part;   // split-K partials of the residual and the chain application
 };
@@ -166,6 +167,11 @@ SolveWs plan_solve(Arena &a, int64_t n, int64_t k, int prec) {
     w.mpart = a.take<double>(residual_tiles(ld, kp));
     w.scal = a.take<double>(kp + 2);
     w.mean = a.take<double>(kp);
+    w.Pt = a.take<double>(panel);
+    w.Qt = a.take<double>(panel);
+    w.Zt = a.take<double>(panel);
+    w.pcg = a.take<double>(3 * (size_t)kp);
+    w.dots = a.take<double>(2 * (size_t)residual_parts(ld) * kp);
     return w;
 }
 
@@ -581,7 +587,6 @@ cdl_status cdl_solve_embedding(cdl_ctx *ctx, const double *W, const double *deg,
         return fail(ctx, CDL_E_ARG, "invalid chain info");
     if (max_iter < 1 || max_iter > 64) return fail(ctx, CDL_E_ARG, "max_iter must be in [1, 64]");
     if (solver != CDL_RICHARDSON && solver != CDL_PCG) return fail(ctx, CDL_E_ARG, "bad solver");
-    if (solver == CDL_PCG) return fail(ctx, CDL_E_UNSUPPORTED, "PCG not available in this build");
     Arena need(nullptr);
     plan_solve(need, n, k, ci->prec);
     if (ws_bytes < need.off) return fail(ctx, CDL_E_WORKSPACE, "solve workspace too small");
@@ -629,41 +634,42 @@ cdl_status cdl_solve_embedding(cdl_ctx *ctx, const double *W, const double *deg,
     double rel = 1.0;
     int it = 0;
     bool conv = false;
-    while (it < max_iter) {
-        // X += P1 R with P1 = D^{-1/2} prod_{l<D} (I + S~^{2^l}) D^{-1/2}.  The
-        // residual step already left V = D^{-1/2} R in V64 / Vlo[0] (FP16:
-        // scaled copy made here).
-        const int d = ci->depth;
-        const int D = ctx->solve_depth > 0 ? ctx->solve_depth
-                      : (tol == 0.0 ? d : choose_depth(prec, n, k, d, rho_model, target / rel));
+    const int d = ci->depth;
+    auto depth_now = [&]() {
+        return ctx->solve_depth > 0 ? ctx->solve_depth
+                                    : (tol == 0.0 ? d : choose_depth(prec, n, k, d, rho_model, target / rel));
+    };
+    // Xdst += P1 r, P1 = D^{-1/2} prod_{l<D} (I + S~^{2^l}) D^{-1/2}, for the
+    // operand V = D^{-1/2} r left in V64 / Vlo[0] by the residual step (FP16:
+    // the scaled copy is made here).  Levels l >= d are applied as
+    // 2^(l-d+1) repetitions of the last stored level.
+    auto precondition = [&](int D, double *Xdst) -> cdl_status {
         if (scaled) { Timed t_(ctx, "prep_v"); HIPCHK(launch_prep_v2(prec, w.Rt, c.dm, ld, kp, w.scal + kp, w.V64, w.Vlo[0], s)); }
         int cur = 0;
         for (int l = 0; l < std::min(d, D); ++l) {
             const bool last = l + 1 == D;
             { Timed t_(ctx, "apply"); HIPCHK(launch_apply(prec, w.Vlo[cur], c.levels + c.level_bytes * l, w.Vlo[cur ^ 1],
-                                w.V64, ld, n, kp, w.Xt, c.dm, last ? inv_vs : nullptr, (float *)w.part, 1, s)); }
+                                w.V64, ld, n, kp, Xdst, c.dm, last ? inv_vs : nullptr, (float *)w.part, 1, s)); }
             cur ^= 1;
         }
         for (int l = d; l < D; ++l) {
-            // S~^{2^l} = (S~_{d-1})^{2^(l-d+1)}: repeated applications into T64
             const int m = 1 << (l - d + 1);
             const void *src = w.Vlo[cur];
             for (int q = 0; q < m; ++q) {
                 void *dst = w.Vlo[2 + (q & 1)];
                 { Timed t_(ctx, "apply"); HIPCHK(launch_apply(prec, src, c.levels + c.level_bytes * (d - 1), dst, w.T64,
-                                    ld, n, kp, w.Xt, c.dm, nullptr, (float *)w.part, 0, s)); }
+                                    ld, n, kp, Xdst, c.dm, nullptr, (float *)w.part, 0, s)); }
                 src = dst;
             }
             const bool last = l + 1 == D;
-            { Timed t_(ctx, "axpy_v"); HIPCHK(launch_axpy_v(prec, w.T64, ld, kp, w.V64, w.Vlo[cur ^ 1], w.Xt, c.dm,
+            { Timed t_(ctx, "axpy_v"); HIPCHK(launch_axpy_v(prec, w.T64, ld, kp, w.V64, w.Vlo[cur ^ 1], Xdst, c.dm,
                                  last ? inv_vs : nullptr, s)); }
             cur ^= 1;
         }
-        ++it;
-        if (info && it <= 64) info->depth_used[it - 1] = D;
-        { Timed t_(ctx, "residual"); HIPCHK(launch_residual_k(prec, w.Xt, W, w.Yt, deg, c.dm, ld, n, kp, k, 0, (double *)w.part, w.Rt,
-                                 w.V64, w.Vlo[0], w.npart, w.mpart, s)); }
-        { Timed t_(ctx, "col_norms"); HIPCHK(launch_col_norms2(w.npart, nparts, kp, w.mpart, ntiles, scaled, w.scal, s)); }
+        return CDL_OK;
+    };
+    // max_r ||r_r|| / ||y_r|| after the norms kernel; syncs.
+    auto residual_check = [&]() -> cdl_status {
         HIPCHK(hipMemcpyAsync(rnorm.data(), w.scal, kp * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         rel = 0.0;
@@ -672,10 +678,49 @@ cdl_status cdl_solve_embedding(cdl_ctx *ctx, const double *W, const double *deg,
             if (ynorm[r] > 0.0) rel = std::max(rel, rnorm[r] / ynorm[r]);
         }
         if (info && it <= 64) info->history[it - 1] = rel;
-        if (target > 0.0 && rel <= target) {
-            conv = true;
-            break;
+        conv = target > 0.0 && rel <= target;
+        return CDL_OK;
+    };
+    cdl_status st = CDL_OK;
+    if (solver == CDL_RICHARDSON) {
+        // x <- x + P1 (y - L x)  (EstimateSolution with P2 y = P1 L y)
+        while (it < max_iter) {
+            const int D = depth_now();
+            if ((st = precondition(D, w.Xt)) != CDL_OK) return st;
+            ++it;
+            if (info && it <= 64) info->depth_used[it - 1] = D;
+            { Timed t_(ctx, "residual"); HIPCHK(launch_residual_k(prec, w.Xt, W, w.Yt, deg, c.dm, ld, n, kp, k, 0, (double *)w.part, w.Rt,
+                                     w.V64, w.Vlo[0], w.npart, w.mpart, s)); }
+            { Timed t_(ctx, "col_norms"); HIPCHK(launch_col_norms2(w.npart, nparts, kp, w.mpart, ntiles, scaled, w.scal, s)); }
+            if ((st = residual_check()) != CDL_OK) return st;
+            if (conv) break;
         }
+    } else {
+        // Conjugate gradients preconditioned by P1, per column; x0 = 0, r0 = y.
+        double *rho = w.pcg, *alpha = w.pcg + kp, *beta = w.pcg + 2 * kp;
+        const size_t pbytes = panel * sizeof(double);
+        while (it < max_iter) {
+            const int D = depth_now();
+            const int first = it == 0;
+            { Timed t_(ctx, "fill_zero"); HIPCHK(launch_fill_zero(w.Zt, pbytes, s)); }
+            if ((st = precondition(D, w.Zt)) != CDL_OK) return st;
+            ++it;
+            if (info && it <= 64) info->depth_used[it - 1] = D;
+            { Timed t_(ctx, "pcg_vec"); HIPCHK(launch_col_dots(w.Zt, w.Rt, first ? nullptr : w.Zt, w.Qt, ld, kp, w.dots, s)); }
+            { Timed t_(ctx, "pcg_vec"); HIPCHK(launch_pcg_scalars(w.dots, ld, kp, 0, first, w.pcg, s)); }
+            { Timed t_(ctx, "pcg_vec"); HIPCHK(launch_pcg_dir(w.Zt, w.Pt, beta, ld, kp, first, s)); }
+            // q' = -L p
+            { Timed t_(ctx, "residual"); HIPCHK(launch_residual_k(-1, w.Pt, W, nullptr, deg, c.dm, ld, n, kp, k, 0, (double *)w.part, w.Qt,
+                                     w.V64, nullptr, w.npart, w.mpart, s)); }
+            { Timed t_(ctx, "pcg_vec"); HIPCHK(launch_col_dots(w.Pt, w.Qt, nullptr, nullptr, ld, kp, w.dots, s)); }
+            { Timed t_(ctx, "pcg_vec"); HIPCHK(launch_pcg_scalars(w.dots, ld, kp, 1, 0, w.pcg, s)); }
+            { Timed t_(ctx, "pcg_update"); HIPCHK(launch_pcg_update(prec, w.Pt, w.Qt, alpha, c.dm, ld, kp, w.Xt, w.Rt, w.V64,
+                                       w.Vlo[0], w.npart, w.mpart, s)); }
+            { Timed t_(ctx, "col_norms"); HIPCHK(launch_col_norms2(w.npart, nparts, kp, w.mpart, ntiles, scaled, w.scal, s)); }
+            if ((st = residual_check()) != CDL_OK) return st;
+            if (conv) break;
+        }
+        (void)rho;
     }
     { Timed t_(ctx, "finalize_z"); HIPCHK(launch_finalize_z2(w.Xt, ld, n, kp, k, w.mean, Z, s)); }
     if (info) {

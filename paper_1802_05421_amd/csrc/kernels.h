@@ -107,4 +107,16 @@ int64_t topk_scratch_elems(int64_t m, int K);
 hipError_t launch_topk(const double *F, int64_t m, int K, void *scratch, int32_t *out,
                        hipStream_t s);
 
+// Preconditioned conjugate gradients (per column, FP64).
+hipError_t launch_col_dots(const double *A0, const double *B0, const double *A1,
+                           const double *B1, int64_t ld, int64_t kpad, double *part,
+                           hipStream_t s);
+hipError_t launch_pcg_scalars(const double *part, int64_t ld, int64_t kpad, int mode, int first,
+                              double *sc, hipStream_t s);
+hipError_t launch_pcg_dir(const double *Zt, double *Pt, const double *beta, int64_t ld,
+                          int64_t kpad, int first, hipStream_t s);
+hipError_t launch_pcg_update(int prec, const double *Pt, const double *Qt, const double *alpha,
+                             const double *dm, int64_t ld, int64_t kpad, double *Xt, double *Rt,
+                             double *V64, void *Vlo, double *npart, double *mpart, hipStream_t s);
+
 } // namespace cdl

@@ -217,7 +217,8 @@ static hipError_t resg_launch(const double *Xt, const double *W, int64_t ld, int
     return hipGetLastError();
 }
 
-// R[r][i] = Y - deg X + sum_s P[s] (zero outside r < k, i < n); optional
+// R[r][i] = Y - deg X + sum_s P[s] (zero outside r < k, i < n; Y = NULL
+// reads as zero, giving -L X); optional
 // V = dm R (FP64) and V rounded to the chain type; per (256-node block, r)
 // partial sums of R^2 and per-block maxima of |dm R|.
 template <typename T>
@@ -233,7 +234,7 @@ __global__ __launch_bounds__(256) void k_residual_reduce(
         double acc = 0.0;
         if (!skip_gemm)
             for (int q = 0; q < S; ++q) acc += P[(int64_t)q * kpad * ld + o];
-        R = Yt[o] - deg[i] * Xt[o] + acc;
+        R = (Yt ? Yt[o] : 0.0) - deg[i] * Xt[o] + acc;
     }
     Rt[o] = R;
     const double v = dm[i] * R;
@@ -392,6 +393,144 @@ hipError_t launch_finalize_z2(const double *Xt, int64_t ld, int64_t n, int64_t k
     hipLaunchKernelGGL(k_col_mean, dim3((unsigned)kpad), dim3(256), 0, s, Xt, ld, n, mean);
     hipLaunchKernelGGL(k_transpose_z, dim3((unsigned)cdiv(n, 32), (unsigned)cdiv(k, 32)),
                        dim3(256), 0, s, Xt, ld, n, k, mean, Z);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Preconditioned conjugate gradients, one independent recurrence per column
+// (flexible form: beta from z_{j+1} . (r_{j+1} - r_j)), all in FP64:
+//   q' = -L p (residual kernels with Y = 0); alpha = rho / (p . L p);
+//   x += alpha p; r -= alpha L p;  z = P1 r (chain);  beta; p = z + beta p.
+
+// part[j][b][r] = sum over the 256 nodes of block b of A_j[r][.] * B_j[r][.]
+// for the pairs j < 2 (pair 1 skipped when A1 is NULL).
+__global__ __launch_bounds__(256) void k_col_dots(const double *A0, const double *B0,
+                                                  const double *A1, const double *B1,
+                                                  int64_t ld, int64_t kpad, int64_t nblk,
+                                                  double *part) {
+    __shared__ double red[2][4];
+    const int64_t r = blockIdx.y, i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t o = r * ld + i;
+    double s0 = A0[o] * B0[o], s1 = A1 ? A1[o] * B1[o] : 0.0;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        s0 += __shfl_xor(s0, off);
+        s1 += __shfl_xor(s1, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = s0;
+        red[1][threadIdx.x >> 6] = s1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part[(int64_t)blockIdx.x * kpad + r] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+        part[(nblk + blockIdx.x) * kpad + r] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+    }
+}
+
+// Per-column scalars sc = [rho | alpha | beta] (kpad each) from the block
+// partials of k_col_dots, summed in block order.
+//   mode 0 (after z = P1 r): rho' = z . r, zq = z . q' (q' = -L p), beta =
+//          alpha zq / rho (0 on the first direction or when rho = 0); rho = rho'
+//   mode 1 (after q' = -L p): alpha = -rho / (p . q') (0 when p . q' = 0)
+__global__ void k_pcg_scalars(const double *part, int64_t nblk, int64_t kpad, int mode,
+                              int first, double *sc) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= kpad) return;
+    double d0 = 0.0, d1 = 0.0;
+    for (int64_t b = 0; b < nblk; ++b) {
+        d0 += part[b * kpad + r];
+        d1 += part[(nblk + b) * kpad + r];
+    }
+    double *rho = sc, *alpha = sc + kpad, *beta = sc + 2 * kpad;
+    if (mode == 0) {
+        beta[r] = (first || rho[r] == 0.0) ? 0.0 : alpha[r] * d1 / rho[r];
+        rho[r] = d0;
+    } else {
+        alpha[r] = d0 != 0.0 ? -rho[r] / d0 : 0.0;
+    }
+}
+
+// p = z + beta p (p = z on the first direction).
+__global__ void k_pcg_dir(const double *Zt, double *Pt, const double *beta, int64_t ld,
+                          int64_t total, int first) {
+    for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < total;
+         o += (int64_t)gridDim.x * blockDim.x)
+        Pt[o] = first ? Zt[o] : Zt[o] + beta[o / ld] * Pt[o];
+}
+
+// x += alpha p, r += alpha q' (q' = -L p); V = D^{-1/2} r for the next
+// preconditioner operand (unless FP16, which scales it separately) and the
+// same per-block partials as the residual reduction.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pcg_update(const double *Pt, const double *Qt,
+                                                    const double *alpha, const double *dm,
+                                                    int64_t ld, int64_t kpad, double *Xt,
+                                                    double *Rt, double *V64, T *Vlo,
+                                                    double *npart, double *mpart) {
+    __shared__ double red[4], redm[4];
+    const int64_t r = blockIdx.y, i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t o = r * ld + i;
+    const double a = alpha[r];
+    Xt[o] += a * Pt[o];
+    const double R = Rt[o] + a * Qt[o];
+    Rt[o] = R;
+    const double v = dm[i] * R;
+    if (Vlo) {
+        V64[o] = v;
+        Vlo[o] = cvtd<T>(v);
+    }
+    double ss = R * R, mx = fabs(v);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        ss += __shfl_xor(ss, off);
+        mx = fmax(mx, __shfl_xor(mx, off));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6] = ss;
+        redm[threadIdx.x >> 6] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        npart[(int64_t)blockIdx.x * kpad + r] = (red[0] + red[1]) + (red[2] + red[3]);
+        mpart[(int64_t)blockIdx.x * kpad + r] = fmax(fmax(redm[0], redm[1]), fmax(redm[2], redm[3]));
+    }
+}
+
+hipError_t launch_col_dots(const double *A0, const double *B0, const double *A1,
+                           const double *B1, int64_t ld, int64_t kpad, double *part,
+                           hipStream_t s) {
+    const int64_t nblk = ld / 256;
+    hipLaunchKernelGGL(k_col_dots, dim3((unsigned)nblk, (unsigned)kpad), dim3(256), 0, s, A0, B0,
+                       A1, B1, ld, kpad, nblk, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_pcg_scalars(const double *part, int64_t ld, int64_t kpad, int mode, int first,
+                              double *sc, hipStream_t s) {
+    hipLaunchKernelGGL(k_pcg_scalars, dim3((unsigned)cdiv(kpad, 64)), dim3(64), 0, s, part,
+                       ld / 256, kpad, mode, first, sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_pcg_dir(const double *Zt, double *Pt, const double *beta, int64_t ld,
+                          int64_t kpad, int first, hipStream_t s) {
+    const int64_t total = kpad * ld;
+    const int grid = (int)(cdiv(total, 256) < 16384 ? cdiv(total, 256) : 16384);
+    hipLaunchKernelGGL(k_pcg_dir, dim3(grid), dim3(256), 0, s, Zt, Pt, beta, ld, total, first);
+    return hipGetLastError();
+}
+
+hipError_t launch_pcg_update(int prec, const double *Pt, const double *Qt, const double *alpha,
+                             const double *dm, int64_t ld, int64_t kpad, double *Xt, double *Rt,
+                             double *V64, void *Vlo, double *npart, double *mpart, hipStream_t s) {
+    dim3 grid((unsigned)(ld / 256), (unsigned)kpad), blk(256);
+    switch (prec) {
+    case 0: hipLaunchKernelGGL(k_pcg_update<double>, grid, blk, 0, s, Pt, Qt, alpha, dm, ld, kpad, Xt, Rt, V64, (double *)Vlo, npart, mpart); break;
+    case 1: hipLaunchKernelGGL(k_pcg_update<float>, grid, blk, 0, s, Pt, Qt, alpha, dm, ld, kpad, Xt, Rt, V64, (float *)Vlo, npart, mpart); break;
+    case 2: hipLaunchKernelGGL(k_pcg_update<__bf16>, grid, blk, 0, s, Pt, Qt, alpha, dm, ld, kpad, Xt, Rt, V64, (__bf16 *)Vlo, npart, mpart); break;
+    default: hipLaunchKernelGGL(k_pcg_update<_Float16>, grid, blk, 0, s, Pt, Qt, alpha, dm, ld, kpad, Xt, Rt, V64, (_Float16 *)nullptr, npart, mpart); break;
+    }
     return hipGetLastError();
 }
 

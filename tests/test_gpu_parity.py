@@ -143,6 +143,50 @@ def test_embedding_matches_oracle(cdl, prec, n, k, perm):
     np.testing.assert_allclose(Zg.sum(axis=0), 0, atol=1e-12 * np.abs(Zg).max() * n)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16", "fp16"])
+@pytest.mark.parametrize("n,k,perm", [(300, 70, False), (257, 64, True)])
+def test_pcg_matches_oracle(cdl, prec, n, k, perm):
+    X = series(n, 24, 7 * n + k)
+    rng = np.random.default_rng(n)
+    gid = (rng.permutation(9000)[:n] if perm else np.sort(rng.choice(9000, n, replace=False))).astype(np.int32)
+    print("pcg case prec=%s n=%d k=%d perm=%s" % (prec, n, k, perm), flush=True)
+    g = cdl.build_graph(dev(X))
+    ch = cdl.build_chain(g, prec=prec, depth=0, depth_max=8)
+    Z, info = cdl.solve_embedding(g, ch, k, 1234, tol=1e-11, max_iter=40, gid=dev(gid), solver="pcg")
+    o = oracle.build_graph(X)
+    Zo = oracle.solve_embedding(o["W"], oracle.rhs(o["W"], k, 1234, gid))
+    Zg = host(Z)
+    e = rel(Zg, Zo)
+    print("  iterations %d residual %.2e e_Z %.2e depth %d" % (info.iterations, info.rel_residual, e, ch.depth))
+    assert info.converged and info.rel_residual <= 1e-11
+    assert e <= 1e-9
+    np.testing.assert_allclose(Zg.sum(axis=0), 0, atol=1e-12 * np.abs(Zg).max() * n)
+
+
+def test_pcg_needs_fewer_iterations_than_richardson(cdl):
+    # Bandwidth 0.3 x median leaves rho(S~) near 0.5; with a one-level chain
+    # Richardson contracts by about rho^2 per step, CG by about
+    # (sqrt(kappa) - 1) / (sqrt(kappa) + 1) with kappa = 1 / (1 - rho^2).
+    n, k = 400, 24
+    X = series(n, 24, 17)
+    o = oracle.build_graph(X)
+    sigma = 0.3 * o["sigma"]
+    W = oracle.build_graph(X, sigma=sigma)["W"]
+    Zo = oracle.solve_embedding(W, oracle.rhs(W, k, 9))
+    g = cdl.build_graph(dev(X), sigma=sigma)
+    ch = cdl.build_chain(g, prec="fp32", depth=1, depth_max=1)
+    cdl.set_solve_depth(1)
+    try:
+        Zr, ir = cdl.solve_embedding(g, ch, k, 9, tol=1e-10, max_iter=64)
+        Zp, ip = cdl.solve_embedding(g, ch, k, 9, tol=1e-10, max_iter=64, solver="pcg")
+    finally:
+        cdl.set_solve_depth(0)
+    print("  rho_hat %.3f richardson %d iterations, pcg %d" % (ch.info.rho_hat, ir.iterations, ip.iterations))
+    assert ir.converged and ip.converged
+    assert ip.iterations < ir.iterations
+    assert rel(host(Zr), Zo) <= 1e-8 and rel(host(Zp), Zo) <= 1e-8
+
+
 def test_fixed_q_richardson_matches_oracle(cdl):
     # EstimateSolution with q = 10 (q - 1 updates) and an 8-level FP64 chain.
     p = gen.make_pair(G=16, T=120, patches=1, patch_size=3)
