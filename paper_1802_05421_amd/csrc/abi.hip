@@ -115,7 +115,7 @@ struct Arena {
 struct GraphWs {
     int *flags;
     SelectState *sel;
-    double *sqn, *Xp;
+    double *sqn, *Xp, *dpart;
 };
 GraphWs plan_graph(Arena &a, int64_t n, int64_t T) {
     const int64_t ld = pad_n(n), Tp = pad_t(T);
@@ -124,6 +124,7 @@ GraphWs plan_graph(Arena &a, int64_t n, int64_t T) {
     w.sel = a.take<SelectState>(1);
     w.sqn = a.take<double>(ld);
     w.Xp = a.take<double>((size_t)ld * Tp);
+    w.dpart = a.take<double>((size_t)(ld / 64) * ld);
     return w;
 }
 
@@ -138,8 +139,8 @@ ChainBuf plan_chain(Arena &a, int64_t n, int prec, int depth_max) {
     c.dmn = a.take<double>(ld);
     c.dm = a.take<double>(ld);
     c.u = a.take<double>(ld);
-    c.fro = a.take<double>(std::max<int64_t>(ld, square_tiles(prec, ld)));
-    c.fro64 = a.take<double>(ld);
+    c.fro = a.take<double>(std::max<int64_t>(sym_tiles64(ld), square_tiles(prec, ld)));
+    c.fro64 = a.take<double>(sym_tiles64(ld));
     c.level_bytes = (size_t)ld * ld * esize(prec);
     c.levels = a.take<char>(c.level_bytes * depth_max);
     return c;
@@ -437,7 +438,7 @@ cdl_status cdl_build_graph(cdl_ctx *ctx, const double *X, int64_t n, int64_t T, 
         { Timed t_(ctx, "set_sigma"); HIPCHK(launch_set_sigma(sigma, stats, s)); }
     else
         { Timed t_(ctx, "select_median"); HIPCHK(launch_select_median(W, ld, n, w.sel, stats, s)); }
-    { Timed t_(ctx, "exp_degree"); HIPCHK(launch_exp_degree(W, ld, n, stats, deg, s)); }
+    { Timed t_(ctx, "exp_degree"); HIPCHK(launch_exp_degree(W, ld, n, stats, deg, w.dpart, s)); }
     { Timed t_(ctx, "graph_stats"); HIPCHK(launch_graph_stats(deg, n, stats, s)); }
     return CDL_OK;
 }
@@ -514,9 +515,10 @@ cdl_status cdl_build_chain(cdl_ctx *ctx, const double *W, const double *deg, con
 
     { Timed t_(ctx, "chain_prep"); HIPCHK(launch_chain_prep(deg, stats, n, ld, info->lazy, c.dmn, c.dm, c.u, s)); }
     { Timed t_(ctx, "normalize"); HIPCHK(launch_normalize(prec, W, ld, n, c.dmn, c.u, info->lazy, c.levels, c.fro, c.fro64, s)); }
-    std::vector<double> part(ld), part64(ld);
-    HIPCHK(hipMemcpyAsync(part.data(), c.fro, ld * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(part64.data(), c.fro64, ld * sizeof(double), hipMemcpyDeviceToHost, s));
+    const int nst = sym_tiles64(ld);
+    std::vector<double> part(nst), part64(nst);
+    HIPCHK(hipMemcpyAsync(part.data(), c.fro, nst * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(part64.data(), c.fro64, nst * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     info->rho_bound = std::sqrt(host_sum(part64));
     double f = std::sqrt(host_sum(part));

@@ -3,7 +3,8 @@
 //   chain_prep  dmn = D^{-1/2}, dm = (cD)^{-1/2} (c = 2 for the lazy walk),
 //               u = D^{1/2} 1 / sqrt(vol)
 //   normalize   S~_0 = D^{-1/2} W D^{-1/2} - u u^T  (lazy: (I + S)/2 - u u^T),
-//               computed in FP64, rounded to the storage type; removing the
+//               computed in FP64 from the upper 64 x 64 tiles of W, rounded
+//               to the storage type and written with the mirror; removing the
 //               eigenvalue-1 mode u makes every power decay (the chain only
 //               ever multiplies vectors orthogonal to u, where S~ = S)
 //   square      S~_{l+1} = S~_l S~_l^T (= S~_l^2, S~ symmetric): upper
@@ -60,44 +61,81 @@ hipError_t launch_chain_prep(const double *deg, const double *stats, int64_t n, 
     return hipGetLastError();
 }
 
+// One upper 64 x 64 tile per workgroup, runs of 8 consecutive elements per
+// thread; the mirror is written from the LDS copy of the rounded tile.
 template <typename T>
 __global__ __launch_bounds__(256) void k_normalize(const double *W, int64_t ld, int64_t n,
                                                    const double *dmn, const double *u, int lazy,
-                                                   double scale, T *S0, double *fro_part,
-                                                   double *fro64_part) {
+                                                   double scale, int nt, T *S0,
+                                                   double *fro_part, double *fro64_part) {
+    __shared__ T t[64][64 + 16 / sizeof(T)];
     __shared__ double red[4];
-    const int64_t i = blockIdx.x;
+    union Run { T e[8]; uint4 q[sizeof(T) * 8 / 16]; };
+    const int total = nt * (nt + 1) / 2;
+    const int id = xcd_remap(blockIdx.x, total);
+    int I, J;
+    sym_tile<8>(id, nt, I, J);
+    const int64_t i0 = (int64_t)I * 64, j0 = (int64_t)J * 64;
+    const int tid = threadIdx.x;
     double s = 0.0, s64 = 0.0;
-    const double di = i < n ? dmn[i] : 0.0, ui = i < n ? u[i] : 0.0;
-    for (int64_t j = threadIdx.x; j < ld; j += 256) {
-        double v = 0.0;
-        if (i < n && j < n) {
-            v = W[i * ld + j] * (di * dmn[j]);   // symmetric rounding: (i,j) == (j,i)
-            if (lazy) v = 0.5 * ((i == j ? 1.0 : 0.0) + v);
-            v -= ui * u[j];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int r = (tid >> 3) + 32 * h, c0 = (tid & 7) * 8;
+        const int64_t i = i0 + r;
+        const double *wr = W + i * ld + j0 + c0;
+        const double di = i < n ? dmn[i] : 0.0, ui = i < n ? u[i] : 0.0;
+        Run out;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int64_t j = j0 + c0 + e;
+            double v = 0.0;
+            if (i < n && j < n) {
+                v = wr[e] * (di * dmn[j]);
+                if (lazy) v = 0.5 * ((i == j ? 1.0 : 0.0) + v);
+                v -= ui * u[j];
+            }
+            const T tv = cvtd<T>(v * scale);
+            out.e[e] = tv;
+            t[r][c0 + e] = tv;
+            const double back = tod<T>(tv) / scale;
+            s += back * back;
+            s64 += v * v;
         }
-        T t = cvtd<T>(v * scale);
-        S0[i * ld + j] = t;
-        double tv = tod<T>(t) / scale;
-        s += tv * tv;
-        s64 += v * v;
+        uint4 *dst = (uint4 *)(S0 + i * ld + j0 + c0);
+#pragma unroll
+        for (int q = 0; q < (int)(sizeof(T) * 8 / 16); ++q) dst[q] = out.q[q];
     }
+    if (I != J) {
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int rr = (tid >> 3) + 32 * h, c0 = (tid & 7) * 8;
+            Run out;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) out.e[e] = t[c0 + e][rr];
+            uint4 *dst = (uint4 *)(S0 + (j0 + rr) * ld + i0 + c0);
+#pragma unroll
+            for (int q = 0; q < (int)(sizeof(T) * 8 / 16); ++q) dst[q] = out.q[q];
+        }
+    }
+    const double w = I != J ? 2.0 : 1.0;
     s = block_sum256c(s, red);
-    if (threadIdx.x == 0) fro_part[i] = s;
+    if (threadIdx.x == 0) fro_part[id] = w * s;
     s64 = block_sum256c(s64, red);
-    if (threadIdx.x == 0) fro64_part[i] = s64;
+    if (threadIdx.x == 0) fro64_part[id] = w * s64;
 }
 
 hipError_t launch_normalize(int prec, const double *W, int64_t ld, int64_t n,
                             const double *dmn, const double *u, int lazy, void *S0,
                             double *fro_part, double *fro64_part, hipStream_t s) {
     const double sc = level_scale(prec, n);
-    dim3 g((unsigned)ld), b(256);
+    const int nt = (int)(ld / 64);
+    dim3 g((unsigned)sym_tiles64(ld)), b(256);
     switch (prec) {
-    case 0: hipLaunchKernelGGL(k_normalize<double>, g, b, 0, s, W, ld, n, dmn, u, lazy, sc, (double *)S0, fro_part, fro64_part); break;
-    case 1: hipLaunchKernelGGL(k_normalize<float>, g, b, 0, s, W, ld, n, dmn, u, lazy, sc, (float *)S0, fro_part, fro64_part); break;
-    case 2: hipLaunchKernelGGL(k_normalize<__bf16>, g, b, 0, s, W, ld, n, dmn, u, lazy, sc, (__bf16 *)S0, fro_part, fro64_part); break;
-    case 3: hipLaunchKernelGGL(k_normalize<_Float16>, g, b, 0, s, W, ld, n, dmn, u, lazy, sc, (_Float16 *)S0, fro_part, fro64_part); break;
+    case 0: hipLaunchKernelGGL(k_normalize<double>, g, b, 0, s, W, ld, n, dmn, u, lazy, sc, nt, (double *)S0, fro_part, fro64_part); break;
+    case 1: hipLaunchKernelGGL(k_normalize<float>, g, b, 0, s, W, ld, n, dmn, u, lazy, sc, nt, (float *)S0, fro_part, fro64_part); break;
+    case 2: hipLaunchKernelGGL(k_normalize<__bf16>, g, b, 0, s, W, ld, n, dmn, u, lazy, sc, nt, (__bf16 *)S0, fro_part, fro64_part); break;
+    case 3: hipLaunchKernelGGL(k_normalize<_Float16>, g, b, 0, s, W, ld, n, dmn, u, lazy, sc, nt, (_Float16 *)S0, fro_part, fro64_part); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -4,10 +4,14 @@
 //
 //   pad_series   copy X into a zero-padded FP64 panel, row norms ||x_i||^2
 //   gram_dist    D2_ij = ||x_i||^2 + ||x_j||^2 - 2 x_i.x_j on FP64 MFMA,
-//                upper-triangular tiles written with their mirror
+//                upper-triangular 128 x 128 tiles only (the lower half of
+//                the buffer is never read)
 //   select       exact lower median of D2 over i < j by 6 radix passes over
 //                the IEEE-754 bit patterns (order-preserving for D2 >= 0)
-//   exp_degree   W = exp(-D2 / sigma^2) in place, W_ii = 0, deg = row sums
+//   exp_sym      per upper 64 x 64 tile: W = exp(-D2 / sigma^2) in place,
+//                W_ii = 0, written with its mirror; row and column sums
+//                into one partial per (tile column, node)
+//   degree       deg = sum of the partials in tile order
 //   graph_stats  vol = sum deg, min and max degree (fixed-order reductions)
 #include "common.h"
 #include "gemm.h"
@@ -114,7 +118,7 @@ __global__ __launch_bounds__(512) void k_gram_dist(const double *Xp, int64_t Tp,
         }
         return d;
     };
-    stage_and_store_rows<kGramRC>(g, smem, f, D2, ld, m0, n0, I != J);
+    stage_and_store_rows<kGramRC>(g, smem, f, D2, ld, m0, n0, false);
     if (st) {
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) {
@@ -332,27 +336,83 @@ hipError_t launch_set_sigma(double sigma, double *stats, hipStream_t s) {
 
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_exp_degree(double *W, int64_t ld, int64_t n,
-                                                    const double *stats, double *deg) {
-    __shared__ double red[4];
-    const int64_t i = blockIdx.x;
+int sym_tiles64(int64_t ld) {
+    const int nt = (int)(ld / 64);
+    return nt * (nt + 1) / 2;
+}
+
+// One 64 x 64 tile (I <= J) per workgroup.  part[J][i] receives the sum of
+// row i over the tile's columns and, for I < J, part[I][j] the sum of column
+// j: every (tile column, node) slot is written by exactly one tile.  Each
+// thread handles runs of 8 consecutive elements (64-byte accesses).
+__global__ __launch_bounds__(256) void k_exp_sym(double *W, int64_t ld, int64_t n,
+                                                 const double *stats, int nt, double *part) {
+    __shared__ double t[64][65];
+    const int total = nt * (nt + 1) / 2;
+    int I, J;
+    sym_tile<8>(xcd_remap(blockIdx.x, total), nt, I, J);
     const double sigma = stats[1];
     const double s2 = sigma * sigma;
-    double s = 0.0;
-    double *row = W + i * ld;
-    for (int64_t j = threadIdx.x; j < ld; j += 256) {
-        double v = 0.0;
-        if (i < n && j < n && i != j) v = exp(-row[j] / s2);
-        row[j] = v;
-        s += v;
+    const int64_t i0 = (int64_t)I * 64, j0 = (int64_t)J * 64;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int r = (tid >> 3) + 32 * h, c0 = (tid & 7) * 8;
+        const int64_t i = i0 + r;
+        double *row = W + i * ld + j0 + c0;
+        double v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = row[e];
+        double rs = 0.0;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int64_t j = j0 + c0 + e;
+            v[e] = (i < n && j < n && i != j) ? exp(-v[e] / s2) : 0.0;
+            t[r][c0 + e] = v[e];
+            rs += v[e];
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) row[e] = v[e];
+        rs += __shfl_xor(rs, 1);
+        rs += __shfl_xor(rs, 2);
+        rs += __shfl_xor(rs, 4);
+        if ((tid & 7) == 0) part[(int64_t)J * ld + i] = rs;
     }
-    s = block_sum256(s, red);
-    if (threadIdx.x == 0 && i < n) deg[i] = s;
+    if (I == J) return;
+    __syncthreads();
+    {   // column sums: thread (column c, quarter q) over 16 rows
+        const int c = tid >> 2, q = tid & 3;
+        double cs = 0.0;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) cs += t[16 * q + r][c];
+        cs += __shfl_xor(cs, 1);
+        cs += __shfl_xor(cs, 2);
+        if (q == 0) part[(int64_t)I * ld + j0 + c] = cs;
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {   // mirror: row j0 + rr gets column rr of the tile
+        const int rr = (tid >> 3) + 32 * h, c0 = (tid & 7) * 8;
+        double *row = W + (j0 + rr) * ld + i0 + c0;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) row[e] = t[c0 + e][rr];
+    }
+}
+
+__global__ void k_degree_reduce(const double *part, int nt, int64_t ld, int64_t n, double *deg) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int b = 0; b < nt; ++b) acc += part[(int64_t)b * ld + i];
+    deg[i] = acc;
 }
 
 hipError_t launch_exp_degree(double *W, int64_t ld, int64_t n, const double *stats,
-                             double *deg, hipStream_t s) {
-    hipLaunchKernelGGL(k_exp_degree, dim3((unsigned)ld), dim3(256), 0, s, W, ld, n, stats, deg);
+                             double *deg, double *part, hipStream_t s) {
+    const int nt = (int)(ld / 64);
+    hipLaunchKernelGGL(k_exp_sym, dim3((unsigned)sym_tiles64(ld)), dim3(256), 0, s, W, ld, n,
+                       stats, nt, part);
+    hipLaunchKernelGGL(k_degree_reduce, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, part, nt,
+                       ld, n, deg);
     return hipGetLastError();
 }
 

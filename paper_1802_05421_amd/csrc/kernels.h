@@ -37,8 +37,10 @@ hipError_t launch_select_reset(SelectState *st, hipStream_t s);
 hipError_t launch_select_median(const double *D2, int64_t ld, int64_t n,
                                 SelectState *st, double *stats, hipStream_t s);
 hipError_t launch_set_sigma(double sigma, double *stats, hipStream_t s);
+// part: (ld / 64) x ld doubles of degree partials.
+int sym_tiles64(int64_t ld);   // upper 64 x 64 tiles of an ld x ld matrix
 hipError_t launch_exp_degree(double *W, int64_t ld, int64_t n, const double *stats,
-                             double *deg, hipStream_t s);
+                             double *deg, double *part, hipStream_t s);
 hipError_t launch_graph_stats(const double *deg, int64_t n, double *stats, hipStream_t s);
 hipError_t launch_import_weights(const double *Win, int64_t ldw, int64_t n, double *W,
                                  int64_t ld, double *deg, int *flags, hipStream_t s);
@@ -48,8 +50,10 @@ hipError_t launch_import_weights(const double *Win, int64_t ldw, int64_t n, doub
 hipError_t launch_chain_prep(const double *deg, const double *stats, int64_t n, int64_t ld,
                              int lazy, double *dmn, double *dm, double *u, hipStream_t s);
 float level_scale(int prec, int64_t n);   // storage scale of FP16 levels (1 otherwise)
-// fro_part: per-row squared Frobenius sums of the stored (rounded) level;
-// fro64_part: the same for the unrounded FP64 values.
+// Reads the upper 64 x 64 tiles of W only and writes S0 with its mirror.
+// fro_part / fro64_part: one squared Frobenius sum of the stored (rounded)
+// and of the unrounded FP64 level per upper tile (doubled off the diagonal),
+// sym_tiles64(ld) entries each.
 hipError_t launch_normalize(int prec, const double *W, int64_t ld, int64_t n,
                             const double *dmn, const double *u, int lazy, void *S0,
                             double *fro_part, double *fro64_part, hipStream_t s);
