@@ -87,11 +87,15 @@ __device__ __forceinline__ void masked_add8(uint32_t &h, double w, double &a0, d
 // one subtraction at the end loses about log2(T / |y|) ~ 7 bits of the 53.
 __global__ __launch_bounds__(256) void k_rhs(const double *W, int64_t ld, int64_t n,
                                              const int32_t *gid, int64_t k, uint64_t mseed,
-                                             double inv_sqrt_k, double *Yt) {
+                                             double inv_sqrt_k, int nb, double *Yt) {
     const int lane = threadIdx.x & 63;
-    // projection block fastest, so the blocks sharing a row of W run together
-    const int64_t i = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 6);
-    const uint64_t beta = blockIdx.x;
+    // Workgroups are dispatched round-robin over the XCDs: the nb projection
+    // blocks of one group of 4 rows get ids 8 apart, so they run together on
+    // one XCD and read those rows of W through its L2 once.
+    const int w = blockIdx.x, per = kNumXcd * nb, l = w % per;
+    const int64_t group = (int64_t)(w / per) * kNumXcd + l % kNumXcd;
+    const uint64_t beta = (uint64_t)(l / kNumXcd);
+    const int64_t i = group * 4 + (threadIdx.x >> 6);
     if (i >= n) return;
     const uint64_t gi = gid ? (uint64_t)(uint32_t)gid[i] : (uint64_t)i;
     double acc[64];
@@ -139,9 +143,10 @@ __global__ __launch_bounds__(256) void k_rhs(const double *W, int64_t ld, int64_
 hipError_t launch_rhs(const double *W, int64_t ld, int64_t n, const int32_t *gid, int64_t k,
                       int64_t kpad, uint64_t seed, double *Yt, hipStream_t s) {
     const uint64_t mseed = splitmix64_mix_host(seed);
-    dim3 grid((unsigned)(kpad / 64), (unsigned)cdiv(n, 4));
-    hipLaunchKernelGGL(k_rhs, grid, dim3(256), 0, s, W, ld, n, gid, k, mseed,
-                       1.0 / sqrt((double)k), Yt);
+    const int nb = (int)(kpad / 64);
+    const int64_t groups = cdiv(cdiv(n, 4), kNumXcd) * kNumXcd;
+    hipLaunchKernelGGL(k_rhs, dim3((unsigned)(groups * nb)), dim3(256), 0, s, W, ld, n, gid, k,
+                       mseed, 1.0 / sqrt((double)k), nb, Yt);
     return hipGetLastError();
 }
 
