@@ -5,7 +5,7 @@
 //   pad_series   copy X into a zero-padded FP64 panel, row norms ||x_i||^2
 //   gram_dist    D2_ij = ||x_i||^2 + ||x_j||^2 - 2 x_i.x_j on FP64 MFMA,
 //                upper-triangular 128 x 128 tiles only (the lower half of
-//                the buffer is never read)
+//                the buffer is never read), stored from the accumulators
 //   select       exact lower median of D2 over i < j by 6 radix passes over
 //                the IEEE-754 bit patterns (order-preserving for D2 >= 0)
 //   exp_sym      per upper 64 x 64 tile: W = exp(-D2 / sigma^2) in place,
@@ -87,9 +87,7 @@ hipError_t launch_pad_series(const double *X, int64_t n, int64_t T, int64_t ldx,
 // Squared distances from the Gram matrix of the series (FP64 MFMA).
 
 using GramCore = GemmCore<MfmaF64, 128, 128, 8, 2, 4>;
-constexpr int kGramRC = 32;
-constexpr size_t kGramStage = kGramRC * (128 + 2) * sizeof(double);
-constexpr size_t kGramSmem = GramCore::SMEM > kGramStage ? GramCore::SMEM : kGramStage;
+constexpr size_t kGramSmem = GramCore::SMEM;
 
 // st != nullptr: also fold the smallest and largest upper-triangle key
 // (i < j) into st->kmin / st->kmax (the median selection starts below their
@@ -118,7 +116,16 @@ __global__ __launch_bounds__(512) void k_gram_dist(const double *Xp, int64_t Tp,
         }
         return d;
     };
-    stage_and_store_rows<kGramRC>(g, smem, f, D2, ld, m0, n0, false);
+    // direct stores: 16 lanes cover 16 consecutive columns of one row
+#pragma unroll
+    for (int a = 0; a < GramCore::WTM; ++a)
+#pragma unroll
+        for (int b = 0; b < GramCore::WTN; ++b)
+#pragma unroll
+            for (int rr = 0; rr < MfmaF64::R; ++rr) {
+                const int r = GramCore::row_of(a, rr), c = GramCore::col_of(b);
+                D2[(m0 + r) * ld + n0 + c] = f(r, c, g.acc[a][b][rr]);
+            }
     if (st) {
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) {
