@@ -106,6 +106,7 @@ def main():
     ap.add_argument("--no-stress", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-sequence", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -232,6 +233,50 @@ def main():
         if "fp32" in st:
             stress["mixed_over_fp32"] = round(st["fp32"]["ms_per_pair"] / st[args.mixed]["ms_per_pair"], 3)
 
+    # Amortised sequence pair: in a sequence every snapshot is embedded once,
+    # so one new pair costs one graph + chain + solve and one score.
+    def seq_step(prec, t):
+        cdl.build_graph(X[t], ws=gws, out=graphs[t], check=True)
+        ch = cdl.build_chain(graphs[t], prec=prec, depth=0, depth_max=DMAX, buf=chb[prec][t])
+        cdl.solve_embedding(graphs[t], ch, k, seed, tol=args.tol, max_iter=30, ws=sws, Z=Zb[prec][t])
+        cdl.anomaly_scores(Zb[prec][t ^ 1], graphs[t ^ 1], Zb[prec][t], graphs[t], top_k=50, ws=scws,
+                           F=Fb[prec], top=Tb[prec])
+
+    seq_step(args.mixed, 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        seq_step(args.mixed, (i + 1) & 1)
+    torch.cuda.synchronize()
+    ms_amort = (time.perf_counter() - t0) / args.steps
+    amortized = {"ms_per_pair": round(ms_amort * 1e3, 3), "pairs_per_s": round(1.0 / ms_amort, 3),
+                 "prec": args.mixed}
+    log("amortised sequence pair: %.2f ms" % (ms_amort * 1e3))
+
+    # Batched uneven sequence: 24 snapshots, n_t ~ U{1024..8192} on a 96 x 96
+    # grid, k = 128, 23 consecutive-pair scores over the common global ids.
+    sequence = None
+    if not args.no_sequence:
+        seqin = gen.make_sequence(G=96, T=120, n_snap=24, stride=30, n_min=1024, n_max=8192,
+                               onsets=(8, 16))
+        Xs = [torch.from_numpy(x).to(dev) for x in seqin.X]
+        gids = [torch.from_numpy(g) for g in seqin.gid]
+        sp = cdl.SeqParams(k=128, seed=seed, prec=args.mixed, depth=0, depth_max=DMAX, tol=1e-8,
+                           max_iter=30, top_k=50)
+        Fs, tops, sinfo = cdl.score_sequence(Xs, gids, sp)        # warm-up (and workspace)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Fs, tops, sinfo = cdl.score_sequence(Xs, gids, sp)
+        torch.cuda.synchronize()
+        ms_seq = time.perf_counter() - t0
+        sequence = {"workload": "24 snapshots, n_t in [1024, 8192] (sum %d), T=120, k=128, %s chain, "
+                                "FP64 residual 1e-8" % (sum(len(g) for g in seqin.gid), args.mixed.upper()),
+                    "ms_per_sequence": round(ms_seq * 1e3, 2), "pairs": sinfo.pairs,
+                    "pairs_per_s": round(sinfo.pairs / ms_seq, 2),
+                    "max_iterations": sinfo.max_iterations,
+                    "max_rel_residual": sinfo.max_rel_residual}
+        log("sequence: %d pairs in %.1f ms" % (sinfo.pairs, ms_seq * 1e3))
+
     # dominant kernel of the mixed step
     modeled = {nm: v for nm, v in times_mixed.items() if kernel_model(nm, n, k, T, args.mixed)}
     dom = max(modeled, key=lambda nm: modeled[nm][1])
@@ -264,6 +309,8 @@ def main():
         "kernels_ms_per_step": {p: {nm: round(v[1] / (args.steps if p == args.mixed else args.fp32_steps), 3)
                                     for nm, v in sorted(res[p][2].items(), key=lambda x: -x[1][1])}
                                 for p in precs},
+        "amortized_sequence_pair": amortized,
+        "sequence_c4": sequence,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -79,49 +79,82 @@ __device__ __forceinline__ void masked_add8(uint32_t &h, double w, double &a0, d
         : "scc");
 }
 
-// Row i of Y for projection block beta = blockIdx.x (64 columns).  The sign
-// of edge {i, j} in column r is B(e, i) * q_r(e) = 1 - 2 b, b = bit r of the
-// sign word, complemented when i is the tail (higher global id).  So
+// Row i of Y for one projection block beta (64 columns).  The sign of edge
+// {i, j} in column r is B(e, i) * q_r(e) = 1 - 2 b, b = bit r of the sign
+// word, complemented when i is the tail (higher global id).  So
 // sum_j s_j w_j = T - 2 M_r with T = sum_j w_j and M_r the sum over the j
 // whose bit is set: only non-negative terms are accumulated (FP64), and the
 // one subtraction at the end loses about log2(T / |y|) ~ 7 bits of the 53.
+//
+// A workgroup is 4 waves: 4/P rows, P projection blocks per row.  The P
+// waves of a row share sqrt(W_ij) and the global ids through LDS: per
+// iteration each computes them for its own 64 neighbours, then all P waves
+// sweep the P * 64 neighbours with their own sign words.
+template <int P>
 __global__ __launch_bounds__(256) void k_rhs(const double *W, int64_t ld, int64_t n,
                                              const int32_t *gid, int64_t k, uint64_t mseed,
                                              double inv_sqrt_k, int nb, double *Yt) {
-    const int lane = threadIdx.x & 63;
-    // Workgroups are dispatched round-robin over the XCDs: the nb projection
-    // blocks of one group of 4 rows get ids 8 apart, so they run together on
-    // one XCD and read those rows of W through its L2 once.
-    const int w = blockIdx.x, per = kNumXcd * nb, l = w % per;
+    constexpr int R = 4 / P;
+    __shared__ double sw[R][P * 64];
+    __shared__ uint32_t sg[R][P * 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int rs = wv / P, q = wv % P;
+    // Workgroups are dispatched round-robin over the XCDs: the projection
+    // groups of one row group get ids 8 apart, so they run together on one
+    // XCD and read those rows of W through its L2 once.
+    const int nbg = (nb + P - 1) / P;
+    const int w = blockIdx.x, per = kNumXcd * nbg, l = w % per;
     const int64_t group = (int64_t)(w / per) * kNumXcd + l % kNumXcd;
-    const uint64_t beta = (uint64_t)(l / kNumXcd);
-    const int64_t i = group * 4 + (threadIdx.x >> 6);
-    if (i >= n) return;
-    const uint64_t gi = gid ? (uint64_t)(uint32_t)gid[i] : (uint64_t)i;
+    const int beta_i = (l / kNumXcd) * P + q;
+    const uint64_t beta = (uint64_t)beta_i;
+    const int64_t i = group * R + rs;
+    const bool row_ok = i < n, active = row_ok && beta_i < nb;
+    const uint64_t gi = !row_ok ? 0 : (gid ? (uint64_t)(uint32_t)gid[i] : (uint64_t)i);
     double acc[64];
 #pragma unroll
     for (int r = 0; r < 64; ++r) acc[r] = 0.0;
     double tsum = 0.0;
-    const double *row = W + i * ld;
-    for (int64_t j = lane; j < n; j += 64) {
-        const uint64_t gj = gid ? (uint64_t)(uint32_t)gid[j] : (uint64_t)j;
-        const uint64_t lo = gi < gj ? gi : gj, hi = gi < gj ? gj : gi;
-        uint64_t h = splitmix64_mix(mseed ^ ((beta << 40) | (lo << 20) | hi));
-        if (gi > gj) h = ~h;
-        // correctly rounded sqrt(W) (the bare hardware instruction is only an
-        // approximation in FP64)
-        const double w = sqrt(row[j]);
-        tsum += w;
-        uint32_t hh = (uint32_t)(h >> 32), hl = (uint32_t)h;
-        masked_add8(hh, w, acc[63], acc[62], acc[61], acc[60], acc[59], acc[58], acc[57], acc[56]);
-        masked_add8(hh, w, acc[55], acc[54], acc[53], acc[52], acc[51], acc[50], acc[49], acc[48]);
-        masked_add8(hh, w, acc[47], acc[46], acc[45], acc[44], acc[43], acc[42], acc[41], acc[40]);
-        masked_add8(hh, w, acc[39], acc[38], acc[37], acc[36], acc[35], acc[34], acc[33], acc[32]);
-        masked_add8(hl, w, acc[31], acc[30], acc[29], acc[28], acc[27], acc[26], acc[25], acc[24]);
-        masked_add8(hl, w, acc[23], acc[22], acc[21], acc[20], acc[19], acc[18], acc[17], acc[16]);
-        masked_add8(hl, w, acc[15], acc[14], acc[13], acc[12], acc[11], acc[10], acc[9], acc[8]);
-        masked_add8(hl, w, acc[7], acc[6], acc[5], acc[4], acc[3], acc[2], acc[1], acc[0]);
+    const double *row = W + (row_ok ? i : 0) * ld;
+    for (int64_t j0 = 0; j0 < n; j0 += P * 64) {
+        {   // correctly rounded sqrt(W) (the bare hardware instruction is only
+            // an approximation in FP64); zero beyond n
+            const int64_t j = j0 + q * 64 + lane;
+            double v = 0.0;
+            uint32_t g = 0;
+            if (row_ok && j < n) {
+                v = sqrt(row[j]);
+                g = gid ? (uint32_t)gid[j] : (uint32_t)j;
+            }
+            sw[rs][q * 64 + lane] = v;
+            sg[rs][q * 64 + lane] = g;
+        }
+        __syncthreads();
+        if (active) {
+#pragma unroll
+            for (int sub = 0; sub < P; ++sub) {
+                const int64_t j = j0 + sub * 64 + lane;
+                if (j < n) {
+                    const double wj = sw[rs][sub * 64 + lane];
+                    const uint64_t gj = sg[rs][sub * 64 + lane];
+                    const uint64_t lo = gi < gj ? gi : gj, hi = gi < gj ? gj : gi;
+                    uint64_t h = splitmix64_mix(mseed ^ ((beta << 40) | (lo << 20) | hi));
+                    if (gi > gj) h = ~h;
+                    tsum += wj;
+                    uint32_t hh = (uint32_t)(h >> 32), hl = (uint32_t)h;
+                    masked_add8(hh, wj, acc[63], acc[62], acc[61], acc[60], acc[59], acc[58], acc[57], acc[56]);
+                    masked_add8(hh, wj, acc[55], acc[54], acc[53], acc[52], acc[51], acc[50], acc[49], acc[48]);
+                    masked_add8(hh, wj, acc[47], acc[46], acc[45], acc[44], acc[43], acc[42], acc[41], acc[40]);
+                    masked_add8(hh, wj, acc[39], acc[38], acc[37], acc[36], acc[35], acc[34], acc[33], acc[32]);
+                    masked_add8(hl, wj, acc[31], acc[30], acc[29], acc[28], acc[27], acc[26], acc[25], acc[24]);
+                    masked_add8(hl, wj, acc[23], acc[22], acc[21], acc[20], acc[19], acc[18], acc[17], acc[16]);
+                    masked_add8(hl, wj, acc[15], acc[14], acc[13], acc[12], acc[11], acc[10], acc[9], acc[8]);
+                    masked_add8(hl, wj, acc[7], acc[6], acc[5], acc[4], acc[3], acc[2], acc[1], acc[0]);
+                }
+            }
+        }
+        __syncthreads();
     }
+    if (!active) return;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) tsum += __shfl_xor(tsum, o);
     // Butterfly transpose-reduction: afterwards lane l holds column l summed
@@ -130,10 +163,10 @@ __global__ __launch_bounds__(256) void k_rhs(const double *W, int64_t ld, int64_
     for (int s = 32; s >= 1; s >>= 1) {
         const bool up = (lane & s) != 0;
 #pragma unroll
-        for (int q = 0; q < s; ++q) {
-            const double send = up ? acc[q] : acc[q + s];
-            const double keep = up ? acc[q + s] : acc[q];
-            acc[q] = keep + __shfl_xor(send, s);
+        for (int q2 = 0; q2 < s; ++q2) {
+            const double send = up ? acc[q2] : acc[q2 + s];
+            const double keep = up ? acc[q2 + s] : acc[q2];
+            acc[q2] = keep + __shfl_xor(send, s);
         }
     }
     const int64_t r = (int64_t)beta * 64 + lane;
@@ -144,9 +177,16 @@ hipError_t launch_rhs(const double *W, int64_t ld, int64_t n, const int32_t *gid
                       int64_t kpad, uint64_t seed, double *Yt, hipStream_t s) {
     const uint64_t mseed = splitmix64_mix_host(seed);
     const int nb = (int)(kpad / 64);
-    const int64_t groups = cdiv(cdiv(n, 4), kNumXcd) * kNumXcd;
-    hipLaunchKernelGGL(k_rhs, dim3((unsigned)(groups * nb)), dim3(256), 0, s, W, ld, n, gid, k,
-                       mseed, 1.0 / sqrt((double)k), nb, Yt);
+    const int P = nb >= 4 ? 4 : (nb >= 2 ? 2 : 1);
+    const int nbg = (nb + P - 1) / P;
+    const int64_t groups = cdiv(cdiv(n, 4 / P), kNumXcd) * kNumXcd;
+    const dim3 grid((unsigned)(groups * nbg)), blk(256);
+    const double isk = 1.0 / sqrt((double)k);
+    switch (P) {
+    case 4: hipLaunchKernelGGL(k_rhs<4>, grid, blk, 0, s, W, ld, n, gid, k, mseed, isk, nb, Yt); break;
+    case 2: hipLaunchKernelGGL(k_rhs<2>, grid, blk, 0, s, W, ld, n, gid, k, mseed, isk, nb, Yt); break;
+    default: hipLaunchKernelGGL(k_rhs<1>, grid, blk, 0, s, W, ld, n, gid, k, mseed, isk, nb, Yt); break;
+    }
     return hipGetLastError();
 }
 
