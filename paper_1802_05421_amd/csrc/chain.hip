@@ -18,6 +18,8 @@
 // FP16 levels hold scale * S~ (scale = a power of two near n) so entries of
 // order 1/n stay in FP16's normal range; the squaring and the application
 // divide the scale back out.
+#include <type_traits>
+
 #include "common.h"
 #include "gemm.h"
 #include "kernels.h"
@@ -241,10 +243,14 @@ hipError_t launch_square(int prec, const void *S, void *S2, int64_t ld, int64_t 
 
 template <typename T> struct ApBK { static constexpr int v = 64 * 2 / (int)sizeof(T) < 16 ? 16 : 64 * 2 / (int)sizeof(T); };
 
+// 16-bit levels stream through the direct-to-LDS core, FP32 levels through
+// the register-staged one.
 template <typename T, int BM> struct ApCfg {
     static constexpr int WM = BM / 128 > 0 ? BM / 128 : 1;
     static constexpr int WN = 8 / WM;
-    using Core = GemmCore<typename MfmaOf<T>::type, BM, 256, ApBK<T>::v, WM, WN>;
+    using Mf = typename MfmaOf<T>::type;
+    using Core = std::conditional_t<sizeof(T) == 2, DmaCore<Mf, BM, 256, WM, WN>,
+                                    GemmCore<Mf, BM, 256, ApBK<T>::v, WM, WN>>;
 };
 
 template <typename T, int BM>
