@@ -86,11 +86,17 @@ def timing(device: int = 0, reset: bool = False) -> dict:
 
 
 def context(device: int = 0) -> Context:
-    c = _ctx_cache.get(device)
+    """The library context for torch's current stream on `device`.
+
+    One context per (device, stream): calls made from different host threads
+    on different streams never share a context.
+    """
+    s = torch.cuda.current_stream(device)
+    key = (device, s.cuda_stream)
+    c = _ctx_cache.get(key)
     if c is None:
-        c = Context(device)
-        _ctx_cache[device] = c
-    c.sync_stream()
+        c = Context(device, s)
+        _ctx_cache[key] = c
     return c
 
 

@@ -232,7 +232,7 @@ __global__ __launch_bounds__(256) void k_select_pass(const double *D2, int64_t l
     if (mode == 0) {
         __syncthreads();
         for (int b = threadIdx.x; b < 4096; b += 256)
-            if (h[b]) atomicAdd(&st->hist[b], h[b]);
+            if (h[b]) atomicAdd(&st->hist[b], (unsigned long long)h[b]);
     }
 }
 

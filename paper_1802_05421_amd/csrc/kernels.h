@@ -21,7 +21,7 @@ struct SelectState {                // device scratch of the exact median select
     int bits;                       // number of resolved high bits
     int mode;                       // 0 histogram, 1 collect, 2 done
     unsigned int count;             // collected candidates
-    unsigned int hist[4096];
+    unsigned long long hist[4096];  // 64-bit: a bin can exceed 2^32 keys for n > 92681
     unsigned long long cand[kSelCap];
 };
 
