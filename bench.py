@@ -21,6 +21,7 @@ import json
 import math
 import os
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -206,6 +207,8 @@ def main():
                             "top50_equal": bool(set(Tb[args.mixed].tolist()) == set(Tb[p].tolist())),
                             "certified_error_bound": max(i["certified_error"] for i in res[p][1])}
 
+    top_ref = Tb[args.mixed].clone()
+
     # The chain squaring itself (the autotuner may skip it at this spectral
     # radius): one two-level chain per type, timed on its own.
     sq = {}
@@ -232,6 +235,51 @@ def main():
         stress = {"sigma": round(sig, 4), "per_prec": st}
         if "fp32" in st:
             stress["mixed_over_fp32"] = round(st["fp32"]["ms_per_pair"] / st[args.mixed]["ms_per_pair"], 3)
+
+    # The two snapshots of a pair are independent until the score: run them
+    # from two host threads on two streams (each with its own library
+    # context and workspaces) and score once both are done.
+    sws2 = torch.empty_like(sws)
+    gws2 = torch.empty_like(gws)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+
+    def concurrent_step(prec):
+        errs = []
+
+        def snap(t):
+            try:
+                with torch.cuda.stream(streams[t]):
+                    cdl.build_graph(X[t], ws=(gws, gws2)[t], out=graphs[t], check=True)
+                    ch = cdl.build_chain(graphs[t], prec=prec, depth=0, depth_max=DMAX, buf=chb[prec][t])
+                    cdl.solve_embedding(graphs[t], ch, k, seed, tol=args.tol, max_iter=30,
+                                        ws=(sws, sws2)[t], Z=Zb[prec][t])
+            except Exception as e:   # re-raised on the main thread
+                errs.append(e)
+
+        ths = [threading.Thread(target=snap, args=(t,)) for t in (0, 1)]
+        for th in ths:
+            th.start()
+        for th in ths:
+            th.join()
+        if errs:
+            raise errs[0]
+        cur = torch.cuda.current_stream()
+        cur.wait_stream(streams[0])
+        cur.wait_stream(streams[1])
+        cdl.anomaly_scores(Zb[prec][0], graphs[0], Zb[prec][1], graphs[1], top_k=50, ws=scws,
+                           F=Fb[prec], top=Tb[prec])
+
+    concurrent_step(args.mixed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        concurrent_step(args.mixed)
+    torch.cuda.synchronize()
+    ms_conc = (time.perf_counter() - t0) / args.steps
+    concurrent = {"ms_per_pair": round(ms_conc * 1e3, 3), "pairs_per_s": round(1.0 / ms_conc, 3),
+                  "prec": args.mixed,
+                  "top50_equal_to_timed_step": bool(torch.equal(Tb[args.mixed], top_ref))}
+    log("two-stream pair: %.2f ms" % (ms_conc * 1e3))
 
     # Amortised sequence pair: in a sequence every snapshot is embedded once,
     # so one new pair costs one graph + chain + solve and one score.
@@ -309,6 +357,7 @@ def main():
         "kernels_ms_per_step": {p: {nm: round(v[1] / (args.steps if p == args.mixed else args.fp32_steps), 3)
                                     for nm, v in sorted(res[p][2].items(), key=lambda x: -x[1][1])}
                                 for p in precs},
+        "concurrent_snapshots": concurrent,
         "amortized_sequence_pair": amortized,
         "sequence_c4": sequence,
         "cpu_baseline": cpu,
