@@ -63,8 +63,9 @@ hipError_t launch_chain_prep(const double *deg, const double *stats, int64_t n, 
     return hipGetLastError();
 }
 
-// One upper 64 x 64 tile per workgroup, runs of 8 consecutive elements per
-// thread; the mirror is written from the LDS copy of the rounded tile.
+// One upper 64 x 64 tile per workgroup; lane = column, so every global
+// access of a wave is one contiguous row segment; the mirror is written from
+// the LDS copy of the rounded tile.
 template <typename T>
 __global__ __launch_bounds__(256) void k_normalize(const double *W, int64_t ld, int64_t n,
                                                    const double *dmn, const double *u, int lazy,
@@ -72,52 +73,38 @@ __global__ __launch_bounds__(256) void k_normalize(const double *W, int64_t ld, 
                                                    double *fro_part, double *fro64_part) {
     __shared__ T t[64][64 + 16 / sizeof(T)];
     __shared__ double red[4];
-    union Run { T e[8]; uint4 q[sizeof(T) * 8 / 16]; };
     const int total = nt * (nt + 1) / 2;
     const int id = xcd_remap(blockIdx.x, total);
     int I, J;
     sym_tile<8>(id, nt, I, J);
     const int64_t i0 = (int64_t)I * 64, j0 = (int64_t)J * 64;
-    const int tid = threadIdx.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t j = j0 + lane;
+    const double dj = j < n ? dmn[j] : 0.0, uj = j < n ? u[j] : 0.0;
     double s = 0.0, s64 = 0.0;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int r = (tid >> 3) + 32 * h, c0 = (tid & 7) * 8;
+#pragma unroll 4
+    for (int rr = 0; rr < 16; ++rr) {
+        const int r = wv * 16 + rr;
         const int64_t i = i0 + r;
-        const double *wr = W + i * ld + j0 + c0;
-        const double di = i < n ? dmn[i] : 0.0, ui = i < n ? u[i] : 0.0;
-        Run out;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int64_t j = j0 + c0 + e;
-            double v = 0.0;
-            if (i < n && j < n) {
-                v = wr[e] * (di * dmn[j]);
-                if (lazy) v = 0.5 * ((i == j ? 1.0 : 0.0) + v);
-                v -= ui * u[j];
-            }
-            const T tv = cvtd<T>(v * scale);
-            out.e[e] = tv;
-            t[r][c0 + e] = tv;
-            const double back = tod<T>(tv) / scale;
-            s += back * back;
-            s64 += v * v;
+        double v = 0.0;
+        if (i < n && j < n) {
+            v = W[i * ld + j] * (dmn[i] * dj);
+            if (lazy) v = 0.5 * ((i == j ? 1.0 : 0.0) + v);
+            v -= u[i] * uj;
         }
-        uint4 *dst = (uint4 *)(S0 + i * ld + j0 + c0);
-#pragma unroll
-        for (int q = 0; q < (int)(sizeof(T) * 8 / 16); ++q) dst[q] = out.q[q];
+        const T tv = cvtd<T>(v * scale);
+        t[r][lane] = tv;
+        S0[i * ld + j] = tv;
+        const double back = tod<T>(tv) / scale;
+        s += back * back;
+        s64 += v * v;
     }
     if (I != J) {
         __syncthreads();
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int rr = (tid >> 3) + 32 * h, c0 = (tid & 7) * 8;
-            Run out;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) out.e[e] = t[c0 + e][rr];
-            uint4 *dst = (uint4 *)(S0 + (j0 + rr) * ld + i0 + c0);
-#pragma unroll
-            for (int q = 0; q < (int)(sizeof(T) * 8 / 16); ++q) dst[q] = out.q[q];
+#pragma unroll 4
+        for (int cc = 0; cc < 16; ++cc) {
+            const int c = wv * 16 + cc;
+            S0[(j0 + c) * ld + i0 + lane] = t[lane][c];
         }
     }
     const double w = I != J ? 2.0 : 1.0;

@@ -350,58 +350,51 @@ int sym_tiles64(int64_t ld) {
 
 // One 64 x 64 tile (I <= J) per workgroup.  part[J][i] receives the sum of
 // row i over the tile's columns and, for I < J, part[I][j] the sum of column
-// j: every (tile column, node) slot is written by exactly one tile.  Each
-// thread handles runs of 8 consecutive elements (64-byte accesses).
+// j: every (tile column, node) slot is written by exactly one tile.  Lane =
+// column, so every global access of a wave is one contiguous 512-byte row
+// segment; the four waves take 16 rows each.
 __global__ __launch_bounds__(256) void k_exp_sym(double *W, int64_t ld, int64_t n,
                                                  const double *stats, int nt, double *part) {
     __shared__ double t[64][65];
+    __shared__ double cs[4][64];
     const int total = nt * (nt + 1) / 2;
     int I, J;
     sym_tile<8>(xcd_remap(blockIdx.x, total), nt, I, J);
     const double sigma = stats[1];
     const double s2 = sigma * sigma;
     const int64_t i0 = (int64_t)I * 64, j0 = (int64_t)J * 64;
-    const int tid = threadIdx.x;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int r = (tid >> 3) + 32 * h, c0 = (tid & 7) * 8;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t j = j0 + lane;
+    double csum = 0.0;
+#pragma unroll 4
+    for (int rr = 0; rr < 16; ++rr) {
+        const int r = wv * 16 + rr;
         const int64_t i = i0 + r;
-        double *row = W + i * ld + j0 + c0;
-        double v[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] = row[e];
+        double *p = W + i * ld + j;
+        const double v = (i < n && j < n && i != j) ? exp(-*p / s2) : 0.0;
+        *p = v;
+        t[r][lane] = v;
+        csum += v;
+    }
+    cs[wv][lane] = csum;
+    __syncthreads();
+    {   // row sums: thread (row r, quarter q) over 16 columns
+        const int r = threadIdx.x >> 2, q = threadIdx.x & 3;
         double rs = 0.0;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int64_t j = j0 + c0 + e;
-            v[e] = (i < n && j < n && i != j) ? exp(-v[e] / s2) : 0.0;
-            t[r][c0 + e] = v[e];
-            rs += v[e];
-        }
-#pragma unroll
-        for (int e = 0; e < 8; ++e) row[e] = v[e];
+        for (int c = 0; c < 16; ++c) rs += t[r][16 * q + c];
         rs += __shfl_xor(rs, 1);
         rs += __shfl_xor(rs, 2);
-        rs += __shfl_xor(rs, 4);
-        if ((tid & 7) == 0) part[(int64_t)J * ld + i] = rs;
+        if (q == 0) part[(int64_t)J * ld + i0 + r] = rs;
     }
     if (I == J) return;
-    __syncthreads();
-    {   // column sums: thread (column c, quarter q) over 16 rows
-        const int c = tid >> 2, q = tid & 3;
-        double cs = 0.0;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) cs += t[16 * q + r][c];
-        cs += __shfl_xor(cs, 1);
-        cs += __shfl_xor(cs, 2);
-        if (q == 0) part[(int64_t)I * ld + j0 + c] = cs;
-    }
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {   // mirror: row j0 + rr gets column rr of the tile
-        const int rr = (tid >> 3) + 32 * h, c0 = (tid & 7) * 8;
-        double *row = W + (j0 + rr) * ld + i0 + c0;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) row[e] = t[c0 + e][rr];
+    if (threadIdx.x < 64)
+        part[(int64_t)I * ld + j0 + threadIdx.x] =
+            (cs[0][threadIdx.x] + cs[1][threadIdx.x]) + (cs[2][threadIdx.x] + cs[3][threadIdx.x]);
+#pragma unroll 4
+    for (int cc = 0; cc < 16; ++cc) {   // mirror: row j0 + c gets column c of the tile
+        const int c = wv * 16 + cc;
+        W[(j0 + c) * ld + i0 + lane] = t[lane][c];
     }
 }
 
