@@ -313,6 +313,31 @@ cdl_status cdl_anomaly_scores(cdl_ctx *ctx, const double *Z0, const double *W0,
                               cdl_score_mode mode, double *F, int32_t top_k,
                               int32_t *top_idx, void *ws, size_t ws_bytes);
 
+/* Edge-level anomalies (Background: the CAD edge score
+ * dE_ab = omega_ab |c_0(a,b) - c_1(a,b)|, whose row sums are the node
+ * scores of Algorithm 4): the top_k edges a < b over the m common nodes.
+ *   Inputs as for cdl_anomaly_scores; F (device, m FP64) receives the node
+ *   scores as a by-product.
+ *   top_k       1..CDL_MAX_TOPK, at most m(m-1)/2.
+ *   edge_a, edge_b  device outputs, top_k int32 common-node indices (a < b),
+ *               sorted by descending score, ties by ascending (a, b).
+ *   edge_val    device output, top_k FP64 scores.
+ *   ws          device workspace of cdl_edges_workspace_bytes(m, k, top_k).
+ * Exact: the per-tile maxima of the fused score give a lower bound on the
+ * K-th largest edge score (the K-th largest tile maximum); only tiles reaching
+ * it are recomputed and their edges at or above it sorted.  Syncs once.
+ * Errors: CDL_E_ARG, CDL_E_WORKSPACE, CDL_E_UNSUPPORTED when more than
+ * max(16384 top_k, 2^22) edges reach that bound (massive exact ties). */
+cdl_status cdl_edges_workspace_bytes(int64_t m, int64_t k, int32_t top_k, size_t *bytes);
+cdl_status cdl_anomaly_edges(cdl_ctx *ctx, const double *Z0, const double *W0,
+                             const double *stats0, int64_t n0,
+                             const double *Z1, const double *W1,
+                             const double *stats1, int64_t n1, int64_t k,
+                             const int32_t *map0, const int32_t *map1, int64_t m,
+                             cdl_score_mode mode, double *F, int32_t top_k,
+                             int32_t *edge_a, int32_t *edge_b, double *edge_val,
+                             void *ws, size_t ws_bytes);
+
 /* Whole sequence: for every snapshot, graph + chain + embedding; for every
  * consecutive pair (t, t+1), scores over the common global ids.
  *   F[t]        device output for pair t: m_t FP64, m_t = |V_t ∩ V_{t+1}|, in

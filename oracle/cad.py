@@ -40,6 +40,7 @@ __all__ = [
     "rhs", "rhs_rows", "rhs_numpy",
     "solve_embedding", "solve_embedding_eigh", "pinv_laplacian",
     "commute_times", "exact_commute_times", "scores", "scores_rows", "top_k",
+    "edge_scores", "top_edges",
     "normalized_deflated", "chain_levels", "chain_apply", "estimate_solution",
     "spectral_radius", "pair_pipeline", "lib",
 ]
@@ -320,6 +321,42 @@ def scores(Z0, vol0, Z1, vol1, W0=None, W1=None, map0=None, map1=None) -> np.nda
             W1 = W1[np.ix_(map1, map1)]
     m = Z0.shape[0]
     return scores_rows(Z0, vol0, Z1, vol1, np.arange(m), W0, W1)
+
+
+def edge_scores(Z0, vol0, Z1, vol1, W0=None, W1=None, map0=None, map1=None,
+                block: int = 64) -> np.ndarray:
+    """The m x m matrix of CAD edge scores omega_ab |c_0(a,b) - c_1(a,b)|.
+
+    c_t(a,b) = vol_t ||z_a - z_b||^2 by direct differences (Background, the
+    edge score whose row sums are Algorithm 4's node scores); omega = 1, or
+    |A1 - A0| on the common nodes when W0 and W1 are given.  Diagonal 0.
+    """
+    if map0 is not None:
+        Z0, Z1 = Z0[map0], Z1[map1]
+        if W0 is not None:
+            W0 = W0[np.ix_(map0, map0)]
+            W1 = W1[np.ix_(map1, map1)]
+    m = Z0.shape[0]
+    E = np.empty((m, m))
+    for r0 in range(0, m, block):
+        r1 = min(m, r0 + block)
+        c0 = vol0 * ((Z0[r0:r1, None, :] - Z0[None, :, :]) ** 2).sum(axis=2)
+        c1 = vol1 * ((Z1[r0:r1, None, :] - Z1[None, :, :]) ** 2).sum(axis=2)
+        e = np.abs(c0 - c1)
+        if W0 is not None:
+            e *= np.abs(W1[r0:r1] - W0[r0:r1])
+        E[r0:r1] = e
+    np.fill_diagonal(E, 0.0)
+    return E
+
+
+def top_edges(E: np.ndarray, K: int):
+    """The K largest entries of the upper triangle (a < b) of E, ordered by
+    value descending, then a, then b.  Returns (a, b, value)."""
+    a, b = np.triu_indices(E.shape[0], 1)
+    v = E[a, b]
+    order = np.lexsort((b, a, -v))[:K]
+    return a[order].astype(np.int32), b[order].astype(np.int32), v[order]
 
 
 def top_k(F: np.ndarray, K: int) -> np.ndarray:

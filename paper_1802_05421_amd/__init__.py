@@ -17,6 +17,7 @@ from .api import (  # noqa: E402,F401
     Context,
     Graph,
     SeqParams,
+    anomaly_edges,
     anomaly_scores,
     build_chain,
     build_graph,

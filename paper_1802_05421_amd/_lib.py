@@ -97,6 +97,9 @@ def load():
                                     I, d, I, P, P, sz, C.POINTER(SolveInfo)]),
         "cdl_anomaly_scores": (I, [P, P, P, P, i64, P, P, P, i64, i64, P, P, i64, I, P,
                                    C.c_int32, P, P, sz]),
+        "cdl_edges_workspace_bytes": (I, [i64, i64, C.c_int32, C.POINTER(sz)]),
+        "cdl_anomaly_edges": (I, [P, P, P, P, i64, P, P, P, i64, i64, P, P, i64, I, P,
+                                  C.c_int32, P, P, P, P, sz]),
         "cdl_sequence_workspace_bytes": (I, [C.c_int32, C.POINTER(Snapshot),
                                              C.POINTER(SeqParams), C.POINTER(sz)]),
         "cdl_score_sequence": (I, [P, C.c_int32, C.POINTER(Snapshot), C.POINTER(SeqParams),

@@ -269,6 +269,35 @@ def anomaly_scores(Z0: torch.Tensor, g0: Graph, Z1: torch.Tensor, g1: Graph,
     return F, top[:top_k]
 
 
+def anomaly_edges(Z0: torch.Tensor, g0: Graph, Z1: torch.Tensor, g1: Graph,
+                  top_k: int = 50, mode: str = "unweighted",
+                  map0: Optional[torch.Tensor] = None, map1: Optional[torch.Tensor] = None,
+                  ws: Optional[torch.Tensor] = None):
+    """Node scores and the top_k edges (a < b) by omega |c_0(a,b) - c_1(a,b)|.
+
+    Returns (F, a, b, value): F over the m common nodes, and the edges as
+    common-node index pairs sorted by descending score, ties by (a, b).
+    """
+    ctx = context(Z0.device.index)
+    k = Z0.shape[1]
+    m = map0.numel() if map0 is not None else g0.n
+    nb = C.c_size_t()
+    _check(_lib().cdl_edges_workspace_bytes(m, k, top_k, C.byref(nb)))
+    if ws is None or ws.numel() < nb.value:
+        ws = _ws(nb.value, Z0.device)
+    F = torch.empty(m, dtype=torch.float64, device=Z0.device)
+    ea = torch.empty(top_k, dtype=torch.int32, device=Z0.device)
+    eb = torch.empty(top_k, dtype=torch.int32, device=Z0.device)
+    ev = torch.empty(top_k, dtype=torch.float64, device=Z0.device)
+    weighted = mode == "delta_a"
+    _check(_lib().cdl_anomaly_edges(ctx.h, _ptr(Z0), _ptr(g0.W) if weighted else None,
+                                    _ptr(g0.stats), g0.n, _ptr(Z1),
+                                    _ptr(g1.W) if weighted else None, _ptr(g1.stats), g1.n, k,
+                                    _ptr(map0), _ptr(map1), m, L.MODE[mode], _ptr(F), top_k,
+                                    _ptr(ea), _ptr(eb), _ptr(ev), _ptr(ws), ws.numel()), ctx.h)
+    return F, ea, eb, ev
+
+
 @dataclass
 class SeqParams:
     k: int = 128

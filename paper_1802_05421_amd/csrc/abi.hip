@@ -192,6 +192,37 @@ ScoreWs plan_score(Arena &a, int64_t m, int64_t k) {
     return w;
 }
 
+struct EdgeWs {
+    ScoreWs sw;
+    double *tmax, *tau, *cval, *vals;
+    int32_t *order;
+    int64_t *cidx, *idx;
+    unsigned int *count;
+    void *tscratch, *cscratch;
+    int64_t cap;
+};
+int64_t edge_cap(int64_t m, int K) {
+    const int64_t pairs = m * (m - 1) / 2;
+    return std::min<int64_t>(std::max<int64_t>((int64_t)K * 16384, (int64_t)1 << 22), pairs);
+}
+EdgeWs plan_edges(Arena &a, int64_t m, int64_t k, int K) {
+    EdgeWs w;
+    w.sw = plan_score(a, m, k);
+    const int64_t nt2 = score_tiles_2d(pad_n(m));
+    w.tmax = a.take<double>(nt2);
+    w.order = a.take<int32_t>(std::max(K, 1));
+    w.tscratch = a.take<char>((size_t)topk_scratch_elems(nt2, K) * (2 * sizeof(double) + 2 * sizeof(int32_t)));
+    w.tau = a.take<double>(1);
+    w.count = a.take<unsigned int>(4);
+    w.cap = edge_cap(m, K);
+    w.cval = a.take<double>(w.cap);
+    w.cidx = a.take<int64_t>(w.cap);
+    w.cscratch = a.take<char>((size_t)topk_scratch_elems(w.cap, K) * (2 * sizeof(double) + 2 * sizeof(int64_t)));
+    w.vals = a.take<double>(std::max(K, 1));
+    w.idx = a.take<int64_t>(std::max(K, 1));
+    return w;
+}
+
 cdl_status fail(cdl_ctx *c, cdl_status s, const std::string &msg) {
     if (c) c->err = msg;
     return s;
@@ -782,9 +813,70 @@ cdl_status cdl_anomaly_scores(cdl_ctx *ctx, const double *Z0, const double *W0,
     hipStream_t s = ctx->stream;
     { Timed t_(ctx, "build_zhat"); HIPCHK(launch_build_zhat(Z0, Z1, map0, map1, m, mp, k, kp, stats0, stats1, w.Zh, w.Zhe, w.sq, s)); }
     { Timed t_(ctx, "score"); HIPCHK(launch_score(w.Zh, w.Zhe, kp, w.sq, m, mp, W0, pad_n(n0), W1, pad_n(n1), map0, map1,
-                        mode == CDL_SCORE_DELTA_A, w.part, s)); }
+                        mode == CDL_SCORE_DELTA_A, w.part, nullptr, s)); }
     { Timed t_(ctx, "score_reduce"); HIPCHK(launch_score_reduce(w.part, score_tiles_1d(mp), m, mp, F, s)); }
     if (top_k > 0) { Timed t_(ctx, "topk"); HIPCHK(launch_topk(F, m, top_k, w.topk, top_idx, s)); }
+    return CDL_OK;
+}
+
+cdl_status cdl_edges_workspace_bytes(int64_t m, int64_t k, int32_t top_k, size_t *bytes) {
+    if (m < 2 || m > (1 << 20) || k < 1 || top_k < 1 || top_k > CDL_MAX_TOPK ||
+        top_k > m * (m - 1) / 2 || !bytes)
+        return CDL_E_ARG;
+    Arena a(nullptr);
+    plan_edges(a, m, k, top_k);
+    *bytes = a.off;
+    return CDL_OK;
+}
+
+cdl_status cdl_anomaly_edges(cdl_ctx *ctx, const double *Z0, const double *W0,
+                             const double *stats0, int64_t n0, const double *Z1,
+                             const double *W1, const double *stats1, int64_t n1, int64_t k,
+                             const int32_t *map0, const int32_t *map1, int64_t m,
+                             cdl_score_mode mode, double *F, int32_t top_k, int32_t *edge_a,
+                             int32_t *edge_b, double *edge_val, void *ws, size_t ws_bytes) {
+    if (!ctx) return CDL_E_ARG;
+    if (n0 < 2 || n1 < 2 || m < 2 || m > std::min(n0, n1) || k < 1)
+        return fail(ctx, CDL_E_ARG, "bad sizes");
+    if (!Z0 || !Z1 || !stats0 || !stats1 || !F || !ws || !edge_a || !edge_b || !edge_val)
+        return fail(ctx, CDL_E_ARG, "null pointer");
+    if (mode != CDL_SCORE_UNWEIGHTED && mode != CDL_SCORE_DELTA_A) return fail(ctx, CDL_E_ARG, "bad mode");
+    if (mode == CDL_SCORE_DELTA_A && (!W0 || !W1)) return fail(ctx, CDL_E_ARG, "weighted mode needs W0, W1");
+    if (top_k < 1 || top_k > CDL_MAX_TOPK || top_k > m * (m - 1) / 2)
+        return fail(ctx, CDL_E_ARG, "bad top_k");
+    if (!aligned(ws, kAlign) || !aligned(Z0, 8) || !aligned(Z1, 8)) return fail(ctx, CDL_E_ARG, "misaligned pointer");
+    if ((map0 == nullptr) != (map1 == nullptr)) return fail(ctx, CDL_E_ARG, "give both maps or neither");
+    Arena need(nullptr);
+    plan_edges(need, m, k, top_k);
+    if (ws_bytes < need.off) return fail(ctx, CDL_E_WORKSPACE, "edge workspace too small");
+    HIPCHK(hipSetDevice(ctx->device));
+    cdl_status st = check_map(ctx, map0, m, n0);
+    if (st != CDL_OK) return st;
+    st = check_map(ctx, map1, m, n1);
+    if (st != CDL_OK) return st;
+    Arena a(ws);
+    EdgeWs e = plan_edges(a, m, k, top_k);
+    ScoreWs &w = e.sw;
+    const int64_t mp = pad_n(m), kp = pad_k(k);
+    const int weighted = mode == CDL_SCORE_DELTA_A;
+    hipStream_t s = ctx->stream;
+    { Timed t_(ctx, "build_zhat"); HIPCHK(launch_build_zhat(Z0, Z1, map0, map1, m, mp, k, kp, stats0, stats1, w.Zh, w.Zhe, w.sq, s)); }
+    { Timed t_(ctx, "score"); HIPCHK(launch_score(w.Zh, w.Zhe, kp, w.sq, m, mp, W0, pad_n(n0), W1, pad_n(n1), map0, map1,
+                        weighted, w.part, e.tmax, s)); }
+    { Timed t_(ctx, "score_reduce"); HIPCHK(launch_score_reduce(w.part, score_tiles_1d(mp), m, mp, F, s)); }
+    const int nt2 = score_tiles_2d(mp);
+    { Timed t_(ctx, "topk"); HIPCHK(launch_topk(e.tmax, nt2, top_k, e.tscratch, e.order, s)); }
+    { Timed t_(ctx, "edge_collect"); HIPCHK(launch_edge_collect(w.Zh, w.Zhe, kp, w.sq, m, mp, W0, pad_n(n0), W1, pad_n(n1),
+                               map0, map1, weighted, e.tmax, e.order, top_k, e.tau, e.cap,
+                               e.count, e.cval, e.cidx, s)); }
+    { Timed t_(ctx, "topk"); HIPCHK(launch_topk64(e.cval, e.cidx, e.cap, e.count, top_k, e.cscratch, edge_val, e.idx, s)); }
+    { Timed t_(ctx, "edge_split"); HIPCHK(launch_edge_split(e.idx, m, top_k, edge_a, edge_b, s)); }
+    unsigned int cnt = 0;
+    HIPCHK(hipMemcpyAsync(&cnt, e.count, sizeof(cnt), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if ((int64_t)cnt > e.cap)
+        return fail(ctx, CDL_E_UNSUPPORTED, "more than " + std::to_string(e.cap) +
+                                                " edges reach the K-th edge score (massive ties)");
     return CDL_OK;
 }
 

@@ -99,10 +99,29 @@ hipError_t launch_build_zhat(const double *Z0, const double *Z1, const int32_t *
                              int64_t kpad, const double *stats0, const double *stats1,
                              double *Zh, double *Zhe, double *sq, hipStream_t s);
 int score_tiles_1d(int64_t mpad);
+// tmax: per-tile maximum edge score (a < b), score_tiles_2d(mpad) entries,
+// or nullptr.
 hipError_t launch_score(const double *Zh, const double *Zhe, int64_t kpad, const double *sq,
                         int64_t m, int64_t mpad, const double *W0, int64_t ld0,
                         const double *W1, int64_t ld1, const int32_t *map0,
-                        const int32_t *map1, int weighted, double *part, hipStream_t s);
+                        const int32_t *map1, int weighted, double *part, double *tmax,
+                        hipStream_t s);
+int score_tiles_2d(int64_t mpad);
+// tile_order: tile indices by descending maximum (first K used); sets tau
+// and clears *count, then appends the edges with score >= tau to
+// (cval, cidx) through *count (at most cap stored).
+hipError_t launch_edge_collect(const double *Zh, const double *Zhe, int64_t kpad,
+                               const double *sq, int64_t m, int64_t mpad, const double *W0,
+                               int64_t ld0, const double *W1, int64_t ld1,
+                               const int32_t *map0, const int32_t *map1, int weighted,
+                               const double *tmax, const int32_t *tile_order, int K,
+                               double *tau, int64_t cap, unsigned int *count, double *cval,
+                               int64_t *cidx, hipStream_t s);
+hipError_t launch_edge_split(const int64_t *idx, int64_t m, int K, int32_t *a, int32_t *b,
+                             hipStream_t s);
+hipError_t launch_topk64(const double *val, const int64_t *idx, int64_t cap,
+                         const unsigned int *dcount, int K, void *scratch, double *val_out,
+                         int64_t *idx_out, hipStream_t s);
 hipError_t launch_score_reduce(const double *part, int nparts, int64_t m, int64_t mpad,
                                double *F, hipStream_t s);
 // Top-K by (descending value, ascending index); scratch holds 2 * cand_cap

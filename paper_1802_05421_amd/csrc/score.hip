@@ -11,6 +11,9 @@
 //   reduce      F_a = sum over tiles of the partials (fixed order)
 //   topk        bitonic sort of chunks in LDS, keep the best K per chunk,
 //               repeat on the candidates (order: value desc, index asc)
+//   edges       the K largest edge scores (a < b) exactly: per-tile maxima
+//               from k_score, threshold = K-th largest tile maximum, only
+//               tiles reaching it recomputed and their edges collected
 #include "common.h"
 #include "gemm.h"
 #include "kernels.h"
@@ -61,25 +64,45 @@ hipError_t launch_build_zhat(const double *Z0, const double *Z1, const int32_t *
 using ScoreCore = GemmCore<MfmaF64, 128, 128, 16, 2, 4>;
 constexpr int kScoreWM = 2, kScoreWN = 4;
 
+// Edge score omega_ab |c_0(a,b) - c_1(a,b)| of common nodes a != b from the
+// signature Gram entry G_ab (shared by the node and the edge kernels, so
+// both see bit-identical values).
+__device__ inline double edge_score(int64_t ga, int64_t gb, double G, const double *sq,
+                                    const double *W0, int64_t ld0, const double *W1,
+                                    int64_t ld1, const int32_t *map0, const int32_t *map1,
+                                    int weighted) {
+    double v = fabs(sq[ga] + sq[gb] - 2.0 * G);
+    if (weighted) {
+        const int64_t a0 = map0 ? map0[ga] : ga, b0 = map0 ? map0[gb] : gb;
+        const int64_t a1 = map1 ? map1[ga] : ga, b1 = map1 ? map1[gb] : gb;
+        v *= fabs(W1[a1 * ld1 + b1] - W0[a0 * ld0 + b0]);
+    }
+    return v;
+}
+
+// tmax != nullptr: also the largest edge score of the tile over a < b, at
+// the tile's logical index.
 __global__ __launch_bounds__(512) void k_score(const double *Zh, const double *Zhe,
                                                int64_t ldz, const double *sq, int64_t m,
                                                int64_t mpad, const double *W0, int64_t ld0,
                                                const double *W1, int64_t ld1,
                                                const int32_t *map0, const int32_t *map1,
-                                               int weighted, int nt, double *part) {
+                                               int weighted, int nt, double *part,
+                                               double *tmax) {
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
     double *smem = (double *)smem_raw;
-    __shared__ double srow[kScoreWN][128], scol[kScoreWM][128];
+    __shared__ double srow[kScoreWN][128], scol[kScoreWM][128], smax[8];
     const int total = nt * (nt + 1) / 2;
+    const int id = xcd_remap(blockIdx.x, total);
     int I, J;
-    sym_tile<8>(xcd_remap(blockIdx.x, total), nt, I, J);
+    sym_tile<8>(id, nt, I, J);
     const int64_t m0 = (int64_t)I * 128, n0 = (int64_t)J * 128;
     ScoreCore g;
     g.run(Zh, ldz, Zhe, ldz, m0, n0, ldz, smem);
 
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int wm = wid % kScoreWM, wn = wid / kScoreWM;
-    double cs[ScoreCore::WTN];
+    double cs[ScoreCore::WTN], vmax = -1.0;
 #pragma unroll
     for (int b = 0; b < ScoreCore::WTN; ++b) cs[b] = 0.0;
 #pragma unroll
@@ -94,12 +117,9 @@ __global__ __launch_bounds__(512) void k_score(const double *Zh, const double *Z
                 const int64_t gb = n0 + ScoreCore::col_of(b);
                 double v = 0.0;
                 if (ga < m && gb < m && ga != gb) {
-                    v = fabs(sq[ga] + sq[gb] - 2.0 * g.acc[a][b][rr]);
-                    if (weighted) {
-                        const int64_t a0 = map0 ? map0[ga] : ga, b0 = map0 ? map0[gb] : gb;
-                        const int64_t a1 = map1 ? map1[ga] : ga, b1 = map1 ? map1[gb] : gb;
-                        v *= fabs(W1[a1 * ld1 + b1] - W0[a0 * ld0 + b0]);
-                    }
+                    v = edge_score(ga, gb, g.acc[a][b][rr], sq, W0, ld0, W1, ld1, map0, map1,
+                                   weighted);
+                    if (ga < gb) vmax = fmax(vmax, v);
                 }
                 rs += v;
                 cs[b] += v;
@@ -115,7 +135,17 @@ __global__ __launch_bounds__(512) void k_score(const double *Zh, const double *Z
         v += __shfl_xor(v, 32);
         if (lane < 16) scol[wm][ScoreCore::col_of(b)] = v;
     }
+    if (tmax) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, o));
+        if (lane == 0) smax[wid] = vmax;
+    }
     __syncthreads();
+    if (tmax && threadIdx.x == 0) {
+        double mx = smax[0];
+        for (int q = 1; q < ScoreCore::NT / 64; ++q) mx = fmax(mx, smax[q]);
+        tmax[id] = mx;
+    }
     for (int t = threadIdx.x; t < 128; t += ScoreCore::NT) {
         double rs = 0.0, cs2 = 0.0;
 #pragma unroll
@@ -132,7 +162,8 @@ int score_tiles_1d(int64_t mpad) { return (int)(mpad / 128); }
 hipError_t launch_score(const double *Zh, const double *Zhe, int64_t kpad, const double *sq,
                         int64_t m, int64_t mpad, const double *W0, int64_t ld0,
                         const double *W1, int64_t ld1, const int32_t *map0,
-                        const int32_t *map1, int weighted, double *part, hipStream_t s) {
+                        const int32_t *map1, int weighted, double *part, double *tmax,
+                        hipStream_t s) {
     static bool attr = false;
     if (!attr) {
         hipError_t e = hipFuncSetAttribute((const void *)k_score,
@@ -144,7 +175,90 @@ hipError_t launch_score(const double *Zh, const double *Zhe, int64_t kpad, const
     const int nt = (int)(mpad / 128);
     const int total = nt * (nt + 1) / 2;
     hipLaunchKernelGGL(k_score, dim3(total), dim3(ScoreCore::NT), ScoreCore::SMEM, s, Zh, Zhe, 2 * kpad,
-                       sq, m, mpad, W0, ld0, W1, ld1, map0, map1, weighted, nt, part);
+                       sq, m, mpad, W0, ld0, W1, ld1, map0, map1, weighted, nt, part, tmax);
+    return hipGetLastError();
+}
+
+int score_tiles_2d(int64_t mpad) {
+    const int nt = (int)(mpad / 128);
+    return nt * (nt + 1) / 2;
+}
+
+// ---------------------------------------------------------------------------
+// Top edges.  The K largest tile maxima are K distinct edges, so the K-th
+// largest edge score is at least tau = the K-th largest tile maximum (when
+// there are fewer than K tiles, tau = -1 and every edge is collected).  Only tiles whose maximum reaches tau are
+// recomputed (same core, same epilogue arithmetic as k_score); their edges
+// a < b with score >= tau are appended to the candidate list.
+
+__global__ void k_edge_threshold(const double *tmax, const int32_t *tile_order, int K,
+                                 int ntiles, double *tau, unsigned int *count) {
+    if (threadIdx.x != 0) return;
+    *tau = ntiles >= K ? tmax[tile_order[K - 1]] : -1.0;
+    *count = 0;
+}
+
+__global__ __launch_bounds__(512) void k_edge_collect(
+    const double *Zh, const double *Zhe, int64_t ldz, const double *sq, int64_t m,
+    const double *W0, int64_t ld0, const double *W1, int64_t ld1, const int32_t *map0,
+    const int32_t *map1, int weighted, int nt, const double *tmax, const double *tau,
+    int64_t cap, unsigned int *count, double *cval, int64_t *cidx) {
+    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+    double *smem = (double *)smem_raw;
+    const int total = nt * (nt + 1) / 2;
+    const int id = xcd_remap(blockIdx.x, total);
+    const double th = *tau;
+    if (tmax[id] < th) return;   // uniform over the workgroup
+    int I, J;
+    sym_tile<8>(id, nt, I, J);
+    const int64_t m0 = (int64_t)I * 128, n0 = (int64_t)J * 128;
+    ScoreCore g;
+    g.run(Zh, ldz, Zhe, ldz, m0, n0, ldz, smem);
+#pragma unroll
+    for (int a = 0; a < ScoreCore::WTM; ++a)
+#pragma unroll
+        for (int rr = 0; rr < MfmaF64::R; ++rr) {
+            const int64_t ga = m0 + ScoreCore::row_of(a, rr);
+#pragma unroll
+            for (int b = 0; b < ScoreCore::WTN; ++b) {
+                const int64_t gb = n0 + ScoreCore::col_of(b);
+                if (ga < m && gb < m && ga < gb) {
+                    const double v = edge_score(ga, gb, g.acc[a][b][rr], sq, W0, ld0, W1, ld1,
+                                                map0, map1, weighted);
+                    if (v >= th) {
+                        const unsigned int q = atomicAdd(count, 1u);
+                        if ((int64_t)q < cap) {
+                            cval[q] = v;
+                            cidx[q] = ga * m + gb;
+                        }
+                    }
+                }
+            }
+        }
+}
+
+hipError_t launch_edge_collect(const double *Zh, const double *Zhe, int64_t kpad,
+                               const double *sq, int64_t m, int64_t mpad, const double *W0,
+                               int64_t ld0, const double *W1, int64_t ld1,
+                               const int32_t *map0, const int32_t *map1, int weighted,
+                               const double *tmax, const int32_t *tile_order, int K,
+                               double *tau, int64_t cap, unsigned int *count, double *cval,
+                               int64_t *cidx, hipStream_t s) {
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_edge_collect,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)ScoreCore::SMEM);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const int nt = (int)(mpad / 128);
+    const int total = nt * (nt + 1) / 2;
+    hipLaunchKernelGGL(k_edge_threshold, dim3(1), dim3(64), 0, s, tmax, tile_order, K, total, tau,
+                       count);
+    hipLaunchKernelGGL(k_edge_collect, dim3(total), dim3(ScoreCore::NT), ScoreCore::SMEM, s, Zh,
+                       Zhe, 2 * kpad, sq, m, W0, ld0, W1, ld1, map0, map1, weighted, nt, tmax,
+                       tau, cap, count, cval, cidx);
     return hipGetLastError();
 }
 
@@ -215,6 +329,98 @@ __global__ __launch_bounds__(256) void k_topk_chunk(const double *val_in, const 
 }
 
 int64_t topk_scratch_elems(int64_t m, int K) { return cdiv(m, kChunk) * (int64_t)K; }
+
+__global__ void k_edge_split(const int64_t *idx, int64_t m, int K, int32_t *a, int32_t *b) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= K) return;
+    const int64_t v = idx[t];
+    a[t] = (int32_t)(v / m);
+    b[t] = (int32_t)(v % m);
+}
+
+hipError_t launch_edge_split(const int64_t *idx, int64_t m, int K, int32_t *a, int32_t *b,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_edge_split, dim3((unsigned)cdiv(K, 256)), dim3(256), 0, s, idx, m, K, a, b);
+    return hipGetLastError();
+}
+
+// As k_topk_chunk for (value, int64 index) pairs; entries at positions >=
+// *dcount (when given) are empty.  Order: value descending, index ascending.
+__device__ inline bool before64(double va, int64_t ia, double vb, int64_t ib) {
+    return va > vb || (va == vb && ia < ib);
+}
+
+__global__ __launch_bounds__(256) void k_topk64_chunk(const double *val_in, const int64_t *idx_in,
+                                                      int64_t count, const unsigned int *dcount,
+                                                      int K, double *val_out, int64_t *idx_out) {
+    __shared__ double sv[kChunk];
+    __shared__ int64_t si[kChunk];
+    const int64_t lim = dcount ? ((int64_t)*dcount < count ? (int64_t)*dcount : count) : count;
+    const int64_t base = (int64_t)blockIdx.x * kChunk;
+    for (int t = threadIdx.x; t < kChunk; t += 256) {
+        const int64_t p = base + t;
+        if (p < lim) {
+            sv[t] = val_in[p];
+            si[t] = idx_in[p];
+        } else {
+            sv[t] = -INFINITY;
+            si[t] = INT64_MAX;
+        }
+    }
+    __syncthreads();
+    for (int size = 2; size <= kChunk; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = threadIdx.x; t < kChunk / 2; t += 256) {
+                const int lo = 2 * t - (t & (stride - 1));
+                const int hi = lo + stride;
+                const bool desc = (lo & size) == 0;
+                const bool swap = desc ? before64(sv[hi], si[hi], sv[lo], si[lo])
+                                       : before64(sv[lo], si[lo], sv[hi], si[hi]);
+                if (swap) {
+                    double tv = sv[lo]; sv[lo] = sv[hi]; sv[hi] = tv;
+                    int64_t ti = si[lo]; si[lo] = si[hi]; si[hi] = ti;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int t = threadIdx.x; t < K; t += 256) {
+        val_out[(int64_t)blockIdx.x * K + t] = sv[t];
+        idx_out[(int64_t)blockIdx.x * K + t] = si[t];
+    }
+}
+
+// Best K of `cap` candidates (count on the device); scratch holds
+// 2 * topk_scratch_elems(cap, K) doubles and as many int64.  Writes the K
+// values and indices to val_out / idx_out.
+hipError_t launch_topk64(const double *val, const int64_t *idx, int64_t cap,
+                         const unsigned int *dcount, int K, void *scratch, double *val_out,
+                         int64_t *idx_out, hipStream_t s) {
+    const int64_t sc = topk_scratch_elems(cap, K);
+    double *v[2] = {(double *)scratch, (double *)scratch + sc};
+    int64_t *ix[2] = {(int64_t *)((double *)scratch + 2 * sc), (int64_t *)((double *)scratch + 2 * sc) + sc};
+    const double *vin = val;
+    const int64_t *iin = idx;
+    const unsigned int *dc = dcount;
+    int64_t count = cap;
+    int side = 0;
+    while (true) {
+        const int64_t blocks = cdiv(count, kChunk);
+        hipLaunchKernelGGL(k_topk64_chunk, dim3((unsigned)blocks), dim3(256), 0, s, vin, iin, count,
+                           dc, K, v[side], ix[side]);
+        if (blocks == 1) break;
+        vin = v[side];
+        iin = ix[side];
+        dc = nullptr;
+        count = blocks * K;
+        side ^= 1;
+    }
+    hipError_t e = hipMemcpyAsync(val_out, v[side], sizeof(double) * K, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(idx_out, ix[side], sizeof(int64_t) * K, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
 
 hipError_t launch_topk(const double *F, int64_t m, int K, void *scratch, int32_t *out,
                        hipStream_t s) {

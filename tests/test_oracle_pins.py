@@ -335,6 +335,46 @@ def test_scores_with_exact_embeddings_equal_eq1():
     np.testing.assert_allclose(Fw, (np.abs(W1 - W0) * np.abs(C0 - C1)).sum(axis=1), rtol=1e-11)
 
 
+def test_edge_scores_sum_to_node_scores():
+    # Algorithm 4's node score is the row sum of the edge scores; the two are
+    # computed independently (direct differences here, the C row loops for
+    # the node scores).
+    n = 40
+    W0 = random_dense_graph(n, 50)
+    W1 = random_dense_graph(n, 51)
+    Z0 = oracle.solve_embedding(W0, oracle.rhs(W0, 12, 4))
+    Z1 = oracle.solve_embedding(W1, oracle.rhs(W1, 12, 4))
+    E = oracle.edge_scores(Z0, W0.sum(), Z1, W1.sum())
+    np.testing.assert_allclose(E, E.T, rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(E.sum(axis=1), oracle.scores(Z0, W0.sum(), Z1, W1.sum()), rtol=1e-12)
+    Ew = oracle.edge_scores(Z0, W0.sum(), Z1, W1.sum(), W0, W1)
+    np.testing.assert_allclose(Ew.sum(axis=1), oracle.scores(Z0, W0.sum(), Z1, W1.sum(), W0, W1), rtol=1e-12)
+    perm = np.random.default_rng(1).permutation(n)[:25]
+    Em = oracle.edge_scores(Z0, W0.sum(), Z1, W1.sum(), map0=perm, map1=perm)
+    np.testing.assert_allclose(Em, E[np.ix_(perm, perm)], rtol=1e-13, atol=1e-12)
+
+
+def test_edge_scores_with_exact_embeddings_equal_eq1():
+    n = 9
+    W0 = random_dense_graph(n, 60)
+    W1 = random_dense_graph(n, 61)
+    Z0, *_ = edge_embedding(W0)
+    Z1, *_ = edge_embedding(W1)
+    C0, C1 = oracle.exact_commute_times(W0), oracle.exact_commute_times(W1)
+    E = oracle.edge_scores(Z0, W0.sum(), Z1, W1.sum())
+    np.testing.assert_allclose(E, np.abs(C0 - C1), rtol=1e-10, atol=1e-10)
+
+
+def test_top_edges_order_and_ties():
+    E = np.zeros((5, 5))
+    E[1, 3] = E[3, 1] = 2.0
+    E[0, 4] = E[4, 0] = 2.0
+    E[2, 3] = E[3, 2] = 5.0
+    a, b, v = oracle.top_edges(E, 4)
+    assert list(zip(a.tolist(), b.tolist())) == [(2, 3), (0, 4), (1, 3), (0, 1)]
+    assert v.tolist() == [5.0, 2.0, 2.0, 0.0]
+
+
 def test_weighted_scores_single_changed_edge():
     # Only one edge changes weight: only its two end nodes score, equally.
     n = 10
