@@ -281,6 +281,19 @@ def main():
                   "top50_equal_to_timed_step": bool(torch.equal(Tb[args.mixed], top_ref))}
     log("two-stream pair: %.2f ms" % (ms_conc * 1e3))
 
+    # Edge-level output for the same pair: top-50 edges (exact).
+    ews = None
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Fe, ea, eb, ev = cdl.anomaly_edges(Zb[args.mixed][0], graphs[0], Zb[args.mixed][1], graphs[1],
+                                           top_k=50, ws=ews)
+        torch.cuda.synchronize()
+        ms_edges = time.perf_counter() - t0
+    edges = {"ms": round(ms_edges * 1e3, 3), "top_k": 50,
+             "best": [int(ea[0]), int(eb[0]), float(ev[0])]}
+    log("top-50 edges: %.2f ms" % (ms_edges * 1e3))
+
     # Amortised sequence pair: in a sequence every snapshot is embedded once,
     # so one new pair costs one graph + chain + solve and one score.
     def seq_step(prec, t):
@@ -324,6 +337,42 @@ def main():
                     "max_iterations": sinfo.max_iterations,
                     "max_rel_residual": sinfo.max_rel_residual}
         log("sequence: %d pairs in %.1f ms" % (sinfo.pairs, ms_seq * 1e3))
+        # The same sequence enqueued with no host reads, then replayed as a HIP
+        # graph: every chain at the depth the adaptive rule gives the largest
+        # snapshot, every solve at the largest iteration count above; the
+        # library rejects the call if any final residual stays above 1e-8.
+        big = max(range(len(Xs)), key=lambda t: Xs[t].shape[0])
+        gb = cdl.build_graph(Xs[big])
+        dfix = cdl.build_chain(gb, prec=args.mixed, depth=0, depth_max=DMAX).depth
+        del gb
+        gdev = [g.to(dev) for g in gids]
+        iters = sinfo.max_iterations
+        for attempt in range(3):
+            spa = cdl.SeqParams(k=128, seed=seed, prec=args.mixed, depth=dfix, tol=1e-8,
+                                max_iter=iters, top_k=50, asynchronous=True)
+            try:
+                sws = torch.empty(cdl.sequence_workspace_bytes(Xs, gdev, spa), dtype=torch.uint8,
+                                  device=dev)
+                Fa, ta, ainfo = cdl.score_sequence(Xs, gdev, spa, ws=sws)   # eager enqueue
+                break
+            except cdl.CdlError as e:
+                log("async sequence at %d iterations: %s" % (iters, e))
+                iters += 2
+        Fa, ta, ainfo = cdl.score_sequence(Xs, gdev, spa, ws=sws, out=(Fa, ta))   # capture
+        torch.cuda.synchronize()
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            Fa, ta, ainfo = cdl.score_sequence(Xs, gdev, spa, ws=sws, out=(Fa, ta))
+        torch.cuda.synchronize()
+        ms_graph = (time.perf_counter() - t0) / reps
+        sequence["graph_replay"] = {"ms_per_sequence": round(ms_graph * 1e3, 2),
+                                    "pairs_per_s": round(ainfo.pairs / ms_graph, 2),
+                                    "chain_depth": dfix, "iterations": iters,
+                                    "graph_launches": ainfo.graph_launches,
+                                    "max_rel_residual": ainfo.max_rel_residual}
+        log("sequence as a graph replay: %.1f ms (depth %d, %d iterations)" % (ms_graph * 1e3, dfix, iters))
+        del sws
 
     # dominant kernel of the mixed step
     modeled = {nm: v for nm, v in times_mixed.items() if kernel_model(nm, n, k, T, args.mixed)}
@@ -358,6 +407,7 @@ def main():
                                     for nm, v in sorted(res[p][2].items(), key=lambda x: -x[1][1])}
                                 for p in precs},
         "concurrent_snapshots": concurrent,
+        "edges_top50": edges,
         "amortized_sequence_pair": amortized,
         "sequence_c4": sequence,
         "cpu_baseline": cpu,

@@ -121,12 +121,22 @@ typedef struct {
     int max_iter;
     cdl_score_mode mode;
     int32_t top_k;
+    int32_t flags;             /* 0, or CDL_SEQ_ASYNC */
 } cdl_seq_params;
+
+/* cdl_seq_params.flags: enqueue the whole sequence with no host reads
+ * between kernels (fixed depth, Richardson with exactly max_iter
+ * iterations, every pair's common-node map uploaded first); one read-back
+ * at the end checks every graph and residual.  A call whose buffers, sizes,
+ * parameters and global ids equal the previous async call on the context is
+ * captured into a HIP graph; later such calls replay it. */
+#define CDL_SEQ_ASYNC 1
 
 typedef struct {
     int32_t pairs;             /* number of scored pairs (n_snap - 1) */
     int32_t max_iterations;    /* largest iteration count over the solves */
     double max_rel_residual;   /* largest final residual over the solves */
+    int32_t graph_launches;    /* CDL_SEQ_ASYNC: 1 if the call ran as a HIP graph */
 } cdl_seq_info;
 
 /* ---- context --------------------------------------------------------- */
@@ -344,7 +354,13 @@ cdl_status cdl_anomaly_edges(cdl_ctx *ctx, const double *Z0, const double *W0,
  *               ascending global-id order.
  *   top_idx[t]  device output for pair t: top_k int32 indices into F[t].
  *   ws          device workspace of cdl_sequence_workspace_bytes().
- * Syncs.  Errors as for the per-snapshot calls. */
+ * Syncs.  Errors as for the per-snapshot calls.  With CDL_SEQ_ASYNC: needs
+ * depth > 0, CDL_RICHARDSON and tol >= 0 (CDL_E_ARG otherwise); the results
+ * equal the synchronous call with tol = 0 and the same depth and max_iter;
+ * tol > 0 turns a final residual above tol into CDL_E_NOCONV, after the
+ * outputs are written.  A graph replay reuses the call's device pointers: the
+ * snapshot series and outputs are read and written where they were when the
+ * graph was captured.  Concurrent calls on one context race. */
 cdl_status cdl_sequence_workspace_bytes(int32_t n_snap, const cdl_snapshot *snaps,
                                         const cdl_seq_params *p, size_t *bytes);
 cdl_status cdl_score_sequence(cdl_ctx *ctx, int32_t n_snap, const cdl_snapshot *snaps,

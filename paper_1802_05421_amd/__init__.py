@@ -27,6 +27,7 @@ from .api import (  # noqa: E402,F401
     level,
     level_scale,
     score_sequence,
+    sequence_workspace_bytes,
     set_solve_depth,
     set_timing,
     timing,

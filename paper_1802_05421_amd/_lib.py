@@ -43,12 +43,13 @@ class SeqParams(C.Structure):
     _fields_ = [("k", C.c_int64), ("seed", C.c_uint64), ("sigma", C.c_double),
                 ("prec", C.c_int), ("depth", C.c_int), ("depth_max", C.c_int),
                 ("chain_eps", C.c_double), ("solver", C.c_int), ("tol", C.c_double),
-                ("max_iter", C.c_int), ("mode", C.c_int), ("top_k", C.c_int32)]
+                ("max_iter", C.c_int), ("mode", C.c_int), ("top_k", C.c_int32),
+                ("flags", C.c_int32)]
 
 
 class SeqInfo(C.Structure):
     _fields_ = [("pairs", C.c_int32), ("max_iterations", C.c_int32),
-                ("max_rel_residual", C.c_double)]
+                ("max_rel_residual", C.c_double), ("graph_launches", C.c_int32)]
 
 
 class CdlError(RuntimeError):

@@ -312,13 +312,13 @@ class SeqParams:
     max_iter: int = 30
     mode: str = "unweighted"
     top_k: int = 50
+    # No host reads inside the sequence (fixed depth, exactly max_iter
+    # Richardson steps); a repeat of the previous call replays a HIP graph.
+    asynchronous: bool = False
 
 
-def score_sequence(Xs: Sequence[torch.Tensor], gids: Sequence[torch.Tensor], p: SeqParams,
-                   ws: Optional[torch.Tensor] = None):
-    """Scores of every consecutive pair of snapshots (common global ids)."""
+def _seq_args(Xs, gids, p: SeqParams):
     dev = Xs[0].device
-    ctx = context(dev.index)
     n_snap = len(Xs)
     gid_host = [g.cpu().to(torch.int32).contiguous() for g in gids]
     gid_dev = [g.to(device=dev, dtype=torch.int32).contiguous() for g in gids]
@@ -331,17 +331,43 @@ def score_sequence(Xs: Sequence[torch.Tensor], gids: Sequence[torch.Tensor], p: 
         snaps[t].gid_host = gid_host[t].data_ptr()
     q = L.SeqParams(k=p.k, seed=p.seed, sigma=p.sigma, prec=L.PREC[p.prec], depth=p.depth,
                     depth_max=p.depth_max, chain_eps=p.chain_eps, solver=L.SOLVER[p.solver],
-                    tol=p.tol, max_iter=p.max_iter, mode=L.MODE[p.mode], top_k=p.top_k)
+                    tol=p.tol, max_iter=p.max_iter, mode=L.MODE[p.mode], top_k=p.top_k,
+                    flags=1 if p.asynchronous else 0)
+    return snaps, q, gid_host, gid_dev
+
+
+def sequence_workspace_bytes(Xs: Sequence[torch.Tensor], gids: Sequence[torch.Tensor],
+                             p: SeqParams) -> int:
+    snaps, q, _, _ = _seq_args(Xs, gids, p)
+    nb = C.c_size_t()
+    _check(_lib().cdl_sequence_workspace_bytes(len(Xs), snaps, C.byref(q), C.byref(nb)))
+    return nb.value
+
+
+def score_sequence(Xs: Sequence[torch.Tensor], gids: Sequence[torch.Tensor], p: SeqParams,
+                   ws: Optional[torch.Tensor] = None, out=None):
+    """Scores of every consecutive pair of snapshots (common global ids).
+
+    out: (Fs, tops) from an earlier call with the same snapshots, written in
+    place (an asynchronous repeat then replays its graph)."""
+    dev = Xs[0].device
+    ctx = context(dev.index)
+    n_snap = len(Xs)
+    snaps, q, gid_host, gid_dev = _seq_args(Xs, gids, p)
     nb = C.c_size_t()
     _check(_lib().cdl_sequence_workspace_bytes(n_snap, snaps, C.byref(q), C.byref(nb)))
     if ws is None or ws.numel() < nb.value:
         ws = _ws(nb.value, dev)
-    Fs, tops = [], []
-    for t in range(n_snap - 1):
-        a = set(gid_host[t].tolist())
-        m = sum(1 for v in gid_host[t + 1].tolist() if v in a)
-        Fs.append(torch.empty(m, dtype=torch.float64, device=dev))
-        tops.append(torch.empty(max(1, min(p.top_k, m)), dtype=torch.int32, device=dev))
+    if out is not None:
+        Fs, tops = out
+        tops = [t._base if t._base is not None else t for t in tops]
+    else:
+        Fs, tops = [], []
+        for t in range(n_snap - 1):
+            a = set(gid_host[t].tolist())
+            m = sum(1 for v in gid_host[t + 1].tolist() if v in a)
+            Fs.append(torch.empty(m, dtype=torch.float64, device=dev))
+            tops.append(torch.empty(max(1, min(p.top_k, m)), dtype=torch.int32, device=dev))
     Fp = (C.c_void_p * (n_snap - 1))(*[f.data_ptr() for f in Fs])
     Tp = (C.c_void_p * (n_snap - 1))(*[t.data_ptr() for t in tops])
     info = L.SeqInfo()

@@ -30,6 +30,11 @@ struct cdl_ctx {
     std::vector<hipEvent_t> pool;
     std::map<std::string, std::pair<int64_t, double>> totals;
     std::vector<std::string> names;   // stable order for cdl_timing_read
+    // Asynchronous sequences: the last call's key and, once the same call
+    // has been seen twice, its captured graph.
+    std::vector<uint64_t> seq_key;
+    hipGraph_t seq_graph = nullptr;
+    hipGraphExec_t seq_exec = nullptr;
 };
 
 namespace {
@@ -235,6 +240,59 @@ cdl_status fail(cdl_ctx *c, cdl_status s, const std::string &msg) {
             return fail(ctx, CDL_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+// Stream-ordered graph construction (arguments already checked).
+cdl_status graph_enqueue(cdl_ctx *ctx, const double *X, int64_t n, int64_t T, int64_t ldx,
+                         double sigma, double *W, double *deg, double *stats, void *ws) {
+    Arena a(ws);
+    GraphWs w = plan_graph(a, n, T);
+    const int64_t ld = pad_n(n), Tp = pad_t(T);
+    hipStream_t s = ctx->stream;
+    { Timed t_(ctx, "fill_zero"); HIPCHK(launch_fill_zero(w.flags, 256, s)); }
+    { Timed t_(ctx, "pad_series"); HIPCHK(launch_pad_series(X, n, T, ldx, w.Xp, ld, Tp, w.sqn, w.flags, s)); }
+    if (sigma <= 0.0) { Timed t_(ctx, "select_median"); HIPCHK(launch_select_reset(w.sel, s)); }
+    { Timed t_(ctx, "gram_dist"); HIPCHK(launch_gram_dist(w.Xp, Tp, w.sqn, n, ld, W, sigma > 0.0 ? nullptr : w.sel, s)); }
+    if (sigma > 0.0)
+        { Timed t_(ctx, "set_sigma"); HIPCHK(launch_set_sigma(sigma, stats, s)); }
+    else
+        { Timed t_(ctx, "select_median"); HIPCHK(launch_select_median(W, ld, n, w.sel, stats, s)); }
+    { Timed t_(ctx, "exp_degree"); HIPCHK(launch_exp_degree(W, ld, n, stats, deg, w.dpart, s)); }
+    { Timed t_(ctx, "graph_stats"); HIPCHK(launch_graph_stats(deg, n, stats, s)); }
+    return CDL_OK;
+}
+
+// Xdst += P1 r, P1 = D^{-1/2} prod_{l<D} (I + S~^{2^l}) D^{-1/2}, for the
+// operand V = D^{-1/2} r left in V64 / Vlo[0] by the residual step (FP16: the
+// scaled copy is made here).  Levels l >= d are applied as 2^(l-d+1)
+// repetitions of the last stored level.  Stream-ordered, no host reads.
+cdl_status precondition_enqueue(cdl_ctx *ctx, int prec, int d, int D, const SolveWs &w,
+                                const ChainBuf &c, int64_t ld, int64_t n, int64_t kp,
+                                bool scaled, const double *inv_vs, double *Xdst) {
+    hipStream_t s = ctx->stream;
+    if (scaled) { Timed t_(ctx, "prep_v"); HIPCHK(launch_prep_v2(prec, w.Rt, c.dm, ld, kp, w.scal + kp, w.V64, w.Vlo[0], s)); }
+    int cur = 0;
+    for (int l = 0; l < std::min(d, D); ++l) {
+        const bool last = l + 1 == D;
+        { Timed t_(ctx, "apply"); HIPCHK(launch_apply(prec, w.Vlo[cur], c.levels + c.level_bytes * l, w.Vlo[cur ^ 1],
+                            w.V64, ld, n, kp, Xdst, c.dm, last ? inv_vs : nullptr, (float *)w.part, 1, s)); }
+        cur ^= 1;
+    }
+    for (int l = d; l < D; ++l) {
+        const int m = 1 << (l - d + 1);
+        const void *src = w.Vlo[cur];
+        for (int q = 0; q < m; ++q) {
+            void *dst = w.Vlo[2 + (q & 1)];
+            { Timed t_(ctx, "apply"); HIPCHK(launch_apply(prec, src, c.levels + c.level_bytes * (d - 1), dst, w.T64,
+                                ld, n, kp, Xdst, c.dm, nullptr, (float *)w.part, 0, s)); }
+            src = dst;
+        }
+        const bool last = l + 1 == D;
+        { Timed t_(ctx, "axpy_v"); HIPCHK(launch_axpy_v(prec, w.T64, ld, kp, w.V64, w.Vlo[cur ^ 1], Xdst, c.dm,
+                             last ? inv_vs : nullptr, s)); }
+        cur ^= 1;
+    }
+    return CDL_OK;
+}
+
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 bool valid_prec(int p) { return p >= 0 && p <= 3; }
 
@@ -370,6 +428,8 @@ cdl_status cdl_ctx_destroy(cdl_ctx *ctx) {
         (void)hipEventDestroy(r.b);
     }
     for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
+    if (ctx->seq_exec) (void)hipGraphExecDestroy(ctx->seq_exec);
+    if (ctx->seq_graph) (void)hipGraphDestroy(ctx->seq_graph);
     delete ctx;
     return CDL_OK;
 }
@@ -456,22 +516,8 @@ cdl_status cdl_build_graph(cdl_ctx *ctx, const double *X, int64_t n, int64_t T, 
     Arena need(nullptr);
     plan_graph(need, n, T);
     if (ws_bytes < need.off) return fail(ctx, CDL_E_WORKSPACE, "graph workspace too small");
-    Arena a(ws);
-    GraphWs w = plan_graph(a, n, T);
-    const int64_t ld = pad_n(n), Tp = pad_t(T);
-    hipStream_t s = ctx->stream;
     HIPCHK(hipSetDevice(ctx->device));
-    { Timed t_(ctx, "fill_zero"); HIPCHK(launch_fill_zero(w.flags, 256, s)); }
-    { Timed t_(ctx, "pad_series"); HIPCHK(launch_pad_series(X, n, T, ldx, w.Xp, ld, Tp, w.sqn, w.flags, s)); }
-    if (sigma <= 0.0) { Timed t_(ctx, "select_median"); HIPCHK(launch_select_reset(w.sel, s)); }
-    { Timed t_(ctx, "gram_dist"); HIPCHK(launch_gram_dist(w.Xp, Tp, w.sqn, n, ld, W, sigma > 0.0 ? nullptr : w.sel, s)); }
-    if (sigma > 0.0)
-        { Timed t_(ctx, "set_sigma"); HIPCHK(launch_set_sigma(sigma, stats, s)); }
-    else
-        { Timed t_(ctx, "select_median"); HIPCHK(launch_select_median(W, ld, n, w.sel, stats, s)); }
-    { Timed t_(ctx, "exp_degree"); HIPCHK(launch_exp_degree(W, ld, n, stats, deg, w.dpart, s)); }
-    { Timed t_(ctx, "graph_stats"); HIPCHK(launch_graph_stats(deg, n, stats, s)); }
-    return CDL_OK;
+    return graph_enqueue(ctx, X, n, T, ldx, sigma, W, deg, stats, ws);
 }
 
 cdl_status cdl_check_graph(cdl_ctx *ctx, const double *deg, const double *stats, int64_t n,
@@ -672,34 +718,8 @@ cdl_status cdl_solve_embedding(cdl_ctx *ctx, const double *W, const double *deg,
         return ctx->solve_depth > 0 ? ctx->solve_depth
                                     : (tol == 0.0 ? d : choose_depth(prec, n, k, d, rho_model, target / rel));
     };
-    // Xdst += P1 r, P1 = D^{-1/2} prod_{l<D} (I + S~^{2^l}) D^{-1/2}, for the
-    // operand V = D^{-1/2} r left in V64 / Vlo[0] by the residual step (FP16:
-    // the scaled copy is made here).  Levels l >= d are applied as
-    // 2^(l-d+1) repetitions of the last stored level.
     auto precondition = [&](int D, double *Xdst) -> cdl_status {
-        if (scaled) { Timed t_(ctx, "prep_v"); HIPCHK(launch_prep_v2(prec, w.Rt, c.dm, ld, kp, w.scal + kp, w.V64, w.Vlo[0], s)); }
-        int cur = 0;
-        for (int l = 0; l < std::min(d, D); ++l) {
-            const bool last = l + 1 == D;
-            { Timed t_(ctx, "apply"); HIPCHK(launch_apply(prec, w.Vlo[cur], c.levels + c.level_bytes * l, w.Vlo[cur ^ 1],
-                                w.V64, ld, n, kp, Xdst, c.dm, last ? inv_vs : nullptr, (float *)w.part, 1, s)); }
-            cur ^= 1;
-        }
-        for (int l = d; l < D; ++l) {
-            const int m = 1 << (l - d + 1);
-            const void *src = w.Vlo[cur];
-            for (int q = 0; q < m; ++q) {
-                void *dst = w.Vlo[2 + (q & 1)];
-                { Timed t_(ctx, "apply"); HIPCHK(launch_apply(prec, src, c.levels + c.level_bytes * (d - 1), dst, w.T64,
-                                    ld, n, kp, Xdst, c.dm, nullptr, (float *)w.part, 0, s)); }
-                src = dst;
-            }
-            const bool last = l + 1 == D;
-            { Timed t_(ctx, "axpy_v"); HIPCHK(launch_axpy_v(prec, w.T64, ld, kp, w.V64, w.Vlo[cur ^ 1], Xdst, c.dm,
-                                 last ? inv_vs : nullptr, s)); }
-            cur ^= 1;
-        }
-        return CDL_OK;
+        return precondition_enqueue(ctx, prec, d, D, w, c, ld, n, kp, scaled, inv_vs, Xdst);
     };
     // max_r ||r_r|| / ||y_r|| after the norms kernel; syncs.
     auto residual_check = [&]() -> cdl_status {
@@ -886,16 +906,82 @@ cdl_status cdl_anomaly_edges(cdl_ctx *ctx, const double *Z0, const double *W0,
 
 namespace {
 struct SeqPlan {
-    int64_t nmax = 0, Tmax = 0, mmax = 0;
+    int64_t nmax = 0, Tmax = 0, mmax = 0, ntot = 0, nsnap = 0;
 };
 SeqPlan seq_plan(int32_t n_snap, const cdl_snapshot *sn) {
     SeqPlan p;
     for (int t = 0; t < n_snap; ++t) {
         p.nmax = std::max(p.nmax, sn[t].n);
         p.Tmax = std::max(p.Tmax, sn[t].T);
+        p.ntot += sn[t].n;
     }
     p.mmax = p.nmax;
+    p.nsnap = n_snap;
     return p;
+}
+
+// Common nodes of snapshots y and x (ascending global id): row indices.
+void common_maps(const cdl_snapshot &y, const cdl_snapshot &x, std::vector<int32_t> &m0,
+                 std::vector<int32_t> &m1) {
+    m0.clear();
+    m1.clear();
+    int64_t i = 0, j = 0;
+    while (i < y.n && j < x.n) {
+        if (y.gid_host[i] == x.gid_host[j]) { m0.push_back((int32_t)i); m1.push_back((int32_t)j); ++i; ++j; }
+        else if (y.gid_host[i] < x.gid_host[j]) ++i;
+        else ++j;
+    }
+}
+
+// Chain with a fixed number of levels, no host reads.
+cdl_status chain_enqueue(cdl_ctx *ctx, const double *W, const double *deg, const double *stats,
+                         int64_t n, int prec, int depth, void *chain) {
+    Arena a(chain);
+    ChainBuf c = plan_chain(a, n, prec, depth);
+    const int64_t ld = pad_n(n);
+    hipStream_t s = ctx->stream;
+    { Timed t_(ctx, "chain_prep"); HIPCHK(launch_chain_prep(deg, stats, n, ld, 0, c.dmn, c.dm, c.u, s)); }
+    { Timed t_(ctx, "normalize"); HIPCHK(launch_normalize(prec, W, ld, n, c.dmn, c.u, 0, c.levels, c.fro, c.fro64, s)); }
+    for (int l = 0; l + 1 < depth; ++l) {
+        Timed t_(ctx, "square");
+        HIPCHK(launch_square(prec, c.levels + c.level_bytes * l, c.levels + c.level_bytes * (l + 1), ld, n, c.fro, s));
+    }
+    return CDL_OK;
+}
+
+// Richardson with exactly `iters` applications of the full stored chain, no
+// host reads: the same kernels, in the same order, as cdl_solve_embedding
+// with tol = 0.  ||y_r|| and the final ||r_r|| go to ynorm / rnorm (device).
+cdl_status solve_enqueue_fixed(cdl_ctx *ctx, const double *W, const double *deg,
+                               const int32_t *gid, int64_t n, const void *chain, int prec,
+                               int depth, int64_t k, uint64_t seed, int iters, double *Z,
+                               void *ws, double *ynorm, double *rnorm) {
+    Arena a(ws);
+    SolveWs w = plan_solve(a, n, k, prec);
+    Arena ac((void *)chain);
+    ChainBuf c = plan_chain(ac, n, prec, depth);
+    const int64_t ld = pad_n(n), kp = pad_k(k);
+    const size_t panel = (size_t)kp * ld;
+    hipStream_t s = ctx->stream;
+    const int nparts = residual_parts(ld), ntiles = residual_tiles(ld, kp);
+    const bool scaled = prec == 3;
+    { Timed t_(ctx, "fill_zero"); HIPCHK(launch_fill_zero(w.Yt, panel * sizeof(double), s)); }
+    { Timed t_(ctx, "fill_zero"); HIPCHK(launch_fill_zero(w.Xt, panel * sizeof(double), s)); }
+    { Timed t_(ctx, "rhs"); HIPCHK(launch_rhs(W, ld, n, gid, k, kp, seed, w.Yt, s)); }
+    { Timed t_(ctx, "residual_init"); HIPCHK(launch_residual_k(prec, w.Xt, W, w.Yt, deg, c.dm, ld, n, kp, k, 1, (double *)w.part, w.Rt, w.V64, w.Vlo[0], w.npart, w.mpart, s)); }
+    { Timed t_(ctx, "col_norms"); HIPCHK(launch_col_norms2(w.npart, nparts, kp, w.mpart, ntiles, scaled, w.scal, s)); }
+    HIPCHK(hipMemcpyAsync(ynorm, w.scal, kp * sizeof(double), hipMemcpyDeviceToDevice, s));
+    const double *inv_vs = w.scal + kp + 1;
+    for (int it = 0; it < iters; ++it) {
+        cdl_status st = precondition_enqueue(ctx, prec, depth, depth, w, c, ld, n, kp, scaled, inv_vs, w.Xt);
+        if (st != CDL_OK) return st;
+        { Timed t_(ctx, "residual"); HIPCHK(launch_residual_k(prec, w.Xt, W, w.Yt, deg, c.dm, ld, n, kp, k, 0, (double *)w.part, w.Rt,
+                                 w.V64, w.Vlo[0], w.npart, w.mpart, s)); }
+        { Timed t_(ctx, "col_norms"); HIPCHK(launch_col_norms2(w.npart, nparts, kp, w.mpart, ntiles, scaled, w.scal, s)); }
+    }
+    HIPCHK(hipMemcpyAsync(rnorm, w.scal, kp * sizeof(double), hipMemcpyDeviceToDevice, s));
+    { Timed t_(ctx, "finalize_z"); HIPCHK(launch_finalize_z2(w.Xt, ld, n, kp, k, w.mean, Z, s)); }
+    return CDL_OK;
 }
 size_t seq_bytes(const SeqPlan &p, const cdl_seq_params *q) {
     const int dmax = q->depth > 0 ? q->depth : q->depth_max;
@@ -909,6 +995,8 @@ size_t seq_bytes(const SeqPlan &p, const cdl_seq_params *q) {
     tot += 2 * al((size_t)p.nmax * q->k * sizeof(double));       // Z ping-pong
     tot += 2 * al((size_t)p.mmax * sizeof(int32_t));             // maps
     tot += g + c + so + sc;
+    tot += 2 * al((size_t)p.ntot * sizeof(int32_t));             // all pair maps (async)
+    tot += al((size_t)p.nsnap * (CDL_GRAPH_STATS + 2 * pad_k(q->k)) * sizeof(double));   // status
     return tot;
 }
 } // namespace
@@ -940,6 +1028,24 @@ cdl_status cdl_score_sequence(cdl_ctx *ctx, int32_t n_snap, const cdl_snapshot *
     }
     const SeqPlan plan = seq_plan(n_snap, sn);
     if (ws_bytes < seq_bytes(plan, q)) return fail(ctx, CDL_E_WORKSPACE, "sequence workspace too small");
+    const bool async = (q->flags & CDL_SEQ_ASYNC) != 0;
+    if (async) {
+        // the enqueue helpers check nothing: every argument is checked here
+        if (q->depth < 1 || q->depth > CDL_MAX_DEPTH || q->solver != CDL_RICHARDSON || !(q->tol >= 0.0))
+            return fail(ctx, CDL_E_ARG, "CDL_SEQ_ASYNC needs 1 <= depth <= 14, Richardson and tol >= 0");
+        if (q->k < 1 || q->k > ((int64_t)1 << 20) || !valid_prec(q->prec) || q->max_iter < 1 ||
+            q->max_iter > 64 || (q->mode != CDL_SCORE_UNWEIGHTED && q->mode != CDL_SCORE_DELTA_A) ||
+            q->top_k < 0 || q->top_k > CDL_MAX_TOPK || !std::isfinite(q->sigma))
+            return fail(ctx, CDL_E_ARG, "bad sequence parameters");
+        if (!aligned(ws, kAlign)) return fail(ctx, CDL_E_ARG, "misaligned workspace");
+        for (int t = 0; t < n_snap; ++t) {
+            if (sn[t].n > (1 << 20) || sn[t].T < 1 || sn[t].ldx < sn[t].T || !aligned(sn[t].X, 8) ||
+                !aligned(sn[t].gid, 4))
+                return fail(ctx, CDL_E_ARG, "bad snapshot");
+            if (t + 1 < n_snap && (!F[t] || !aligned(F[t], 8) || (q->top_k > 0 && top_idx && !top_idx[t])))
+                return fail(ctx, CDL_E_ARG, "bad output pointer");
+        }
+    }
     const int dmax = q->depth > 0 ? q->depth : q->depth_max;
     size_t gB = 0, cB = 0, soB = 0, scB = 0;
     cdl_workspace_bytes(plan.nmax, plan.Tmax, q->k, dmax, q->prec, &gB, &cB, &soB, &scB);
@@ -951,6 +1057,147 @@ cdl_status cdl_score_sequence(cdl_ctx *ctx, int32_t n_snap, const cdl_snapshot *
     double *Zb[2] = {a.take<double>((size_t)plan.nmax * q->k), a.take<double>((size_t)plan.nmax * q->k)};
     int32_t *mapb[2] = {a.take<int32_t>(plan.mmax), a.take<int32_t>(plan.mmax)};
     char *gws = a.take<char>(gB), *cws = a.take<char>(cB), *sows = a.take<char>(soB), *scws = a.take<char>(scB);
+    int32_t *maps_all = a.take<int32_t>(2 * (size_t)plan.ntot);
+    const int64_t kp = pad_k(q->k);
+    double *status = a.take<double>((size_t)n_snap * (CDL_GRAPH_STATS + 2 * kp));
+    if (async) {
+        if (info) std::memset(info, 0, sizeof(*info));
+        hipStream_t s = ctx->stream;
+        HIPCHK(hipSetDevice(ctx->device));
+        // all common-node maps, uploaded before anything is enqueued
+        std::vector<int32_t> hm, m0, m1;
+        std::vector<int64_t> moff(n_snap, 0), mcnt(n_snap, 0);
+        for (int t = 1; t < n_snap; ++t) {
+            common_maps(sn[t - 1], sn[t], m0, m1);
+            if ((int64_t)m0.size() < 2) return fail(ctx, CDL_E_GRAPH, "consecutive snapshots share fewer than two nodes");
+            moff[t] = (int64_t)hm.size();
+            mcnt[t] = (int64_t)m0.size();
+            hm.insert(hm.end(), m0.begin(), m0.end());
+            hm.insert(hm.end(), m1.begin(), m1.end());
+        }
+        HIPCHK(hipMemcpyAsync(maps_all, hm.data(), hm.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+        // the key of this call: buffers, shapes, parameters, global ids
+        std::vector<uint64_t> key = {(uint64_t)n_snap, (uint64_t)(uintptr_t)ws, (uint64_t)ws_bytes,
+                                     (uint64_t)q->k, q->seed, (uint64_t)q->prec, (uint64_t)q->depth,
+                                     (uint64_t)q->max_iter, (uint64_t)q->mode, (uint64_t)q->top_k};
+        uint64_t sb;
+        std::memcpy(&sb, &q->sigma, sizeof(sb));
+        key.push_back(sb);
+        for (int t = 0; t < n_snap; ++t) {
+            uint64_t h = 1469598103934665603ull;
+            for (int64_t i = 0; i < sn[t].n; ++i) h = (h ^ (uint32_t)sn[t].gid_host[i]) * 1099511628211ull;
+            key.insert(key.end(), {(uint64_t)(uintptr_t)sn[t].X, (uint64_t)sn[t].n, (uint64_t)sn[t].T,
+                                   (uint64_t)sn[t].ldx, (uint64_t)(uintptr_t)sn[t].gid, h,
+                                   (uint64_t)(uintptr_t)(t + 1 < n_snap ? F[t] : nullptr),
+                                   (uint64_t)(uintptr_t)(t + 1 < n_snap && top_idx ? top_idx[t] : nullptr)});
+        }
+        auto enqueue = [&]() -> cdl_status {
+            hipStream_t es = ctx->stream;   // the capture stream while capturing
+            for (int t = 0; t < n_snap; ++t) {
+                const int b = t & 1;
+                const cdl_snapshot &x = sn[t];
+                cdl_status st = graph_enqueue(ctx, x.X, x.n, x.T, x.ldx, q->sigma, Wb[b], degb[b], stb[b], gws);
+                if (st != CDL_OK) return st;
+                double *stat_t = status + (size_t)t * (CDL_GRAPH_STATS + 2 * kp);
+                HIPCHK(hipMemcpyAsync(stat_t, stb[b], CDL_GRAPH_STATS * sizeof(double), hipMemcpyDeviceToDevice, es));
+                if ((st = chain_enqueue(ctx, Wb[b], degb[b], stb[b], x.n, q->prec, q->depth, cws)) != CDL_OK) return st;
+                if ((st = solve_enqueue_fixed(ctx, Wb[b], degb[b], x.gid, x.n, cws, q->prec, q->depth, q->k, q->seed,
+                                              q->max_iter, Zb[b], sows, stat_t + CDL_GRAPH_STATS,
+                                              stat_t + CDL_GRAPH_STATS + kp)) != CDL_OK)
+                    return st;
+                if (t == 0) continue;
+                const int pb = b ^ 1;
+                const cdl_snapshot &y = sn[t - 1];
+                const int64_t m = mcnt[t], mp = pad_n(m);
+                const int32_t *mp0 = maps_all + moff[t], *mp1 = mp0 + m;
+                Arena as(scws);
+                ScoreWs w = plan_score(as, m, q->k);
+                const int32_t K = top_idx ? std::min<int32_t>(q->top_k, (int32_t)m) : 0;
+                const int weighted = q->mode == CDL_SCORE_DELTA_A;
+                { Timed t_(ctx, "build_zhat"); HIPCHK(launch_build_zhat(Zb[pb], Zb[b], mp0, mp1, m, mp, q->k, kp, stb[pb], stb[b], w.Zh, w.Zhe, w.sq, es)); }
+                { Timed t_(ctx, "score"); HIPCHK(launch_score(w.Zh, w.Zhe, kp, w.sq, m, mp, Wb[pb], pad_n(y.n), Wb[b], pad_n(x.n),
+                                    mp0, mp1, weighted, w.part, nullptr, es)); }
+                { Timed t_(ctx, "score_reduce"); HIPCHK(launch_score_reduce(w.part, score_tiles_1d(mp), m, mp, F[t - 1], es)); }
+                if (K > 0) { Timed t_(ctx, "topk"); HIPCHK(launch_topk(F[t - 1], m, K, w.topk, top_idx[t - 1], es)); }
+            }
+            return CDL_OK;
+        };
+        const bool timing = ctx->timing;
+        cdl_status st = CDL_OK;
+        if (key == ctx->seq_key && ctx->seq_exec) {
+            HIPCHK(hipGraphLaunch(ctx->seq_exec, s));
+            if (info) info->graph_launches = 1;
+        } else if (key == ctx->seq_key) {
+            // second identical call: capture the enqueue into a graph, on a
+            // private stream (the caller's may be the null stream, which
+            // cannot be captured), then launch it on the caller's stream
+            hipStream_t cap = nullptr;
+            HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+            const hipError_t eb = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+            if (eb != hipSuccess) {
+                (void)hipStreamDestroy(cap);
+                HIPCHK(eb);
+            }
+            ctx->timing = false;
+            ctx->stream = cap;
+            st = enqueue();
+            hipGraph_t g = nullptr;
+            const hipError_t ec = hipStreamEndCapture(cap, &g);
+            ctx->stream = s;
+            ctx->timing = timing;
+            (void)hipStreamDestroy(cap);
+            if (st != CDL_OK || ec != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                ctx->seq_key.clear();
+                if (st != CDL_OK) return st;
+                HIPCHK(ec);
+            }
+            hipGraphExec_t ex = nullptr;
+            const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            if (ei != hipSuccess) {
+                (void)hipGraphDestroy(g);
+                HIPCHK(ei);
+            }
+            ctx->seq_graph = g;
+            ctx->seq_exec = ex;
+            HIPCHK(hipGraphLaunch(ex, s));
+            if (info) info->graph_launches = 1;
+        } else {
+            if (ctx->seq_exec) (void)hipGraphExecDestroy(ctx->seq_exec);
+            if (ctx->seq_graph) (void)hipGraphDestroy(ctx->seq_graph);
+            ctx->seq_exec = nullptr;
+            ctx->seq_graph = nullptr;
+            ctx->seq_key = key;
+            if ((st = enqueue()) != CDL_OK) return st;
+        }
+        // one read-back for the whole sequence: graph checks and residuals
+        std::vector<double> hs((size_t)n_snap * (CDL_GRAPH_STATS + 2 * kp));
+        HIPCHK(hipMemcpyAsync(hs.data(), status, hs.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        double worst = 0.0;
+        for (int t = 0; t < n_snap; ++t) {
+            const double *h = hs.data() + (size_t)t * (CDL_GRAPH_STATS + 2 * kp);
+            for (int q2 = 0; q2 < CDL_GRAPH_STATS; ++q2)
+                if (!std::isfinite(h[q2])) return fail(ctx, CDL_E_NONFINITE, "snapshot " + std::to_string(t) + ": non-finite weights or degrees");
+            if (!(h[2] > 0.0)) return fail(ctx, CDL_E_GRAPH, "snapshot " + std::to_string(t) + ": a node has zero degree");
+            double rel = 0.0;
+            for (int64_t r = 0; r < q->k; ++r) {
+                const double yn = h[CDL_GRAPH_STATS + r], rn = h[CDL_GRAPH_STATS + kp + r];
+                if (!std::isfinite(rn)) return fail(ctx, CDL_E_NONFINITE, "snapshot " + std::to_string(t) + ": non-finite residual");
+                if (yn > 0.0) rel = std::max(rel, rn / yn);
+            }
+            worst = std::max(worst, rel);
+        }
+        if (info) {
+            info->pairs = n_snap - 1;
+            info->max_iterations = q->max_iter;
+            info->max_rel_residual = worst;
+        }
+        if (q->tol > 0.0 && worst > q->tol)
+            return fail(ctx, CDL_E_NOCONV, "residual " + std::to_string(worst) + " above tol after the fixed iterations");
+        return CDL_OK;
+    }
     if (info) std::memset(info, 0, sizeof(*info));
     hipStream_t s = ctx->stream;
     for (int t = 0; t < n_snap; ++t) {
@@ -978,12 +1225,7 @@ cdl_status cdl_score_sequence(cdl_ctx *ctx, int32_t n_snap, const cdl_snapshot *
         // common nodes of (t-1, t) in ascending global id order
         const cdl_snapshot &y = sn[t - 1];
         std::vector<int32_t> m0, m1;
-        int64_t i = 0, j = 0;
-        while (i < y.n && j < x.n) {
-            if (y.gid_host[i] == x.gid_host[j]) { m0.push_back((int32_t)i); m1.push_back((int32_t)j); ++i; ++j; }
-            else if (y.gid_host[i] < x.gid_host[j]) ++i;
-            else ++j;
-        }
+        common_maps(y, x, m0, m1);
         const int64_t m = (int64_t)m0.size();
         if (m < 2) return fail(ctx, CDL_E_GRAPH, "consecutive snapshots share fewer than two nodes");
         HIPCHK(hipMemcpyAsync(mapb[0], m0.data(), m * sizeof(int32_t), hipMemcpyHostToDevice, s));

@@ -116,3 +116,63 @@ def test_sequence_input_errors(cdl):
                            [torch.arange(100, dtype=torch.int32),
                             torch.arange(99, 199, dtype=torch.int32)], p)
     assert e.value.status == 4
+
+
+@pytest.mark.parametrize("prec,mode", [("fp32", "delta_a"), ("fp16", "unweighted")])
+def test_async_sequence_and_graph_replays(cdl, prec, mode):
+    # The asynchronous path (no host reads, one final check) runs the same
+    # kernels as the synchronous one with tol = 0, fixed depth and iteration
+    # count: the results agree bit for bit.  The second identical call is
+    # captured into a HIP graph, later ones replay it; each replay is checked
+    # against the eager result, with other eager work in between, and a
+    # replay after new series are written in place must follow the new data.
+    seq = small_sequence()
+    k, seed = 40, gen.grid.PROJ_SEED
+    Xs = [dev(X) for X in seq.X]
+    gdev = [torch.from_numpy(g).cuda() for g in seq.gid]
+    base = dict(k=k, seed=seed, prec=prec, depth=5, tol=0.0, max_iter=6, mode=mode, top_k=50)
+    print("async sequence", prec, mode, [len(g) for g in seq.gid], flush=True)
+
+    def eager():
+        F, tp, inf = cdl.score_sequence(Xs, gdev, cdl.SeqParams(**base))
+        return [host(f) for f in F], [host(t) for t in tp], inf
+
+    wF, wT, wi = eager()
+    pa = cdl.SeqParams(**base, asynchronous=True)
+    ws = torch.empty(cdl.sequence_workspace_bytes(Xs, gdev, pa), dtype=torch.uint8, device="cuda")
+    Fs, tops, info = cdl.score_sequence(Xs, gdev, pa, ws=ws)
+    assert info.graph_launches == 0 and info.pairs == len(Xs) - 1 and info.max_iterations == 6
+    assert info.max_rel_residual == wi.max_rel_residual
+    for t in range(len(wF)):
+        np.testing.assert_array_equal(host(Fs[t]), wF[t])
+        np.testing.assert_array_equal(host(tops[t]), wT[t])
+    launches = []
+    for r in range(4):
+        if r == 3:
+            # new data at the same addresses: the replay must follow it
+            Xs[2].mul_(1.05).add_(0.01)
+            wF, wT, wi = eager()
+        for f in Fs:
+            f.fill_(-1.0)
+        F2, T2, info = cdl.score_sequence(Xs, gdev, pa, ws=ws, out=(Fs, tops))
+        launches.append(info.graph_launches)
+        print("  call %d: graph %d residual %.3e" % (r, info.graph_launches, info.max_rel_residual), flush=True)
+        assert info.max_rel_residual == wi.max_rel_residual
+        for t in range(len(wF)):
+            np.testing.assert_array_equal(host(F2[t]), wF[t])
+            np.testing.assert_array_equal(host(T2[t]), wT[t])
+        # eager work on the same stream between replays
+        Fx, _, _ = cdl.score_sequence(Xs[:2], gdev[:2], cdl.SeqParams(**base))
+        np.testing.assert_array_equal(host(Fx[0]), wF[0])
+    assert launches == [1, 1, 1, 1]
+
+
+def test_async_sequence_rejects_adaptive_settings(cdl):
+    seq = small_sequence()
+    Xs = [dev(X) for X in seq.X[:2]]
+    gdev = [torch.from_numpy(g).cuda() for g in seq.gid[:2]]
+    for bad in (dict(depth=0), dict(solver="pcg"), dict(tol=-1e-6)):
+        q = dict(k=16, prec="fp32", depth=4, tol=0.0, max_iter=3, asynchronous=True)
+        q.update(bad)
+        with pytest.raises(cdl.CdlError):
+            cdl.score_sequence(Xs, gdev, cdl.SeqParams(**q))
