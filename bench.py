@@ -338,15 +338,17 @@ def main():
                     "max_rel_residual": sinfo.max_rel_residual}
         log("sequence: %d pairs in %.1f ms" % (sinfo.pairs, ms_seq * 1e3))
         # The same sequence enqueued with no host reads, then replayed as a HIP
-        # graph: every chain at the depth the adaptive rule gives the largest
-        # snapshot, every solve at the largest iteration count above; the
-        # library rejects the call if any final residual stays above 1e-8.
-        big = max(range(len(Xs)), key=lambda t: Xs[t].shape[0])
-        gb = cdl.build_graph(Xs[big])
-        dfix = cdl.build_chain(gb, prec=args.mixed, depth=0, depth_max=DMAX).depth
-        del gb
+        # graph: every chain at the largest depth the adaptive rule picks over
+        # the snapshots, every solve at the largest iteration count above (two
+        # more per retry); the library rejects the call if any final residual
+        # stays above 1e-8.
+        dfix = 1
+        for X in Xs:
+            gb = cdl.build_graph(X)
+            dfix = max(dfix, cdl.build_chain(gb, prec=args.mixed, depth=0, depth_max=DMAX).depth)
+            del gb
         gdev = [g.to(dev) for g in gids]
-        iters = sinfo.max_iterations
+        iters, err, replay = sinfo.max_iterations, None, None
         for attempt in range(3):
             spa = cdl.SeqParams(k=128, seed=seed, prec=args.mixed, depth=dfix, tol=1e-8,
                                 max_iter=iters, top_k=50, asynchronous=True)
@@ -354,25 +356,27 @@ def main():
                 sws = torch.empty(cdl.sequence_workspace_bytes(Xs, gdev, spa), dtype=torch.uint8,
                                   device=dev)
                 Fa, ta, ainfo = cdl.score_sequence(Xs, gdev, spa, ws=sws)   # eager enqueue
+                Fa, ta, ainfo = cdl.score_sequence(Xs, gdev, spa, ws=sws, out=(Fa, ta))   # capture
+                torch.cuda.synchronize()
+                reps = 3
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    Fa, ta, ainfo = cdl.score_sequence(Xs, gdev, spa, ws=sws, out=(Fa, ta))
+                torch.cuda.synchronize()
+                ms_graph = (time.perf_counter() - t0) / reps
+                replay = {"ms_per_sequence": round(ms_graph * 1e3, 2),
+                          "pairs_per_s": round(ainfo.pairs / ms_graph, 2),
+                          "chain_depth": dfix, "iterations": iters,
+                          "graph_launches": ainfo.graph_launches,
+                          "max_rel_residual": ainfo.max_rel_residual}
+                log("sequence as a graph replay: %.1f ms (depth %d, %d iterations)" % (ms_graph * 1e3, dfix, iters))
                 break
             except cdl.CdlError as e:
-                log("async sequence at %d iterations: %s" % (iters, e))
+                err = str(e)
+                log("async sequence at depth %d, %d iterations: %s" % (dfix, iters, e))
                 iters += 2
-        Fa, ta, ainfo = cdl.score_sequence(Xs, gdev, spa, ws=sws, out=(Fa, ta))   # capture
-        torch.cuda.synchronize()
-        reps = 3
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            Fa, ta, ainfo = cdl.score_sequence(Xs, gdev, spa, ws=sws, out=(Fa, ta))
-        torch.cuda.synchronize()
-        ms_graph = (time.perf_counter() - t0) / reps
-        sequence["graph_replay"] = {"ms_per_sequence": round(ms_graph * 1e3, 2),
-                                    "pairs_per_s": round(ainfo.pairs / ms_graph, 2),
-                                    "chain_depth": dfix, "iterations": iters,
-                                    "graph_launches": ainfo.graph_launches,
-                                    "max_rel_residual": ainfo.max_rel_residual}
-        log("sequence as a graph replay: %.1f ms (depth %d, %d iterations)" % (ms_graph * 1e3, dfix, iters))
-        del sws
+        sequence["graph_replay"] = replay if replay is not None else {"error": err}
+        sws = None
 
     # dominant kernel of the mixed step
     modeled = {nm: v for nm, v in times_mixed.items() if kernel_model(nm, n, k, T, args.mixed)}
