@@ -158,6 +158,15 @@ const char *cdl_version(void);
  * 0 restores autotuning.  CDL_E_ARG outside [0, 16]. */
 cdl_status cdl_ctx_set_solve_depth(cdl_ctx *ctx, int depth);
 
+/* Median-rule bandwidth selection of later cdl_build_graph calls on this
+ * context.  0 (default): a sorted sample of 4096 pair distances brackets the
+ * target rank, one pass over the matrix counts the keys below the bracket and
+ * collects those inside, and the radix passes run over the collected keys
+ * (over the matrix when the rank falls outside the bracket).  1: radix passes
+ * over the matrix only.  Both are exact and give the same sigma.  CDL_E_ARG
+ * for other values. */
+cdl_status cdl_ctx_set_select(cdl_ctx *ctx, int mode);
+
 /* ---- per-kernel timing ------------------------------------------------- */
 
 /* enable != 0: every kernel launch of later calls on this context is

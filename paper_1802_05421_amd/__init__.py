@@ -28,6 +28,7 @@ from .api import (  # noqa: E402,F401
     level_scale,
     score_sequence,
     sequence_workspace_bytes,
+    set_select,
     set_solve_depth,
     set_timing,
     timing,

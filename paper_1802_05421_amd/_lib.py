@@ -82,6 +82,7 @@ def load():
         "cdl_version": (C.c_char_p, []),
         "cdl_ctx_set_timing": (I, [P, I]),
         "cdl_ctx_set_solve_depth": (I, [P, I]),
+        "cdl_ctx_set_select": (I, [P, I]),
         "cdl_timing_read": (I, [P, C.c_int32, C.POINTER(C.c_char_p), C.POINTER(i64),
                                 C.POINTER(d)]),
         "cdl_timing_reset": (I, [P]),

@@ -66,6 +66,12 @@ def set_solve_depth(depth: int, device: int = 0):
     _check(_lib().cdl_ctx_set_solve_depth(ctx.h, int(depth)), ctx.h)
 
 
+def set_select(mode: int, device: int = 0):
+    """Median selection of later graph builds: 0 bracketed (default), 1 radix over the matrix."""
+    ctx = context(device)
+    _check(_lib().cdl_ctx_set_select(ctx.h, int(mode)), ctx.h)
+
+
 def set_timing(enable: bool, device: int = 0):
     """Per-kernel HIP-event timing on the context's stream (see include/caddelag.h)."""
     ctx = context(device)

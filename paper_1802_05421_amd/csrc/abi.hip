@@ -32,6 +32,7 @@ struct cdl_ctx {
     std::vector<std::string> names;   // stable order for cdl_timing_read
     // Asynchronous sequences: the last call's key and, once the same call
     // has been seen twice, its captured graph.
+    int select_mode = 0;   // 0 bracketed median selection, 1 radix over the matrix only
     std::vector<uint64_t> seq_key;
     hipGraph_t seq_graph = nullptr;
     hipGraphExec_t seq_exec = nullptr;
@@ -120,6 +121,7 @@ struct Arena {
 struct GraphWs {
     int *flags;
     SelectState *sel;
+    unsigned long long *selbuf;
     double *sqn, *Xp, *dpart;
 };
 GraphWs plan_graph(Arena &a, int64_t n, int64_t T) {
@@ -127,6 +129,7 @@ GraphWs plan_graph(Arena &a, int64_t n, int64_t T) {
     GraphWs w;
     w.flags = a.take<int>(64);
     w.sel = a.take<SelectState>(1);
+    w.selbuf = a.take<unsigned long long>((size_t)select_buffer_keys(n));
     w.sqn = a.take<double>(ld);
     w.Xp = a.take<double>((size_t)ld * Tp);
     w.dpart = a.take<double>((size_t)(ld / 64) * ld);
@@ -254,7 +257,7 @@ cdl_status graph_enqueue(cdl_ctx *ctx, const double *X, int64_t n, int64_t T, in
     if (sigma > 0.0)
         { Timed t_(ctx, "set_sigma"); HIPCHK(launch_set_sigma(sigma, stats, s)); }
     else
-        { Timed t_(ctx, "select_median"); HIPCHK(launch_select_median(W, ld, n, w.sel, stats, s)); }
+        { Timed t_(ctx, "select_median"); HIPCHK(launch_select_median(W, ld, n, w.sel, w.selbuf, ctx->select_mode == 0, stats, s)); }
     { Timed t_(ctx, "exp_degree"); HIPCHK(launch_exp_degree(W, ld, n, stats, deg, w.dpart, s)); }
     { Timed t_(ctx, "graph_stats"); HIPCHK(launch_graph_stats(deg, n, stats, s)); }
     return CDL_OK;
@@ -437,6 +440,12 @@ cdl_status cdl_ctx_destroy(cdl_ctx *ctx) {
 cdl_status cdl_ctx_set_solve_depth(cdl_ctx *ctx, int depth) {
     if (!ctx || depth < 0 || depth > 16) return CDL_E_ARG;
     ctx->solve_depth = depth;
+    return CDL_OK;
+}
+
+cdl_status cdl_ctx_set_select(cdl_ctx *ctx, int mode) {
+    if (!ctx || mode < 0 || mode > 1) return CDL_E_ARG;
+    ctx->select_mode = mode;
     return CDL_OK;
 }
 

@@ -160,11 +160,16 @@ hipError_t launch_gram_dist(const double *Xp, int64_t Tp, const double *sqn, int
 // ---------------------------------------------------------------------------
 // Exact selection of the element of rank floor((N-1)/2), N = n(n-1)/2, among
 // D2_ij (i < j).  D2 >= 0, so its IEEE bit pattern orders like its value.
-// Radix passes of 12-bit digits start below the common prefix of the
-// smallest and largest key; as soon as the selected bin holds at most
-// kSelCap keys, one pass collects them and a single workgroup sorts them.
-// Every pass kernel reads the state's mode, so the fixed launch sequence
-// turns into no-ops once the answer is known.
+// First a bracket: a sorted sample of kSelSample keys gives [lo, hi] around
+// the target quantile (three standard deviations of the sample quantile on
+// each side); one pass over the matrix counts the keys below lo and appends
+// those in [lo, hi] to a buffer.  If the target rank falls inside the bracket
+// the radix passes below run over the buffer, else over the matrix (the
+// result is exact either way).  Radix passes of 12-bit digits start below the
+// common prefix of the bracket (or of the smallest and largest key); as soon
+// as the selected bin holds at most kSelCap keys, one pass collects them and
+// a single workgroup sorts them.  Every pass kernel reads the state's mode,
+// so the fixed launch sequence turns into no-ops once the answer is known.
 
 __global__ void k_select_reset(SelectState *st) {
     for (int b = threadIdx.x; b < 4096; b += blockDim.x) st->hist[b] = 0;
@@ -173,7 +178,152 @@ __global__ void k_select_reset(SelectState *st) {
         st->kmax = 0ull;
         st->count = 0;
         st->mode = 0;
+        st->src = 0;
+        st->below = 0;
+        st->nbuf = 0;
     }
+}
+
+constexpr int kSelSample = 4096;
+constexpr int kSelMargin = 96;    // 3 sqrt(kSelSample / 4): misses in ~0.3% of calls
+
+int64_t select_buffer_keys(int64_t n) {
+    const int64_t N = n * (n - 1) / 2;
+    const int64_t cap = N / 8 + 65536;
+    return cap < ((int64_t)1 << 27) ? cap : ((int64_t)1 << 27);
+}
+
+__device__ inline unsigned long long sel_mix(unsigned long long z) {
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// One workgroup: kSelSample keys at pseudo-random pairs i != j, bitonic sort
+// in LDS, bracket of kSelMargin sample ranks on each side of the target.
+__global__ __launch_bounds__(1024) void k_select_sample(const double *D2, int64_t ld, int64_t n,
+                                                        SelectState *st) {
+    extern __shared__ unsigned long long sk[];
+    if (st->mode == 2) return;
+    const int t = threadIdx.x;
+    unsigned long long v[kSelSample / 1024];
+#pragma unroll
+    for (int u = 0; u < kSelSample / 1024; ++u) {   // independent loads in flight together
+        const unsigned long long h = sel_mix(0x5851f42d4c957f2dull + (unsigned long long)(t + 1024 * u));
+        int64_t i = (int64_t)((h & 0xffffffffull) % (unsigned long long)n);
+        int64_t j = (int64_t)((h >> 32) % (unsigned long long)(n - 1));
+        if (j >= i) ++j;   // j != i
+        const int64_t a = i < j ? i : j, b = i < j ? j : i;
+        v[u] = (unsigned long long)__double_as_longlong(D2[a * ld + b]);
+    }
+#pragma unroll
+    for (int u = 0; u < kSelSample / 1024; ++u) sk[t + 1024 * u] = v[u];
+    __syncthreads();
+    for (int size = 2; size <= kSelSample; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int q = t; q < kSelSample / 2; q += 1024) {
+                const int lo = 2 * q - (q & (stride - 1)), hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const unsigned long long a = sk[lo], b = sk[hi];
+                if ((a > b) == up) { sk[lo] = b; sk[hi] = a; }
+            }
+            __syncthreads();
+        }
+    if (t == 0) {
+        const unsigned long long N = (unsigned long long)n * (unsigned long long)(n - 1) / 2ull;
+        const double rho = (double)((N - 1ull) / 2ull) / (double)N;
+        const int q = (int)(rho * kSelSample);
+        st->lo = q - kSelMargin <= 0 ? 0ull : sk[q - kSelMargin];
+        st->hi = q + kSelMargin >= kSelSample - 1 ? ~0ull : sk[q + kSelMargin];
+        st->below = 0;
+        st->nbuf = 0;
+    }
+}
+
+// Count the keys below lo; append those in [lo, hi] to buf (at most cap).
+// Appends go to a per-workgroup LDS stage (one LDS atomic each) copied out
+// behind one global atomic at the end; a workgroup holds about
+// N / 2048 * 2 kSelMargin / kSelSample ~ 3000 bracket keys for n = 16384, and
+// keys past the stage's end take a global slot each.
+__global__ __launch_bounds__(256) void k_select_bracket(const double *D2, int64_t ld, int64_t n,
+                                                        SelectState *st, unsigned long long *buf,
+                                                        int64_t cap) {
+    constexpr unsigned int kStage = 4096;
+    __shared__ unsigned long long sb[kStage];
+    __shared__ unsigned int scnt;
+    __shared__ unsigned long long sbase, spart[4];
+    if (st->mode == 2) return;
+    const unsigned long long lo = st->lo, hi = st->hi;
+    const int t = threadIdx.x;
+    if (t == 0) scnt = 0;
+    __syncthreads();
+    unsigned long long below = 0;
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+        const unsigned long long *row = (const unsigned long long *)(D2 + i * ld);
+        for (int64_t j0 = i + 1 + t; j0 < n; j0 += 8 * 256) {
+            unsigned long long key[8];   // eight independent loads in flight
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t j = j0 + 256 * u;
+                key[u] = j < n ? row[j] : ~0ull;   // ~0: above every bracket
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (key[u] < lo) {
+                    ++below;
+                } else if (key[u] <= hi && key[u] != ~0ull) {
+                    const unsigned int q = atomicAdd(&scnt, 1u);
+                    if (q < kStage) {
+                        sb[q] = key[u];
+                    } else {
+                        const unsigned long long g = atomicAdd(&st->nbuf, 1ull);
+                        if (g < (unsigned long long)cap) buf[g] = key[u];
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const unsigned int c = scnt < kStage ? scnt : kStage;
+    if (t == 0 && c > 0) sbase = atomicAdd(&st->nbuf, (unsigned long long)c);
+    __syncthreads();
+    if (c > 0) {
+        const unsigned long long base = sbase;
+        for (unsigned int q = t; q < c; q += 256)
+            if (base + q < (unsigned long long)cap) buf[base + q] = sb[q];
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) below += __shfl_xor(below, o);
+    if ((t & 63) == 0) spart[t >> 6] = below;
+    __syncthreads();
+    if (t == 0) {
+        const unsigned long long b = spart[0] + spart[1] + spart[2] + spart[3];
+        if (b) atomicAdd(&st->below, b);
+    }
+}
+
+// Switch the radix passes to the buffer when the target lies in the bracket.
+__global__ void k_select_check(SelectState *st, int64_t cap, double *stats) {
+    if (threadIdx.x != 0 || st->mode == 2) return;
+    const unsigned long long below = st->below, nb = st->nbuf, rank = st->rank;
+    if (nb > (unsigned long long)cap || rank < below || rank >= below + nb) return;   // stay on the matrix
+    st->src = 1;
+    st->rank = rank - below;
+    const unsigned long long x = st->lo ^ st->hi;
+    if (x == 0ull) {   // every bracket key equals lo
+        st->prefix = st->lo;
+        st->bits = 64;
+        st->mode = 2;
+        stats[1] = sqrt(__longlong_as_double((long long)st->lo));
+        return;
+    }
+    const int L = __clzll((long long)x);
+    if (L > st->bits) {
+        st->bits = L;
+        st->prefix = st->lo & ~((1ull << (64 - L)) - 1ull);
+    }
+    st->mode = nb <= (unsigned long long)kSelCap ? 1 : 0;
+    st->count = 0;
 }
 
 __global__ void k_select_setup(SelectState *st, int64_t n, double *stats) {
@@ -203,7 +353,8 @@ __device__ inline void sel_digit(const SelectState *st, int &shift, int &width,
 }
 
 __global__ __launch_bounds__(256) void k_select_pass(const double *D2, int64_t ld, int64_t n,
-                                                     SelectState *st) {
+                                                     SelectState *st,
+                                                     const unsigned long long *buf) {
     __shared__ unsigned int h[4096];
     const int mode = st->mode;
     if (mode == 2) return;
@@ -216,16 +367,36 @@ __global__ __launch_bounds__(256) void k_select_pass(const double *D2, int64_t l
         __syncthreads();
     }
     const unsigned long long dmask = (1ull << width) - 1ull;
-    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
-        const unsigned long long *row = (const unsigned long long *)(D2 + i * ld);
-        for (int64_t j = i + 1 + threadIdx.x; j < n; j += 256) {
-            const unsigned long long key = row[j];
-            if ((key & hi_mask) != prefix) continue;
-            if (mode == 0) {
-                atomicAdd(&h[(key >> shift) & dmask], 1u);
-            } else {
-                const unsigned int q = atomicAdd(&st->count, 1u);
-                if (q < kSelCap) st->cand[q] = key;
+    auto take = [&](unsigned long long key) {
+        if ((key & hi_mask) != prefix) return;
+        if (mode == 0) {
+            atomicAdd(&h[(key >> shift) & dmask], 1u);
+        } else {
+            const unsigned int q = atomicAdd(&st->count, 1u);
+            if (q < kSelCap) st->cand[q] = key;
+        }
+    };
+    // eight independent loads in flight per thread
+    if (st->src == 1) {
+        const int64_t nb = (int64_t)st->nbuf, stride = (int64_t)gridDim.x * 256;
+        for (int64_t q0 = (int64_t)blockIdx.x * 256 + threadIdx.x; q0 < nb; q0 += 8 * stride) {
+            unsigned long long key[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) key[u] = q0 + u * stride < nb ? buf[q0 + u * stride] : 0ull;
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (q0 + u * stride < nb) take(key[u]);
+        }
+    } else {
+        for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+            const unsigned long long *row = (const unsigned long long *)(D2 + i * ld);
+            for (int64_t j0 = i + 1 + threadIdx.x; j0 < n; j0 += 8 * 256) {
+                unsigned long long key[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) key[u] = j0 + 256 * u < n ? row[j0 + 256 * u] : 0ull;
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (j0 + 256 * u < n) take(key[u]);
             }
         }
     }
@@ -236,8 +407,9 @@ __global__ __launch_bounds__(256) void k_select_pass(const double *D2, int64_t l
     }
 }
 
-__global__ __launch_bounds__(256) void k_select_pick(SelectState *st, double *stats) {
-    __shared__ unsigned long long part[256];
+__global__ __launch_bounds__(1024) void k_select_pick(SelectState *st, double *stats) {
+    constexpr int NT = 1024, BPT = 4096 / NT;
+    __shared__ unsigned long long part[NT / 64];
     __shared__ unsigned long long keys[kSelCap];
     const int t = threadIdx.x;
     const int mode = st->mode;
@@ -245,11 +417,11 @@ __global__ __launch_bounds__(256) void k_select_pick(SelectState *st, double *st
     if (mode == 1) {
         // sort the collected candidates (count <= kSelCap) and take the rank
         const unsigned int cnt = st->count;
-        for (int q = t; q < kSelCap; q += 256) keys[q] = q < (int)cnt ? st->cand[q] : ~0ull;
+        for (int q = t; q < kSelCap; q += NT) keys[q] = q < (int)cnt ? st->cand[q] : ~0ull;
         __syncthreads();
         for (int size = 2; size <= kSelCap; size <<= 1)
             for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                for (int q = t; q < kSelCap / 2; q += 256) {
+                for (int q = t; q < kSelCap / 2; q += NT) {
                     const int lo = 2 * q - (q & (stride - 1)), hi = lo + stride;
                     const bool up = (lo & size) == 0;
                     const unsigned long long a = keys[lo], b = keys[hi];
@@ -269,31 +441,31 @@ __global__ __launch_bounds__(256) void k_select_pick(SelectState *st, double *st
     int shift, width;
     unsigned long long hi_mask;
     sel_digit(st, shift, width, hi_mask);
-    unsigned long long c[16], sum = 0;
+    unsigned long long c[BPT], sum = 0;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        c[q] = st->hist[t * 16 + q];
+    for (int q = 0; q < BPT; ++q) {
+        c[q] = st->hist[t * BPT + q];
         sum += c[q];
     }
-    part[t] = sum;
-    __syncthreads();
-    if (t == 0) {
-        unsigned long long acc = 0;
-        for (int q = 0; q < 256; ++q) {
-            const unsigned long long v = part[q];
-            part[q] = acc;
-            acc += v;
-        }
+    // exclusive prefix of the per-thread bin sums: within each wave by
+    // shuffles, then across the waves
+    unsigned long long incl = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned long long y = __shfl_up(incl, o);
+        if ((t & 63) >= o) incl += y;
     }
+    if ((t & 63) == 63) part[t >> 6] = incl;
     __syncthreads();
+    unsigned long long before = incl - sum;
+    for (int w = 0; w < (t >> 6); ++w) before += part[w];
     const unsigned long long rank = st->rank;
-    unsigned long long before = part[t];
     int bin = -1;
     unsigned long long newrank = 0, cnt = 0;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
+    for (int q = 0; q < BPT; ++q) {
         if (bin < 0 && rank >= before && rank < before + c[q]) {
-            bin = t * 16 + q;
+            bin = t * BPT + q;
             newrank = rank - before;
             cnt = c[q];
         }
@@ -314,7 +486,7 @@ __global__ __launch_bounds__(256) void k_select_pick(SelectState *st, double *st
         }
     }
     __syncthreads();
-    for (int b = t; b < 4096; b += 256) st->hist[b] = 0;
+    for (int b = t; b < 4096; b += NT) st->hist[b] = 0;
 }
 
 hipError_t launch_select_reset(SelectState *st, hipStream_t s) {
@@ -323,13 +495,31 @@ hipError_t launch_select_reset(SelectState *st, hipStream_t s) {
 }
 
 hipError_t launch_select_median(const double *D2, int64_t ld, int64_t n, SelectState *st,
-                                double *stats, hipStream_t s) {
+                                unsigned long long *buf, bool bracket, double *stats,
+                                hipStream_t s) {
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_select_sample,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           kSelSample * 8);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
     hipLaunchKernelGGL(k_select_setup, dim3(1), dim3(64), 0, s, st, n, stats);
     const int grid = (int)(n < 2048 ? n : 2048);
+    const int64_t cap = select_buffer_keys(n);
+    // the bracket holds about 2 kSelMargin / kSelSample of the N keys: skip it
+    // when that would not fit the buffer
+    const double N = (double)n * (double)(n - 1) / 2.0;
+    if (bracket && N * 2.0 * kSelMargin / kSelSample <= 0.8 * (double)cap) {
+        hipLaunchKernelGGL(k_select_sample, dim3(1), dim3(1024), kSelSample * 8, s, D2, ld, n, st);
+        hipLaunchKernelGGL(k_select_bracket, dim3(grid), dim3(256), 0, s, D2, ld, n, st, buf, cap);
+        hipLaunchKernelGGL(k_select_check, dim3(1), dim3(64), 0, s, st, cap, stats);
+    }
     // at most 6 digit passes resolve 64 bits; the collect pass is one more
     for (int p = 0; p < 7; ++p) {
-        hipLaunchKernelGGL(k_select_pass, dim3(grid), dim3(256), 0, s, D2, ld, n, st);
-        hipLaunchKernelGGL(k_select_pick, dim3(1), dim3(256), 0, s, st, stats);
+        hipLaunchKernelGGL(k_select_pass, dim3(grid), dim3(256), 0, s, D2, ld, n, st, buf);
+        hipLaunchKernelGGL(k_select_pick, dim3(1), dim3(1024), 0, s, st, stats);
     }
     return hipGetLastError();
 }

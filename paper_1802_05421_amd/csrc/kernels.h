@@ -21,9 +21,15 @@ struct SelectState {                // device scratch of the exact median select
     int bits;                       // number of resolved high bits
     int mode;                       // 0 histogram, 1 collect, 2 done
     unsigned int count;             // collected candidates
+    int src;                        // keys read from 0: the matrix, 1: the bracket buffer
+    unsigned long long lo, hi;      // sampled bracket [lo, hi] around the target rank
+    unsigned long long below;       // keys < lo
+    unsigned long long nbuf;        // keys in [lo, hi] (appended to the bracket buffer)
     unsigned long long hist[4096];  // 64-bit: a bin can exceed 2^32 keys for n > 92681
     unsigned long long cand[kSelCap];
 };
+// Keys the bracket buffer of the selection holds for n nodes.
+int64_t select_buffer_keys(int64_t n);
 
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_pad_series(const double *X, int64_t n, int64_t T, int64_t ldx,
@@ -34,8 +40,11 @@ hipError_t launch_pad_series(const double *X, int64_t n, int64_t T, int64_t ldx,
 hipError_t launch_gram_dist(const double *Xp, int64_t Tp, const double *sqn, int64_t n,
                             int64_t ld, double *D2, SelectState *st, hipStream_t s);
 hipError_t launch_select_reset(SelectState *st, hipStream_t s);
+// buf: select_buffer_keys(n) words of scratch; bracket = false: radix
+// passes over the matrix only.
 hipError_t launch_select_median(const double *D2, int64_t ld, int64_t n,
-                                SelectState *st, double *stats, hipStream_t s);
+                                SelectState *st, unsigned long long *buf, bool bracket,
+                                double *stats, hipStream_t s);
 hipError_t launch_set_sigma(double sigma, double *stats, hipStream_t s);
 // part: (ld / 64) x ld doubles of degree partials.
 int sym_tiles64(int64_t ld);   // upper 64 x 64 tiles of an ld x ld matrix

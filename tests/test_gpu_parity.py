@@ -5,6 +5,8 @@ tiles, T not a multiple of 16, k not a multiple of 64).  Every call goes
 through the C ABI (libcaddelag.so) via the thin torch binding.
 """
 
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -71,6 +73,39 @@ def test_graph_given_sigma_and_median_rank_exact(cdl):
     o2 = oracle.build_graph(X, sigma=2.5)
     assert g2.host_stats()["sigma"] == 2.5
     np.testing.assert_allclose(host(g2.W)[:120, :120], o2["W"], rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("kind", ["continuous", "three_values", "two_clusters"])
+def test_median_exact_through_the_bracket(cdl, kind):
+    # n = 3000: N = 4.5e6 keys, a sampled bracket of ~1.8e5 keys is selected
+    # by radix passes over the bracket buffer.  With three distinct distances
+    # the bracket collapses to one value; with two far clusters the median
+    # sits in a sparse gap between the within- and between-cluster distances.
+    n, rng = 3000, np.random.default_rng(17)
+    if kind == "continuous":
+        X = rng.standard_normal((n, 20))
+    elif kind == "three_values":
+        X = np.array([[0.0, 0.0], [3.0, 0.0], [0.0, 4.0]])[rng.integers(0, 3, n)]
+    else:
+        X = np.concatenate([rng.standard_normal((n // 2, 4)), 50 + rng.standard_normal((n - n // 2, 4))])
+    print("median case %s n=%d" % (kind, n), flush=True)
+    g = cdl.build_graph(dev(X))
+    want = oracle.bandwidth(oracle.sq_distances(X))
+    assert g.host_stats()["sigma"] == pytest.approx(want, rel=1e-13)
+    # radix passes over the whole matrix (the path taken when the rank falls
+    # outside the bracket): the same key
+    cdl.set_select(1)
+    try:
+        g1 = cdl.build_graph(dev(X))
+    finally:
+        cdl.set_select(0)
+    assert g1.host_stats()["sigma"] == g.host_stats()["sigma"]
+    # rank property on the GPU's own weights: exactly floor((N-1)/2) above e^-1
+    W = host(g.W)[:n, :n]
+    iu = np.triu_indices(n, 1)
+    w, e1 = W[iu], math.exp(-1.0)
+    rank = (len(w) - 1) // 2
+    assert (w > e1 * (1 + 1e-12)).sum() <= rank < (w >= e1 * (1 - 1e-12)).sum()
 
 
 def test_graph_from_weights(cdl):
