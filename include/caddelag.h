@@ -88,6 +88,8 @@ typedef struct {
     double rho_hat;            /* fro(S~_{d-1})^(1/2^(d-1)): upper estimate of rho(S~) */
     double rho_bound;          /* ||S~||_F of the unrounded FP64 S~: rigorous bound on rho */
     double fro[CDL_MAX_DEPTH + 1]; /* Frobenius norm of each stored level */
+    int dense_levels;          /* 0: a chain of levels; m > 0: after cdl_chain_densify, the
+                                  one stored matrix is prod_{l<m} (I + S~^{2^l}) - I (depth 1) */
 } cdl_chain_info;
 
 typedef struct {
@@ -266,6 +268,23 @@ cdl_status cdl_build_chain(cdl_ctx *ctx, const double *W, const double *deg,
                            const double *stats, int64_t n, cdl_prec prec,
                            int depth, int depth_max, double chain_eps, int lazy,
                            void *chain, size_t chain_bytes, cdl_chain_info *info);
+
+/* The dense schedule of Algorithm 2 (the factor P of ChainProduct formed
+ * once, then one product per Richardson step): replaces the info->depth
+ * stored levels by the single matrix Q = prod_{l<d} (I + S~^{2^l}) - I, in
+ * the level type and storage scale, built by d - 1 products
+ * Q <- Q + L + Q L (symmetric MFMA GEMMs, upper tiles mirrored; the factors
+ * commute).  The identity stays out of Q, so the solve applies
+ * P = I + Q as it applies a one-level chain (the identity term in FP64).
+ * On return info->depth = 1 and info->dense_levels = d; later solves apply P
+ * once per iteration (no repeated levels).
+ *   n      nodes of the chain's graph.
+ *   chain  the buffer cdl_build_chain filled; for d >= 2 it must hold d + 1
+ *          levels (the last as scratch): cdl_workspace_bytes with
+ *          depth_max >= d + 1.
+ * Errors: CDL_E_ARG (bad info, already dense), CDL_E_WORKSPACE. */
+cdl_status cdl_chain_densify(cdl_ctx *ctx, int64_t n, void *chain, size_t chain_bytes,
+                             cdl_chain_info *info);
 
 /* ---- embedding (Algorithm 3 with Algorithm 1's right-hand sides) ---------- */
 

@@ -41,7 +41,7 @@ __all__ = [
     "solve_embedding", "solve_embedding_eigh", "pinv_laplacian",
     "commute_times", "exact_commute_times", "scores", "scores_rows", "top_k",
     "edge_scores", "top_edges",
-    "normalized_deflated", "chain_levels", "chain_apply", "estimate_solution",
+    "normalized_deflated", "chain_levels", "chain_product", "chain_apply", "estimate_solution",
     "spectral_radius", "pair_pipeline", "lib",
 ]
 
@@ -389,6 +389,16 @@ def chain_levels(St: np.ndarray, d: int) -> List[np.ndarray]:
     for _ in range(d - 1):
         levels.append(levels[-1] @ levels[-1])
     return levels
+
+
+def chain_product(levels: List[np.ndarray]) -> np.ndarray:
+    """P = prod_l (I + S~_l), the dense factor of ChainProduct (Algorithm 2)
+    before the outer D^{-1/2} factors, multiplied in level order."""
+    n = levels[0].shape[0]
+    P = np.eye(n)
+    for S in levels:
+        P = P @ (np.eye(n) + S)
+    return P
 
 
 def chain_apply(levels: List[np.ndarray], deg: np.ndarray, R: np.ndarray,

@@ -20,6 +20,7 @@ from .api import (  # noqa: E402,F401
     anomaly_edges,
     anomaly_scores,
     build_chain,
+    chain_densify,
     build_graph,
     check_graph,
     graph_from_weights,

@@ -24,7 +24,7 @@ MODE = {"unweighted": 0, "delta_a": 1}
 class ChainInfo(C.Structure):
     _fields_ = [("depth", C.c_int), ("lazy", C.c_int), ("prec", C.c_int),
                 ("rho_hat", C.c_double), ("rho_bound", C.c_double),
-                ("fro", C.c_double * (CDL_MAX_DEPTH + 1))]
+                ("fro", C.c_double * (CDL_MAX_DEPTH + 1)), ("dense_levels", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -95,6 +95,7 @@ def load():
         "cdl_graph_from_weights": (I, [P, P, i64, i64, P, P, P, P, sz]),
         "cdl_check_graph": (I, [P, P, P, i64, P]),
         "cdl_build_chain": (I, [P, P, P, P, i64, I, I, I, d, I, P, sz, C.POINTER(ChainInfo)]),
+        "cdl_chain_densify": (I, [P, i64, P, sz, C.POINTER(ChainInfo)]),
         "cdl_solve_embedding": (I, [P, P, P, P, P, i64, P, C.POINTER(ChainInfo), i64, d, u64,
                                     I, d, I, P, P, sz, C.POINTER(SolveInfo)]),
         "cdl_anomaly_scores": (I, [P, P, P, P, i64, P, P, P, i64, i64, P, P, i64, I, P,

@@ -147,6 +147,10 @@ class Chain:
     def fro(self) -> List[float]:
         return [self.info.fro[i] for i in range(self.info.depth)]
 
+    @property
+    def dense_levels(self) -> int:
+        return self.info.dense_levels
+
 
 def build_graph(X: torch.Tensor, sigma: Optional[float] = None, ws: Optional[torch.Tensor] = None,
                 out: Optional[Graph] = None, check: bool = True) -> Graph:
@@ -205,6 +209,22 @@ def build_chain(g: Graph, prec: str = "bf16", depth: int = 0, depth_max: int = 1
                                   L.PREC[prec], depth, depth_max, chain_eps, int(lazy),
                                   _ptr(buf), buf.numel(), C.byref(info)), ctx.h)
     return Chain(buf=buf, info=info, n=g.n)
+
+
+def chain_densify(chain: Chain) -> Chain:
+    """Replace the levels by Q = prod_l (I + S~^{2^l}) - I (Algorithm 2's
+    dense schedule; see cdl_chain_densify).  Grows the buffer when it has no
+    scratch level."""
+    ctx = context(chain.buf.device.index)
+    d = chain.info.depth
+    need = workspace_bytes(chain.n, 1, 1, d + 1 if d >= 2 else 1, L.PREC_NAME[chain.info.prec])["chain"]
+    if chain.buf.numel() < need:
+        buf = _ws(need, chain.buf.device)
+        buf[:chain.buf.numel()].copy_(chain.buf)
+        chain.buf = buf
+    _check(_lib().cdl_chain_densify(ctx.h, chain.n, _ptr(chain.buf), chain.buf.numel(),
+                                    C.byref(chain.info)), ctx.h)
+    return chain
 
 
 def level(chain: Chain, l: int) -> torch.Tensor:

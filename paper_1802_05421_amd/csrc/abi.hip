@@ -653,6 +653,42 @@ cdl_status cdl_build_chain(cdl_ctx *ctx, const double *W, const double *deg, con
     return CDL_OK;
 }
 
+cdl_status cdl_chain_densify(cdl_ctx *ctx, int64_t n, void *chain, size_t chain_bytes,
+                             cdl_chain_info *info) {
+    if (!ctx) return CDL_E_ARG;
+    if (!chain || !info || n < 2 || n > (1 << 20)) return fail(ctx, CDL_E_ARG, "bad arguments");
+    if (!aligned(chain, kAlign)) return fail(ctx, CDL_E_ARG, "misaligned pointer");
+    const int d = info->depth;
+    if (d < 1 || d > CDL_MAX_DEPTH || !valid_prec(info->prec)) return fail(ctx, CDL_E_ARG, "invalid chain info");
+    if (info->dense_levels != 0) return fail(ctx, CDL_E_ARG, "chain is already dense");
+    const int slots = d >= 2 ? d + 1 : 1;
+    Arena need(nullptr);
+    plan_chain(need, n, info->prec, slots);
+    if (chain_bytes < need.off) return fail(ctx, CDL_E_WORKSPACE, "chain buffer needs depth + 1 levels");
+    Arena a(chain);
+    ChainBuf c = plan_chain(a, n, info->prec, slots);
+    const int64_t ld = pad_n(n);
+    hipStream_t s = ctx->stream;
+    HIPCHK(hipSetDevice(ctx->device));
+    auto slot = [&](int l) { return c.levels + c.level_bytes * l; };
+    if (d >= 2) {
+        // Q_1 = L_0 + L_1 + L_0 L_1 into the scratch slot, then
+        // Q_{j} = Q_{j-1} + L_j + Q_{j-1} L_j alternating between the scratch
+        // slot and slot 0 (free once L_0 is consumed); Q ends in slot 0.
+        char *scratch = slot(d), *cur = scratch;
+        { Timed t_(ctx, "chain_product"); HIPCHK(launch_chain_product(info->prec, slot(0), slot(1), scratch, ld, n, c.fro, s)); }
+        for (int j = 2; j < d; ++j) {
+            char *dst = cur == scratch ? slot(0) : scratch;
+            { Timed t_(ctx, "chain_product"); HIPCHK(launch_chain_product(info->prec, cur, slot(j), dst, ld, n, c.fro, s)); }
+            cur = dst;
+        }
+        if (cur != slot(0)) HIPCHK(hipMemcpyAsync(slot(0), cur, c.level_bytes, hipMemcpyDeviceToDevice, s));
+    }
+    info->dense_levels = d;
+    info->depth = 1;
+    return CDL_OK;
+}
+
 // ---- embedding -------------------------------------------------------------------
 
 cdl_status cdl_solve_embedding(cdl_ctx *ctx, const double *W, const double *deg,
@@ -671,7 +707,8 @@ cdl_status cdl_solve_embedding(cdl_ctx *ctx, const double *W, const double *deg,
         k = (int64_t)std::ceil(std::log((double)n / eps_rp));
     }
     if (k > (int64_t)1 << 20) return fail(ctx, CDL_E_ARG, "k too large");
-    if (ci->depth < 1 || ci->depth > CDL_MAX_DEPTH || !valid_prec(ci->prec))
+    if (ci->depth < 1 || ci->depth > CDL_MAX_DEPTH || !valid_prec(ci->prec) ||
+        ci->dense_levels < 0 || ci->dense_levels > CDL_MAX_DEPTH || (ci->dense_levels > 0 && ci->depth != 1))
         return fail(ctx, CDL_E_ARG, "invalid chain info");
     if (max_iter < 1 || max_iter > 64) return fail(ctx, CDL_E_ARG, "max_iter must be in [1, 64]");
     if (solver != CDL_RICHARDSON && solver != CDL_PCG) return fail(ctx, CDL_E_ARG, "bad solver");
@@ -724,6 +761,7 @@ cdl_status cdl_solve_embedding(cdl_ctx *ctx, const double *W, const double *deg,
     bool conv = false;
     const int d = ci->depth;
     auto depth_now = [&]() {
+        if (ci->dense_levels > 0) return 1;   // the one stored matrix is the whole product
         return ctx->solve_depth > 0 ? ctx->solve_depth
                                     : (tol == 0.0 ? d : choose_depth(prec, n, k, d, rho_model, target / rel));
     };

@@ -146,10 +146,16 @@ template <typename T> constexpr size_t sq_smem() {
     return C::SMEM > stage ? C::SMEM : stage;
 }
 
+// C = A B (upper tiles, mirrored), scaled back by inv_scale; add != 0 also
+// adds A + B (the next factor of the dense chain product, below).  A and B
+// are polynomials in the same symmetric matrix, so they commute and C is
+// symmetric.  The squaring is A = B = S, add = 0.
 template <typename T>
-__global__ __launch_bounds__(SqCfg<T>::Core::NT) void k_square(const T *S, T *S2, int64_t ld, int64_t kend,
-                                                int nt, float inv_scale, double *fro_part) {
+__global__ __launch_bounds__(SqCfg<T>::Core::NT) void k_square(const T *A, const T *B, T *S2, int64_t ld,
+                                                int64_t kend, int nt, float inv_scale,
+                                                int add, double *fro_part) {
     using Core = typename SqCfg<T>::Core;
+    using Acc = typename Core::MF::Acc;
     constexpr int TL = SqCfg<T>::TILE;
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
     T *smem = (T *)smem_raw;
@@ -160,10 +166,15 @@ __global__ __launch_bounds__(SqCfg<T>::Core::NT) void k_square(const T *S, T *S2
     sym_tile<8>(id, nt, I, J);
     const int64_t m0 = (int64_t)I * TL, n0 = (int64_t)J * TL;
     Core g;
-    g.run(S, ld, S, ld, m0, n0, kend, smem);
+    g.run(A, ld, B, ld, m0, n0, kend, smem);
     double fro = 0.0;
-    auto f = [&](int, int, typename Core::MF::Acc acc) -> T {
-        T t = (T)(acc * inv_scale);
+    auto f = [&](int r, int c, Acc acc) -> T {
+        Acc v = acc * (Acc)inv_scale;
+        if (add) {
+            const int64_t o = (m0 + r) * ld + n0 + c;
+            v += (Acc)tod<T>(A[o]) + (Acc)tod<T>(B[o]);
+        }
+        T t = (T)v;
         double tv = tod<T>(t) * (double)inv_scale;
         fro += tv * tv;
         return t;
@@ -188,8 +199,8 @@ int square_tiles(int prec, int64_t ld) {
 }
 
 template <typename T>
-static hipError_t sq_launch(const void *S, void *S2, int64_t ld, int64_t n, float inv_scale,
-                            double *fro_part, hipStream_t s) {
+static hipError_t sq_launch(const void *A, const void *B, void *S2, int64_t ld, int64_t n,
+                            float inv_scale, int add, double *fro_part, hipStream_t s) {
     constexpr int TL = SqCfg<T>::TILE;
     constexpr size_t smem = sq_smem<T>();
     static bool attr = false;
@@ -204,19 +215,57 @@ static hipError_t sq_launch(const void *S, void *S2, int64_t ld, int64_t n, floa
     constexpr int BK = (int)(64 * 2 / sizeof(T)) < 16 ? 16 : (int)(64 * 2 / sizeof(T));
     const int64_t kend = (n + 63) / 64 * 64;   // multiple of every BK used (64/32/16)
     (void)BK;
-    hipLaunchKernelGGL(k_square<T>, dim3(total), dim3(SqCfg<T>::Core::NT), smem, s, (const T *)S, (T *)S2, ld,
-                       kend, nt, inv_scale, fro_part);
+    hipLaunchKernelGGL(k_square<T>, dim3(total), dim3(SqCfg<T>::Core::NT), smem, s, (const T *)A, (const T *)B,
+                       (T *)S2, ld, kend, nt, inv_scale, add, fro_part);
     return hipGetLastError();
+}
+
+static hipError_t sq_dispatch(int prec, const void *A, const void *B, void *C, int64_t ld, int64_t n,
+                              int add, double *fro_part, hipStream_t s) {
+    const float inv = 1.0f / level_scale(prec, n);
+    switch (prec) {
+    case 0: return sq_launch<double>(A, B, C, ld, n, inv, add, fro_part, s);
+    case 1: return sq_launch<float>(A, B, C, ld, n, inv, add, fro_part, s);
+    case 2: return sq_launch<__bf16>(A, B, C, ld, n, inv, add, fro_part, s);
+    case 3: return sq_launch<_Float16>(A, B, C, ld, n, inv, add, fro_part, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_square(int prec, const void *S, void *S2, int64_t ld, int64_t n,
                          double *fro_part, hipStream_t s) {
-    const float inv = 1.0f / level_scale(prec, n);
+    return sq_dispatch(prec, S, S, S2, ld, n, 0, fro_part, s);
+}
+
+// Inside a diagonal tile both triangles come out of the GEMM, and for A != B
+// C_ij and C_ji are sums in different orders: copy the upper triangle of each
+// diagonal tile onto its lower one so the stored product is exactly
+// symmetric.  One workgroup per diagonal tile.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sym_diag(T *C, int64_t ld, int TL) {
+    const int64_t t0 = (int64_t)blockIdx.x * TL;
+    for (int64_t q = threadIdx.x; q < (int64_t)TL * TL; q += 256) {
+        const int r = (int)(q / TL), c = (int)(q % TL);
+        if (r > c) C[(t0 + r) * ld + t0 + c] = C[(t0 + c) * ld + t0 + r];
+    }
+}
+
+template <typename T>
+static hipError_t sym_diag_launch(void *C, int64_t ld, hipStream_t s) {
+    const int TL = SqCfg<T>::TILE;
+    hipLaunchKernelGGL(k_sym_diag<T>, dim3((unsigned)(ld / TL)), dim3(256), 0, s, (T *)C, ld, TL);
+    return hipGetLastError();
+}
+
+hipError_t launch_chain_product(int prec, const void *Q, const void *L, void *C, int64_t ld,
+                                int64_t n, double *fro_part, hipStream_t s) {
+    hipError_t e = sq_dispatch(prec, Q, L, C, ld, n, 1, fro_part, s);
+    if (e != hipSuccess) return e;
     switch (prec) {
-    case 0: return sq_launch<double>(S, S2, ld, n, inv, fro_part, s);
-    case 1: return sq_launch<float>(S, S2, ld, n, inv, fro_part, s);
-    case 2: return sq_launch<__bf16>(S, S2, ld, n, inv, fro_part, s);
-    case 3: return sq_launch<_Float16>(S, S2, ld, n, inv, fro_part, s);
+    case 0: return sym_diag_launch<double>(C, ld, s);
+    case 1: return sym_diag_launch<float>(C, ld, s);
+    case 2: return sym_diag_launch<__bf16>(C, ld, s);
+    case 3: return sym_diag_launch<_Float16>(C, ld, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -69,6 +69,9 @@ hipError_t launch_normalize(int prec, const double *W, int64_t ld, int64_t n,
 int square_tiles(int prec, int64_t ld);   // number of partial norms written
 hipError_t launch_square(int prec, const void *S, void *S2, int64_t ld, int64_t n,
                          double *fro_part, hipStream_t s);
+// C = Q + L + Q L for commuting symmetric Q, L (levels' storage scale).
+hipError_t launch_chain_product(int prec, const void *Q, const void *L, void *C, int64_t ld,
+                                int64_t n, double *fro_part, hipStream_t s);
 // accumulate: V64 += S~ Vin (else V64 = S~ Vin); Vout = V64 rounded.
 // inv_vs != nullptr marks the last level: X += dm * V * (*inv_vs).  P is the
 // split-K partial buffer (apply_splits() x kpad x ld floats; unused for FP64).

@@ -85,6 +85,7 @@ def test_calls_reject_a_null_context(L):
     assert L.cdl_ctx_set_timing(None, 1) == 1
     assert L.cdl_ctx_set_solve_depth(None, 2) == 1
     assert L.cdl_ctx_set_select(None, 0) == 1
+    assert L.cdl_chain_densify(None, 100, None, 0, None) == 1
     assert L.cdl_timing_reset(None) == 1
     assert L.cdl_ctx_destroy(None) == 0
 

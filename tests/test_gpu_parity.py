@@ -144,6 +144,69 @@ def test_chain_levels_match_oracle(cdl, prec, tol):
         assert ch.info.fro[l] == pytest.approx(np.linalg.norm(lev[l]), rel=10 * tol * 2 ** l)
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 3e-6), ("bf16", 3e-2), ("fp16", 8e-3)])
+@pytest.mark.parametrize("depth", [1, 2, 4])
+def test_dense_chain_product_matches_oracle(cdl, prec, tol, depth):
+    # Algorithm 2's dense schedule: Q = prod_l (I + S~^{2^l}) - I in one
+    # stored matrix (scale of the level type), exactly symmetric, zero padding.
+    n = 300
+    X = series(n, 20, 11)
+    g = cdl.build_graph(dev(X))
+    W = host(g.W)[:n, :n]
+    deg, vol = oracle.degrees(W)
+    want = oracle.chain_product(oracle.chain_levels(oracle.normalized_deflated(W, deg, vol), depth)) - np.eye(n)
+    ch = cdl.build_chain(g, prec=prec, depth=depth, depth_max=depth)
+    print("dense chain prec=%s depth=%d" % (prec, depth), flush=True)
+    cdl.chain_densify(ch)
+    assert ch.depth == 1 and ch.dense_levels == depth
+    Qg = host(cdl.level(ch, 0).double()) / cdl.level_scale(ch)
+    np.testing.assert_array_equal(Qg, Qg.T)
+    assert np.all(Qg[n:, :] == 0) and np.all(Qg[:, n:] == 0)
+    e = rel(Qg[:n, :n], want)
+    print("  rel err %.3e" % e)
+    assert e <= tol * 2 ** (depth - 1)
+    with pytest.raises(cdl.CdlError):
+        cdl.chain_densify(ch)   # already dense
+
+
+def test_dense_chain_fixed_q_richardson_matches_oracle(cdl):
+    # The paper's schedule end to end: dense P1 from an 8-level FP64 chain,
+    # then EstimateSolution with q = 10 (one P1 product per step).
+    p = gen.make_pair(G=16, T=120, patches=1, patch_size=3)
+    g = cdl.build_graph(dev(p.X0))
+    ch = cdl.build_chain(g, prec="fp64", depth=8, depth_max=8)
+    cdl.set_timing(True)
+    cdl.timing(reset=True)
+    cdl.chain_densify(ch)
+    Z, info = cdl.solve_embedding(g, ch, 32, 7, tol=0.0, max_iter=9)
+    t = cdl.timing(reset=True)
+    cdl.set_timing(False)
+    assert info.iterations == 9 and list(info.depth_used[:9]) == [1] * 9
+    assert t["apply"][0] == 9           # one product with P1 per step
+    assert t["chain_product"][0] == 7   # d - 1 products formed it
+    W = host(g.W)[:256, :256]
+    deg, vol = oracle.degrees(W)
+    lev = oracle.chain_levels(oracle.normalized_deflated(W, deg, vol), 8)
+    Zo = oracle.estimate_solution(W, deg, oracle.rhs(W, 32, 7), lev, q=10)
+    Zo -= Zo.mean(axis=0)
+    assert rel(host(Z), Zo) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+def test_dense_chain_solve_converges(cdl, prec):
+    # With a rounded dense P1 the FP64 residual still drives Z to L^+ Y.
+    n, k = 300, 40
+    X = series(n, 24, 7)
+    g = cdl.build_graph(dev(X))
+    ch = cdl.build_chain(g, prec=prec, depth=3, depth_max=3)
+    cdl.chain_densify(ch)   # grows the buffer for the scratch level
+    Z, info = cdl.solve_embedding(g, ch, k, 1234, tol=1e-11, max_iter=40)
+    o = oracle.build_graph(X)
+    Zo = oracle.solve_embedding(o["W"], oracle.rhs(o["W"], k, 1234))
+    print("dense %s: iterations %d residual %.1e" % (prec, info.iterations, info.rel_residual))
+    assert info.converged and rel(host(Z), Zo) <= 1e-9
+
+
 def test_chain_complete_graph_closed_form(cdl):
     # K_n: S~ = -Pi/(n-1), S~^{2^l} = Pi/(n-1)^{2^l} (exact in FP64)
     n = 200
