@@ -82,13 +82,16 @@ __global__ __launch_bounds__(256) void k_normalize(const double *W, int64_t ld, 
     const int64_t j = j0 + lane;
     const double dj = j < n ? dmn[j] : 0.0, uj = j < n ? u[j] : 0.0;
     double s = 0.0, s64 = 0.0;
-#pragma unroll 4
+    double wl[16];   // all sixteen row loads in flight before the first use
+#pragma unroll
+    for (int rr = 0; rr < 16; ++rr) wl[rr] = W[(i0 + wv * 16 + rr) * ld + j];
+#pragma unroll
     for (int rr = 0; rr < 16; ++rr) {
         const int r = wv * 16 + rr;
         const int64_t i = i0 + r;
         double v = 0.0;
         if (i < n && j < n) {
-            v = W[i * ld + j] * (dmn[i] * dj);
+            v = wl[rr] * (dmn[i] * dj);
             if (lazy) v = 0.5 * ((i == j ? 1.0 : 0.0) + v);
             v -= u[i] * uj;
         }

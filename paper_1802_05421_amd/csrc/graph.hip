@@ -556,13 +556,15 @@ __global__ __launch_bounds__(256) void k_exp_sym(double *W, int64_t ld, int64_t 
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t j = j0 + lane;
     double csum = 0.0;
-#pragma unroll 4
+    double d2[16];   // all sixteen row loads in flight before the first exp
+#pragma unroll
+    for (int rr = 0; rr < 16; ++rr) d2[rr] = W[(i0 + wv * 16 + rr) * ld + j];
+#pragma unroll
     for (int rr = 0; rr < 16; ++rr) {
         const int r = wv * 16 + rr;
         const int64_t i = i0 + r;
-        double *p = W + i * ld + j;
-        const double v = (i < n && j < n && i != j) ? exp(-*p / s2) : 0.0;
-        *p = v;
+        const double v = (i < n && j < n && i != j) ? exp(-d2[rr] / s2) : 0.0;
+        W[i * ld + j] = v;
         t[r][lane] = v;
         csum += v;
     }
