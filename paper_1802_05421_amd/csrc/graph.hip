@@ -86,21 +86,34 @@ hipError_t launch_pad_series(const double *X, int64_t n, int64_t T, int64_t ldx,
 // ---------------------------------------------------------------------------
 // Squared distances from the Gram matrix of the series (FP64 MFMA).
 
-using GramCore = GemmCore<MfmaF64, 128, 128, 8, 2, 4>;
+// 256 x 128 tiles (each wave 64 x 64: 16 MFMAs per 8 fragment reads), BK 16.
+using GramCore = GemmCore<MfmaF64, 256, 128, 16, 4, 2>;
 constexpr size_t kGramSmem = GramCore::SMEM;
+
+// Upper-triangle cover by 256 x 128 tiles: row block I takes the column
+// blocks J = 2I .. ncol - 1, so block I starts at I (ncol + 1 - I).
+__device__ inline void gram_tile(int id, int ncol, int &I, int &J) {
+    const double b = (double)ncol + 1.0;
+    int i = (int)((b - sqrt(b * b - 4.0 * (double)id)) * 0.5);
+    i = i < 0 ? 0 : i;
+    while (i > 0 && (int64_t)i * (ncol + 1 - i) > id) --i;
+    while ((int64_t)(i + 1) * (ncol - i) <= id) ++i;
+    I = i;
+    J = 2 * i + (id - i * (ncol + 1 - i));
+}
 
 // st != nullptr: also fold the smallest and largest upper-triangle key
 // (i < j) into st->kmin / st->kmax (the median selection starts below their
 // common bit prefix).
 __global__ __launch_bounds__(512) void k_gram_dist(const double *Xp, int64_t Tp,
                                                    const double *sqn, int64_t n, int64_t ld,
-                                                   double *D2, int nt, SelectState *st) {
+                                                   double *D2, int ncol, int total,
+                                                   SelectState *st) {
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
     double *smem = (double *)smem_raw;
-    const int total = nt * (nt + 1) / 2;
     int I, J;
-    sym_tile<8>(xcd_remap(blockIdx.x, total), nt, I, J);
-    const int64_t m0 = (int64_t)I * 128, n0 = (int64_t)J * 128;
+    gram_tile(xcd_remap(blockIdx.x, total), ncol, I, J);
+    const int64_t m0 = (int64_t)I * 256, n0 = (int64_t)J * 128;
     GramCore g;
     g.run(Xp, Tp, Xp, Tp, m0, n0, Tp, smem);
     unsigned long long kmin = ~0ull, kmax = 0ull;
@@ -150,10 +163,10 @@ hipError_t launch_gram_dist(const double *Xp, int64_t Tp, const double *sqn, int
         if (e != hipSuccess) return e;
         attr = true;
     }
-    const int nt = (int)(ld / 128);
-    const int total = nt * (nt + 1) / 2;
+    const int ncol = (int)(ld / 128), nrow = (int)(ld / 256);
+    const int total = nrow * ncol - nrow * (nrow - 1);   // sum over I of ncol - 2I
     hipLaunchKernelGGL(k_gram_dist, dim3(total), dim3(512), kGramSmem, s, Xp, Tp, sqn, n, ld,
-                       D2, nt, st);
+                       D2, ncol, total, st);
     return hipGetLastError();
 }
 
