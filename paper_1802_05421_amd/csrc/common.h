@@ -110,6 +110,24 @@ template <> __device__ inline double tod<double>(double x) { return x; }
 // XCDs, each with its own L2; remapping so that consecutive logical tiles
 // land on the same XCD lets neighbouring tiles share operand panels in L2.
 
+// Upper-triangle cover by 256 x 128 tiles of an ld x ld matrix (ncol =
+// ld / 128 column blocks, ld / 256 row blocks): row block I takes the column
+// blocks J = 2I .. ncol - 1, so its tiles start at id = I (ncol + 1 - I);
+// rect_upper_tiles(ld) = nrow ncol - nrow (nrow - 1) tiles in all.
+__device__ inline void upper_rect_tile(int id, int ncol, int &I, int &J) {
+    const double b = (double)ncol + 1.0;
+    int i = (int)((b - sqrt(b * b - 4.0 * (double)id)) * 0.5);
+    i = i < 0 ? 0 : i;
+    while (i > 0 && (int64_t)i * (ncol + 1 - i) > id) --i;
+    while ((int64_t)(i + 1) * (ncol - i) <= id) ++i;
+    I = i;
+    J = 2 * i + (id - i * (ncol + 1 - i));
+}
+__host__ __device__ inline int rect_upper_tiles(int64_t ld) {
+    const int ncol = (int)(ld / 128), nrow = (int)(ld / 256);
+    return nrow * ncol - nrow * (nrow - 1);
+}
+
 __device__ inline int xcd_remap(int w, int total) {
     int x = w % kNumXcd, j = w / kNumXcd;
     int base = total / kNumXcd, rem = total % kNumXcd;

@@ -90,17 +90,7 @@ hipError_t launch_pad_series(const double *X, int64_t n, int64_t T, int64_t ldx,
 using GramCore = GemmCore<MfmaF64, 256, 128, 16, 4, 2>;
 constexpr size_t kGramSmem = GramCore::SMEM;
 
-// Upper-triangle cover by 256 x 128 tiles: row block I takes the column
-// blocks J = 2I .. ncol - 1, so block I starts at I (ncol + 1 - I).
-__device__ inline void gram_tile(int id, int ncol, int &I, int &J) {
-    const double b = (double)ncol + 1.0;
-    int i = (int)((b - sqrt(b * b - 4.0 * (double)id)) * 0.5);
-    i = i < 0 ? 0 : i;
-    while (i > 0 && (int64_t)i * (ncol + 1 - i) > id) --i;
-    while ((int64_t)(i + 1) * (ncol - i) <= id) ++i;
-    I = i;
-    J = 2 * i + (id - i * (ncol + 1 - i));
-}
+
 
 // st != nullptr: also fold the smallest and largest upper-triangle key
 // (i < j) into st->kmin / st->kmax (the median selection starts below their
@@ -112,7 +102,7 @@ __global__ __launch_bounds__(512) void k_gram_dist(const double *Xp, int64_t Tp,
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
     double *smem = (double *)smem_raw;
     int I, J;
-    gram_tile(xcd_remap(blockIdx.x, total), ncol, I, J);
+    upper_rect_tile(xcd_remap(blockIdx.x, total), ncol, I, J);
     const int64_t m0 = (int64_t)I * 256, n0 = (int64_t)J * 128;
     GramCore g;
     g.run(Xp, Tp, Xp, Tp, m0, n0, Tp, smem);
@@ -163,8 +153,8 @@ hipError_t launch_gram_dist(const double *Xp, int64_t Tp, const double *sqn, int
         if (e != hipSuccess) return e;
         attr = true;
     }
-    const int ncol = (int)(ld / 128), nrow = (int)(ld / 256);
-    const int total = nrow * ncol - nrow * (nrow - 1);   // sum over I of ncol - 2I
+    const int ncol = (int)(ld / 128);
+    const int total = rect_upper_tiles(ld);
     hipLaunchKernelGGL(k_gram_dist, dim3(total), dim3(512), kGramSmem, s, Xp, Tp, sqn, n, ld,
                        D2, ncol, total, st);
     return hipGetLastError();

@@ -110,7 +110,9 @@ hipError_t launch_build_zhat(const double *Z0, const double *Z1, const int32_t *
                              const int32_t *map1, int64_t m, int64_t mpad, int64_t k,
                              int64_t kpad, const double *stats0, const double *stats1,
                              double *Zh, double *Zhe, double *sq, hipStream_t s);
+// Partial-sum slots of mpad entries each (mpad / 128 + mpad / 256).
 int score_tiles_1d(int64_t mpad);
+// Score tiles: 256 x 128 over the upper triangle (rect_upper_tiles).
 // tmax: per-tile maximum edge score (a < b), score_tiles_2d(mpad) entries,
 // or nullptr.
 hipError_t launch_score(const double *Zh, const double *Zhe, int64_t kpad, const double *sq,

@@ -61,8 +61,11 @@ hipError_t launch_build_zhat(const double *Z0, const double *Z1, const int32_t *
     return hipGetLastError();
 }
 
-using ScoreCore = GemmCore<MfmaF64, 128, 128, 16, 2, 4>;
-constexpr int kScoreWM = 2, kScoreWN = 4;
+// 256 x 128 tiles covering the upper triangle (upper_rect_tile); each wave
+// 64 x 64.  Only pairs a < b count: a tile straddling the diagonal also holds
+// pairs a > b, whose mirror images another tile covers.
+using ScoreCore = GemmCore<MfmaF64, 256, 128, 16, 4, 2>;
+constexpr int kScoreWM = 4, kScoreWN = 2;
 
 // Edge score omega_ab |c_0(a,b) - c_1(a,b)| of common nodes a != b from the
 // signature Gram entry G_ab (shared by the node and the edge kernels, so
@@ -80,23 +83,25 @@ __device__ inline double edge_score(int64_t ga, int64_t gb, double G, const doub
     return v;
 }
 
-// tmax != nullptr: also the largest edge score of the tile over a < b, at
-// the tile's logical index.
+// Partial sums: row a's sum over the columns of tile (I, J) goes to
+// part[J][a], column b's sum over the rows of the tile to part[ncol + I][b];
+// each slot has exactly one writer.  tmax != nullptr: also the largest edge
+// score of the tile over a < b, at the tile's logical index.
 __global__ __launch_bounds__(512) void k_score(const double *Zh, const double *Zhe,
                                                int64_t ldz, const double *sq, int64_t m,
                                                int64_t mpad, const double *W0, int64_t ld0,
                                                const double *W1, int64_t ld1,
                                                const int32_t *map0, const int32_t *map1,
-                                               int weighted, int nt, double *part,
+                                               int weighted, int ncol, double *part,
                                                double *tmax) {
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
     double *smem = (double *)smem_raw;
-    __shared__ double srow[kScoreWN][128], scol[kScoreWM][128], smax[8];
-    const int total = nt * (nt + 1) / 2;
+    __shared__ double srow[kScoreWN][256], scol[kScoreWM][128], smax[8];
+    const int total = rect_upper_tiles(mpad);
     const int id = xcd_remap(blockIdx.x, total);
     int I, J;
-    sym_tile<8>(id, nt, I, J);
-    const int64_t m0 = (int64_t)I * 128, n0 = (int64_t)J * 128;
+    upper_rect_tile(id, ncol, I, J);
+    const int64_t m0 = (int64_t)I * 256, n0 = (int64_t)J * 128;
     ScoreCore g;
     g.run(Zh, ldz, Zhe, ldz, m0, n0, ldz, smem);
 
@@ -116,10 +121,10 @@ __global__ __launch_bounds__(512) void k_score(const double *Zh, const double *Z
             for (int b = 0; b < ScoreCore::WTN; ++b) {
                 const int64_t gb = n0 + ScoreCore::col_of(b);
                 double v = 0.0;
-                if (ga < m && gb < m && ga != gb) {
+                if (ga < gb && gb < m) {
                     v = edge_score(ga, gb, g.acc[a][b][rr], sq, W0, ld0, W1, ld1, map0, map1,
                                    weighted);
-                    if (ga < gb) vmax = fmax(vmax, v);
+                    vmax = fmax(vmax, v);
                 }
                 rs += v;
                 cs[b] += v;
@@ -146,18 +151,21 @@ __global__ __launch_bounds__(512) void k_score(const double *Zh, const double *Z
         for (int q = 1; q < ScoreCore::NT / 64; ++q) mx = fmax(mx, smax[q]);
         tmax[id] = mx;
     }
-    for (int t = threadIdx.x; t < 128; t += ScoreCore::NT) {
-        double rs = 0.0, cs2 = 0.0;
+    for (int t = threadIdx.x; t < 256; t += ScoreCore::NT) {
+        double rs = 0.0;
 #pragma unroll
         for (int q = 0; q < kScoreWN; ++q) rs += srow[q][t];
+        part[(int64_t)J * mpad + m0 + t] = rs;
+    }
+    for (int t = threadIdx.x; t < 128; t += ScoreCore::NT) {
+        double cs2 = 0.0;
 #pragma unroll
         for (int q = 0; q < kScoreWM; ++q) cs2 += scol[q][t];
-        part[(int64_t)J * mpad + m0 + t] = rs;
-        if (I != J) part[(int64_t)I * mpad + n0 + t] = cs2;
+        part[(int64_t)(ncol + I) * mpad + n0 + t] = cs2;
     }
 }
 
-int score_tiles_1d(int64_t mpad) { return (int)(mpad / 128); }
+int score_tiles_1d(int64_t mpad) { return (int)(mpad / 128 + mpad / 256); }
 
 hipError_t launch_score(const double *Zh, const double *Zhe, int64_t kpad, const double *sq,
                         int64_t m, int64_t mpad, const double *W0, int64_t ld0,
@@ -172,17 +180,14 @@ hipError_t launch_score(const double *Zh, const double *Zhe, int64_t kpad, const
         if (e != hipSuccess) return e;
         attr = true;
     }
-    const int nt = (int)(mpad / 128);
-    const int total = nt * (nt + 1) / 2;
+    const int ncol = (int)(mpad / 128);
+    const int total = rect_upper_tiles(mpad);
     hipLaunchKernelGGL(k_score, dim3(total), dim3(ScoreCore::NT), ScoreCore::SMEM, s, Zh, Zhe, 2 * kpad,
-                       sq, m, mpad, W0, ld0, W1, ld1, map0, map1, weighted, nt, part, tmax);
+                       sq, m, mpad, W0, ld0, W1, ld1, map0, map1, weighted, ncol, part, tmax);
     return hipGetLastError();
 }
 
-int score_tiles_2d(int64_t mpad) {
-    const int nt = (int)(mpad / 128);
-    return nt * (nt + 1) / 2;
-}
+int score_tiles_2d(int64_t mpad) { return rect_upper_tiles(mpad); }
 
 // ---------------------------------------------------------------------------
 // Top edges.  The K largest tile maxima are K distinct edges, so the K-th
@@ -201,17 +206,17 @@ __global__ void k_edge_threshold(const double *tmax, const int32_t *tile_order, 
 __global__ __launch_bounds__(512) void k_edge_collect(
     const double *Zh, const double *Zhe, int64_t ldz, const double *sq, int64_t m,
     const double *W0, int64_t ld0, const double *W1, int64_t ld1, const int32_t *map0,
-    const int32_t *map1, int weighted, int nt, const double *tmax, const double *tau,
-    int64_t cap, unsigned int *count, double *cval, int64_t *cidx) {
+    const int32_t *map1, int weighted, int ncol, int64_t mpad, const double *tmax,
+    const double *tau, int64_t cap, unsigned int *count, double *cval, int64_t *cidx) {
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
     double *smem = (double *)smem_raw;
-    const int total = nt * (nt + 1) / 2;
+    const int total = rect_upper_tiles(mpad);
     const int id = xcd_remap(blockIdx.x, total);
     const double th = *tau;
     if (tmax[id] < th) return;   // uniform over the workgroup
     int I, J;
-    sym_tile<8>(id, nt, I, J);
-    const int64_t m0 = (int64_t)I * 128, n0 = (int64_t)J * 128;
+    upper_rect_tile(id, ncol, I, J);
+    const int64_t m0 = (int64_t)I * 256, n0 = (int64_t)J * 128;
     ScoreCore g;
     g.run(Zh, ldz, Zhe, ldz, m0, n0, ldz, smem);
 #pragma unroll
@@ -252,29 +257,35 @@ hipError_t launch_edge_collect(const double *Zh, const double *Zhe, int64_t kpad
         if (e != hipSuccess) return e;
         attr = true;
     }
-    const int nt = (int)(mpad / 128);
-    const int total = nt * (nt + 1) / 2;
+    const int ncol = (int)(mpad / 128);
+    const int total = rect_upper_tiles(mpad);
     hipLaunchKernelGGL(k_edge_threshold, dim3(1), dim3(64), 0, s, tmax, tile_order, K, total, tau,
                        count);
     hipLaunchKernelGGL(k_edge_collect, dim3(total), dim3(ScoreCore::NT), ScoreCore::SMEM, s, Zh,
-                       Zhe, 2 * kpad, sq, m, W0, ld0, W1, ld1, map0, map1, weighted, nt, tmax,
-                       tau, cap, count, cval, cidx);
+                       Zhe, 2 * kpad, sq, m, W0, ld0, W1, ld1, map0, map1, weighted, ncol, mpad,
+                       tmax, tau, cap, count, cval, cidx);
     return hipGetLastError();
 }
 
-__global__ void k_score_reduce(const double *part, int nparts, int64_t m, int64_t mpad,
+// F_a = its row partials over the column blocks J >= 2 (a / 256), then its
+// column partials over the row blocks I <= (a / 128) / 2: exactly the slots
+// the score tiles wrote, summed in a fixed order.
+__global__ void k_score_reduce(const double *part, int ncol, int64_t m, int64_t mpad,
                                double *F) {
     int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= m) return;
     double s = 0.0;
-    for (int t = 0; t < nparts; ++t) s += part[(int64_t)t * mpad + a];
+    for (int J = (int)(a / 256) * 2; J < ncol; ++J) s += part[(int64_t)J * mpad + a];
+    const int Imax = (int)(a / 128) / 2;
+    for (int I = 0; I <= Imax; ++I) s += part[(int64_t)(ncol + I) * mpad + a];
     F[a] = s;
 }
 
 hipError_t launch_score_reduce(const double *part, int nparts, int64_t m, int64_t mpad,
                                double *F, hipStream_t s) {
+    (void)nparts;   // the slot layout follows from mpad
     hipLaunchKernelGGL(k_score_reduce, dim3((unsigned)cdiv(m, 256)), dim3(256), 0, s, part,
-                       nparts, m, mpad, F);
+                       (int)(mpad / 128), m, mpad, F);
     return hipGetLastError();
 }
 
