@@ -107,10 +107,19 @@ __global__ __launch_bounds__(512) void k_gram_dist(const double *Xp, int64_t Tp,
     GramCore g;
     g.run(Xp, Tp, Xp, Tp, m0, n0, Tp, smem);
     unsigned long long kmin = ~0ull, kmax = 0ull;
-    auto f = [&](int r, int c, double acc) -> double {
+    // the squared norms of this lane's rows and columns, loaded once (the
+    // stores below may alias sqn as far as the compiler knows)
+    double sa[GramCore::WTM][MfmaF64::R], sb[GramCore::WTN];
+#pragma unroll
+    for (int a = 0; a < GramCore::WTM; ++a)
+#pragma unroll
+        for (int rr = 0; rr < MfmaF64::R; ++rr) sa[a][rr] = sqn[m0 + GramCore::row_of(a, rr)];
+#pragma unroll
+    for (int b = 0; b < GramCore::WTN; ++b) sb[b] = sqn[n0 + GramCore::col_of(b)];
+    auto f = [&](int r, int c, double acc, double sqa, double sqb) -> double {
         const int64_t a = m0 + r, b = n0 + c;
         if (a >= n || b >= n || a == b) return 0.0;
-        double d = sqn[a] + sqn[b] - 2.0 * acc;
+        double d = sqa + sqb - 2.0 * acc;
         d = d < 0.0 ? 0.0 : d;
         if (a < b) {
             const unsigned long long key = (unsigned long long)__double_as_longlong(d);
@@ -127,7 +136,7 @@ __global__ __launch_bounds__(512) void k_gram_dist(const double *Xp, int64_t Tp,
 #pragma unroll
             for (int rr = 0; rr < MfmaF64::R; ++rr) {
                 const int r = GramCore::row_of(a, rr), c = GramCore::col_of(b);
-                D2[(m0 + r) * ld + n0 + c] = f(r, c, g.acc[a][b][rr]);
+                D2[(m0 + r) * ld + n0 + c] = f(r, c, g.acc[a][b][rr], sa[a][rr], sb[b]);
             }
     if (st) {
 #pragma unroll

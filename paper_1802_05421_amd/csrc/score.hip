@@ -70,11 +70,11 @@ constexpr int kScoreWM = 4, kScoreWN = 2;
 // Edge score omega_ab |c_0(a,b) - c_1(a,b)| of common nodes a != b from the
 // signature Gram entry G_ab (shared by the node and the edge kernels, so
 // both see bit-identical values).
-__device__ inline double edge_score(int64_t ga, int64_t gb, double G, const double *sq,
+__device__ inline double edge_score(int64_t ga, int64_t gb, double G, double sqa, double sqb,
                                     const double *W0, int64_t ld0, const double *W1,
                                     int64_t ld1, const int32_t *map0, const int32_t *map1,
                                     int weighted) {
-    double v = fabs(sq[ga] + sq[gb] - 2.0 * G);
+    double v = fabs(sqa + sqb - 2.0 * G);
     if (weighted) {
         const int64_t a0 = map0 ? map0[ga] : ga, b0 = map0 ? map0[gb] : gb;
         const int64_t a1 = map1 ? map1[ga] : ga, b1 = map1 ? map1[gb] : gb;
@@ -107,23 +107,27 @@ __global__ __launch_bounds__(512) void k_score(const double *Zh, const double *Z
 
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int wm = wid % kScoreWM, wn = wid / kScoreWM;
-    double cs[ScoreCore::WTN], vmax = -1.0;
+    double cs[ScoreCore::WTN], vmax = -1.0, sqb[ScoreCore::WTN];
 #pragma unroll
-    for (int b = 0; b < ScoreCore::WTN; ++b) cs[b] = 0.0;
+    for (int b = 0; b < ScoreCore::WTN; ++b) {
+        cs[b] = 0.0;
+        sqb[b] = sq[n0 + ScoreCore::col_of(b)];
+    }
 #pragma unroll
     for (int a = 0; a < ScoreCore::WTM; ++a)
 #pragma unroll
         for (int rr = 0; rr < MfmaF64::R; ++rr) {
             const int lr = ScoreCore::row_of(a, rr);
             const int64_t ga = m0 + lr;
+            const double sqa = sq[ga];
             double rs = 0.0;
 #pragma unroll
             for (int b = 0; b < ScoreCore::WTN; ++b) {
                 const int64_t gb = n0 + ScoreCore::col_of(b);
                 double v = 0.0;
                 if (ga < gb && gb < m) {
-                    v = edge_score(ga, gb, g.acc[a][b][rr], sq, W0, ld0, W1, ld1, map0, map1,
-                                   weighted);
+                    v = edge_score(ga, gb, g.acc[a][b][rr], sqa, sqb[b], W0, ld0, W1, ld1, map0,
+                                   map1, weighted);
                     vmax = fmax(vmax, v);
                 }
                 rs += v;
@@ -228,8 +232,8 @@ __global__ __launch_bounds__(512) void k_edge_collect(
             for (int b = 0; b < ScoreCore::WTN; ++b) {
                 const int64_t gb = n0 + ScoreCore::col_of(b);
                 if (ga < m && gb < m && ga < gb) {
-                    const double v = edge_score(ga, gb, g.acc[a][b][rr], sq, W0, ld0, W1, ld1,
-                                                map0, map1, weighted);
+                    const double v = edge_score(ga, gb, g.acc[a][b][rr], sq[ga], sq[gb], W0, ld0,
+                                                W1, ld1, map0, map1, weighted);
                     if (v >= th) {
                         const unsigned int q = atomicAdd(count, 1u);
                         if ((int64_t)q < cap) {
