@@ -356,9 +356,10 @@ def main():
                     "max_iterations": sinfo.max_iterations,
                     "max_rel_residual": sinfo.max_rel_residual}
         log("sequence: %d pairs in %.1f ms" % (sinfo.pairs, ms_seq * 1e3))
-        # The same sequence enqueued with no host reads, then replayed as a HIP
-        # graph: every chain at the largest depth the adaptive rule picks over
-        # the snapshots, every solve at the largest iteration count above (two
+        # The same sequence enqueued with no host reads, consecutive snapshots
+        # on two streams, then also captured and replayed as a HIP graph:
+        # every chain at the largest depth the adaptive rule picks over the
+        # snapshots, every solve at the largest iteration count above (two
         # more per retry); the library rejects the call if any final residual
         # stays above 1e-8.
         dfix = 1
@@ -370,11 +371,25 @@ def main():
         iters, err, replay = sinfo.max_iterations, None, None
         for attempt in range(3):
             spa = cdl.SeqParams(k=128, seed=seed, prec=args.mixed, depth=dfix, tol=1e-8,
+                                max_iter=iters, top_k=50, asynchronous=True, graph=True)
+            spe = cdl.SeqParams(k=128, seed=seed, prec=args.mixed, depth=dfix, tol=1e-8,
                                 max_iter=iters, top_k=50, asynchronous=True)
             try:
                 sws = torch.empty(cdl.sequence_workspace_bytes(Xs, gdev, spa), dtype=torch.uint8,
                                   device=dev)
-                Fa, ta, ainfo = cdl.score_sequence(Xs, gdev, spa, ws=sws)   # eager enqueue
+                Fa, ta, ainfo = cdl.score_sequence(Xs, gdev, spe, ws=sws, out=None)   # warm-up
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(3):
+                    Fa, ta, ainfo = cdl.score_sequence(Xs, gdev, spe, ws=sws, out=(Fa, ta))
+                torch.cuda.synchronize()
+                ms_async = (time.perf_counter() - t0) / 3
+                sequence["async_two_streams"] = {
+                    "ms_per_sequence": round(ms_async * 1e3, 2),
+                    "pairs_per_s": round(ainfo.pairs / ms_async, 2), "chain_depth": dfix,
+                    "iterations": iters, "max_rel_residual": ainfo.max_rel_residual}
+                log("sequence, two streams, no host reads: %.1f ms" % (ms_async * 1e3))
+                Fa, ta, ainfo = cdl.score_sequence(Xs, gdev, spa, ws=sws, out=(Fa, ta))   # eager enqueue
                 Fa, ta, ainfo = cdl.score_sequence(Xs, gdev, spa, ws=sws, out=(Fa, ta))   # capture
                 torch.cuda.synchronize()
                 reps = 3

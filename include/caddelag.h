@@ -123,22 +123,27 @@ typedef struct {
     int max_iter;
     cdl_score_mode mode;
     int32_t top_k;
-    int32_t flags;             /* 0, or CDL_SEQ_ASYNC */
+    int32_t flags;             /* 0, CDL_SEQ_ASYNC, or CDL_SEQ_ASYNC | CDL_SEQ_GRAPH */
 } cdl_seq_params;
 
-/* cdl_seq_params.flags: enqueue the whole sequence with no host reads
- * between kernels (fixed depth, Richardson with exactly max_iter
- * iterations, every pair's common-node map uploaded first); one read-back
- * at the end checks every graph and residual.  A call whose buffers, sizes,
- * parameters and global ids equal the previous async call on the context is
- * captured into a HIP graph; later such calls replay it. */
+/* cdl_seq_params.flags.  CDL_SEQ_ASYNC: enqueue the whole sequence with no
+ * host reads between kernels (fixed depth, Richardson with exactly max_iter
+ * iterations, every pair's common-node map uploaded first), alternate
+ * snapshots on the context's stream and a second stream of the context
+ * (consecutive snapshots overlap; a pair is scored once both are done); one
+ * read-back at the end checks every graph and residual.
+ * CDL_SEQ_GRAPH (with CDL_SEQ_ASYNC): a call whose buffers, sizes,
+ * parameters and global ids equal the previous graph call on the context is
+ * captured into a HIP graph (both streams), later such calls replay it with
+ * one launch. */
 #define CDL_SEQ_ASYNC 1
+#define CDL_SEQ_GRAPH 2
 
 typedef struct {
     int32_t pairs;             /* number of scored pairs (n_snap - 1) */
     int32_t max_iterations;    /* largest iteration count over the solves */
     double max_rel_residual;   /* largest final residual over the solves */
-    int32_t graph_launches;    /* CDL_SEQ_ASYNC: 1 if the call ran as a HIP graph */
+    int32_t graph_launches;    /* CDL_SEQ_GRAPH: 1 if the call ran as a HIP graph */
 } cdl_seq_info;
 
 /* ---- context --------------------------------------------------------- */

@@ -339,8 +339,10 @@ class SeqParams:
     mode: str = "unweighted"
     top_k: int = 50
     # No host reads inside the sequence (fixed depth, exactly max_iter
-    # Richardson steps); a repeat of the previous call replays a HIP graph.
+    # Richardson steps), snapshots alternating over two streams.
     asynchronous: bool = False
+    # With asynchronous: a repeat of the previous call replays a HIP graph.
+    graph: bool = False
 
 
 def _seq_args(Xs, gids, p: SeqParams):
@@ -358,7 +360,7 @@ def _seq_args(Xs, gids, p: SeqParams):
     q = L.SeqParams(k=p.k, seed=p.seed, sigma=p.sigma, prec=L.PREC[p.prec], depth=p.depth,
                     depth_max=p.depth_max, chain_eps=p.chain_eps, solver=L.SOLVER[p.solver],
                     tol=p.tol, max_iter=p.max_iter, mode=L.MODE[p.mode], top_k=p.top_k,
-                    flags=1 if p.asynchronous else 0)
+                    flags=(1 if p.asynchronous else 0) | (2 if p.graph else 0))
     return snaps, q, gid_host, gid_dev
 
 

@@ -36,6 +36,7 @@ struct cdl_ctx {
     std::vector<uint64_t> seq_key;
     hipGraph_t seq_graph = nullptr;
     hipGraphExec_t seq_exec = nullptr;
+    hipStream_t side = nullptr;   // second stream of asynchronous sequences (created on first use)
 };
 
 namespace {
@@ -433,6 +434,7 @@ cdl_status cdl_ctx_destroy(cdl_ctx *ctx) {
     for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
     if (ctx->seq_exec) (void)hipGraphExecDestroy(ctx->seq_exec);
     if (ctx->seq_graph) (void)hipGraphDestroy(ctx->seq_graph);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
     delete ctx;
     return CDL_OK;
 }
@@ -1044,6 +1046,12 @@ size_t seq_bytes(const SeqPlan &p, const cdl_seq_params *q) {
     tot += g + c + so + sc;
     tot += 2 * al((size_t)p.ntot * sizeof(int32_t));             // all pair maps (async)
     tot += al((size_t)p.nsnap * (CDL_GRAPH_STATS + 2 * pad_k(q->k)) * sizeof(double));   // status
+    if (q->flags & CDL_SEQ_ASYNC) {
+        // two streams: a third set of per-snapshot state, a second set of workspaces
+        tot += al(ld * ld * sizeof(double)) + al(ld * sizeof(double)) +
+               al(CDL_GRAPH_STATS * sizeof(double)) + al((size_t)p.nmax * q->k * sizeof(double));
+        tot += g + c + so + sc;
+    }
     return tot;
 }
 } // namespace
@@ -1076,6 +1084,8 @@ cdl_status cdl_score_sequence(cdl_ctx *ctx, int32_t n_snap, const cdl_snapshot *
     const SeqPlan plan = seq_plan(n_snap, sn);
     if (ws_bytes < seq_bytes(plan, q)) return fail(ctx, CDL_E_WORKSPACE, "sequence workspace too small");
     const bool async = (q->flags & CDL_SEQ_ASYNC) != 0;
+    if ((q->flags & ~(CDL_SEQ_ASYNC | CDL_SEQ_GRAPH)) != 0 || ((q->flags & CDL_SEQ_GRAPH) && !async))
+        return fail(ctx, CDL_E_ARG, "bad sequence flags");
     if (async) {
         // the enqueue helpers check nothing: every argument is checked here
         if (q->depth < 1 || q->depth > CDL_MAX_DEPTH || q->solver != CDL_RICHARDSON || !(q->tol >= 0.0))
@@ -1111,6 +1121,21 @@ cdl_status cdl_score_sequence(cdl_ctx *ctx, int32_t n_snap, const cdl_snapshot *
         if (info) std::memset(info, 0, sizeof(*info));
         hipStream_t s = ctx->stream;
         HIPCHK(hipSetDevice(ctx->device));
+        // per-snapshot state rotates over three sets (snapshot t + 3 reuses t's
+        // only after every reader of t's set is done); workspaces per stream
+        double *W3[3] = {Wb[0], Wb[1], a.take<double>(ld * ld)};
+        double *deg3[3] = {degb[0], degb[1], a.take<double>(ld)};
+        double *st3[3] = {stb[0], stb[1], a.take<double>(CDL_GRAPH_STATS)};
+        double *Z3[3] = {Zb[0], Zb[1], a.take<double>((size_t)plan.nmax * q->k)};
+        char *gws2[2] = {gws, a.take<char>(gB)}, *cws2[2] = {cws, a.take<char>(cB)};
+        char *sows2[2] = {sows, a.take<char>(soB)}, *scws2[2] = {scws, a.take<char>(scB)};
+        if (!ctx->side) HIPCHK(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+        std::vector<hipEvent_t> ev(n_snap + 1, nullptr);
+        struct EvGuard {
+            std::vector<hipEvent_t> &v;
+            ~EvGuard() { for (hipEvent_t e : v) if (e) (void)hipEventDestroy(e); }
+        } ev_guard{ev};
+        for (auto &e : ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         // all common-node maps, uploaded before anything is enqueued
         std::vector<int32_t> hm, m0, m1;
         std::vector<int64_t> moff(n_snap, 0), mcnt(n_snap, 0);
@@ -1139,61 +1164,103 @@ cdl_status cdl_score_sequence(cdl_ctx *ctx, int32_t n_snap, const cdl_snapshot *
                                    (uint64_t)(uintptr_t)(t + 1 < n_snap ? F[t] : nullptr),
                                    (uint64_t)(uintptr_t)(t + 1 < n_snap && top_idx ? top_idx[t] : nullptr)});
         }
-        auto enqueue = [&]() -> cdl_status {
-            hipStream_t es = ctx->stream;   // the capture stream while capturing
-            for (int t = 0; t < n_snap; ++t) {
-                const int b = t & 1;
+        // Snapshot t runs on stream t % 2 (the second joins after a fork
+        // event), then scores pair (t - 1, t) once snapshot t - 1 and its own
+        // score are done (event ev[t - 1]); ev[t] marks the end of both.
+        // Consecutive snapshots therefore overlap.  s0 joins s1 at the end.
+        auto enqueue = [&](hipStream_t s0, hipStream_t s1) -> cdl_status {
+            hipStream_t ss[2] = {s0, s1};
+            HIPCHK(hipEventRecord(ev[n_snap], s0));
+            HIPCHK(hipStreamWaitEvent(s1, ev[n_snap], 0));
+            cdl_status st = CDL_OK;
+            for (int t = 0; t < n_snap && st == CDL_OK; ++t) {
+                const int si = t & 1, b = t % 3;
+                hipStream_t es = ss[si];
+                ctx->stream = es;
                 const cdl_snapshot &x = sn[t];
-                cdl_status st = graph_enqueue(ctx, x.X, x.n, x.T, x.ldx, q->sigma, Wb[b], degb[b], stb[b], gws);
-                if (st != CDL_OK) return st;
+                st = graph_enqueue(ctx, x.X, x.n, x.T, x.ldx, q->sigma, W3[b], deg3[b], st3[b], gws2[si]);
+                if (st != CDL_OK) break;
                 double *stat_t = status + (size_t)t * (CDL_GRAPH_STATS + 2 * kp);
-                HIPCHK(hipMemcpyAsync(stat_t, stb[b], CDL_GRAPH_STATS * sizeof(double), hipMemcpyDeviceToDevice, es));
-                if ((st = chain_enqueue(ctx, Wb[b], degb[b], stb[b], x.n, q->prec, q->depth, cws)) != CDL_OK) return st;
-                if ((st = solve_enqueue_fixed(ctx, Wb[b], degb[b], x.gid, x.n, cws, q->prec, q->depth, q->k, q->seed,
-                                              q->max_iter, Zb[b], sows, stat_t + CDL_GRAPH_STATS,
+                if (hipMemcpyAsync(stat_t, st3[b], CDL_GRAPH_STATS * sizeof(double), hipMemcpyDeviceToDevice, es) != hipSuccess) {
+                    st = fail(ctx, CDL_E_HIP, "status copy failed");
+                    break;
+                }
+                if ((st = chain_enqueue(ctx, W3[b], deg3[b], st3[b], x.n, q->prec, q->depth, cws2[si])) != CDL_OK) break;
+                if ((st = solve_enqueue_fixed(ctx, W3[b], deg3[b], x.gid, x.n, cws2[si], q->prec, q->depth, q->k, q->seed,
+                                              q->max_iter, Z3[b], sows2[si], stat_t + CDL_GRAPH_STATS,
                                               stat_t + CDL_GRAPH_STATS + kp)) != CDL_OK)
-                    return st;
-                if (t == 0) continue;
-                const int pb = b ^ 1;
-                const cdl_snapshot &y = sn[t - 1];
-                const int64_t m = mcnt[t], mp = pad_n(m);
-                const int32_t *mp0 = maps_all + moff[t], *mp1 = mp0 + m;
-                Arena as(scws);
-                ScoreWs w = plan_score(as, m, q->k);
-                const int32_t K = top_idx ? std::min<int32_t>(q->top_k, (int32_t)m) : 0;
-                const int weighted = q->mode == CDL_SCORE_DELTA_A;
-                { Timed t_(ctx, "build_zhat"); HIPCHK(launch_build_zhat(Zb[pb], Zb[b], mp0, mp1, m, mp, q->k, kp, stb[pb], stb[b], w.Zh, w.Zhe, w.sq, es)); }
-                { Timed t_(ctx, "score"); HIPCHK(launch_score(w.Zh, w.Zhe, kp, w.sq, m, mp, Wb[pb], pad_n(y.n), Wb[b], pad_n(x.n),
-                                    mp0, mp1, weighted, w.part, nullptr, es)); }
-                { Timed t_(ctx, "score_reduce"); HIPCHK(launch_score_reduce(w.part, score_tiles_1d(mp), m, mp, F[t - 1], es)); }
-                if (K > 0) { Timed t_(ctx, "topk"); HIPCHK(launch_topk(F[t - 1], m, K, w.topk, top_idx[t - 1], es)); }
+                    break;
+                if (t > 0) {
+                    if (hipStreamWaitEvent(es, ev[t - 1], 0) != hipSuccess) {
+                        st = fail(ctx, CDL_E_HIP, "event wait failed");
+                        break;
+                    }
+                    const int pb = (t - 1) % 3;
+                    const cdl_snapshot &y = sn[t - 1];
+                    const int64_t m = mcnt[t], mp = pad_n(m);
+                    const int32_t *mp0 = maps_all + moff[t], *mp1 = mp0 + m;
+                    Arena as(scws2[si]);
+                    ScoreWs w = plan_score(as, m, q->k);
+                    const int32_t K = top_idx ? std::min<int32_t>(q->top_k, (int32_t)m) : 0;
+                    const int weighted = q->mode == CDL_SCORE_DELTA_A;
+                    hipError_t e = hipSuccess;
+                    { Timed t_(ctx, "build_zhat"); e = launch_build_zhat(Z3[pb], Z3[b], mp0, mp1, m, mp, q->k, kp, st3[pb], st3[b], w.Zh, w.Zhe, w.sq, es); }
+                    if (e == hipSuccess) { Timed t_(ctx, "score"); e = launch_score(w.Zh, w.Zhe, kp, w.sq, m, mp, W3[pb], pad_n(y.n), W3[b], pad_n(x.n),
+                                        mp0, mp1, weighted, w.part, nullptr, es); }
+                    if (e == hipSuccess) { Timed t_(ctx, "score_reduce"); e = launch_score_reduce(w.part, score_tiles_1d(mp), m, mp, F[t - 1], es); }
+                    if (e == hipSuccess && K > 0) { Timed t_(ctx, "topk"); e = launch_topk(F[t - 1], m, K, w.topk, top_idx[t - 1], es); }
+                    if (e != hipSuccess) {
+                        st = fail(ctx, CDL_E_HIP, std::string("score launch: ") + hipGetErrorString(e));
+                        break;
+                    }
+                }
+                if (hipEventRecord(ev[t], es) != hipSuccess) st = fail(ctx, CDL_E_HIP, "event record failed");
             }
-            return CDL_OK;
+            ctx->stream = s0;
+            // join: s0 waits for the last snapshot on s1 (the last on s0 is in order)
+            const int last1 = (n_snap - 1) & 1 ? n_snap - 1 : n_snap - 2;
+            if (hipStreamWaitEvent(s0, ev[last1 >= 1 ? last1 : n_snap], 0) != hipSuccess && st == CDL_OK)
+                st = fail(ctx, CDL_E_HIP, "event wait failed");
+            return st;
         };
         const bool timing = ctx->timing;
         cdl_status st = CDL_OK;
-        if (key == ctx->seq_key && ctx->seq_exec) {
+        const bool use_graph = (q->flags & CDL_SEQ_GRAPH) != 0;
+        if (!use_graph) {
+            // eager two-stream enqueue; a later graph call starts its key afresh
+            ctx->seq_key.clear();
+            if ((st = enqueue(s, ctx->side)) != CDL_OK) {
+                (void)hipStreamSynchronize(ctx->side);
+                return st;
+            }
+        } else if (key == ctx->seq_key && ctx->seq_exec) {
             HIPCHK(hipGraphLaunch(ctx->seq_exec, s));
             if (info) info->graph_launches = 1;
         } else if (key == ctx->seq_key) {
             // second identical call: capture the enqueue into a graph, on a
             // private stream (the caller's may be the null stream, which
             // cannot be captured), then launch it on the caller's stream
-            hipStream_t cap = nullptr;
+            hipStream_t cap = nullptr, cap2 = nullptr;
             HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+            const hipError_t e2 = hipStreamCreateWithFlags(&cap2, hipStreamNonBlocking);
+            if (e2 != hipSuccess) {
+                (void)hipStreamDestroy(cap);
+                HIPCHK(e2);
+            }
             const hipError_t eb = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
             if (eb != hipSuccess) {
                 (void)hipStreamDestroy(cap);
+                (void)hipStreamDestroy(cap2);
                 HIPCHK(eb);
             }
             ctx->timing = false;
-            ctx->stream = cap;
-            st = enqueue();
+            st = enqueue(cap, cap2);   // cap2 joins the capture through the fork event
             hipGraph_t g = nullptr;
             const hipError_t ec = hipStreamEndCapture(cap, &g);
             ctx->stream = s;
             ctx->timing = timing;
             (void)hipStreamDestroy(cap);
+            (void)hipStreamDestroy(cap2);
             if (st != CDL_OK || ec != hipSuccess) {
                 if (g) (void)hipGraphDestroy(g);
                 ctx->seq_key.clear();
@@ -1216,7 +1283,10 @@ cdl_status cdl_score_sequence(cdl_ctx *ctx, int32_t n_snap, const cdl_snapshot *
             ctx->seq_exec = nullptr;
             ctx->seq_graph = nullptr;
             ctx->seq_key = key;
-            if ((st = enqueue()) != CDL_OK) return st;
+            if ((st = enqueue(s, ctx->side)) != CDL_OK) {
+                (void)hipStreamSynchronize(ctx->side);   // nothing may stay in flight on the side stream
+                return st;
+            }
         }
         // one read-back for the whole sequence: graph checks and residuals
         std::vector<double> hs((size_t)n_snap * (CDL_GRAPH_STATS + 2 * kp));

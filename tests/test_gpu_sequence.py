@@ -138,7 +138,15 @@ def test_async_sequence_and_graph_replays(cdl, prec, mode):
         return [host(f) for f in F], [host(t) for t in tp], inf
 
     wF, wT, wi = eager()
-    pa = cdl.SeqParams(**base, asynchronous=True)
+    # two streams, no graph: every call enqueued afresh
+    pe = cdl.SeqParams(**base, asynchronous=True)
+    for _ in range(2):
+        Fa, ta, ia = cdl.score_sequence(Xs, gdev, pe)
+        assert ia.graph_launches == 0 and ia.max_rel_residual == wi.max_rel_residual
+        for t in range(len(wF)):
+            np.testing.assert_array_equal(host(Fa[t]), wF[t])
+            np.testing.assert_array_equal(host(ta[t]), wT[t])
+    pa = cdl.SeqParams(**base, asynchronous=True, graph=True)
     ws = torch.empty(cdl.sequence_workspace_bytes(Xs, gdev, pa), dtype=torch.uint8, device="cuda")
     Fs, tops, info = cdl.score_sequence(Xs, gdev, pa, ws=ws)
     assert info.graph_launches == 0 and info.pairs == len(Xs) - 1 and info.max_iterations == 6
@@ -171,7 +179,7 @@ def test_async_sequence_rejects_adaptive_settings(cdl):
     seq = small_sequence()
     Xs = [dev(X) for X in seq.X[:2]]
     gdev = [torch.from_numpy(g).cuda() for g in seq.gid[:2]]
-    for bad in (dict(depth=0), dict(solver="pcg"), dict(tol=-1e-6)):
+    for bad in (dict(depth=0), dict(solver="pcg"), dict(tol=-1e-6), dict(asynchronous=False, graph=True)):
         q = dict(k=16, prec="fp32", depth=4, tol=0.0, max_iter=3, asynchronous=True)
         q.update(bad)
         with pytest.raises(cdl.CdlError):
