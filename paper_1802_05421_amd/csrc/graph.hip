@@ -4,10 +4,15 @@
 //
 //   pad_series   copy X into a zero-padded FP64 panel, row norms ||x_i||^2
 //   gram_dist    D2_ij = ||x_i||^2 + ||x_j||^2 - 2 x_i.x_j on FP64 MFMA,
-//                upper-triangular 128 x 128 tiles only (the lower half of
-//                the buffer is never read), stored from the accumulators
-//   select       exact lower median of D2 over i < j by 6 radix passes over
-//                the IEEE-754 bit patterns (order-preserving for D2 >= 0)
+//                256 x 128 tiles covering the upper triangle (the strictly
+//                lower tiles are never computed or read), stored from the
+//                accumulators
+//   select       exact lower median of D2 over i < j: a sampled bracket
+//                around the median rank, the keys inside it gathered into a
+//                buffer and ranked by radix passes over their IEEE-754 bit
+//                patterns (order-preserving for D2 >= 0); the same radix
+//                passes over the whole upper triangle when the bracket
+//                misses the rank or overflows the buffer
 //   exp_sym      per upper 64 x 64 tile: W = exp(-D2 / sigma^2) in place,
 //                W_ii = 0, written with its mirror; row and column sums
 //                into one partial per (tile column, node)

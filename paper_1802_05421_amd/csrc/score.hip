@@ -3,12 +3,13 @@
 //
 //   build_zhat  Zh = [sqrt(vol0) Z0 | sqrt(vol1) Z1] over the common nodes,
 //               Zhe = Zh with the second half negated, sq_c = Zh_c . Zhe_c
-//   score       G = Zh Zhe^T on FP64 MFMA (upper-triangular tiles); per pair
-//               dc_ab = sq_a + sq_b - 2 G_ab = c_0(a,b) - c_1(a,b) (eq. 1 in
-//               embedding form), weighted by |W1 - W0| on request; |dc| is
-//               summed per row and, for off-diagonal tiles, per column into
-//               one partial per (tile, node)
-//   reduce      F_a = sum over tiles of the partials (fixed order)
+//   score       G = Zh Zhe^T on FP64 MFMA over 256 x 128 tiles covering the
+//               upper triangle; per pair a < b, dc_ab = sq_a + sq_b - 2 G_ab
+//               = c_0(a,b) - c_1(a,b) (eq. 1 in embedding form), weighted by
+//               |W1 - W0| on request; |dc| is summed per row into one
+//               partial per (column block, node) and per column into one
+//               partial per (row block, node)
+//   reduce      F_a = sum of exactly the written partials (fixed order)
 //   topk        bitonic sort of chunks in LDS, keep the best K per chunk,
 //               repeat on the candidates (order: value desc, index asc)
 //   edges       the K largest edge scores (a < b) exactly: per-tile maxima
