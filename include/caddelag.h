@@ -333,6 +333,47 @@ cdl_status cdl_solve_embedding(cdl_ctx *ctx, const double *W, const double *deg,
                                double *Z, void *ws, size_t ws_bytes,
                                cdl_solve_info *info);
 
+/* ---- streamed snapshots (graphs larger than device memory) ---------------- */
+
+/* One snapshot end to end - bandwidth, weights, degrees, right-hand sides and
+ * the solve of cdl_solve_embedding - without storing any n x n matrix
+ * (Algorithm 3 with the graph of the "Climate Data" section).  Every sweep
+ * over the weights recomputes them row panel by row panel from X (the
+ * distance Gram of cdl_build_graph, then W = exp(-D2 / sigma^2) with
+ * W_ii = 0); each panel value equals the stored matrix's bit for bit.  The
+ * device memory needed grows as n (T + 5 k + panel_rows) instead of n^2:
+ * the complexity section's recomputation/communication trade made on one
+ * device, where memory capacity rather than arithmetic limits n.
+ *   X, n, T, ldx, sigma   as for cdl_build_graph (sigma <= 0: the exact
+ *           lower median rule, one sweep over the upper row panels per
+ *           12-bit digit of the key).
+ *   gid, k, seed          as for cdl_solve_embedding (k >= 1).
+ *   tol, max_iter         as for cdl_solve_embedding.  The preconditioner is
+ *           the chain of depth 1, P1 = D^{-1/2} (I + S) D^{-1/2} (Algorithm 2
+ *           with d = 1: no squaring needs a stored matrix), in Richardson's
+ *           iteration x <- x + P1 (y - L x); each iteration is two sweeps
+ *           (one product with W for P1, one for the residual), the residual
+ *           contracting by rho(S~)^2 per iteration.  kappa (for tol < 0) uses
+ *           rho_bound = ||S~||_F from the first sweep.
+ *   panel_rows            rows of W recomputed per panel (rounded up to a
+ *           multiple of 256, at most ld; 0: 32768).  Results do not depend on
+ *           it.
+ *   deg, stats            device outputs as for cdl_build_graph.
+ *   Z, info               as for cdl_solve_embedding (depth_used = 1).
+ *   ws, ws_bytes          device workspace of cdl_stream_workspace_bytes.
+ * Scores of two streamed snapshots come from cdl_anomaly_scores in the
+ * unweighted mode (W0 = W1 = NULL).  Syncs once per digit of the median and
+ * once per iteration.  Errors: CDL_E_ARG, CDL_E_WORKSPACE, CDL_E_NONFINITE
+ * (non-finite series, degrees or residuals), CDL_E_GRAPH (zero degree),
+ * CDL_E_NOCONV (Z holds the last iterate). */
+cdl_status cdl_stream_workspace_bytes(int64_t n, int64_t T, int64_t k, int64_t panel_rows,
+                                      size_t *bytes);
+cdl_status cdl_stream_embedding(cdl_ctx *ctx, const double *X, int64_t n, int64_t T,
+                                int64_t ldx, double sigma, const int32_t *gid, int64_t k,
+                                uint64_t seed, double tol, int max_iter, int64_t panel_rows,
+                                double *deg, double *stats, double *Z, void *ws,
+                                size_t ws_bytes, cdl_solve_info *info);
+
 /* ---- scores (Algorithm 4) -------------------------------------------------- */
 
 /* F_c = sum_{c'} omega |c_0(a,b) - c_1(a',b')| over the m common nodes, where

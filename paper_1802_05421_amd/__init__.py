@@ -34,6 +34,8 @@ from .api import (  # noqa: E402,F401
     set_timing,
     timing,
     solve_embedding,
+    stream_embedding,
+    stream_workspace_bytes,
     workspace_bytes,
 )
 from ._lib import CdlError  # noqa: E402,F401

@@ -123,7 +123,7 @@ def _ws(nbytes: int, device) -> torch.Tensor:
 
 @dataclass
 class Graph:
-    W: torch.Tensor          # (ld, ld) float64, padded
+    W: Optional[torch.Tensor]  # (ld, ld) float64, padded (None for streamed snapshots)
     deg: torch.Tensor        # (n,) float64
     stats: torch.Tensor      # (4,) float64: vol, sigma, deg_min, deg_max
     n: int
@@ -269,6 +269,44 @@ def solve_embedding(g: Graph, chain: Chain, k: int, seed: int, tol: float = 1e-8
     if st != 0 and not (st == 6 and not raise_noconv):
         _check(st, ctx.h)
     return Z, info
+
+
+def stream_workspace_bytes(n: int, T: int, k: int, panel_rows: int = 0) -> int:
+    out = C.c_size_t()
+    _check(_lib().cdl_stream_workspace_bytes(n, T, k, panel_rows, C.byref(out)))
+    return out.value
+
+
+def stream_embedding(X: torch.Tensor, k: int, seed: int, sigma: Optional[float] = None,
+                     gid: Optional[torch.Tensor] = None, tol: float = 1e-8, max_iter: int = 30,
+                     panel_rows: int = 0, ws: Optional[torch.Tensor] = None,
+                     Z: Optional[torch.Tensor] = None, raise_noconv: bool = True):
+    """Graph and embedding of one snapshot with no n x n matrix in memory: the
+    weights are recomputed from X row panel by row panel on every sweep
+    (cdl_stream_embedding).  Returns (Graph with W = None, Z, info); the graph
+    serves anomaly_scores in the unweighted mode."""
+    if X.dtype != torch.float64 or not X.is_cuda or X.dim() != 2 or X.stride(1) != 1:
+        raise ValueError("X must be a CUDA float64 matrix with unit column stride")
+    if gid is not None and (gid.dtype != torch.int32 or not gid.is_cuda):
+        raise ValueError("gid must be a CUDA int32 vector")
+    ctx = context(X.device.index)
+    n, T = X.shape
+    need = stream_workspace_bytes(n, T, k, panel_rows)
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, X.device)
+    if Z is None:
+        Z = torch.empty((n, k), dtype=torch.float64, device=X.device)
+    g = Graph(W=None, deg=torch.empty(n, dtype=torch.float64, device=X.device),
+              stats=torch.empty(L.CDL_GRAPH_STATS, dtype=torch.float64, device=X.device), n=n)
+    info = L.SolveInfo()
+    st = _lib().cdl_stream_embedding(ctx.h, _ptr(X), n, T, X.stride(0),
+                                     float(sigma) if sigma else 0.0, _ptr(gid), k,
+                                     C.c_uint64(seed), float(tol), max_iter, panel_rows,
+                                     _ptr(g.deg), _ptr(g.stats), _ptr(Z), _ptr(ws), ws.numel(),
+                                     C.byref(info))
+    if st != 0 and not (st == 6 and not raise_noconv):
+        _check(st, ctx.h)
+    return g, Z, info
 
 
 def anomaly_scores(Z0: torch.Tensor, g0: Graph, Z1: torch.Tensor, g1: Graph,

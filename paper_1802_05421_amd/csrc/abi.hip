@@ -232,6 +232,47 @@ EdgeWs plan_edges(Arena &a, int64_t m, int64_t k, int K) {
     return w;
 }
 
+// Streamed snapshot: the series, one row panel of the distances / weights
+// and the solve's kpad x ld panels; nothing of size n x n.
+struct StreamWs {
+    int *flags;
+    SelectState *sel;
+    double *sqn, *Xp, *panel;
+    double *Yt, *Xt, *Rt, *Ut, *Prod;
+    double *npart, *mpart, *scal, *mean, *dinv, *rdeg, *fro;
+    int64_t prow;   // rows per panel
+};
+int64_t stream_panel_rows(int64_t n, int64_t panel_rows) {
+    const int64_t ld = pad_n(n);
+    int64_t p = panel_rows > 0 ? panel_rows : 32768;
+    p = (p + 255) / 256 * 256;
+    return std::min(p, ld);
+}
+StreamWs plan_stream(Arena &a, int64_t n, int64_t T, int64_t k, int64_t panel_rows) {
+    const int64_t ld = pad_n(n), Tp = pad_t(T), kp = pad_k(k);
+    const size_t kpan = (size_t)kp * ld;
+    StreamWs w;
+    w.prow = stream_panel_rows(n, panel_rows);
+    w.flags = a.take<int>(64);
+    w.sel = a.take<SelectState>(1);
+    w.sqn = a.take<double>(ld);
+    w.Xp = a.take<double>((size_t)ld * Tp);
+    w.panel = a.take<double>((size_t)w.prow * ld);
+    w.Yt = a.take<double>(kpan);
+    w.Xt = a.take<double>(kpan);
+    w.Rt = a.take<double>(kpan);
+    w.Ut = a.take<double>(kpan);
+    w.Prod = a.take<double>(kpan);
+    w.npart = a.take<double>((size_t)residual_parts(ld) * kp);
+    w.mpart = a.take<double>(residual_tiles(ld, kp));
+    w.scal = a.take<double>(kp + 2);
+    w.mean = a.take<double>(kp);
+    w.dinv = a.take<double>(ld);
+    w.rdeg = a.take<double>(ld);
+    w.fro = a.take<double>(ld);
+    return w;
+}
+
 cdl_status fail(cdl_ctx *c, cdl_status s, const std::string &msg) {
     if (c) c->err = msg;
     return s;
@@ -823,6 +864,169 @@ cdl_status cdl_solve_embedding(cdl_ctx *ctx, const double *W, const double *deg,
             if (conv) break;
         }
         (void)rho;
+    }
+    { Timed t_(ctx, "finalize_z"); HIPCHK(launch_finalize_z2(w.Xt, ld, n, kp, k, w.mean, Z, s)); }
+    if (info) {
+        info->iterations = it;
+        info->converged = conv || tol == 0.0;
+        info->rel_residual = rel;
+        info->kappa = kappa;
+        info->certified_error = kappa * rel + 1e-14;
+    }
+    if (tol != 0.0 && !conv) {
+        char buf[160];
+        std::snprintf(buf, sizeof(buf), "residual %.3e > target %.3e after %d iterations", rel, target, it);
+        return fail(ctx, CDL_E_NOCONV, buf);
+    }
+    return CDL_OK;
+}
+
+// ---- streamed snapshots ---------------------------------------------------------
+
+cdl_status cdl_stream_workspace_bytes(int64_t n, int64_t T, int64_t k, int64_t panel_rows,
+                                      size_t *bytes) {
+    if (n < 2 || n > (1 << 20) || T < 1 || k < 1 || k > ((int64_t)1 << 20) || panel_rows < 0 ||
+        !bytes)
+        return CDL_E_ARG;
+    Arena a(nullptr);
+    plan_stream(a, n, T, k, panel_rows);
+    *bytes = a.off;
+    return CDL_OK;
+}
+
+cdl_status cdl_stream_embedding(cdl_ctx *ctx, const double *X, int64_t n, int64_t T,
+                                int64_t ldx, double sigma, const int32_t *gid, int64_t k,
+                                uint64_t seed, double tol, int max_iter, int64_t panel_rows,
+                                double *deg, double *stats, double *Z, void *ws,
+                                size_t ws_bytes, cdl_solve_info *info) {
+    if (!ctx) return CDL_E_ARG;
+    if (n < 2 || n > (1 << 20)) return fail(ctx, CDL_E_ARG, "n must be in [2, 2^20]");
+    if (T < 1 || ldx < T) return fail(ctx, CDL_E_ARG, "need T >= 1 and ldx >= T");
+    if (k < 1 || k > ((int64_t)1 << 20)) return fail(ctx, CDL_E_ARG, "k must be in [1, 2^20]");
+    if (!X || !deg || !stats || !Z || !ws) return fail(ctx, CDL_E_ARG, "null pointer");
+    if (!aligned(X, 8) || !aligned(deg, 8) || !aligned(stats, 8) || !aligned(Z, 8) ||
+        !aligned(ws, kAlign))
+        return fail(ctx, CDL_E_ARG, "misaligned pointer");
+    if (!std::isfinite(sigma) || !std::isfinite(tol)) return fail(ctx, CDL_E_ARG, "sigma and tol must be finite");
+    if (max_iter < 1 || max_iter > 64) return fail(ctx, CDL_E_ARG, "max_iter must be in [1, 64]");
+    if (panel_rows < 0) return fail(ctx, CDL_E_ARG, "panel_rows must be >= 0");
+    Arena need(nullptr);
+    plan_stream(need, n, T, k, panel_rows);
+    if (ws_bytes < need.off) return fail(ctx, CDL_E_WORKSPACE, "stream workspace too small");
+    HIPCHK(hipSetDevice(ctx->device));
+    if (info) std::memset(info, 0, sizeof(*info));
+    Arena a(ws);
+    const StreamWs w = plan_stream(a, n, T, k, panel_rows);
+    const int64_t ld = pad_n(n), Tp = pad_t(T), kp = pad_k(k), P = w.prow;
+    const size_t kbytes = (size_t)kp * ld * sizeof(double);
+    hipStream_t s = ctx->stream;
+
+    { Timed t_(ctx, "fill_zero"); HIPCHK(launch_fill_zero(w.flags, 256, s)); }
+    { Timed t_(ctx, "pad_series"); HIPCHK(launch_pad_series(X, n, T, ldx, w.Xp, ld, Tp, w.sqn, w.flags, s)); }
+    int hflag = 0;
+    HIPCHK(hipMemcpyAsync(&hflag, w.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hflag) return fail(ctx, CDL_E_NONFINITE, "non-finite node series");
+
+    // Bandwidth: exact lower median of the upper-triangle distances, one
+    // 12-bit digit per sweep over the recomputed upper row panels.
+    if (sigma > 0.0) {
+        { Timed t_(ctx, "set_sigma"); HIPCHK(launch_set_sigma(sigma, stats, s)); }
+    } else {
+        { Timed t_(ctx, "stream_select"); HIPCHK(launch_select_start_top(w.sel, n, s)); }
+        int mode = 0;
+        for (int digit = 0; digit < 7 && mode != 2; ++digit) {
+            for (int64_t r0 = 0; r0 < n; r0 += P) {
+                const int64_t rows = std::min(P, ld - r0);
+                { Timed t_(ctx, "stream_gram_upper"); HIPCHK(launch_gram_panel(w.Xp, Tp, w.sqn, n, ld, r0, rows, false, w.panel, s)); }
+                { Timed t_(ctx, "stream_select"); HIPCHK(launch_select_panel(w.panel, ld, n, r0, std::min(r0 + rows, n), w.sel, s)); }
+            }
+            { Timed t_(ctx, "stream_select"); HIPCHK(launch_select_pick(w.sel, stats, s)); }
+            HIPCHK(hipMemcpyAsync(&mode, &w.sel->mode, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+        }
+        if (mode != 2) return fail(ctx, CDL_E_HIP, "median selection did not finish");
+    }
+
+    // Weights, degrees and right-hand sides: one sweep over the full row panels.
+    { Timed t_(ctx, "fill_zero"); HIPCHK(launch_fill_zero(w.Yt, kbytes, s)); }
+    { Timed t_(ctx, "fill_zero"); HIPCHK(launch_fill_zero(w.Xt, kbytes, s)); }
+    for (int64_t r0 = 0; r0 < n; r0 += P) {
+        const int64_t rows = std::min(P, ld - r0);
+        { Timed t_(ctx, "stream_gram"); HIPCHK(launch_gram_panel(w.Xp, Tp, w.sqn, n, ld, r0, rows, true, w.panel, s)); }
+        { Timed t_(ctx, "stream_exp"); HIPCHK(launch_exp_rows(w.panel, ld, n, r0, rows, stats, deg, nullptr, nullptr, s)); }
+        { Timed t_(ctx, "rhs"); HIPCHK(launch_rhs_rows(w.panel, ld, n, r0, std::min(r0 + rows, n), gid, k, kp, seed, w.Yt, s)); }
+    }
+    { Timed t_(ctx, "graph_stats"); HIPCHK(launch_graph_stats(deg, n, stats, s)); }
+    { Timed t_(ctx, "stream_prep"); HIPCHK(launch_stream_prep(deg, n, ld, w.dinv, w.rdeg, s)); }
+    const int nparts = residual_parts(ld), ntiles = residual_tiles(ld, kp);
+    // R = Y (X = 0) and the norms of Y's columns
+    { Timed t_(ctx, "residual_init"); HIPCHK(launch_residual_reduce(nullptr, 0, w.Yt, w.Xt, deg, w.rdeg, ld, n, kp, k, w.Rt, w.npart, w.mpart, s)); }
+    { Timed t_(ctx, "col_norms"); HIPCHK(launch_col_norms2(w.npart, nparts, kp, w.mpart, ntiles, 0, w.scal, s)); }
+    std::vector<double> ynorm(kp), rnorm(kp);
+    double hstats[CDL_GRAPH_STATS];
+    HIPCHK(hipMemcpyAsync(ynorm.data(), w.scal, kp * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hstats, stats, sizeof(hstats), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (double v : hstats)
+        if (!std::isfinite(v)) return fail(ctx, CDL_E_NONFINITE, "non-finite weights or degrees");
+    if (!(hstats[2] > 0.0)) return fail(ctx, CDL_E_GRAPH, "a node has zero degree");
+    for (int64_t r = 0; r < k; ++r)
+        if (!std::isfinite(ynorm[r])) return fail(ctx, CDL_E_NONFINITE, "non-finite right-hand side");
+
+    // One sweep: Prod = W V over the recomputed full row panels (the first
+    // sweep also collects the row norms of S for the certificate).
+    auto product_sweep = [&](const double *Vt, bool frob) -> cdl_status {
+        for (int64_t r0 = 0; r0 < n; r0 += P) {
+            const int64_t rows = std::min(P, ld - r0);
+            { Timed t_(ctx, "stream_gram"); HIPCHK(launch_gram_panel(w.Xp, Tp, w.sqn, n, ld, r0, rows, true, w.panel, s)); }
+            { Timed t_(ctx, "stream_exp"); HIPCHK(launch_exp_rows(w.panel, ld, n, r0, rows, stats, nullptr, frob ? w.dinv : nullptr, frob ? w.fro + r0 : nullptr, s)); }
+            { Timed t_(ctx, "stream_product"); HIPCHK(launch_panel_product(Vt, w.panel, ld, n, kp, r0, rows, w.Prod, s)); }
+        }
+        return CDL_OK;
+    };
+
+    double kappa = INFINITY, rb = INFINITY, target = tol > 0.0 ? tol : 0.0, rel = 1.0;
+    int it = 0;
+    bool conv = false;
+    cdl_status st = CDL_OK;
+    while (it < max_iter) {
+        // X += P1 R, P1 = D^{-1} + D^{-1} W D^{-1}
+        { Timed t_(ctx, "stream_scale"); HIPCHK(launch_stream_scale(w.Rt, w.rdeg, ld, kp, w.Ut, s)); }
+        if ((st = product_sweep(w.Ut, it == 0)) != CDL_OK) return st;
+        { Timed t_(ctx, "stream_update"); HIPCHK(launch_stream_update(w.Ut, w.Prod, w.rdeg, ld, kp, w.Xt, s)); }
+        if (it == 0) {
+            // ||S~||_F^2 = ||S||_F^2 - 1 for the deflated S~ = S - u u^T
+            std::vector<double> fro(n);
+            HIPCHK(hipMemcpyAsync(fro.data(), w.fro, n * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            const double f2 = host_sum(fro) - 1.0;
+            rb = std::sqrt(std::max(f2, 0.0));
+            if (rb < 1.0) kappa = hstats[3] * (1.0 + rb) / (hstats[2] * (1.0 - rb));
+            if (tol < 0.0) {
+                if (!std::isfinite(kappa))
+                    return fail(ctx, CDL_E_ARG, "certified tolerance needs ||S~||_F < 1; use tol > 0");
+                target = -tol / kappa;
+            }
+        }
+        ++it;
+        if (info && it <= 64) info->depth_used[it - 1] = 1;
+        // R = Y - D X + W X
+        if ((st = product_sweep(w.Xt, false)) != CDL_OK) return st;
+        { Timed t_(ctx, "residual"); HIPCHK(launch_residual_reduce(w.Prod, 1, w.Yt, w.Xt, deg, w.rdeg, ld, n, kp, k, w.Rt, w.npart, w.mpart, s)); }
+        { Timed t_(ctx, "col_norms"); HIPCHK(launch_col_norms2(w.npart, nparts, kp, w.mpart, ntiles, 0, w.scal, s)); }
+        HIPCHK(hipMemcpyAsync(rnorm.data(), w.scal, kp * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        rel = 0.0;
+        for (int64_t r = 0; r < k; ++r) {
+            if (!std::isfinite(rnorm[r])) return fail(ctx, CDL_E_NONFINITE, "non-finite residual");
+            if (ynorm[r] > 0.0) rel = std::max(rel, rnorm[r] / ynorm[r]);
+        }
+        if (info && it <= 64) info->history[it - 1] = rel;
+        if (target > 0.0 && rel <= target) {
+            conv = true;
+            break;
+        }
     }
     { Timed t_(ctx, "finalize_z"); HIPCHK(launch_finalize_z2(w.Xt, ld, n, kp, k, w.mean, Z, s)); }
     if (info) {

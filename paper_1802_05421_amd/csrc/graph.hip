@@ -97,18 +97,29 @@ constexpr size_t kGramSmem = GramCore::SMEM;
 
 
 
+// Tiles of row blocks [I0, I0 + pb): those of the upper-triangle cover
+// (full = 0; I0 = 0 and pb = ld / 256 give the whole cover) or all ncol of
+// each row block (full = 1).  Row i is stored at D2 + (i - 256 I0) ld, so a
+// row panel needs a buffer of 256 pb rows only.
 // st != nullptr: also fold the smallest and largest upper-triangle key
 // (i < j) into st->kmin / st->kmax (the median selection starts below their
 // common bit prefix).
 __global__ __launch_bounds__(512) void k_gram_dist(const double *Xp, int64_t Tp,
                                                    const double *sqn, int64_t n, int64_t ld,
-                                                   double *D2, int ncol, int total,
-                                                   SelectState *st) {
+                                                   double *D2, int ncol, int I0, int pb,
+                                                   int full, int total, SelectState *st) {
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
     double *smem = (double *)smem_raw;
     int I, J;
-    upper_rect_tile(xcd_remap(blockIdx.x, total), ncol, I, J);
+    const int id = xcd_remap(blockIdx.x, total);
+    if (full) {
+        rect_tile<4>(id, pb, ncol, I, J);
+        I += I0;
+    } else {
+        upper_rect_tile(id + I0 * (ncol + 1 - I0), ncol, I, J);
+    }
     const int64_t m0 = (int64_t)I * 256, n0 = (int64_t)J * 128;
+    double *const out = D2 - (int64_t)I0 * 256 * ld;
     GramCore g;
     g.run(Xp, Tp, Xp, Tp, m0, n0, Tp, smem);
     unsigned long long kmin = ~0ull, kmax = 0ull;
@@ -141,7 +152,7 @@ __global__ __launch_bounds__(512) void k_gram_dist(const double *Xp, int64_t Tp,
 #pragma unroll
             for (int rr = 0; rr < MfmaF64::R; ++rr) {
                 const int r = GramCore::row_of(a, rr), c = GramCore::col_of(b);
-                D2[(m0 + r) * ld + n0 + c] = f(r, c, g.acc[a][b][rr], sa[a][rr], sb[b]);
+                out[(m0 + r) * ld + n0 + c] = f(r, c, g.acc[a][b][rr], sa[a][rr], sb[b]);
             }
     if (st) {
 #pragma unroll
@@ -157,8 +168,7 @@ __global__ __launch_bounds__(512) void k_gram_dist(const double *Xp, int64_t Tp,
     }
 }
 
-hipError_t launch_gram_dist(const double *Xp, int64_t Tp, const double *sqn, int64_t n,
-                            int64_t ld, double *D2, SelectState *st, hipStream_t s) {
+static hipError_t gram_attr() {
     static bool attr = false;
     if (!attr) {
         hipError_t e = hipFuncSetAttribute((const void *)k_gram_dist,
@@ -167,10 +177,36 @@ hipError_t launch_gram_dist(const double *Xp, int64_t Tp, const double *sqn, int
         if (e != hipSuccess) return e;
         attr = true;
     }
+    return hipSuccess;
+}
+
+hipError_t launch_gram_dist(const double *Xp, int64_t Tp, const double *sqn, int64_t n,
+                            int64_t ld, double *D2, SelectState *st, hipStream_t s) {
+    hipError_t e = gram_attr();
+    if (e != hipSuccess) return e;
     const int ncol = (int)(ld / 128);
     const int total = rect_upper_tiles(ld);
     hipLaunchKernelGGL(k_gram_dist, dim3(total), dim3(512), kGramSmem, s, Xp, Tp, sqn, n, ld,
-                       D2, ncol, total, st);
+                       D2, ncol, 0, (int)(ld / 256), 0, total, st);
+    return hipGetLastError();
+}
+
+int64_t gram_panel_tiles(int64_t ld, int64_t row0, int64_t rows, bool full) {
+    const int64_t ncol = ld / 128, I0 = row0 / 256, pb = rows / 256;
+    return full ? pb * ncol : pb * ncol - 2 * (I0 * pb + pb * (pb - 1) / 2);
+}
+
+hipError_t launch_gram_panel(const double *Xp, int64_t Tp, const double *sqn, int64_t n,
+                             int64_t ld, int64_t row0, int64_t rows, bool full, double *D2p,
+                             hipStream_t s) {
+    if (row0 % 256 || rows % 256 || rows <= 0 || row0 + rows > ld) return hipErrorInvalidValue;
+    hipError_t e = gram_attr();
+    if (e != hipSuccess) return e;
+    const int64_t total = gram_panel_tiles(ld, row0, rows, full);
+    if (total <= 0 || total > INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gram_dist, dim3((unsigned)total), dim3(512), kGramSmem, s, Xp, Tp, sqn,
+                       n, ld, D2p, (int)(ld / 128), (int)(row0 / 256), (int)(rows / 256),
+                       full ? 1 : 0, (int)total, (SelectState *)nullptr);
     return hipGetLastError();
 }
 
@@ -369,7 +405,10 @@ __device__ inline void sel_digit(const SelectState *st, int &shift, int &width,
     hi_mask = bits == 0 ? 0ull : ~((1ull << (64 - bits)) - 1ull);
 }
 
+// Keys of rows [row0, row1): row i at D2 + (i - row0) ld (a row panel, or
+// the whole matrix with row0 = 0, row1 = n).
 __global__ __launch_bounds__(256) void k_select_pass(const double *D2, int64_t ld, int64_t n,
+                                                     int64_t row0, int64_t row1,
                                                      SelectState *st,
                                                      const unsigned long long *buf) {
     __shared__ unsigned int h[4096];
@@ -405,8 +444,8 @@ __global__ __launch_bounds__(256) void k_select_pass(const double *D2, int64_t l
                 if (q0 + u * stride < nb) take(key[u]);
         }
     } else {
-        for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
-            const unsigned long long *row = (const unsigned long long *)(D2 + i * ld);
+        for (int64_t i = row0 + blockIdx.x; i < row1; i += gridDim.x) {
+            const unsigned long long *row = (const unsigned long long *)(D2 + (i - row0) * ld);
             for (int64_t j0 = i + 1 + threadIdx.x; j0 < n; j0 += 8 * 256) {
                 unsigned long long key[8];
 #pragma unroll
@@ -535,9 +574,102 @@ hipError_t launch_select_median(const double *D2, int64_t ld, int64_t n, SelectS
     }
     // at most 6 digit passes resolve 64 bits; the collect pass is one more
     for (int p = 0; p < 7; ++p) {
-        hipLaunchKernelGGL(k_select_pass, dim3(grid), dim3(256), 0, s, D2, ld, n, st, buf);
+        hipLaunchKernelGGL(k_select_pass, dim3(grid), dim3(256), 0, s, D2, ld, n, (int64_t)0, n,
+                           st, buf);
         hipLaunchKernelGGL(k_select_pick, dim3(1), dim3(1024), 0, s, st, stats);
     }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Streamed selection (no stored matrix): radix digits from the top bit, each
+// digit one k_select_pass per recomputed row panel of the upper triangle and
+// one pick; the collect pass and the final sort are those of the stored path.
+
+__global__ void k_select_start_top(SelectState *st, int64_t n) {
+    if (threadIdx.x != 0) return;
+    const unsigned long long N = (unsigned long long)n * (unsigned long long)(n - 1) / 2ull;
+    st->rank = (N - 1ull) / 2ull;
+    st->prefix = 0ull;
+    st->bits = 0;
+    st->mode = 0;
+    st->src = 0;
+    st->count = 0;
+}
+
+hipError_t launch_select_start_top(SelectState *st, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_select_reset, dim3(1), dim3(256), 0, s, st);
+    hipLaunchKernelGGL(k_select_start_top, dim3(1), dim3(64), 0, s, st, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_panel(const double *D2p, int64_t ld, int64_t n, int64_t row0,
+                               int64_t row1, SelectState *st, hipStream_t s) {
+    if (row1 <= row0) return hipSuccess;
+    const int64_t rows = row1 - row0;
+    const int grid = (int)(rows < 2048 ? rows : 2048);
+    hipLaunchKernelGGL(k_select_pass, dim3(grid), dim3(256), 0, s, D2p, ld, n, row0, row1, st,
+                       (const unsigned long long *)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_pick(SelectState *st, double *stats, hipStream_t s) {
+    hipLaunchKernelGGL(k_select_pick, dim3(1), dim3(1024), 0, s, st, stats);
+    return hipGetLastError();
+}
+
+// Row panel of the weights from its squared distances, in place: W_ij =
+// exp(-D2_ij / sigma^2) for i != j (both < n), else 0 - the expression of
+// k_exp_sym, so each value equals the stored matrix's bit for bit.  Panel row
+// q is node row0 + q.  deg != nullptr: deg_i = sum_j W_ij (fixed order).
+// dinv != nullptr: fro[q] = sum_j (W_ij dinv_i dinv_j)^2 with dinv = D^{-1/2},
+// a row of the squared Frobenius norm of S = D^{-1/2} W D^{-1/2}.
+__global__ __launch_bounds__(256) void k_exp_rows(double *Wp, int64_t ld, int64_t n,
+                                                  int64_t row0, const double *stats,
+                                                  double *deg, const double *dinv,
+                                                  double *fro) {
+    __shared__ double red[4];
+    const int64_t i = row0 + blockIdx.x;
+    double *row = Wp + (int64_t)blockIdx.x * ld;
+    const double sigma = stats[1];
+    const double s2 = sigma * sigma;
+    const bool live = i < n;
+    const double di = (dinv && live) ? dinv[i] : 0.0;
+    double acc = 0.0, f = 0.0;
+    for (int64_t j0 = threadIdx.x; j0 < ld; j0 += 4 * 256) {
+        double d2[4];   // four loads in flight before the first exp
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t j = j0 + 256 * u;
+            d2[u] = j < ld ? row[j] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t j = j0 + 256 * u;
+            if (j >= ld) break;
+            const double v = (live && j < n && i != j) ? exp(-d2[u] / s2) : 0.0;
+            row[j] = v;
+            acc += v;
+            if (dinv && v != 0.0) {
+                const double sv = v * di * dinv[j];
+                f += sv * sv;
+            }
+        }
+    }
+    acc = block_sum256(acc, red);
+    if (deg && live && threadIdx.x == 0) deg[i] = acc;
+    if (fro) {
+        f = block_sum256(f, red);
+        if (threadIdx.x == 0) fro[blockIdx.x] = f;
+    }
+}
+
+hipError_t launch_exp_rows(double *Wp, int64_t ld, int64_t n, int64_t row0, int64_t rows,
+                           const double *stats, double *deg, const double *dinv, double *fro,
+                           hipStream_t s) {
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_exp_rows, dim3((unsigned)rows), dim3(256), 0, s, Wp, ld, n, row0, stats,
+                       deg, dinv, fro);
     return hipGetLastError();
 }
 

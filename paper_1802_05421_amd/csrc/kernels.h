@@ -39,7 +39,27 @@ hipError_t launch_pad_series(const double *X, int64_t n, int64_t T, int64_t ldx,
 // (st must have been reset with launch_select_reset).
 hipError_t launch_gram_dist(const double *Xp, int64_t Tp, const double *sqn, int64_t n,
                             int64_t ld, double *D2, SelectState *st, hipStream_t s);
+// Row panel [row0, row0 + rows) of the same tiles (row0 and rows multiples of
+// 256): the upper-triangle cover only (full = false) or every tile of the
+// rows (full = true), row i stored at D2p + (i - row0) ld.
+hipError_t launch_gram_panel(const double *Xp, int64_t Tp, const double *sqn, int64_t n,
+                             int64_t ld, int64_t row0, int64_t rows, bool full, double *D2p,
+                             hipStream_t s);
+int64_t gram_panel_tiles(int64_t ld, int64_t row0, int64_t rows, bool full);
 hipError_t launch_select_reset(SelectState *st, hipStream_t s);
+// Streamed median: start at the top bit; per digit one launch_select_panel
+// per row panel of D2 (rows [row0, row1) at D2p) and one launch_select_pick.
+// st->mode == 2 once stats[1] holds the bandwidth.
+hipError_t launch_select_start_top(SelectState *st, int64_t n, hipStream_t s);
+hipError_t launch_select_panel(const double *D2p, int64_t ld, int64_t n, int64_t row0,
+                               int64_t row1, SelectState *st, hipStream_t s);
+hipError_t launch_select_pick(SelectState *st, double *stats, hipStream_t s);
+// Weights of a row panel in place from its squared distances (bit-identical
+// to the stored matrix); optional row sums into deg[row0 + q] and, with
+// dinv = D^{-1/2}, per-row squared Frobenius norms of S into fro[q].
+hipError_t launch_exp_rows(double *Wp, int64_t ld, int64_t n, int64_t row0, int64_t rows,
+                           const double *stats, double *deg, const double *dinv, double *fro,
+                           hipStream_t s);
 // buf: select_buffer_keys(n) words of scratch; bracket = false: radix
 // passes over the matrix only.
 hipError_t launch_select_median(const double *D2, int64_t ld, int64_t n,
@@ -87,6 +107,29 @@ int apply_splits(int prec, int64_t ld, int64_t kpad, int64_t n);
 // ---- solve ------------------------------------------------------------------
 hipError_t launch_rhs(const double *W, int64_t ld, int64_t n, const int32_t *gid, int64_t k,
                       int64_t kpad, uint64_t seed, double *Yt, hipStream_t s);
+// Rows [row0, row1) of Y from a row panel of W (row i at Wp + (i - row0) ld).
+hipError_t launch_rhs_rows(const double *Wp, int64_t ld, int64_t n, int64_t row0, int64_t row1,
+                           const int32_t *gid, int64_t k, int64_t kpad, uint64_t seed,
+                           double *Yt, hipStream_t s);
+// Prod[r][row0 + q] = sum_j Vt[r][j] Wp[q][j] for the rows of a panel
+// (rows a multiple of 128; one FP64 MFMA pass, no split).
+hipError_t launch_panel_product(const double *Vt, const double *Wp, int64_t ld, int64_t n,
+                                int64_t kpad, int64_t row0, int64_t rows, double *Prod,
+                                hipStream_t s);
+// The residual reduction with S explicit split partials (S = 1: P is W X);
+// dm (ld entries) scales the maxima written to mpart.
+hipError_t launch_residual_reduce(const double *P, int S, const double *Yt, const double *Xt,
+                                  const double *deg, const double *dm, int64_t ld, int64_t n,
+                                  int64_t kpad, int64_t k, double *Rt, double *npart,
+                                  double *mpart, hipStream_t s);
+// Streamed solve steps: dinv = D^{-1/2}, rdeg = D^{-1}; Ut = rdeg * Rt;
+// Xt += Ut + rdeg * Prod (Xt += P1 r for the one-level chain).
+hipError_t launch_stream_prep(const double *deg, int64_t n, int64_t ld, double *dinv,
+                              double *rdeg, hipStream_t s);
+hipError_t launch_stream_scale(const double *Rt, const double *rdeg, int64_t ld, int64_t kpad,
+                               double *Ut, hipStream_t s);
+hipError_t launch_stream_update(const double *Ut, const double *Prod, const double *rdeg,
+                                int64_t ld, int64_t kpad, double *Xt, hipStream_t s);
 // R = Y - deg * X + W X (skip_gemm: R = Y - deg * X).  P: residual_splits()
 // x kpad x ld doubles of split-K partials.  For prec 0..2 the reduction also
 // writes V = dm * R (V64) and its rounded copy (Vlo); prec 3 leaves V alone.

@@ -90,8 +90,12 @@ __device__ __forceinline__ void masked_add8(uint32_t &h, double w, double &a0, d
 // waves of a row share sqrt(W_ij) and the global ids through LDS: per
 // iteration each computes them for its own 64 neighbours, then all P waves
 // sweep the P * 64 neighbours with their own sign words.
+//
+// Rows [row0, row1): row i is read at W + (i - row0) ld (the whole matrix with
+// row0 = 0, row1 = n, or one row panel of it).
 template <int P>
 __global__ __launch_bounds__(256) void k_rhs(const double *W, int64_t ld, int64_t n,
+                                             int64_t row0, int64_t row1,
                                              const int32_t *gid, int64_t k, uint64_t mseed,
                                              double inv_sqrt_k, int nb, double *Yt) {
     constexpr int R = 4 / P;
@@ -107,14 +111,14 @@ __global__ __launch_bounds__(256) void k_rhs(const double *W, int64_t ld, int64_
     const int64_t group = (int64_t)(w / per) * kNumXcd + l % kNumXcd;
     const int beta_i = (l / kNumXcd) * P + q;
     const uint64_t beta = (uint64_t)beta_i;
-    const int64_t i = group * R + rs;
-    const bool row_ok = i < n, active = row_ok && beta_i < nb;
+    const int64_t i = row0 + group * R + rs;
+    const bool row_ok = i < row1, active = row_ok && beta_i < nb;
     const uint64_t gi = !row_ok ? 0 : (gid ? (uint64_t)(uint32_t)gid[i] : (uint64_t)i);
     double acc[64];
 #pragma unroll
     for (int r = 0; r < 64; ++r) acc[r] = 0.0;
     double tsum = 0.0;
-    const double *row = W + (row_ok ? i : 0) * ld;
+    const double *row = W + (row_ok ? i - row0 : 0) * ld;
     for (int64_t j0 = 0; j0 < n; j0 += P * 64) {
         {   // correctly rounded sqrt(W) (the bare hardware instruction is only
             // an approximation in FP64); zero beyond n
@@ -173,21 +177,29 @@ __global__ __launch_bounds__(256) void k_rhs(const double *W, int64_t ld, int64_
     Yt[r * ld + i] = r < k ? (tsum - 2.0 * acc[0]) * inv_sqrt_k : 0.0;
 }
 
-hipError_t launch_rhs(const double *W, int64_t ld, int64_t n, const int32_t *gid, int64_t k,
-                      int64_t kpad, uint64_t seed, double *Yt, hipStream_t s) {
+hipError_t launch_rhs_rows(const double *W, int64_t ld, int64_t n, int64_t row0, int64_t row1,
+                           const int32_t *gid, int64_t k, int64_t kpad, uint64_t seed,
+                           double *Yt, hipStream_t s) {
+    if (row0 < 0 || row1 > n) return hipErrorInvalidValue;
+    if (row1 <= row0) return hipSuccess;
     const uint64_t mseed = splitmix64_mix_host(seed);
     const int nb = (int)(kpad / 64);
     const int P = nb >= 4 ? 4 : (nb >= 2 ? 2 : 1);
     const int nbg = (nb + P - 1) / P;
-    const int64_t groups = cdiv(cdiv(n, 4 / P), kNumXcd) * kNumXcd;
+    const int64_t groups = cdiv(cdiv(row1 - row0, 4 / P), kNumXcd) * kNumXcd;
     const dim3 grid((unsigned)(groups * nbg)), blk(256);
     const double isk = 1.0 / sqrt((double)k);
     switch (P) {
-    case 4: hipLaunchKernelGGL(k_rhs<4>, grid, blk, 0, s, W, ld, n, gid, k, mseed, isk, nb, Yt); break;
-    case 2: hipLaunchKernelGGL(k_rhs<2>, grid, blk, 0, s, W, ld, n, gid, k, mseed, isk, nb, Yt); break;
-    default: hipLaunchKernelGGL(k_rhs<1>, grid, blk, 0, s, W, ld, n, gid, k, mseed, isk, nb, Yt); break;
+    case 4: hipLaunchKernelGGL(k_rhs<4>, grid, blk, 0, s, W, ld, n, row0, row1, gid, k, mseed, isk, nb, Yt); break;
+    case 2: hipLaunchKernelGGL(k_rhs<2>, grid, blk, 0, s, W, ld, n, row0, row1, gid, k, mseed, isk, nb, Yt); break;
+    default: hipLaunchKernelGGL(k_rhs<1>, grid, blk, 0, s, W, ld, n, row0, row1, gid, k, mseed, isk, nb, Yt); break;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_rhs(const double *W, int64_t ld, int64_t n, const int32_t *gid, int64_t k,
+                      int64_t kpad, uint64_t seed, double *Yt, hipStream_t s) {
+    return launch_rhs_rows(W, ld, n, 0, n, gid, k, kpad, seed, Yt, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -200,11 +212,13 @@ template <int BM> struct ResCfg {
     using Core = GemmCore<MfmaF64, BM, 128, 16, WM, WN>;
 };
 
+// W may be a row panel: its row q holds node row0 + q, whose products land in
+// column row0 + q of the partials (row0 = 0 for the whole matrix).
 template <int BM>
 __global__ __launch_bounds__(512) void k_residual_gemm(const double *Xt, const double *W,
                                                        int64_t ld, int64_t kend, int64_t ks,
                                                        int mt, int nt, int S, double *P,
-                                                       int64_t kpad) {
+                                                       int64_t kpad, int64_t row0) {
     using Core = typename ResCfg<BM>::Core;
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
     double *smem = (double *)smem_raw;
@@ -219,7 +233,7 @@ __global__ __launch_bounds__(512) void k_residual_gemm(const double *Xt, const d
     const int64_t kk = k0 < kend ? (kend - k0 < ks ? kend - k0 : ks) : 0;
     Core g;
     g.run(Xt + k0, ld, W + k0, ld, m0, n0, kk, smem);
-    double *Ps = P + (int64_t)split * kpad * ld;
+    double *Ps = P + (int64_t)split * kpad * ld + row0;
 #pragma unroll
     for (int a = 0; a < Core::WTM; ++a)
 #pragma unroll
@@ -258,8 +272,41 @@ static hipError_t resg_launch(const double *Xt, const double *W, int64_t ld, int
     const int64_t kend = (n + 63) / 64 * 64;
     const int64_t ks = (cdiv(kend, S) + 15) / 16 * 16;
     hipLaunchKernelGGL(k_residual_gemm<BM>, dim3(mt * nt * S), dim3(512), Core::SMEM, s, Xt, W,
-                       ld, kend, ks, mt, nt, S, P, kpad);
+                       ld, kend, ks, mt, nt, S, P, kpad, (int64_t)0);
     return hipGetLastError();
+}
+
+template <int BM>
+static hipError_t panel_launch(const double *Vt, const double *Wp, int64_t ld, int64_t n,
+                               int64_t kpad, int64_t row0, int64_t rows, double *Prod,
+                               hipStream_t s) {
+    using Core = typename ResCfg<BM>::Core;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_residual_gemm<BM>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)Core::SMEM);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const int mt = (int)(kpad / BM), nt = (int)(rows / 128);
+    const int64_t kend = (n + 63) / 64 * 64;
+    const int64_t ks = (kend + 15) / 16 * 16;
+    hipLaunchKernelGGL(k_residual_gemm<BM>, dim3(mt * nt), dim3(512), Core::SMEM, s, Vt, Wp, ld,
+                       kend, ks, mt, nt, 1, Prod, kpad, row0);
+    return hipGetLastError();
+}
+
+hipError_t launch_panel_product(const double *Vt, const double *Wp, int64_t ld, int64_t n,
+                                int64_t kpad, int64_t row0, int64_t rows, double *Prod,
+                                hipStream_t s) {
+    if (rows <= 0 || rows % 128 || row0 < 0 || row0 + rows > ld || kpad % 64)
+        return hipErrorInvalidValue;
+    switch (res_bm(kpad)) {
+    case 256: return panel_launch<256>(Vt, Wp, ld, n, kpad, row0, rows, Prod, s);
+    case 128: return panel_launch<128>(Vt, Wp, ld, n, kpad, row0, rows, Prod, s);
+    default: return panel_launch<64>(Vt, Wp, ld, n, kpad, row0, rows, Prod, s);
+    }
 }
 
 // R[r][i] = Y - deg X + sum_s P[s] (zero outside r < k, i < n; Y = NULL
@@ -302,6 +349,69 @@ __global__ __launch_bounds__(256) void k_residual_reduce(
         npart[(int64_t)blockIdx.x * kpad + r] = (red[0] + red[1]) + (red[2] + red[3]);
         mpart[(int64_t)blockIdx.x * kpad + r] = fmax(fmax(redm[0], redm[1]), fmax(redm[2], redm[3]));
     }
+}
+
+hipError_t launch_residual_reduce(const double *P, int S, const double *Yt, const double *Xt,
+                                  const double *deg, const double *dm, int64_t ld, int64_t n,
+                                  int64_t kpad, int64_t k, double *Rt, double *npart,
+                                  double *mpart, hipStream_t s) {
+    dim3 grid((unsigned)(ld / 256), (unsigned)kpad), blk(256);
+    hipLaunchKernelGGL(k_residual_reduce<double>, grid, blk, 0, s, P, S, Yt, Xt, deg, dm, ld, n,
+                       k, kpad, 0, Rt, (double *)nullptr, (double *)nullptr, npart, mpart);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Streamed solve (the weights recomputed panel by panel): the one-level
+// chain P1 = D^{-1/2} (I + S) D^{-1/2} = D^{-1} + D^{-1} W D^{-1} (Algorithm
+// 2 with d = 1).  Its apply is Xt += U + D^{-1} (W U), U = D^{-1} R.
+
+__global__ void k_stream_prep(const double *deg, int64_t n, int64_t ld, double *dinv,
+                              double *rdeg) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ld) return;
+    const double d = i < n ? deg[i] : 0.0;
+    dinv[i] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
+    rdeg[i] = d > 0.0 ? 1.0 / d : 0.0;
+}
+
+hipError_t launch_stream_prep(const double *deg, int64_t n, int64_t ld, double *dinv,
+                              double *rdeg, hipStream_t s) {
+    hipLaunchKernelGGL(k_stream_prep, dim3((unsigned)cdiv(ld, 256)), dim3(256), 0, s, deg, n, ld,
+                       dinv, rdeg);
+    return hipGetLastError();
+}
+
+// One thread per element of the kpad x ld panels (zero rows and columns stay zero:
+// rdeg is zero beyond n and R is zero beyond k).
+__global__ void k_stream_scale(const double *Rt, const double *rdeg, int64_t ld, int64_t total,
+                               double *Ut) {
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= total) return;
+    Ut[o] = Rt[o] * rdeg[o % ld];
+}
+
+hipError_t launch_stream_scale(const double *Rt, const double *rdeg, int64_t ld, int64_t kpad,
+                               double *Ut, hipStream_t s) {
+    const int64_t total = ld * kpad;
+    hipLaunchKernelGGL(k_stream_scale, dim3((unsigned)cdiv(total, 256)), dim3(256), 0, s, Rt,
+                       rdeg, ld, total, Ut);
+    return hipGetLastError();
+}
+
+__global__ void k_stream_update(const double *Ut, const double *Prod, const double *rdeg,
+                                int64_t ld, int64_t total, double *Xt) {
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= total) return;
+    Xt[o] += Ut[o] + rdeg[o % ld] * Prod[o];
+}
+
+hipError_t launch_stream_update(const double *Ut, const double *Prod, const double *rdeg,
+                                int64_t ld, int64_t kpad, double *Xt, hipStream_t s) {
+    const int64_t total = ld * kpad;
+    hipLaunchKernelGGL(k_stream_update, dim3((unsigned)cdiv(total, 256)), dim3(256), 0, s, Ut,
+                       Prod, rdeg, ld, total, Xt);
+    return hipGetLastError();
 }
 
 // prec < 0: no fused operand (FP16 chains scale it separately).

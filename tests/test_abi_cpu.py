@@ -71,6 +71,28 @@ def test_workspace_sizes_and_validation(L):
     assert L.cdl_workspace_bytes(300, 10, 5, 2, 1, None, None, None, None) == 0
 
 
+def test_stream_workspace_grows_linearly_in_n(L):
+    def size(n, T, k, p):
+        out = C.c_size_t()
+        st = L.cdl_stream_workspace_bytes(n, T, k, p, C.byref(out))
+        return st, out.value
+    # n = 2^18 with 8192-row panels: series, one panel and five k-wide panels;
+    # the full weight matrix (512 GiB) is never part of it
+    st, b = size(262144, 240, 256, 8192)
+    ld = 262144
+    assert st == 0 and b % 256 == 0
+    assert b >= ld * 240 * 8 + 8192 * ld * 8 + 5 * 256 * ld * 8
+    assert b < 2 * (ld * 240 * 8 + 8192 * ld * 8 + 5 * 256 * ld * 8)
+    # panel rows: rounded up to 256, at most ld; 0 = default
+    assert size(1000, 10, 4, 300)[1] == size(1000, 10, 4, 512)[1]
+    assert size(1000, 10, 4, 10 ** 6)[1] == size(1000, 10, 4, 1024)[1]
+    assert size(1000, 10, 4, 0)[1] == size(1000, 10, 4, 1024)[1]
+    for bad in [(1, 10, 4, 0), (1000, 0, 4, 0), (1000, 10, 0, 0), (1000, 10, 4, -1),
+                ((1 << 20) + 1, 10, 4, 0)]:
+        assert size(*bad)[0] == 1
+    assert L.cdl_stream_workspace_bytes(1000, 10, 4, 0, None) == 1
+
+
 def test_calls_reject_a_null_context(L):
     # every entry point checks its context before touching a device
     assert L.cdl_build_graph(None, None, 10, 5, 5, 0.0, None, None, None, None, 0) == 1
@@ -86,6 +108,8 @@ def test_calls_reject_a_null_context(L):
     assert L.cdl_ctx_set_solve_depth(None, 2) == 1
     assert L.cdl_ctx_set_select(None, 0) == 1
     assert L.cdl_chain_densify(None, 100, None, 0, None) == 1
+    assert L.cdl_stream_embedding(None, None, 10, 5, 5, 0.0, None, 4, 1, 1e-8, 5, 0, None,
+                                  None, None, None, 0, None) == 1
     assert L.cdl_timing_reset(None) == 1
     assert L.cdl_ctx_destroy(None) == 0
 

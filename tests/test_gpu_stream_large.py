@@ -1,0 +1,127 @@
+"""Streamed snapshots beyond device memory: a 512 x 512 grid (n = 262144,
+T = 240, four 8 x 8 patches, k = 256).  The stored path would need the
+512 GiB FP64 weight matrix; the streamed path holds one 32768-row panel
+(64 GiB) and recomputes the weights from the series on every sweep.
+
+The oracle cannot take the median of the 3.4e10 pair distances, so the
+bandwidth is checked (a) bit for bit against the stored path at n = 65536,
+where the stored matrix still fits, and (b) at n = 262144 as a property on
+sampled rows.  Weights, degrees, the solve (through the residual of the
+oracle's right-hand-side rows) and the scores (through their definition on
+the embeddings) are checked on sampled rows.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow, pytest.mark.timeout(1200)]
+
+K = 256
+SEED = gen.grid.PROJ_SEED
+
+
+@pytest.fixture(scope="module")
+def cdl():
+    import paper_1802_05421_amd as cdl
+    return cdl
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def test_stream_sigma_equals_stored_at_n65536(cdl):
+    cfg = gen.CONFIGS["C5"]
+    X = dev(gen.make_pair(cfg["G"], cfg["T"], cfg["patches"], cfg["patch_size"]).X0)
+    print("stored vs streamed median: n=%d T=%d" % tuple(X.shape), flush=True)
+    g = cdl.build_graph(X)
+    a = g.host_stats()
+    deg = g.deg.clone()
+    del g
+    torch.cuda.empty_cache()
+    gs, _, _ = cdl.stream_embedding(X, 64, SEED, tol=1e-6, max_iter=8, panel_rows=16384)
+    b = gs.host_stats()
+    print("  sigma %.17g / %.17g" % (a["sigma"], b["sigma"]))
+    assert a["sigma"] == b["sigma"]
+    np.testing.assert_allclose(host(gs.deg), host(deg), rtol=1e-13)
+
+
+@pytest.fixture(scope="module")
+def run(cdl):
+    pair = gen.make_pair(512, 240, 4, 8)
+    n = pair.X0.shape[0]
+    ws = torch.empty(cdl.stream_workspace_bytes(n, 240, K, 32768), dtype=torch.uint8, device="cuda")
+    out = {}
+    gs = []
+    for t, X in ((0, pair.X0), (1, pair.X1)):
+        print("streamed snapshot %d: n=%d T=%d k=%d" % (t, n, X.shape[1], K), flush=True)
+        g, Z, info = cdl.stream_embedding(dev(X), K, SEED, tol=1e-9, max_iter=12,
+                                          panel_rows=32768, ws=ws)
+        s = g.host_stats()
+        print("  sigma %.6f iterations %d residual %.2e certified %.2e" % (
+            s["sigma"], info.iterations, info.rel_residual, info.certified_error), flush=True)
+        gs.append(g)
+        out[t] = dict(X=X, g=g, Z=Z, info=info, stats=s)
+    del ws
+    torch.cuda.empty_cache()
+    F, top = cdl.anomaly_scores(out[0]["Z"], gs[0], out[1]["Z"], gs[1], top_k=50)
+    out["F"], out["top"] = host(F), host(top)
+    for t in (0, 1):
+        out[t]["Zh"] = host(out[t]["Z"])
+        out[t]["degh"] = host(out[t]["g"].deg)
+    return out
+
+
+@pytest.mark.parametrize("t", [0, 1])
+def test_graph_and_solve_sampled_rows(run, t):
+    r = run[t]
+    X, s = r["X"], r["stats"]
+    n = X.shape[0]
+    rows = np.sort(np.concatenate([np.random.default_rng(70 + t).choice(n, 40, replace=False),
+                                   [0, n - 1]]))
+    D2 = oracle.sq_distances_rows(X, rows)
+    sigma = s["sigma"]
+    # the median rule as a property: about half of the sampled pair distances
+    # lie below sigma (rows are correlated, hence the loose bound)
+    upper = np.arange(n)[None, :] > rows[:, None]
+    frac = np.count_nonzero((D2 < sigma * sigma) & upper) / np.count_nonzero(upper)
+    print("  snapshot %d: sampled fraction below sigma %.4f" % (t, frac))
+    assert abs(frac - 0.5) < 0.05
+    W = np.exp(-D2 / (sigma * sigma))
+    W[np.arange(len(rows)), rows] = 0.0
+    deg = W.sum(axis=1)
+    np.testing.assert_allclose(r["degh"][rows], deg, rtol=1e-11)
+    assert s["vol"] == pytest.approx(r["degh"].sum(), rel=1e-12)
+    Y = oracle.rhs_rows(W, rows, K, SEED)
+    Z = r["Zh"]
+    LZ = deg[:, None] * Z[rows] - W @ Z
+    e = np.linalg.norm(LZ - Y) / np.linalg.norm(Y)
+    print("  snapshot %d: sampled residual %.2e (reported %.2e)" % (t, e, r["info"].rel_residual))
+    assert r["info"].converged
+    assert e <= max(20 * r["info"].rel_residual, 1e-12)
+    assert np.abs(Z.sum(axis=0)).max() <= 1e-10 * np.abs(Z).max() * np.sqrt(n)
+
+
+def test_scores_sampled_rows_and_top50(run):
+    Z0, Z1, F = run[0]["Zh"], run[1]["Zh"], run["F"]
+    n = Z0.shape[0]
+    v0, v1 = run[0]["stats"]["vol"], run[1]["stats"]["vol"]
+    rows = np.union1d(np.random.default_rng(8).choice(n, 16, replace=False), run["top"][:8])
+    sq0 = (Z0 * Z0).sum(1)
+    sq1 = (Z1 * Z1).sum(1)
+    for a in rows:
+        d = np.abs(v0 * (sq0[a] + sq0 - 2.0 * Z0 @ Z0[a]) - v1 * (sq1[a] + sq1 - 2.0 * Z1 @ Z1[a]))
+        d[a] = 0.0
+        assert F[a] == pytest.approx(d.sum(), rel=1e-9)
+    top = run["top"]
+    assert len(set(top.tolist())) == 50 and np.all(np.diff(F[top]) <= 0)
+    assert np.delete(F, top).max() <= F[top].min()
