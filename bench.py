@@ -110,6 +110,12 @@ def main():
     ap.add_argument("--no-sequence", action="store_true")
     ap.add_argument("--no-concurrent", action="store_true",
                     help="skip the two-stream pair (its kernels overlap, so per-kernel traces exclude it)")
+    ap.add_argument("--no-stream", action="store_true",
+                    help="skip the streamed pair (weights recomputed panel by panel)")
+    ap.add_argument("--stream-grid", type=int, default=0,
+                    help="also time one streamed pair on a G x G grid (e.g. 512: n = 262144)")
+    ap.add_argument("--stream-only", action="store_true",
+                    help="run only the streamed section (prints its results as one JSON line)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -140,6 +146,11 @@ def main():
     pair = gen.make_pair(G, T, 4, 4)
     dev = torch.device("cuda:0")
     X = [torch.from_numpy(pair.X0).to(dev), torch.from_numpy(pair.X1).to(dev)]
+    Xpair = list(X)
+    if args.stream_only:   # the streamed section alone (for kernel traces)
+        print(json.dumps({"streamed": streamed_section(args, cdl, gen, torch, dev, Xpair, n, T, k,
+                                                       seed, None)}), flush=True)
+        return
     m = cdl.ld(n)
     graphs = [cdl.Graph(W=torch.empty((m, m), dtype=torch.float64, device=dev),
                         deg=torch.empty(n, dtype=torch.float64, device=dev),
@@ -363,8 +374,8 @@ def main():
         # more per retry); the library rejects the call if any final residual
         # stays above 1e-8.
         dfix = 1
-        for X in Xs:
-            gb = cdl.build_graph(X)
+        for Xq in Xs:
+            gb = cdl.build_graph(Xq)
             dfix = max(dfix, cdl.build_chain(gb, prec=args.mixed, depth=0, depth_max=DMAX).depth)
             del gb
         gdev = [g.to(dev) for g in gids]
@@ -412,6 +423,10 @@ def main():
         sequence["graph_replay"] = replay if replay is not None else {"error": err}
         sws = None
 
+    streamed = None
+    if not args.no_stream:
+        streamed = streamed_section(args, cdl, gen, torch, dev, Xpair, n, T, k, seed, top_ref)
+
     # dominant kernel of the mixed step
     modeled = {nm: v for nm, v in times_mixed.items() if kernel_model(nm, n, k, T, args.mixed)}
     dom = max(modeled, key=lambda nm: modeled[nm][1])
@@ -448,9 +463,73 @@ def main():
         "edges_top50": edges,
         "amortized_sequence_pair": amortized,
         "sequence_c4": sequence,
+        "streamed": streamed,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def streamed_section(args, cdl, gen, torch, dev, Xpair, n, T, k, seed, top_ref):
+    """Streamed snapshots: the same pair with no n x n matrix stored (the
+    weights recomputed from the series on every sweep), and optionally a pair
+    whose weight matrices exceed device memory."""
+    def stream_pair(Xp, wsb, reps):
+        cdl.timing(reset=True)
+        cdl.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            gz = [cdl.stream_embedding(x, k, seed, tol=args.tol, max_iter=30, ws=wsb) for x in Xp]
+            Fz, tz = cdl.anomaly_scores(gz[0][1], gz[0][0], gz[1][1], gz[1][0], top_k=50)
+        torch.cuda.synchronize()
+        msp = (time.perf_counter() - t0) / reps
+        cdl.set_timing(False)
+        tms = cdl.timing(reset=True)
+        nn, TT = Xp[0].shape
+        kern = {nm: {"launches": v[0] // reps, "ms": round(v[1] / reps, 3)}
+                for nm, v in sorted(tms.items(), key=lambda x: -x[1][1])}
+        # algorithmic FP64 work of the two MFMA kernels: 2 n^2 T per full
+        # Gram sweep, 2 n^2 k per product sweep
+        sweeps = sum(1 for _ in range(0, nn, min(32768, cdl.ld(nn))))
+        for nm, fl in (("stream_gram", 2.0 * nn * nn * TT), ("stream_product", 2.0 * nn * nn * k)):
+            if nm in kern and kern[nm]["ms"] > 0:
+                nsw = kern[nm]["launches"] / sweeps
+                kern[nm]["sweeps"] = nsw
+                kern[nm]["tflops"] = round(nsw * fl / (kern[nm]["ms"] * 1e-3) / 1e12, 2)
+                kern[nm]["frac_fp64_peak"] = round(kern[nm]["tflops"] / 78.6, 4)
+        return {"ms_per_pair": round(msp * 1e3, 2), "pairs_per_s": round(1.0 / msp, 4),
+                "iterations": [z[2].iterations for z in gz],
+                "certified_error": max(z[2].certified_error for z in gz),
+                "kernels_ms": kern}, tz
+
+    streamed = {"c3_pair": None}
+    if not (args.stream_only and args.stream_grid > 0):
+        swsb = torch.empty(cdl.stream_workspace_bytes(n, T, k, 0), dtype=torch.uint8, device=dev)
+        stream_pair(Xpair, swsb, 1)   # warm-up
+        r, tz = stream_pair(Xpair, swsb, args.steps)
+        if top_ref is not None:
+            r["top50_equal_to_timed_step"] = bool(set(tz.tolist()) == set(top_ref.tolist()))
+        streamed["c3_pair"] = r
+        log("streamed C3 pair: %.2f ms" % r["ms_per_pair"])
+        del swsb
+    if args.stream_grid > 0:
+        Gs = args.stream_grid
+        log("generating the streamed pair G=%d n=%d" % (Gs, Gs * Gs))
+        big = gen.make_pair(Gs, T, 4, 8)
+        Xbig = [torch.from_numpy(big.X0).to(dev), torch.from_numpy(big.X1).to(dev)]
+        del big
+        swsb = torch.empty(cdl.stream_workspace_bytes(Gs * Gs, T, k, 0), dtype=torch.uint8,
+                           device=dev)
+        r, _ = stream_pair(Xbig, swsb, 1)
+        r["workload"] = ("%dx%d grid, n=%d, T=%d, four 8x8 patches, k=%d; the FP64 weight "
+                         "matrix of one snapshot would take %.0f GiB" % (
+                             Gs, Gs, Gs * Gs, T, k, (Gs * Gs) ** 2 * 8 / 2 ** 30))
+        r["workspace_gib"] = round(swsb.numel() / 2 ** 30, 2)
+        streamed["large_pair"] = r
+        log("streamed pair n=%d: %.1f s" % (Gs * Gs, r["ms_per_pair"] / 1e3))
+        del swsb, Xbig
+    torch.cuda.empty_cache()
+    return streamed
 
 
 def cpu_baseline(pair, k, seed, rows=1024, score_rows=64):
