@@ -80,11 +80,11 @@ __device__ __forceinline__ void masked_add8(uint32_t &h, double w, double &a0, d
 }
 
 // Row i of Y for one projection block beta (64 columns).  The sign of edge
-// {i, j} in column r is B(e, i) * q_r(e) = 1 - 2 b, b = bit r of the sign
-// word, complemented when i is the tail (higher global id).  So
-// sum_j s_j w_j = T - 2 M_r with T = sum_j w_j and M_r the sum over the j
-// whose bit is set: only non-negative terms are accumulated (FP64), and the
-// one subtraction at the end loses about log2(T / |y|) ~ 7 bits of the 53.
+// {i, j} in column r is B(e, i) * q_r(e) = c (1 - 2 b), b = bit r of the sign
+// word, c = 1 when i is the head (lower global id) and -1 when it is the
+// tail.  So sum_j s_j w_j = T - 2 M_r with v_j = c_j w_j, T = sum_j v_j and
+// M_r the sum of v_j over the j whose bit is set, all in FP64; the sums'
+// rounding errors stay below 1e-15 sum_j w_j, far below |y| here.
 //
 // A workgroup is 4 waves: 4/P rows, P projection blocks per row.  The P
 // waves of a row share sqrt(W_ij) and the global ids through LDS: per
@@ -99,8 +99,8 @@ __global__ __launch_bounds__(256) void k_rhs(const double *W, int64_t ld, int64_
                                              const int32_t *gid, int64_t k, uint64_t mseed,
                                              double inv_sqrt_k, int nb, double *Yt) {
     constexpr int R = 4 / P;
-    __shared__ double sw[R][P * 64];
-    __shared__ uint32_t sg[R][P * 64];
+    __shared__ double sw[R][P * 64];   // c_j sqrt(W_ij)
+    __shared__ uint2 sz[R][P * 64];    // key halves of {i, j} XOR the mixed seed, beta = 0
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int rs = wv / P, q = wv % P;
     // Workgroups are dispatched round-robin over the XCDs: the projection
@@ -113,47 +113,53 @@ __global__ __launch_bounds__(256) void k_rhs(const double *W, int64_t ld, int64_
     const uint64_t beta = (uint64_t)beta_i;
     const int64_t i = row0 + group * R + rs;
     const bool row_ok = i < row1, active = row_ok && beta_i < nb;
-    const uint64_t gi = !row_ok ? 0 : (gid ? (uint64_t)(uint32_t)gid[i] : (uint64_t)i);
+    const uint32_t gi = !row_ok ? 0u : (gid ? (uint32_t)gid[i] : (uint32_t)i);
+    // The key beta << 40 | lo << 20 | hi of a pair (ids < 2^20) XOR the mixed
+    // seed in 32-bit halves: low = lo << 20 | hi, high = beta << 8 | lo >> 12
+    // (disjoint bits, so the ORs are XORs and beta enters last).
+    const uint32_t seed_lo = (uint32_t)mseed, seed_hi = (uint32_t)(mseed >> 32);
+    const uint32_t kbeta = (uint32_t)beta_i << 8;
     double acc[64];
 #pragma unroll
     for (int r = 0; r < 64; ++r) acc[r] = 0.0;
     double tsum = 0.0;
     const double *row = W + (row_ok ? i - row0 : 0) * ld;
     for (int64_t j0 = 0; j0 < n; j0 += P * 64) {
-        {   // correctly rounded sqrt(W) (the bare hardware instruction is only
-            // an approximation in FP64); zero beyond n
+        {   // per neighbour, once for the P projection blocks: the correctly
+            // rounded sqrt(W) (the bare hardware instruction is only an
+            // approximation in FP64), negated when row i is the edge's tail
+            // (gi > gj: every sign flips, so T and M both take -w), and the
+            // key halves; zero beyond n (no contribution whatever the sign)
             const int64_t j = j0 + q * 64 + lane;
             double v = 0.0;
-            uint32_t g = 0;
+            uint2 z = make_uint2(0u, 0u);
             if (row_ok && j < n) {
-                v = sqrt(row[j]);
-                g = gid ? (uint32_t)gid[j] : (uint32_t)j;
+                const uint32_t gj = gid ? (uint32_t)gid[j] : (uint32_t)j;
+                const double wj = sqrt(row[j]);
+                const uint32_t lo = gi < gj ? gi : gj, hi = gi < gj ? gj : gi;
+                z = make_uint2(((lo << 20) | hi) ^ seed_lo, (lo >> 12) ^ seed_hi);
+                v = gi > gj ? -wj : wj;
             }
             sw[rs][q * 64 + lane] = v;
-            sg[rs][q * 64 + lane] = g;
+            sz[rs][q * 64 + lane] = z;
         }
         __syncthreads();
         if (active) {
 #pragma unroll
             for (int sub = 0; sub < P; ++sub) {
-                const int64_t j = j0 + sub * 64 + lane;
-                if (j < n) {
-                    const double wj = sw[rs][sub * 64 + lane];
-                    const uint64_t gj = sg[rs][sub * 64 + lane];
-                    const uint64_t lo = gi < gj ? gi : gj, hi = gi < gj ? gj : gi;
-                    uint64_t h = splitmix64_mix(mseed ^ ((beta << 40) | (lo << 20) | hi));
-                    if (gi > gj) h = ~h;
-                    tsum += wj;
-                    uint32_t hh = (uint32_t)(h >> 32), hl = (uint32_t)h;
-                    masked_add8(hh, wj, acc[63], acc[62], acc[61], acc[60], acc[59], acc[58], acc[57], acc[56]);
-                    masked_add8(hh, wj, acc[55], acc[54], acc[53], acc[52], acc[51], acc[50], acc[49], acc[48]);
-                    masked_add8(hh, wj, acc[47], acc[46], acc[45], acc[44], acc[43], acc[42], acc[41], acc[40]);
-                    masked_add8(hh, wj, acc[39], acc[38], acc[37], acc[36], acc[35], acc[34], acc[33], acc[32]);
-                    masked_add8(hl, wj, acc[31], acc[30], acc[29], acc[28], acc[27], acc[26], acc[25], acc[24]);
-                    masked_add8(hl, wj, acc[23], acc[22], acc[21], acc[20], acc[19], acc[18], acc[17], acc[16]);
-                    masked_add8(hl, wj, acc[15], acc[14], acc[13], acc[12], acc[11], acc[10], acc[9], acc[8]);
-                    masked_add8(hl, wj, acc[7], acc[6], acc[5], acc[4], acc[3], acc[2], acc[1], acc[0]);
-                }
+                const double ws = sw[rs][sub * 64 + lane];
+                const uint2 z = sz[rs][sub * 64 + lane];
+                const uint64_t h = splitmix64_mix(((uint64_t)(z.y ^ kbeta) << 32) | z.x);
+                tsum += ws;
+                uint32_t hh = (uint32_t)(h >> 32), hl = (uint32_t)h;
+                masked_add8(hh, ws, acc[63], acc[62], acc[61], acc[60], acc[59], acc[58], acc[57], acc[56]);
+                masked_add8(hh, ws, acc[55], acc[54], acc[53], acc[52], acc[51], acc[50], acc[49], acc[48]);
+                masked_add8(hh, ws, acc[47], acc[46], acc[45], acc[44], acc[43], acc[42], acc[41], acc[40]);
+                masked_add8(hh, ws, acc[39], acc[38], acc[37], acc[36], acc[35], acc[34], acc[33], acc[32]);
+                masked_add8(hl, ws, acc[31], acc[30], acc[29], acc[28], acc[27], acc[26], acc[25], acc[24]);
+                masked_add8(hl, ws, acc[23], acc[22], acc[21], acc[20], acc[19], acc[18], acc[17], acc[16]);
+                masked_add8(hl, ws, acc[15], acc[14], acc[13], acc[12], acc[11], acc[10], acc[9], acc[8]);
+                masked_add8(hl, ws, acc[7], acc[6], acc[5], acc[4], acc[3], acc[2], acc[1], acc[0]);
             }
         }
         __syncthreads();
