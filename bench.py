@@ -491,7 +491,8 @@ def streamed_section(args, cdl, gen, torch, dev, Xpair, n, T, k, seed, top_ref):
         # algorithmic FP64 work of the two MFMA kernels: 2 n^2 T per full
         # Gram sweep, 2 n^2 k per product sweep
         sweeps = sum(1 for _ in range(0, nn, min(32768, cdl.ld(nn))))
-        for nm, fl in (("stream_gram", 2.0 * nn * nn * TT), ("stream_product", 2.0 * nn * nn * k)):
+        for nm, fl in (("stream_gram", 2.0 * nn * nn * TT), ("stream_gram_exp", 2.0 * nn * nn * TT),
+                       ("stream_product", 2.0 * nn * nn * k)):
             if nm in kern and kern[nm]["ms"] > 0:
                 nsw = kern[nm]["launches"] / sweeps
                 kern[nm]["sweeps"] = nsw

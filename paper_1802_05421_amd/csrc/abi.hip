@@ -938,7 +938,7 @@ cdl_status cdl_stream_embedding(cdl_ctx *ctx, const double *X, int64_t n, int64_
         for (int digit = 0; digit < 7 && mode != 2; ++digit) {
             for (int64_t r0 = 0; r0 < n; r0 += P) {
                 const int64_t rows = std::min(P, ld - r0);
-                { Timed t_(ctx, "stream_gram_upper"); HIPCHK(launch_gram_panel(w.Xp, Tp, w.sqn, n, ld, r0, rows, false, w.panel, s)); }
+                { Timed t_(ctx, "stream_gram_upper"); HIPCHK(launch_gram_panel(w.Xp, Tp, w.sqn, n, ld, r0, rows, false, w.panel, nullptr, s)); }
                 { Timed t_(ctx, "stream_select"); HIPCHK(launch_select_panel(w.panel, ld, n, r0, std::min(r0 + rows, n), w.sel, s)); }
             }
             { Timed t_(ctx, "stream_select"); HIPCHK(launch_select_pick(w.sel, stats, s)); }
@@ -953,7 +953,7 @@ cdl_status cdl_stream_embedding(cdl_ctx *ctx, const double *X, int64_t n, int64_
     { Timed t_(ctx, "fill_zero"); HIPCHK(launch_fill_zero(w.Xt, kbytes, s)); }
     for (int64_t r0 = 0; r0 < n; r0 += P) {
         const int64_t rows = std::min(P, ld - r0);
-        { Timed t_(ctx, "stream_gram"); HIPCHK(launch_gram_panel(w.Xp, Tp, w.sqn, n, ld, r0, rows, true, w.panel, s)); }
+        { Timed t_(ctx, "stream_gram"); HIPCHK(launch_gram_panel(w.Xp, Tp, w.sqn, n, ld, r0, rows, true, w.panel, nullptr, s)); }
         { Timed t_(ctx, "stream_exp"); HIPCHK(launch_exp_rows(w.panel, ld, n, r0, rows, stats, deg, nullptr, nullptr, s)); }
         { Timed t_(ctx, "rhs"); HIPCHK(launch_rhs_rows(w.panel, ld, n, r0, std::min(r0 + rows, n), gid, k, kp, seed, w.Yt, s)); }
     }
@@ -974,13 +974,19 @@ cdl_status cdl_stream_embedding(cdl_ctx *ctx, const double *X, int64_t n, int64_
     for (int64_t r = 0; r < k; ++r)
         if (!std::isfinite(ynorm[r])) return fail(ctx, CDL_E_NONFINITE, "non-finite right-hand side");
 
-    // One sweep: Prod = W V over the recomputed full row panels (the first
-    // sweep also collects the row norms of S for the certificate).
+    // One sweep: Prod = W V over the recomputed full row panels.  The first
+    // sweep also collects the row norms of S for the certificate (separate
+    // exponential kernel); the others take the weights straight from the
+    // Gram epilogue.
     auto product_sweep = [&](const double *Vt, bool frob) -> cdl_status {
         for (int64_t r0 = 0; r0 < n; r0 += P) {
             const int64_t rows = std::min(P, ld - r0);
-            { Timed t_(ctx, "stream_gram"); HIPCHK(launch_gram_panel(w.Xp, Tp, w.sqn, n, ld, r0, rows, true, w.panel, s)); }
-            { Timed t_(ctx, "stream_exp"); HIPCHK(launch_exp_rows(w.panel, ld, n, r0, rows, stats, nullptr, frob ? w.dinv : nullptr, frob ? w.fro + r0 : nullptr, s)); }
+            if (frob) {
+                { Timed t_(ctx, "stream_gram"); HIPCHK(launch_gram_panel(w.Xp, Tp, w.sqn, n, ld, r0, rows, true, w.panel, nullptr, s)); }
+                { Timed t_(ctx, "stream_exp"); HIPCHK(launch_exp_rows(w.panel, ld, n, r0, rows, stats, nullptr, w.dinv, w.fro + r0, s)); }
+            } else {
+                { Timed t_(ctx, "stream_gram_exp"); HIPCHK(launch_gram_panel(w.Xp, Tp, w.sqn, n, ld, r0, rows, true, w.panel, stats, s)); }
+            }
             { Timed t_(ctx, "stream_product"); HIPCHK(launch_panel_product(Vt, w.panel, ld, n, kp, r0, rows, w.Prod, s)); }
         }
         return CDL_OK;

@@ -103,11 +103,15 @@ constexpr size_t kGramSmem = GramCore::SMEM;
 // row panel needs a buffer of 256 pb rows only.
 // st != nullptr: also fold the smallest and largest upper-triangle key
 // (i < j) into st->kmin / st->kmax (the median selection starts below their
-// common bit prefix).
+// common bit prefix).  kExp: store the weights exp(-D2 / sigma^2) instead
+// (zero on the diagonal and outside n; sigma = wstats[1]), the expression of
+// the separate exponential kernels, so the values are the same bits.
+template <bool kExp>
 __global__ __launch_bounds__(512) void k_gram_dist(const double *Xp, int64_t Tp,
                                                    const double *sqn, int64_t n, int64_t ld,
                                                    double *D2, int ncol, int I0, int pb,
-                                                   int full, int total, SelectState *st) {
+                                                   int full, int total, SelectState *st,
+                                                   const double *wstats) {
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
     double *smem = (double *)smem_raw;
     int I, J;
@@ -144,6 +148,11 @@ __global__ __launch_bounds__(512) void k_gram_dist(const double *Xp, int64_t Tp,
         }
         return d;
     };
+    double s2 = 0.0;
+    if (kExp) {
+        const double sigma = wstats[1];
+        s2 = sigma * sigma;
+    }
     // direct stores: 16 lanes cover 16 consecutive columns of one row
 #pragma unroll
     for (int a = 0; a < GramCore::WTM; ++a)
@@ -152,7 +161,12 @@ __global__ __launch_bounds__(512) void k_gram_dist(const double *Xp, int64_t Tp,
 #pragma unroll
             for (int rr = 0; rr < MfmaF64::R; ++rr) {
                 const int r = GramCore::row_of(a, rr), c = GramCore::col_of(b);
-                out[(m0 + r) * ld + n0 + c] = f(r, c, g.acc[a][b][rr], sa[a][rr], sb[b]);
+                double v = f(r, c, g.acc[a][b][rr], sa[a][rr], sb[b]);
+                if (kExp) {
+                    const int64_t ia = m0 + r, ib = n0 + c;
+                    v = (ia < n && ib < n && ia != ib) ? exp(-v / s2) : 0.0;
+                }
+                out[(m0 + r) * ld + n0 + c] = v;
             }
     if (st) {
 #pragma unroll
@@ -171,9 +185,12 @@ __global__ __launch_bounds__(512) void k_gram_dist(const double *Xp, int64_t Tp,
 static hipError_t gram_attr() {
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_gram_dist,
+        hipError_t e = hipFuncSetAttribute((const void *)k_gram_dist<false>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)kGramSmem);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void *)k_gram_dist<true>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGramSmem);
         if (e != hipSuccess) return e;
         attr = true;
     }
@@ -186,8 +203,8 @@ hipError_t launch_gram_dist(const double *Xp, int64_t Tp, const double *sqn, int
     if (e != hipSuccess) return e;
     const int ncol = (int)(ld / 128);
     const int total = rect_upper_tiles(ld);
-    hipLaunchKernelGGL(k_gram_dist, dim3(total), dim3(512), kGramSmem, s, Xp, Tp, sqn, n, ld,
-                       D2, ncol, 0, (int)(ld / 256), 0, total, st);
+    hipLaunchKernelGGL(k_gram_dist<false>, dim3(total), dim3(512), kGramSmem, s, Xp, Tp, sqn, n,
+                       ld, D2, ncol, 0, (int)(ld / 256), 0, total, st, (const double *)nullptr);
     return hipGetLastError();
 }
 
@@ -198,15 +215,22 @@ int64_t gram_panel_tiles(int64_t ld, int64_t row0, int64_t rows, bool full) {
 
 hipError_t launch_gram_panel(const double *Xp, int64_t Tp, const double *sqn, int64_t n,
                              int64_t ld, int64_t row0, int64_t rows, bool full, double *D2p,
-                             hipStream_t s) {
+                             const double *wstats, hipStream_t s) {
     if (row0 % 256 || rows % 256 || rows <= 0 || row0 + rows > ld) return hipErrorInvalidValue;
+    if (wstats && !full) return hipErrorInvalidValue;
     hipError_t e = gram_attr();
     if (e != hipSuccess) return e;
     const int64_t total = gram_panel_tiles(ld, row0, rows, full);
     if (total <= 0 || total > INT32_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_gram_dist, dim3((unsigned)total), dim3(512), kGramSmem, s, Xp, Tp, sqn,
-                       n, ld, D2p, (int)(ld / 128), (int)(row0 / 256), (int)(rows / 256),
-                       full ? 1 : 0, (int)total, (SelectState *)nullptr);
+    const int ncol = (int)(ld / 128), I0 = (int)(row0 / 256), pb = (int)(rows / 256);
+    if (wstats)
+        hipLaunchKernelGGL(k_gram_dist<true>, dim3((unsigned)total), dim3(512), kGramSmem, s, Xp,
+                           Tp, sqn, n, ld, D2p, ncol, I0, pb, 1, (int)total,
+                           (SelectState *)nullptr, wstats);
+    else
+        hipLaunchKernelGGL(k_gram_dist<false>, dim3((unsigned)total), dim3(512), kGramSmem, s, Xp,
+                           Tp, sqn, n, ld, D2p, ncol, I0, pb, full ? 1 : 0, (int)total,
+                           (SelectState *)nullptr, (const double *)nullptr);
     return hipGetLastError();
 }
 

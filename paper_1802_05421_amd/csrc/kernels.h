@@ -41,10 +41,12 @@ hipError_t launch_gram_dist(const double *Xp, int64_t Tp, const double *sqn, int
                             int64_t ld, double *D2, SelectState *st, hipStream_t s);
 // Row panel [row0, row0 + rows) of the same tiles (row0 and rows multiples of
 // 256): the upper-triangle cover only (full = false) or every tile of the
-// rows (full = true), row i stored at D2p + (i - row0) ld.
+// rows (full = true), row i stored at D2p + (i - row0) ld.  wstats != nullptr
+// (full panels only): store the weights exp(-D2 / sigma^2) with the zero
+// diagonal instead, sigma = wstats[1] (the same bits as launch_exp_rows).
 hipError_t launch_gram_panel(const double *Xp, int64_t Tp, const double *sqn, int64_t n,
                              int64_t ld, int64_t row0, int64_t rows, bool full, double *D2p,
-                             hipStream_t s);
+                             const double *wstats, hipStream_t s);
 int64_t gram_panel_tiles(int64_t ld, int64_t row0, int64_t rows, bool full);
 hipError_t launch_select_reset(SelectState *st, hipStream_t s);
 // Streamed median: start at the top bit; per digit one launch_select_panel

@@ -21,9 +21,12 @@
 
 namespace cdl {
 
-// SplitMix64 output function (Steele, Lea & Flood, OOPSLA 2014).
-__device__ inline uint64_t splitmix64_mix(uint64_t z) {
-    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+// SplitMix64 output function (Steele, Lea & Flood, OOPSLA 2014), split after
+// its first step z ^ (z >> 30): that step is linear over GF(2), so it can be
+// applied to the parts of a key separately and the results XORed.
+__device__ inline uint64_t xorshift30(uint64_t z) { return z ^ (z >> 30); }
+__device__ inline uint64_t splitmix64_mix_tail(uint64_t z) {
+    z = z * 0xbf58476d1ce4e5b9ull;
     z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
     return z ^ (z >> 31);
 }
@@ -100,7 +103,7 @@ __global__ __launch_bounds__(256) void k_rhs(const double *W, int64_t ld, int64_
                                              double inv_sqrt_k, int nb, double *Yt) {
     constexpr int R = 4 / P;
     __shared__ double sw[R][P * 64];   // c_j sqrt(W_ij)
-    __shared__ uint2 sz[R][P * 64];    // key halves of {i, j} XOR the mixed seed, beta = 0
+    __shared__ uint2 sz[R][P * 64];    // xorshift30 of the key of {i, j} (beta = 0) XOR the mixed seed
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int rs = wv / P, q = wv % P;
     // Workgroups are dispatched round-robin over the XCDs: the projection
@@ -118,7 +121,7 @@ __global__ __launch_bounds__(256) void k_rhs(const double *W, int64_t ld, int64_
     // seed in 32-bit halves: low = lo << 20 | hi, high = beta << 8 | lo >> 12
     // (disjoint bits, so the ORs are XORs and beta enters last).
     const uint32_t seed_lo = (uint32_t)mseed, seed_hi = (uint32_t)(mseed >> 32);
-    const uint32_t kbeta = (uint32_t)beta_i << 8;
+    const uint64_t fbeta = xorshift30((uint64_t)((uint32_t)beta_i << 8) << 32);
     double acc[64];
 #pragma unroll
     for (int r = 0; r < 64; ++r) acc[r] = 0.0;
@@ -137,7 +140,9 @@ __global__ __launch_bounds__(256) void k_rhs(const double *W, int64_t ld, int64_
                 const uint32_t gj = gid ? (uint32_t)gid[j] : (uint32_t)j;
                 const double wj = sqrt(row[j]);
                 const uint32_t lo = gi < gj ? gi : gj, hi = gi < gj ? gj : gi;
-                z = make_uint2(((lo << 20) | hi) ^ seed_lo, (lo >> 12) ^ seed_hi);
+                const uint64_t f = xorshift30(((uint64_t)((lo >> 12) ^ seed_hi) << 32) |
+                                              (((lo << 20) | hi) ^ seed_lo));
+                z = make_uint2((uint32_t)f, (uint32_t)(f >> 32));
                 v = gi > gj ? -wj : wj;
             }
             sw[rs][q * 64 + lane] = v;
@@ -149,7 +154,7 @@ __global__ __launch_bounds__(256) void k_rhs(const double *W, int64_t ld, int64_
             for (int sub = 0; sub < P; ++sub) {
                 const double ws = sw[rs][sub * 64 + lane];
                 const uint2 z = sz[rs][sub * 64 + lane];
-                const uint64_t h = splitmix64_mix(((uint64_t)(z.y ^ kbeta) << 32) | z.x);
+                const uint64_t h = splitmix64_mix_tail((((uint64_t)z.y << 32) | z.x) ^ fbeta);
                 tsum += ws;
                 uint32_t hh = (uint32_t)(h >> 32), hl = (uint32_t)h;
                 masked_add8(hh, ws, acc[63], acc[62], acc[61], acc[60], acc[59], acc[58], acc[57], acc[56]);
