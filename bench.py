@@ -54,6 +54,8 @@ def kernel_model(name, n, k, T, prec):
         return "mfma", float(n) * n * T, "TFLOP/s", PEAK["fp64_mfma"]      # half of n x n x T
     if name == "rhs":
         return "alu", float(n) * (n - 1) * k, "TFLOP/s", PEAK["fp64_valu_add"]
+    if name == "rhs_pair":   # both snapshots of the pair
+        return "alu", 2.0 * n * (n - 1) * k, "TFLOP/s", PEAK["fp64_valu_add"]
     if name == "apply":
         return "hbm", float(n) * n * esz, "GB/s", PEAK["hbm"]
     if name == "exp_degree":
@@ -166,16 +168,23 @@ def main():
     Fb = {p: torch.empty(n, dtype=torch.float64, device=dev) for p in precs}
     Tb = {p: torch.empty(50, dtype=torch.int32, device=dev) for p in precs}
 
+    sws_pair = torch.empty_like(sws)
+
     def step(prec, sigma=None, Xs=X, tol=None, dense=False):
+        # graphs and chains of both snapshots, then both solves with the
+        # right-hand sides of the pair made in one sweep (shared sign words)
         tol = args.tol if tol is None else tol
-        infos = []
+        infos, chs = [], []
         for t in (0, 1):
             cdl.build_graph(Xs[t], sigma=sigma, ws=gws, out=graphs[t], check=True)
             ch = cdl.build_chain(graphs[t], prec=prec, depth=0, depth_max=DMAX, buf=chb[prec][t])
             if dense:   # Algorithm 2's schedule: one dense P1 product per iteration
                 cdl.chain_densify(ch)
-            _, si = cdl.solve_embedding(graphs[t], ch, k, seed, tol=tol, max_iter=30, ws=sws,
-                                        Z=Zb[prec][t])
+            chs.append(ch)
+        _, _, si0, si1 = cdl.solve_embedding_pair(graphs[0], chs[0], graphs[1], chs[1], k, seed,
+                                                  tol=tol, max_iter=30, ws=(sws, sws_pair),
+                                                  Z=(Zb[prec][0], Zb[prec][1]))
+        for ch, si in ((chs[0], si0), (chs[1], si1)):
             infos.append({"depth": ch.info.depth, "dense_levels": ch.info.dense_levels,
                           "rho_hat": round(ch.info.rho_hat, 5),
                           "rho_bound": round(ch.info.rho_bound, 5),

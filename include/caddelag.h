@@ -333,6 +333,33 @@ cdl_status cdl_solve_embedding(cdl_ctx *ctx, const double *W, const double *deg,
                                double *Z, void *ws, size_t ws_bytes,
                                cdl_solve_info *info);
 
+/* Both snapshots of a pair on one node set (the same n and global ids):
+ * cdl_solve_embedding for each, with the right-hand sides of both made in
+ * one sweep over W0 and W1.  The two graphs share the projection on every
+ * edge (the same seed and ids give the same signs), so each edge's sign word
+ * and each lane mask is made once for both (Algorithm 4 over Algorithm 3's
+ * embeddings of G1 and G2).  Results equal two cdl_solve_embedding calls up
+ * to the rounding of the right-hand sides' sums (< 1e-15 relative).
+ *   W0, deg0, stats0, chain0, chain_info0   snapshot 0 as for
+ *           cdl_solve_embedding (likewise for snapshot 1; the chains may
+ *           differ in type and depth).
+ *   gid, n, k, seed, solver, tol, max_iter   shared; k >= 1.
+ *   Z0, Z1  device outputs, n x k FP64 each.
+ *   ws0, ws1  two solve workspaces of at least ws_bytes each (the size of
+ *           cdl_workspace_bytes for that chain type).
+ *   info0, info1  host outputs (may be NULL).
+ * Snapshot 0 is solved first; if it fails, its status is returned and Z1 is
+ * unspecified.  Errors as for cdl_solve_embedding. */
+cdl_status cdl_solve_embedding_pair(cdl_ctx *ctx, const double *W0, const double *deg0,
+                                    const double *stats0, const void *chain0,
+                                    const cdl_chain_info *chain_info0, const double *W1,
+                                    const double *deg1, const double *stats1,
+                                    const void *chain1, const cdl_chain_info *chain_info1,
+                                    const int32_t *gid, int64_t n, int64_t k, uint64_t seed,
+                                    cdl_solver solver, double tol, int max_iter, double *Z0,
+                                    double *Z1, void *ws0, void *ws1, size_t ws_bytes,
+                                    cdl_solve_info *info0, cdl_solve_info *info1);
+
 /* ---- streamed snapshots (graphs larger than device memory) ---------------- */
 
 /* One snapshot end to end - bandwidth, weights, degrees, right-hand sides and

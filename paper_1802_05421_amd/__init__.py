@@ -34,6 +34,7 @@ from .api import (  # noqa: E402,F401
     set_timing,
     timing,
     solve_embedding,
+    solve_embedding_pair,
     stream_embedding,
     stream_workspace_bytes,
     workspace_bytes,

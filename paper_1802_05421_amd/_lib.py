@@ -98,6 +98,9 @@ def load():
         "cdl_chain_densify": (I, [P, i64, P, sz, C.POINTER(ChainInfo)]),
         "cdl_solve_embedding": (I, [P, P, P, P, P, i64, P, C.POINTER(ChainInfo), i64, d, u64,
                                     I, d, I, P, P, sz, C.POINTER(SolveInfo)]),
+        "cdl_solve_embedding_pair": (I, [P, P, P, P, P, C.POINTER(ChainInfo), P, P, P, P,
+                                         C.POINTER(ChainInfo), P, i64, i64, u64, I, d, I, P, P,
+                                         P, P, sz, C.POINTER(SolveInfo), C.POINTER(SolveInfo)]),
         "cdl_stream_workspace_bytes": (I, [i64, i64, i64, i64, C.POINTER(sz)]),
         "cdl_stream_embedding": (I, [P, P, i64, i64, i64, d, P, i64, u64, d, I, i64, P, P, P,
                                      P, sz, C.POINTER(SolveInfo)]),

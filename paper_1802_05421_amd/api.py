@@ -271,6 +271,39 @@ def solve_embedding(g: Graph, chain: Chain, k: int, seed: int, tol: float = 1e-8
     return Z, info
 
 
+def solve_embedding_pair(g0: Graph, chain0: Chain, g1: Graph, chain1: Chain, k: int, seed: int,
+                         tol: float = 1e-8, max_iter: int = 30,
+                         gid: Optional[torch.Tensor] = None, solver: str = "richardson",
+                         ws: Optional[tuple] = None, Z: Optional[tuple] = None,
+                         raise_noconv: bool = True):
+    """Embeddings of both snapshots of a pair on one node set, their
+    right-hand sides made in one sweep (cdl_solve_embedding_pair).
+    Returns (Z0, Z1, info0, info1)."""
+    if g0.n != g1.n:
+        raise ValueError("the two snapshots need the same node set")
+    dev = g0.W.device
+    ctx = context(dev.index)
+    need = max(workspace_bytes(g0.n, 1, k, max(c.info.depth, 1), L.PREC_NAME[c.info.prec])["solve"]
+               for c in (chain0, chain1))
+    if ws is None or min(w.numel() for w in ws) < need:
+        ws = (_ws(need, dev), _ws(need, dev))
+    if Z is None:
+        Z = (torch.empty((g0.n, k), dtype=torch.float64, device=dev),
+             torch.empty((g0.n, k), dtype=torch.float64, device=dev))
+    if gid is not None and (gid.dtype != torch.int32 or not gid.is_cuda):
+        raise ValueError("gid must be a CUDA int32 vector")
+    i0, i1 = L.SolveInfo(), L.SolveInfo()
+    st = _lib().cdl_solve_embedding_pair(
+        ctx.h, _ptr(g0.W), _ptr(g0.deg), _ptr(g0.stats), _ptr(chain0.buf), C.byref(chain0.info),
+        _ptr(g1.W), _ptr(g1.deg), _ptr(g1.stats), _ptr(chain1.buf), C.byref(chain1.info),
+        _ptr(gid), g0.n, k, C.c_uint64(seed), L.SOLVER[solver], float(tol), max_iter,
+        _ptr(Z[0]), _ptr(Z[1]), _ptr(ws[0]), _ptr(ws[1]), min(w.numel() for w in ws),
+        C.byref(i0), C.byref(i1))
+    if st != 0 and not (st == 6 and not raise_noconv):
+        _check(st, ctx.h)
+    return Z[0], Z[1], i0, i1
+
+
 def stream_workspace_bytes(n: int, T: int, k: int, panel_rows: int = 0) -> int:
     out = C.c_size_t()
     _check(_lib().cdl_stream_workspace_bytes(n, T, k, panel_rows, C.byref(out)))

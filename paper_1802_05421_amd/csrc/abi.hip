@@ -734,44 +734,17 @@ cdl_status cdl_chain_densify(cdl_ctx *ctx, int64_t n, void *chain, size_t chain_
 
 // ---- embedding -------------------------------------------------------------------
 
-cdl_status cdl_solve_embedding(cdl_ctx *ctx, const double *W, const double *deg,
-                               const double *stats, const int32_t *gid, int64_t n,
-                               const void *chain, const cdl_chain_info *ci, int64_t k,
-                               double eps_rp, uint64_t seed, cdl_solver solver, double tol,
-                               int max_iter, double *Z, void *ws, size_t ws_bytes,
-                               cdl_solve_info *info) {
-    if (!ctx) return CDL_E_ARG;
-    if (n < 2 || n > (1 << 20)) return fail(ctx, CDL_E_ARG, "bad n");
-    if (!W || !deg || !stats || !chain || !ci || !Z || !ws) return fail(ctx, CDL_E_ARG, "null pointer");
-    if (!aligned(W, 16) || !aligned(chain, kAlign) || !aligned(ws, kAlign) || !aligned(Z, 8))
-        return fail(ctx, CDL_E_ARG, "misaligned pointer");
-    if (k <= 0) {
-        if (!(eps_rp > 0.0 && eps_rp < 1.0)) return fail(ctx, CDL_E_ARG, "need 0 < eps_rp < 1 when k <= 0");
-        k = (int64_t)std::ceil(std::log((double)n / eps_rp));
-    }
-    if (k > (int64_t)1 << 20) return fail(ctx, CDL_E_ARG, "k too large");
-    if (ci->depth < 1 || ci->depth > CDL_MAX_DEPTH || !valid_prec(ci->prec) ||
-        ci->dense_levels < 0 || ci->dense_levels > CDL_MAX_DEPTH || (ci->dense_levels > 0 && ci->depth != 1))
-        return fail(ctx, CDL_E_ARG, "invalid chain info");
-    if (max_iter < 1 || max_iter > 64) return fail(ctx, CDL_E_ARG, "max_iter must be in [1, 64]");
-    if (solver != CDL_RICHARDSON && solver != CDL_PCG) return fail(ctx, CDL_E_ARG, "bad solver");
-    Arena need(nullptr);
-    plan_solve(need, n, k, ci->prec);
-    if (ws_bytes < need.off) return fail(ctx, CDL_E_WORKSPACE, "solve workspace too small");
-    Arena a(ws);
-    SolveWs w = plan_solve(a, n, k, ci->prec);
-    Arena ac((void *)chain);
-    ChainBuf c = plan_chain(ac, n, ci->prec, ci->depth);
+// The solve from the right-hand sides in w.Yt (X = 0 in w.Xt): norms, the
+// refinement iterations and the centred Z.  Syncs once per iteration.
+static cdl_status solve_from_rhs(cdl_ctx *ctx, const double *W, const double *deg,
+                                 const double *stats, int64_t n, const ChainBuf &c,
+                                 const cdl_chain_info *ci, int64_t k, cdl_solver solver,
+                                 double tol, int max_iter, double *Z, const SolveWs &w,
+                                 cdl_solve_info *info) {
     const int prec = ci->prec;
     const int64_t ld = pad_n(n), kp = pad_k(k);
     const size_t panel = (size_t)kp * ld;
     hipStream_t s = ctx->stream;
-    HIPCHK(hipSetDevice(ctx->device));
-    if (info) std::memset(info, 0, sizeof(*info));
-
-    { Timed t_(ctx, "fill_zero"); HIPCHK(launch_fill_zero(w.Yt, panel * sizeof(double), s)); }
-    { Timed t_(ctx, "fill_zero"); HIPCHK(launch_fill_zero(w.Xt, panel * sizeof(double), s)); }
-    { Timed t_(ctx, "rhs"); HIPCHK(launch_rhs(W, ld, n, gid, k, kp, seed, w.Yt, s)); }
     const int nparts = residual_parts(ld), ntiles = residual_tiles(ld, kp);
     const int scaled = prec == 3;   // FP16 operands need a power-of-two scale
     { Timed t_(ctx, "residual_init"); HIPCHK(launch_residual_k(prec, w.Xt, W, w.Yt, deg, c.dm, ld, n, kp, k, 1, (double *)w.part, w.Rt, w.V64, w.Vlo[0], w.npart, w.mpart, s)); }
@@ -879,6 +852,92 @@ cdl_status cdl_solve_embedding(cdl_ctx *ctx, const double *W, const double *deg,
         return fail(ctx, CDL_E_NOCONV, buf);
     }
     return CDL_OK;
+}
+
+// Arguments of one snapshot's solve (k already resolved).
+static cdl_status check_solve(cdl_ctx *ctx, const double *W, const double *deg,
+                              const double *stats, int64_t n, const void *chain,
+                              const cdl_chain_info *ci, int64_t k, cdl_solver solver,
+                              int max_iter, const double *Z, const void *ws, size_t ws_bytes) {
+    if (n < 2 || n > (1 << 20)) return fail(ctx, CDL_E_ARG, "bad n");
+    if (!W || !deg || !stats || !chain || !ci || !Z || !ws) return fail(ctx, CDL_E_ARG, "null pointer");
+    if (!aligned(W, 16) || !aligned(chain, kAlign) || !aligned(ws, kAlign) || !aligned(Z, 8))
+        return fail(ctx, CDL_E_ARG, "misaligned pointer");
+    if (k < 1 || k > (int64_t)1 << 20) return fail(ctx, CDL_E_ARG, "k must be in [1, 2^20]");
+    if (ci->depth < 1 || ci->depth > CDL_MAX_DEPTH || !valid_prec(ci->prec) ||
+        ci->dense_levels < 0 || ci->dense_levels > CDL_MAX_DEPTH || (ci->dense_levels > 0 && ci->depth != 1))
+        return fail(ctx, CDL_E_ARG, "invalid chain info");
+    if (max_iter < 1 || max_iter > 64) return fail(ctx, CDL_E_ARG, "max_iter must be in [1, 64]");
+    if (solver != CDL_RICHARDSON && solver != CDL_PCG) return fail(ctx, CDL_E_ARG, "bad solver");
+    Arena need(nullptr);
+    plan_solve(need, n, k, ci->prec);
+    if (ws_bytes < need.off) return fail(ctx, CDL_E_WORKSPACE, "solve workspace too small");
+    return CDL_OK;
+}
+
+cdl_status cdl_solve_embedding(cdl_ctx *ctx, const double *W, const double *deg,
+                               const double *stats, const int32_t *gid, int64_t n,
+                               const void *chain, const cdl_chain_info *ci, int64_t k,
+                               double eps_rp, uint64_t seed, cdl_solver solver, double tol,
+                               int max_iter, double *Z, void *ws, size_t ws_bytes,
+                               cdl_solve_info *info) {
+    if (!ctx) return CDL_E_ARG;
+    if (k <= 0) {
+        if (!(eps_rp > 0.0 && eps_rp < 1.0)) return fail(ctx, CDL_E_ARG, "need 0 < eps_rp < 1 when k <= 0");
+        if (n < 2) return fail(ctx, CDL_E_ARG, "bad n");
+        k = (int64_t)std::ceil(std::log((double)n / eps_rp));
+    }
+    cdl_status st = check_solve(ctx, W, deg, stats, n, chain, ci, k, solver, max_iter, Z, ws, ws_bytes);
+    if (st != CDL_OK) return st;
+    Arena a(ws);
+    SolveWs w = plan_solve(a, n, k, ci->prec);
+    Arena ac((void *)chain);
+    ChainBuf c = plan_chain(ac, n, ci->prec, ci->depth);
+    const int64_t ld = pad_n(n), kp = pad_k(k);
+    const size_t panel = (size_t)kp * ld;
+    hipStream_t s = ctx->stream;
+    HIPCHK(hipSetDevice(ctx->device));
+    if (info) std::memset(info, 0, sizeof(*info));
+
+    { Timed t_(ctx, "fill_zero"); HIPCHK(launch_fill_zero(w.Yt, panel * sizeof(double), s)); }
+    { Timed t_(ctx, "fill_zero"); HIPCHK(launch_fill_zero(w.Xt, panel * sizeof(double), s)); }
+    { Timed t_(ctx, "rhs"); HIPCHK(launch_rhs(W, ld, n, gid, k, kp, seed, w.Yt, s)); }
+    return solve_from_rhs(ctx, W, deg, stats, n, c, ci, k, solver, tol, max_iter, Z, w, info);
+}
+
+cdl_status cdl_solve_embedding_pair(cdl_ctx *ctx, const double *W0, const double *deg0,
+                                    const double *stats0, const void *chain0,
+                                    const cdl_chain_info *ci0, const double *W1,
+                                    const double *deg1, const double *stats1,
+                                    const void *chain1, const cdl_chain_info *ci1,
+                                    const int32_t *gid, int64_t n, int64_t k, uint64_t seed,
+                                    cdl_solver solver, double tol, int max_iter, double *Z0,
+                                    double *Z1, void *ws0, void *ws1, size_t ws_bytes,
+                                    cdl_solve_info *info0, cdl_solve_info *info1) {
+    if (!ctx) return CDL_E_ARG;
+    cdl_status st = check_solve(ctx, W0, deg0, stats0, n, chain0, ci0, k, solver, max_iter, Z0, ws0, ws_bytes);
+    if (st == CDL_OK)
+        st = check_solve(ctx, W1, deg1, stats1, n, chain1, ci1, k, solver, max_iter, Z1, ws1, ws_bytes);
+    if (st != CDL_OK) return st;
+    if (W0 == W1 || ws0 == ws1 || Z0 == Z1) return fail(ctx, CDL_E_ARG, "the two snapshots need their own W, Z and workspace");
+    Arena a0(ws0), a1(ws1);
+    SolveWs w0 = plan_solve(a0, n, k, ci0->prec), w1 = plan_solve(a1, n, k, ci1->prec);
+    Arena ac0((void *)chain0), ac1((void *)chain1);
+    ChainBuf c0 = plan_chain(ac0, n, ci0->prec, ci0->depth), c1 = plan_chain(ac1, n, ci1->prec, ci1->depth);
+    const int64_t ld = pad_n(n), kp = pad_k(k);
+    const size_t pbytes = (size_t)kp * ld * sizeof(double);
+    hipStream_t s = ctx->stream;
+    HIPCHK(hipSetDevice(ctx->device));
+    if (info0) std::memset(info0, 0, sizeof(*info0));
+    if (info1) std::memset(info1, 0, sizeof(*info1));
+    { Timed t_(ctx, "fill_zero"); HIPCHK(launch_fill_zero(w0.Yt, pbytes, s)); }
+    { Timed t_(ctx, "fill_zero"); HIPCHK(launch_fill_zero(w0.Xt, pbytes, s)); }
+    { Timed t_(ctx, "fill_zero"); HIPCHK(launch_fill_zero(w1.Yt, pbytes, s)); }
+    { Timed t_(ctx, "fill_zero"); HIPCHK(launch_fill_zero(w1.Xt, pbytes, s)); }
+    { Timed t_(ctx, "rhs_pair"); HIPCHK(launch_rhs_pair(W0, W1, ld, n, gid, k, kp, seed, w0.Yt, w1.Yt, s)); }
+    st = solve_from_rhs(ctx, W0, deg0, stats0, n, c0, ci0, k, solver, tol, max_iter, Z0, w0, info0);
+    if (st != CDL_OK) return st;
+    return solve_from_rhs(ctx, W1, deg1, stats1, n, c1, ci1, k, solver, tol, max_iter, Z1, w1, info1);
 }
 
 // ---- streamed snapshots ---------------------------------------------------------

@@ -109,6 +109,11 @@ int apply_splits(int prec, int64_t ld, int64_t kpad, int64_t n);
 // ---- solve ------------------------------------------------------------------
 hipError_t launch_rhs(const double *W, int64_t ld, int64_t n, const int32_t *gid, int64_t k,
                       int64_t kpad, uint64_t seed, double *Yt, hipStream_t s);
+// Y0 and Y1 of two snapshots on one node set (the same ids, so the same
+// sign words) in one sweep over W0 and W1.
+hipError_t launch_rhs_pair(const double *W0, const double *W1, int64_t ld, int64_t n,
+                           const int32_t *gid, int64_t k, int64_t kpad, uint64_t seed,
+                           double *Y0t, double *Y1t, hipStream_t s);
 // Rows [row0, row1) of Y from a row panel of W (row i at Wp + (i - row0) ld).
 hipError_t launch_rhs_rows(const double *Wp, int64_t ld, int64_t n, int64_t row0, int64_t row1,
                            const int32_t *gid, int64_t k, int64_t kpad, uint64_t seed,

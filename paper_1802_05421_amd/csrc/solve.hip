@@ -188,6 +188,184 @@ __global__ __launch_bounds__(256) void k_rhs(const double *W, int64_t ld, int64_
     Yt[r * ld + i] = r < k ? (tsum - 2.0 * acc[0]) * inv_sqrt_k : 0.0;
 }
 
+// masked_add8 for two sums with the same signs: one lane mask per column
+// serves acc_a (+= wa) and acc_b (+= wb).
+__device__ __forceinline__ void masked_add8x2(uint32_t &h, double wa, double wb, double &a0,
+                                              double &a1, double &a2, double &a3, double &a4,
+                                              double &a5, double &a6, double &a7, double &b0,
+                                              double &b1, double &b2, double &b3, double &b4,
+                                              double &b5, double &b6, double &b7) {
+    uint64_t sv, m0, m1, m2, m3, m4, m5, m6, m7;
+    asm volatile(
+        "s_mov_b64 %[sv], exec\n\t"
+        "v_add_co_u32 %[h], %[m0], %[h], %[h]\n\t"
+        "v_add_co_u32 %[h], %[m1], %[h], %[h]\n\t"
+        "v_add_co_u32 %[h], %[m2], %[h], %[h]\n\t"
+        "v_add_co_u32 %[h], %[m3], %[h], %[h]\n\t"
+        "v_add_co_u32 %[h], %[m4], %[h], %[h]\n\t"
+        "v_add_co_u32 %[h], %[m5], %[h], %[h]\n\t"
+        "v_add_co_u32 %[h], %[m6], %[h], %[h]\n\t"
+        "v_add_co_u32 %[h], %[m7], %[h], %[h]\n\t"
+        "s_and_b64 exec, %[sv], %[m0]\n\t"
+        "v_add_f64 %[a0], %[a0], %[wa]\n\t"
+        "v_add_f64 %[b0], %[b0], %[wb]\n\t"
+        "s_and_b64 exec, %[sv], %[m1]\n\t"
+        "v_add_f64 %[a1], %[a1], %[wa]\n\t"
+        "v_add_f64 %[b1], %[b1], %[wb]\n\t"
+        "s_and_b64 exec, %[sv], %[m2]\n\t"
+        "v_add_f64 %[a2], %[a2], %[wa]\n\t"
+        "v_add_f64 %[b2], %[b2], %[wb]\n\t"
+        "s_and_b64 exec, %[sv], %[m3]\n\t"
+        "v_add_f64 %[a3], %[a3], %[wa]\n\t"
+        "v_add_f64 %[b3], %[b3], %[wb]\n\t"
+        "s_and_b64 exec, %[sv], %[m4]\n\t"
+        "v_add_f64 %[a4], %[a4], %[wa]\n\t"
+        "v_add_f64 %[b4], %[b4], %[wb]\n\t"
+        "s_and_b64 exec, %[sv], %[m5]\n\t"
+        "v_add_f64 %[a5], %[a5], %[wa]\n\t"
+        "v_add_f64 %[b5], %[b5], %[wb]\n\t"
+        "s_and_b64 exec, %[sv], %[m6]\n\t"
+        "v_add_f64 %[a6], %[a6], %[wa]\n\t"
+        "v_add_f64 %[b6], %[b6], %[wb]\n\t"
+        "s_and_b64 exec, %[sv], %[m7]\n\t"
+        "v_add_f64 %[a7], %[a7], %[wa]\n\t"
+        "v_add_f64 %[b7], %[b7], %[wb]\n\t"
+        "s_mov_b64 exec, %[sv]"
+        : [h] "+v"(h), [a0] "+v"(a0), [a1] "+v"(a1), [a2] "+v"(a2), [a3] "+v"(a3),
+          [a4] "+v"(a4), [a5] "+v"(a5), [a6] "+v"(a6), [a7] "+v"(a7), [b0] "+v"(b0),
+          [b1] "+v"(b1), [b2] "+v"(b2), [b3] "+v"(b3), [b4] "+v"(b4), [b5] "+v"(b5),
+          [b6] "+v"(b6), [b7] "+v"(b7), [sv] "=&s"(sv), [m0] "=&s"(m0), [m1] "=&s"(m1),
+          [m2] "=&s"(m2), [m3] "=&s"(m3), [m4] "=&s"(m4), [m5] "=&s"(m5), [m6] "=&s"(m6),
+          [m7] "=&s"(m7)
+        : [wa] "v"(wa), [wb] "v"(wb)
+        : "scc");
+}
+
+// Rows of Y for two snapshots on one node set (the same global ids, so the
+// same sign words on every edge): Y0 from W0 and Y1 from W1 in one sweep,
+// each word and each lane mask serving both.  A workgroup is one row and 16
+// waves: projection block beta = 4 g + wave / 4 (g the block group), the
+// wave's quarter of it the 16 columns [64 beta + 16 c, 64 beta + 16 c + 16),
+// so that 32 accumulators per lane leave room for four waves per SIMD.
+// Neighbours come in chunks of 512; every thread stages two sign words and
+// one signed square root of the chunk (the stage is the same work for every
+// wave, so the one barrier per chunk finds them together), into one of two
+// LDS buffers, and issues the next chunk's loads before summing this one.
+__global__ __launch_bounds__(1024) void k_rhs_pair(const double *W0, const double *W1, int64_t ld,
+                                                   int64_t n, const int32_t *gid, int64_t k,
+                                                   uint64_t mseed, double inv_sqrt_k, int nb,
+                                                   double *Y0t, double *Y1t) {
+    constexpr int C = 512;
+    __shared__ uint64_t sh[2][4][C];
+    __shared__ double sw[2][2][C];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int bq = wv >> 2, quarter = wv & 3;
+    const int nbg = (nb + 3) / 4;
+    const int w = blockIdx.x, per = kNumXcd * nbg, l = w % per;
+    const int64_t i = (int64_t)(w / per) * kNumXcd + l % kNumXcd;
+    const int bgrp = l / kNumXcd;
+    const bool row_ok = i < n, active = row_ok && bgrp * 4 + bq < nb;
+    const uint32_t gi = !row_ok ? 0u : (gid ? (uint32_t)gid[i] : (uint32_t)i);
+    // stage roles: neighbour jj = t % C; the words of blocks 4 g + 2 s and
+    // 4 g + 2 s + 1, and the root of snapshot s, s = t / C
+    const int jj = t & (C - 1), sr = t / C;
+    const uint64_t kb0 = (uint64_t)(bgrp * 4 + 2 * sr) << 40, kb1 = kb0 + (1ull << 40);
+    const double *wrow = (sr == 0 ? W0 : W1) + (row_ok ? i : 0) * ld;
+    double acc0[16], acc1[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc0[q] = acc1[q] = 0.0;
+    double t0 = 0.0, t1 = 0.0;
+    auto load = [&](int64_t j0, uint32_t &g, double &v) {
+        const int64_t j = j0 + jj;
+        g = 0u;
+        v = 0.0;
+        if (row_ok && j < n) {
+            g = gid ? (uint32_t)gid[j] : (uint32_t)j;
+            v = wrow[j];
+        }
+    };
+    auto word = [&](uint64_t key) -> uint64_t {
+        uint64_t z = mseed ^ key;
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+        return z ^ (z >> 31);
+    };
+    uint32_t gj;
+    double wv0;
+    load(0, gj, wv0);
+    int buf = 0;
+    for (int64_t j0 = 0; j0 < n; j0 += C, buf ^= 1) {
+        {   // stage this chunk: zero beyond n (no contribution whatever the sign)
+            const uint32_t lo = gi < gj ? gi : gj, hi = gi < gj ? gj : gi;
+            const uint64_t key = ((uint64_t)lo << 20) | (uint64_t)hi;
+            sh[buf][2 * sr][jj] = word(kb0 | key);
+            sh[buf][2 * sr + 1][jj] = word(kb1 | key);
+            const double r = sqrt(wv0);   // correctly rounded
+            sw[buf][sr][jj] = gi > gj ? -r : r;
+        }
+        load(j0 + C, gj, wv0);   // in flight while this chunk is summed
+        __syncthreads();
+        if (active) {
+#pragma unroll 2
+            for (int sub = 0; sub < C / 64; ++sub) {
+                const int q = sub * 64 + lane;
+                const uint64_t hw = sh[buf][bq][q];
+                const double a = sw[buf][0][q], b = sw[buf][1][q];
+                // the quarter's 16 bits, most significant first
+                uint32_t h = (uint32_t)(hw >> (16 * quarter)) << 16;
+                t0 += a;
+                t1 += b;
+                masked_add8x2(h, a, b, acc0[15], acc0[14], acc0[13], acc0[12], acc0[11], acc0[10],
+                              acc0[9], acc0[8], acc1[15], acc1[14], acc1[13], acc1[12], acc1[11],
+                              acc1[10], acc1[9], acc1[8]);
+                masked_add8x2(h, a, b, acc0[7], acc0[6], acc0[5], acc0[4], acc0[3], acc0[2],
+                              acc0[1], acc0[0], acc1[7], acc1[6], acc1[5], acc1[4], acc1[3],
+                              acc1[2], acc1[1], acc1[0]);
+            }
+        }
+    }
+    if (!active) return;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        t0 += __shfl_xor(t0, o);
+        t1 += __shfl_xor(t1, o);
+    }
+    // Butterfly transpose-reduction over each 16-lane group, then across the
+    // groups: lane l ends with column l % 16 summed over all 64 lanes.
+#pragma unroll
+    for (int s = 8; s >= 1; s >>= 1) {
+        const bool up = (lane & s) != 0;
+#pragma unroll
+        for (int q2 = 0; q2 < s; ++q2) {
+            const double s0 = up ? acc0[q2] : acc0[q2 + s], k0 = up ? acc0[q2 + s] : acc0[q2];
+            const double s1 = up ? acc1[q2] : acc1[q2 + s], k1 = up ? acc1[q2 + s] : acc1[q2];
+            acc0[q2] = k0 + __shfl_xor(s0, s);
+            acc1[q2] = k1 + __shfl_xor(s1, s);
+        }
+    }
+    acc0[0] += __shfl_xor(acc0[0], 16);
+    acc1[0] += __shfl_xor(acc1[0], 16);
+    acc0[0] += __shfl_xor(acc0[0], 32);
+    acc1[0] += __shfl_xor(acc1[0], 32);
+    if (lane < 16) {
+        const int64_t r = (int64_t)(bgrp * 4 + bq) * 64 + quarter * 16 + lane;
+        Y0t[r * ld + i] = r < k ? (t0 - 2.0 * acc0[0]) * inv_sqrt_k : 0.0;
+        Y1t[r * ld + i] = r < k ? (t1 - 2.0 * acc1[0]) * inv_sqrt_k : 0.0;
+    }
+}
+
+hipError_t launch_rhs_pair(const double *W0, const double *W1, int64_t ld, int64_t n,
+                           const int32_t *gid, int64_t k, int64_t kpad, uint64_t seed,
+                           double *Y0t, double *Y1t, hipStream_t s) {
+    const uint64_t mseed = splitmix64_mix_host(seed);
+    const int nb = (int)(kpad / 64);
+    const int nbg = (nb + 3) / 4;
+    const int64_t rows = cdiv(n, kNumXcd) * kNumXcd;
+    hipLaunchKernelGGL(k_rhs_pair, dim3((unsigned)(rows * nbg)), dim3(1024), 0, s, W0, W1, ld, n,
+                       gid, k, mseed, 1.0 / sqrt((double)k), nb, Y0t, Y1t);
+    return hipGetLastError();
+}
+
 hipError_t launch_rhs_rows(const double *W, int64_t ld, int64_t n, int64_t row0, int64_t row1,
                            const int32_t *gid, int64_t k, int64_t kpad, uint64_t seed,
                            double *Yt, hipStream_t s) {

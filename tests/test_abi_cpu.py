@@ -108,6 +108,9 @@ def test_calls_reject_a_null_context(L):
     assert L.cdl_ctx_set_solve_depth(None, 2) == 1
     assert L.cdl_ctx_set_select(None, 0) == 1
     assert L.cdl_chain_densify(None, 100, None, 0, None) == 1
+    assert L.cdl_solve_embedding_pair(None, None, None, None, None, None, None, None, None, None,
+                                      None, None, 10, 4, 1, 0, 1e-8, 5, None, None, None, None, 0,
+                                      None, None) == 1
     assert L.cdl_stream_embedding(None, None, 10, 5, 5, 0.0, None, 4, 1, 1e-8, 5, 0, None,
                                   None, None, None, 0, None) == 1
     assert L.cdl_timing_reset(None) == 1

@@ -241,6 +241,38 @@ def test_embedding_matches_oracle(cdl, prec, n, k, perm):
     np.testing.assert_allclose(Zg.sum(axis=0), 0, atol=1e-12 * np.abs(Zg).max() * n)
 
 
+@pytest.mark.parametrize("n,k,perm,precs", [(300, 70, False, ("fp64", "fp32")),
+                                             (257, 64, True, ("bf16", "fp16")),
+                                             (700, 300, True, ("fp32", "fp16"))])
+def test_pair_solve_matches_two_solves_and_oracle(cdl, n, k, perm, precs):
+    # two snapshots on one node set: the right-hand sides of both from one
+    # sweep (shared sign words) give the embeddings of two separate solves
+    rng = np.random.default_rng(n + k)
+    gid = (rng.permutation(9000)[:n] if perm else np.sort(rng.choice(9000, n, replace=False))).astype(np.int32)
+    Xs = [series(n, 24, 11 * n + t) for t in (0, 1)]
+    print("pair solve case n=%d k=%d perm=%s precs=%s" % (n, k, perm, precs), flush=True)
+    gs = [cdl.build_graph(dev(X)) for X in Xs]
+    chs = [cdl.build_chain(g, prec=p, depth=0, depth_max=8) for g, p in zip(gs, precs)]
+    Z0, Z1, i0, i1 = cdl.solve_embedding_pair(gs[0], chs[0], gs[1], chs[1], k, 1234, tol=1e-11,
+                                              max_iter=40, gid=dev(gid))
+    for t, (Zp, info) in enumerate(((Z0, i0), (Z1, i1))):
+        Zs, infs = cdl.solve_embedding(gs[t], chs[t], k, 1234, tol=1e-11, max_iter=40, gid=dev(gid))
+        o = oracle.build_graph(Xs[t])
+        Zo = oracle.solve_embedding(o["W"], oracle.rhs(o["W"], k, 1234, gid))
+        e, d = rel(host(Zp), Zo), rel(host(Zp), host(Zs))
+        print("  snapshot %d: e_Z %.2e, vs single solve %.2e" % (t, e, d))
+        assert info.converged and info.rel_residual <= 1e-11
+        assert e <= 1e-9 and d <= 1e-10
+
+
+def test_pair_solve_rejects_shared_buffers(cdl):
+    X = dev(series(200, 10, 3))
+    g = cdl.build_graph(X)
+    ch = cdl.build_chain(g, prec="fp32", depth=0, depth_max=4)
+    with pytest.raises(cdl.CdlError):
+        cdl.solve_embedding_pair(g, ch, g, ch, 16, 1)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16", "fp16"])
 @pytest.mark.parametrize("n,k,perm", [(300, 70, False), (257, 64, True)])
 def test_pcg_matches_oracle(cdl, prec, n, k, perm):

@@ -64,6 +64,23 @@ def test_stream_matches_oracle(cdl, n, T, k, panel):
     assert e <= 1e-9
 
 
+@pytest.mark.parametrize("perm", [False, True])
+def test_stream_global_ids(cdl, perm):
+    n, T, k = 600, 24, 70
+    X = series(n, T, 5 + perm)
+    rng = np.random.default_rng(n + perm)
+    gid = (rng.permutation(9000)[:n] if perm else np.sort(rng.choice(9000, n, replace=False)))
+    gid = gid.astype(np.int32)
+    g, Z, info = cdl.stream_embedding(dev(X), k, 1234, gid=dev(gid), tol=1e-11, panel_rows=256)
+    o = oracle.build_graph(X)
+    Zo = oracle.solve_embedding(o["W"], oracle.rhs(o["W"], k, 1234, gid))
+    Zg = host(Z)
+    e = rel(Zg, Zo)
+    print("  perm=%s iterations %d e_Z %.2e" % (perm, info.iterations, e))
+    assert info.converged and e <= 1e-9
+    np.testing.assert_allclose(Zg.sum(axis=0), 0, atol=1e-12 * np.abs(Zg).max() * n)
+
+
 def test_stream_given_sigma_and_certified_tolerance(cdl):
     n, T, k = 700, 19, 64
     X = series(n, T, 3)
