@@ -1,6 +1,7 @@
 """The full-size pair (128 x 128 grid, n = 16384, T = 240, k = 256) in the
 launch configuration the benchmark times: FP16 chain levels, adaptive depth
-(at most 6 stored levels), certified stop at 1e-6, top-50.
+(at most 6 stored levels), both right-hand sides from one sweep, certified
+stop at 1e-6, top-50.
 
 The graph stage is compared with the oracle in full.  The oracle cannot solve
 this size within a test, so the solve is checked on sampled rows (the oracle's
@@ -42,12 +43,17 @@ def run(cdl):
     p = gen.make_pair(cfg["G"], cfg["T"], cfg["patches"], cfg["patch_size"])
     seed = gen.grid.PROJ_SEED
     out = {"seed": seed}
+    gs, chs = [], []
     for t, X in ((0, p.X0), (1, p.X1)):
         print("full-size snapshot %d: n=%d T=%d fp16 chain" % (t, *X.shape), flush=True)
         g = cdl.build_graph(dev(X))
-        ch = cdl.build_chain(g, prec="fp16", depth=0, depth_max=DEPTH_MAX)
-        Z, info = cdl.solve_embedding(g, ch, K, seed, tol=TOL, max_iter=30)
-        out[t] = dict(X=X, g=g, ch=ch, Z=host(Z), info=info)
+        gs.append(g)
+        chs.append(cdl.build_chain(g, prec="fp16", depth=0, depth_max=DEPTH_MAX))
+    # both right-hand sides from one sweep, as the benchmark's pair step
+    Z0, Z1, i0, i1 = cdl.solve_embedding_pair(gs[0], chs[0], gs[1], chs[1], K, seed, tol=TOL,
+                                              max_iter=30)
+    for t, X, Z, info in ((0, p.X0, Z0, i0), (1, p.X1, Z1, i1)):
+        out[t] = dict(X=X, g=gs[t], ch=chs[t], Z=host(Z), info=info)
     F, top = cdl.anomaly_scores(dev(out[0]["Z"]), out[0]["g"], dev(out[1]["Z"]), out[1]["g"],
                                 top_k=50)
     out["F"], out["top"] = host(F), host(top)
@@ -87,6 +93,16 @@ def test_solve_sampled_rows(run, graphs, t):
         t, run[t]["ch"].depth, info.iterations, info.rel_residual, rel, info.kappa))
     assert rel <= max(20 * info.rel_residual, 1e-13)
     assert rel * info.kappa <= 10 * abs(TOL)
+
+
+@pytest.mark.parametrize("t", [0, 1])
+def test_pair_solve_equals_single_solve(cdl, run, t):
+    r = run[t]
+    Z, info = cdl.solve_embedding(r["g"], r["ch"], K, run["seed"], tol=TOL, max_iter=30)
+    d = np.linalg.norm(host(Z) - r["Z"]) / np.linalg.norm(r["Z"])
+    print("snapshot %d: paired vs single solve %.2e (certified %.2e / %.2e)" % (
+        t, d, r["info"].certified_error, info.certified_error))
+    assert info.converged and d <= max(r["info"].certified_error, info.certified_error)
 
 
 def test_scores_sampled_rows_and_top50(run, graphs):
