@@ -5,7 +5,10 @@
 //   rhs         Y = B^T W^{1/2} Q^T / sqrt(k) with counter-based SplitMix64
 //               signs, one row of Y per wave (lane = neighbour j), FP64
 //               accumulation of EXEC-masked adds, deterministic butterfly
-//               reduction
+//               reduction; rhs_pair does the same for two snapshots on one
+//               node set, each sign word and lane mask serving both
+//   streamed    the products with W of the streamed solve, one row panel of
+//               W at a time, and the one-level chain's vector steps
 //   residual    R = Y - (deg * X - W X) on FP64 MFMA, per-column partial
 //               sums of R^2 and the tile maximum of |D^{-1/2} R|
 //   col_norms   ||R_r|| (fixed-order sums) and a power-of-two scale for the
