@@ -19,8 +19,15 @@
  *                          (eq. 1) of two snapshots, node scores
  *                          F_i = sum_j omega_ij |c_t(i,j) - c_{t+1}(i,j)| and
  *                          the top-K nodes.
+ *   cdl_solve_embedding_pair - the same for both snapshots of a pair on one
+ *                          node set, their right-hand sides made together.
+ *   cdl_anomaly_edges    - the K largest edge scores of a pair (the CAD edge
+ *                          score of the Background section).
+ *   cdl_chain_densify    - Algorithm 2's dense product of the chain.
  *   cdl_score_sequence   - Algorithm 4 over consecutive pairs of a sequence
  *                          of snapshots with uneven node sets.
+ *   cdl_stream_embedding - graph and embedding of one snapshot without storing
+ *                          any n x n matrix (weights recomputed per sweep).
  *
  * Conventions
  * -----------
