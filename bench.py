@@ -481,16 +481,18 @@ def main():
 
 
 def streamed_section(args, cdl, gen, torch, dev, Xpair, n, T, k, seed, top_ref):
-    """Streamed snapshots: the same pair with no n x n matrix stored (the
-    weights recomputed from the series on every sweep), and optionally a pair
+    """Streamed snapshots: the same pair with no n x n FP64 matrix stored (the
+    weights recomputed from the series on every sweep), with no n x n storage
+    at all or with chain level 0 stored in the mixed type; optionally a pair
     whose weight matrices exceed device memory."""
-    def stream_pair(Xp, wsb, reps):
+    def stream_pair(Xp, wsb, reps, level=None, cbuf=None):
         cdl.timing(reset=True)
         cdl.set_timing(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(reps):
-            gz = [cdl.stream_embedding(x, k, seed, tol=args.tol, max_iter=30, ws=wsb) for x in Xp]
+            gz = [cdl.stream_embedding(x, k, seed, tol=args.tol, max_iter=30, ws=wsb, level=level,
+                                       chain_buf=cbuf) for x in Xp]
             Fz, tz = cdl.anomaly_scores(gz[0][1], gz[0][0], gz[1][1], gz[1][0], top_k=50)
         torch.cuda.synchronize()
         msp = (time.perf_counter() - t0) / reps
@@ -514,32 +516,41 @@ def streamed_section(args, cdl, gen, torch, dev, Xpair, n, T, k, seed, top_ref):
                 "certified_error": max(z[2].certified_error for z in gz),
                 "kernels_ms": kern}, tz
 
+    def both_forms(Xp, nn, reps, warm):
+        out = {}
+        for level in (None, args.mixed):
+            wsb = torch.empty(cdl.stream_workspace_bytes(nn, T, k, 0, level), dtype=torch.uint8,
+                              device=dev)
+            cbuf = None if level is None else torch.empty(
+                cdl.workspace_bytes(nn, 1, 1, 1, level)["chain"], dtype=torch.uint8, device=dev)
+            if warm:
+                stream_pair(Xp, wsb, 1, level, cbuf)
+            r, tz = stream_pair(Xp, wsb, reps, level, cbuf)
+            r["workspace_gib"] = round((wsb.numel() + (0 if cbuf is None else cbuf.numel())) / 2 ** 30, 2)
+            if top_ref is not None and nn == n:
+                r["top50_equal_to_timed_step"] = bool(set(tz.tolist()) == set(top_ref.tolist()))
+            out["no_matrix" if level is None else "stored_%s_level" % level] = r
+            log("streamed pair n=%d (%s): %.1f ms" % (nn, "no n x n storage" if level is None else
+                                                     "stored %s level" % level, r["ms_per_pair"]))
+            del wsb, cbuf
+            torch.cuda.empty_cache()
+        return out
+
     streamed = {"c3_pair": None}
     if not (args.stream_only and args.stream_grid > 0):
-        swsb = torch.empty(cdl.stream_workspace_bytes(n, T, k, 0), dtype=torch.uint8, device=dev)
-        stream_pair(Xpair, swsb, 1)   # warm-up
-        r, tz = stream_pair(Xpair, swsb, args.steps)
-        if top_ref is not None:
-            r["top50_equal_to_timed_step"] = bool(set(tz.tolist()) == set(top_ref.tolist()))
-        streamed["c3_pair"] = r
-        log("streamed C3 pair: %.2f ms" % r["ms_per_pair"])
-        del swsb
+        streamed["c3_pair"] = both_forms(Xpair, n, args.steps, True)
     if args.stream_grid > 0:
         Gs = args.stream_grid
         log("generating the streamed pair G=%d n=%d" % (Gs, Gs * Gs))
         big = gen.make_pair(Gs, T, 4, 8)
         Xbig = [torch.from_numpy(big.X0).to(dev), torch.from_numpy(big.X1).to(dev)]
         del big
-        swsb = torch.empty(cdl.stream_workspace_bytes(Gs * Gs, T, k, 0), dtype=torch.uint8,
-                           device=dev)
-        r, _ = stream_pair(Xbig, swsb, 1)
+        r = both_forms(Xbig, Gs * Gs, 1, False)
         r["workload"] = ("%dx%d grid, n=%d, T=%d, four 8x8 patches, k=%d; the FP64 weight "
                          "matrix of one snapshot would take %.0f GiB" % (
                              Gs, Gs, Gs * Gs, T, k, (Gs * Gs) ** 2 * 8 / 2 ** 30))
-        r["workspace_gib"] = round(swsb.numel() / 2 ** 30, 2)
         streamed["large_pair"] = r
-        log("streamed pair n=%d: %.1f s" % (Gs * Gs, r["ms_per_pair"] / 1e3))
-        del swsb, Xbig
+        del Xbig
     torch.cuda.empty_cache()
     return streamed
 

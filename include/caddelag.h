@@ -392,6 +392,18 @@ cdl_status cdl_solve_embedding_pair(cdl_ctx *ctx, const double *W0, const double
  *   panel_rows            rows of W recomputed per panel (rounded up to a
  *           multiple of 256, at most ld; 0: 32768).  Results do not depend on
  *           it.
+ *   level_prec, chain, chain_bytes, chain_info   level_prec = -1: as above,
+ *           no n x n storage at all (chain and chain_info may be NULL).
+ *           level_prec = a cdl_prec: level 0 of the chain, S~ in that type
+ *           (n^2 x 2 bytes in FP16: 128 GiB at n = 262144, where the FP64 W
+ *           would take 512 GiB), is stored in the caller's chain buffer
+ *           (cdl_workspace_bytes with depth_max = 1) by one more sweep, and
+ *           the solve is cdl_solve_embedding's (solver CDL_RICHARDSON, the
+ *           cost model's depth with deeper levels applied by repetition),
+ *           its FP64 residual's product W X taken by a streamed sweep.  The
+ *           level is exactly symmetric and equals cdl_build_chain's up to the
+ *           rounding of the degrees (summed in another order).  chain_info
+ *           (host, may be NULL) receives the level's description (depth 1).
  *   deg, stats            device outputs as for cdl_build_graph.
  *   Z, info               as for cdl_solve_embedding (depth_used = 1).
  *   ws, ws_bytes          device workspace of cdl_stream_workspace_bytes.
@@ -401,12 +413,13 @@ cdl_status cdl_solve_embedding_pair(cdl_ctx *ctx, const double *W0, const double
  * (non-finite series, degrees or residuals), CDL_E_GRAPH (zero degree),
  * CDL_E_NOCONV (Z holds the last iterate). */
 cdl_status cdl_stream_workspace_bytes(int64_t n, int64_t T, int64_t k, int64_t panel_rows,
-                                      size_t *bytes);
+                                      int level_prec, size_t *bytes);
 cdl_status cdl_stream_embedding(cdl_ctx *ctx, const double *X, int64_t n, int64_t T,
                                 int64_t ldx, double sigma, const int32_t *gid, int64_t k,
                                 uint64_t seed, double tol, int max_iter, int64_t panel_rows,
-                                double *deg, double *stats, double *Z, void *ws,
-                                size_t ws_bytes, cdl_solve_info *info);
+                                int level_prec, void *chain, size_t chain_bytes,
+                                cdl_chain_info *chain_info, double *deg, double *stats,
+                                double *Z, void *ws, size_t ws_bytes, cdl_solve_info *info);
 
 /* ---- scores (Algorithm 4) -------------------------------------------------- */
 

@@ -127,6 +127,7 @@ class Graph:
     deg: torch.Tensor        # (n,) float64
     stats: torch.Tensor      # (4,) float64: vol, sigma, deg_min, deg_max
     n: int
+    chain: Optional["Chain"] = None   # streamed snapshots with a stored level
 
     def host_stats(self):
         s = self.stats.cpu().tolist()
@@ -304,39 +305,55 @@ def solve_embedding_pair(g0: Graph, chain0: Chain, g1: Graph, chain1: Chain, k: 
     return Z[0], Z[1], i0, i1
 
 
-def stream_workspace_bytes(n: int, T: int, k: int, panel_rows: int = 0) -> int:
+def stream_workspace_bytes(n: int, T: int, k: int, panel_rows: int = 0,
+                           level: Optional[str] = None) -> int:
     out = C.c_size_t()
-    _check(_lib().cdl_stream_workspace_bytes(n, T, k, panel_rows, C.byref(out)))
+    _check(_lib().cdl_stream_workspace_bytes(n, T, k, panel_rows,
+                                             -1 if level is None else L.PREC[level], C.byref(out)))
     return out.value
 
 
 def stream_embedding(X: torch.Tensor, k: int, seed: int, sigma: Optional[float] = None,
                      gid: Optional[torch.Tensor] = None, tol: float = 1e-8, max_iter: int = 30,
-                     panel_rows: int = 0, ws: Optional[torch.Tensor] = None,
+                     panel_rows: int = 0, level: Optional[str] = None,
+                     ws: Optional[torch.Tensor] = None, chain_buf: Optional[torch.Tensor] = None,
                      Z: Optional[torch.Tensor] = None, raise_noconv: bool = True):
-    """Graph and embedding of one snapshot with no n x n matrix in memory: the
-    weights are recomputed from X row panel by row panel on every sweep
-    (cdl_stream_embedding).  Returns (Graph with W = None, Z, info); the graph
-    serves anomaly_scores in the unweighted mode."""
+    """Graph and embedding of one snapshot with no n x n FP64 matrix in
+    memory: the weights are recomputed from X row panel by row panel on every
+    sweep (cdl_stream_embedding).  level (e.g. "fp16") stores chain level 0 in
+    that type and solves as solve_embedding does.  Returns (Graph with W =
+    None and, with a level, .chain set; Z; info); the graph serves
+    anomaly_scores in the unweighted mode."""
     if X.dtype != torch.float64 or not X.is_cuda or X.dim() != 2 or X.stride(1) != 1:
         raise ValueError("X must be a CUDA float64 matrix with unit column stride")
     if gid is not None and (gid.dtype != torch.int32 or not gid.is_cuda):
         raise ValueError("gid must be a CUDA int32 vector")
     ctx = context(X.device.index)
     n, T = X.shape
-    need = stream_workspace_bytes(n, T, k, panel_rows)
+    need = stream_workspace_bytes(n, T, k, panel_rows, level)
     if ws is None or ws.numel() < need:
         ws = _ws(need, X.device)
+    chain = None
+    cinfo = L.ChainInfo()
+    if level is not None:
+        cneed = workspace_bytes(n, 1, 1, 1, level)["chain"]
+        if chain_buf is None or chain_buf.numel() < cneed:
+            chain_buf = _ws(cneed, X.device)
+        chain = Chain(buf=chain_buf, info=cinfo, n=n)
     if Z is None:
         Z = torch.empty((n, k), dtype=torch.float64, device=X.device)
     g = Graph(W=None, deg=torch.empty(n, dtype=torch.float64, device=X.device),
-              stats=torch.empty(L.CDL_GRAPH_STATS, dtype=torch.float64, device=X.device), n=n)
+              stats=torch.empty(L.CDL_GRAPH_STATS, dtype=torch.float64, device=X.device), n=n,
+              chain=chain)
     info = L.SolveInfo()
     st = _lib().cdl_stream_embedding(ctx.h, _ptr(X), n, T, X.stride(0),
                                      float(sigma) if sigma else 0.0, _ptr(gid), k,
                                      C.c_uint64(seed), float(tol), max_iter, panel_rows,
-                                     _ptr(g.deg), _ptr(g.stats), _ptr(Z), _ptr(ws), ws.numel(),
-                                     C.byref(info))
+                                     -1 if level is None else L.PREC[level],
+                                     _ptr(chain_buf) if level is not None else None,
+                                     chain_buf.numel() if level is not None else 0,
+                                     C.byref(cinfo), _ptr(g.deg), _ptr(g.stats), _ptr(Z),
+                                     _ptr(ws), ws.numel(), C.byref(info))
     if st != 0 and not (st == 6 and not raise_noconv):
         _check(st, ctx.h)
     return g, Z, info

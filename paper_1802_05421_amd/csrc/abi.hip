@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -233,13 +234,16 @@ EdgeWs plan_edges(Arena &a, int64_t m, int64_t k, int K) {
 }
 
 // Streamed snapshot: the series, one row panel of the distances / weights
-// and the solve's kpad x ld panels; nothing of size n x n.
+// and the solve's kpad x ld panels; nothing of size n x n.  With a stored
+// chain level (level_prec >= 0) the solve's panels are those of the stored
+// path's solve (plan_solve), the level lives in the caller's chain buffer.
 struct StreamWs {
     int *flags;
     SelectState *sel;
     double *sqn, *Xp, *panel;
     double *Yt, *Xt, *Rt, *Ut, *Prod;
-    double *npart, *mpart, *scal, *mean, *dinv, *rdeg, *fro;
+    double *npart, *mpart, *scal, *mean, *dinv, *rdeg, *fro, *fro64;
+    SolveWs sw;
     int64_t prow;   // rows per panel
 };
 int64_t stream_panel_rows(int64_t n, int64_t panel_rows) {
@@ -248,16 +252,29 @@ int64_t stream_panel_rows(int64_t n, int64_t panel_rows) {
     p = (p + 255) / 256 * 256;
     return std::min(p, ld);
 }
-StreamWs plan_stream(Arena &a, int64_t n, int64_t T, int64_t k, int64_t panel_rows) {
+StreamWs plan_stream(Arena &a, int64_t n, int64_t T, int64_t k, int64_t panel_rows,
+                     int level_prec) {
     const int64_t ld = pad_n(n), Tp = pad_t(T), kp = pad_k(k);
     const size_t kpan = (size_t)kp * ld;
     StreamWs w;
+    std::memset(&w, 0, sizeof(w));
     w.prow = stream_panel_rows(n, panel_rows);
     w.flags = a.take<int>(64);
     w.sel = a.take<SelectState>(1);
     w.sqn = a.take<double>(ld);
     w.Xp = a.take<double>((size_t)ld * Tp);
     w.panel = a.take<double>((size_t)w.prow * ld);
+    w.dinv = a.take<double>(ld);
+    w.rdeg = a.take<double>(ld);
+    w.fro = a.take<double>(ld);
+    w.fro64 = a.take<double>(ld);
+    if (level_prec >= 0) {
+        w.sw = plan_solve(a, n, k, level_prec);
+        w.Yt = w.sw.Yt;
+        w.Xt = w.sw.Xt;
+        w.Prod = (double *)w.sw.part;
+        return w;
+    }
     w.Yt = a.take<double>(kpan);
     w.Xt = a.take<double>(kpan);
     w.Rt = a.take<double>(kpan);
@@ -267,9 +284,6 @@ StreamWs plan_stream(Arena &a, int64_t n, int64_t T, int64_t k, int64_t panel_ro
     w.mpart = a.take<double>(residual_tiles(ld, kp));
     w.scal = a.take<double>(kp + 2);
     w.mean = a.take<double>(kp);
-    w.dinv = a.take<double>(ld);
-    w.rdeg = a.take<double>(ld);
-    w.fro = a.take<double>(ld);
     return w;
 }
 
@@ -734,9 +748,23 @@ cdl_status cdl_chain_densify(cdl_ctx *ctx, int64_t n, void *chain, size_t chain_
 
 // ---- embedding -------------------------------------------------------------------
 
+// W V for the residual: fills S partial panels of P (summed by the
+// reduction); the stored matrix's split-K GEMM or a streamed sweep.
+using WProduct = std::function<cdl_status(const double *Vt, double *P, int &S)>;
+
+// The stored matrix's product: split-K FP64 MFMA GEMM.
+static WProduct stored_product(cdl_ctx *ctx, const double *W, int64_t n, int64_t k) {
+    return [ctx, W, n, k](const double *Vt, double *P, int &S) -> cdl_status {
+        const int64_t ld = pad_n(n), kp = pad_k(k);
+        S = residual_splits(ld, kp, n);
+        { Timed t_(ctx, "residual"); HIPCHK(launch_residual_gemm(Vt, W, ld, n, kp, P, ctx->stream)); }
+        return CDL_OK;
+    };
+}
+
 // The solve from the right-hand sides in w.Yt (X = 0 in w.Xt): norms, the
 // refinement iterations and the centred Z.  Syncs once per iteration.
-static cdl_status solve_from_rhs(cdl_ctx *ctx, const double *W, const double *deg,
+static cdl_status solve_from_rhs(cdl_ctx *ctx, const WProduct &wprod, const double *deg,
                                  const double *stats, int64_t n, const ChainBuf &c,
                                  const cdl_chain_info *ci, int64_t k, cdl_solver solver,
                                  double tol, int max_iter, double *Z, const SolveWs &w,
@@ -747,7 +775,7 @@ static cdl_status solve_from_rhs(cdl_ctx *ctx, const double *W, const double *de
     hipStream_t s = ctx->stream;
     const int nparts = residual_parts(ld), ntiles = residual_tiles(ld, kp);
     const int scaled = prec == 3;   // FP16 operands need a power-of-two scale
-    { Timed t_(ctx, "residual_init"); HIPCHK(launch_residual_k(prec, w.Xt, W, w.Yt, deg, c.dm, ld, n, kp, k, 1, (double *)w.part, w.Rt, w.V64, w.Vlo[0], w.npart, w.mpart, s)); }
+    { Timed t_(ctx, "residual_init"); HIPCHK(launch_residual_reduce_k(prec, nullptr, 0, w.Yt, w.Xt, deg, c.dm, ld, n, kp, k, w.Rt, w.V64, w.Vlo[0], w.npart, w.mpart, s)); }
     { Timed t_(ctx, "col_norms"); HIPCHK(launch_col_norms2(w.npart, nparts, kp, w.mpart, ntiles, scaled, w.scal, s)); }
     std::vector<double> ynorm(kp), rnorm(kp);
     double hstats[CDL_GRAPH_STATS];
@@ -805,8 +833,10 @@ static cdl_status solve_from_rhs(cdl_ctx *ctx, const double *W, const double *de
             if ((st = precondition(D, w.Xt)) != CDL_OK) return st;
             ++it;
             if (info && it <= 64) info->depth_used[it - 1] = D;
-            { Timed t_(ctx, "residual"); HIPCHK(launch_residual_k(prec, w.Xt, W, w.Yt, deg, c.dm, ld, n, kp, k, 0, (double *)w.part, w.Rt,
-                                     w.V64, w.Vlo[0], w.npart, w.mpart, s)); }
+            int S = 0;
+            if ((st = wprod(w.Xt, (double *)w.part, S)) != CDL_OK) return st;
+            { Timed t_(ctx, "residual_reduce"); HIPCHK(launch_residual_reduce_k(prec, (double *)w.part, S, w.Yt, w.Xt, deg, c.dm, ld, n, kp, k,
+                                     w.Rt, w.V64, w.Vlo[0], w.npart, w.mpart, s)); }
             { Timed t_(ctx, "col_norms"); HIPCHK(launch_col_norms2(w.npart, nparts, kp, w.mpart, ntiles, scaled, w.scal, s)); }
             if ((st = residual_check()) != CDL_OK) return st;
             if (conv) break;
@@ -826,8 +856,10 @@ static cdl_status solve_from_rhs(cdl_ctx *ctx, const double *W, const double *de
             { Timed t_(ctx, "pcg_vec"); HIPCHK(launch_pcg_scalars(w.dots, ld, kp, 0, first, w.pcg, s)); }
             { Timed t_(ctx, "pcg_vec"); HIPCHK(launch_pcg_dir(w.Zt, w.Pt, beta, ld, kp, first, s)); }
             // q' = -L p
-            { Timed t_(ctx, "residual"); HIPCHK(launch_residual_k(-1, w.Pt, W, nullptr, deg, c.dm, ld, n, kp, k, 0, (double *)w.part, w.Qt,
-                                     w.V64, nullptr, w.npart, w.mpart, s)); }
+            int S = 0;
+            if ((st = wprod(w.Pt, (double *)w.part, S)) != CDL_OK) return st;
+            { Timed t_(ctx, "residual_reduce"); HIPCHK(launch_residual_reduce_k(-1, (double *)w.part, S, nullptr, w.Pt, deg, c.dm, ld, n, kp, k,
+                                     w.Qt, w.V64, nullptr, w.npart, w.mpart, s)); }
             { Timed t_(ctx, "pcg_vec"); HIPCHK(launch_col_dots(w.Pt, w.Qt, nullptr, nullptr, ld, kp, w.dots, s)); }
             { Timed t_(ctx, "pcg_vec"); HIPCHK(launch_pcg_scalars(w.dots, ld, kp, 1, 0, w.pcg, s)); }
             { Timed t_(ctx, "pcg_update"); HIPCHK(launch_pcg_update(prec, w.Pt, w.Qt, alpha, c.dm, ld, kp, w.Xt, w.Rt, w.V64,
@@ -902,7 +934,8 @@ cdl_status cdl_solve_embedding(cdl_ctx *ctx, const double *W, const double *deg,
     { Timed t_(ctx, "fill_zero"); HIPCHK(launch_fill_zero(w.Yt, panel * sizeof(double), s)); }
     { Timed t_(ctx, "fill_zero"); HIPCHK(launch_fill_zero(w.Xt, panel * sizeof(double), s)); }
     { Timed t_(ctx, "rhs"); HIPCHK(launch_rhs(W, ld, n, gid, k, kp, seed, w.Yt, s)); }
-    return solve_from_rhs(ctx, W, deg, stats, n, c, ci, k, solver, tol, max_iter, Z, w, info);
+    return solve_from_rhs(ctx, stored_product(ctx, W, n, k), deg, stats, n, c, ci, k, solver, tol,
+                          max_iter, Z, w, info);
 }
 
 cdl_status cdl_solve_embedding_pair(cdl_ctx *ctx, const double *W0, const double *deg0,
@@ -935,20 +968,22 @@ cdl_status cdl_solve_embedding_pair(cdl_ctx *ctx, const double *W0, const double
     { Timed t_(ctx, "fill_zero"); HIPCHK(launch_fill_zero(w1.Yt, pbytes, s)); }
     { Timed t_(ctx, "fill_zero"); HIPCHK(launch_fill_zero(w1.Xt, pbytes, s)); }
     { Timed t_(ctx, "rhs_pair"); HIPCHK(launch_rhs_pair(W0, W1, ld, n, gid, k, kp, seed, w0.Yt, w1.Yt, s)); }
-    st = solve_from_rhs(ctx, W0, deg0, stats0, n, c0, ci0, k, solver, tol, max_iter, Z0, w0, info0);
+    st = solve_from_rhs(ctx, stored_product(ctx, W0, n, k), deg0, stats0, n, c0, ci0, k, solver,
+                        tol, max_iter, Z0, w0, info0);
     if (st != CDL_OK) return st;
-    return solve_from_rhs(ctx, W1, deg1, stats1, n, c1, ci1, k, solver, tol, max_iter, Z1, w1, info1);
+    return solve_from_rhs(ctx, stored_product(ctx, W1, n, k), deg1, stats1, n, c1, ci1, k, solver,
+                          tol, max_iter, Z1, w1, info1);
 }
 
 // ---- streamed snapshots ---------------------------------------------------------
 
 cdl_status cdl_stream_workspace_bytes(int64_t n, int64_t T, int64_t k, int64_t panel_rows,
-                                      size_t *bytes) {
+                                      int level_prec, size_t *bytes) {
     if (n < 2 || n > (1 << 20) || T < 1 || k < 1 || k > ((int64_t)1 << 20) || panel_rows < 0 ||
-        !bytes)
+        !bytes || level_prec < -1 || level_prec > 3)
         return CDL_E_ARG;
     Arena a(nullptr);
-    plan_stream(a, n, T, k, panel_rows);
+    plan_stream(a, n, T, k, panel_rows, level_prec);
     *bytes = a.off;
     return CDL_OK;
 }
@@ -956,8 +991,9 @@ cdl_status cdl_stream_workspace_bytes(int64_t n, int64_t T, int64_t k, int64_t p
 cdl_status cdl_stream_embedding(cdl_ctx *ctx, const double *X, int64_t n, int64_t T,
                                 int64_t ldx, double sigma, const int32_t *gid, int64_t k,
                                 uint64_t seed, double tol, int max_iter, int64_t panel_rows,
-                                double *deg, double *stats, double *Z, void *ws,
-                                size_t ws_bytes, cdl_solve_info *info) {
+                                int level_prec, void *chain, size_t chain_bytes,
+                                cdl_chain_info *chain_info, double *deg, double *stats,
+                                double *Z, void *ws, size_t ws_bytes, cdl_solve_info *info) {
     if (!ctx) return CDL_E_ARG;
     if (n < 2 || n > (1 << 20)) return fail(ctx, CDL_E_ARG, "n must be in [2, 2^20]");
     if (T < 1 || ldx < T) return fail(ctx, CDL_E_ARG, "need T >= 1 and ldx >= T");
@@ -969,13 +1005,22 @@ cdl_status cdl_stream_embedding(cdl_ctx *ctx, const double *X, int64_t n, int64_
     if (!std::isfinite(sigma) || !std::isfinite(tol)) return fail(ctx, CDL_E_ARG, "sigma and tol must be finite");
     if (max_iter < 1 || max_iter > 64) return fail(ctx, CDL_E_ARG, "max_iter must be in [1, 64]");
     if (panel_rows < 0) return fail(ctx, CDL_E_ARG, "panel_rows must be >= 0");
+    if (level_prec < -1 || level_prec > 3) return fail(ctx, CDL_E_ARG, "bad level type");
+    const bool stored_level = level_prec >= 0;
+    if (stored_level) {
+        if (!chain || !aligned(chain, kAlign)) return fail(ctx, CDL_E_ARG, "a stored level needs an aligned chain buffer");
+        Arena cneed(nullptr);
+        plan_chain(cneed, n, level_prec, 1);
+        if (chain_bytes < cneed.off) return fail(ctx, CDL_E_WORKSPACE, "chain buffer too small");
+    }
     Arena need(nullptr);
-    plan_stream(need, n, T, k, panel_rows);
+    plan_stream(need, n, T, k, panel_rows, level_prec);
     if (ws_bytes < need.off) return fail(ctx, CDL_E_WORKSPACE, "stream workspace too small");
     HIPCHK(hipSetDevice(ctx->device));
     if (info) std::memset(info, 0, sizeof(*info));
+    if (chain_info) std::memset(chain_info, 0, sizeof(*chain_info));
     Arena a(ws);
-    const StreamWs w = plan_stream(a, n, T, k, panel_rows);
+    const StreamWs w = plan_stream(a, n, T, k, panel_rows, level_prec);
     const int64_t ld = pad_n(n), Tp = pad_t(T), kp = pad_k(k), P = w.prow;
     const size_t kbytes = (size_t)kp * ld * sizeof(double);
     hipStream_t s = ctx->stream;
@@ -1017,6 +1062,53 @@ cdl_status cdl_stream_embedding(cdl_ctx *ctx, const double *X, int64_t n, int64_
         { Timed t_(ctx, "rhs"); HIPCHK(launch_rhs_rows(w.panel, ld, n, r0, std::min(r0 + rows, n), gid, k, kp, seed, w.Yt, s)); }
     }
     { Timed t_(ctx, "graph_stats"); HIPCHK(launch_graph_stats(deg, n, stats, s)); }
+    if (stored_level) {
+        // Level 0 of the chain is stored in the level type (the FP64 weights
+        // are not): one more sweep normalises each recomputed panel into it.
+        // The solve is then the stored path's (level applications, repeated
+        // for deeper levels), with the FP64 residual's product W X taken by a
+        // streamed sweep.
+        double hst[CDL_GRAPH_STATS];
+        HIPCHK(hipMemcpyAsync(hst, stats, sizeof(hst), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (double v : hst)
+            if (!std::isfinite(v)) return fail(ctx, CDL_E_NONFINITE, "non-finite weights or degrees");
+        if (!(hst[2] > 0.0)) return fail(ctx, CDL_E_GRAPH, "a node has zero degree");
+        Arena ac(chain);
+        const ChainBuf c = plan_chain(ac, n, level_prec, 1);
+        { Timed t_(ctx, "chain_prep"); HIPCHK(launch_chain_prep(deg, stats, n, ld, 0, c.dmn, c.dm, c.u, s)); }
+        for (int64_t r0 = 0; r0 < n; r0 += P) {
+            const int64_t rows = std::min(P, ld - r0);
+            { Timed t_(ctx, "stream_gram_exp"); HIPCHK(launch_gram_panel(w.Xp, Tp, w.sqn, n, ld, r0, rows, true, w.panel, stats, s)); }
+            { Timed t_(ctx, "stream_normalize"); HIPCHK(launch_normalize_rows(level_prec, w.panel, ld, n, r0, rows, c.dmn, c.u, 0, c.levels,
+                                                w.fro + r0, w.fro64 + r0, s)); }
+        }
+        std::vector<double> f1(n), f2(n);
+        HIPCHK(hipMemcpyAsync(f1.data(), w.fro, n * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(f2.data(), w.fro64, n * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        cdl_chain_info ci;
+        std::memset(&ci, 0, sizeof(ci));
+        ci.prec = (cdl_prec)level_prec;
+        ci.lazy = 0;
+        ci.depth = 1;
+        ci.fro[0] = std::sqrt(host_sum(f1));
+        ci.rho_bound = std::sqrt(host_sum(f2));
+        ci.rho_hat = ci.fro[0];
+        if (chain_info) *chain_info = ci;
+        if (!std::isfinite(ci.fro[0])) return fail(ctx, CDL_E_NONFINITE, "non-finite chain level");
+        const WProduct sweep = [&](const double *Vt, double *Pp, int &S) -> cdl_status {
+            S = 1;
+            for (int64_t r0 = 0; r0 < n; r0 += P) {
+                const int64_t rows = std::min(P, ld - r0);
+                { Timed t_(ctx, "stream_gram_exp"); HIPCHK(launch_gram_panel(w.Xp, Tp, w.sqn, n, ld, r0, rows, true, w.panel, stats, s)); }
+                { Timed t_(ctx, "stream_product"); HIPCHK(launch_panel_product(Vt, w.panel, ld, n, kp, r0, rows, Pp, s)); }
+            }
+            return CDL_OK;
+        };
+        return solve_from_rhs(ctx, sweep, deg, stats, n, c, &ci, k, CDL_RICHARDSON, tol, max_iter,
+                              Z, w.sw, info);
+    }
     { Timed t_(ctx, "stream_prep"); HIPCHK(launch_stream_prep(deg, n, ld, w.dinv, w.rdeg, s)); }
     const int nparts = residual_parts(ld), ntiles = residual_tiles(ld, kp);
     // R = Y (X = 0) and the norms of Y's columns

@@ -133,6 +133,66 @@ hipError_t launch_normalize(int prec, const double *W, int64_t ld, int64_t n,
     return hipGetLastError();
 }
 
+// The same level from a row panel of W (panel row q = node row0 + q, full
+// rows): one workgroup per row, the expression of k_normalize, so the same
+// weights and degrees give the same bits in both triangles.  fro_part[q] and
+// fro64_part[q] get the row's sums of squares (rounded and exact).
+template <typename T>
+__global__ __launch_bounds__(256) void k_normalize_rows(const double *Wp, int64_t ld, int64_t n,
+                                                        int64_t row0, const double *dmn,
+                                                        const double *u, int lazy, double scale,
+                                                        T *S0, double *fro_part,
+                                                        double *fro64_part) {
+    __shared__ double red[4];
+    const int64_t q = blockIdx.x, i = row0 + q;
+    const double *row = Wp + q * ld;
+    T *out = S0 + i * ld;
+    const bool live = i < n;
+    const double di = live ? dmn[i] : 0.0, ui = live ? u[i] : 0.0;
+    double s = 0.0, s64 = 0.0;
+    for (int64_t j0 = threadIdx.x; j0 < ld; j0 += 4 * 256) {
+        double wl[4];   // four loads in flight
+#pragma unroll
+        for (int c = 0; c < 4; ++c) wl[c] = j0 + 256 * c < ld ? row[j0 + 256 * c] : 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int64_t j = j0 + 256 * c;
+            if (j >= ld) break;
+            double v = 0.0;
+            if (live && j < n) {
+                v = wl[c] * (di * dmn[j]);
+                if (lazy) v = 0.5 * ((i == j ? 1.0 : 0.0) + v);
+                v -= ui * u[j];
+            }
+            const T tv = cvtd<T>(v * scale);
+            out[j] = tv;
+            const double back = tod<T>(tv) / scale;
+            s += back * back;
+            s64 += v * v;
+        }
+    }
+    s = block_sum256c(s, red);
+    if (threadIdx.x == 0) fro_part[q] = s;
+    s64 = block_sum256c(s64, red);
+    if (threadIdx.x == 0) fro64_part[q] = s64;
+}
+
+hipError_t launch_normalize_rows(int prec, const double *Wp, int64_t ld, int64_t n, int64_t row0,
+                                 int64_t rows, const double *dmn, const double *u, int lazy,
+                                 void *S0, double *fro_part, double *fro64_part, hipStream_t s) {
+    if (rows <= 0) return hipSuccess;
+    const double sc = level_scale(prec, n);
+    dim3 g((unsigned)rows), b(256);
+    switch (prec) {
+    case 0: hipLaunchKernelGGL(k_normalize_rows<double>, g, b, 0, s, Wp, ld, n, row0, dmn, u, lazy, sc, (double *)S0, fro_part, fro64_part); break;
+    case 1: hipLaunchKernelGGL(k_normalize_rows<float>, g, b, 0, s, Wp, ld, n, row0, dmn, u, lazy, sc, (float *)S0, fro_part, fro64_part); break;
+    case 2: hipLaunchKernelGGL(k_normalize_rows<__bf16>, g, b, 0, s, Wp, ld, n, row0, dmn, u, lazy, sc, (__bf16 *)S0, fro_part, fro64_part); break;
+    case 3: hipLaunchKernelGGL(k_normalize_rows<_Float16>, g, b, 0, s, Wp, ld, n, row0, dmn, u, lazy, sc, (_Float16 *)S0, fro_part, fro64_part); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Symmetric squaring.
 

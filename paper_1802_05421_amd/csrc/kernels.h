@@ -89,6 +89,12 @@ hipError_t launch_normalize(int prec, const double *W, int64_t ld, int64_t n,
                             const double *dmn, const double *u, int lazy, void *S0,
                             double *fro_part, double *fro64_part, hipStream_t s);
 int square_tiles(int prec, int64_t ld);   // number of partial norms written
+// Level 0 from a row panel of W (rows [row0, row0 + rows), full rows): the
+// values of launch_normalize; per-row sums of squares (rounded, exact) into
+// fro_part[q], fro64_part[q].
+hipError_t launch_normalize_rows(int prec, const double *Wp, int64_t ld, int64_t n, int64_t row0,
+                                 int64_t rows, const double *dmn, const double *u, int lazy,
+                                 void *S0, double *fro_part, double *fro64_part, hipStream_t s);
 hipError_t launch_square(int prec, const void *S, void *S2, int64_t ld, int64_t n,
                          double *fro_part, hipStream_t s);
 // C = Q + L + Q L for commuting symmetric Q, L (levels' storage scale).
@@ -146,6 +152,16 @@ hipError_t launch_residual_k(int prec, const double *Xt, const double *W, const 
                              double *V64, void *Vlo, double *npart, double *mpart,
                              hipStream_t s);
 int residual_splits(int64_t ld, int64_t kpad, int64_t n);
+// The two halves of launch_residual_k: the split-K product W X into P
+// (residual_splits partials), and the reduction over S partials (S = 0: none,
+// R = Y - deg X) that forms R, the operand V and the norm partials.
+hipError_t launch_residual_gemm(const double *Xt, const double *W, int64_t ld, int64_t n,
+                                int64_t kpad, double *P, hipStream_t s);
+hipError_t launch_residual_reduce_k(int prec, const double *P, int S, const double *Yt,
+                                    const double *Xt, const double *deg, const double *dm,
+                                    int64_t ld, int64_t n, int64_t kpad, int64_t k, double *Rt,
+                                    double *V64, void *Vlo, double *npart, double *mpart,
+                                    hipStream_t s);
 int residual_parts(int64_t ld);               // column-norm partials per column
 int residual_tiles(int64_t ld, int64_t kpad); // maxima written
 hipError_t launch_col_norms2(const double *npart, int nparts, int64_t kpad, const double *mpart,

@@ -606,6 +606,31 @@ hipError_t launch_stream_update(const double *Ut, const double *Prod, const doub
     return hipGetLastError();
 }
 
+hipError_t launch_residual_gemm(const double *Xt, const double *W, int64_t ld, int64_t n,
+                                int64_t kpad, double *P, hipStream_t s) {
+    switch (res_bm(kpad)) {
+    case 256: return resg_launch<256>(Xt, W, ld, n, kpad, P, s);
+    case 128: return resg_launch<128>(Xt, W, ld, n, kpad, P, s);
+    default: return resg_launch<64>(Xt, W, ld, n, kpad, P, s);
+    }
+}
+
+hipError_t launch_residual_reduce_k(int prec, const double *P, int S, const double *Yt,
+                                    const double *Xt, const double *deg, const double *dm,
+                                    int64_t ld, int64_t n, int64_t kpad, int64_t k, double *Rt,
+                                    double *V64, void *Vlo, double *npart, double *mpart,
+                                    hipStream_t s) {
+    const int skip = S == 0;
+    dim3 grid((unsigned)(ld / 256), (unsigned)kpad), blk(256);
+    switch (prec) {
+    case 0: hipLaunchKernelGGL(k_residual_reduce<double>, grid, blk, 0, s, P, S, Yt, Xt, deg, dm, ld, n, k, kpad, skip, Rt, V64, (double *)Vlo, npart, mpart); break;
+    case 1: hipLaunchKernelGGL(k_residual_reduce<float>, grid, blk, 0, s, P, S, Yt, Xt, deg, dm, ld, n, k, kpad, skip, Rt, V64, (float *)Vlo, npart, mpart); break;
+    case 2: hipLaunchKernelGGL(k_residual_reduce<__bf16>, grid, blk, 0, s, P, S, Yt, Xt, deg, dm, ld, n, k, kpad, skip, Rt, V64, (__bf16 *)Vlo, npart, mpart); break;
+    default: hipLaunchKernelGGL(k_residual_reduce<_Float16>, grid, blk, 0, s, P, S, Yt, Xt, deg, dm, ld, n, k, kpad, skip, Rt, V64, (_Float16 *)nullptr, npart, mpart); break;
+    }
+    return hipGetLastError();
+}
+
 // prec < 0: no fused operand (FP16 chains scale it separately).
 hipError_t launch_residual_k(int prec, const double *Xt, const double *W, const double *Yt,
                              const double *deg, const double *dm, int64_t ld, int64_t n,
@@ -613,23 +638,11 @@ hipError_t launch_residual_k(int prec, const double *Xt, const double *W, const 
                              double *V64, void *Vlo, double *npart, double *mpart,
                              hipStream_t s) {
     if (!skip_gemm) {
-        hipError_t e;
-        switch (res_bm(kpad)) {
-        case 256: e = resg_launch<256>(Xt, W, ld, n, kpad, P, s); break;
-        case 128: e = resg_launch<128>(Xt, W, ld, n, kpad, P, s); break;
-        default: e = resg_launch<64>(Xt, W, ld, n, kpad, P, s); break;
-        }
+        hipError_t e = launch_residual_gemm(Xt, W, ld, n, kpad, P, s);
         if (e != hipSuccess) return e;
     }
-    const int S = residual_splits(ld, kpad, n);
-    dim3 grid((unsigned)(ld / 256), (unsigned)kpad), blk(256);
-    switch (prec) {
-    case 0: hipLaunchKernelGGL(k_residual_reduce<double>, grid, blk, 0, s, P, S, Yt, Xt, deg, dm, ld, n, k, kpad, skip_gemm, Rt, V64, (double *)Vlo, npart, mpart); break;
-    case 1: hipLaunchKernelGGL(k_residual_reduce<float>, grid, blk, 0, s, P, S, Yt, Xt, deg, dm, ld, n, k, kpad, skip_gemm, Rt, V64, (float *)Vlo, npart, mpart); break;
-    case 2: hipLaunchKernelGGL(k_residual_reduce<__bf16>, grid, blk, 0, s, P, S, Yt, Xt, deg, dm, ld, n, k, kpad, skip_gemm, Rt, V64, (__bf16 *)Vlo, npart, mpart); break;
-    default: hipLaunchKernelGGL(k_residual_reduce<_Float16>, grid, blk, 0, s, P, S, Yt, Xt, deg, dm, ld, n, k, kpad, skip_gemm, Rt, V64, (_Float16 *)nullptr, npart, mpart); break;
-    }
-    return hipGetLastError();
+    return launch_residual_reduce_k(prec, P, skip_gemm ? 0 : residual_splits(ld, kpad, n), Yt,
+                                    Xt, deg, dm, ld, n, kpad, k, Rt, V64, Vlo, npart, mpart, s);
 }
 
 int residual_parts(int64_t ld) { return (int)(ld / 256); }

@@ -72,9 +72,9 @@ def test_workspace_sizes_and_validation(L):
 
 
 def test_stream_workspace_grows_linearly_in_n(L):
-    def size(n, T, k, p):
+    def size(n, T, k, p, lev=-1):
         out = C.c_size_t()
-        st = L.cdl_stream_workspace_bytes(n, T, k, p, C.byref(out))
+        st = L.cdl_stream_workspace_bytes(n, T, k, p, lev, C.byref(out))
         return st, out.value
     # n = 2^18 with 8192-row panels: series, one panel and five k-wide panels;
     # the full weight matrix (512 GiB) is never part of it
@@ -88,9 +88,12 @@ def test_stream_workspace_grows_linearly_in_n(L):
     assert size(1000, 10, 4, 10 ** 6)[1] == size(1000, 10, 4, 1024)[1]
     assert size(1000, 10, 4, 0)[1] == size(1000, 10, 4, 1024)[1]
     for bad in [(1, 10, 4, 0), (1000, 0, 4, 0), (1000, 10, 0, 0), (1000, 10, 4, -1),
-                ((1 << 20) + 1, 10, 4, 0)]:
+                ((1 << 20) + 1, 10, 4, 0), (1000, 10, 4, 0, 4), (1000, 10, 4, 0, -2)]:
         assert size(*bad)[0] == 1
-    assert L.cdl_stream_workspace_bytes(1000, 10, 4, 0, None) == 1
+    assert L.cdl_stream_workspace_bytes(1000, 10, 4, 0, -1, None) == 1
+    # with a stored FP16 level: the stored path's solve panels instead
+    st, b16 = size(262144, 240, 256, 8192, 3)
+    assert st == 0 and b16 >= ld * 240 * 8 + 8192 * ld * 8 + 8 * 256 * ld * 8
 
 
 def test_calls_reject_a_null_context(L):
@@ -111,8 +114,8 @@ def test_calls_reject_a_null_context(L):
     assert L.cdl_solve_embedding_pair(None, None, None, None, None, None, None, None, None, None,
                                       None, None, 10, 4, 1, 0, 1e-8, 5, None, None, None, None, 0,
                                       None, None) == 1
-    assert L.cdl_stream_embedding(None, None, 10, 5, 5, 0.0, None, 4, 1, 1e-8, 5, 0, None,
-                                  None, None, None, 0, None) == 1
+    assert L.cdl_stream_embedding(None, None, 10, 5, 5, 0.0, None, 4, 1, 1e-8, 5, 0, -1, None, 0,
+                                  None, None, None, None, None, 0, None) == 1
     assert L.cdl_timing_reset(None) == 1
     assert L.cdl_ctx_destroy(None) == 0
 

@@ -140,6 +140,46 @@ def test_stream_equals_stored_path_on_grid_pair(cdl):
     assert set(host(tops).tolist()) == set(host(top).tolist())
 
 
+@pytest.mark.parametrize("prec,u", [("fp16", 2.0 ** -11), ("bf16", 2.0 ** -8), ("fp32", 2.0 ** -24)])
+def test_stream_stored_level_equals_stored_chain(cdl, prec, u):
+    # the level normalised from the recomputed panels is the stored path's
+    # level 0 up to the degrees' rounding (the two paths sum the rows in other
+    # orders): a few entries at most one unit of the level type apart; the
+    # solves agree to their tolerance
+    cfg = gen.CONFIGS["C2"]
+    X = dev(gen.make_pair(cfg["G"], cfg["T"], cfg["patches"], cfg["patch_size"]).X0)
+    k = 128
+    g = cdl.build_graph(X)
+    ch = cdl.build_chain(g, prec=prec, depth=1, depth_max=1)
+    Z, info = cdl.solve_embedding(g, ch, k, SEED, tol=1e-11, max_iter=30)
+    gs, Zs, infs = cdl.stream_embedding(X, k, SEED, tol=1e-11, panel_rows=1024, level=prec)
+    print("  %s: iterations %d / %d, fro %.15g / %.15g" % (
+        prec, info.iterations, infs.iterations, ch.info.fro[0], gs.chain.info.fro[0]))
+    assert gs.chain.info.depth == 1 and gs.chain.info.prec == ch.info.prec
+    A, B = cdl.level(ch, 0).double(), cdl.level(gs.chain, 0).double()
+    d = A != B
+    print("  %s: %d of %d level entries differ" % (prec, int(d.sum()), d.numel()))
+    assert float(d.double().mean()) <= 1e-6
+    assert bool(((A - B).abs() <= 2 * u * A.abs()).all())
+    assert torch.equal(B, B.T)
+    assert gs.chain.info.fro[0] == pytest.approx(ch.info.fro[0], rel=1e-13)
+    assert gs.chain.info.rho_bound == pytest.approx(ch.info.rho_bound, rel=1e-13)
+    assert infs.converged and infs.rel_residual <= 1e-11
+    assert rel(host(Zs), host(Z)) <= 1e-9
+
+
+@pytest.mark.parametrize("n,T,k,panel", [(513, 40, 70, 256), (1100, 50, 130, 0)])
+def test_stream_stored_level_matches_oracle(cdl, n, T, k, panel):
+    X = series(n, T, 3 * n + T)
+    gs, Z, info = cdl.stream_embedding(dev(X), k, SEED, tol=1e-11, panel_rows=panel, level="fp16")
+    o = oracle.build_graph(X)
+    Zo = oracle.solve_embedding(o["W"], oracle.rhs(o["W"], k, SEED), o["deg"])
+    e = rel(host(Z), Zo)
+    print("  n=%d: iterations %d e_Z %.2e depth used %s" % (
+        n, info.iterations, e, [info.depth_used[i] for i in range(info.iterations)]))
+    assert info.converged and e <= 1e-9
+
+
 def test_stream_rejects_bad_arguments(cdl):
     X = dev(series(100, 5, 1))
     with pytest.raises(cdl.CdlError):

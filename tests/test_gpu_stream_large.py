@@ -3,6 +3,10 @@ T = 240, four 8 x 8 patches, k = 256).  The stored path would need the
 512 GiB FP64 weight matrix; the streamed path holds one 32768-row panel
 (64 GiB) and recomputes the weights from the series on every sweep.
 
+Snapshot 0 is solved a second time with chain level 0 stored in FP16
+(128 GiB) and must agree with the one-level streamed solve within the sum of
+their certified errors.
+
 The oracle cannot take the median of the 3.4e10 pair distances, so the
 bandwidth is checked (a) bit for bit against the stored path at n = 65536,
 where the stored matrix still fits, and (b) at n = 262144 as a property on
@@ -73,6 +77,16 @@ def run(cdl):
         out[t] = dict(X=X, g=g, Z=Z, info=info, stats=s)
     del ws
     torch.cuda.empty_cache()
+    # snapshot 0 again with chain level 0 stored in FP16 (128 GiB; the FP64
+    # weights would need 512 GiB)
+    print("streamed snapshot 0 with a stored FP16 level", flush=True)
+    g16, Z16, i16 = cdl.stream_embedding(dev(pair.X0), K, SEED, tol=1e-9, max_iter=12,
+                                         panel_rows=32768, level="fp16")
+    print("  fro %.6f iterations %d residual %.2e certified %.2e" % (
+        g16.chain.info.fro[0], i16.iterations, i16.rel_residual, i16.certified_error), flush=True)
+    out["level"] = dict(Z=host(Z16), info=i16, stats=g16.host_stats())
+    del g16, Z16
+    torch.cuda.empty_cache()
     F, top = cdl.anomaly_scores(out[0]["Z"], gs[0], out[1]["Z"], gs[1], top_k=50)
     out["F"], out["top"] = host(F), host(top)
     for t in (0, 1):
@@ -109,6 +123,15 @@ def test_graph_and_solve_sampled_rows(run, t):
     assert r["info"].converged
     assert e <= max(20 * r["info"].rel_residual, 1e-12)
     assert np.abs(Z.sum(axis=0)).max() <= 1e-10 * np.abs(Z).max() * np.sqrt(n)
+
+
+def test_stored_level_solve_agrees(run):
+    a, b = run[0], run["level"]
+    assert b["stats"]["sigma"] == a["stats"]["sigma"]
+    assert b["info"].converged
+    d = np.linalg.norm(b["Z"] - a["Zh"]) / np.linalg.norm(a["Zh"])
+    print("  stored-level vs streamed solve: %.2e" % d)
+    assert d <= a["info"].certified_error + b["info"].certified_error
 
 
 def test_scores_sampled_rows_and_top50(run):
