@@ -18,6 +18,12 @@
 //                into one partial per (tile column, node)
 //   degree       deg = sum of the partials in tile order
 //   graph_stats  vol = sum deg, min and max degree (fixed-order reductions)
+//
+// Streamed snapshots (no n x n matrix stored) use the same tiles on row
+// panels: gram_dist over the panel's upper tiles (median sweeps) or all of
+// its tiles, optionally with the weights formed in the epilogue; select by
+// radix digits from the top bit, one sweep over the upper panels per digit;
+// exp_rows for the weights, degrees and Frobenius rows of a panel.
 #include "common.h"
 #include "gemm.h"
 #include "kernels.h"
