@@ -172,13 +172,15 @@ const char *cdl_version(void);
  * 0 restores autotuning.  CDL_E_ARG outside [0, 16]. */
 cdl_status cdl_ctx_set_solve_depth(cdl_ctx *ctx, int depth);
 
-/* Median-rule bandwidth selection of later cdl_build_graph calls on this
- * context.  0 (default): a sorted sample of 4096 pair distances brackets the
- * target rank, one pass over the matrix counts the keys below the bracket and
+/* Median-rule bandwidth selection of later cdl_build_graph and
+ * cdl_stream_embedding calls on this context.  0 (default): a sorted sample
+ * of pair distances (4096; 16384 computed from the series when streamed)
+ * brackets the target rank, one pass over the matrix (streamed: one sweep
+ * over the recomputed upper panels) counts the keys below the bracket and
  * collects those inside, and the radix passes run over the collected keys
- * (over the matrix when the rank falls outside the bracket).  1: radix passes
- * over the matrix only.  Both are exact and give the same sigma.  CDL_E_ARG
- * for other values. */
+ * (over the matrix, or one sweep per 12-bit digit, when the rank falls
+ * outside the bracket).  1: radix passes over the matrix (digit sweeps) only.
+ * Both are exact and give the same sigma.  CDL_E_ARG for other values. */
 cdl_status cdl_ctx_set_select(cdl_ctx *ctx, int mode);
 
 /* ---- per-kernel timing ------------------------------------------------- */
@@ -379,8 +381,10 @@ cdl_status cdl_solve_embedding_pair(cdl_ctx *ctx, const double *W0, const double
  * the complexity section's recomputation/communication trade made on one
  * device, where memory capacity rather than arithmetic limits n.
  *   X, n, T, ldx, sigma   as for cdl_build_graph (sigma <= 0: the exact
- *           lower median rule, one sweep over the upper row panels per
- *           12-bit digit of the key).
+ *           lower median rule: one sweep over the upper row panels gathers
+ *           the keys inside a sampled bracket (about 2.3 % of them, into the
+ *           workspace), or, when the bracket misses, one sweep per 12-bit
+ *           digit of the key; see cdl_ctx_set_select).
  *   gid, k, seed          as for cdl_solve_embedding (k >= 1).
  *   tol, max_iter         as for cdl_solve_embedding.  The preconditioner is
  *           the chain of depth 1, P1 = D^{-1/2} (I + S) D^{-1/2} (Algorithm 2

@@ -240,6 +240,7 @@ EdgeWs plan_edges(Arena &a, int64_t m, int64_t k, int K) {
 struct StreamWs {
     int *flags;
     SelectState *sel;
+    unsigned long long *selbuf;   // keys inside the sampled bracket
     double *sqn, *Xp, *panel;
     double *Yt, *Xt, *Rt, *Ut, *Prod;
     double *npart, *mpart, *scal, *mean, *dinv, *rdeg, *fro, *fro64;
@@ -261,6 +262,7 @@ StreamWs plan_stream(Arena &a, int64_t n, int64_t T, int64_t k, int64_t panel_ro
     w.prow = stream_panel_rows(n, panel_rows);
     w.flags = a.take<int>(64);
     w.sel = a.take<SelectState>(1);
+    w.selbuf = a.take<unsigned long long>((size_t)select_stream_keys(n));
     w.sqn = a.take<double>(ld);
     w.Xp = a.take<double>((size_t)ld * Tp);
     w.panel = a.take<double>((size_t)w.prow * ld);
@@ -1032,13 +1034,36 @@ cdl_status cdl_stream_embedding(cdl_ctx *ctx, const double *X, int64_t n, int64_
     HIPCHK(hipStreamSynchronize(s));
     if (hflag) return fail(ctx, CDL_E_NONFINITE, "non-finite node series");
 
-    // Bandwidth: exact lower median of the upper-triangle distances, one
-    // 12-bit digit per sweep over the recomputed upper row panels.
+    // Bandwidth: exact lower median of the upper-triangle distances.  One
+    // sweep over the recomputed upper row panels counts the keys below a
+    // sampled bracket and gathers those inside; the radix passes then run over
+    // the gathered keys.  If the bracket misses the rank (or the buffer
+    // overflows), one 12-bit digit per sweep from the top bit instead.
     if (sigma > 0.0) {
         { Timed t_(ctx, "set_sigma"); HIPCHK(launch_set_sigma(sigma, stats, s)); }
     } else {
+        const int64_t cap = select_stream_keys(n);
         { Timed t_(ctx, "stream_select"); HIPCHK(launch_select_start_top(w.sel, n, s)); }
-        int mode = 0;
+        int src = 0, mode = 0;
+        if (ctx->select_mode == 0) {   // 1: the digit sweeps only (cdl_ctx_set_select)
+            { Timed t_(ctx, "stream_select"); HIPCHK(launch_select_sample_x(w.Xp, Tp, w.sqn, n, w.sel, s)); }
+            for (int64_t r0 = 0; r0 < n; r0 += P) {
+                const int64_t rows = std::min(P, ld - r0);
+                { Timed t_(ctx, "stream_gram_upper"); HIPCHK(launch_gram_panel(w.Xp, Tp, w.sqn, n, ld, r0, rows, false, w.panel, nullptr, s)); }
+                { Timed t_(ctx, "stream_select"); HIPCHK(launch_select_bracket_panel(w.panel, ld, n, r0, std::min(r0 + rows, n), w.sel, w.selbuf, cap, s)); }
+            }
+            { Timed t_(ctx, "stream_select"); HIPCHK(launch_select_check(w.sel, cap, stats, s)); }
+            HIPCHK(hipMemcpyAsync(&src, &w.sel->src, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(&mode, &w.sel->mode, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+        }
+        if (src == 1 && mode != 2) {
+            // at most 6 digit passes resolve 64 bits; the collect pass is one more
+            for (int p = 0; p < 7; ++p)
+                { Timed t_(ctx, "stream_select"); HIPCHK(launch_select_buffer_pass(w.sel, w.selbuf, cap, stats, s)); }
+            HIPCHK(hipMemcpyAsync(&mode, &w.sel->mode, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+        }
         for (int digit = 0; digit < 7 && mode != 2; ++digit) {
             for (int64_t r0 = 0; r0 < n; r0 += P) {
                 const int64_t rows = std::min(P, ld - r0);

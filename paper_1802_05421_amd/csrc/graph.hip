@@ -328,7 +328,10 @@ __global__ __launch_bounds__(1024) void k_select_sample(const double *D2, int64_
 // behind one global atomic at the end; a workgroup holds about
 // N / 2048 * 2 kSelMargin / kSelSample ~ 3000 bracket keys for n = 16384, and
 // keys past the stage's end take a global slot each.
+// Rows [row0, row1): row i at D2 + (i - row0) ld (a row panel, or the whole
+// matrix with row0 = 0, row1 = n).
 __global__ __launch_bounds__(256) void k_select_bracket(const double *D2, int64_t ld, int64_t n,
+                                                        int64_t row0, int64_t row1,
                                                         SelectState *st, unsigned long long *buf,
                                                         int64_t cap) {
     constexpr unsigned int kStage = 4096;
@@ -341,8 +344,8 @@ __global__ __launch_bounds__(256) void k_select_bracket(const double *D2, int64_
     if (t == 0) scnt = 0;
     __syncthreads();
     unsigned long long below = 0;
-    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
-        const unsigned long long *row = (const unsigned long long *)(D2 + i * ld);
+    for (int64_t i = row0 + blockIdx.x; i < row1; i += gridDim.x) {
+        const unsigned long long *row = (const unsigned long long *)(D2 + (i - row0) * ld);
         for (int64_t j0 = i + 1 + t; j0 < n; j0 += 8 * 256) {
             unsigned long long key[8];   // eight independent loads in flight
 #pragma unroll
@@ -375,6 +378,73 @@ __global__ __launch_bounds__(256) void k_select_bracket(const double *D2, int64_
         for (unsigned int q = t; q < c; q += 256)
             if (base + q < (unsigned long long)cap) buf[base + q] = sb[q];
     }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) below += __shfl_xor(below, o);
+    if ((t & 63) == 0) spart[t >> 6] = below;
+    __syncthreads();
+    if (t == 0) {
+        const unsigned long long b = spart[0] + spart[1] + spart[2] + spart[3];
+        if (b) atomicAdd(&st->below, b);
+    }
+}
+
+// The bracket pass for very many keys (streamed panels: billions of keys,
+// tens of thousands inside the bracket per workgroup): the workgroup's rows
+// go in rounds of 2048 keys with a barrier after each, and whenever the LDS
+// stage holds 2048 or more keys it is copied out behind one global atomic,
+// so the global counter sees one atomic per ~2048 keys instead of one each.
+__global__ __launch_bounds__(256) void k_select_bracket_flush(const double *D2, int64_t ld,
+                                                              int64_t n, int64_t row0,
+                                                              int64_t row1, SelectState *st,
+                                                              unsigned long long *buf,
+                                                              int64_t cap) {
+    constexpr unsigned int kStage = 4096, kRound = 8 * 256;
+    __shared__ unsigned long long sb[kStage];
+    __shared__ unsigned int scnt;
+    __shared__ unsigned long long sbase, spart[4];
+    if (st->mode == 2) return;
+    const unsigned long long lo = st->lo, hi = st->hi;
+    const int t = threadIdx.x;
+    if (t == 0) scnt = 0;
+    __syncthreads();
+    unsigned long long below = 0;
+    auto flush = [&]() {   // every thread, after a barrier
+        const unsigned int c = scnt;
+        if (t == 0 && c > 0) sbase = atomicAdd(&st->nbuf, (unsigned long long)c);
+        __syncthreads();
+        const unsigned long long base = sbase;
+        for (unsigned int q = t; q < c; q += 256)
+            if (base + q < (unsigned long long)cap) buf[base + q] = sb[q];
+        __syncthreads();
+        if (t == 0) scnt = 0;
+        __syncthreads();
+    };
+    for (int64_t i = row0 + blockIdx.x; i < row1; i += gridDim.x) {
+        const unsigned long long *row = (const unsigned long long *)(D2 + (i - row0) * ld);
+        for (int64_t jb = i + 1; jb < n; jb += kRound) {   // the same trip count in every thread
+            unsigned long long key[8];   // eight independent loads in flight
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t j = jb + t + 256 * u;
+                key[u] = j < n ? row[j] : ~0ull;   // ~0: above every bracket
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (key[u] < lo) {
+                    ++below;
+                } else if (key[u] <= hi && key[u] != ~0ull) {
+                    const unsigned int q = atomicAdd(&scnt, 1u);   // < kStage: at most kRound per round
+                    sb[q] = key[u];
+                }
+            }
+            __syncthreads();
+            const unsigned int c = scnt;
+            __syncthreads();   // read by every thread before the next round appends
+            if (c >= kStage - kRound) flush();
+        }
+    }
+    __syncthreads();
+    flush();
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) below += __shfl_xor(below, o);
     if ((t & 63) == 0) spart[t >> 6] = below;
@@ -599,7 +669,8 @@ hipError_t launch_select_median(const double *D2, int64_t ld, int64_t n, SelectS
     const double N = (double)n * (double)(n - 1) / 2.0;
     if (bracket && N * 2.0 * kSelMargin / kSelSample <= 0.8 * (double)cap) {
         hipLaunchKernelGGL(k_select_sample, dim3(1), dim3(1024), kSelSample * 8, s, D2, ld, n, st);
-        hipLaunchKernelGGL(k_select_bracket, dim3(grid), dim3(256), 0, s, D2, ld, n, st, buf, cap);
+        hipLaunchKernelGGL(k_select_bracket, dim3(grid), dim3(256), 0, s, D2, ld, n, (int64_t)0, n,
+                           st, buf, cap);
         hipLaunchKernelGGL(k_select_check, dim3(1), dim3(64), 0, s, st, cap, stats);
     }
     // at most 6 digit passes resolve 64 bits; the collect pass is one more
@@ -644,6 +715,101 @@ hipError_t launch_select_panel(const double *D2p, int64_t ld, int64_t n, int64_t
 }
 
 hipError_t launch_select_pick(SelectState *st, double *stats, hipStream_t s) {
+    hipLaunchKernelGGL(k_select_pick, dim3(1), dim3(1024), 0, s, st, stats);
+    return hipGetLastError();
+}
+
+// The streamed bracket: kStreamSample distances of pseudo-random pairs
+// computed directly from the padded series (sq_a + sq_b - 2 x_a.x_b in
+// sequential FP64, an estimate of the quantile only: the bracket is checked
+// against exact counts), sorted in LDS, bracket of kStreamMargin sample ranks
+// on each side of the target; then one sweep over the upper panels counts the
+// keys below the bracket and gathers those inside it, and the radix passes run
+// over the gathered keys.  The larger sample keeps the bracket to about 2.3 %
+// of the keys.
+constexpr int kStreamSample = 16384;
+constexpr int kStreamMargin = 192;   // 3 sqrt(kStreamSample / 4)
+
+int64_t select_stream_keys(int64_t n) {
+    const int64_t N = n * (n - 1) / 2;
+    return N / 100 * 3 + 65536;
+}
+
+__global__ __launch_bounds__(1024) void k_select_sample_x(const double *Xp, int64_t Tp,
+                                                          const double *sqn, int64_t n,
+                                                          SelectState *st) {
+    extern __shared__ unsigned long long sk[];
+    const int t = threadIdx.x;
+    for (int u = 0; u < kStreamSample / 1024; ++u) {
+        const unsigned long long h = sel_mix(0x5851f42d4c957f2dull + (unsigned long long)(t + 1024 * u));
+        int64_t i = (int64_t)((h & 0xffffffffull) % (unsigned long long)n);
+        int64_t j = (int64_t)((h >> 32) % (unsigned long long)(n - 1));
+        if (j >= i) ++j;   // j != i
+        const double *xa = Xp + i * Tp, *xb = Xp + j * Tp;
+        double dot = 0.0;
+        for (int64_t q = 0; q < Tp; ++q) dot += xa[q] * xb[q];
+        double d = sqn[i] + sqn[j] - 2.0 * dot;
+        d = d < 0.0 ? 0.0 : d;
+        sk[t + 1024 * u] = (unsigned long long)__double_as_longlong(d);
+    }
+    __syncthreads();
+    for (int size = 2; size <= kStreamSample; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int q = t; q < kStreamSample / 2; q += 1024) {
+                const int lo = 2 * q - (q & (stride - 1)), hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const unsigned long long a = sk[lo], b = sk[hi];
+                if ((a > b) == up) { sk[lo] = b; sk[hi] = a; }
+            }
+            __syncthreads();
+        }
+    if (t == 0) {
+        const unsigned long long N = (unsigned long long)n * (unsigned long long)(n - 1) / 2ull;
+        const double rho = (double)((N - 1ull) / 2ull) / (double)N;
+        const int q = (int)(rho * kStreamSample);
+        st->lo = q - kStreamMargin <= 0 ? 0ull : sk[q - kStreamMargin];
+        st->hi = q + kStreamMargin >= kStreamSample - 1 ? ~0ull : sk[q + kStreamMargin];
+        st->below = 0;
+        st->nbuf = 0;
+    }
+}
+
+hipError_t launch_select_sample_x(const double *Xp, int64_t Tp, const double *sqn, int64_t n,
+                                  SelectState *st, hipStream_t s) {
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_select_sample_x,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           kStreamSample * 8);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL(k_select_sample_x, dim3(1), dim3(1024), kStreamSample * 8, s, Xp, Tp, sqn,
+                       n, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_bracket_panel(const double *D2p, int64_t ld, int64_t n, int64_t row0,
+                                       int64_t row1, SelectState *st, unsigned long long *buf,
+                                       int64_t cap, hipStream_t s) {
+    if (row1 <= row0) return hipSuccess;
+    const int64_t rows = row1 - row0;
+    const int grid = (int)(rows < 2048 ? rows : 2048);
+    hipLaunchKernelGGL(k_select_bracket_flush, dim3(grid), dim3(256), 0, s, D2p, ld, n, row0, row1,
+                       st, buf, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_check(SelectState *st, int64_t cap, double *stats, hipStream_t s) {
+    hipLaunchKernelGGL(k_select_check, dim3(1), dim3(64), 0, s, st, cap, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_buffer_pass(SelectState *st, const unsigned long long *buf, int64_t cap,
+                                     double *stats, hipStream_t s) {
+    const int grid = (int)(cap / 2048 + 1 < 2048 ? cap / 2048 + 1 : 2048);
+    hipLaunchKernelGGL(k_select_pass, dim3(grid), dim3(256), 0, s, (const double *)nullptr,
+                       (int64_t)0, (int64_t)0, (int64_t)0, (int64_t)0, st, buf);
     hipLaunchKernelGGL(k_select_pick, dim3(1), dim3(1024), 0, s, st, stats);
     return hipGetLastError();
 }

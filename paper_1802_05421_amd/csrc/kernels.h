@@ -56,6 +56,21 @@ hipError_t launch_select_start_top(SelectState *st, int64_t n, hipStream_t s);
 hipError_t launch_select_panel(const double *D2p, int64_t ld, int64_t n, int64_t row0,
                                int64_t row1, SelectState *st, hipStream_t s);
 hipError_t launch_select_pick(SelectState *st, double *stats, hipStream_t s);
+// Streamed bracket: a sample of distances computed from the series brackets
+// the median rank; one sweep of launch_select_bracket_panel over the upper
+// panels counts keys below the bracket and gathers those inside into buf (at
+// most cap = select_stream_keys(n)); launch_select_check moves the radix to
+// the buffer (st->src = 1) when the rank lies inside and nothing overflowed;
+// then launch_select_buffer_pass (one radix pass and pick) until st->mode = 2.
+int64_t select_stream_keys(int64_t n);
+hipError_t launch_select_sample_x(const double *Xp, int64_t Tp, const double *sqn, int64_t n,
+                                  SelectState *st, hipStream_t s);
+hipError_t launch_select_bracket_panel(const double *D2p, int64_t ld, int64_t n, int64_t row0,
+                                       int64_t row1, SelectState *st, unsigned long long *buf,
+                                       int64_t cap, hipStream_t s);
+hipError_t launch_select_check(SelectState *st, int64_t cap, double *stats, hipStream_t s);
+hipError_t launch_select_buffer_pass(SelectState *st, const unsigned long long *buf, int64_t cap,
+                                     double *stats, hipStream_t s);
 // Weights of a row panel in place from its squared distances (bit-identical
 // to the stored matrix); optional row sums into deg[row0 + q] and, with
 // dinv = D^{-1/2}, per-row squared Frobenius norms of S into fro[q].

@@ -98,6 +98,22 @@ def test_stream_given_sigma_and_certified_tolerance(cdl):
     assert e <= info.certified_error
 
 
+def test_stream_median_bracket_and_digit_sweeps_agree(cdl):
+    # the sampled bracket (default) and the digit sweeps from the top bit
+    # (select mode 1) are both exact: the same bandwidth bits
+    X = dev(series(2100, 33, 21))
+    try:
+        cdl.set_select(1)
+        g1, _, _ = cdl.stream_embedding(X, 8, SEED, tol=1e-6, panel_rows=512)
+    finally:
+        cdl.set_select(0)
+    g0, _, _ = cdl.stream_embedding(X, 8, SEED, tol=1e-6, panel_rows=512)
+    gs = cdl.build_graph(X)
+    print("  sigma %.17g / %.17g / %.17g" % (g0.host_stats()["sigma"], g1.host_stats()["sigma"],
+                                            gs.host_stats()["sigma"]))
+    assert g0.host_stats()["sigma"] == g1.host_stats()["sigma"] == gs.host_stats()["sigma"]
+
+
 def test_panel_size_does_not_change_results(cdl):
     n, T, k = 1300, 61, 64
     X = dev(series(n, T, 11))
