@@ -265,6 +265,20 @@ def test_pair_solve_matches_two_solves_and_oracle(cdl, n, k, perm, precs):
         assert e <= 1e-9 and d <= 1e-10
 
 
+@pytest.mark.parametrize("n,k", [(2, 1), (3, 1), (5, 65)])
+def test_pair_solve_tiny(cdl, n, k):
+    Xs = [series(n, 3, 7 * n + t) for t in (0, 1)]
+    gs = [cdl.build_graph(dev(X)) for X in Xs]
+    # lazy levels: two nodes make a bipartite graph
+    chs = [cdl.build_chain(g, prec="fp64", depth=0, depth_max=4, lazy=True) for g in gs]
+    Z0, Z1, i0, i1 = cdl.solve_embedding_pair(gs[0], chs[0], gs[1], chs[1], k, 3, tol=1e-11,
+                                              max_iter=40)
+    for t, Z in ((0, Z0), (1, Z1)):
+        o = oracle.build_graph(Xs[t])
+        Zo = oracle.solve_embedding(o["W"], oracle.rhs(o["W"], k, 3))
+        np.testing.assert_allclose(host(Z), Zo, rtol=0, atol=1e-9 * np.abs(Zo).max() + 1e-300)
+
+
 def test_pair_solve_rejects_shared_buffers(cdl):
     X = dev(series(200, 10, 3))
     g = cdl.build_graph(X)

@@ -196,6 +196,22 @@ def test_stream_stored_level_matches_oracle(cdl, n, T, k, panel):
     assert info.converged and e <= 1e-9
 
 
+@pytest.mark.parametrize("n,T,k", [(3, 1, 1), (4, 6, 1), (5, 3, 65)])
+def test_stream_tiny_snapshots(cdl, n, T, k):
+    # the smallest graphs the one-level chain converges on (two nodes form a
+    # bipartite graph, eigenvalue -1 of S: the stored path's lazy chain is
+    # the tool for that); rho(S~) = 0.79, 0.46, 0.60 here, so the residual
+    # contracts by rho^2 per iteration; ragged k
+    X = series(n, T, 100 + n)
+    g, Z, info = cdl.stream_embedding(dev(X), k, SEED, tol=1e-10, max_iter=64)
+    o = oracle.build_graph(X)
+    assert g.host_stats()["sigma"] == pytest.approx(o["sigma"], rel=1e-12)
+    np.testing.assert_allclose(host(g.deg), o["deg"], rtol=1e-12)
+    Zo = oracle.solve_embedding(o["W"], oracle.rhs(o["W"], k, SEED), o["deg"])
+    assert info.converged
+    np.testing.assert_allclose(host(Z), Zo, rtol=0, atol=1e-8 * np.abs(Zo).max() + 1e-300)
+
+
 def test_stream_rejects_bad_arguments(cdl):
     X = dev(series(100, 5, 1))
     with pytest.raises(cdl.CdlError):
