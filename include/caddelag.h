@@ -191,6 +191,12 @@ cdl_status cdl_ctx_set_select(cdl_ctx *ctx, int mode);
  * ("gram_dist", "select_median", "exp_degree", "normalize", "square",
  * "apply", "rhs", "residual", "score", "topk", ...). */
 cdl_status cdl_ctx_set_timing(cdl_ctx *ctx, int enable);
+/* Restricts the timing to the named kernels: `names` is a comma-separated
+ * list of the names above ("rhs_pair,residual"; spaces ignored), copied;
+ * NULL or "" times every kernel again.  Each timed launch adds two event
+ * records to the stream, so timing only the kernel of interest keeps the
+ * others' launches back to back.  CDL_E_ARG for a null context only. */
+cdl_status cdl_ctx_set_timing_only(cdl_ctx *ctx, const char *names);
 /* Syncs.  Entry idx (0-based, in first-seen order) of the totals: kernel
  * name (valid until the next reset), launches and summed milliseconds.
  * CDL_E_ARG past the last entry. */

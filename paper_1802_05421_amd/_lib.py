@@ -81,6 +81,7 @@ def load():
         "cdl_last_error": (C.c_char_p, [P]),
         "cdl_version": (C.c_char_p, []),
         "cdl_ctx_set_timing": (I, [P, I]),
+        "cdl_ctx_set_timing_only": (I, [P, C.c_char_p]),
         "cdl_ctx_set_solve_depth": (I, [P, I]),
         "cdl_ctx_set_select": (I, [P, I]),
         "cdl_timing_read": (I, [P, C.c_int32, C.POINTER(C.c_char_p), C.POINTER(i64),

@@ -72,9 +72,12 @@ def set_select(mode: int, device: int = 0):
     _check(_lib().cdl_ctx_set_select(ctx.h, int(mode)), ctx.h)
 
 
-def set_timing(enable: bool, device: int = 0):
-    """Per-kernel HIP-event timing on the context's stream (see include/caddelag.h)."""
+def set_timing(enable: bool, device: int = 0, only=None):
+    """Per-kernel HIP-event timing on the context's stream (see include/caddelag.h);
+    `only`: kernel names to time (None: every kernel)."""
     ctx = context(device)
+    names = None if only is None else ",".join(only).encode()
+    _check(_lib().cdl_ctx_set_timing_only(ctx.h, names), ctx.h)
     _check(_lib().cdl_ctx_set_timing(ctx.h, int(enable)), ctx.h)
 
 

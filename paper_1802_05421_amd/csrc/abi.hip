@@ -27,6 +27,7 @@ struct cdl_ctx {
     // kernel launch, resolved when the totals are read.
     int solve_depth = 0;   // > 0: total chain depth used by every solve iteration
     bool timing = false;
+    std::vector<std::string> timing_only;   // empty: every scope is timed
     std::vector<cdl_timer_rec> pending;
     std::vector<hipEvent_t> pool;
     std::map<std::string, std::pair<int64_t, double>> totals;
@@ -52,13 +53,21 @@ hipEvent_t take_event(cdl_ctx *c) {
     return e;
 }
 
+bool timing_selected(const cdl_ctx *c, const char *nm) {
+    if (c->timing_only.empty()) return true;
+    for (const auto &s : c->timing_only)
+        if (s == nm) return true;
+    return false;
+}
+
 // Brackets one kernel launch (or a fixed group of launches) with events.
 struct Timed {
     cdl_ctx *c;
     const char *name;
     hipEvent_t a = nullptr;
     Timed(cdl_ctx *ctx, const char *nm) : c(ctx), name(nm) {
-        if (c->timing && (a = take_event(c)) && hipEventRecord(a, c->stream) != hipSuccess) {
+        if (c->timing && timing_selected(c, nm) && (a = take_event(c)) &&
+            hipEventRecord(a, c->stream) != hipSuccess) {
             c->pool.push_back(a);
             a = nullptr;
         }
@@ -511,6 +520,23 @@ cdl_status cdl_ctx_set_select(cdl_ctx *ctx, int mode) {
 cdl_status cdl_ctx_set_timing(cdl_ctx *ctx, int enable) {
     if (!ctx) return CDL_E_ARG;
     ctx->timing = enable != 0;
+    return CDL_OK;
+}
+
+cdl_status cdl_ctx_set_timing_only(cdl_ctx *ctx, const char *names) {
+    if (!ctx) return CDL_E_ARG;
+    ctx->timing_only.clear();
+    if (!names) return CDL_OK;
+    std::string cur;
+    for (const char *p = names;; ++p) {
+        if (*p == ',' || *p == '\0') {
+            if (!cur.empty()) ctx->timing_only.push_back(cur);
+            cur.clear();
+            if (!*p) break;
+        } else if (*p != ' ') {
+            cur.push_back(*p);
+        }
+    }
     return CDL_OK;
 }
 

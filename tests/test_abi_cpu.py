@@ -108,6 +108,7 @@ def test_calls_reject_a_null_context(L):
                                 None, 10, 0, None, 5, None, None, 0) == 1
     assert L.cdl_ctx_set_stream(None, None) == 1
     assert L.cdl_ctx_set_timing(None, 1) == 1
+    assert L.cdl_ctx_set_timing_only(None, b"rhs") == 1
     assert L.cdl_ctx_set_solve_depth(None, 2) == 1
     assert L.cdl_ctx_set_select(None, 0) == 1
     assert L.cdl_chain_densify(None, 100, None, 0, None) == 1

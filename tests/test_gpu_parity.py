@@ -184,6 +184,11 @@ def test_dense_chain_fixed_q_richardson_matches_oracle(cdl):
     assert info.iterations == 9 and list(info.depth_used[:9]) == [1] * 9
     assert t["apply"][0] == 9           # one product with P1 per step
     assert t["chain_product"][0] == 7   # d - 1 products formed it
+    cdl.set_timing(True, only=["apply", "residual"])
+    cdl.solve_embedding(g, ch, 32, 7, tol=0.0, max_iter=3)
+    t = cdl.timing(reset=True)
+    cdl.set_timing(False, only=None)
+    assert set(t) == {"apply", "residual"} and t["apply"][0] == 3 and t["residual"][0] == 3
     W = host(g.W)[:256, :256]
     deg, vol = oracle.degrees(W)
     lev = oracle.chain_levels(oracle.normalized_deflated(W, deg, vol), 8)
