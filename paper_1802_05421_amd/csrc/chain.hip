@@ -81,6 +81,7 @@ __global__ __launch_bounds__(256) void k_normalize(const double *W, int64_t ld, 
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t j = j0 + lane;
     const double dj = j < n ? dmn[j] : 0.0, uj = j < n ? u[j] : 0.0;
+    const double inv_scale = 1.0 / scale;   // scale is a power of two: exact
     double s = 0.0, s64 = 0.0;
     double wl[16];   // all sixteen row loads in flight before the first use
 #pragma unroll
@@ -98,7 +99,7 @@ __global__ __launch_bounds__(256) void k_normalize(const double *W, int64_t ld, 
         const T tv = cvtd<T>(v * scale);
         t[r][lane] = tv;
         S0[i * ld + j] = tv;
-        const double back = tod<T>(tv) / scale;
+        const double back = tod<T>(tv) * inv_scale;
         s += back * back;
         s64 += v * v;
     }
@@ -149,6 +150,7 @@ __global__ __launch_bounds__(256) void k_normalize_rows(const double *Wp, int64_
     T *out = S0 + i * ld;
     const bool live = i < n;
     const double di = live ? dmn[i] : 0.0, ui = live ? u[i] : 0.0;
+    const double inv_scale = 1.0 / scale;   // scale is a power of two: exact
     double s = 0.0, s64 = 0.0;
     for (int64_t j0 = threadIdx.x; j0 < ld; j0 += 4 * 256) {
         double wl[4];   // four loads in flight
@@ -166,7 +168,7 @@ __global__ __launch_bounds__(256) void k_normalize_rows(const double *Wp, int64_
             }
             const T tv = cvtd<T>(v * scale);
             out[j] = tv;
-            const double back = tod<T>(tv) / scale;
+            const double back = tod<T>(tv) * inv_scale;
             s += back * back;
             s64 += v * v;
         }
