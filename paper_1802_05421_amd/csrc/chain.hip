@@ -63,15 +63,22 @@ hipError_t launch_chain_prep(const double *deg, const double *stats, int64_t n, 
     return hipGetLastError();
 }
 
-// One upper 64 x 64 tile per workgroup; lane = column, so every global
-// access of a wave is one contiguous row segment; the mirror is written from
-// the LDS copy of the rounded tile.
+// One upper 64 x 64 tile per workgroup.  A lane takes two adjacent columns
+// of every other row: 16-byte loads of W and two-element stores of the
+// level, so a wave access covers two contiguous row segments.  The mirror is
+// written from the LDS copy of the rounded tile, two adjacent rows per lane.
+// Every element is the expression of k_normalize_rows.
 template <typename T>
 __global__ __launch_bounds__(256) void k_normalize(const double *W, int64_t ld, int64_t n,
                                                    const double *dmn, const double *u, int lazy,
                                                    double scale, int nt, T *S0,
                                                    double *fro_part, double *fro64_part) {
-    __shared__ T t[64][64 + 16 / sizeof(T)];
+    struct alignas(2 * sizeof(T)) T2 { T a, b; };
+    struct alignas(16) D2 { double x, y; };
+    // row pitch: a whole number of T2 pairs; 2-byte types get an odd word
+    // count, so the mirror's column reads spread over the banks
+    constexpr int PAD = sizeof(T) == 2 ? 2 : 16 / (int)sizeof(T);
+    __shared__ T t[64][64 + PAD];
     __shared__ double red[4];
     const int total = nt * (nt + 1) / 2;
     const int id = xcd_remap(blockIdx.x, total);
@@ -79,36 +86,58 @@ __global__ __launch_bounds__(256) void k_normalize(const double *W, int64_t ld, 
     sym_tile<8>(id, nt, I, J);
     const int64_t i0 = (int64_t)I * 64, j0 = (int64_t)J * 64;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t j = j0 + lane;
-    const double dj = j < n ? dmn[j] : 0.0, uj = j < n ? u[j] : 0.0;
+    const int cp = lane & 31, h = lane >> 5;
+    const int64_t ja = j0 + 2 * cp;   // this lane's columns ja, ja + 1
+    double dj[2], uj[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        dj[e] = ja + e < n ? dmn[ja + e] : 0.0;
+        uj[e] = ja + e < n ? u[ja + e] : 0.0;
+    }
     const double inv_scale = 1.0 / scale;   // scale is a power of two: exact
     double s = 0.0, s64 = 0.0;
-    double wl[16];   // all sixteen row loads in flight before the first use
+    // all row loads (W pairs and the rows' factors) in flight before the
+    // first use: the rows of a wave differ between its halves, so the
+    // factors are vector loads
+    D2 wl[8];
+    double di[8], ui[8];
 #pragma unroll
-    for (int rr = 0; rr < 16; ++rr) wl[rr] = W[(i0 + wv * 16 + rr) * ld + j];
+    for (int rr = 0; rr < 8; ++rr) {
+        const int64_t i = i0 + wv * 16 + 2 * rr + h;
+        wl[rr] = *(const D2 *)(W + i * ld + ja);
+        di[rr] = i < n ? dmn[i] : 0.0;
+        ui[rr] = i < n ? u[i] : 0.0;
+    }
 #pragma unroll
-    for (int rr = 0; rr < 16; ++rr) {
-        const int r = wv * 16 + rr;
+    for (int rr = 0; rr < 8; ++rr) {
+        const int r = wv * 16 + 2 * rr + h;
         const int64_t i = i0 + r;
-        double v = 0.0;
-        if (i < n && j < n) {
-            v = wl[rr] * (dmn[i] * dj);
-            if (lazy) v = 0.5 * ((i == j ? 1.0 : 0.0) + v);
-            v -= u[i] * uj;
+        T tv[2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int64_t j = ja + e;
+            double v = 0.0;
+            if (i < n && j < n) {
+                v = (e ? wl[rr].y : wl[rr].x) * (di[rr] * dj[e]);
+                if (lazy) v = 0.5 * ((i == j ? 1.0 : 0.0) + v);
+                v -= ui[rr] * uj[e];
+            }
+            tv[e] = cvtd<T>(v * scale);
+            const double back = tod<T>(tv[e]) * inv_scale;
+            s += back * back;
+            s64 += v * v;
         }
-        const T tv = cvtd<T>(v * scale);
-        t[r][lane] = tv;
-        S0[i * ld + j] = tv;
-        const double back = tod<T>(tv) * inv_scale;
-        s += back * back;
-        s64 += v * v;
+        const T2 pk{tv[0], tv[1]};
+        *(T2 *)&t[r][2 * cp] = pk;
+        *(T2 *)(S0 + i * ld + ja) = pk;
     }
     if (I != J) {
         __syncthreads();
 #pragma unroll 4
-        for (int cc = 0; cc < 16; ++cc) {
-            const int c = wv * 16 + cc;
-            S0[(j0 + c) * ld + i0 + lane] = t[lane][c];
+        for (int cc = 0; cc < 8; ++cc) {
+            const int c = wv * 16 + 2 * cc + h;
+            const T2 pk{t[2 * cp][c], t[2 * cp + 1][c]};
+            *(T2 *)(S0 + (j0 + c) * ld + i0 + 2 * cp) = pk;
         }
     }
     const double w = I != J ? 2.0 : 1.0;
