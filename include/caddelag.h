@@ -186,8 +186,8 @@ cdl_status cdl_ctx_set_select(cdl_ctx *ctx, int mode);
 /* ---- per-kernel timing ------------------------------------------------- */
 
 /* enable != 0: every kernel launch of later calls on this context is
- * bracketed by HIP events recorded on the context's stream (a few
- * microseconds of overhead per launch); totals accumulate per kernel name
+ * bracketed by HIP events recorded on the context's stream (about ten
+ * microseconds of stream time per timed launch); totals accumulate per kernel name
  * ("gram_dist", "select_median", "exp_degree", "normalize", "square",
  * "apply", "rhs", "residual", "score", "topk", ...). */
 cdl_status cdl_ctx_set_timing(cdl_ctx *ctx, int enable);
