@@ -123,7 +123,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only (single-GPU hot path); "
+        print("bench.py: the library runs on one GPU only (single-GPU hot path); "
               "--gpus %d is not supported" % max(args.gpus, world), file=sys.stderr)
         sys.exit(2)
 

@@ -74,7 +74,7 @@ typedef enum {
                                normalised, deflated matrix is >= 1) */
     CDL_E_NOCONV = 6,       /* solve did not reach tol within max_iter */
     CDL_E_HIP = 7,          /* HIP runtime error */
-    CDL_E_UNSUPPORTED = 8   /* valid request this build does not implement */
+    CDL_E_UNSUPPORTED = 8   /* valid request the library does not implement */
 } cdl_status;
 
 typedef enum { CDL_FP64 = 0, CDL_FP32 = 1, CDL_BF16 = 2, CDL_FP16 = 3 } cdl_prec;

@@ -153,7 +153,7 @@ def bandwidth(D2: np.ndarray) -> float:
 
     The element of 0-based rank floor((N-1)/2) among the N = n(n-1)/2 sorted
     distances.  (The paper fixes sigma by hand for its climate graph; the
-    median-distance rule is this build's reading for synthetic inputs.)
+    median-distance rule is the reading taken here for synthetic inputs.)
     """
     n = D2.shape[0]
     if n < 2:
