@@ -144,6 +144,29 @@ def test_chain_levels_match_oracle(cdl, prec, tol):
         assert ch.info.fro[l] == pytest.approx(np.linalg.norm(lev[l]), rel=10 * tol * 2 ** l)
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 3e-6), ("bf16", 2e-2), ("fp16", 4e-3)])
+def test_lazy_levels_match_oracle(cdl, prec, tol):
+    # lazy walk (I + S)/2 - u u^T; n = 333 is odd and not a multiple of 64,
+    # so the last column pair of a row straddles the end of the graph
+    n = 333
+    X = series(n, 17, 5)
+    g = cdl.build_graph(dev(X))
+    W = host(g.W)[:n, :n]
+    deg, vol = oracle.degrees(W)
+    lev = oracle.chain_levels(oracle.normalized_deflated(W, deg, vol, lazy=True), 2)
+    ch = cdl.build_chain(g, prec=prec, depth=2, depth_max=2, lazy=True)
+    assert ch.info.lazy == 1 and ch.depth == 2
+    sc = cdl.level_scale(ch)
+    for l in range(2):
+        Lg = host(cdl.level(ch, l).double()) / sc
+        np.testing.assert_array_equal(Lg, Lg.T)
+        assert np.all(Lg[n:, :] == 0) and np.all(Lg[:, n:] == 0)
+        e = rel(Lg[:n, :n], lev[l])
+        print("lazy prec %s level %d rel err %.3e" % (prec, l, e))
+        assert e <= tol * (2 ** l), (prec, l, e)
+        assert ch.info.fro[l] == pytest.approx(np.linalg.norm(lev[l]), rel=10 * tol * 2 ** l)
+
+
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 3e-6), ("bf16", 3e-2), ("fp16", 8e-3)])
 @pytest.mark.parametrize("depth", [1, 2, 4])
 def test_dense_chain_product_matches_oracle(cdl, prec, tol, depth):
