@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <functional>
+#include <initializer_list>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -39,6 +40,10 @@ struct cdl_ctx {
     hipGraph_t seq_graph = nullptr;
     hipGraphExec_t seq_exec = nullptr;
     hipStream_t side = nullptr;   // second stream of asynchronous sequences (created on first use)
+    // Pinned host staging for device-to-host reads (grown on demand): a copy
+    // into pageable memory is staged by the runtime one copy at a time.
+    void *stage = nullptr;
+    size_t stage_bytes = 0;
 };
 
 namespace {
@@ -58,6 +63,46 @@ bool timing_selected(const cdl_ctx *c, const char *nm) {
     for (const auto &s : c->timing_only)
         if (s == nm) return true;
     return false;
+}
+
+// One device-to-host read: `bytes` from device `src` into host `dst`.
+struct HostRead {
+    void *dst;
+    const void *src;
+    size_t bytes;
+};
+
+// Enqueues the reads into the context's pinned staging buffer, synchronises
+// the stream and copies the results out (every read in one round trip).
+hipError_t read_to_host(cdl_ctx *c, std::initializer_list<HostRead> reads) {
+    size_t total = 0;
+    for (const auto &r : reads) total += (r.bytes + 255) / 256 * 256;
+    if (total > c->stage_bytes) {
+        // no copy into the old buffer is pending: every read ends with a sync
+        if (c->stage) (void)hipHostFree(c->stage);
+        c->stage = nullptr;
+        c->stage_bytes = 0;
+        void *p = nullptr;
+        const hipError_t e = hipHostMalloc(&p, total, hipHostMallocDefault);
+        if (e != hipSuccess) return e;
+        c->stage = p;
+        c->stage_bytes = total;
+    }
+    size_t off = 0;
+    for (const auto &r : reads) {
+        const hipError_t e = hipMemcpyAsync((char *)c->stage + off, r.src, r.bytes,
+                                            hipMemcpyDeviceToHost, c->stream);
+        if (e != hipSuccess) return e;
+        off += (r.bytes + 255) / 256 * 256;
+    }
+    const hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return e;
+    off = 0;
+    for (const auto &r : reads) {
+        std::memcpy(r.dst, (const char *)c->stage + off, r.bytes);
+        off += (r.bytes + 255) / 256 * 256;
+    }
+    return hipSuccess;
 }
 
 // Brackets one kernel launch (or a fixed group of launches) with events.
@@ -501,6 +546,10 @@ cdl_status cdl_ctx_destroy(cdl_ctx *ctx) {
     if (ctx->seq_exec) (void)hipGraphExecDestroy(ctx->seq_exec);
     if (ctx->seq_graph) (void)hipGraphDestroy(ctx->seq_graph);
     if (ctx->side) (void)hipStreamDestroy(ctx->side);
+    if (ctx->stage) {
+        (void)hipStreamSynchronize(ctx->stream);
+        (void)hipHostFree(ctx->stage);
+    }
     delete ctx;
     return CDL_OK;
 }
@@ -688,9 +737,8 @@ cdl_status cdl_build_chain(cdl_ctx *ctx, const double *W, const double *deg, con
     { Timed t_(ctx, "normalize"); HIPCHK(launch_normalize(prec, W, ld, n, c.dmn, c.u, info->lazy, c.levels, c.fro, c.fro64, s)); }
     const int nst = sym_tiles64(ld);
     std::vector<double> part(nst), part64(nst);
-    HIPCHK(hipMemcpyAsync(part.data(), c.fro, nst * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(part64.data(), c.fro64, nst * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(read_to_host(ctx, {{part.data(), c.fro, nst * sizeof(double)},
+                              {part64.data(), c.fro64, nst * sizeof(double)}}));
     info->rho_bound = std::sqrt(host_sum(part64));
     double f = std::sqrt(host_sum(part));
     if (!std::isfinite(f)) return fail(ctx, CDL_E_NONFINITE, "non-finite chain level");
@@ -711,8 +759,7 @@ cdl_status cdl_build_chain(cdl_ctx *ctx, const double *W, const double *deg, con
         { Timed t_(ctx, "square"); HIPCHK(launch_square(prec, c.levels + c.level_bytes * l, c.levels + c.level_bytes * (l + 1),
                              ld, n, c.fro, s)); }
         part.resize(ntl);
-        HIPCHK(hipMemcpyAsync(part.data(), c.fro, ntl * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
+        HIPCHK(read_to_host(ctx, {{part.data(), c.fro, ntl * sizeof(double)}}));
         const double fprev = f;
         f = std::sqrt(host_sum(part));
         if (!std::isfinite(f)) return fail(ctx, CDL_E_NONFINITE, "non-finite chain level");
@@ -807,9 +854,8 @@ static cdl_status solve_from_rhs(cdl_ctx *ctx, const WProduct &wprod, const doub
     { Timed t_(ctx, "col_norms"); HIPCHK(launch_col_norms2(w.npart, nparts, kp, w.mpart, ntiles, scaled, w.scal, s)); }
     std::vector<double> ynorm(kp), rnorm(kp);
     double hstats[CDL_GRAPH_STATS];
-    HIPCHK(hipMemcpyAsync(ynorm.data(), w.scal, kp * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(hstats, stats, sizeof(hstats), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(read_to_host(ctx, {{ynorm.data(), w.scal, kp * sizeof(double)},
+                              {hstats, stats, sizeof(hstats)}}));
     for (int64_t r = 0; r < k; ++r)
         if (!std::isfinite(ynorm[r])) return fail(ctx, CDL_E_NONFINITE, "non-finite right-hand side");
     // kappa bounds ||e|| / ||z|| per unit relative residual: the nonzero
@@ -842,8 +888,7 @@ static cdl_status solve_from_rhs(cdl_ctx *ctx, const WProduct &wprod, const doub
     };
     // max_r ||r_r|| / ||y_r|| after the norms kernel; syncs.
     auto residual_check = [&]() -> cdl_status {
-        HIPCHK(hipMemcpyAsync(rnorm.data(), w.scal, kp * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
+        HIPCHK(read_to_host(ctx, {{rnorm.data(), w.scal, kp * sizeof(double)}}));
         rel = 0.0;
         for (int64_t r = 0; r < k; ++r) {
             if (!std::isfinite(rnorm[r])) return fail(ctx, CDL_E_NONFINITE, "non-finite residual");
