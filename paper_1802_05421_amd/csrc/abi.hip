@@ -72,9 +72,10 @@ struct HostRead {
     size_t bytes;
 };
 
-// Enqueues the reads into the context's pinned staging buffer, synchronises
-// the stream and copies the results out (every read in one round trip).
-hipError_t read_to_host(cdl_ctx *c, std::initializer_list<HostRead> reads) {
+// Enqueues the reads on `stream` into the context's pinned staging buffer,
+// synchronises that stream and copies the results out (every read in one
+// round trip).
+hipError_t read_to_host(cdl_ctx *c, hipStream_t stream, std::initializer_list<HostRead> reads) {
     size_t total = 0;
     for (const auto &r : reads) total += (r.bytes + 255) / 256 * 256;
     if (total > c->stage_bytes) {
@@ -91,11 +92,11 @@ hipError_t read_to_host(cdl_ctx *c, std::initializer_list<HostRead> reads) {
     size_t off = 0;
     for (const auto &r : reads) {
         const hipError_t e = hipMemcpyAsync((char *)c->stage + off, r.src, r.bytes,
-                                            hipMemcpyDeviceToHost, c->stream);
+                                            hipMemcpyDeviceToHost, stream);
         if (e != hipSuccess) return e;
         off += (r.bytes + 255) / 256 * 256;
     }
-    const hipError_t e = hipStreamSynchronize(c->stream);
+    const hipError_t e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return e;
     off = 0;
     for (const auto &r : reads) {
@@ -668,8 +669,7 @@ cdl_status cdl_check_graph(cdl_ctx *ctx, const double *deg, const double *stats,
     if (!ctx) return CDL_E_ARG;
     if (!deg || !stats || n < 2) return fail(ctx, CDL_E_ARG, "bad arguments");
     double h[CDL_GRAPH_STATS];
-    HIPCHK(hipMemcpyAsync(h, stats, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(read_to_host(ctx, ctx->stream, {{h, stats, sizeof(h)}}));
     if (host_stats) std::memcpy(host_stats, h, sizeof(h));
     for (double v : h)
         if (!std::isfinite(v)) return fail(ctx, CDL_E_NONFINITE, "non-finite weights or degrees");
@@ -695,8 +695,7 @@ cdl_status cdl_graph_from_weights(cdl_ctx *ctx, const double *Win, int64_t n, in
     { Timed t_(ctx, "set_sigma"); HIPCHK(launch_set_sigma(0.0, stats, s)); }
     { Timed t_(ctx, "graph_stats"); HIPCHK(launch_graph_stats(deg, n, stats, s)); }
     int hf = 0;
-    HIPCHK(hipMemcpyAsync(&hf, flags, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(read_to_host(ctx, s, {{&hf, flags, sizeof(int)}}));
     if (hf & 1) return fail(ctx, CDL_E_NONFINITE, "non-finite weight");
     if (hf & 2) return fail(ctx, CDL_E_GRAPH, "negative weight");
     if (hf & 4) return fail(ctx, CDL_E_GRAPH, "asymmetric weights");
@@ -737,7 +736,7 @@ cdl_status cdl_build_chain(cdl_ctx *ctx, const double *W, const double *deg, con
     { Timed t_(ctx, "normalize"); HIPCHK(launch_normalize(prec, W, ld, n, c.dmn, c.u, info->lazy, c.levels, c.fro, c.fro64, s)); }
     const int nst = sym_tiles64(ld);
     std::vector<double> part(nst), part64(nst);
-    HIPCHK(read_to_host(ctx, {{part.data(), c.fro, nst * sizeof(double)},
+    HIPCHK(read_to_host(ctx, s, {{part.data(), c.fro, nst * sizeof(double)},
                               {part64.data(), c.fro64, nst * sizeof(double)}}));
     info->rho_bound = std::sqrt(host_sum(part64));
     double f = std::sqrt(host_sum(part));
@@ -759,7 +758,7 @@ cdl_status cdl_build_chain(cdl_ctx *ctx, const double *W, const double *deg, con
         { Timed t_(ctx, "square"); HIPCHK(launch_square(prec, c.levels + c.level_bytes * l, c.levels + c.level_bytes * (l + 1),
                              ld, n, c.fro, s)); }
         part.resize(ntl);
-        HIPCHK(read_to_host(ctx, {{part.data(), c.fro, ntl * sizeof(double)}}));
+        HIPCHK(read_to_host(ctx, s, {{part.data(), c.fro, ntl * sizeof(double)}}));
         const double fprev = f;
         f = std::sqrt(host_sum(part));
         if (!std::isfinite(f)) return fail(ctx, CDL_E_NONFINITE, "non-finite chain level");
@@ -854,7 +853,7 @@ static cdl_status solve_from_rhs(cdl_ctx *ctx, const WProduct &wprod, const doub
     { Timed t_(ctx, "col_norms"); HIPCHK(launch_col_norms2(w.npart, nparts, kp, w.mpart, ntiles, scaled, w.scal, s)); }
     std::vector<double> ynorm(kp), rnorm(kp);
     double hstats[CDL_GRAPH_STATS];
-    HIPCHK(read_to_host(ctx, {{ynorm.data(), w.scal, kp * sizeof(double)},
+    HIPCHK(read_to_host(ctx, s, {{ynorm.data(), w.scal, kp * sizeof(double)},
                               {hstats, stats, sizeof(hstats)}}));
     for (int64_t r = 0; r < k; ++r)
         if (!std::isfinite(ynorm[r])) return fail(ctx, CDL_E_NONFINITE, "non-finite right-hand side");
@@ -888,7 +887,7 @@ static cdl_status solve_from_rhs(cdl_ctx *ctx, const WProduct &wprod, const doub
     };
     // max_r ||r_r|| / ||y_r|| after the norms kernel; syncs.
     auto residual_check = [&]() -> cdl_status {
-        HIPCHK(read_to_host(ctx, {{rnorm.data(), w.scal, kp * sizeof(double)}}));
+        HIPCHK(read_to_host(ctx, s, {{rnorm.data(), w.scal, kp * sizeof(double)}}));
         rel = 0.0;
         for (int64_t r = 0; r < k; ++r) {
             if (!std::isfinite(rnorm[r])) return fail(ctx, CDL_E_NONFINITE, "non-finite residual");
@@ -1101,8 +1100,7 @@ cdl_status cdl_stream_embedding(cdl_ctx *ctx, const double *X, int64_t n, int64_
     { Timed t_(ctx, "fill_zero"); HIPCHK(launch_fill_zero(w.flags, 256, s)); }
     { Timed t_(ctx, "pad_series"); HIPCHK(launch_pad_series(X, n, T, ldx, w.Xp, ld, Tp, w.sqn, w.flags, s)); }
     int hflag = 0;
-    HIPCHK(hipMemcpyAsync(&hflag, w.flags, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(read_to_host(ctx, s, {{&hflag, w.flags, sizeof(int)}}));
     if (hflag) return fail(ctx, CDL_E_NONFINITE, "non-finite node series");
 
     // Bandwidth: exact lower median of the upper-triangle distances.  One
@@ -1124,16 +1122,13 @@ cdl_status cdl_stream_embedding(cdl_ctx *ctx, const double *X, int64_t n, int64_
                 { Timed t_(ctx, "stream_select"); HIPCHK(launch_select_bracket_panel(w.panel, ld, n, r0, std::min(r0 + rows, n), w.sel, w.selbuf, cap, s)); }
             }
             { Timed t_(ctx, "stream_select"); HIPCHK(launch_select_check(w.sel, cap, stats, s)); }
-            HIPCHK(hipMemcpyAsync(&src, &w.sel->src, sizeof(int), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipMemcpyAsync(&mode, &w.sel->mode, sizeof(int), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
+            HIPCHK(read_to_host(ctx, s, {{&src, &w.sel->src, sizeof(int)}, {&mode, &w.sel->mode, sizeof(int)}}));
         }
         if (src == 1 && mode != 2) {
             // at most 6 digit passes resolve 64 bits; the collect pass is one more
             for (int p = 0; p < 7; ++p)
                 { Timed t_(ctx, "stream_select"); HIPCHK(launch_select_buffer_pass(w.sel, w.selbuf, cap, stats, s)); }
-            HIPCHK(hipMemcpyAsync(&mode, &w.sel->mode, sizeof(int), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
+            HIPCHK(read_to_host(ctx, s, {{&mode, &w.sel->mode, sizeof(int)}}));
         }
         for (int digit = 0; digit < 7 && mode != 2; ++digit) {
             for (int64_t r0 = 0; r0 < n; r0 += P) {
@@ -1142,8 +1137,7 @@ cdl_status cdl_stream_embedding(cdl_ctx *ctx, const double *X, int64_t n, int64_
                 { Timed t_(ctx, "stream_select"); HIPCHK(launch_select_panel(w.panel, ld, n, r0, std::min(r0 + rows, n), w.sel, s)); }
             }
             { Timed t_(ctx, "stream_select"); HIPCHK(launch_select_pick(w.sel, stats, s)); }
-            HIPCHK(hipMemcpyAsync(&mode, &w.sel->mode, sizeof(int), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
+            HIPCHK(read_to_host(ctx, s, {{&mode, &w.sel->mode, sizeof(int)}}));
         }
         if (mode != 2) return fail(ctx, CDL_E_HIP, "median selection did not finish");
     }
@@ -1165,8 +1159,7 @@ cdl_status cdl_stream_embedding(cdl_ctx *ctx, const double *X, int64_t n, int64_
         // for deeper levels), with the FP64 residual's product W X taken by a
         // streamed sweep.
         double hst[CDL_GRAPH_STATS];
-        HIPCHK(hipMemcpyAsync(hst, stats, sizeof(hst), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
+        HIPCHK(read_to_host(ctx, s, {{hst, stats, sizeof(hst)}}));
         for (double v : hst)
             if (!std::isfinite(v)) return fail(ctx, CDL_E_NONFINITE, "non-finite weights or degrees");
         if (!(hst[2] > 0.0)) return fail(ctx, CDL_E_GRAPH, "a node has zero degree");
@@ -1180,9 +1173,7 @@ cdl_status cdl_stream_embedding(cdl_ctx *ctx, const double *X, int64_t n, int64_
                                                 w.fro + r0, w.fro64 + r0, s)); }
         }
         std::vector<double> f1(n), f2(n);
-        HIPCHK(hipMemcpyAsync(f1.data(), w.fro, n * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(f2.data(), w.fro64, n * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
+        HIPCHK(read_to_host(ctx, s, {{f1.data(), w.fro, n * sizeof(double)}, {f2.data(), w.fro64, n * sizeof(double)}}));
         cdl_chain_info ci;
         std::memset(&ci, 0, sizeof(ci));
         ci.prec = (cdl_prec)level_prec;
@@ -1212,9 +1203,7 @@ cdl_status cdl_stream_embedding(cdl_ctx *ctx, const double *X, int64_t n, int64_
     { Timed t_(ctx, "col_norms"); HIPCHK(launch_col_norms2(w.npart, nparts, kp, w.mpart, ntiles, 0, w.scal, s)); }
     std::vector<double> ynorm(kp), rnorm(kp);
     double hstats[CDL_GRAPH_STATS];
-    HIPCHK(hipMemcpyAsync(ynorm.data(), w.scal, kp * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(hstats, stats, sizeof(hstats), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(read_to_host(ctx, s, {{ynorm.data(), w.scal, kp * sizeof(double)}, {hstats, stats, sizeof(hstats)}}));
     for (double v : hstats)
         if (!std::isfinite(v)) return fail(ctx, CDL_E_NONFINITE, "non-finite weights or degrees");
     if (!(hstats[2] > 0.0)) return fail(ctx, CDL_E_GRAPH, "a node has zero degree");
@@ -1251,8 +1240,7 @@ cdl_status cdl_stream_embedding(cdl_ctx *ctx, const double *X, int64_t n, int64_
         if (it == 0) {
             // ||S~||_F^2 = ||S||_F^2 - 1 for the deflated S~ = S - u u^T
             std::vector<double> fro(n);
-            HIPCHK(hipMemcpyAsync(fro.data(), w.fro, n * sizeof(double), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
+            HIPCHK(read_to_host(ctx, s, {{fro.data(), w.fro, n * sizeof(double)}}));
             const double f2 = host_sum(fro) - 1.0;
             rb = std::sqrt(std::max(f2, 0.0));
             if (rb < 1.0) kappa = hstats[3] * (1.0 + rb) / (hstats[2] * (1.0 - rb));
@@ -1268,8 +1256,7 @@ cdl_status cdl_stream_embedding(cdl_ctx *ctx, const double *X, int64_t n, int64_
         if ((st = product_sweep(w.Xt, false)) != CDL_OK) return st;
         { Timed t_(ctx, "residual"); HIPCHK(launch_residual_reduce(w.Prod, 1, w.Yt, w.Xt, deg, w.rdeg, ld, n, kp, k, w.Rt, w.npart, w.mpart, s)); }
         { Timed t_(ctx, "col_norms"); HIPCHK(launch_col_norms2(w.npart, nparts, kp, w.mpart, ntiles, 0, w.scal, s)); }
-        HIPCHK(hipMemcpyAsync(rnorm.data(), w.scal, kp * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
+        HIPCHK(read_to_host(ctx, s, {{rnorm.data(), w.scal, kp * sizeof(double)}}));
         rel = 0.0;
         for (int64_t r = 0; r < k; ++r) {
             if (!std::isfinite(rnorm[r])) return fail(ctx, CDL_E_NONFINITE, "non-finite residual");
@@ -1302,8 +1289,7 @@ cdl_status cdl_stream_embedding(cdl_ctx *ctx, const double *X, int64_t n, int64_
 static cdl_status check_map(cdl_ctx *ctx, const int32_t *map, int64_t m, int64_t n) {
     if (!map) return m == n ? CDL_OK : fail(ctx, CDL_E_ARG, "identity map needs m == n");
     std::vector<int32_t> h(m);
-    HIPCHK(hipMemcpyAsync(h.data(), map, m * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(read_to_host(ctx, ctx->stream, {{h.data(), map, m * sizeof(int32_t)}}));
     for (int32_t v : h)
         if (v < 0 || v >= n) return fail(ctx, CDL_E_ARG, "map entry out of range");
     return CDL_OK;
@@ -1398,8 +1384,7 @@ cdl_status cdl_anomaly_edges(cdl_ctx *ctx, const double *Z0, const double *W0,
     { Timed t_(ctx, "topk"); HIPCHK(launch_topk64(e.cval, e.cidx, e.cap, e.count, top_k, e.cscratch, edge_val, e.idx, s)); }
     { Timed t_(ctx, "edge_split"); HIPCHK(launch_edge_split(e.idx, m, top_k, edge_a, edge_b, s)); }
     unsigned int cnt = 0;
-    HIPCHK(hipMemcpyAsync(&cnt, e.count, sizeof(cnt), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(read_to_host(ctx, s, {{&cnt, e.count, sizeof(cnt)}}));
     if ((int64_t)cnt > e.cap)
         return fail(ctx, CDL_E_UNSUPPORTED, "more than " + std::to_string(e.cap) +
                                                 " edges reach the K-th edge score (massive ties)");
@@ -1747,8 +1732,7 @@ cdl_status cdl_score_sequence(cdl_ctx *ctx, int32_t n_snap, const cdl_snapshot *
         }
         // one read-back for the whole sequence: graph checks and residuals
         std::vector<double> hs((size_t)n_snap * (CDL_GRAPH_STATS + 2 * kp));
-        HIPCHK(hipMemcpyAsync(hs.data(), status, hs.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
+        HIPCHK(read_to_host(ctx, s, {{hs.data(), status, hs.size() * sizeof(double)}}));
         double worst = 0.0;
         for (int t = 0; t < n_snap; ++t) {
             const double *h = hs.data() + (size_t)t * (CDL_GRAPH_STATS + 2 * kp);
