@@ -35,7 +35,9 @@
  *   caller; "host" pointers point to CPU memory.  The library never allocates
  *   or frees device memory: every scratch buffer is a caller-supplied
  *   workspace whose size is returned by cdl_workspace_bytes().  Workspaces
- *   must be 256-byte aligned.
+ *   must be 256-byte aligned.  A context keeps one pinned host buffer for the
+ *   values that calls read back (norms, statistics, flags), grown on demand
+ *   and freed by cdl_ctx_destroy.
  * Layout.  n x n matrices (weights W, chain levels) use the library's padded
  *   square layout: cdl_ld(n) rows of cdl_ld(n) elements, row-major, with
  *   cdl_ld(n) = n rounded up to a multiple of 256; entries in padding rows and
