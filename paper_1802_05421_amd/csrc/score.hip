@@ -15,6 +15,7 @@
 //   edges       the K largest edge scores (a < b) exactly: per-tile maxima
 //               from k_score, threshold = K-th largest tile maximum, only
 //               tiles reaching it recomputed and their edges collected
+#include "caddelag.h"
 #include "common.h"
 #include "gemm.h"
 #include "kernels.h"
@@ -297,7 +298,11 @@ hipError_t launch_score_reduce(const double *part, int nparts, int64_t m, int64_
 // ---------------------------------------------------------------------------
 // Top-K.
 
-constexpr int kChunk = 2048;
+// Chunks of 512 (one compare-exchange per thread and stage, 45 stages):
+// twice the largest K, so every round at least halves the candidates, and
+// small enough that the first round spreads over many workgroups.
+constexpr int kChunk = 512;
+static_assert(kChunk >= 2 * CDL_MAX_TOPK, "every round must shrink the candidates");
 
 __device__ inline bool before(double va, int ia, double vb, int ib) {
     return va > vb || (va == vb && ia < ib);
