@@ -187,4 +187,19 @@ __device__ inline void rect_tile(int id, int mt, int nt, int &I, int &J) {
     J = j0 + q % w;
 }
 
+// acc + p[0] + p[stride] + ... + p[(cnt - 1) stride], added in index order
+// (the same rounding as a plain loop), with 32 loads in flight at a time.
+__device__ inline double ordered_sum(const double *p, int64_t stride, int cnt, double acc) {
+    int b = 0;
+    for (; b + 32 <= cnt; b += 32) {
+        double v[32];
+#pragma unroll
+        for (int u = 0; u < 32; ++u) v[u] = p[(int64_t)(b + u) * stride];
+#pragma unroll
+        for (int u = 0; u < 32; ++u) acc += v[u];
+    }
+    for (; b < cnt; ++b) acc += p[(int64_t)b * stride];
+    return acc;
+}
+
 } // namespace cdl

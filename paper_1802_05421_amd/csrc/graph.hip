@@ -938,9 +938,7 @@ __global__ __launch_bounds__(256) void k_exp_sym(double *W, int64_t ld, int64_t 
 __global__ void k_degree_reduce(const double *part, int nt, int64_t ld, int64_t n, double *deg) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    double acc = 0.0;
-    for (int b = 0; b < nt; ++b) acc += part[(int64_t)b * ld + i];
-    deg[i] = acc;
+    deg[i] = ordered_sum(part + i, ld, nt, 0.0);
 }
 
 hipError_t launch_exp_degree(double *W, int64_t ld, int64_t n, const double *stats,
@@ -948,7 +946,8 @@ hipError_t launch_exp_degree(double *W, int64_t ld, int64_t n, const double *sta
     const int nt = (int)(ld / 64);
     hipLaunchKernelGGL(k_exp_sym, dim3((unsigned)sym_tiles64(ld)), dim3(256), 0, s, W, ld, n,
                        stats, nt, part);
-    hipLaunchKernelGGL(k_degree_reduce, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, part, nt,
+    // one wave per workgroup: the n threads spread over every CU
+    hipLaunchKernelGGL(k_degree_reduce, dim3((unsigned)cdiv(n, 64)), dim3(64), 0, s, part, nt,
                        ld, n, deg);
     return hipGetLastError();
 }

@@ -280,17 +280,17 @@ __global__ void k_score_reduce(const double *part, int ncol, int64_t m, int64_t 
                                double *F) {
     int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= m) return;
-    double s = 0.0;
-    for (int J = (int)(a / 256) * 2; J < ncol; ++J) s += part[(int64_t)J * mpad + a];
+    const int J0 = (int)(a / 256) * 2;
+    double s = J0 < ncol ? ordered_sum(part + (int64_t)J0 * mpad + a, mpad, ncol - J0, 0.0) : 0.0;
     const int Imax = (int)(a / 128) / 2;
-    for (int I = 0; I <= Imax; ++I) s += part[(int64_t)(ncol + I) * mpad + a];
+    s = ordered_sum(part + (int64_t)ncol * mpad + a, mpad, Imax + 1, s);
     F[a] = s;
 }
 
 hipError_t launch_score_reduce(const double *part, int nparts, int64_t m, int64_t mpad,
                                double *F, hipStream_t s) {
     (void)nparts;   // the slot layout follows from mpad
-    hipLaunchKernelGGL(k_score_reduce, dim3((unsigned)cdiv(m, 256)), dim3(256), 0, s, part,
+    hipLaunchKernelGGL(k_score_reduce, dim3((unsigned)cdiv(m, 64)), dim3(64), 0, s, part,
                        (int)(mpad / 128), m, mpad, F);
     return hipGetLastError();
 }
