@@ -957,12 +957,20 @@ __global__ __launch_bounds__(256) void k_graph_stats(const double *deg, int64_t 
     __shared__ double red[4];
     __shared__ double rmin[256], rmax[256];
     double s = 0.0, lo = INFINITY, hi = -INFINITY;
-    for (int64_t i = threadIdx.x; i < n; i += 256) {
-        double d = deg[i];
-        s += d;
-        lo = fmin(lo, d);
-        hi = fmax(hi, d);
-        if (isnan(d)) lo = hi = d;
+    // a thread's nodes in increasing order, sixteen loads in flight
+    for (int64_t i0 = threadIdx.x; i0 < n; i0 += 16 * 256) {
+        double dv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) dv[u] = i0 + 256 * u < n ? deg[i0 + 256 * u] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            if (i0 + 256 * u >= n) break;
+            const double d = dv[u];
+            s += d;
+            lo = fmin(lo, d);
+            hi = fmax(hi, d);
+            if (isnan(d)) lo = hi = d;
+        }
     }
     rmin[threadIdx.x] = lo;
     rmax[threadIdx.x] = hi;

@@ -722,8 +722,9 @@ __global__ __launch_bounds__(256) void k_col_mean(const double *Xt, int64_t ld, 
                                                   double *mean) {
     __shared__ double red[4];
     const int64_t r = blockIdx.x;
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += 256) s += Xt[r * ld + i];
+    // a thread's entries in increasing order, 32 loads in flight
+    const int64_t cnt = n > threadIdx.x ? (n - threadIdx.x + 255) / 256 : 0;
+    double s = ordered_sum(Xt + r * ld + threadIdx.x, 256, (int)cnt, 0.0);
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
