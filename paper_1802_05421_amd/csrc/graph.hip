@@ -514,6 +514,12 @@ __global__ __launch_bounds__(256) void k_select_pass(const double *D2, int64_t l
     __shared__ unsigned int h[4096];
     const int mode = st->mode;
     if (mode == 2) return;
+    // Buffered keys go to at most kBufBlocks workgroups, each flushing its
+    // histogram once for many keys: the flush is global atomics on the same
+    // 4096 bins, and thousands of workgroups flushing them contend.
+    constexpr int kBufBlocks = 256;
+    const bool from_buf = st->src == 1;
+    if (from_buf && (int)blockIdx.x >= kBufBlocks) return;
     int shift, width;
     unsigned long long hi_mask;
     sel_digit(st, shift, width, hi_mask);
@@ -533,8 +539,9 @@ __global__ __launch_bounds__(256) void k_select_pass(const double *D2, int64_t l
         }
     };
     // eight independent loads in flight per thread
-    if (st->src == 1) {
-        const int64_t nb = (int64_t)st->nbuf, stride = (int64_t)gridDim.x * 256;
+    if (from_buf) {
+        const int64_t gb = (int)gridDim.x < kBufBlocks ? (int64_t)gridDim.x : (int64_t)kBufBlocks;
+        const int64_t nb = (int64_t)st->nbuf, stride = gb * 256;
         for (int64_t q0 = (int64_t)blockIdx.x * 256 + threadIdx.x; q0 < nb; q0 += 8 * stride) {
             unsigned long long key[8];
 #pragma unroll
