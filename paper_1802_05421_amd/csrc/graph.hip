@@ -514,12 +514,14 @@ __global__ __launch_bounds__(256) void k_select_pass(const double *D2, int64_t l
     __shared__ unsigned int h[4096];
     const int mode = st->mode;
     if (mode == 2) return;
-    // Buffered keys go to at most kBufBlocks workgroups, each flushing its
-    // histogram once for many keys: the flush is global atomics on the same
-    // 4096 bins, and thousands of workgroups flushing them contend.
+    // Up to 2^24 buffered keys go to at most kBufBlocks workgroups, each
+    // flushing its histogram once for many keys: the flush is global atomics
+    // on the same 4096 bins, and thousands of workgroups flushing them
+    // contend.  Larger buffers keep the whole grid for bandwidth.
     constexpr int kBufBlocks = 256;
     const bool from_buf = st->src == 1;
-    if (from_buf && (int)blockIdx.x >= kBufBlocks) return;
+    const bool few = from_buf && st->nbuf <= (1ull << 24);
+    if (few && (int)blockIdx.x >= kBufBlocks) return;
     int shift, width;
     unsigned long long hi_mask;
     sel_digit(st, shift, width, hi_mask);
@@ -540,7 +542,7 @@ __global__ __launch_bounds__(256) void k_select_pass(const double *D2, int64_t l
     };
     // eight independent loads in flight per thread
     if (from_buf) {
-        const int64_t gb = (int)gridDim.x < kBufBlocks ? (int64_t)gridDim.x : (int64_t)kBufBlocks;
+        const int64_t gb = few && (int)gridDim.x > kBufBlocks ? (int64_t)kBufBlocks : (int64_t)gridDim.x;
         const int64_t nb = (int64_t)st->nbuf, stride = gb * 256;
         for (int64_t q0 = (int64_t)blockIdx.x * 256 + threadIdx.x; q0 < nb; q0 += 8 * stride) {
             unsigned long long key[8];
