@@ -211,6 +211,20 @@ cdl_status cdl_timing_reset(cdl_ctx *ctx);
 
 /* Padded leading dimension (and row count) of the library's n x n layout. */
 int64_t cdl_ld(int64_t n);
+/* Number of random projections k_RP = ceil(ln(n / eps_rp)) that Algorithm 1
+ * and Algorithm 3 take for n nodes and accuracy eps_rp (the paper leaves the
+ * logarithm's base open; the natural log is used).  This is the k that
+ * cdl_solve_embedding uses when it is called with k <= 0.
+ *   k       host output.
+ * Errors: CDL_E_ARG for n < 2, eps_rp outside (0, 1) or a NULL k. */
+cdl_status cdl_k_rp(int64_t n, double eps_rp, int64_t *k);
+/* Storage scale of chain levels of type prec for n nodes: FP16 levels hold
+ * scale * S~ with scale = 2^floor(log2 n), so that entries of order 1/n stay
+ * in FP16's normal range; 1 for the other types.  Divide a level read back
+ * through cdl_chain_level_offset by it.
+ *   scale   host output.
+ * Errors: CDL_E_ARG for n < 1, an invalid prec or a NULL scale. */
+cdl_status cdl_level_scale(int64_t n, cdl_prec prec, double *scale);
 /* Bytes of an n x n matrix of `prec` elements in the padded layout. */
 size_t cdl_matrix_bytes(int64_t n, cdl_prec prec);
 /* Byte offset of level 0 inside a chain buffer; level l starts at

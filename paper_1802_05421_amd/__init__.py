@@ -26,6 +26,7 @@ from .api import (  # noqa: E402,F401
     graph_from_weights,
     ld,
     level,
+    k_rp,
     level_scale,
     score_sequence,
     sequence_workspace_bytes,

@@ -9,7 +9,6 @@ fallback: if the library is missing, importing the package fails.
 from __future__ import annotations
 
 import ctypes as C
-import math
 from dataclasses import dataclass, field
 from typing import List, Optional, Sequence
 
@@ -242,12 +241,17 @@ def level(chain: Chain, l: int) -> torch.Tensor:
 
 
 def level_scale(chain: Chain) -> float:
-    if chain.info.prec != 3:
-        return 1.0
-    s = 1.0
-    while s * 2 <= chain.n:
-        s *= 2
-    return s
+    """Storage scale of the chain's levels (cdl_level_scale)."""
+    out = C.c_double()
+    _check(_lib().cdl_level_scale(chain.n, chain.info.prec, C.byref(out)))
+    return out.value
+
+
+def k_rp(n: int, eps_rp: float) -> int:
+    """Algorithm 1's number of projections for n nodes and accuracy eps_rp (cdl_k_rp)."""
+    out = C.c_int64()
+    _check(_lib().cdl_k_rp(int(n), float(eps_rp), C.byref(out)))
+    return out.value
 
 
 def solve_embedding(g: Graph, chain: Chain, k: int, seed: int, tol: float = 1e-8,
@@ -257,7 +261,7 @@ def solve_embedding(g: Graph, chain: Chain, k: int, seed: int, tol: float = 1e-8
                     raise_noconv: bool = True):
     """Embedding Z (n, k) float64 with L Z = Y to relative residual tol."""
     ctx = context(g.W.device.index)
-    kk = k if k > 0 else int(math.ceil(math.log(g.n / eps_rp)))
+    kk = k if k > 0 else k_rp(g.n, eps_rp)
     need = workspace_bytes(g.n, 1, kk, max(chain.info.depth, 1), L.PREC_NAME[chain.info.prec])["solve"]
     if ws is None or ws.numel() < need:
         ws = _ws(need, g.W.device)

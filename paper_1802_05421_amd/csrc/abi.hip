@@ -619,6 +619,18 @@ cdl_status cdl_ctx_set_stream(cdl_ctx *ctx, void *stream) {
 
 int64_t cdl_ld(int64_t n) { return n > 0 ? pad_n(n) : 0; }
 
+cdl_status cdl_k_rp(int64_t n, double eps_rp, int64_t *k) {
+    if (!k || n < 2 || !(eps_rp > 0.0 && eps_rp < 1.0)) return CDL_E_ARG;
+    *k = (int64_t)std::ceil(std::log((double)n / eps_rp));
+    return CDL_OK;
+}
+
+cdl_status cdl_level_scale(int64_t n, cdl_prec prec, double *scale) {
+    if (!scale || n < 1 || !valid_prec(prec)) return CDL_E_ARG;
+    *scale = (double)level_scale(prec, n);
+    return CDL_OK;
+}
+
 size_t cdl_chain_level_offset(int64_t n, cdl_prec prec) {
     if (n < 2 || !valid_prec(prec)) return 0;
     Arena a(nullptr);
@@ -986,11 +998,8 @@ cdl_status cdl_solve_embedding(cdl_ctx *ctx, const double *W, const double *deg,
                                int max_iter, double *Z, void *ws, size_t ws_bytes,
                                cdl_solve_info *info) {
     if (!ctx) return CDL_E_ARG;
-    if (k <= 0) {
-        if (!(eps_rp > 0.0 && eps_rp < 1.0)) return fail(ctx, CDL_E_ARG, "need 0 < eps_rp < 1 when k <= 0");
-        if (n < 2) return fail(ctx, CDL_E_ARG, "bad n");
-        k = (int64_t)std::ceil(std::log((double)n / eps_rp));
-    }
+    if (k <= 0 && cdl_k_rp(n, eps_rp, &k) != CDL_OK)
+        return fail(ctx, CDL_E_ARG, "need n >= 2 and 0 < eps_rp < 1 when k <= 0");
     cdl_status st = check_solve(ctx, W, deg, stats, n, chain, ci, k, solver, max_iter, Z, ws, ws_bytes);
     if (st != CDL_OK) return st;
     Arena a(ws);

@@ -160,3 +160,21 @@ def test_package_import_fails_loudly_without_library(tmp_path):
         ROOT, str(tmp_path / "missing.so"), str(tmp_path / "missing.so"))
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True)
     assert "refused" in out.stdout
+
+
+def test_k_rp_and_level_scale_queries(L):
+    import math
+    k = C.c_int64()
+    assert L.cdl_k_rp(16384, 1e-2, C.byref(k)) == 0
+    assert k.value == math.ceil(math.log(16384 / 1e-2)) == 15
+    for n, eps in [(1, 0.1), (100, 0.0), (100, 1.0), (100, -0.5), (100, float("nan"))]:
+        assert L.cdl_k_rp(n, eps, C.byref(k)) == 1          # CDL_E_ARG
+    assert L.cdl_k_rp(100, 0.1, None) == 1
+    s = C.c_double()
+    for n, want in [(1, 1.0), (2, 2.0), (300, 256.0), (16384, 16384.0), (16385, 16384.0)]:
+        assert L.cdl_level_scale(n, 3, C.byref(s)) == 0 and s.value == want
+        for p in (0, 1, 2):
+            assert L.cdl_level_scale(n, p, C.byref(s)) == 0 and s.value == 1.0
+    assert L.cdl_level_scale(0, 3, C.byref(s)) == 1
+    assert L.cdl_level_scale(10, 4, C.byref(s)) == 1
+    assert L.cdl_level_scale(10, 3, None) == 1

@@ -335,6 +335,23 @@ def test_scores_with_exact_embeddings_equal_eq1():
     np.testing.assert_allclose(Fw, (np.abs(W1 - W0) * np.abs(C0 - C1)).sum(axis=1), rtol=1e-11)
 
 
+def test_embedding_commute_times_equal_eq1():
+    # Algorithm 1's embedding form vol * ||z_i - z_j||^2 with the full
+    # edge-space embedding (||z_i - z_j||^2 = R_ij exactly) against eq. (1)
+    # and, on K_n, against the closed form c = 2 (n - 1).
+    W = random_dense_graph(8, 40)
+    Z, *_ = edge_embedding(W)
+    C = oracle.commute_times(Z, W.sum())
+    np.testing.assert_allclose(C, oracle.exact_commute_times(W), rtol=1e-11, atol=1e-11)
+    assert np.all(np.diag(C) == 0.0)
+    n = 7
+    Kn = np.ones((n, n)) - np.eye(n)
+    Zk, *_ = edge_embedding(Kn)
+    Ck = oracle.commute_times(Zk, Kn.sum())
+    off = ~np.eye(n, dtype=bool)
+    np.testing.assert_allclose(Ck[off], 2.0 * (n - 1), rtol=1e-12)
+
+
 def test_edge_scores_sum_to_node_scores():
     # Algorithm 4's node score is the row sum of the edge scores; the two are
     # computed independently (direct differences here, the C row loops for
