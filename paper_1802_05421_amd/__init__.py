@@ -28,6 +28,7 @@ from .api import (  # noqa: E402,F401
     level,
     k_rp,
     level_scale,
+    level_scale_for,
     score_sequence,
     sequence_workspace_bytes,
     set_select,

@@ -247,6 +247,13 @@ def level_scale(chain: Chain) -> float:
     return out.value
 
 
+def level_scale_for(n: int, prec: str) -> float:
+    """Storage scale of chain levels of type `prec` for n nodes (cdl_level_scale)."""
+    out = C.c_double()
+    _check(_lib().cdl_level_scale(int(n), L.PREC[prec], C.byref(out)))
+    return out.value
+
+
 def k_rp(n: int, eps_rp: float) -> int:
     """Algorithm 1's number of projections for n nodes and accuracy eps_rp (cdl_k_rp)."""
     out = C.c_int64()

@@ -1,13 +1,19 @@
 """The full-size pair (128 x 128 grid, n = 16384, T = 240, k = 256) in the
 launch configuration the benchmark times: FP16 chain levels, adaptive depth
 (at most 6 stored levels), both right-hand sides from one sweep, certified
-stop at 1e-6, top-50.
+stop at 1e-6, top-50 - compared with the oracle run on the same pair in
+full: the Gaussian-kernel graph element by element, the embeddings
+Z = L^+ Y of both snapshots (dense Cholesky of the n x n Laplacian, the same
+seeded signs; Algorithm 3), the node scores of Algorithm 4 by direct
+differences and the top-50 set.
 
-The graph stage is compared with the oracle in full.  The oracle cannot solve
-this size within a test, so the solve is checked on sampled rows (the oracle's
-right-hand-side rows against L Z on those rows) and through properties that
-hold at any size (centred columns, the certificate), and the scores through
-their definition on the embeddings the GPU produced plus the top-K order.
+Gates: e_Z = ||Z - Z_o||_F / ||Z_o||_F <= 1e-6 per snapshot, and below the
+solve's own certificate; e_F = ||F - F_o||_inf / ||F_o||_inf <= 1e-5; the
+same top-50 set whenever the oracle's gap between its 50th and 51st score
+exceeds 2 e_F (relative to ||F_o||_inf).
+
+The oracle takes about a minute per snapshot on 16 host cores, so each
+snapshot's oracle run happens in its own test (cached for the later ones).
 """
 
 import numpy as np
@@ -20,6 +26,7 @@ import oracle
 pytestmark = [pytest.mark.gpu, pytest.mark.slow, pytest.mark.timeout(900)]
 
 K, DEPTH_MAX, TOL = 256, 6, -1e-6
+EZ_MAX, EF_MAX = 1e-6, 1e-5
 
 
 @pytest.fixture(scope="module")
@@ -60,39 +67,60 @@ def run(cdl):
     return out
 
 
-@pytest.fixture(scope="module")
-def graphs(run):
-    return {t: oracle.build_graph(run[t]["X"]) for t in (0, 1)}
+_oracle = {}
+
+
+def oracle_snapshot(run, t):
+    """The oracle's graph, right-hand sides and embedding of snapshot t (cached)."""
+    if t not in _oracle:
+        print("oracle snapshot %d: graph, right-hand sides, Cholesky solve" % t, flush=True)
+        o = oracle.build_graph(run[t]["X"])
+        del o["D2"]
+        o["Y"] = oracle.rhs(o["W"], K, run["seed"])
+        o["Z"] = oracle.solve_embedding(o["W"], o["Y"], o["deg"])
+        _oracle[t] = o
+    return _oracle[t]
 
 
 @pytest.mark.parametrize("t", [0, 1])
-def test_graph_full_parity(cdl, run, graphs, t):
-    o, g = graphs[t], run[t]["g"]
+def test_graph_full_parity(cdl, run, t):
+    o, g = oracle_snapshot(run, t), run[t]["g"]
     n = o["W"].shape[0]
     s = g.host_stats()
     assert s["sigma"] == pytest.approx(o["sigma"], rel=1e-12)
     W = host(g.W)
     np.testing.assert_allclose(W[:n, :n], o["W"], rtol=0, atol=2e-13)
+    del W
     np.testing.assert_allclose(host(g.deg), o["deg"], rtol=1e-12)
     assert s["vol"] == pytest.approx(o["vol"], rel=1e-12)
 
 
 @pytest.mark.parametrize("t", [0, 1])
-def test_solve_sampled_rows(run, graphs, t):
-    o, Z, info = graphs[t], run[t]["Z"], run[t]["info"]
-    n = Z.shape[0]
+def test_embedding_matches_oracle(run, t):
+    o, Z, info = oracle_snapshot(run, t), run[t]["Z"], run[t]["info"]
+    ez = np.linalg.norm(Z - o["Z"]) / np.linalg.norm(o["Z"])
+    print("snapshot %d: depth %d iterations %d residual %.2e certified %.2e e_Z %.2e" % (
+        t, run[t]["ch"].depth, info.iterations, info.rel_residual, info.certified_error, ez))
     assert info.converged and info.certified_error <= abs(TOL)
-    # columns orthogonal to the constant vector
+    assert ez <= EZ_MAX
+    # the certificate bounds the distance to L^+ Y (the two right-hand sides
+    # differ by rounding only, ~1e-14)
+    assert ez <= info.certified_error + 1e-10
+
+
+@pytest.mark.parametrize("t", [0, 1])
+def test_solve_sampled_rows(run, t):
+    # the oracle's right-hand-side rows against L Z on those rows
+    o, Z, info = oracle_snapshot(run, t), run[t]["Z"], run[t]["info"]
+    n = Z.shape[0]
     assert np.abs(Z.sum(axis=0)).max() <= 1e-10 * np.abs(Z).max() * np.sqrt(n)
     rows = np.random.default_rng(100 + t).choice(n, size=96, replace=False)
     rows = np.sort(np.concatenate([rows, [0, n - 1]]))
-    Y = oracle.rhs_rows(o["W"][rows], rows, K, run["seed"])
+    Y = o["Y"][rows]
     LZ = o["deg"][rows, None] * Z[rows] - o["W"][rows] @ Z
     rel = np.linalg.norm(LZ - Y) / np.linalg.norm(Y)
-    print("snapshot %d: depth %d iterations %d residual %.2e sampled %.2e kappa %.2f" % (
-        t, run[t]["ch"].depth, info.iterations, info.rel_residual, rel, info.kappa))
+    print("snapshot %d: sampled residual %.2e (reported %.2e)" % (t, rel, info.rel_residual))
     assert rel <= max(20 * info.rel_residual, 1e-13)
-    assert rel * info.kappa <= 10 * abs(TOL)
 
 
 @pytest.mark.parametrize("t", [0, 1])
@@ -105,23 +133,23 @@ def test_pair_solve_equals_single_solve(cdl, run, t):
     assert info.converged and d <= max(r["info"].certified_error, info.certified_error)
 
 
-def test_scores_sampled_rows_and_top50(run, graphs):
-    Z0, Z1, F = run[0]["Z"], run[1]["Z"], run["F"]
-    n = Z0.shape[0]
-    v0, v1 = graphs[0]["vol"], graphs[1]["vol"]
-    rows = np.sort(np.random.default_rng(5).choice(n, size=64, replace=False))
-    rows = np.union1d(rows, run["top"][:8])
-    sq0 = (Z0 * Z0).sum(1)
-    sq1 = (Z1 * Z1).sum(1)
-    for a in rows:
-        c0 = v0 * (sq0[a] + sq0 - 2.0 * Z0 @ Z0[a])
-        c1 = v1 * (sq1[a] + sq1 - 2.0 * Z1 @ Z1[a])
-        d = np.abs(c0 - c1)
-        d[a] = 0.0
-        want = d.sum()
-        assert F[a] == pytest.approx(want, rel=1e-9)
-    top = run["top"]
+def test_scores_and_top50_match_oracle(run):
+    o0, o1 = oracle_snapshot(run, 0), oracle_snapshot(run, 1)
+    print("oracle scores (direct differences)", flush=True)
+    Fo = oracle.scores(o0["Z"], o0["vol"], o1["Z"], o1["vol"])
+    topo = oracle.top_k(Fo, 50)
+    F, top = run["F"], run["top"]
+    ef = np.abs(F - Fo).max() / np.abs(Fo).max()
+    e2 = np.linalg.norm(F - Fo) / np.linalg.norm(Fo)
+    srt = np.sort(Fo)[::-1]
+    gap = (srt[49] - srt[50]) / np.abs(Fo).max()
+    same = set(top.tolist()) == set(topo.tolist())
+    print("e_F %.2e (2-norm %.2e), top-50 gap %.2e, same top-50 %s" % (ef, e2, gap, same))
+    assert ef <= EF_MAX
+    if gap > 2 * ef:
+        assert same
+    # the GPU's own ordering of its top-50
     assert len(set(top.tolist())) == 50
     assert np.all(np.diff(F[top]) <= 0)
-    rest = np.setdiff1d(np.arange(n), top)
+    rest = np.setdiff1d(np.arange(F.size), top)
     assert F[rest].max() <= F[top].min()
