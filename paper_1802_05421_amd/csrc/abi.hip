@@ -195,6 +195,7 @@ GraphWs plan_graph(Arena &a, int64_t n, int64_t T) {
 
 struct ChainBuf {
     double *dmn, *dm, *u, *fro, *fro64;
+    float *tail;   // partial tiles of a squaring's last round (nullptr: none)
     char *levels;
     size_t level_bytes;
 };
@@ -206,6 +207,8 @@ ChainBuf plan_chain(Arena &a, int64_t n, int prec, int depth_max) {
     c.u = a.take<double>(ld);
     c.fro = a.take<double>(std::max<int64_t>(sym_tiles64(ld), square_tiles(prec, ld)));
     c.fro64 = a.take<double>(sym_tiles64(ld));
+    const size_t tb = square_tail_bytes(prec, ld, n);
+    c.tail = tb ? a.take<float>(tb / sizeof(float)) : nullptr;
     c.level_bytes = (size_t)ld * ld * esize(prec);
     c.levels = a.take<char>(c.level_bytes * depth_max);
     return c;
@@ -768,7 +771,7 @@ cdl_status cdl_build_chain(cdl_ctx *ctx, const double *W, const double *deg, con
         if (!more) break;
         const int ntl = square_tiles(prec, ld);
         { Timed t_(ctx, "square"); HIPCHK(launch_square(prec, c.levels + c.level_bytes * l, c.levels + c.level_bytes * (l + 1),
-                             ld, n, c.fro, s)); }
+                             ld, n, c.fro, c.tail, s)); }
         part.resize(ntl);
         HIPCHK(read_to_host(ctx, s, {{part.data(), c.fro, ntl * sizeof(double)}}));
         const double fprev = f;
@@ -819,10 +822,10 @@ cdl_status cdl_chain_densify(cdl_ctx *ctx, int64_t n, void *chain, size_t chain_
         // Q_{j} = Q_{j-1} + L_j + Q_{j-1} L_j alternating between the scratch
         // slot and slot 0 (free once L_0 is consumed); Q ends in slot 0.
         char *scratch = slot(d), *cur = scratch;
-        { Timed t_(ctx, "chain_product"); HIPCHK(launch_chain_product(info->prec, slot(0), slot(1), scratch, ld, n, c.fro, s)); }
+        { Timed t_(ctx, "chain_product"); HIPCHK(launch_chain_product(info->prec, slot(0), slot(1), scratch, ld, n, c.fro, c.tail, s)); }
         for (int j = 2; j < d; ++j) {
             char *dst = cur == scratch ? slot(0) : scratch;
-            { Timed t_(ctx, "chain_product"); HIPCHK(launch_chain_product(info->prec, cur, slot(j), dst, ld, n, c.fro, s)); }
+            { Timed t_(ctx, "chain_product"); HIPCHK(launch_chain_product(info->prec, cur, slot(j), dst, ld, n, c.fro, c.tail, s)); }
             cur = dst;
         }
         if (cur != slot(0)) HIPCHK(hipMemcpyAsync(slot(0), cur, c.level_bytes, hipMemcpyDeviceToDevice, s));
@@ -1444,7 +1447,7 @@ cdl_status chain_enqueue(cdl_ctx *ctx, const double *W, const double *deg, const
     { Timed t_(ctx, "normalize"); HIPCHK(launch_normalize(prec, W, ld, n, c.dmn, c.u, 0, c.levels, c.fro, c.fro64, s)); }
     for (int l = 0; l + 1 < depth; ++l) {
         Timed t_(ctx, "square");
-        HIPCHK(launch_square(prec, c.levels + c.level_bytes * l, c.levels + c.level_bytes * (l + 1), ld, n, c.fro, s));
+        HIPCHK(launch_square(prec, c.levels + c.level_bytes * l, c.levels + c.level_bytes * (l + 1), ld, n, c.fro, c.tail, s));
     }
     return CDL_OK;
 }

@@ -240,27 +240,17 @@ template <typename T> constexpr size_t sq_smem() {
     return C::SMEM > stage ? C::SMEM : stage;
 }
 
-// C = A B (upper tiles, mirrored), scaled back by inv_scale; add != 0 also
-// adds A + B (the next factor of the dense chain product, below).  A and B
-// are polynomials in the same symmetric matrix, so they commute and C is
-// symmetric.  The squaring is A = B = S, add = 0.
-template <typename T>
-__global__ __launch_bounds__(SqCfg<T>::Core::NT) void k_square(const T *A, const T *B, T *S2, int64_t ld,
-                                                int64_t kend, int nt, float inv_scale,
-                                                int add, double *fro_part) {
-    using Core = typename SqCfg<T>::Core;
+// Epilogue of one output tile of C = A B (tile rows m0.., columns n0..):
+// scale back by inv_scale, with add != 0 also add A + B (the next factor of
+// the dense chain product, below), round to T, store the tile and (off the
+// diagonal) its mirror, and write the squared Frobenius norm of the stored
+// values (doubled off the diagonal) to *fro_out.  A and B are polynomials in
+// the same symmetric matrix, so they commute and C is symmetric.
+template <typename T, class Core>
+__device__ inline void square_epilogue(Core &g, const T *A, const T *B, T *S2, int64_t ld,
+                                       int64_t m0, int64_t n0, bool mirror, float inv_scale,
+                                       int add, double *fro_out, T *smem, double *red) {
     using Acc = typename Core::MF::Acc;
-    constexpr int TL = SqCfg<T>::TILE;
-    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
-    T *smem = (T *)smem_raw;
-    __shared__ double red[Core::NT / 64];
-    const int total = nt * (nt + 1) / 2;
-    const int id = TL == 256 ? round_remap(blockIdx.x, total) : xcd_remap(blockIdx.x, total);
-    int I, J;
-    sym_tile<8>(id, nt, I, J);
-    const int64_t m0 = (int64_t)I * TL, n0 = (int64_t)J * TL;
-    Core g;
-    g.run(A, ld, B, ld, m0, n0, kend, smem);
     double fro = 0.0;
     auto f = [&](int r, int c, Acc acc) -> T {
         Acc v = acc * (Acc)inv_scale;
@@ -273,7 +263,7 @@ __global__ __launch_bounds__(SqCfg<T>::Core::NT) void k_square(const T *A, const
         fro += tv * tv;
         return t;
     };
-    stage_and_store(g, smem, f, S2, ld, m0, n0, I != J);
+    stage_and_store(g, smem, f, S2, ld, m0, n0, mirror);
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) fro += __shfl_xor(fro, o);
     __syncthreads();
@@ -282,8 +272,88 @@ __global__ __launch_bounds__(SqCfg<T>::Core::NT) void k_square(const T *A, const
     if (threadIdx.x == 0) {
         double t = 0.0;
         for (int q = 0; q < Core::NT / 64; ++q) t += red[q];
-        fro_part[id] = (I != J ? 2.0 : 1.0) * t;
+        *fro_out = (mirror ? 2.0 : 1.0) * t;
     }
+}
+
+// C = A B over the upper tiles with logical ids [0, count) (count = all
+// tiles, or the full rounds of 256 workgroups when the last round is split
+// over k below).  The squaring is A = B = S, add = 0.
+template <typename T>
+__global__ __launch_bounds__(SqCfg<T>::Core::NT) void k_square(const T *A, const T *B, T *S2, int64_t ld,
+                                                int64_t kend, int nt, int count, float inv_scale,
+                                                int add, double *fro_part) {
+    using Core = typename SqCfg<T>::Core;
+    constexpr int TL = SqCfg<T>::TILE;
+    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+    __shared__ double red[Core::NT / 64];
+    const int id = TL == 256 ? round_remap(blockIdx.x, count) : xcd_remap(blockIdx.x, count);
+    int I, J;
+    sym_tile<8>(id, nt, I, J);
+    const int64_t m0 = (int64_t)I * TL, n0 = (int64_t)J * TL;
+    Core g;
+    g.run(A, ld, B, ld, m0, n0, kend, (T *)smem_raw);
+    square_epilogue<T>(g, A, B, S2, ld, m0, n0, I != J, inv_scale, add, fro_part + id,
+                       (T *)smem_raw, red);
+}
+
+// The tiles of the last, partial round of workgroups (logical ids
+// first + b / splits), each split into `splits` k-ranges of ks elements:
+// workgroup b multiplies its range and stores the FP32 accumulators as a
+// partial tile (element e of thread t at P[b * TL^2 + e * NT + t]).
+template <typename T>
+__global__ __launch_bounds__(SqCfg<T>::Core::NT) void k_square_part(const T *A, const T *B, int64_t ld,
+                                                     int64_t kend, int64_t ks, int nt, int first,
+                                                     int splits, float *P) {
+    using Core = typename SqCfg<T>::Core;
+    constexpr int TL = SqCfg<T>::TILE;
+    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+    const int b = blockIdx.x, sp = b % splits;
+    int I, J;
+    sym_tile<8>(first + b / splits, nt, I, J);
+    const int64_t k0 = (int64_t)sp * ks;
+    const int64_t kk = kend - k0 < ks ? kend - k0 : ks;
+    Core g;
+    g.run(A + k0, ld, B + k0, ld, (int64_t)I * TL, (int64_t)J * TL, kk, (T *)smem_raw);
+    float *Pb = P + (size_t)b * TL * TL;
+    int e = 0;
+#pragma unroll
+    for (int i = 0; i < Core::WTM; ++i)
+#pragma unroll
+        for (int j = 0; j < Core::WTN; ++j)
+#pragma unroll
+            for (int r = 0; r < Core::MF::R; ++r, ++e) Pb[(size_t)e * Core::NT + threadIdx.x] = g.acc[i][j][r];
+}
+
+// One workgroup per tile of the split round: the partial tiles summed in
+// split order into the accumulator layout of the core, then the epilogue.
+template <typename T>
+__global__ __launch_bounds__(SqCfg<T>::Core::NT) void k_square_tail(const T *A, const T *B, T *S2,
+                                                     int64_t ld, int nt, int first, int splits,
+                                                     const float *P, float inv_scale, int add,
+                                                     double *fro_part) {
+    using Core = typename SqCfg<T>::Core;
+    constexpr int TL = SqCfg<T>::TILE;
+    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+    __shared__ double red[Core::NT / 64];
+    const int id = first + blockIdx.x;
+    int I, J;
+    sym_tile<8>(id, nt, I, J);
+    Core g;
+    const float *Pt = P + (size_t)blockIdx.x * splits * TL * TL;
+    int e = 0;
+#pragma unroll
+    for (int i = 0; i < Core::WTM; ++i)
+#pragma unroll
+        for (int j = 0; j < Core::WTN; ++j)
+#pragma unroll
+            for (int r = 0; r < Core::MF::R; ++r, ++e) {
+                float v = 0.f;
+                for (int sp = 0; sp < splits; ++sp) v += Pt[(size_t)sp * TL * TL + (size_t)e * Core::NT + threadIdx.x];
+                g.acc[i][j][r] = v;
+            }
+    square_epilogue<T>(g, A, B, S2, ld, (int64_t)I * TL, (int64_t)J * TL, I != J, inv_scale, add,
+                       fro_part + id, (T *)smem_raw, red);
 }
 
 int square_tiles(int prec, int64_t ld) {
@@ -292,43 +362,90 @@ int square_tiles(int prec, int64_t ld) {
     return nt * (nt + 1) / 2;
 }
 
+// Work split of one 16-bit squaring: the upper tiles fill `full` rounds of
+// one workgroup per CU; when a last round of at most half the CUs remains,
+// its `rem` tiles are split over k into `splits` ranges of ks elements, so
+// that the last round occupies the whole chip.
+struct SqPlan {
+    int total, full, rem, splits;
+    int64_t kend, ks;
+};
+static SqPlan square_plan(int prec, int64_t ld, int64_t n) {
+    SqPlan p;
+    p.total = square_tiles(prec, ld);
+    p.kend = (n + 63) / 64 * 64;   // multiple of every BK used (64/32/16)
+    p.full = p.total;
+    p.rem = 0;
+    p.splits = 0;
+    p.ks = 0;
+    const bool dma = prec == 2 || prec == 3;
+    const int rem = p.total % kNumCu;
+    if (!dma || p.total < kNumCu || rem == 0 || rem > kNumCu / 2) return p;
+    const int64_t nk = p.kend / 64;
+    int s = kNumCu / rem;
+    if (s > nk / 2) s = (int)(nk / 2);
+    if (s < 2) return p;
+    p.ks = cdiv(nk, s) * 64;
+    p.splits = (int)cdiv(p.kend, p.ks);
+    if (p.splits < 2) return p;
+    p.full = p.total - rem;
+    p.rem = rem;
+    return p;
+}
+
+size_t square_tail_bytes(int prec, int64_t ld, int64_t n) {
+    const SqPlan p = square_plan(prec, ld, n);
+    return (size_t)p.rem * p.splits * 256 * 256 * sizeof(float);
+}
+
 template <typename T>
 static hipError_t sq_launch(const void *A, const void *B, void *S2, int64_t ld, int64_t n,
-                            float inv_scale, int add, double *fro_part, hipStream_t s) {
+                            float inv_scale, int add, double *fro_part, float *tail, hipStream_t s) {
     constexpr int TL = SqCfg<T>::TILE;
     constexpr size_t smem = sq_smem<T>();
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_square<T>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-        if (e != hipSuccess) return e;
+        for (const void *fn : {(const void *)k_square<T>, (const void *)k_square_part<T>,
+                               (const void *)k_square_tail<T>}) {
+            hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+            if (e != hipSuccess) return e;
+        }
         attr = true;
     }
     const int nt = (int)(ld / TL);
-    const int total = nt * (nt + 1) / 2;
-    constexpr int BK = (int)(64 * 2 / sizeof(T)) < 16 ? 16 : (int)(64 * 2 / sizeof(T));
-    const int64_t kend = (n + 63) / 64 * 64;   // multiple of every BK used (64/32/16)
-    (void)BK;
-    hipLaunchKernelGGL(k_square<T>, dim3(total), dim3(SqCfg<T>::Core::NT), smem, s, (const T *)A, (const T *)B,
-                       (T *)S2, ld, kend, nt, inv_scale, add, fro_part);
+    const int prec = std::is_same<T, double>::value ? 0 : std::is_same<T, float>::value ? 1 :
+                     std::is_same<T, __bf16>::value ? 2 : 3;
+    SqPlan p = square_plan(prec, ld, n);
+    if (!tail) p = SqPlan{p.total, p.total, 0, 0, p.kend, 0};
+    hipLaunchKernelGGL(k_square<T>, dim3(p.full), dim3(SqCfg<T>::Core::NT), smem, s, (const T *)A,
+                       (const T *)B, (T *)S2, ld, p.kend, nt, p.full, inv_scale, add, fro_part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || p.rem == 0) return e;
+    hipLaunchKernelGGL(k_square_part<T>, dim3(p.rem * p.splits), dim3(SqCfg<T>::Core::NT), smem, s,
+                       (const T *)A, (const T *)B, ld, p.kend, p.ks, nt, p.full, p.splits, tail);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_square_tail<T>, dim3(p.rem), dim3(SqCfg<T>::Core::NT), smem, s, (const T *)A,
+                       (const T *)B, (T *)S2, ld, nt, p.full, p.splits, (const float *)tail,
+                       inv_scale, add, fro_part);
     return hipGetLastError();
 }
 
 static hipError_t sq_dispatch(int prec, const void *A, const void *B, void *C, int64_t ld, int64_t n,
-                              int add, double *fro_part, hipStream_t s) {
+                              int add, double *fro_part, float *tail, hipStream_t s) {
     const float inv = 1.0f / level_scale(prec, n);
     switch (prec) {
-    case 0: return sq_launch<double>(A, B, C, ld, n, inv, add, fro_part, s);
-    case 1: return sq_launch<float>(A, B, C, ld, n, inv, add, fro_part, s);
-    case 2: return sq_launch<__bf16>(A, B, C, ld, n, inv, add, fro_part, s);
-    case 3: return sq_launch<_Float16>(A, B, C, ld, n, inv, add, fro_part, s);
+    case 0: return sq_launch<double>(A, B, C, ld, n, inv, add, fro_part, nullptr, s);
+    case 1: return sq_launch<float>(A, B, C, ld, n, inv, add, fro_part, nullptr, s);
+    case 2: return sq_launch<__bf16>(A, B, C, ld, n, inv, add, fro_part, tail, s);
+    case 3: return sq_launch<_Float16>(A, B, C, ld, n, inv, add, fro_part, tail, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_square(int prec, const void *S, void *S2, int64_t ld, int64_t n,
-                         double *fro_part, hipStream_t s) {
-    return sq_dispatch(prec, S, S, S2, ld, n, 0, fro_part, s);
+                         double *fro_part, float *tail, hipStream_t s) {
+    return sq_dispatch(prec, S, S, S2, ld, n, 0, fro_part, tail, s);
 }
 
 // Inside a diagonal tile both triangles come out of the GEMM, and for A != B
@@ -352,8 +469,8 @@ static hipError_t sym_diag_launch(void *C, int64_t ld, hipStream_t s) {
 }
 
 hipError_t launch_chain_product(int prec, const void *Q, const void *L, void *C, int64_t ld,
-                                int64_t n, double *fro_part, hipStream_t s) {
-    hipError_t e = sq_dispatch(prec, Q, L, C, ld, n, 1, fro_part, s);
+                                int64_t n, double *fro_part, float *tail, hipStream_t s) {
+    hipError_t e = sq_dispatch(prec, Q, L, C, ld, n, 1, fro_part, tail, s);
     if (e != hipSuccess) return e;
     switch (prec) {
     case 0: return sym_diag_launch<double>(C, ld, s);

@@ -206,33 +206,39 @@ __device__ inline void stage_and_store_rows(Core &g, O *sC, F f, O *C, int64_t l
 
 // ---------------------------------------------------------------------------
 // 16-bit operand core fed by direct global->LDS loads (gfx950
-// global_load_lds_dwordx4): each wave instruction moves 64 x 16 bytes into
-// 1 KB of LDS at M0 + 16 * lane, so operands never pass through VGPRs.  LDS
-// rows are BK = 64 elements (128 B) with the 16-byte chunks XOR-swizzled by
+// buffer_load_dwordx4 ... lds): each wave instruction moves 64 x 16 bytes
+// into 1 KB of LDS, so operands never pass through VGPRs.  The two operand
+// panels are addressed through buffer resources (base = first row of the
+// panel, in SGPRs); per instruction the wave-uniform part of the offset (row
+// block, k-slice) is a scalar offset and the per-lane part one of two VGPR
+// offsets, so the loads need no 64-bit address arithmetic.  LDS rows are
+// BK = 64 elements (128 B) with the 16-byte chunks XOR-swizzled by
 // (row >> 1) & 7, which keeps the 16 lanes that an ds_read_b128 serves per
-// cycle on distinct banks for the 32-row MFMA fragments.  Two stages: the
-// loads of k-tile t+1 are issued before the MFMAs of tile t; the fragments
-// of the next 16-wide k-step are read while the current ones are consumed.
-// The loads are issued from inline assembly because the compiler cannot tell
-// the target stage from the one being read and would otherwise wait for
-// every outstanding load before each LDS read.
+// cycle on distinct banks for the 32-row MFMA fragments.
+//
+// Pipeline (two LDS stages): the fragments of k-step q + 1 are read while
+// the MFMAs of k-step q run (sched_group_barrier interleaves one LDS read
+// with the MFMAs that fit beside it); before the last k-step of a stage
+// every wave waits for the next stage's loads and meets the others at a
+// barrier, then reads the next stage's first fragments beside the last
+// k-step's MFMAs and issues the loads of the stage after next into the buffer
+// just released.  The loop body is uniform; the last stage is peeled.
 
-typedef __attribute__((address_space(3))) char lds_char;
+typedef __attribute__((address_space(3))) void lds_void;
 
-__device__ inline uint32_t lds_offset(const void *p) {
-    return (uint32_t)(uintptr_t)(const lds_char *)p;
+template <int N> __device__ inline void wait_vmcnt() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
 }
 
-// 16 bytes per lane from src into LDS at m0base + 16 * lane.  M0 is set in
-// the same statement (one wait state before the load, as the ISA requires).
-__device__ inline void lds_dma16(const void *src, uint32_t m0base) {
-    asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
-                 :
-                 : "v"(src), "s"(__builtin_amdgcn_readfirstlane(m0base))
-                 : "memory", "m0");
+// Workgroup barrier without a memory fence (the loads into LDS are waited
+// for explicitly); the empty asm statements keep the compiler from moving
+// memory accesses across it.
+__device__ inline void lds_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
 }
-
-__device__ inline void wait_vmem_all() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 template <class Mf, int BM, int BN, int WM, int WN>
 struct DmaCore {
@@ -253,61 +259,75 @@ struct DmaCore {
     static constexpr int WTM = BM / WM / Mf::M, WTN = BN / WN / Mf::M;
     static constexpr int AI = BM / RPI / NW, BI = BN / RPI / NW;
     static constexpr int NKK = BK / Mf::KI;
+    static constexpr int NF = WTM + WTN;          // fragment reads per k-step
+    static constexpr int NM = WTM * WTN;          // MFMAs per k-step
     static_assert(AI * RPI * NW == BM && BI * RPI * NW == BN, "rows per wave");
+    static_assert(NKK == 4, "four k-steps per stage");
 
     AccV acc[WTM][WTN];
 
     __device__ static inline int swz(int c, int row) { return c ^ ((row >> 1) & 7); }
 
-    __device__ inline void issue(uint32_t stage, const T *A, int64_t lda, const T *B, int64_t ldb,
-                                 int64_t m0, int64_t n0, int64_t k0) {
-        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-        const int rl = lane / CPR, sl = lane % CPR;
+    // Loads of one 64-wide k-slice (element offset k0) of both panels into
+    // the LDS stage at byte offset `stage`.  Row r of a panel lies at byte
+    // r * ld * 2 of its resource; rows of one instruction start at a multiple
+    // of 8, so their swizzle depends only on the parity of the row block.
+    __device__ inline void issue(uint32_t stage, __amdgpu_buffer_rsrc_t ra, __amdgpu_buffer_rsrc_t rb,
+                                 int64_t lda, int64_t ldb, int64_t k0, int w, const uint32_t *voa,
+                                 const uint32_t *vob) {
 #pragma unroll
         for (int q = 0; q < AI; ++q) {
-            const int row0 = (w * AI + q) * RPI, row = row0 + rl;
-            lds_dma16(A + (m0 + row) * lda + k0 + swz(sl, row) * CE, stage + row0 * ROWB);
+            const int blk = w * AI + q, row0 = blk * RPI;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                ra, (lds_void *)(uintptr_t)(stage + row0 * ROWB), 16, voa[blk & 1],
+                (uint32_t)((int64_t)row0 * lda * 2 + k0 * 2), 0, 0);
         }
 #pragma unroll
         for (int q = 0; q < BI; ++q) {
-            const int row0 = (w * BI + q) * RPI, row = row0 + rl;
-            lds_dma16(B + (n0 + row) * ldb + k0 + swz(sl, row) * CE, stage + (BM + row0) * ROWB);
+            const int blk = w * BI + q, row0 = blk * RPI;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                rb, (lds_void *)(uintptr_t)(stage + (BM + row0) * ROWB), 16, vob[blk & 1],
+                (uint32_t)((int64_t)row0 * ldb * 2 + k0 * 2), 0, 0);
         }
     }
 
-    __device__ inline void load_frags(const char *sA, const char *sB, int kk, Frag *a, Frag *b) {
+    __device__ inline void load_frags(const char *s, int kk, Frag *f) {
         const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
         const int wm = wid % WM, wn = wid / WM;
         const int ch = (kk + Mf::E * (lane / Mf::M)) / CE;
+        const char *sA = s, *sB = s + BM * ROWB;
 #pragma unroll
         for (int i = 0; i < WTM; ++i) {
             const int row = wm * WTM * Mf::M + i * Mf::M + lane % Mf::M;
-            a[i] = *(const Frag *)(sA + row * ROWB + 16 * swz(ch, row));
+            f[i] = *(const Frag *)(sA + row * ROWB + 16 * swz(ch, row));
         }
 #pragma unroll
         for (int j = 0; j < WTN; ++j) {
             const int row = wn * WTN * Mf::M + j * Mf::M + lane % Mf::M;
-            b[j] = *(const Frag *)(sB + row * ROWB + 16 * swz(ch, row));
+            f[WTM + j] = *(const Frag *)(sB + row * ROWB + 16 * swz(ch, row));
         }
     }
 
-    __device__ inline void compute(const char *s) {
-        const char *sA = s, *sB = s + BM * ROWB;
-        Frag a[2][WTM], b[2][WTN];
-        load_frags(sA, sB, 0, a[0], b[0]);
+    __device__ inline void mmas(const Frag *f) {
 #pragma unroll
-        for (int q = 0; q < NKK; ++q) {
-            if (q + 1 < NKK) load_frags(sA, sB, (q + 1) * Mf::KI, a[(q + 1) & 1], b[(q + 1) & 1]);
+        for (int i = 0; i < WTM; ++i)
 #pragma unroll
-            for (int i = 0; i < WTM; ++i)
-#pragma unroll
-                for (int j = 0; j < WTN; ++j)
-                    acc[i][j] = Mf::mma(a[q & 1][i], b[q & 1][j], acc[i][j]);
-        }
+            for (int j = 0; j < WTN; ++j) acc[i][j] = Mf::mma(f[i], f[WTM + j], acc[i][j]);
     }
 
-    // Full K loop (K a multiple of 64; rows m0.. and n0.. inside the
-    // allocations).  smem holds SMEM bytes.
+    // Scheduling order of one k-step: the NF fragment reads spread evenly
+    // between its NM MFMAs.
+    template <int I = 0> __device__ static inline void interleave() {
+        constexpr int G = NF > NM ? NF : NM;
+        constexpr int nd = (I + 1) * NF / G - I * NF / G;
+        constexpr int nm = (I + 1) * NM / G - I * NM / G;
+        if constexpr (nd > 0) __builtin_amdgcn_sched_group_barrier(0x100, nd, 0);
+        if constexpr (nm > 0) __builtin_amdgcn_sched_group_barrier(0x008, nm, 0);
+        if constexpr (I + 1 < G) interleave<I + 1>();
+    }
+
+    // Full K loop (K a multiple of 64; rows m0.. and n0.. of the operands
+    // inside the allocations).  smem holds SMEM bytes.
     __device__ inline void run(const T *A, int64_t lda, const T *B, int64_t ldb, int64_t m0,
                                int64_t n0, int64_t K, void *smem_v) {
         char *smem = (char *)smem_v;
@@ -319,17 +339,56 @@ struct DmaCore {
                 for (int r = 0; r < Mf::R; ++r) acc[i][j][r] = 0;
         const int nk = (int)(K / BK);
         if (nk == 0) return;
-        const uint32_t s0 = lds_offset(smem);
-        issue(s0, A, lda, B, ldb, m0, n0, 0);
-        wait_vmem_all();
-        __syncthreads();
-        for (int kt = 0; kt < nk; ++kt) {
-            if (kt + 1 < nk)
-                issue(s0 + ((kt + 1) & 1) * STAGE, A, lda, B, ldb, m0, n0, (int64_t)(kt + 1) * BK);
-            compute(smem + (kt & 1) * STAGE);
-            wait_vmem_all();
-            __syncthreads();
+        const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        const uint32_t s0 = (uint32_t)(uintptr_t)(lds_void *)smem;
+        __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(A + m0 * lda), 0, (int)(BM * lda * 2), 0x00020000);
+        __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(B + n0 * ldb), 0, (int)(BN * ldb * 2), 0x00020000);
+        uint32_t voa[2], vob[2];
+        {
+            const int lane = threadIdx.x & 63, rl = lane / CPR, sl = lane % CPR;
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                const int c = 16 * (sl ^ (((rl >> 1) + 4 * p) & 7));
+                voa[p] = (uint32_t)(rl * lda * 2 + c);
+                vob[p] = (uint32_t)(rl * ldb * 2 + c);
+            }
         }
+        issue(s0, ra, rb, lda, ldb, 0, w, voa, vob);
+        if (nk > 1) {
+            issue(s0 + STAGE, ra, rb, lda, ldb, BK, w, voa, vob);
+            wait_vmcnt<AI + BI>();
+        } else {
+            wait_vmcnt<0>();
+        }
+        lds_barrier();
+        Frag f[2][NF];
+        load_frags(smem, 0, f[0]);
+        for (int kt = 0; kt < nk - 1; ++kt) {
+            const char *cur = smem + (kt & 1) * STAGE;
+#pragma unroll
+            for (int q = 0; q < NKK - 1; ++q) {
+                load_frags(cur, (q + 1) * Mf::KI, f[(q + 1) & 1]);
+                mmas(f[q & 1]);
+                interleave();
+            }
+            wait_vmcnt<0>();      // stage kt + 1, issued one stage ago, has landed
+            lds_barrier();        // ... for every wave, and nobody reads stage kt any more
+            load_frags(smem + ((kt + 1) & 1) * STAGE, 0, f[0]);
+            mmas(f[1]);
+            interleave();
+            if (kt + 2 < nk) issue(s0 + (kt & 1) * STAGE, ra, rb, lda, ldb, (int64_t)(kt + 2) * BK, w, voa, vob);
+        }
+        const char *cur = smem + ((nk - 1) & 1) * STAGE;
+#pragma unroll
+        for (int q = 0; q < NKK - 1; ++q) {
+            load_frags(cur, (q + 1) * Mf::KI, f[(q + 1) & 1]);
+            mmas(f[q & 1]);
+            interleave();
+        }
+        mmas(f[1]);
+        lds_barrier();
     }
 
     __device__ static inline int row_of(int i, int r) {

@@ -110,11 +110,15 @@ int square_tiles(int prec, int64_t ld);   // number of partial norms written
 hipError_t launch_normalize_rows(int prec, const double *Wp, int64_t ld, int64_t n, int64_t row0,
                                  int64_t rows, const double *dmn, const double *u, int lazy,
                                  void *S0, double *fro_part, double *fro64_part, hipStream_t s);
+// Bytes of the FP32 partial tiles that a 16-bit squaring of an n-node level
+// uses for its last, partial round of workgroups (split over k); 0 if none.
+size_t square_tail_bytes(int prec, int64_t ld, int64_t n);
+// tail: square_tail_bytes() of scratch (nullptr: no split).
 hipError_t launch_square(int prec, const void *S, void *S2, int64_t ld, int64_t n,
-                         double *fro_part, hipStream_t s);
+                         double *fro_part, float *tail, hipStream_t s);
 // C = Q + L + Q L for commuting symmetric Q, L (levels' storage scale).
 hipError_t launch_chain_product(int prec, const void *Q, const void *L, void *C, int64_t ld,
-                                int64_t n, double *fro_part, hipStream_t s);
+                                int64_t n, double *fro_part, float *tail, hipStream_t s);
 // accumulate: V64 += S~ Vin (else V64 = S~ Vin); Vout = V64 rounded.
 // inv_vs != nullptr marks the last level: X += dm * V * (*inv_vs).  P is the
 // split-K partial buffer (apply_splits() x kpad x ld floats; unused for FP64).
