@@ -158,8 +158,11 @@ typedef struct {
 /* ---- context --------------------------------------------------------- */
 
 /* Create a context on HIP device `device` using HIP stream `stream` (a
- * hipStream_t; NULL = the default stream).  Loads nothing, allocates no
- * device memory. */
+ * hipStream_t; NULL = the default stream).  Allocates no device memory; takes
+ * a 4 KiB pinned host buffer for read-backs, and on the first context of a
+ * device resolves that device's address of the fixed scratch array of
+ * cdl_anomaly_scores_noalloc (with the device made current for the call,
+ * the caller's current device restored). */
 cdl_status cdl_ctx_create(int device, void *stream, cdl_ctx **out);
 cdl_status cdl_ctx_destroy(cdl_ctx *ctx);
 cdl_status cdl_ctx_set_stream(cdl_ctx *ctx, void *stream);
@@ -469,6 +472,31 @@ cdl_status cdl_anomaly_scores(cdl_ctx *ctx, const double *Z0, const double *W0,
                               const int32_t *map0, const int32_t *map1, int64_t m,
                               cdl_score_mode mode, double *F, int32_t top_k,
                               int32_t *top_idx, void *ws, size_t ws_bytes);
+
+/* cdl_anomaly_scores without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Arguments, results and errors as for
+ * cdl_anomaly_scores; the workspace is a fixed 160 MiB array in device memory
+ * that the library holds on every device it runs on until the process ends
+ * (enough for m = 16384 common nodes at k = 256; the bytes needed are
+ * cdl_workspace_bytes' score size plus 256).  Larger m, k: CDL_E_WORKSPACE,
+ * nothing enqueued.  The call allocates and frees nothing (device or pinned
+ * memory, events) and does not time its kernels.  Every byte the kernels
+ * read is written earlier in the same call, so the array's contents from an
+ * earlier call do not matter; but all calls on one device share the array,
+ * so calls that overlap on a device (other host threads, other streams not
+ * ordered with this one) race and give undefined results.  With maps, their
+ * entries are checked on the device and the stream is synchronised once
+ * (CDL_E_ARG for an entry out of range); without maps the call is
+ * asynchronous.  CDL_E_HIP if the device's scratch address could not be
+ * resolved when its first context was created. */
+cdl_status cdl_anomaly_scores_noalloc(cdl_ctx *ctx, const double *Z0, const double *W0,
+                                      const double *stats0, int64_t n0,
+                                      const double *Z1, const double *W1,
+                                      const double *stats1, int64_t n1, int64_t k,
+                                      const int32_t *map0, const int32_t *map1, int64_t m,
+                                      cdl_score_mode mode, double *F, int32_t top_k,
+                                      int32_t *top_idx);
 
 /* Edge-level anomalies (Background: the CAD edge score
  * dE_ab = omega_ab |c_0(a,b) - c_1(a,b)|, whose row sums are the node

@@ -110,6 +110,8 @@ def load():
                                      C.POINTER(SolveInfo)]),
         "cdl_anomaly_scores": (I, [P, P, P, P, i64, P, P, P, i64, i64, P, P, i64, I, P,
                                    C.c_int32, P, P, sz]),
+        "cdl_anomaly_scores_noalloc": (I, [P, P, P, P, i64, P, P, P, i64, i64, P, P, i64, I, P,
+                                           C.c_int32, P]),
         "cdl_edges_workspace_bytes": (I, [i64, i64, C.c_int32, C.POINTER(sz)]),
         "cdl_anomaly_edges": (I, [P, P, P, P, i64, P, P, P, i64, i64, P, P, i64, I, P,
                                   C.c_int32, P, P, P, P, sz]),

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -46,7 +47,41 @@ struct cdl_ctx {
     size_t stage_bytes = 0;
 };
 
+// Device scratch of cdl_anomaly_scores_noalloc: a file-scope array that
+// every device running the library holds once its code object is loaded
+// there.  Host code never uses its name as an address: each device's address
+// comes from hipGetSymbolAddress (resolved once per device by
+// cdl_ctx_create) and only that pointer reaches kernels.
+constexpr size_t kNoAllocScratchBytes = (size_t)160 << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
 namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+bool g_scratch_resolved[kMaxDevices];
+
+// Resolves `device`'s address of the scratch array with that device current
+// (the caller's current device is restored).  Failure leaves the pointer
+// null, which only the allocation-free entry point reports.
+void resolve_scratch(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (device < 0 || device >= kMaxDevices || g_scratch_resolved[device]) return;
+    int prev = -1;
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (hipSetDevice(device) == hipSuccess) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess) g_scratch_ptr[device] = p;
+    }
+    if (prev >= 0) (void)hipSetDevice(prev);
+    g_scratch_resolved[device] = true;
+}
+
+void *scratch_ptr(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return device >= 0 && device < kMaxDevices ? g_scratch_ptr[device] : nullptr;
+}
+
 hipEvent_t take_event(cdl_ctx *c) {
     if (!c->pool.empty()) {
         hipEvent_t e = c->pool.back();
@@ -64,6 +99,8 @@ bool timing_selected(const cdl_ctx *c, const char *nm) {
         if (s == nm) return true;
     return false;
 }
+
+constexpr size_t kStageInitBytes = 4096;
 
 // One device-to-host read: `bytes` from device `src` into host `dst`.
 struct HostRead {
@@ -535,6 +572,14 @@ cdl_status cdl_ctx_create(int device, void *stream, cdl_ctx **out) {
     if (!c) return CDL_E_HIP;
     c->device = device;
     c->stream = (hipStream_t)stream;
+    resolve_scratch(device);
+    // a first pinned staging buffer, so that small read-backs (the
+    // allocation-free entry point's flag) never allocate
+    void *p = nullptr;
+    if (hipHostMalloc(&p, kStageInitBytes, hipHostMallocDefault) == hipSuccess) {
+        c->stage = p;
+        c->stage_bytes = kStageInitBytes;
+    }
     *out = c;
     return CDL_OK;
 }
@@ -818,13 +863,13 @@ cdl_status cdl_chain_densify(cdl_ctx *ctx, int64_t n, void *chain, size_t chain_
     HIPCHK(hipSetDevice(ctx->device));
     auto slot = [&](int l) { return c.levels + c.level_bytes * l; };
     if (d >= 2) {
-        // Q_1 = L_0 + L_1 + L_0 L_1 into the scratch slot, then
-        // Q_{j} = Q_{j-1} + L_j + Q_{j-1} L_j alternating between the scratch
+        // Q_1 = L_0 + L_1 + L_0 L_1 into the spare slot, then
+        // Q_{j} = Q_{j-1} + L_j + Q_{j-1} L_j alternating between the spare
         // slot and slot 0 (free once L_0 is consumed); Q ends in slot 0.
-        char *scratch = slot(d), *cur = scratch;
-        { Timed t_(ctx, "chain_product"); HIPCHK(launch_chain_product(info->prec, slot(0), slot(1), scratch, ld, n, c.fro, c.tail, s)); }
+        char *spare = slot(d), *cur = spare;
+        { Timed t_(ctx, "chain_product"); HIPCHK(launch_chain_product(info->prec, slot(0), slot(1), spare, ld, n, c.fro, c.tail, s)); }
         for (int j = 2; j < d; ++j) {
-            char *dst = cur == scratch ? slot(0) : scratch;
+            char *dst = cur == spare ? slot(0) : spare;
             { Timed t_(ctx, "chain_product"); HIPCHK(launch_chain_product(info->prec, cur, slot(j), dst, ld, n, c.fro, c.tail, s)); }
             cur = dst;
         }
@@ -1307,22 +1352,63 @@ static cdl_status check_map(cdl_ctx *ctx, const int32_t *map, int64_t m, int64_t
     return CDL_OK;
 }
 
+// Argument checks shared by both score entry points (everything but the
+// workspace and the map entries).
+static cdl_status check_scores(cdl_ctx *ctx, const double *Z0, const double *W0,
+                               const double *stats0, int64_t n0, const double *Z1,
+                               const double *W1, const double *stats1, int64_t n1, int64_t k,
+                               const int32_t *map0, const int32_t *map1, int64_t m,
+                               cdl_score_mode mode, double *F, int32_t top_k,
+                               int32_t *top_idx) {
+    if (!ctx) return CDL_E_ARG;
+    if (n0 < 2 || n1 < 2 || m < 1 || m > std::min(n0, n1) || k < 1)
+        return fail(ctx, CDL_E_ARG, "bad sizes");
+    if (!Z0 || !Z1 || !stats0 || !stats1 || !F) return fail(ctx, CDL_E_ARG, "null pointer");
+    if (mode != CDL_SCORE_UNWEIGHTED && mode != CDL_SCORE_DELTA_A) return fail(ctx, CDL_E_ARG, "bad mode");
+    if (mode == CDL_SCORE_DELTA_A && (!W0 || !W1)) return fail(ctx, CDL_E_ARG, "weighted mode needs W0, W1");
+    if (top_k < 0 || top_k > CDL_MAX_TOPK || top_k > m || (top_k > 0 && !top_idx))
+        return fail(ctx, CDL_E_ARG, "bad top_k");
+    if (!aligned(Z0, 8) || !aligned(Z1, 8)) return fail(ctx, CDL_E_ARG, "misaligned pointer");
+    if ((map0 == nullptr) != (map1 == nullptr)) return fail(ctx, CDL_E_ARG, "give both maps or neither");
+    return CDL_OK;
+}
+
+// The score kernels over workspace `ws` (plan_score layout); `timed`: bracket
+// them with the context's timing events.
+static cdl_status score_enqueue(cdl_ctx *ctx, bool timed, const double *Z0, const double *W0,
+                                const double *stats0, int64_t n0, const double *Z1,
+                                const double *W1, const double *stats1, int64_t n1, int64_t k,
+                                const int32_t *map0, const int32_t *map1, int64_t m,
+                                cdl_score_mode mode, double *F, int32_t top_k, int32_t *top_idx,
+                                void *ws) {
+    Arena a(ws);
+    ScoreWs w = plan_score(a, m, k);
+    const int64_t mp = pad_n(m), kp = pad_k(k);
+    hipStream_t s = ctx->stream;
+    auto scope = [&](const char *nm, auto &&fn) -> hipError_t {
+        if (!timed) return fn();
+        Timed t_(ctx, nm);
+        return fn();
+    };
+    HIPCHK(scope("build_zhat", [&] { return launch_build_zhat(Z0, Z1, map0, map1, m, mp, k, kp, stats0, stats1, w.Zh, w.Zhe, w.sq, s); }));
+    HIPCHK(scope("score", [&] { return launch_score(w.Zh, w.Zhe, kp, w.sq, m, mp, W0, pad_n(n0), W1, pad_n(n1), map0, map1,
+                                                    mode == CDL_SCORE_DELTA_A, w.part, nullptr, s); }));
+    HIPCHK(scope("score_reduce", [&] { return launch_score_reduce(w.part, score_tiles_1d(mp), m, mp, F, s); }));
+    if (top_k > 0) HIPCHK(scope("topk", [&] { return launch_topk(F, m, top_k, w.topk, top_idx, s); }));
+    return CDL_OK;
+}
+
 cdl_status cdl_anomaly_scores(cdl_ctx *ctx, const double *Z0, const double *W0,
                               const double *stats0, int64_t n0, const double *Z1,
                               const double *W1, const double *stats1, int64_t n1, int64_t k,
                               const int32_t *map0, const int32_t *map1, int64_t m,
                               cdl_score_mode mode, double *F, int32_t top_k, int32_t *top_idx,
                               void *ws, size_t ws_bytes) {
-    if (!ctx) return CDL_E_ARG;
-    if (n0 < 2 || n1 < 2 || m < 1 || m > std::min(n0, n1) || k < 1)
-        return fail(ctx, CDL_E_ARG, "bad sizes");
-    if (!Z0 || !Z1 || !stats0 || !stats1 || !F || !ws) return fail(ctx, CDL_E_ARG, "null pointer");
-    if (mode != CDL_SCORE_UNWEIGHTED && mode != CDL_SCORE_DELTA_A) return fail(ctx, CDL_E_ARG, "bad mode");
-    if (mode == CDL_SCORE_DELTA_A && (!W0 || !W1)) return fail(ctx, CDL_E_ARG, "weighted mode needs W0, W1");
-    if (top_k < 0 || top_k > CDL_MAX_TOPK || top_k > m || (top_k > 0 && !top_idx))
-        return fail(ctx, CDL_E_ARG, "bad top_k");
-    if (!aligned(ws, kAlign) || !aligned(Z0, 8) || !aligned(Z1, 8)) return fail(ctx, CDL_E_ARG, "misaligned pointer");
-    if ((map0 == nullptr) != (map1 == nullptr)) return fail(ctx, CDL_E_ARG, "give both maps or neither");
+    cdl_status st0 = check_scores(ctx, Z0, W0, stats0, n0, Z1, W1, stats1, n1, k, map0, map1, m,
+                                  mode, F, top_k, top_idx);
+    if (st0 != CDL_OK) return st0;
+    if (!ws) return fail(ctx, CDL_E_ARG, "null pointer");
+    if (!aligned(ws, kAlign)) return fail(ctx, CDL_E_ARG, "misaligned pointer");
     Arena need(nullptr);
     plan_score(need, m, k);
     if (ws_bytes < need.off) return fail(ctx, CDL_E_WORKSPACE, "score workspace too small");
@@ -1331,16 +1417,44 @@ cdl_status cdl_anomaly_scores(cdl_ctx *ctx, const double *Z0, const double *W0,
     if (st != CDL_OK) return st;
     st = check_map(ctx, map1, m, n1);
     if (st != CDL_OK) return st;
-    Arena a(ws);
-    ScoreWs w = plan_score(a, m, k);
-    const int64_t mp = pad_n(m), kp = pad_k(k);
-    hipStream_t s = ctx->stream;
-    { Timed t_(ctx, "build_zhat"); HIPCHK(launch_build_zhat(Z0, Z1, map0, map1, m, mp, k, kp, stats0, stats1, w.Zh, w.Zhe, w.sq, s)); }
-    { Timed t_(ctx, "score"); HIPCHK(launch_score(w.Zh, w.Zhe, kp, w.sq, m, mp, W0, pad_n(n0), W1, pad_n(n1), map0, map1,
-                        mode == CDL_SCORE_DELTA_A, w.part, nullptr, s)); }
-    { Timed t_(ctx, "score_reduce"); HIPCHK(launch_score_reduce(w.part, score_tiles_1d(mp), m, mp, F, s)); }
-    if (top_k > 0) { Timed t_(ctx, "topk"); HIPCHK(launch_topk(F, m, top_k, w.topk, top_idx, s)); }
-    return CDL_OK;
+    return score_enqueue(ctx, true, Z0, W0, stats0, n0, Z1, W1, stats1, n1, k, map0, map1, m, mode,
+                         F, top_k, top_idx, ws);
+}
+
+cdl_status cdl_anomaly_scores_noalloc(cdl_ctx *ctx, const double *Z0, const double *W0,
+                                      const double *stats0, int64_t n0, const double *Z1,
+                                      const double *W1, const double *stats1, int64_t n1,
+                                      int64_t k, const int32_t *map0, const int32_t *map1,
+                                      int64_t m, cdl_score_mode mode, double *F, int32_t top_k,
+                                      int32_t *top_idx) {
+    cdl_status st = check_scores(ctx, Z0, W0, stats0, n0, Z1, W1, stats1, n1, k, map0, map1, m,
+                                 mode, F, top_k, top_idx);
+    if (st != CDL_OK) return st;
+    Arena need(nullptr);
+    plan_score(need, m, k);
+    int *flag = (int *)nullptr;
+    const size_t bytes = need.off + kAlign;   // the workspace, then the map flag
+    if (bytes > kNoAllocScratchBytes) {
+        char buf[200];
+        std::snprintf(buf, sizeof(buf), "m = %lld, k = %lld need %zu bytes of scratch; the fixed "
+                      "device scratch holds %zu", (long long)m, (long long)k, bytes,
+                      kNoAllocScratchBytes);
+        return fail(ctx, CDL_E_WORKSPACE, buf);
+    }
+    char *ws = (char *)scratch_ptr(ctx->device);
+    if (!ws) return fail(ctx, CDL_E_HIP, "the device scratch of this device has no address");
+    if (map0 && (!ctx->stage || ctx->stage_bytes < kAlign))
+        return fail(ctx, CDL_E_HIP, "no pinned staging buffer for the map check");
+    flag = (int *)(ws + need.off);
+    HIPCHK(hipSetDevice(ctx->device));
+    if (map0) {
+        int bad = 0;
+        HIPCHK(launch_check_maps(map0, map1, m, n0, n1, flag, ctx->stream));
+        HIPCHK(read_to_host(ctx, ctx->stream, {{&bad, flag, sizeof(int)}}));
+        if (bad) return fail(ctx, CDL_E_ARG, "map entry out of range");
+    }
+    return score_enqueue(ctx, false, Z0, W0, stats0, n0, Z1, W1, stats1, n1, k, map0, map1, m,
+                         mode, F, top_k, top_idx, ws);
 }
 
 cdl_status cdl_edges_workspace_bytes(int64_t m, int64_t k, int32_t top_k, size_t *bytes) {

@@ -197,6 +197,9 @@ hipError_t launch_build_zhat(const double *Z0, const double *Z1, const int32_t *
                              double *Zh, double *Zhe, double *sq, hipStream_t s);
 // Partial-sum slots of mpad entries each (mpad / 128 + mpad / 256).
 int score_tiles_1d(int64_t mpad);
+// *flag = 1 if an entry of map0 (map1) is outside [0, n0) ([0, n1)), else 0.
+hipError_t launch_check_maps(const int32_t *map0, const int32_t *map1, int64_t m, int64_t n0,
+                             int64_t n1, int *flag, hipStream_t s);
 // Score tiles: 256 x 128 over the upper triangle (rect_upper_tiles).
 // tmax: per-tile maximum edge score (a < b), score_tiles_2d(mpad) entries,
 // or nullptr.

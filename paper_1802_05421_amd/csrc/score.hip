@@ -273,6 +273,26 @@ hipError_t launch_edge_collect(const double *Zh, const double *Zhe, int64_t kpad
     return hipGetLastError();
 }
 
+// flag = 1 if some entry of map0 lies outside [0, n0) or of map1 outside
+// [0, n1), else 0.  One workgroup; the flag needs no initial value.
+__global__ __launch_bounds__(256) void k_check_maps(const int32_t *map0, const int32_t *map1,
+                                                    int64_t m, int64_t n0, int64_t n1,
+                                                    int *flag) {
+    int bad = 0;
+    for (int64_t c = threadIdx.x; c < m; c += blockDim.x) {
+        const int32_t a = map0[c], b = map1[c];
+        bad |= (a < 0 || a >= n0 || b < 0 || b >= n1);
+    }
+    bad = __syncthreads_or(bad);
+    if (threadIdx.x == 0) *flag = bad ? 1 : 0;
+}
+
+hipError_t launch_check_maps(const int32_t *map0, const int32_t *map1, int64_t m, int64_t n0,
+                             int64_t n1, int *flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_check_maps, dim3(1), dim3(256), 0, s, map0, map1, m, n0, n1, flag);
+    return hipGetLastError();
+}
+
 // F_a = its row partials over the column blocks J >= 2 (a / 256), then its
 // column partials over the row blocks I <= (a / 128) / 2: exactly the slots
 // the score tiles wrote, summed in a fixed order.
