@@ -210,6 +210,57 @@ cdl_status cdl_timing_read(cdl_ctx *ctx, int32_t idx, const char **name, int64_t
 /* Syncs.  Clears the totals. */
 cdl_status cdl_timing_reset(cdl_ctx *ctx);
 
+/* ---- launch-configuration tuning ---------------------------------------- */
+
+/* Three kernel families have several correct launch configurations, which
+ * give the same results up to the rounding order of their sums:
+ *   "square"    16-bit levels (cdl_build_chain, cdl_chain_densify): 256 x 256
+ *               tiles on 8 waves (choices 0, 1) or 4 waves (2, 3), the last
+ *               partial round of workgroups split over the reduction
+ *               (0, 2) or not (1, 3); other level types: one choice;
+ *   "apply"     the chain application (cdl_solve_embedding*), BF16/FP16/FP32
+ *               levels: the split-K count, the default (0), half (1) or
+ *               twice (2) it; FP64 levels: one choice;
+ *   "residual"  the FP64 residual product W X of the solves: split-K count,
+ *               choices as for "apply".
+ * A table per process keeps, per GPU architecture name, family, element
+ * type and padded shape (cdl_ld(n), and the padded k for apply/residual),
+ * the measured milliseconds of every candidate and the fastest one's index;
+ * calls use the table's choice, else choice 0.  The environment variable
+ * CDL_AUTOTUNE_CACHE names a JSON file that is merged into the table on first
+ * use and rewritten after every new entry.  The chain-depth cost model of
+ * cdl_build_chain and of the solves uses the measured times of the chosen
+ * configurations when the table holds the shape. */
+
+/* mode 1: later calls on this context time every candidate of a family the
+ * first time they meet a shape the table does not hold (on the call's own
+ * data; every candidate leaves a complete result; syncs once per candidate)
+ * and record them; 0 (default): use the table only.  Calls of
+ * cdl_score_sequence never tune.  CDL_E_ARG for other modes. */
+cdl_status cdl_ctx_set_autotune(cdl_ctx *ctx, int mode);
+/* Pins family ("square", "apply", "residual") to candidate `choice` on this
+ * context (choice < 0 releases it; a choice beyond the family's candidates
+ * for some shape falls back to the table there).  CDL_E_ARG for an unknown
+ * family. */
+cdl_status cdl_ctx_force_choice(cdl_ctx *ctx, const char *family, int choice);
+/* The table's entry for family, element type and shape (n nodes, k columns;
+ * k is ignored for "square") on device `device`'s architecture (device < 0:
+ * the architecture name "none").  choice, candidates, ms (the chosen
+ * candidate's time) may be NULL.  CDL_E_UNSUPPORTED: no entry;
+ * CDL_E_ARG: invalid arguments. */
+cdl_status cdl_autotune_lookup(int device, const char *family, cdl_prec prec, int64_t n,
+                               int64_t k, int *choice, int *candidates, double *ms);
+/* Merge a JSON table file into the table / write the whole table / empty it
+ * (also forgetting CDL_AUTOTUNE_CACHE's file for the rest of the process).
+ * CDL_E_ARG for an unreadable or malformed file or an unwritable path.
+ * File format: {"format": "caddelag-autotune-1", "entries": [{"arch": name,
+ * "key": "square/bf16/ld16384", "choice": i, "ms": [t0, t1, ...]}, ...]}. */
+cdl_status cdl_autotune_load(const char *path);
+cdl_status cdl_autotune_save(const char *path);
+cdl_status cdl_autotune_clear(void);
+/* Number of entries in the table. */
+int32_t cdl_autotune_entries(void);
+
 /* ---- sizes ------------------------------------------------------------- */
 
 /* Padded leading dimension (and row count) of the library's n x n layout. */

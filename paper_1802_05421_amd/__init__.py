@@ -18,9 +18,15 @@ from .api import (  # noqa: E402,F401
     Graph,
     SeqParams,
     anomaly_edges,
+    autotune_clear,
+    autotune_entries,
+    autotune_load,
+    autotune_lookup,
+    autotune_save,
     anomaly_scores,
     build_chain,
     chain_densify,
+    force_choice,
     build_graph,
     check_graph,
     graph_from_weights,
@@ -31,6 +37,7 @@ from .api import (  # noqa: E402,F401
     level_scale_for,
     score_sequence,
     sequence_workspace_bytes,
+    set_autotune,
     set_select,
     set_solve_depth,
     set_timing,

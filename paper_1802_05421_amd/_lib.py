@@ -87,6 +87,14 @@ def load():
         "cdl_timing_read": (I, [P, C.c_int32, C.POINTER(C.c_char_p), C.POINTER(i64),
                                 C.POINTER(d)]),
         "cdl_timing_reset": (I, [P]),
+        "cdl_ctx_set_autotune": (I, [P, I]),
+        "cdl_ctx_force_choice": (I, [P, C.c_char_p, I]),
+        "cdl_autotune_lookup": (I, [I, C.c_char_p, I, i64, i64, C.POINTER(I), C.POINTER(I),
+                                    C.POINTER(d)]),
+        "cdl_autotune_load": (I, [C.c_char_p]),
+        "cdl_autotune_save": (I, [C.c_char_p]),
+        "cdl_autotune_clear": (I, []),
+        "cdl_autotune_entries": (C.c_int32, []),
         "cdl_ld": (i64, [i64]),
         "cdl_k_rp": (I, [i64, d, C.POINTER(i64)]),
         "cdl_level_scale": (I, [i64, I, C.POINTER(d)]),

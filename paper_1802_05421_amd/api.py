@@ -93,6 +93,46 @@ def timing(device: int = 0, reset: bool = False) -> dict:
     return out
 
 
+def set_autotune(enable: bool, device: int = 0):
+    """Time every launch candidate of a tuned kernel family on first use of a
+    shape (cdl_ctx_set_autotune)."""
+    ctx = context(device)
+    _check(_lib().cdl_ctx_set_autotune(ctx.h, 1 if enable else 0), ctx.h)
+
+
+def force_choice(family: str, choice: int, device: int = 0):
+    """Pin a tuned kernel family to one candidate on this stream's context (-1 releases)."""
+    ctx = context(device)
+    _check(_lib().cdl_ctx_force_choice(ctx.h, family.encode(), int(choice)), ctx.h)
+
+
+def autotune_lookup(family: str, prec: str, n: int, k: int = 0, device: int = 0):
+    """(choice, candidates, ms) of the tuning table's entry, or None."""
+    ch, nc, ms = C.c_int(), C.c_int(), C.c_double()
+    st = _lib().cdl_autotune_lookup(device, family.encode(), L.PREC[prec], int(n), int(k),
+                                    C.byref(ch), C.byref(nc), C.byref(ms))
+    if st == 8:
+        return None
+    _check(st)
+    return ch.value, nc.value, ms.value
+
+
+def autotune_save(path: str):
+    _check(_lib().cdl_autotune_save(path.encode()))
+
+
+def autotune_load(path: str):
+    _check(_lib().cdl_autotune_load(path.encode()))
+
+
+def autotune_clear():
+    _check(_lib().cdl_autotune_clear())
+
+
+def autotune_entries() -> int:
+    return int(_lib().cdl_autotune_entries())
+
+
 def context(device: int = 0) -> Context:
     """The library context for torch's current stream on `device`.
 

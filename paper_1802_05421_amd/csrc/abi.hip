@@ -15,6 +15,16 @@
 
 #include "caddelag.h"
 #include "kernels.h"
+#include "tune.h"
+
+using cdl::tune_arch;
+using cdl::tune_get;
+using cdl::tune_key;
+using cdl::tune_put;
+using cdl::tune_load;
+using cdl::tune_save;
+using cdl::tune_clear;
+using cdl::tune_entries;
 
 struct cdl_timer_rec {
     const char *name;
@@ -45,6 +55,11 @@ struct cdl_ctx {
     // into pageable memory is staged by the runtime one copy at a time.
     void *stage = nullptr;
     size_t stage_bytes = 0;
+    // Launch-configuration tuning: 1 = time every candidate of a kernel
+    // family the first time a shape is met (the process-wide table keeps the
+    // fastest); `forced` pins a family's candidate on this context.
+    int autotune = 0;
+    std::map<std::string, int> forced;
 };
 
 // Device scratch of cdl_anomaly_scores_noalloc: a file-scope array that
@@ -195,6 +210,39 @@ namespace {
 
 using namespace cdl;
 
+// Candidate of a tuned kernel family for one shape: the context's forced
+// one, else the table's choice, else 0 (*tune: the context tunes and the
+// table has no entry yet).
+int pick_choice(cdl_ctx *c, const char *family, int prec, int64_t ld, int64_t kp, int ncand,
+                bool allow_tune, bool *tune) {
+    *tune = false;
+    auto f = c->forced.find(family);
+    if (f != c->forced.end() && f->second >= 0 && f->second < ncand) return f->second;
+    if (ncand <= 1) return 0;
+    int ch = 0;
+    if (cdl::tune_get(cdl::tune_arch(c->device), cdl::tune_key(family, prec, ld, kp), &ch, nullptr,
+                      nullptr) && ch < ncand)
+        return ch;
+    *tune = allow_tune && c->autotune != 0;
+    return 0;
+}
+
+// Milliseconds of the launches of fn() on the context's stream (syncs).
+template <class F>
+hipError_t time_launch(cdl_ctx *c, F &&fn, double *ms) {
+    hipEvent_t a = take_event(c), b = take_event(c);
+    hipError_t e = (a && b) ? hipEventRecord(a, c->stream) : hipErrorOutOfMemory;
+    if (e == hipSuccess) e = fn();
+    if (e == hipSuccess) e = hipEventRecord(b, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+    if (a) c->pool.push_back(a);
+    if (b) c->pool.push_back(b);
+    *ms = t;
+    return e;
+}
+
 constexpr size_t kAlign = 256;
 size_t al(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -261,8 +309,9 @@ SolveWs plan_solve(Arena &a, int64_t n, int64_t k, int prec) {
     const int64_t ld = pad_n(n), kp = pad_k(k);
     const size_t panel = (size_t)kp * ld;
     SolveWs w;
-    w.part = a.take<char>(panel * std::max<size_t>(8 * (size_t)residual_splits(ld, kp, n),
-                                                   4 * (size_t)apply_splits(prec, ld, kp, n)));
+    // split-K partials for the largest candidate split counts
+    w.part = a.take<char>(panel * std::max<size_t>(8 * (size_t)residual_splits(ld, kp, n, 2),
+                                                   4 * (size_t)apply_splits(prec, ld, kp, n, 2)));
     w.Yt = a.take<double>(panel);
     w.Xt = a.take<double>(panel);
     w.Rt = a.take<double>(panel);
@@ -422,14 +471,30 @@ cdl_status graph_enqueue(cdl_ctx *ctx, const double *X, int64_t n, int64_t T, in
 // repetitions of the last stored level.  Stream-ordered, no host reads.
 cdl_status precondition_enqueue(cdl_ctx *ctx, int prec, int d, int D, const SolveWs &w,
                                 const ChainBuf &c, int64_t ld, int64_t n, int64_t kp,
-                                bool scaled, const double *inv_vs, double *Xdst) {
+                                bool scaled, const double *inv_vs, double *Xdst,
+                                bool allow_tune = true) {
     hipStream_t s = ctx->stream;
     if (scaled) { Timed t_(ctx, "prep_v"); HIPCHK(launch_prep_v2(prec, w.Rt, c.dm, ld, kp, w.scal + kp, w.V64, w.Vlo[0], s)); }
+    bool tune = false;
+    const int nc = prec == 0 ? 1 : 3;
+    int ch = pick_choice(ctx, "apply", prec, ld, kp, nc, allow_tune, &tune);
+    if (tune) {
+        // the split-K product alone for each candidate (its partials are
+        // scratch; the applications below recompute them)
+        std::vector<double> ms(nc);
+        for (int q = 0; q < nc; ++q)
+            HIPCHK(time_launch(ctx, [&] {
+                return launch_apply_gemm(prec, w.Vlo[0], c.levels, ld, n, kp,
+                                         apply_splits(prec, ld, kp, n, q), (float *)w.part, s);
+            }, &ms[q]));
+        ch = cdl::tune_put(cdl::tune_arch(ctx->device), cdl::tune_key("apply", prec, ld, kp), ms);
+    }
+    const int ns = apply_splits(prec, ld, kp, n, ch);
     int cur = 0;
     for (int l = 0; l < std::min(d, D); ++l) {
         const bool last = l + 1 == D;
         { Timed t_(ctx, "apply"); HIPCHK(launch_apply(prec, w.Vlo[cur], c.levels + c.level_bytes * l, w.Vlo[cur ^ 1],
-                            w.V64, ld, n, kp, Xdst, c.dm, last ? inv_vs : nullptr, (float *)w.part, 1, s)); }
+                            w.V64, ld, n, kp, Xdst, c.dm, last ? inv_vs : nullptr, (float *)w.part, 1, ns, s)); }
         cur ^= 1;
     }
     for (int l = d; l < D; ++l) {
@@ -438,7 +503,7 @@ cdl_status precondition_enqueue(cdl_ctx *ctx, int prec, int d, int D, const Solv
         for (int q = 0; q < m; ++q) {
             void *dst = w.Vlo[2 + (q & 1)];
             { Timed t_(ctx, "apply"); HIPCHK(launch_apply(prec, src, c.levels + c.level_bytes * (d - 1), dst, w.T64,
-                                ld, n, kp, Xdst, c.dm, nullptr, (float *)w.part, 0, s)); }
+                                ld, n, kp, Xdst, c.dm, nullptr, (float *)w.part, 0, ns, s)); }
             src = dst;
         }
         const bool last = l + 1 == D;
@@ -488,13 +553,43 @@ double apply_floor(int prec) {
 // Level applications for total depth D over d stored levels: the stored ones
 // once each, level l >= d as 2^(l-d+1) applications of the last stored level.
 int applies_for(int d, int D) { return D <= d ? D : d + (1 << (D - d + 1)) - 2; }
+// Kernel times of the depth model for n nodes, k columns and level type
+// prec: the tuner's measured times of the chosen configurations when its
+// table holds this exact shape (split-K products only: their reductions are
+// small), else estimates at fixed fractions of the peaks (the FP64 residual
+// at 3/4 of the FP64 MFMA peak, applications at half the level type's MFMA
+// peak or at the HBM rate, whichever is slower, squarings at half the peak).
+struct CostModel {
+    double t_res, t_ap, t_sq;
+    bool measured_res = false, measured_ap = false, measured_sq = false;
+};
+CostModel cost_model(int device, int prec, int64_t n, int64_t k) {
+    const double nn = (double)n, kk = (double)k;
+    CostModel m;
+    m.t_res = 2.0 * nn * nn * kk / (78.6e12 * 0.75);
+    m.t_ap = std::max(2.0 * nn * nn * kk / (peak_flops(prec) * 0.5), nn * nn * esize(prec) / 4.0e12);
+    m.t_sq = nn * nn * nn / (peak_flops(prec) * 0.5);
+    const std::string arch = tune_arch(device);
+    const int64_t ld = pad_n(n), kp = pad_k(k);
+    double ms = 0.0;
+    if (tune_get(arch, tune_key("residual", 0, ld, kp), nullptr, &ms, nullptr) && ms > 0.0) {
+        m.t_res = ms * 1e-3;
+        m.measured_res = true;
+    }
+    if (prec != 0 && tune_get(arch, tune_key("apply", prec, ld, kp), nullptr, &ms, nullptr) && ms > 0.0) {
+        m.t_ap = ms * 1e-3;
+        m.measured_ap = true;
+    }
+    if (tune_get(arch, tune_key("square", prec, ld, 0), nullptr, &ms, nullptr) && ms > 0.0) {
+        m.t_sq = ms * 1e-3;
+        m.measured_sq = true;
+    }
+    return m;
+}
+
 // Depth for the next iteration: minimise (iterations to gain `need`) x (FP64
 // residual + level applications), with contraction max(rho^(2^D), floor).
-int choose_depth(int prec, int64_t n, int64_t k, int d, double rho, double need) {
-    const double nn = (double)n, kk = (double)k;
-    const double t_res = 2.0 * nn * nn * kk / (78.6e12 * 0.75);
-    const double t_ap = std::max(2.0 * nn * nn * kk / (peak_flops(prec) * 0.5),
-                                 nn * nn * esize(prec) / 4.0e12);
+int choose_depth(int prec, int d, double rho, double need, const CostModel &m) {
     if (!(need < 1.0)) return d;
     const double r = std::min(std::max(rho, 1e-6), 0.999999);
     int best = d;
@@ -502,7 +597,7 @@ int choose_depth(int prec, int64_t n, int64_t k, int d, double rho, double need)
     for (int D = 1; D <= d + 3 && D <= 16; ++D) {
         const double c = std::max(std::pow(r, std::ldexp(1.0, D)), apply_floor(prec));
         const double it = iters_for(c, need);
-        const double cost = it * (t_res + applies_for(d, D) * t_ap);
+        const double cost = it * (m.t_res + applies_for(d, D) * m.t_ap);
         if (cost < best_cost * (1.0 - 1e-9)) {
             best_cost = cost;
             best = D;
@@ -513,32 +608,25 @@ int choose_depth(int prec, int64_t n, int64_t k, int d, double rho, double need)
 
 // Predicted time of one solve that must gain `need` with d stored levels,
 // using the best total depth per iteration (same model as choose_depth).
-double solve_cost(int prec, int64_t n, int64_t k, int d, double rho, double need) {
-    const double nn = (double)n, kk = (double)k;
-    const double t_res = 2.0 * nn * nn * kk / (78.6e12 * 0.75);
-    const double t_ap = std::max(2.0 * nn * nn * kk / (peak_flops(prec) * 0.5),
-                                 nn * nn * esize(prec) / 4.0e12);
+double solve_cost(int prec, int d, double rho, double need, const CostModel &m) {
     const double r = std::min(std::max(rho, 1e-6), 0.999999);
     double best = 1e300;
     for (int D = 1; D <= d + 3 && D <= 16; ++D) {
         const double c = std::max(std::pow(r, std::ldexp(1.0, D)), apply_floor(prec));
-        best = std::min(best, iters_for(c, need) * (t_res + applies_for(d, D) * t_ap));
+        best = std::min(best, iters_for(c, need) * (m.t_res + applies_for(d, D) * m.t_ap));
     }
     return best;
 }
 // Should the chain with levels 0..l (last Frobenius norm f, spectral estimate
-// rho) get level l+1?  Yes when one squaring (MFMA at half the peak of the
-// level type) plus the cheapest solve with l+2 stored levels is predicted to
-// beat the cheapest solve with l+1 (k = 256 columns, a 1e-8 residual target;
-// deeper levels can always be applied by repetition instead).
-bool model_wants_square(int prec, int64_t n, int l, double f, double rho) {
+// rho) get level l+1?  Yes when one squaring plus the cheapest solve with
+// l+2 stored levels is predicted to beat the cheapest solve with l+1 (model
+// times for k = 256 columns, a 1e-8 residual target; deeper levels can
+// always be applied by repetition instead).
+bool model_wants_square(int prec, int l, double f, double rho, const CostModel &m) {
     (void)f;
     if (!(rho < 1.0 - 1e-9)) return true;   // not contracting yet: keep testing
-    const double nn = (double)n;
-    const double t_sq = nn * nn * nn / (peak_flops(prec) * 0.5);
     const double need = 1e-8;
-    return t_sq + solve_cost(prec, n, 256, l + 2, rho, need) <
-           solve_cost(prec, n, 256, l + 1, rho, need);
+    return m.t_sq + solve_cost(prec, l + 2, rho, need, m) < solve_cost(prec, l + 1, rho, need, m);
 }
 
 } // namespace
@@ -665,6 +753,50 @@ cdl_status cdl_ctx_set_stream(cdl_ctx *ctx, void *stream) {
     return CDL_OK;
 }
 
+cdl_status cdl_ctx_set_autotune(cdl_ctx *ctx, int mode) {
+    if (!ctx || mode < 0 || mode > 1) return CDL_E_ARG;
+    ctx->autotune = mode;
+    return CDL_OK;
+}
+
+static bool tuned_family(const char *f) {
+    return f && (!std::strcmp(f, "square") || !std::strcmp(f, "apply") || !std::strcmp(f, "residual"));
+}
+
+cdl_status cdl_ctx_force_choice(cdl_ctx *ctx, const char *family, int choice) {
+    if (!ctx || !tuned_family(family)) return CDL_E_ARG;
+    if (choice < 0) ctx->forced.erase(family);
+    else ctx->forced[family] = choice;
+    return CDL_OK;
+}
+
+cdl_status cdl_autotune_lookup(int device, const char *family, cdl_prec prec, int64_t n, int64_t k,
+                               int *choice, int *candidates, double *ms) {
+    if (!tuned_family(family) || !valid_prec(prec) || n < 2 || n > (1 << 20)) return CDL_E_ARG;
+    const bool sq = !std::strcmp(family, "square");
+    if (!sq && k < 1) return CDL_E_ARG;
+    const std::string key = tune_key(family, prec, pad_n(n), sq ? 0 : pad_k(k));
+    if (!tune_get(tune_arch(device), key, choice, ms, candidates)) return CDL_E_UNSUPPORTED;
+    return CDL_OK;
+}
+
+cdl_status cdl_autotune_load(const char *path) {
+    if (!path) return CDL_E_ARG;
+    return tune_load(path, nullptr) ? CDL_OK : CDL_E_ARG;
+}
+
+cdl_status cdl_autotune_save(const char *path) {
+    if (!path) return CDL_E_ARG;
+    return tune_save(path, nullptr) ? CDL_OK : CDL_E_ARG;
+}
+
+cdl_status cdl_autotune_clear(void) {
+    tune_clear();
+    return CDL_OK;
+}
+
+int32_t cdl_autotune_entries(void) { return tune_entries(); }
+
 int64_t cdl_ld(int64_t n) { return n > 0 ? pad_n(n) : 0; }
 
 cdl_status cdl_k_rp(int64_t n, double eps_rp, int64_t *k) {
@@ -764,6 +896,29 @@ cdl_status cdl_graph_from_weights(cdl_ctx *ctx, const double *Win, int64_t n, in
 
 // ---- chain ---------------------------------------------------------------------
 
+// One squaring (or dense-chain product when A != B) with the tuned tile
+// variant; a tuning context times every variant first (each leaves a
+// complete, correct output).
+static cdl_status square_step(cdl_ctx *ctx, int prec, const void *A, const void *B, void *C,
+                              int64_t ld, int64_t n, const ChainBuf &c, bool allow_tune) {
+    const bool product = A != B;
+    bool tune = false;
+    const int nv = square_variants(prec);
+    int v = pick_choice(ctx, "square", prec, ld, 0, nv, allow_tune, &tune);
+    auto go = [&](int var) {
+        return product ? launch_chain_product(prec, A, B, C, ld, n, c.fro, c.tail, var, ctx->stream)
+                       : launch_square(prec, A, C, ld, n, c.fro, c.tail, var, ctx->stream);
+    };
+    if (tune) {
+        std::vector<double> ms(nv);
+        for (int q = 0; q < nv; ++q) HIPCHK(time_launch(ctx, [&] { return go(q); }, &ms[q]));
+        v = cdl::tune_put(cdl::tune_arch(ctx->device), cdl::tune_key("square", prec, ld, 0), ms);
+    }
+    Timed t_(ctx, product ? "chain_product" : "square");
+    HIPCHK(go(v));
+    return CDL_OK;
+}
+
 static double host_sum(const std::vector<double> &v) {
     double s = 0.0;
     for (double x : v) s += x;
@@ -787,6 +942,7 @@ cdl_status cdl_build_chain(cdl_ctx *ctx, const double *W, const double *deg, con
     ChainBuf c = plan_chain(a, n, prec, depth_max);
     const int64_t ld = pad_n(n);
     hipStream_t s = ctx->stream;
+    const CostModel cm = cost_model(ctx->device, prec, n, 256);
     HIPCHK(hipSetDevice(ctx->device));
     std::memset(info, 0, sizeof(*info));
     info->lazy = lazy ? 1 : 0;
@@ -812,11 +968,14 @@ cdl_status cdl_build_chain(cdl_ctx *ctx, const double *W, const double *deg, con
         else if (chain_eps > 0.0)
             more = l + 1 < depth_max && !(rho < 1.0 && f * f / (1.0 - rho) <= chain_eps);
         else
-            more = l + 1 < depth_max && model_wants_square(prec, n, l, f, rho);
+            more = l + 1 < depth_max && model_wants_square(prec, l, f, rho, cm);
         if (!more) break;
         const int ntl = square_tiles(prec, ld);
-        { Timed t_(ctx, "square"); HIPCHK(launch_square(prec, c.levels + c.level_bytes * l, c.levels + c.level_bytes * (l + 1),
-                             ld, n, c.fro, c.tail, s)); }
+        {
+            const cdl_status sq = square_step(ctx, prec, c.levels + c.level_bytes * l, c.levels + c.level_bytes * l,
+                                              c.levels + c.level_bytes * (l + 1), ld, n, c, true);
+            if (sq != CDL_OK) return sq;
+        }
         part.resize(ntl);
         HIPCHK(read_to_host(ctx, s, {{part.data(), c.fro, ntl * sizeof(double)}}));
         const double fprev = f;
@@ -867,10 +1026,11 @@ cdl_status cdl_chain_densify(cdl_ctx *ctx, int64_t n, void *chain, size_t chain_
         // Q_{j} = Q_{j-1} + L_j + Q_{j-1} L_j alternating between the spare
         // slot and slot 0 (free once L_0 is consumed); Q ends in slot 0.
         char *spare = slot(d), *cur = spare;
-        { Timed t_(ctx, "chain_product"); HIPCHK(launch_chain_product(info->prec, slot(0), slot(1), spare, ld, n, c.fro, c.tail, s)); }
+        cdl_status st = square_step(ctx, info->prec, slot(0), slot(1), spare, ld, n, c, true);
+        if (st != CDL_OK) return st;
         for (int j = 2; j < d; ++j) {
             char *dst = cur == spare ? slot(0) : spare;
-            { Timed t_(ctx, "chain_product"); HIPCHK(launch_chain_product(info->prec, cur, slot(j), dst, ld, n, c.fro, c.tail, s)); }
+            if ((st = square_step(ctx, info->prec, cur, slot(j), dst, ld, n, c, true)) != CDL_OK) return st;
             cur = dst;
         }
         if (cur != slot(0)) HIPCHK(hipMemcpyAsync(slot(0), cur, c.level_bytes, hipMemcpyDeviceToDevice, s));
@@ -890,8 +1050,19 @@ using WProduct = std::function<cdl_status(const double *Vt, double *P, int &S)>;
 static WProduct stored_product(cdl_ctx *ctx, const double *W, int64_t n, int64_t k) {
     return [ctx, W, n, k](const double *Vt, double *P, int &S) -> cdl_status {
         const int64_t ld = pad_n(n), kp = pad_k(k);
-        S = residual_splits(ld, kp, n);
-        { Timed t_(ctx, "residual"); HIPCHK(launch_residual_gemm(Vt, W, ld, n, kp, P, ctx->stream)); }
+        bool tune = false;
+        int ch = pick_choice(ctx, "residual", 0, ld, kp, 3, true, &tune);
+        if (tune) {
+            std::vector<double> ms(3);
+            for (int q = 0; q < 3; ++q)
+                HIPCHK(time_launch(ctx, [&] {
+                    return launch_residual_gemm(Vt, W, ld, n, kp, residual_splits(ld, kp, n, q), P,
+                                                ctx->stream);
+                }, &ms[q]));
+            ch = cdl::tune_put(cdl::tune_arch(ctx->device), cdl::tune_key("residual", 0, ld, kp), ms);
+        }
+        S = residual_splits(ld, kp, n, ch);
+        { Timed t_(ctx, "residual"); HIPCHK(launch_residual_gemm(Vt, W, ld, n, kp, S, P, ctx->stream)); }
         return CDL_OK;
     };
 }
@@ -932,6 +1103,7 @@ static cdl_status solve_from_rhs(cdl_ctx *ctx, const WProduct &wprod, const doub
         return fail(ctx, CDL_E_ARG, "certified tolerance needs ||S~||_F < 1; use tol > 0");
     const double rho_model = std::min(ci->rho_hat, ci->rho_bound);
     const double *inv_vs = w.scal + kp + 1;
+    const CostModel cm = cost_model(ctx->device, prec, n, k);
 
     double rel = 1.0;
     int it = 0;
@@ -940,7 +1112,7 @@ static cdl_status solve_from_rhs(cdl_ctx *ctx, const WProduct &wprod, const doub
     auto depth_now = [&]() {
         if (ci->dense_levels > 0) return 1;   // the one stored matrix is the whole product
         return ctx->solve_depth > 0 ? ctx->solve_depth
-                                    : (tol == 0.0 ? d : choose_depth(prec, n, k, d, rho_model, target / rel));
+                                    : (tol == 0.0 ? d : choose_depth(prec, d, rho_model, target / rel, cm));
     };
     auto precondition = [&](int D, double *Xdst) -> cdl_status {
         return precondition_enqueue(ctx, prec, d, D, w, c, ld, n, kp, scaled, inv_vs, Xdst);
@@ -1560,8 +1732,9 @@ cdl_status chain_enqueue(cdl_ctx *ctx, const double *W, const double *deg, const
     { Timed t_(ctx, "chain_prep"); HIPCHK(launch_chain_prep(deg, stats, n, ld, 0, c.dmn, c.dm, c.u, s)); }
     { Timed t_(ctx, "normalize"); HIPCHK(launch_normalize(prec, W, ld, n, c.dmn, c.u, 0, c.levels, c.fro, c.fro64, s)); }
     for (int l = 0; l + 1 < depth; ++l) {
-        Timed t_(ctx, "square");
-        HIPCHK(launch_square(prec, c.levels + c.level_bytes * l, c.levels + c.level_bytes * (l + 1), ld, n, c.fro, c.tail, s));
+        const cdl_status sq = square_step(ctx, prec, c.levels + c.level_bytes * l, c.levels + c.level_bytes * l,
+                                          c.levels + c.level_bytes * (l + 1), ld, n, c, false);
+        if (sq != CDL_OK) return sq;
     }
     return CDL_OK;
 }
@@ -1590,7 +1763,7 @@ cdl_status solve_enqueue_fixed(cdl_ctx *ctx, const double *W, const double *deg,
     HIPCHK(hipMemcpyAsync(ynorm, w.scal, kp * sizeof(double), hipMemcpyDeviceToDevice, s));
     const double *inv_vs = w.scal + kp + 1;
     for (int it = 0; it < iters; ++it) {
-        cdl_status st = precondition_enqueue(ctx, prec, depth, depth, w, c, ld, n, kp, scaled, inv_vs, w.Xt);
+        cdl_status st = precondition_enqueue(ctx, prec, depth, depth, w, c, ld, n, kp, scaled, inv_vs, w.Xt, false);
         if (st != CDL_OK) return st;
         { Timed t_(ctx, "residual"); HIPCHK(launch_residual_k(prec, w.Xt, W, w.Yt, deg, c.dm, ld, n, kp, k, 0, (double *)w.part, w.Rt,
                                  w.V64, w.Vlo[0], w.npart, w.mpart, s)); }

@@ -227,15 +227,17 @@ hipError_t launch_normalize_rows(int prec, const double *Wp, int64_t ld, int64_t
 // ---------------------------------------------------------------------------
 // Symmetric squaring.
 
-template <typename T> struct SqCfg;
-template <> struct SqCfg<__bf16> { using Core = DmaCore<MfmaBF16, 256, 256, 2, 4>; static constexpr int TILE = 256; };
-template <> struct SqCfg<_Float16> { using Core = DmaCore<MfmaF16, 256, 256, 2, 4>; static constexpr int TILE = 256; };
-template <> struct SqCfg<float> { using Core = GemmCore<MfmaF32, 128, 128, 32, 2, 2>; static constexpr int TILE = 128; };
-template <> struct SqCfg<double> { using Core = GemmCore<MfmaF64, 128, 128, 16, 2, 2>; static constexpr int TILE = 128; };
+// 16-bit levels: 256 x 256 tiles on NW = 8 waves (2 x 4 of 128 x 64) or
+// NW = 4 waves (2 x 2 of 128 x 128); FP32/FP64 levels: one configuration.
+template <typename T, int NW> struct SqCfg;
+template <int NW> struct SqCfg<__bf16, NW> { using Core = DmaCore<MfmaBF16, 256, 256, 2, NW / 2>; static constexpr int TILE = 256; };
+template <int NW> struct SqCfg<_Float16, NW> { using Core = DmaCore<MfmaF16, 256, 256, 2, NW / 2>; static constexpr int TILE = 256; };
+template <int NW> struct SqCfg<float, NW> { using Core = GemmCore<MfmaF32, 128, 128, 32, 2, 2>; static constexpr int TILE = 128; };
+template <int NW> struct SqCfg<double, NW> { using Core = GemmCore<MfmaF64, 128, 128, 16, 2, 2>; static constexpr int TILE = 128; };
 
-template <typename T> constexpr size_t sq_smem() {
-    using C = typename SqCfg<T>::Core;
-    constexpr int TL = SqCfg<T>::TILE;
+template <typename T, int NW> constexpr size_t sq_smem() {
+    using C = typename SqCfg<T, NW>::Core;
+    constexpr int TL = SqCfg<T, NW>::TILE;
     constexpr size_t stage = (size_t)TL * (TL + 16 / sizeof(T)) * sizeof(T);
     return C::SMEM > stage ? C::SMEM : stage;
 }
@@ -279,12 +281,12 @@ __device__ inline void square_epilogue(Core &g, const T *A, const T *B, T *S2, i
 // C = A B over the upper tiles with logical ids [0, count) (count = all
 // tiles, or the full rounds of 256 workgroups when the last round is split
 // over k below).  The squaring is A = B = S, add = 0.
-template <typename T>
-__global__ __launch_bounds__(SqCfg<T>::Core::NT) void k_square(const T *A, const T *B, T *S2, int64_t ld,
+template <typename T, int NW>
+__global__ __launch_bounds__((SqCfg<T, NW>::Core::NT)) void k_square(const T *A, const T *B, T *S2, int64_t ld,
                                                 int64_t kend, int nt, int count, float inv_scale,
                                                 int add, double *fro_part) {
-    using Core = typename SqCfg<T>::Core;
-    constexpr int TL = SqCfg<T>::TILE;
+    using Core = typename SqCfg<T, NW>::Core;
+    constexpr int TL = SqCfg<T, NW>::TILE;
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
     __shared__ double red[Core::NT / 64];
     const int id = TL == 256 ? round_remap(blockIdx.x, count) : xcd_remap(blockIdx.x, count);
@@ -301,12 +303,12 @@ __global__ __launch_bounds__(SqCfg<T>::Core::NT) void k_square(const T *A, const
 // first + b / splits), each split into `splits` k-ranges of ks elements:
 // workgroup b multiplies its range and stores the FP32 accumulators as a
 // partial tile (element e of thread t at P[b * TL^2 + e * NT + t]).
-template <typename T>
-__global__ __launch_bounds__(SqCfg<T>::Core::NT) void k_square_part(const T *A, const T *B, int64_t ld,
+template <typename T, int NW>
+__global__ __launch_bounds__((SqCfg<T, NW>::Core::NT)) void k_square_part(const T *A, const T *B, int64_t ld,
                                                      int64_t kend, int64_t ks, int nt, int first,
                                                      int splits, float *P) {
-    using Core = typename SqCfg<T>::Core;
-    constexpr int TL = SqCfg<T>::TILE;
+    using Core = typename SqCfg<T, NW>::Core;
+    constexpr int TL = SqCfg<T, NW>::TILE;
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
     const int b = blockIdx.x, sp = b % splits;
     int I, J;
@@ -327,13 +329,13 @@ __global__ __launch_bounds__(SqCfg<T>::Core::NT) void k_square_part(const T *A, 
 
 // One workgroup per tile of the split round: the partial tiles summed in
 // split order into the accumulator layout of the core, then the epilogue.
-template <typename T>
-__global__ __launch_bounds__(SqCfg<T>::Core::NT) void k_square_tail(const T *A, const T *B, T *S2,
+template <typename T, int NW>
+__global__ __launch_bounds__((SqCfg<T, NW>::Core::NT)) void k_square_tail(const T *A, const T *B, T *S2,
                                                      int64_t ld, int nt, int first, int splits,
                                                      const float *P, float inv_scale, int add,
                                                      double *fro_part) {
-    using Core = typename SqCfg<T>::Core;
-    constexpr int TL = SqCfg<T>::TILE;
+    using Core = typename SqCfg<T, NW>::Core;
+    constexpr int TL = SqCfg<T, NW>::TILE;
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
     __shared__ double red[Core::NT / 64];
     const int id = first + blockIdx.x;
@@ -398,15 +400,16 @@ size_t square_tail_bytes(int prec, int64_t ld, int64_t n) {
     return (size_t)p.rem * p.splits * 256 * 256 * sizeof(float);
 }
 
-template <typename T>
+template <typename T, int NW>
 static hipError_t sq_launch(const void *A, const void *B, void *S2, int64_t ld, int64_t n,
                             float inv_scale, int add, double *fro_part, float *tail, hipStream_t s) {
-    constexpr int TL = SqCfg<T>::TILE;
-    constexpr size_t smem = sq_smem<T>();
+    using Cfg = SqCfg<T, NW>;
+    constexpr int TL = Cfg::TILE;
+    constexpr size_t smem = sq_smem<T, NW>();
     static bool attr = false;
     if (!attr) {
-        for (const void *fn : {(const void *)k_square<T>, (const void *)k_square_part<T>,
-                               (const void *)k_square_tail<T>}) {
+        for (const void *fn : {(const void *)k_square<T, NW>, (const void *)k_square_part<T, NW>,
+                               (const void *)k_square_tail<T, NW>}) {
             hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
             if (e != hipSuccess) return e;
         }
@@ -417,35 +420,44 @@ static hipError_t sq_launch(const void *A, const void *B, void *S2, int64_t ld, 
                      std::is_same<T, __bf16>::value ? 2 : 3;
     SqPlan p = square_plan(prec, ld, n);
     if (!tail) p = SqPlan{p.total, p.total, 0, 0, p.kend, 0};
-    hipLaunchKernelGGL(k_square<T>, dim3(p.full), dim3(SqCfg<T>::Core::NT), smem, s, (const T *)A,
+    constexpr int NT = Cfg::Core::NT;
+    hipLaunchKernelGGL((k_square<T, NW>), dim3(p.full), dim3(NT), smem, s, (const T *)A,
                        (const T *)B, (T *)S2, ld, p.kend, nt, p.full, inv_scale, add, fro_part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || p.rem == 0) return e;
-    hipLaunchKernelGGL(k_square_part<T>, dim3(p.rem * p.splits), dim3(SqCfg<T>::Core::NT), smem, s,
+    hipLaunchKernelGGL((k_square_part<T, NW>), dim3(p.rem * p.splits), dim3(NT), smem, s,
                        (const T *)A, (const T *)B, ld, p.kend, p.ks, nt, p.full, p.splits, tail);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_square_tail<T>, dim3(p.rem), dim3(SqCfg<T>::Core::NT), smem, s, (const T *)A,
+    hipLaunchKernelGGL((k_square_tail<T, NW>), dim3(p.rem), dim3(NT), smem, s, (const T *)A,
                        (const T *)B, (T *)S2, ld, nt, p.full, p.splits, (const float *)tail,
                        inv_scale, add, fro_part);
     return hipGetLastError();
 }
 
+int square_variants(int prec) { return prec == 2 || prec == 3 ? 4 : 1; }
+
+// variant (16-bit levels): bit 0 set = no k-split of the last round, bit 1
+// set = the 4-wave core; other types have one variant.
 static hipError_t sq_dispatch(int prec, const void *A, const void *B, void *C, int64_t ld, int64_t n,
-                              int add, double *fro_part, float *tail, hipStream_t s) {
+                              int add, double *fro_part, float *tail, int variant, hipStream_t s) {
     const float inv = 1.0f / level_scale(prec, n);
+    float *t = (variant & 1) ? nullptr : tail;
+    const bool four = (variant & 2) != 0;
     switch (prec) {
-    case 0: return sq_launch<double>(A, B, C, ld, n, inv, add, fro_part, nullptr, s);
-    case 1: return sq_launch<float>(A, B, C, ld, n, inv, add, fro_part, nullptr, s);
-    case 2: return sq_launch<__bf16>(A, B, C, ld, n, inv, add, fro_part, tail, s);
-    case 3: return sq_launch<_Float16>(A, B, C, ld, n, inv, add, fro_part, tail, s);
+    case 0: return sq_launch<double, 8>(A, B, C, ld, n, inv, add, fro_part, nullptr, s);
+    case 1: return sq_launch<float, 8>(A, B, C, ld, n, inv, add, fro_part, nullptr, s);
+    case 2: return four ? sq_launch<__bf16, 4>(A, B, C, ld, n, inv, add, fro_part, t, s)
+                        : sq_launch<__bf16, 8>(A, B, C, ld, n, inv, add, fro_part, t, s);
+    case 3: return four ? sq_launch<_Float16, 4>(A, B, C, ld, n, inv, add, fro_part, t, s)
+                        : sq_launch<_Float16, 8>(A, B, C, ld, n, inv, add, fro_part, t, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_square(int prec, const void *S, void *S2, int64_t ld, int64_t n,
-                         double *fro_part, float *tail, hipStream_t s) {
-    return sq_dispatch(prec, S, S, S2, ld, n, 0, fro_part, tail, s);
+                         double *fro_part, float *tail, int variant, hipStream_t s) {
+    return sq_dispatch(prec, S, S, S2, ld, n, 0, fro_part, tail, variant, s);
 }
 
 // Inside a diagonal tile both triangles come out of the GEMM, and for A != B
@@ -463,14 +475,15 @@ __global__ __launch_bounds__(256) void k_sym_diag(T *C, int64_t ld, int TL) {
 
 template <typename T>
 static hipError_t sym_diag_launch(void *C, int64_t ld, hipStream_t s) {
-    const int TL = SqCfg<T>::TILE;
+    const int TL = SqCfg<T, 8>::TILE;
     hipLaunchKernelGGL(k_sym_diag<T>, dim3((unsigned)(ld / TL)), dim3(256), 0, s, (T *)C, ld, TL);
     return hipGetLastError();
 }
 
 hipError_t launch_chain_product(int prec, const void *Q, const void *L, void *C, int64_t ld,
-                                int64_t n, double *fro_part, float *tail, hipStream_t s) {
-    hipError_t e = sq_dispatch(prec, Q, L, C, ld, n, 1, fro_part, tail, s);
+                                int64_t n, double *fro_part, float *tail, int variant,
+                                hipStream_t s) {
+    hipError_t e = sq_dispatch(prec, Q, L, C, ld, n, 1, fro_part, tail, variant, s);
     if (e != hipSuccess) return e;
     switch (prec) {
     case 0: return sym_diag_launch<double>(C, ld, s);
@@ -529,11 +542,16 @@ __global__ __launch_bounds__(512) void k_apply_gemm(const T *Vin, const T *S, in
 
 static int ap_bm(int64_t kpad) { return kpad % 256 == 0 ? 256 : (kpad % 128 == 0 ? 128 : 64); }
 
-int apply_splits(int prec, int64_t ld, int64_t kpad, int64_t n) {
+// Split-K count of the chain application: choice 0 aims at >= 256
+// workgroups, 1 halves that count, 2 doubles it (at least two 64-wide
+// k-tiles per split either way); FP64 levels are not split.
+int apply_splits(int prec, int64_t ld, int64_t kpad, int64_t n, int choice) {
     if (prec == 0) return 1;
     const int64_t base = (kpad / ap_bm(kpad)) * (ld / 256);
     const int64_t kend = (n + 63) / 64 * 64;
     int64_t S = (256 + base - 1) / base;
+    if (choice == 1) S = S / 2;
+    if (choice == 2) S = 2 * S;
     const int64_t smax = kend / 128 > 0 ? kend / 128 : 1;   // >= 2 k-tiles per split
     if (S > smax) S = smax;
     if (S < 1) S = 1;
@@ -579,17 +597,21 @@ static hipError_t apg_launch(const void *Vin, const void *S, int64_t ld, int64_t
 }
 
 template <typename T>
+static hipError_t ap_gemm_launch(const void *Vin, const void *S, int64_t ld, int64_t n,
+                                 int64_t kpad, int ns, float *P, hipStream_t s) {
+    switch (ap_bm(kpad)) {
+    case 256: return apg_launch<T, 256>(Vin, S, ld, n, kpad, ns, P, s);
+    case 128: return apg_launch<T, 128>(Vin, S, ld, n, kpad, ns, P, s);
+    default: return apg_launch<T, 64>(Vin, S, ld, n, kpad, ns, P, s);
+    }
+}
+
+template <typename T>
 static hipError_t ap_split_launch(const void *Vin, const void *S, void *Vout, double *V64,
                                   int64_t ld, int64_t n, int64_t kpad, float inv_scale,
                                   double *Xt, const double *dm, const double *inv_vs, float *P,
-                                  int accumulate, hipStream_t s) {
-    const int ns = apply_splits(1, ld, kpad, n);
-    hipError_t e;
-    switch (ap_bm(kpad)) {
-    case 256: e = apg_launch<T, 256>(Vin, S, ld, n, kpad, ns, P, s); break;
-    case 128: e = apg_launch<T, 128>(Vin, S, ld, n, kpad, ns, P, s); break;
-    default: e = apg_launch<T, 64>(Vin, S, ld, n, kpad, ns, P, s); break;
-    }
+                                  int accumulate, int ns, hipStream_t s) {
+    hipError_t e = ap_gemm_launch<T>(Vin, S, ld, n, kpad, ns, P, s);
     if (e != hipSuccess) return e;
     const int64_t total = kpad * ld;
     const int grid = (int)(cdiv(total, 256) < 16384 ? cdiv(total, 256) : 16384);
@@ -651,16 +673,27 @@ static hipError_t apf64_launch(const void *Vin, const void *S, void *Vout, doubl
 
 hipError_t launch_apply(int prec, const void *Vin, const void *S, void *Vout, double *V64,
                         int64_t ld, int64_t n, int64_t kpad, double *Xt, const double *dm,
-                        const double *inv_vs, float *P, int accumulate, hipStream_t s) {
+                        const double *inv_vs, float *P, int accumulate, int nsplit, hipStream_t s) {
     const float inv = 1.0f / level_scale(prec, n);
+    const int ns = nsplit;
     switch (prec) {
     case 0:
         if (kpad % 256 == 0) return apf64_launch<256>(Vin, S, Vout, V64, ld, n, kpad, Xt, dm, inv_vs, accumulate, s);
         if (kpad % 128 == 0) return apf64_launch<128>(Vin, S, Vout, V64, ld, n, kpad, Xt, dm, inv_vs, accumulate, s);
         return apf64_launch<64>(Vin, S, Vout, V64, ld, n, kpad, Xt, dm, inv_vs, accumulate, s);
-    case 1: return ap_split_launch<float>(Vin, S, Vout, V64, ld, n, kpad, inv, Xt, dm, inv_vs, P, accumulate, s);
-    case 2: return ap_split_launch<__bf16>(Vin, S, Vout, V64, ld, n, kpad, inv, Xt, dm, inv_vs, P, accumulate, s);
-    case 3: return ap_split_launch<_Float16>(Vin, S, Vout, V64, ld, n, kpad, inv, Xt, dm, inv_vs, P, accumulate, s);
+    case 1: return ap_split_launch<float>(Vin, S, Vout, V64, ld, n, kpad, inv, Xt, dm, inv_vs, P, accumulate, ns, s);
+    case 2: return ap_split_launch<__bf16>(Vin, S, Vout, V64, ld, n, kpad, inv, Xt, dm, inv_vs, P, accumulate, ns, s);
+    case 3: return ap_split_launch<_Float16>(Vin, S, Vout, V64, ld, n, kpad, inv, Xt, dm, inv_vs, P, accumulate, ns, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_apply_gemm(int prec, const void *Vin, const void *S, int64_t ld, int64_t n,
+                             int64_t kpad, int nsplit, float *P, hipStream_t s) {
+    switch (prec) {
+    case 1: return ap_gemm_launch<float>(Vin, S, ld, n, kpad, nsplit, P, s);
+    case 2: return ap_gemm_launch<__bf16>(Vin, S, ld, n, kpad, nsplit, P, s);
+    case 3: return ap_gemm_launch<_Float16>(Vin, S, ld, n, kpad, nsplit, P, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -114,22 +114,31 @@ hipError_t launch_normalize_rows(int prec, const double *Wp, int64_t ld, int64_t
 // uses for its last, partial round of workgroups (split over k); 0 if none.
 size_t square_tail_bytes(int prec, int64_t ld, int64_t n);
 // tail: square_tail_bytes() of scratch (nullptr: no split).
+// variant < square_variants(prec): for 16-bit levels bit 0 set = no k-split
+// of the last round, bit 1 set = the 4-wave tile core.
+int square_variants(int prec);
 hipError_t launch_square(int prec, const void *S, void *S2, int64_t ld, int64_t n,
-                         double *fro_part, float *tail, hipStream_t s);
+                         double *fro_part, float *tail, int variant, hipStream_t s);
 // C = Q + L + Q L for commuting symmetric Q, L (levels' storage scale).
 hipError_t launch_chain_product(int prec, const void *Q, const void *L, void *C, int64_t ld,
-                                int64_t n, double *fro_part, float *tail, hipStream_t s);
+                                int64_t n, double *fro_part, float *tail, int variant,
+                                hipStream_t s);
 // accumulate: V64 += S~ Vin (else V64 = S~ Vin); Vout = V64 rounded.
 // inv_vs != nullptr marks the last level: X += dm * V * (*inv_vs).  P is the
-// split-K partial buffer (apply_splits() x kpad x ld floats; unused for FP64).
+// split-K partial buffer (nsplit x kpad x ld floats; unused for FP64).
 hipError_t launch_apply(int prec, const void *Vin, const void *S, void *Vout, double *V64,
                         int64_t ld, int64_t n, int64_t kpad, double *Xt, const double *dm,
-                        const double *inv_vs, float *P, int accumulate, hipStream_t s);
+                        const double *inv_vs, float *P, int accumulate, int nsplit,
+                        hipStream_t s);
+// The split-K product of one application alone (partials into P), for timing.
+hipError_t launch_apply_gemm(int prec, const void *Vin, const void *S, int64_t ld, int64_t n,
+                             int64_t kpad, int nsplit, float *P, hipStream_t s);
 // V64 += T64, Vout = V64 rounded, last level: X += dm * V64 * (*inv_vs).
 hipError_t launch_axpy_v(int prec, const double *T64, int64_t ld, int64_t kpad, double *V64,
                          void *Vout, double *Xt, const double *dm, const double *inv_vs,
                          hipStream_t s);
-int apply_splits(int prec, int64_t ld, int64_t kpad, int64_t n);
+// Split-K count of the chain application (choices as for residual_splits).
+int apply_splits(int prec, int64_t ld, int64_t kpad, int64_t n, int choice);
 
 // ---- solve ------------------------------------------------------------------
 hipError_t launch_rhs(const double *W, int64_t ld, int64_t n, const int32_t *gid, int64_t k,
@@ -170,12 +179,14 @@ hipError_t launch_residual_k(int prec, const double *Xt, const double *W, const 
                              int64_t kpad, int64_t k, int skip_gemm, double *P, double *Rt,
                              double *V64, void *Vlo, double *npart, double *mpart,
                              hipStream_t s);
-int residual_splits(int64_t ld, int64_t kpad, int64_t n);
-// The two halves of launch_residual_k: the split-K product W X into P
-// (residual_splits partials), and the reduction over S partials (S = 0: none,
+// Split-K count of the residual product: choice 0 the default, 1 half of
+// it, 2 twice it (the candidates of the tuner; workspaces hold choice 2).
+int residual_splits(int64_t ld, int64_t kpad, int64_t n, int choice);
+// The two halves of launch_residual_k: the split-K product W X into S
+// partials of P, and the reduction over S partials (S = 0: none,
 // R = Y - deg X) that forms R, the operand V and the norm partials.
 hipError_t launch_residual_gemm(const double *Xt, const double *W, int64_t ld, int64_t n,
-                                int64_t kpad, double *P, hipStream_t s);
+                                int64_t kpad, int S, double *P, hipStream_t s);
 hipError_t launch_residual_reduce_k(int prec, const double *P, int S, const double *Yt,
                                     const double *Xt, const double *deg, const double *dm,
                                     int64_t ld, int64_t n, int64_t kpad, int64_t k, double *Rt,

@@ -437,10 +437,15 @@ __global__ __launch_bounds__(512) void k_residual_gemm(const double *Xt, const d
 
 static int res_bm(int64_t kpad) { return kpad % 256 == 0 ? 256 : (kpad % 128 == 0 ? 128 : 64); }
 
-int residual_splits(int64_t ld, int64_t kpad, int64_t n) {
+// Split-K count of the FP64 residual product: choice 0 aims at >= 256
+// workgroups, 1 halves that count, 2 doubles it (at least four 16-wide
+// k-tiles per split either way).
+int residual_splits(int64_t ld, int64_t kpad, int64_t n, int choice) {
     const int64_t base = (kpad / res_bm(kpad)) * (ld / 128);
     const int64_t kend = (n + 63) / 64 * 64;
     int64_t S = (256 + base - 1) / base;          // aim at >= 256 workgroups
+    if (choice == 1) S = S / 2;
+    if (choice == 2) S = 2 * S;
     const int64_t smax = kend / 64 > 0 ? kend / 64 : 1;   // >= 4 k-tiles per split
     if (S > smax) S = smax;
     if (S < 1) S = 1;
@@ -449,7 +454,7 @@ int residual_splits(int64_t ld, int64_t kpad, int64_t n) {
 
 template <int BM>
 static hipError_t resg_launch(const double *Xt, const double *W, int64_t ld, int64_t n,
-                              int64_t kpad, double *P, hipStream_t s) {
+                              int64_t kpad, int S, double *P, hipStream_t s) {
     using Core = typename ResCfg<BM>::Core;
     static bool attr = false;
     if (!attr) {
@@ -460,7 +465,6 @@ static hipError_t resg_launch(const double *Xt, const double *W, int64_t ld, int
         attr = true;
     }
     const int mt = (int)(kpad / BM), nt = (int)(ld / 128);
-    const int S = residual_splits(ld, kpad, n);
     const int64_t kend = (n + 63) / 64 * 64;
     const int64_t ks = (cdiv(kend, S) + 15) / 16 * 16;
     hipLaunchKernelGGL(k_residual_gemm<BM>, dim3(mt * nt * S), dim3(512), Core::SMEM, s, Xt, W,
@@ -607,11 +611,11 @@ hipError_t launch_stream_update(const double *Ut, const double *Prod, const doub
 }
 
 hipError_t launch_residual_gemm(const double *Xt, const double *W, int64_t ld, int64_t n,
-                                int64_t kpad, double *P, hipStream_t s) {
+                                int64_t kpad, int S, double *P, hipStream_t s) {
     switch (res_bm(kpad)) {
-    case 256: return resg_launch<256>(Xt, W, ld, n, kpad, P, s);
-    case 128: return resg_launch<128>(Xt, W, ld, n, kpad, P, s);
-    default: return resg_launch<64>(Xt, W, ld, n, kpad, P, s);
+    case 256: return resg_launch<256>(Xt, W, ld, n, kpad, S, P, s);
+    case 128: return resg_launch<128>(Xt, W, ld, n, kpad, S, P, s);
+    default: return resg_launch<64>(Xt, W, ld, n, kpad, S, P, s);
     }
 }
 
@@ -637,11 +641,12 @@ hipError_t launch_residual_k(int prec, const double *Xt, const double *W, const 
                              int64_t kpad, int64_t k, int skip_gemm, double *P, double *Rt,
                              double *V64, void *Vlo, double *npart, double *mpart,
                              hipStream_t s) {
+    const int S = residual_splits(ld, kpad, n, 0);
     if (!skip_gemm) {
-        hipError_t e = launch_residual_gemm(Xt, W, ld, n, kpad, P, s);
+        hipError_t e = launch_residual_gemm(Xt, W, ld, n, kpad, S, P, s);
         if (e != hipSuccess) return e;
     }
-    return launch_residual_reduce_k(prec, P, skip_gemm ? 0 : residual_splits(ld, kpad, n), Yt,
+    return launch_residual_reduce_k(prec, P, skip_gemm ? 0 : S, Yt,
                                     Xt, deg, dm, ld, n, kpad, k, Rt, V64, Vlo, npart, mpart, s);
 }
 

@@ -178,3 +178,41 @@ def test_k_rp_and_level_scale_queries(L):
     assert L.cdl_level_scale(0, 3, C.byref(s)) == 1
     assert L.cdl_level_scale(10, 4, C.byref(s)) == 1
     assert L.cdl_level_scale(10, 3, None) == 1
+
+
+def test_autotune_table_json_round_trip(L, tmp_path):
+    # without a GPU the table's architecture is "none" (device < 0)
+    assert L.cdl_autotune_clear() == 0
+    src = tmp_path / "tune.json"
+    src.write_text(
+        '{"format": "caddelag-autotune-1", "entries": ['
+        '{"arch": "none", "key": "square/bf16/ld16384", "choice": 1, "ms": [4.8, 4.3, 5.3, 5.0]},'
+        '{"arch": "none", "key": "apply/fp16/ld16384/k256", "choice": 2, "ms": [0.20, 0.24, 0.18]},'
+        '{"arch": "gfx950:sramecc+:xnack-", "key": "residual/fp64/ld16384/k256", "choice": 0,'
+        ' "ms": [2.2, 2.4, 2.3]}]}')
+    assert L.cdl_autotune_load(str(src).encode()) == 0
+    assert L.cdl_autotune_entries() == 3
+    ch, nc, ms = C.c_int(), C.c_int(), C.c_double()
+
+    def look(fam, prec, n, k):
+        return L.cdl_autotune_lookup(-1, fam, prec, n, k, C.byref(ch), C.byref(nc), C.byref(ms))
+
+    assert look(b"square", 2, 16384, 0) == 0 and (ch.value, nc.value, ms.value) == (1, 4, 4.3)
+    assert look(b"square", 2, 16300, 0) == 0            # same padded shape (ld 16384)
+    assert look(b"apply", 3, 16384, 250) == 0 and (ch.value, ms.value) == (2, 0.18)   # k pads to 256
+    assert look(b"residual", 0, 16384, 256) == 8         # another architecture's entry
+    assert look(b"square", 3, 16384, 0) == 8             # no FP16 squaring entry
+    assert look(b"nonsense", 2, 16384, 0) == 1
+    assert look(b"apply", 2, 16384, 0) == 1               # apply needs k
+    out = tmp_path / "out.json"
+    assert L.cdl_autotune_save(str(out).encode()) == 0
+    assert L.cdl_autotune_clear() == 0 and L.cdl_autotune_entries() == 0
+    assert L.cdl_autotune_load(str(out).encode()) == 0 and L.cdl_autotune_entries() == 3
+    assert look(b"apply", 3, 16384, 256) == 0 and (ch.value, nc.value) == (2, 3)
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"format": "something else", "entries": []}')
+    assert L.cdl_autotune_load(str(bad).encode()) == 1
+    bad.write_text('{"format": "caddelag-autotune-1", "entries": [')
+    assert L.cdl_autotune_load(str(bad).encode()) == 1
+    assert L.cdl_autotune_load(str(tmp_path / "missing.json").encode()) == 1
+    assert L.cdl_autotune_clear() == 0
