@@ -132,7 +132,7 @@ typedef struct {
     int max_iter;
     cdl_score_mode mode;
     int32_t top_k;
-    int32_t flags;             /* 0, CDL_SEQ_ASYNC, or CDL_SEQ_ASYNC | CDL_SEQ_GRAPH */
+    int32_t flags;             /* 0, or CDL_SEQ_ASYNC with CDL_SEQ_GRAPH and/or CDL_SEQ_BATCHED */
 } cdl_seq_params;
 
 /* cdl_seq_params.flags.  CDL_SEQ_ASYNC: enqueue the whole sequence with no
@@ -147,6 +147,19 @@ typedef struct {
  * one launch. */
 #define CDL_SEQ_ASYNC 1
 #define CDL_SEQ_GRAPH 2
+/* CDL_SEQ_BATCHED (with CDL_SEQ_ASYNC; FP32, BF16 or FP16 levels): one pass
+ * over the whole sequence with every snapshot resident (the workspace grows
+ * with the sum of the snapshots' sizes): graphs, level-0 chains and
+ * right-hand sides per snapshot on two streams, then grouped launches over
+ * all snapshots for each chain squaring, each step of the refinement (the
+ * applications level by level, the FP64 residual product and reduction, the
+ * norms) and the embeddings, and over all pairs for the scores.  Convergence
+ * is tested on the device after every iteration: a snapshot whose relative
+ * residual reaches tol (> 0) stops (its workgroups of later iterations
+ * return at once), so max_iter is only an upper bound; tol = 0 runs exactly
+ * max_iter iterations.  info->max_iterations is the largest iteration count
+ * used; CDL_E_NOCONV if a snapshot ends above tol. */
+#define CDL_SEQ_BATCHED 4
 
 typedef struct {
     int32_t pairs;             /* number of scored pairs (n_snap - 1) */

@@ -485,6 +485,9 @@ class SeqParams:
     asynchronous: bool = False
     # With asynchronous: a repeat of the previous call replays a HIP graph.
     graph: bool = False
+    # With asynchronous: one pass with grouped launches over all snapshots
+    # and pairs, convergence tested on the device (max_iter an upper bound).
+    batched: bool = False
 
 
 def _seq_args(Xs, gids, p: SeqParams):
@@ -502,7 +505,8 @@ def _seq_args(Xs, gids, p: SeqParams):
     q = L.SeqParams(k=p.k, seed=p.seed, sigma=p.sigma, prec=L.PREC[p.prec], depth=p.depth,
                     depth_max=p.depth_max, chain_eps=p.chain_eps, solver=L.SOLVER[p.solver],
                     tol=p.tol, max_iter=p.max_iter, mode=L.MODE[p.mode], top_k=p.top_k,
-                    flags=(1 if p.asynchronous else 0) | (2 if p.graph else 0))
+                    flags=(1 if p.asynchronous else 0) | (2 if p.graph else 0) |
+                    (4 if p.batched else 0))
     return snaps, q, gid_host, gid_dev
 
 

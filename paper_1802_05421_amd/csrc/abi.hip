@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "caddelag.h"
+#include "batch.h"
 #include "kernels.h"
 #include "tune.h"
 
@@ -1722,16 +1723,17 @@ void common_maps(const cdl_snapshot &y, const cdl_snapshot &x, std::vector<int32
     }
 }
 
-// Chain with a fixed number of levels, no host reads.
+// Chain with a fixed number of levels, no host reads (square = false: level 0
+// only; the caller squares, grouped over several chains).
 cdl_status chain_enqueue(cdl_ctx *ctx, const double *W, const double *deg, const double *stats,
-                         int64_t n, int prec, int depth, void *chain) {
+                         int64_t n, int prec, int depth, void *chain, bool square = true) {
     Arena a(chain);
     ChainBuf c = plan_chain(a, n, prec, depth);
     const int64_t ld = pad_n(n);
     hipStream_t s = ctx->stream;
     { Timed t_(ctx, "chain_prep"); HIPCHK(launch_chain_prep(deg, stats, n, ld, 0, c.dmn, c.dm, c.u, s)); }
     { Timed t_(ctx, "normalize"); HIPCHK(launch_normalize(prec, W, ld, n, c.dmn, c.u, 0, c.levels, c.fro, c.fro64, s)); }
-    for (int l = 0; l + 1 < depth; ++l) {
+    for (int l = 0; square && l + 1 < depth; ++l) {
         const cdl_status sq = square_step(ctx, prec, c.levels + c.level_bytes * l, c.levels + c.level_bytes * l,
                                           c.levels + c.level_bytes * (l + 1), ld, n, c, false);
         if (sq != CDL_OK) return sq;
@@ -1773,6 +1775,69 @@ cdl_status solve_enqueue_fixed(cdl_ctx *ctx, const double *W, const double *deg,
     { Timed t_(ctx, "finalize_z"); HIPCHK(launch_finalize_z2(w.Xt, ld, n, kp, k, w.mean, Z, s)); }
     return CDL_OK;
 }
+// ---- one-pass sequences (CDL_SEQ_BATCHED) ------------------------------------
+// Every snapshot's weights, chain, solve workspace and embedding and every
+// pair's score workspace are resident at once, so each kernel family of the
+// chain squarings, the refinement iterations and the scores runs as one
+// grouped launch over all snapshots (pairs).
+
+size_t put(Arena &a, size_t bytes) {
+    const size_t o = a.off;
+    a.take<char>(bytes);
+    return o;
+}
+
+struct BatchLayout {
+    std::vector<size_t> W, deg, st, chain, solve, Z, score;
+    size_t gws[2] = {0, 0}, maps = 0, snaps = 0, pairs = 0, prefix = 0, flags = 0, ynorm = 0,
+           rel = 0, status = 0, total = 0;
+};
+constexpr int kBatchTables = 10;   // prefix tables of the grouped launches
+
+BatchLayout batch_layout(int32_t n_snap, const cdl_snapshot *sn, const cdl_seq_params *q) {
+    BatchLayout L;
+    Arena a(nullptr);
+    const int depth = std::max(q->depth, 1);
+    int64_t nmax = 0, Tmax = 0, ntot = 0;
+    for (int t = 0; t < n_snap; ++t) {
+        const int64_t n = sn[t].n, ld = pad_n(n);
+        nmax = std::max(nmax, n);
+        Tmax = std::max(Tmax, sn[t].T);
+        ntot += n;
+        L.W.push_back(put(a, (size_t)ld * ld * sizeof(double)));
+        L.deg.push_back(put(a, (size_t)ld * sizeof(double)));
+        L.st.push_back(put(a, CDL_GRAPH_STATS * sizeof(double)));
+        Arena c(nullptr);
+        plan_chain(c, n, q->prec, depth);
+        L.chain.push_back(put(a, c.off));
+        Arena w(nullptr);
+        plan_solve(w, n, q->k, q->prec);
+        L.solve.push_back(put(a, w.off));
+        L.Z.push_back(put(a, (size_t)n * q->k * sizeof(double)));
+    }
+    for (int t = 1; t < n_snap; ++t) {
+        Arena w(nullptr);
+        plan_score(w, std::min(sn[t - 1].n, sn[t].n), q->k);
+        L.score.push_back(put(a, w.off));
+    }
+    for (int b = 0; b < 2; ++b) {
+        Arena g(nullptr);
+        plan_graph(g, nmax, Tmax);
+        L.gws[b] = put(a, g.off);
+    }
+    const int64_t kp = pad_k(q->k);
+    L.maps = put(a, 2 * (size_t)ntot * sizeof(int32_t));
+    L.snaps = put(a, (size_t)n_snap * sizeof(cdl::BatchSnap));
+    L.pairs = put(a, (size_t)n_snap * sizeof(cdl::BatchPair));
+    L.prefix = put(a, (size_t)kBatchTables * (n_snap + 1) * sizeof(int));
+    L.flags = put(a, 2 * (size_t)n_snap * sizeof(int));
+    L.ynorm = put(a, (size_t)n_snap * kp * sizeof(double));
+    L.rel = put(a, (size_t)n_snap * sizeof(double));
+    L.status = put(a, (size_t)n_snap * CDL_GRAPH_STATS * sizeof(double));
+    L.total = a.off;
+    return L;
+}
+
 size_t seq_bytes(const SeqPlan &p, const cdl_seq_params *q) {
     const int dmax = q->depth > 0 ? q->depth : q->depth_max;
     size_t g = 0, c = 0, so = 0, sc = 0;
@@ -1797,6 +1862,324 @@ size_t seq_bytes(const SeqPlan &p, const cdl_seq_params *q) {
 }
 } // namespace
 
+// Runs enqueue(s0, s1) eagerly on the context's stream and its second
+// stream; with use_graph, the second call with the same key is captured into
+// a HIP graph (both streams forked and joined inside the capture) and later
+// calls with that key replay it in one launch.
+static cdl_status run_sequence(cdl_ctx *ctx, bool use_graph, const std::vector<uint64_t> &key,
+                               const std::function<cdl_status(hipStream_t, hipStream_t)> &enqueue,
+                               cdl_seq_info *info) {
+    const bool timing = ctx->timing;
+    hipStream_t s = ctx->stream;
+    cdl_status st = CDL_OK;
+    if (!use_graph) {
+        // eager two-stream enqueue; a later graph call starts its key afresh
+        ctx->seq_key.clear();
+        if ((st = enqueue(s, ctx->side)) != CDL_OK) {
+            (void)hipStreamSynchronize(ctx->side);
+            return st;
+        }
+    } else if (key == ctx->seq_key && ctx->seq_exec) {
+        HIPCHK(hipGraphLaunch(ctx->seq_exec, s));
+        if (info) info->graph_launches = 1;
+    } else if (key == ctx->seq_key) {
+        // second identical call: capture the enqueue into a graph, on a
+        // private stream (the caller's may be the null stream, which
+        // cannot be captured), then launch it on the caller's stream
+        hipStream_t cap = nullptr, cap2 = nullptr;
+        HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        const hipError_t e2 = hipStreamCreateWithFlags(&cap2, hipStreamNonBlocking);
+        if (e2 != hipSuccess) {
+            (void)hipStreamDestroy(cap);
+            HIPCHK(e2);
+        }
+        const hipError_t eb = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (eb != hipSuccess) {
+            (void)hipStreamDestroy(cap);
+            (void)hipStreamDestroy(cap2);
+            HIPCHK(eb);
+        }
+        ctx->timing = false;
+        st = enqueue(cap, cap2);   // cap2 joins the capture through the fork event
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(cap, &g);
+        ctx->stream = s;
+        ctx->timing = timing;
+        (void)hipStreamDestroy(cap);
+        (void)hipStreamDestroy(cap2);
+        if (st != CDL_OK || ec != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            ctx->seq_key.clear();
+            if (st != CDL_OK) return st;
+            HIPCHK(ec);
+        }
+        hipGraphExec_t ex = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            HIPCHK(ei);
+        }
+        ctx->seq_graph = g;
+        ctx->seq_exec = ex;
+        HIPCHK(hipGraphLaunch(ex, s));
+        if (info) info->graph_launches = 1;
+    } else {
+        if (ctx->seq_exec) (void)hipGraphExecDestroy(ctx->seq_exec);
+        if (ctx->seq_graph) (void)hipGraphDestroy(ctx->seq_graph);
+        ctx->seq_exec = nullptr;
+        ctx->seq_graph = nullptr;
+        ctx->seq_key = key;
+        if ((st = enqueue(s, ctx->side)) != CDL_OK) {
+            (void)hipStreamSynchronize(ctx->side);   // nothing may stay in flight on the side stream
+            return st;
+        }
+    }
+    return CDL_OK;
+}
+
+// CDL_SEQ_BATCHED: the snapshots' graphs, level-0 chains and right-hand sides
+// alternate over two streams; then, on the context's stream, grouped
+// launches over all snapshots run the squarings (one per level), the
+// initial residuals and every refinement iteration (the applications level
+// by level, the FP64 residual product and its reduction, the norms and the
+// device-side convergence test: converged snapshots skip their workgroups),
+// the centred embeddings, and grouped launches over all pairs the scores;
+// top-K per pair.  Nothing is read back until the end.
+static cdl_status score_sequence_batched(cdl_ctx *ctx, int32_t n_snap, const cdl_snapshot *sn,
+                                         const cdl_seq_params *q, double *const *F,
+                                         int32_t *const *top_idx, void *ws,
+                                         cdl_seq_info *info) {
+    using cdl::BatchPair;
+    using cdl::BatchSnap;
+    const int P = n_snap, NP = n_snap - 1;
+    const int depth = q->depth, prec = q->prec;
+    const int64_t k = q->k, kp = pad_k(k);
+    const bool scaled = prec == 3;
+    const BatchLayout L = batch_layout(n_snap, sn, q);
+    char *base = (char *)ws;
+    if (info) std::memset(info, 0, sizeof(*info));
+    hipStream_t s = ctx->stream;
+    HIPCHK(hipSetDevice(ctx->device));
+    // host tables: snapshot and pair descriptors, prefix tables, maps
+    std::vector<BatchSnap> hs(P);
+    std::vector<ChainBuf> chains(P);
+    std::vector<SolveWs> solves(P);
+    for (int t = 0; t < P; ++t) {
+        const int64_t n = sn[t].n, ld = pad_n(n);
+        Arena ac(base + L.chain[t]);
+        chains[t] = plan_chain(ac, n, prec, depth);
+        Arena aw(base + L.solve[t]);
+        solves[t] = plan_solve(aw, n, k, prec);
+        const ChainBuf &c = chains[t];
+        const SolveWs &w = solves[t];
+        bool tune = false;
+        const int ca = pick_choice(ctx, "apply", prec, ld, kp, 3, false, &tune);
+        const int cr = pick_choice(ctx, "residual", 0, ld, kp, 3, false, &tune);
+        BatchSnap &d = hs[t];
+        d.n = n;
+        d.ld = ld;
+        d.W = (const double *)(base + L.W[t]);
+        d.deg = (const double *)(base + L.deg[t]);
+        d.levels = c.levels;
+        d.level_bytes = (int64_t)c.level_bytes;
+        d.dm = c.dm;
+        d.fro = c.fro;
+        d.inv_scale = 1.0f / level_scale(prec, n);
+        d.Yt = w.Yt;
+        d.Xt = w.Xt;
+        d.Rt = w.Rt;
+        d.V64 = w.V64;
+        d.Vlo[0] = w.Vlo[0];
+        d.Vlo[1] = w.Vlo[1];
+        d.Pap = (float *)w.part;
+        d.Pres = (double *)w.part;
+        d.npart = w.npart;
+        d.mpart = w.mpart;
+        d.scal = w.scal;
+        d.ap_splits = apply_splits(prec, ld, kp, n, ca);
+        d.res_splits = residual_splits(ld, kp, n, cr);
+    }
+    std::vector<BatchPair> hp(NP);
+    std::vector<int32_t> hm, m0, m1;
+    std::vector<int64_t> mcnt(NP);
+    int32_t *maps = (int32_t *)(base + L.maps);
+    for (int t = 1; t < P; ++t) {
+        common_maps(sn[t - 1], sn[t], m0, m1);
+        const int64_t m = (int64_t)m0.size();
+        if (m < 2) return fail(ctx, CDL_E_GRAPH, "consecutive snapshots share fewer than two nodes");
+        BatchPair &r = hp[t - 1];
+        r.m = m;
+        r.mpad = pad_n(m);
+        r.Z0 = (const double *)(base + L.Z[t - 1]);
+        r.Z1 = (const double *)(base + L.Z[t]);
+        r.map0 = maps + hm.size();
+        r.map1 = r.map0 + m;
+        hm.insert(hm.end(), m0.begin(), m0.end());
+        hm.insert(hm.end(), m1.begin(), m1.end());
+        r.stats0 = (const double *)(base + L.st[t - 1]);
+        r.stats1 = (const double *)(base + L.st[t]);
+        r.W0 = (const double *)(base + L.W[t - 1]);
+        r.W1 = (const double *)(base + L.W[t]);
+        r.ld0 = pad_n(sn[t - 1].n);
+        r.ld1 = pad_n(sn[t].n);
+        Arena as(base + L.score[t - 1]);
+        const ScoreWs sw = plan_score(as, m, k);
+        r.Zh = sw.Zh;
+        r.Zhe = sw.Zhe;
+        r.sq = sw.sq;
+        r.part = sw.part;
+        r.F = F[t - 1];
+        mcnt[t - 1] = m;
+    }
+    // prefix tables: 0 squaring, 1 apply product, 2 apply update, 3 residual
+    // product, 4 residual reduction, 5 FP16 operand, 6 signature rows,
+    // 7 score tiles, 8 score reduction
+    std::vector<int> pre((size_t)kBatchTables * (P + 1), 0);
+    auto table = [&](int id) { return pre.data() + (size_t)id * (P + 1); };
+    auto fill = [&](int id, int cnt, const std::function<int(int)> &f) {
+        int *tb = table(id);
+        tb[0] = 0;
+        for (int i = 0; i < cnt; ++i) tb[i + 1] = tb[i] + f(i);
+        return tb[cnt];
+    };
+    const int tot_sq = fill(0, P, [&](int t) { return square_tiles(prec, hs[t].ld); });
+    const int tot_ag = fill(1, P, [&](int t) { return apply_gemm_tiles(hs[t].ld, kp, hs[t].ap_splits); });
+    const int tot_ar = fill(2, P, [&](int t) { return apply_reduce_blocks(hs[t].ld, kp); });
+    const int tot_rg = fill(3, P, [&](int t) { return residual_gemm_tiles(hs[t].ld, kp, hs[t].res_splits); });
+    const int tot_rr = fill(4, P, [&](int t) { return (int)(hs[t].ld / 256 * kp); });
+    const int tot_pv = fill(5, P, [&](int t) { return apply_reduce_blocks(hs[t].ld, kp); });
+    const int tot_zh = fill(6, NP, [&](int t) { return (int)hp[t].mpad; });
+    const int tot_sc = fill(7, NP, [&](int t) { return score_tiles_2d(hp[t].mpad); });
+    const int tot_sr = fill(8, NP, [&](int t) { return (int)((hp[t].m + 63) / 64); });
+    BatchSnap *dsnap = (BatchSnap *)(base + L.snaps);
+    BatchPair *dpair = (BatchPair *)(base + L.pairs);
+    int *dpre = (int *)(base + L.prefix);
+    auto dtable = [&](int id) { return dpre + (size_t)id * (P + 1); };
+    HIPCHK(hipMemcpyAsync(maps, hm.data(), hm.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(dsnap, hs.data(), hs.size() * sizeof(BatchSnap), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(dpair, hp.data(), hp.size() * sizeof(BatchPair), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(dpre, pre.data(), pre.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    int *done = (int *)(base + L.flags), *iters = done + P;
+    double *ynorm = (double *)(base + L.ynorm), *rel = (double *)(base + L.rel);
+    double *status = (double *)(base + L.status);
+    if (!ctx->side) HIPCHK(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+    hipEvent_t evs[2] = {nullptr, nullptr};
+    struct EvGuard {
+        hipEvent_t *v;
+        ~EvGuard() { for (int i = 0; i < 2; ++i) if (v[i]) (void)hipEventDestroy(v[i]); }
+    } ev_guard{evs};
+    for (auto &e : evs) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    const int weighted = q->mode == CDL_SCORE_DELTA_A;
+
+    auto enqueue = [&](hipStream_t s0, hipStream_t s1) -> cdl_status {
+        hipStream_t ss[2] = {s0, s1};
+        cdl_status st = CDL_OK;
+        HIPCHK(hipEventRecord(evs[0], s0));
+        HIPCHK(hipStreamWaitEvent(s1, evs[0], 0));
+        for (int t = 0; t < P && st == CDL_OK; ++t) {
+            hipStream_t es = ss[t & 1];
+            ctx->stream = es;
+            const cdl_snapshot &x = sn[t];
+            const double *W = hs[t].W, *deg = hs[t].deg;
+            double *stats = (double *)(base + L.st[t]);
+            st = graph_enqueue(ctx, x.X, x.n, x.T, x.ldx, q->sigma, (double *)W, (double *)deg, stats,
+                               base + L.gws[t & 1]);
+            if (st == CDL_OK) st = chain_enqueue(ctx, W, deg, stats, x.n, prec, depth, base + L.chain[t], false);
+            if (st != CDL_OK) break;
+            const SolveWs &w = solves[t];
+            const size_t panel = (size_t)kp * hs[t].ld * sizeof(double);
+            { Timed t_(ctx, "fill_zero"); HIPCHK(launch_fill_zero(w.Yt, panel, es)); }
+            { Timed t_(ctx, "fill_zero"); HIPCHK(launch_fill_zero(w.Xt, panel, es)); }
+            { Timed t_(ctx, "rhs"); HIPCHK(launch_rhs(W, hs[t].ld, x.n, x.gid, k, kp, q->seed, w.Yt, es)); }
+            HIPCHK(hipMemcpyAsync(status + (size_t)t * CDL_GRAPH_STATS, stats,
+                                  CDL_GRAPH_STATS * sizeof(double), hipMemcpyDeviceToDevice, es));
+        }
+        ctx->stream = s0;
+        HIPCHK(hipEventRecord(evs[1], s1));
+        HIPCHK(hipStreamWaitEvent(s0, evs[1], 0));
+        if (st != CDL_OK) return st;
+        for (int l = 0; l + 1 < depth; ++l)
+            { Timed t_(ctx, "square"); HIPCHK(cdl::launch_square_grouped(prec, dsnap, dtable(0), P, tot_sq, l, s0)); }
+        // done and iteration flags (their region is rounded up to 256 bytes)
+        { Timed t_(ctx, "fill_zero"); HIPCHK(launch_fill_zero(done, (2 * (size_t)P * sizeof(int) + 15) / 16 * 16, s0)); }
+        { Timed t_(ctx, "residual_init"); HIPCHK(cdl::launch_residual_grouped(prec, dsnap, dtable(3), tot_rg, dtable(4), tot_rr, P, kp, k, 1, done, s0)); }
+        { Timed t_(ctx, "col_norms"); HIPCHK(cdl::launch_norms_grouped(dsnap, P, kp, k, scaled, q->tol, 1, ynorm, rel, done, iters, s0)); }
+        for (int it = 0; it < q->max_iter; ++it) {
+            if (scaled) { Timed t_(ctx, "prep_v"); HIPCHK(cdl::launch_prep_grouped(prec, dsnap, dtable(5), tot_pv, P, kp, done, s0)); }
+            int cur = 0;
+            for (int l = 0; l < depth; ++l) {
+                { Timed t_(ctx, "apply"); HIPCHK(cdl::launch_apply_grouped(prec, dsnap, dtable(1), tot_ag, dtable(2), tot_ar, P, kp, l, cur, 1,
+                                                                     l + 1 == depth, done, s0)); }
+                cur ^= 1;
+            }
+            { Timed t_(ctx, "residual"); HIPCHK(cdl::launch_residual_grouped(prec, dsnap, dtable(3), tot_rg, dtable(4), tot_rr, P, kp, k, 0, done, s0)); }
+            { Timed t_(ctx, "col_norms"); HIPCHK(cdl::launch_norms_grouped(dsnap, P, kp, k, scaled, q->tol, 0, ynorm, rel, done, iters, s0)); }
+        }
+        for (int t = 0; t < P; ++t)
+            { Timed t_(ctx, "finalize_z"); HIPCHK(launch_finalize_z2(solves[t].Xt, hs[t].ld, sn[t].n, kp, k, solves[t].mean,
+                                                             (double *)(base + L.Z[t]), s0)); }
+        { Timed t_(ctx, "score"); HIPCHK(cdl::launch_score_grouped(dpair, dtable(6), tot_zh, dtable(7), tot_sc, dtable(8), tot_sr, NP, k, kp,
+                                                             weighted, s0)); }
+        if (top_idx && q->top_k > 0)
+            for (int t = 0; t < NP; ++t) {
+                Arena as(base + L.score[t]);
+                const ScoreWs sw = plan_score(as, mcnt[t], k);
+                const int32_t K = std::min<int32_t>(q->top_k, (int32_t)mcnt[t]);
+                Timed t_(ctx, "topk");
+                HIPCHK(launch_topk(F[t], mcnt[t], K, sw.topk, top_idx[t], s0));
+            }
+        return CDL_OK;
+    };
+    // the key of a graph: buffers, shapes, parameters, global ids
+    std::vector<uint64_t> key = {(uint64_t)n_snap, (uint64_t)(uintptr_t)ws, (uint64_t)L.total,
+                                 (uint64_t)q->k, q->seed, (uint64_t)q->prec, (uint64_t)q->depth,
+                                 (uint64_t)q->max_iter, (uint64_t)q->mode, (uint64_t)q->top_k,
+                                 (uint64_t)q->flags};
+    uint64_t bits;
+    std::memcpy(&bits, &q->sigma, sizeof(bits));
+    key.push_back(bits);
+    std::memcpy(&bits, &q->tol, sizeof(bits));
+    key.push_back(bits);
+    for (int t = 0; t < n_snap; ++t) {
+        uint64_t h = 1469598103934665603ull;
+        for (int64_t i = 0; i < sn[t].n; ++i) h = (h ^ (uint32_t)sn[t].gid_host[i]) * 1099511628211ull;
+        key.insert(key.end(), {(uint64_t)(uintptr_t)sn[t].X, (uint64_t)sn[t].n, (uint64_t)sn[t].T,
+                               (uint64_t)sn[t].ldx, (uint64_t)(uintptr_t)sn[t].gid, h,
+                               (uint64_t)(uintptr_t)(t + 1 < n_snap ? F[t] : nullptr),
+                               (uint64_t)(uintptr_t)(t + 1 < n_snap && top_idx ? top_idx[t] : nullptr)});
+        key.insert(key.end(), {(uint64_t)hs[t].ap_splits, (uint64_t)hs[t].res_splits});
+    }
+    cdl_status st = run_sequence(ctx, (q->flags & CDL_SEQ_GRAPH) != 0, key, enqueue, info);
+    if (st != CDL_OK) return st;
+    // one read-back: graph statistics, final residuals, iterations
+    std::vector<double> hst((size_t)P * CDL_GRAPH_STATS), hrel(P);
+    std::vector<int> hit(P), hdone(P);
+    HIPCHK(read_to_host(ctx, s, {{hst.data(), status, hst.size() * sizeof(double)},
+                                 {hrel.data(), rel, hrel.size() * sizeof(double)},
+                                 {hdone.data(), done, hdone.size() * sizeof(int)},
+                                 {hit.data(), iters, hit.size() * sizeof(int)}}));
+    double worst = 0.0;
+    int most = 0;
+    for (int t = 0; t < P; ++t) {
+        const double *h = hst.data() + (size_t)t * CDL_GRAPH_STATS;
+        for (int q2 = 0; q2 < CDL_GRAPH_STATS; ++q2)
+            if (!std::isfinite(h[q2])) return fail(ctx, CDL_E_NONFINITE, "snapshot " + std::to_string(t) + ": non-finite weights or degrees");
+        if (!(h[2] > 0.0)) return fail(ctx, CDL_E_GRAPH, "snapshot " + std::to_string(t) + ": a node has zero degree");
+        if (!std::isfinite(hrel[t])) return fail(ctx, CDL_E_NONFINITE, "snapshot " + std::to_string(t) + ": non-finite residual");
+        worst = std::max(worst, hrel[t]);
+        most = std::max(most, hit[t]);
+    }
+    if (info) {
+        info->pairs = NP;
+        info->max_iterations = most;
+        info->max_rel_residual = worst;
+    }
+    if (q->tol > 0.0 && worst > q->tol)
+        return fail(ctx, CDL_E_NOCONV, "residual " + std::to_string(worst) + " above tol after max_iter iterations");
+    return CDL_OK;
+}
+
 extern "C" {
 
 cdl_status cdl_sequence_workspace_bytes(int32_t n_snap, const cdl_snapshot *snaps,
@@ -1804,7 +2187,8 @@ cdl_status cdl_sequence_workspace_bytes(int32_t n_snap, const cdl_snapshot *snap
     if (n_snap < 2 || !snaps || !p || !bytes || p->k < 1) return CDL_E_ARG;
     for (int t = 0; t < n_snap; ++t)
         if (snaps[t].n < 2 || snaps[t].T < 1) return CDL_E_ARG;
-    *bytes = seq_bytes(seq_plan(n_snap, snaps), p);
+    *bytes = (p->flags & CDL_SEQ_BATCHED) ? batch_layout(n_snap, snaps, p).total
+                                           : seq_bytes(seq_plan(n_snap, snaps), p);
     return CDL_OK;
 }
 
@@ -1823,10 +2207,13 @@ cdl_status cdl_score_sequence(cdl_ctx *ctx, int32_t n_snap, const cdl_snapshot *
             return fail(ctx, CDL_E_ARG, "global ids must be in [0, 2^20)");
     }
     const SeqPlan plan = seq_plan(n_snap, sn);
-    if (ws_bytes < seq_bytes(plan, q)) return fail(ctx, CDL_E_WORKSPACE, "sequence workspace too small");
     const bool async = (q->flags & CDL_SEQ_ASYNC) != 0;
-    if ((q->flags & ~(CDL_SEQ_ASYNC | CDL_SEQ_GRAPH)) != 0 || ((q->flags & CDL_SEQ_GRAPH) && !async))
+    const bool batched = (q->flags & CDL_SEQ_BATCHED) != 0;
+    if ((q->flags & ~(CDL_SEQ_ASYNC | CDL_SEQ_GRAPH | CDL_SEQ_BATCHED)) != 0 ||
+        ((q->flags & (CDL_SEQ_GRAPH | CDL_SEQ_BATCHED)) && !async))
         return fail(ctx, CDL_E_ARG, "bad sequence flags");
+    if (ws_bytes < (batched ? batch_layout(n_snap, sn, q).total : seq_bytes(plan, q)))
+        return fail(ctx, CDL_E_WORKSPACE, "sequence workspace too small");
     if (async) {
         // the enqueue helpers check nothing: every argument is checked here
         if (q->depth < 1 || q->depth > CDL_MAX_DEPTH || q->solver != CDL_RICHARDSON || !(q->tol >= 0.0))
@@ -1842,6 +2229,11 @@ cdl_status cdl_score_sequence(cdl_ctx *ctx, int32_t n_snap, const cdl_snapshot *
                 return fail(ctx, CDL_E_ARG, "bad snapshot");
             if (t + 1 < n_snap && (!F[t] || !aligned(F[t], 8) || (q->top_k > 0 && top_idx && !top_idx[t])))
                 return fail(ctx, CDL_E_ARG, "bad output pointer");
+        }
+        if (batched) {
+            if (q->prec == CDL_FP64) return fail(ctx, CDL_E_ARG, "CDL_SEQ_BATCHED needs FP32, BF16 or FP16 levels");
+            if (n_snap > 4096) return fail(ctx, CDL_E_ARG, "CDL_SEQ_BATCHED takes at most 4096 snapshots");
+            return score_sequence_batched(ctx, n_snap, sn, q, F, top_idx, ws, info);
         }
     }
     const int dmax = q->depth > 0 ? q->depth : q->depth_max;
@@ -1964,71 +2356,8 @@ cdl_status cdl_score_sequence(cdl_ctx *ctx, int32_t n_snap, const cdl_snapshot *
                 st = fail(ctx, CDL_E_HIP, "event wait failed");
             return st;
         };
-        const bool timing = ctx->timing;
-        cdl_status st = CDL_OK;
-        const bool use_graph = (q->flags & CDL_SEQ_GRAPH) != 0;
-        if (!use_graph) {
-            // eager two-stream enqueue; a later graph call starts its key afresh
-            ctx->seq_key.clear();
-            if ((st = enqueue(s, ctx->side)) != CDL_OK) {
-                (void)hipStreamSynchronize(ctx->side);
-                return st;
-            }
-        } else if (key == ctx->seq_key && ctx->seq_exec) {
-            HIPCHK(hipGraphLaunch(ctx->seq_exec, s));
-            if (info) info->graph_launches = 1;
-        } else if (key == ctx->seq_key) {
-            // second identical call: capture the enqueue into a graph, on a
-            // private stream (the caller's may be the null stream, which
-            // cannot be captured), then launch it on the caller's stream
-            hipStream_t cap = nullptr, cap2 = nullptr;
-            HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-            const hipError_t e2 = hipStreamCreateWithFlags(&cap2, hipStreamNonBlocking);
-            if (e2 != hipSuccess) {
-                (void)hipStreamDestroy(cap);
-                HIPCHK(e2);
-            }
-            const hipError_t eb = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-            if (eb != hipSuccess) {
-                (void)hipStreamDestroy(cap);
-                (void)hipStreamDestroy(cap2);
-                HIPCHK(eb);
-            }
-            ctx->timing = false;
-            st = enqueue(cap, cap2);   // cap2 joins the capture through the fork event
-            hipGraph_t g = nullptr;
-            const hipError_t ec = hipStreamEndCapture(cap, &g);
-            ctx->stream = s;
-            ctx->timing = timing;
-            (void)hipStreamDestroy(cap);
-            (void)hipStreamDestroy(cap2);
-            if (st != CDL_OK || ec != hipSuccess) {
-                if (g) (void)hipGraphDestroy(g);
-                ctx->seq_key.clear();
-                if (st != CDL_OK) return st;
-                HIPCHK(ec);
-            }
-            hipGraphExec_t ex = nullptr;
-            const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-            if (ei != hipSuccess) {
-                (void)hipGraphDestroy(g);
-                HIPCHK(ei);
-            }
-            ctx->seq_graph = g;
-            ctx->seq_exec = ex;
-            HIPCHK(hipGraphLaunch(ex, s));
-            if (info) info->graph_launches = 1;
-        } else {
-            if (ctx->seq_exec) (void)hipGraphExecDestroy(ctx->seq_exec);
-            if (ctx->seq_graph) (void)hipGraphDestroy(ctx->seq_graph);
-            ctx->seq_exec = nullptr;
-            ctx->seq_graph = nullptr;
-            ctx->seq_key = key;
-            if ((st = enqueue(s, ctx->side)) != CDL_OK) {
-                (void)hipStreamSynchronize(ctx->side);   // nothing may stay in flight on the side stream
-                return st;
-            }
-        }
+        cdl_status st = run_sequence(ctx, (q->flags & CDL_SEQ_GRAPH) != 0, key, enqueue, info);
+        if (st != CDL_OK) return st;
         // one read-back for the whole sequence: graph checks and residuals
         std::vector<double> hs((size_t)n_snap * (CDL_GRAPH_STATS + 2 * kp));
         HIPCHK(read_to_host(ctx, s, {{hs.data(), status, hs.size() * sizeof(double)}}));

@@ -20,6 +20,7 @@
 // divide the scale back out.
 #include <type_traits>
 
+#include "batch.h"
 #include "common.h"
 #include "gemm.h"
 #include "kernels.h"
@@ -281,6 +282,22 @@ __device__ inline void square_epilogue(Core &g, const T *A, const T *B, T *S2, i
 // C = A B over the upper tiles with logical ids [0, count) (count = all
 // tiles, or the full rounds of 256 workgroups when the last round is split
 // over k below).  The squaring is A = B = S, add = 0.
+// Upper tile `id` of C = A B and its epilogue (one workgroup).
+template <typename T, int NW>
+__device__ inline void square_tile(const T *A, const T *B, T *S2, int64_t ld, int64_t kend, int nt,
+                                   int id, float inv_scale, int add, double *fro_part,
+                                   char *smem_raw, double *red) {
+    using Core = typename SqCfg<T, NW>::Core;
+    constexpr int TL = SqCfg<T, NW>::TILE;
+    int I, J;
+    sym_tile<8>(id, nt, I, J);
+    const int64_t m0 = (int64_t)I * TL, n0 = (int64_t)J * TL;
+    Core g;
+    g.run(A, ld, B, ld, m0, n0, kend, (T *)smem_raw);
+    square_epilogue<T>(g, A, B, S2, ld, m0, n0, I != J, inv_scale, add, fro_part + id,
+                       (T *)smem_raw, red);
+}
+
 template <typename T, int NW>
 __global__ __launch_bounds__((SqCfg<T, NW>::Core::NT)) void k_square(const T *A, const T *B, T *S2, int64_t ld,
                                                 int64_t kend, int nt, int count, float inv_scale,
@@ -290,13 +307,25 @@ __global__ __launch_bounds__((SqCfg<T, NW>::Core::NT)) void k_square(const T *A,
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
     __shared__ double red[Core::NT / 64];
     const int id = TL == 256 ? round_remap(blockIdx.x, count) : xcd_remap(blockIdx.x, count);
-    int I, J;
-    sym_tile<8>(id, nt, I, J);
-    const int64_t m0 = (int64_t)I * TL, n0 = (int64_t)J * TL;
-    Core g;
-    g.run(A, ld, B, ld, m0, n0, kend, (T *)smem_raw);
-    square_epilogue<T>(g, A, B, S2, ld, m0, n0, I != J, inv_scale, add, fro_part + id,
-                       (T *)smem_raw, red);
+    square_tile<T, NW>(A, B, S2, ld, kend, nt, id, inv_scale, add, fro_part, smem_raw, red);
+}
+
+// Level `level` squared into level + 1 for every snapshot of a sequence:
+// workgroup b is upper tile b - prefix[p] of snapshot p.
+template <typename T>
+__global__ __launch_bounds__((SqCfg<T, 8>::Core::NT)) void k_square_grouped(const BatchSnap *snaps,
+                                                                           const int *prefix, int P,
+                                                                           int level) {
+    using Core = typename SqCfg<T, 8>::Core;
+    constexpr int TL = SqCfg<T, 8>::TILE;
+    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+    __shared__ double red[Core::NT / 64];
+    const int p = group_find(prefix, P, blockIdx.x);
+    const BatchSnap &d = snaps[p];
+    const T *A = (const T *)(d.levels + d.level_bytes * level);
+    T *C = (T *)(d.levels + d.level_bytes * (level + 1));
+    square_tile<T, 8>(A, A, C, d.ld, (d.n + 63) / 64 * 64, (int)(d.ld / TL), blockIdx.x - prefix[p],
+                      d.inv_scale, 0, d.fro, smem_raw, red);
 }
 
 // The tiles of the last, partial round of workgroups (logical ids
@@ -513,15 +542,13 @@ template <typename T, int BM> struct ApCfg {
                                     GemmCore<Mf, BM, 256, ApBK<T>::v, WM, WN>>;
 };
 
+// Split-K product tile `id` of the chain application (one workgroup).
 template <typename T, int BM>
-__global__ __launch_bounds__(512) void k_apply_gemm(const T *Vin, const T *S, int64_t ld,
-                                                    int64_t kend, int64_t ks, int mt, int nt,
-                                                    int nsplit, float *P, int64_t kpad) {
+__device__ inline void apply_gemm_tile(const T *Vin, const T *S, int64_t ld, int64_t kend,
+                                       int64_t ks, int mt, int nt, float *P, int64_t kpad, int id,
+                                       char *smem_raw) {
     using Core = typename ApCfg<T, BM>::Core;
-    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
     T *smem = (T *)smem_raw;
-    const int total = mt * nt * nsplit;
-    const int id = xcd_remap(blockIdx.x, total);
     const int split = id / (mt * nt);
     int I, J;
     rect_tile<4>(id % (mt * nt), mt, nt, I, J);
@@ -540,7 +567,22 @@ __global__ __launch_bounds__(512) void k_apply_gemm(const T *Vin, const T *S, in
                 Ps[(m0 + Core::row_of(a, r)) * ld + n0 + Core::col_of(b)] = g.acc[a][b][r];
 }
 
+template <typename T, int BM>
+__global__ __launch_bounds__(512) void k_apply_gemm(const T *Vin, const T *S, int64_t ld,
+                                                    int64_t kend, int64_t ks, int mt, int nt,
+                                                    int nsplit, float *P, int64_t kpad) {
+    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+    const int id = xcd_remap(blockIdx.x, mt * nt * nsplit);
+    apply_gemm_tile<T, BM>(Vin, S, ld, kend, ks, mt, nt, P, kpad, id, smem_raw);
+}
+
 static int ap_bm(int64_t kpad) { return kpad % 256 == 0 ? 256 : (kpad % 128 == 0 ? 128 : 64); }
+
+// k-range of one split of an application's product (64-element multiples).
+__host__ __device__ inline int64_t apply_split_len(int64_t n, int nsplit) {
+    const int64_t kend = (n + 63) / 64 * 64;
+    return (cdiv(kend, nsplit) + 63) / 64 * 64;
+}
 
 // Split-K count of the chain application: choice 0 aims at >= 256
 // workgroups, 1 halves that count, 2 doubles it (at least two 64-wide
@@ -558,15 +600,14 @@ int apply_splits(int prec, int64_t ld, int64_t kpad, int64_t n, int choice) {
     return (int)S;
 }
 
+// Elements first, first + step, ... (< total) of the application's update.
 template <typename T>
-__global__ __launch_bounds__(256) void k_apply_reduce(const float *P, int nsplit, int64_t total,
-                                                      int64_t ld, int64_t kpad, float inv_scale,
-                                                      int accumulate, double *V64, T *Vout,
-                                                      double *Xt, const double *dm,
-                                                      const double *inv_vs) {
+__device__ inline void apply_reduce_range(const float *P, int nsplit, int64_t total, int64_t ld,
+                                          int64_t kpad, float inv_scale, int accumulate,
+                                          double *V64, T *Vout, double *Xt, const double *dm,
+                                          const double *inv_vs, int64_t first, int64_t step) {
     const double ivs = inv_vs ? *inv_vs : 0.0;
-    for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < total;
-         o += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t o = first; o < total; o += step) {
         float acc = 0.f;
         for (int q = 0; q < nsplit; ++q) acc += P[(int64_t)q * kpad * ld + o];
         const double v = (accumulate ? V64[o] : 0.0) + (double)acc * (double)inv_scale;
@@ -574,6 +615,17 @@ __global__ __launch_bounds__(256) void k_apply_reduce(const float *P, int nsplit
         Vout[o] = cvtd<T>(v);
         if (inv_vs) Xt[o] += dm[o % ld] * v * ivs;
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_apply_reduce(const float *P, int nsplit, int64_t total,
+                                                      int64_t ld, int64_t kpad, float inv_scale,
+                                                      int accumulate, double *V64, T *Vout,
+                                                      double *Xt, const double *dm,
+                                                      const double *inv_vs) {
+    apply_reduce_range<T>(P, nsplit, total, ld, kpad, inv_scale, accumulate, V64, Vout, Xt, dm,
+                          inv_vs, (int64_t)blockIdx.x * blockDim.x + threadIdx.x,
+                          (int64_t)gridDim.x * blockDim.x);
 }
 
 template <typename T, int BM>
@@ -618,6 +670,119 @@ static hipError_t ap_split_launch(const void *Vin, const void *S, void *Vout, do
     hipLaunchKernelGGL(k_apply_reduce<T>, dim3(grid), dim3(256), 0, s, P, ns, total, ld, kpad,
                        inv_scale, accumulate, V64, (T *)Vout, Xt, dm, inv_vs);
     return hipGetLastError();
+}
+
+// ---- grouped over the snapshots of a sequence ----------------------------
+
+template <typename T, int BM>
+__global__ __launch_bounds__(512) void k_apply_gemm_grouped(const BatchSnap *snaps, const int *prefix,
+                                                            int P, int64_t kpad, int level, int in,
+                                                            const int *done) {
+    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+    const int p = group_find(prefix, P, blockIdx.x);
+    if (done[p]) return;
+    const BatchSnap &d = snaps[p];
+    const int mt = (int)(kpad / BM), nt = (int)(d.ld / 256);
+    const int count = prefix[p + 1] - prefix[p];
+    const int id = xcd_remap(blockIdx.x - prefix[p], count);
+    apply_gemm_tile<T, BM>((const T *)d.Vlo[in], (const T *)(d.levels + d.level_bytes * level), d.ld,
+                           (d.n + 63) / 64 * 64, apply_split_len(d.n, d.ap_splits), mt, nt, d.Pap,
+                           kpad, id, smem_raw);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_apply_reduce_grouped(const BatchSnap *snaps, const int *prefix,
+                                                              int P, int64_t kpad, int in,
+                                                              int accumulate, int last,
+                                                              const int *done) {
+    const int p = group_find(prefix, P, blockIdx.x);
+    if (done[p]) return;
+    const BatchSnap &d = snaps[p];
+    const int64_t nb = prefix[p + 1] - prefix[p];
+    apply_reduce_range<T>(d.Pap, d.ap_splits, kpad * d.ld, d.ld, kpad, d.inv_scale, accumulate,
+                          d.V64, (T *)d.Vlo[in ^ 1], d.Xt, d.dm, last ? d.scal + kpad + 1 : nullptr,
+                          (int64_t)(blockIdx.x - prefix[p]) * 256 + threadIdx.x, nb * 256);
+}
+
+int apply_gemm_tiles(int64_t ld, int64_t kpad, int nsplit) {
+    return (int)(kpad / ap_bm(kpad) * (ld / 256)) * nsplit;
+}
+
+int apply_reduce_blocks(int64_t ld, int64_t kpad) {
+    const int64_t b = cdiv(kpad * ld, 256);
+    return (int)(b < 2048 ? b : 2048);
+}
+
+template <typename T, int BM>
+static hipError_t apply_grouped_launch(const BatchSnap *snaps, const int *prefix_gemm, int total_gemm,
+                                       const int *prefix_red, int total_red, int P, int64_t kpad,
+                                       int level, int in, int accumulate, int last, const int *done,
+                                       hipStream_t s) {
+    using Core = typename ApCfg<T, BM>::Core;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_apply_gemm_grouped<T, BM>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)Core::SMEM);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL((k_apply_gemm_grouped<T, BM>), dim3(total_gemm), dim3(512), Core::SMEM, s, snaps,
+                       prefix_gemm, P, kpad, level, in, done);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_apply_reduce_grouped<T>, dim3(total_red), dim3(256), 0, s, snaps, prefix_red,
+                       P, kpad, in, accumulate, last, done);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t apply_grouped_bm(const BatchSnap *snaps, const int *pg, int tg, const int *pr,
+                                   int tr, int P, int64_t kpad, int level, int in, int accumulate,
+                                   int last, const int *done, hipStream_t s) {
+    switch (ap_bm(kpad)) {
+    case 256: return apply_grouped_launch<T, 256>(snaps, pg, tg, pr, tr, P, kpad, level, in, accumulate, last, done, s);
+    case 128: return apply_grouped_launch<T, 128>(snaps, pg, tg, pr, tr, P, kpad, level, in, accumulate, last, done, s);
+    default: return apply_grouped_launch<T, 64>(snaps, pg, tg, pr, tr, P, kpad, level, in, accumulate, last, done, s);
+    }
+}
+
+hipError_t launch_apply_grouped(int prec, const BatchSnap *snaps, const int *prefix_gemm,
+                                int total_gemm, const int *prefix_red, int total_red, int P,
+                                int64_t kpad, int level, int in, int accumulate, int last,
+                                const int *done, hipStream_t s) {
+    switch (prec) {
+    case 1: return apply_grouped_bm<float>(snaps, prefix_gemm, total_gemm, prefix_red, total_red, P, kpad, level, in, accumulate, last, done, s);
+    case 2: return apply_grouped_bm<__bf16>(snaps, prefix_gemm, total_gemm, prefix_red, total_red, P, kpad, level, in, accumulate, last, done, s);
+    case 3: return apply_grouped_bm<_Float16>(snaps, prefix_gemm, total_gemm, prefix_red, total_red, P, kpad, level, in, accumulate, last, done, s);
+    default: return hipErrorInvalidValue;   // FP64 chains are not grouped
+    }
+}
+
+template <typename T>
+static hipError_t square_grouped_launch(const BatchSnap *snaps, const int *prefix, int P, int total,
+                                        int level, hipStream_t s) {
+    constexpr size_t smem = sq_smem<T, 8>();
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_square_grouped<T>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL(k_square_grouped<T>, dim3(total), dim3(SqCfg<T, 8>::Core::NT), smem, s, snaps,
+                       prefix, P, level);
+    return hipGetLastError();
+}
+
+hipError_t launch_square_grouped(int prec, const BatchSnap *snaps, const int *prefix, int P,
+                                 int total, int level, hipStream_t s) {
+    switch (prec) {
+    case 1: return square_grouped_launch<float>(snaps, prefix, P, total, level, s);
+    case 2: return square_grouped_launch<__bf16>(snaps, prefix, P, total, level, s);
+    case 3: return square_grouped_launch<_Float16>(snaps, prefix, P, total, level, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 // FP64 levels: in-epilogue update (small n only in practice).

@@ -15,6 +15,7 @@
 //   edges       the K largest edge scores (a < b) exactly: per-tile maxima
 //               from k_score, threshold = K-th largest tile maximum, only
 //               tiles reaching it recomputed and their edges collected
+#include "batch.h"
 #include "caddelag.h"
 #include "common.h"
 #include "gemm.h"
@@ -22,12 +23,11 @@
 
 namespace cdl {
 
-// One wave per common node.
-__global__ void k_build_zhat(const double *Z0, const double *Z1, const int32_t *map0,
-                             const int32_t *map1, int64_t m, int64_t k, int64_t kpad,
-                             const double *stats0, const double *stats1, double *Zh,
-                             double *Zhe, double *sq) {
-    const int64_t c = blockIdx.x;
+// Row c of the signature embeddings (one wave).
+__device__ inline void build_zhat_row(const double *Z0, const double *Z1, const int32_t *map0,
+                                      const int32_t *map1, int64_t m, int64_t k, int64_t kpad,
+                                      const double *stats0, const double *stats1, double *Zh,
+                                      double *Zhe, double *sq, int64_t c) {
     const int lane = threadIdx.x;
     const double s0 = sqrt(stats0[0]), s1 = sqrt(stats1[0]);
     const int64_t ldz = 2 * kpad;
@@ -52,6 +52,14 @@ __global__ void k_build_zhat(const double *Z0, const double *Z1, const int32_t *
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
     if (lane == 0) sq[c] = acc;
+}
+
+// One wave per common node.
+__global__ void k_build_zhat(const double *Z0, const double *Z1, const int32_t *map0,
+                             const int32_t *map1, int64_t m, int64_t k, int64_t kpad,
+                             const double *stats0, const double *stats1, double *Zh,
+                             double *Zhe, double *sq) {
+    build_zhat_row(Z0, Z1, map0, map1, m, k, kpad, stats0, stats1, Zh, Zhe, sq, blockIdx.x);
 }
 
 hipError_t launch_build_zhat(const double *Z0, const double *Z1, const int32_t *map0,
@@ -89,18 +97,22 @@ __device__ inline double edge_score(int64_t ga, int64_t gb, double G, double sqa
 // part[J][a], column b's sum over the rows of the tile to part[ncol + I][b];
 // each slot has exactly one writer.  tmax != nullptr: also the largest edge
 // score of the tile over a < b, at the tile's logical index.
-__global__ __launch_bounds__(512) void k_score(const double *Zh, const double *Zhe,
-                                               int64_t ldz, const double *sq, int64_t m,
-                                               int64_t mpad, const double *W0, int64_t ld0,
-                                               const double *W1, int64_t ld1,
-                                               const int32_t *map0, const int32_t *map1,
-                                               int weighted, int ncol, double *part,
-                                               double *tmax) {
-    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+struct ScoreShared {
+    double srow[kScoreWN][256], scol[kScoreWM][128], smax[8];
+};
+
+// Upper-triangle tile `id` of the score Gram with its partial sums (one
+// workgroup).
+__device__ inline void score_tile(const double *Zh, const double *Zhe, int64_t ldz,
+                                  const double *sq, int64_t m, int64_t mpad, const double *W0,
+                                  int64_t ld0, const double *W1, int64_t ld1,
+                                  const int32_t *map0, const int32_t *map1, int weighted,
+                                  int ncol, double *part, double *tmax, int id, char *smem_raw,
+                                  ScoreShared &sh) {
     double *smem = (double *)smem_raw;
-    __shared__ double srow[kScoreWN][256], scol[kScoreWM][128], smax[8];
-    const int total = rect_upper_tiles(mpad);
-    const int id = xcd_remap(blockIdx.x, total);
+    auto &srow = sh.srow;
+    auto &scol = sh.scol;
+    auto &smax = sh.smax;
     int I, J;
     upper_rect_tile(id, ncol, I, J);
     const int64_t m0 = (int64_t)I * 256, n0 = (int64_t)J * 128;
@@ -169,6 +181,20 @@ __global__ __launch_bounds__(512) void k_score(const double *Zh, const double *Z
         for (int q = 0; q < kScoreWM; ++q) cs2 += scol[q][t];
         part[(int64_t)(ncol + I) * mpad + n0 + t] = cs2;
     }
+}
+
+__global__ __launch_bounds__(512) void k_score(const double *Zh, const double *Zhe,
+                                               int64_t ldz, const double *sq, int64_t m,
+                                               int64_t mpad, const double *W0, int64_t ld0,
+                                               const double *W1, int64_t ld1,
+                                               const int32_t *map0, const int32_t *map1,
+                                               int weighted, int ncol, double *part,
+                                               double *tmax) {
+    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+    __shared__ ScoreShared sh;
+    const int id = xcd_remap(blockIdx.x, rect_upper_tiles(mpad));
+    score_tile(Zh, Zhe, ldz, sq, m, mpad, W0, ld0, W1, ld1, map0, map1, weighted, ncol, part, tmax,
+               id, smem_raw, sh);
 }
 
 int score_tiles_1d(int64_t mpad) { return (int)(mpad / 128 + mpad / 256); }
@@ -296,15 +322,71 @@ hipError_t launch_check_maps(const int32_t *map0, const int32_t *map1, int64_t m
 // F_a = its row partials over the column blocks J >= 2 (a / 256), then its
 // column partials over the row blocks I <= (a / 128) / 2: exactly the slots
 // the score tiles wrote, summed in a fixed order.
-__global__ void k_score_reduce(const double *part, int ncol, int64_t m, int64_t mpad,
-                               double *F) {
-    int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ inline void score_reduce_node(const double *part, int ncol, int64_t m, int64_t mpad,
+                                         double *F, int64_t a) {
     if (a >= m) return;
     const int J0 = (int)(a / 256) * 2;
     double s = J0 < ncol ? ordered_sum(part + (int64_t)J0 * mpad + a, mpad, ncol - J0, 0.0) : 0.0;
     const int Imax = (int)(a / 128) / 2;
     s = ordered_sum(part + (int64_t)ncol * mpad + a, mpad, Imax + 1, s);
     F[a] = s;
+}
+
+__global__ void k_score_reduce(const double *part, int ncol, int64_t m, int64_t mpad,
+                               double *F) {
+    score_reduce_node(part, ncol, m, mpad, F, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// ---- grouped over the pairs of a sequence ------------------------------------
+
+__global__ void k_build_zhat_grouped(const BatchPair *pairs, const int *prefix, int P, int64_t k,
+                                     int64_t kpad) {
+    const int p = group_find(prefix, P, blockIdx.x);
+    const BatchPair &q = pairs[p];
+    build_zhat_row(q.Z0, q.Z1, q.map0, q.map1, q.m, k, kpad, q.stats0, q.stats1, q.Zh, q.Zhe, q.sq,
+                   blockIdx.x - prefix[p]);
+}
+
+__global__ __launch_bounds__(512) void k_score_grouped(const BatchPair *pairs, const int *prefix, int P,
+                                                       int64_t kpad, int weighted) {
+    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+    __shared__ ScoreShared sh;
+    const int p = group_find(prefix, P, blockIdx.x);
+    const BatchPair &q = pairs[p];
+    const int id = xcd_remap(blockIdx.x - prefix[p], prefix[p + 1] - prefix[p]);
+    score_tile(q.Zh, q.Zhe, 2 * kpad, q.sq, q.m, q.mpad, q.W0, q.ld0, q.W1, q.ld1, q.map0, q.map1,
+               weighted, (int)(q.mpad / 128), q.part, nullptr, id, smem_raw, sh);
+}
+
+__global__ void k_score_reduce_grouped(const BatchPair *pairs, const int *prefix, int P) {
+    const int p = group_find(prefix, P, blockIdx.x);
+    const BatchPair &q = pairs[p];
+    score_reduce_node(q.part, (int)(q.mpad / 128), q.m, q.mpad, q.F,
+                      (int64_t)(blockIdx.x - prefix[p]) * blockDim.x + threadIdx.x);
+}
+
+hipError_t launch_score_grouped(const BatchPair *pairs, const int *prefix_zhat, int total_zhat,
+                                const int *prefix_score, int total_score,
+                                const int *prefix_red, int total_red, int P, int64_t k,
+                                int64_t kpad, int weighted, hipStream_t s) {
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_score_grouped,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)ScoreCore::SMEM);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL(k_build_zhat_grouped, dim3(total_zhat), dim3(64), 0, s, pairs, prefix_zhat, P,
+                       k, kpad);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_score_grouped, dim3(total_score), dim3(ScoreCore::NT), ScoreCore::SMEM, s,
+                       pairs, prefix_score, P, kpad, weighted);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_score_reduce_grouped, dim3(total_red), dim3(64), 0, s, pairs, prefix_red, P);
+    return hipGetLastError();
 }
 
 hipError_t launch_score_reduce(const double *part, int nparts, int64_t m, int64_t mpad,

@@ -18,6 +18,7 @@
 //
 // Vectors of k columns are stored transposed: row r of a kpad x ld panel
 // holds column r over all (padded) nodes.
+#include "batch.h"
 #include "common.h"
 #include "gemm.h"
 #include "kernels.h"
@@ -407,15 +408,11 @@ template <int BM> struct ResCfg {
 // W may be a row panel: its row q holds node row0 + q, whose products land in
 // column row0 + q of the partials (row0 = 0 for the whole matrix).
 template <int BM>
-__global__ __launch_bounds__(512) void k_residual_gemm(const double *Xt, const double *W,
-                                                       int64_t ld, int64_t kend, int64_t ks,
-                                                       int mt, int nt, int S, double *P,
-                                                       int64_t kpad, int64_t row0) {
+__device__ inline void residual_gemm_tile(const double *Xt, const double *W, int64_t ld,
+                                          int64_t kend, int64_t ks, int mt, int nt, double *P,
+                                          int64_t kpad, int64_t row0, int id, char *smem_raw) {
     using Core = typename ResCfg<BM>::Core;
-    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
     double *smem = (double *)smem_raw;
-    const int total = mt * nt * S;
-    const int id = xcd_remap(blockIdx.x, total);
     // split-major order: the WGs of one split stream the same K range
     const int split = id / (mt * nt);
     int I, J;
@@ -435,7 +432,23 @@ __global__ __launch_bounds__(512) void k_residual_gemm(const double *Xt, const d
                 Ps[(m0 + Core::row_of(a, rr)) * ld + n0 + Core::col_of(b)] = g.acc[a][b][rr];
 }
 
+template <int BM>
+__global__ __launch_bounds__(512) void k_residual_gemm(const double *Xt, const double *W,
+                                                       int64_t ld, int64_t kend, int64_t ks,
+                                                       int mt, int nt, int S, double *P,
+                                                       int64_t kpad, int64_t row0) {
+    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+    const int id = xcd_remap(blockIdx.x, mt * nt * S);
+    residual_gemm_tile<BM>(Xt, W, ld, kend, ks, mt, nt, P, kpad, row0, id, smem_raw);
+}
+
 static int res_bm(int64_t kpad) { return kpad % 256 == 0 ? 256 : (kpad % 128 == 0 ? 128 : 64); }
+
+// k-range of one split of the residual product (16-element multiples).
+__host__ __device__ inline int64_t residual_split_len(int64_t n, int S) {
+    const int64_t kend = (n + 63) / 64 * 64;
+    return (cdiv(kend, S) + 15) / 16 * 16;
+}
 
 // Split-K count of the FP64 residual product: choice 0 aims at >= 256
 // workgroups, 1 halves that count, 2 doubles it (at least four 16-wide
@@ -509,13 +522,14 @@ hipError_t launch_panel_product(const double *Vt, const double *Wp, int64_t ld, 
 // reads as zero, giving -L X); optional
 // V = dm R (FP64) and V rounded to the chain type; per (256-node block, r)
 // partial sums of R^2 and per-block maxima of |dm R|.
+// Node block bx, column r of the residual's reduction (one workgroup).
 template <typename T>
-__global__ __launch_bounds__(256) void k_residual_reduce(
+__device__ inline void residual_reduce_block(
     const double *P, int S, const double *Yt, const double *Xt, const double *deg,
     const double *dm, int64_t ld, int64_t n, int64_t k, int64_t kpad, int skip_gemm,
-    double *Rt, double *V64, T *Vlo, double *npart, double *mpart) {
-    __shared__ double red[4], redm[4];
-    const int64_t r = blockIdx.y, i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double *Rt, double *V64, T *Vlo, double *npart, double *mpart, int64_t bx, int64_t r,
+    double *red, double *redm) {
+    const int64_t i = bx * 256 + threadIdx.x;
     const int64_t o = r * ld + i;
     double R = 0.0;
     if (r < k && i < n) {
@@ -542,9 +556,19 @@ __global__ __launch_bounds__(256) void k_residual_reduce(
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        npart[(int64_t)blockIdx.x * kpad + r] = (red[0] + red[1]) + (red[2] + red[3]);
-        mpart[(int64_t)blockIdx.x * kpad + r] = fmax(fmax(redm[0], redm[1]), fmax(redm[2], redm[3]));
+        npart[bx * kpad + r] = (red[0] + red[1]) + (red[2] + red[3]);
+        mpart[bx * kpad + r] = fmax(fmax(redm[0], redm[1]), fmax(redm[2], redm[3]));
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_residual_reduce(
+    const double *P, int S, const double *Yt, const double *Xt, const double *deg,
+    const double *dm, int64_t ld, int64_t n, int64_t k, int64_t kpad, int skip_gemm,
+    double *Rt, double *V64, T *Vlo, double *npart, double *mpart) {
+    __shared__ double red[4], redm[4];
+    residual_reduce_block<T>(P, S, Yt, Xt, deg, dm, ld, n, k, kpad, skip_gemm, Rt, V64, Vlo, npart,
+                             mpart, blockIdx.x, blockIdx.y, red, redm);
 }
 
 hipError_t launch_residual_reduce(const double *P, int S, const double *Yt, const double *Xt,
@@ -657,11 +681,9 @@ int residual_tiles(int64_t ld, int64_t kpad) { return (int)(ld / 256 * kpad); }
 // out[r] = ||R_r|| (fixed-order sum of the partials), r < kpad; block kpad
 // writes out[kpad] = scale, out[kpad+1] = 1/scale: a power of two bringing
 // max |D^{-1/2} R| into [0.5, 1) when `scaled`, else 1.
-__global__ __launch_bounds__(256) void k_col_norms(const double *npart, int nparts,
-                                                   int64_t kpad, const double *mpart,
-                                                   int ntiles, int scaled, double *out) {
-    __shared__ double red[4];
-    const int64_t r = blockIdx.x;
+__device__ inline void col_norms_block(const double *npart, int nparts, int64_t kpad,
+                                       const double *mpart, int ntiles, int scaled, double *out,
+                                       int64_t r, double *red) {
     if (r < kpad) {
         double s = 0.0;
         for (int p = threadIdx.x; p < nparts; p += 256) s += npart[(int64_t)p * kpad + r];
@@ -687,6 +709,13 @@ __global__ __launch_bounds__(256) void k_col_norms(const double *npart, int npar
     }
 }
 
+__global__ __launch_bounds__(256) void k_col_norms(const double *npart, int nparts,
+                                                   int64_t kpad, const double *mpart,
+                                                   int ntiles, int scaled, double *out) {
+    __shared__ double red[4];
+    col_norms_block(npart, nparts, kpad, mpart, ntiles, scaled, out, blockIdx.x, red);
+}
+
 hipError_t launch_col_norms2(const double *npart, int nparts, int64_t kpad, const double *mpart,
                              int ntiles, int scaled, double *out, hipStream_t s) {
     hipLaunchKernelGGL(k_col_norms, dim3((unsigned)kpad + 1), dim3(256), 0, s, npart, nparts, kpad,
@@ -695,16 +724,23 @@ hipError_t launch_col_norms2(const double *npart, int nparts, int64_t kpad, cons
 }
 
 template <typename T>
-__global__ void k_prep_v(const double *Rt, const double *dm, int64_t ld, int64_t total,
-                         const double *scal, double scale_lo, double *V64, T *Vlo) {
+__device__ inline void prep_v_range(const double *Rt, const double *dm, int64_t ld, int64_t total,
+                                    const double *scal, double scale_lo, double *V64, T *Vlo,
+                                    int64_t first, int64_t step) {
     const double sc = *scal;
-    for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < total;
-         o += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t o = first; o < total; o += step) {
         const int64_t col = o % ld;
         const double v = sc * dm[col] * Rt[o];
         V64[o] = v;
         Vlo[o] = cvtd<T>(v * scale_lo);
     }
+}
+
+template <typename T>
+__global__ void k_prep_v(const double *Rt, const double *dm, int64_t ld, int64_t total,
+                         const double *scal, double scale_lo, double *V64, T *Vlo) {
+    prep_v_range<T>(Rt, dm, ld, total, scal, scale_lo, V64, Vlo,
+                    (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
 }
 
 hipError_t launch_prep_v2(int prec, const double *Rt, const double *dm, int64_t ld, int64_t kpad,
@@ -717,6 +753,166 @@ hipError_t launch_prep_v2(int prec, const double *Rt, const double *dm, int64_t 
     case 2: hipLaunchKernelGGL(k_prep_v<__bf16>, dim3(grid), dim3(256), 0, s, Rt, dm, ld, total, scal, 1.0, V64, (__bf16 *)Vlo); break;
     case 3: hipLaunchKernelGGL(k_prep_v<_Float16>, dim3(grid), dim3(256), 0, s, Rt, dm, ld, total, scal, 1.0, V64, (_Float16 *)Vlo); break;
     default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Grouped over the snapshots of a sequence (one launch for all of them;
+// converged snapshots skip their workgroups).
+
+template <int BM>
+__global__ __launch_bounds__(512) void k_residual_gemm_grouped(const BatchSnap *snaps, const int *prefix,
+                                                               int P, int64_t kpad, const int *done) {
+    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+    const int p = group_find(prefix, P, blockIdx.x);
+    if (done[p]) return;
+    const BatchSnap &d = snaps[p];
+    const int mt = (int)(kpad / BM), nt = (int)(d.ld / 128);
+    const int id = xcd_remap(blockIdx.x - prefix[p], prefix[p + 1] - prefix[p]);
+    residual_gemm_tile<BM>(d.Xt, d.W, d.ld, (d.n + 63) / 64 * 64, residual_split_len(d.n, d.res_splits),
+                           mt, nt, d.Pres, kpad, 0, id, smem_raw);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_residual_reduce_grouped(const BatchSnap *snaps, const int *prefix,
+                                                                 int P, int64_t kpad, int64_t k,
+                                                                 int skip_gemm, int fused,
+                                                                 const int *done) {
+    __shared__ double red[4], redm[4];
+    const int p = group_find(prefix, P, blockIdx.x);
+    if (done[p]) return;
+    const BatchSnap &d = snaps[p];
+    const int64_t nb = d.ld / 256, lb = blockIdx.x - prefix[p];
+    residual_reduce_block<T>(d.Pres, d.res_splits, d.Yt, d.Xt, d.deg, d.dm, d.ld, d.n, k, kpad,
+                             skip_gemm, d.Rt, d.V64, fused ? (T *)d.Vlo[0] : (T *)nullptr, d.npart,
+                             d.mpart, lb % nb, lb / nb, red, redm);
+}
+
+template <int BM>
+static hipError_t resg_grouped_launch(const BatchSnap *snaps, const int *prefix, int total, int P,
+                                      int64_t kpad, const int *done, hipStream_t s) {
+    using Core = typename ResCfg<BM>::Core;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_residual_gemm_grouped<BM>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)Core::SMEM);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL(k_residual_gemm_grouped<BM>, dim3(total), dim3(512), Core::SMEM, s, snaps,
+                       prefix, P, kpad, done);
+    return hipGetLastError();
+}
+
+int residual_gemm_tiles(int64_t ld, int64_t kpad, int S) {
+    return (int)(kpad / res_bm(kpad) * (ld / 128)) * S;
+}
+
+hipError_t launch_residual_grouped(int prec, const BatchSnap *snaps, const int *prefix_gemm,
+                                   int total_gemm, const int *prefix_red, int total_red, int P,
+                                   int64_t kpad, int64_t k, int skip_gemm, const int *done,
+                                   hipStream_t s) {
+    if (!skip_gemm) {
+        hipError_t e;
+        switch (res_bm(kpad)) {
+        case 256: e = resg_grouped_launch<256>(snaps, prefix_gemm, total_gemm, P, kpad, done, s); break;
+        case 128: e = resg_grouped_launch<128>(snaps, prefix_gemm, total_gemm, P, kpad, done, s); break;
+        default: e = resg_grouped_launch<64>(snaps, prefix_gemm, total_gemm, P, kpad, done, s); break;
+        }
+        if (e != hipSuccess) return e;
+    }
+    // FP16 operands get their power-of-two scale from the norms first (prep)
+    const int fused = prec != 3;
+    switch (prec) {
+    case 0: hipLaunchKernelGGL(k_residual_reduce_grouped<double>, dim3(total_red), dim3(256), 0, s, snaps, prefix_red, P, kpad, k, skip_gemm, fused, done); break;
+    case 1: hipLaunchKernelGGL(k_residual_reduce_grouped<float>, dim3(total_red), dim3(256), 0, s, snaps, prefix_red, P, kpad, k, skip_gemm, fused, done); break;
+    case 2: hipLaunchKernelGGL(k_residual_reduce_grouped<__bf16>, dim3(total_red), dim3(256), 0, s, snaps, prefix_red, P, kpad, k, skip_gemm, fused, done); break;
+    case 3: hipLaunchKernelGGL(k_residual_reduce_grouped<_Float16>, dim3(total_red), dim3(256), 0, s, snaps, prefix_red, P, kpad, k, skip_gemm, fused, done); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// Block b: snapshot b / (kpad + 1), column norm (or operand scale) b % (kpad + 1).
+__global__ __launch_bounds__(256) void k_col_norms_grouped(const BatchSnap *snaps, int P, int64_t kpad,
+                                                           int scaled, const int *done) {
+    __shared__ double red[4];
+    const int p = (int)(blockIdx.x / (kpad + 1));
+    if (p >= P || done[p]) return;
+    const BatchSnap &d = snaps[p];
+    const int nparts = (int)(d.ld / 256);
+    col_norms_block(d.npart, nparts, kpad, d.mpart, nparts * (int)kpad, scaled, d.scal,
+                    blockIdx.x % (kpad + 1), red);
+}
+
+// One workgroup per snapshot: rel = max over the k columns of ||R_r|| / ||Y_r||;
+// init: ||Y_r|| is taken from these norms.  An unconverged snapshot counts
+// the iteration and is marked done once rel <= tol (tol > 0).
+__global__ __launch_bounds__(256) void k_converge(const BatchSnap *snaps, int P, int64_t kpad,
+                                                  int64_t k, double tol, int init, double *ynorm,
+                                                  double *rel_out, int *done, int *iters) {
+    __shared__ double red[4];
+    const int p = blockIdx.x;
+    if (p >= P || done[p]) return;
+    const double *nr = snaps[p].scal;
+    double *yn = ynorm + (int64_t)p * kpad;
+    double rel = 0.0;
+    for (int64_t r = threadIdx.x; r < k; r += 256) {
+        if (init) yn[r] = nr[r];
+        const double y = yn[r];
+        const double q = y > 0.0 ? nr[r] / y : 0.0;
+        rel = (q > rel || q != q) ? q : rel;   // NaN propagates
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const double v = __shfl_xor(rel, o);
+        rel = (v > rel || v != v) ? v : rel;
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = rel;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int w = 1; w < 4; ++w) m = (red[w] > m || red[w] != red[w]) ? red[w] : m;
+        if (init) {
+            rel_out[p] = 1.0;
+            return;
+        }
+        rel_out[p] = m;
+        iters[p] += 1;
+        if (tol > 0.0 && m <= tol) done[p] = 1;
+    }
+}
+
+hipError_t launch_norms_grouped(const BatchSnap *snaps, int P, int64_t kpad, int64_t k,
+                                int scaled, double tol, int init, double *ynorm,
+                                double *rel_out, int *done, int *iters, hipStream_t s) {
+    hipLaunchKernelGGL(k_col_norms_grouped, dim3((unsigned)(P * (kpad + 1))), dim3(256), 0, s, snaps,
+                       P, kpad, scaled, done);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_converge, dim3((unsigned)P), dim3(256), 0, s, snaps, P, kpad, k, tol, init,
+                       ynorm, rel_out, done, iters);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_prep_grouped(const BatchSnap *snaps, const int *prefix, int P, int64_t kpad,
+                               const int *done) {
+    const int p = group_find(prefix, P, blockIdx.x);
+    if (done[p]) return;
+    const BatchSnap &d = snaps[p];
+    const int64_t nb = prefix[p + 1] - prefix[p];
+    prep_v_range<T>(d.Rt, d.dm, d.ld, kpad * d.ld, d.scal + kpad, 1.0, d.V64, (T *)d.Vlo[0],
+                    (int64_t)(blockIdx.x - prefix[p]) * 256 + threadIdx.x, nb * 256);
+}
+
+hipError_t launch_prep_grouped(int prec, const BatchSnap *snaps, const int *prefix, int total,
+                               int P, int64_t kpad, const int *done, hipStream_t s) {
+    switch (prec) {
+    case 3: hipLaunchKernelGGL(k_prep_grouped<_Float16>, dim3(total), dim3(256), 0, s, snaps, prefix, P, kpad, done); break;
+    default: return hipErrorInvalidValue;   // only FP16 operands are prepared separately
     }
     return hipGetLastError();
 }
