@@ -228,19 +228,22 @@ int pick_choice(cdl_ctx *c, const char *family, int prec, int64_t ld, int64_t kp
     return 0;
 }
 
-// Milliseconds of the launches of fn() on the context's stream (syncs).
+// Mean milliseconds of the launches of fn() on the context's stream over
+// `reps` timed calls after one untimed call (which takes the first-launch
+// costs: code-object load, cold caches); syncs.
 template <class F>
-hipError_t time_launch(cdl_ctx *c, F &&fn, double *ms) {
+hipError_t time_launch(cdl_ctx *c, F &&fn, double *ms, int reps = 3) {
     hipEvent_t a = take_event(c), b = take_event(c);
-    hipError_t e = (a && b) ? hipEventRecord(a, c->stream) : hipErrorOutOfMemory;
-    if (e == hipSuccess) e = fn();
+    hipError_t e = (a && b) ? fn() : hipErrorOutOfMemory;
+    if (e == hipSuccess) e = hipEventRecord(a, c->stream);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = fn();
     if (e == hipSuccess) e = hipEventRecord(b, c->stream);
     if (e == hipSuccess) e = hipEventSynchronize(b);
     float t = 0.f;
     if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
     if (a) c->pool.push_back(a);
     if (b) c->pool.push_back(b);
-    *ms = t;
+    *ms = (double)t / reps;
     return e;
 }
 
@@ -480,13 +483,14 @@ cdl_status precondition_enqueue(cdl_ctx *ctx, int prec, int d, int D, const Solv
     const int nc = prec == 0 ? 1 : 3;
     int ch = pick_choice(ctx, "apply", prec, ld, kp, nc, allow_tune, &tune);
     if (tune) {
-        // the split-K product alone for each candidate (its partials are
-        // scratch; the applications below recompute them)
+        // one whole application per candidate (split-K product and its
+        // reduction, whose reads grow with the split count) into scratch
+        // panels: T64 and Vlo[2] take the result, V and X stay untouched
         std::vector<double> ms(nc);
         for (int q = 0; q < nc; ++q)
             HIPCHK(time_launch(ctx, [&] {
-                return launch_apply_gemm(prec, w.Vlo[0], c.levels, ld, n, kp,
-                                         apply_splits(prec, ld, kp, n, q), (float *)w.part, s);
+                return launch_apply(prec, w.Vlo[0], c.levels, w.Vlo[2], w.T64, ld, n, kp, nullptr,
+                                    c.dm, nullptr, (float *)w.part, 0, apply_splits(prec, ld, kp, n, q), s);
             }, &ms[q]));
         ch = cdl::tune_put(cdl::tune_arch(ctx->device), cdl::tune_key("apply", prec, ld, kp), ms);
     }
