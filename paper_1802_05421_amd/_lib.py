@@ -70,6 +70,10 @@ def load():
     if not os.path.exists(LIB):
         raise ImportError("libcaddelag.so is missing: run __graft_entry__.build() "
                           "(the GPU path has no fallback)")
+    # torch ships its own HIP runtime under the same soname as the system
+    # one the library links: load torch's first, so that the library binds
+    # to it (the other order leaves torch with a runtime that sees no GPU)
+    import torch  # noqa: F401
     L = C.CDLL(LIB)
     P, i64, u64, d, sz = C.c_void_p, C.c_int64, C.c_uint64, C.c_double, C.c_size_t
     I = C.c_int

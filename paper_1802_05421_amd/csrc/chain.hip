@@ -284,7 +284,7 @@ __device__ inline void square_epilogue(Core &g, const T *A, const T *B, T *S2, i
 // over k below).  The squaring is A = B = S, add = 0.
 // Upper tile `id` of C = A B and its epilogue (one workgroup).
 template <typename T, int NW>
-__device__ inline void square_tile(const T *A, const T *B, T *S2, int64_t ld, int64_t kend, int nt,
+__device__ __forceinline__ void square_tile(const T *A, const T *B, T *S2, int64_t ld, int64_t kend, int nt,
                                    int id, float inv_scale, int add, double *fro_part,
                                    char *smem_raw, double *red) {
     using Core = typename SqCfg<T, NW>::Core;
@@ -544,7 +544,7 @@ template <typename T, int BM> struct ApCfg {
 
 // Split-K product tile `id` of the chain application (one workgroup).
 template <typename T, int BM>
-__device__ inline void apply_gemm_tile(const T *Vin, const T *S, int64_t ld, int64_t kend,
+__device__ __forceinline__ void apply_gemm_tile(const T *Vin, const T *S, int64_t ld, int64_t kend,
                                        int64_t ks, int mt, int nt, float *P, int64_t kpad, int id,
                                        char *smem_raw) {
     using Core = typename ApCfg<T, BM>::Core;

@@ -111,17 +111,40 @@ template <> __device__ inline double tod<double>(double x) { return x; }
 // land on the same XCD lets neighbouring tiles share operand panels in L2.
 
 // Upper-triangle cover by 256 x 128 tiles of an ld x ld matrix (ncol =
-// ld / 128 column blocks, ld / 256 row blocks): row block I takes the column
-// blocks J = 2I .. ncol - 1, so its tiles start at id = I (ncol + 1 - I);
-// rect_upper_tiles(ld) = nrow ncol - nrow (nrow - 1) tiles in all.
-__device__ inline void upper_rect_tile(int id, int ncol, int &I, int &J) {
-    const double b = (double)ncol + 1.0;
-    int i = (int)((b - sqrt(b * b - 4.0 * (double)id)) * 0.5);
-    i = i < 0 ? 0 : i;
-    while (i > 0 && (int64_t)i * (ncol + 1 - i) > id) --i;
-    while ((int64_t)(i + 1) * (ncol - i) <= id) ++i;
-    I = i;
-    J = 2 * i + (id - i * (ncol + 1 - i));
+// ld / 128 column blocks, nrow = ld / 256 row blocks): row block I takes the
+// column blocks J = 2I .. ncol - 1; rect_upper_tiles(ld) = nrow ncol -
+// nrow (nrow - 1) tiles in all.
+// The tiles of the cover in the row panel [I0, I0 + nrows) (I0 = 0, nrows = ld / 256:
+// the whole matrix), enumerated in bands of G tile rows: within a band column
+// by column, so that consecutive ids (which one XCD runs side by side) share
+// their 128-column operand block across up to G row blocks.  A band starting
+// at row r0 with h rows holds h (h + 1) tiles in columns 2 r0 .. 2 (r0 + h) - 1
+// (column pair p has p + 1 rows) and h tiles in each later column.
+template <int G>
+__host__ __device__ inline void upper_band_tile(int id, int I0, int nrows, int ncol, int &I,
+                                                int &J) {
+    int r0 = I0;
+    while (true) {
+        const int h = I0 + nrows - r0 < G ? I0 + nrows - r0 : G;
+        const int cnt = h * (h + 1) + (ncol - 2 * r0 - 2 * h) * h;
+        if (id < cnt || r0 + h >= I0 + nrows) {
+            if (id < h * (h + 1)) {
+                int p = (int)((sqrt(4.0 * (double)id + 1.0) - 1.0) * 0.5);
+                while (p > 0 && p * (p + 1) > id) --p;
+                while ((p + 1) * (p + 2) <= id) ++p;
+                const int r = id - p * (p + 1);
+                J = 2 * r0 + 2 * p + r / (p + 1);
+                I = r0 + r % (p + 1);
+            } else {
+                const int q = id - h * (h + 1);
+                J = 2 * r0 + 2 * h + q / h;
+                I = r0 + q % h;
+            }
+            return;
+        }
+        id -= cnt;
+        r0 += h;
+    }
 }
 __host__ __device__ inline int rect_upper_tiles(int64_t ld) {
     const int ncol = (int)(ld / 128), nrow = (int)(ld / 256);

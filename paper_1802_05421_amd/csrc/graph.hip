@@ -126,7 +126,7 @@ __global__ __launch_bounds__(512) void k_gram_dist(const double *Xp, int64_t Tp,
         rect_tile<4>(id, pb, ncol, I, J);
         I += I0;
     } else {
-        upper_rect_tile(id + I0 * (ncol + 1 - I0), ncol, I, J);
+        upper_band_tile<4>(id, I0, pb, ncol, I, J);
     }
     const int64_t m0 = (int64_t)I * 256, n0 = (int64_t)J * 128;
     double *const out = D2 - (int64_t)I0 * 256 * ld;

@@ -71,7 +71,7 @@ hipError_t launch_build_zhat(const double *Z0, const double *Z1, const int32_t *
     return hipGetLastError();
 }
 
-// 256 x 128 tiles covering the upper triangle (upper_rect_tile); each wave
+// 256 x 128 tiles covering the upper triangle (upper_band_tile); each wave
 // 64 x 64.  Only pairs a < b count: a tile straddling the diagonal also holds
 // pairs a > b, whose mirror images another tile covers.
 using ScoreCore = GemmCore<MfmaF64, 256, 128, 16, 4, 2>;
@@ -103,7 +103,7 @@ struct ScoreShared {
 
 // Upper-triangle tile `id` of the score Gram with its partial sums (one
 // workgroup).
-__device__ inline void score_tile(const double *Zh, const double *Zhe, int64_t ldz,
+__device__ __forceinline__ void score_tile(const double *Zh, const double *Zhe, int64_t ldz,
                                   const double *sq, int64_t m, int64_t mpad, const double *W0,
                                   int64_t ld0, const double *W1, int64_t ld1,
                                   const int32_t *map0, const int32_t *map1, int weighted,
@@ -114,7 +114,7 @@ __device__ inline void score_tile(const double *Zh, const double *Zhe, int64_t l
     auto &scol = sh.scol;
     auto &smax = sh.smax;
     int I, J;
-    upper_rect_tile(id, ncol, I, J);
+    upper_band_tile<4>(id, 0, ncol / 2, ncol, I, J);
     const int64_t m0 = (int64_t)I * 256, n0 = (int64_t)J * 128;
     ScoreCore g;
     g.run(Zh, ldz, Zhe, ldz, m0, n0, ldz, smem);
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(512) void k_edge_collect(
     const double th = *tau;
     if (tmax[id] < th) return;   // uniform over the workgroup
     int I, J;
-    upper_rect_tile(id, ncol, I, J);
+    upper_band_tile<4>(id, 0, ncol / 2, ncol, I, J);
     const int64_t m0 = (int64_t)I * 256, n0 = (int64_t)J * 128;
     ScoreCore g;
     g.run(Zh, ldz, Zhe, ldz, m0, n0, ldz, smem);

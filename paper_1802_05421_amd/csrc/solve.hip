@@ -408,7 +408,7 @@ template <int BM> struct ResCfg {
 // W may be a row panel: its row q holds node row0 + q, whose products land in
 // column row0 + q of the partials (row0 = 0 for the whole matrix).
 template <int BM>
-__device__ inline void residual_gemm_tile(const double *Xt, const double *W, int64_t ld,
+__device__ __forceinline__ void residual_gemm_tile(const double *Xt, const double *W, int64_t ld,
                                           int64_t kend, int64_t ks, int mt, int nt, double *P,
                                           int64_t kpad, int64_t row0, int id, char *smem_raw) {
     using Core = typename ResCfg<BM>::Core;
