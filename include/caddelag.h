@@ -292,6 +292,16 @@ cdl_status cdl_k_rp(int64_t n, double eps_rp, int64_t *k);
  *   scale   host output.
  * Errors: CDL_E_ARG for n < 1, an invalid prec or a NULL scale. */
 cdl_status cdl_level_scale(int64_t n, cdl_prec prec, double *scale);
+/* Plain device-to-device copy on the context's stream (one 16-byte
+ * nontemporal load and store per lane over a grid that covers the buffer):
+ * the reference stream against which the hot kernels' HBM traffic and
+ * bandwidth are read.  Not part of the method.
+ *   src, dst  device buffers of `bytes` bytes, 16-byte aligned, disjoint;
+ *             the caller owns both.
+ *   bytes     a multiple of 16 (0: nothing to do).
+ * Errors: CDL_E_ARG for a NULL ctx or buffer, misalignment, a size that is
+ * not a multiple of 16 or overlapping buffers; CDL_E_HIP if the launch fails. */
+cdl_status cdl_device_copy(cdl_ctx *ctx, const void *src, void *dst, size_t bytes);
 /* Bytes of an n x n matrix of `prec` elements in the padded layout. */
 size_t cdl_matrix_bytes(int64_t n, cdl_prec prec);
 /* Byte offset of level 0 inside a chain buffer; level l starts at

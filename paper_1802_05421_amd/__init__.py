@@ -26,6 +26,7 @@ from .api import (  # noqa: E402,F401
     anomaly_scores,
     build_chain,
     chain_densify,
+    device_copy,
     force_choice,
     build_graph,
     check_graph,

@@ -102,6 +102,7 @@ def load():
         "cdl_ld": (i64, [i64]),
         "cdl_k_rp": (I, [i64, d, C.POINTER(i64)]),
         "cdl_level_scale": (I, [i64, I, C.POINTER(d)]),
+        "cdl_device_copy": (I, [P, P, P, sz]),
         "cdl_matrix_bytes": (sz, [i64, I]),
         "cdl_chain_level_offset": (sz, [i64, I]),
         "cdl_workspace_bytes": (I, [i64, i64, i64, I, I, C.POINTER(sz), C.POINTER(sz),

@@ -280,6 +280,18 @@ def level(chain: Chain, l: int) -> torch.Tensor:
     return raw.view(prec).view(m, m)
 
 
+def device_copy(src: torch.Tensor, dst: torch.Tensor):
+    """dst <- src bytewise on the current stream with the library's plain copy
+    kernel (cdl_device_copy): the bandwidth and byte-counter reference."""
+    if not (src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("device_copy: contiguous tensors only")
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nb:
+        raise ValueError("device_copy: sizes differ")
+    ctx = context(src.device.index or 0)
+    _check(_lib().cdl_device_copy(ctx.h, _ptr(src), _ptr(dst), nb), ctx.h)
+
+
 def level_scale(chain: Chain) -> float:
     """Storage scale of the chain's levels (cdl_level_scale)."""
     out = C.c_double()

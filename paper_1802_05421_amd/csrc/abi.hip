@@ -810,6 +810,17 @@ cdl_status cdl_k_rp(int64_t n, double eps_rp, int64_t *k) {
     return CDL_OK;
 }
 
+cdl_status cdl_device_copy(cdl_ctx *ctx, const void *src, void *dst, size_t bytes) {
+    if (!ctx) return CDL_E_ARG;
+    if (bytes == 0) return CDL_OK;
+    if (!src || !dst || bytes % 16 || !aligned(src, 16) || !aligned(dst, 16))
+        return fail(ctx, CDL_E_ARG, "device copy: NULL, unaligned or not a multiple of 16 bytes");
+    const char *a = (const char *)src, *b = (const char *)dst;
+    if (a < b + bytes && b < a + bytes) return fail(ctx, CDL_E_ARG, "device copy: buffers overlap");
+    HIPCHK(launch_copy16(src, dst, bytes, ctx->stream));
+    return CDL_OK;
+}
+
 cdl_status cdl_level_scale(int64_t n, cdl_prec prec, double *scale) {
     if (!scale || n < 1 || !valid_prec(prec)) return CDL_E_ARG;
     *scale = (double)level_scale(prec, n);

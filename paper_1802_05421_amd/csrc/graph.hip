@@ -68,6 +68,28 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Plain device copy: one 16-byte element per lane, a grid covering the whole
+// buffer (consecutive workgroups stream consecutive memory), nontemporal
+// loads and stores (the data is touched once).  The reference stream for HBM
+// bandwidth and for the byte counters; measured on gfx950 at 1 GiB it moves
+// about 1.5x the bytes per second of a grid-stride loop over the same data.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_copy16(const u32x4 *__restrict__ src,
+                                                u32x4 *__restrict__ dst, size_t n16) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n16) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+hipError_t launch_copy16(const void *src, void *dst, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return hipSuccess;
+    if (bytes % 16 || ((uintptr_t)src) % 16 || ((uintptr_t)dst) % 16) return hipErrorInvalidValue;
+    const size_t n16 = bytes / 16, grid = (n16 + 255) / 256;
+    if (grid > 0xffffffffull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_copy16, dim3((unsigned)grid), dim3(256), 0, s, (const u32x4 *)src,
+                       (u32x4 *)dst, n16);
+    return hipGetLastError();
+}
+
 // One wave per (padded) row.
 __global__ void k_pad_series(const double *X, int64_t n, int64_t T, int64_t ldx,
                              double *Xp, int64_t Tp, double *sqn, int *flags) {

@@ -32,6 +32,8 @@ struct SelectState {                // device scratch of the exact median select
 int64_t select_buffer_keys(int64_t n);
 
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+// dst = src (bytes a multiple of 16, both 16-byte aligned, no overlap).
+hipError_t launch_copy16(const void *src, void *dst, size_t bytes, hipStream_t s);
 hipError_t launch_pad_series(const double *X, int64_t n, int64_t T, int64_t ldx,
                              double *Xp, int64_t rows, int64_t Tp, double *sqn,
                              int *flags, hipStream_t s);

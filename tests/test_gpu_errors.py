@@ -281,3 +281,25 @@ def test_bad_arguments_are_refused(cdl, L):
     # the context still works after every refusal
     F2, t2 = cdl.anomaly_scores(Z, g, Z, g, top_k=5)
     assert np.all(np.isfinite(host(F2)))
+
+
+def test_device_copy_bytes_and_argument_checks(cdl, L):
+    """The plain copy used as the bandwidth and byte-counter reference: exact
+    bytes (random bits, a ragged tail past the grid-stride unroll) and its
+    argument checks, all decided on the host."""
+    g = torch.Generator().manual_seed(7)
+    for nbytes in (16, 4096 + 48, (1 << 20) * 33 + 16 * 7):
+        src = torch.randint(0, 256, (nbytes,), dtype=torch.uint8, generator=g).cuda()
+        dst = torch.zeros_like(src)
+        cdl.device_copy(src, dst)
+        torch.cuda.synchronize()
+        assert torch.equal(src.cpu(), dst.cpu())
+    from paper_1802_05421_amd.api import context
+    ctx = context(0)
+    buf = torch.zeros(1024, dtype=torch.uint8, device="cuda")
+    p = buf.data_ptr()
+    assert L.cdl_device_copy(ctx.h, C.c_void_p(p), C.c_void_p(p + 512), 24) == E_ARG       # size
+    assert L.cdl_device_copy(ctx.h, C.c_void_p(p + 8), C.c_void_p(p + 512), 32) == E_ARG   # align
+    assert L.cdl_device_copy(ctx.h, C.c_void_p(p), C.c_void_p(p + 256), 512) == E_ARG      # overlap
+    assert L.cdl_device_copy(ctx.h, None, C.c_void_p(p), 16) == E_ARG
+    assert L.cdl_device_copy(ctx.h, C.c_void_p(p), C.c_void_p(p + 512), 0) == 0
