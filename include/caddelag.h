@@ -158,7 +158,12 @@ typedef struct {
  * residual reaches tol (> 0) stops (its workgroups of later iterations
  * return at once), so max_iter is only an upper bound; tol = 0 runs exactly
  * max_iter iterations.  info->max_iterations is the largest iteration count
- * used; CDL_E_NOCONV if a snapshot ends above tol. */
+ * used; CDL_E_NOCONV if a snapshot ends above tol.  The split-K counts of the
+ * grouped level applications and FP64 residual products are chosen for the
+ * whole group (the smallest that gives two workgroups per CU), so the
+ * results equal the per-snapshot path's to rounding; with the "apply" and
+ * "residual" choices pinned on the context (cdl_ctx_force_choice) each
+ * snapshot keeps its own counts and the results are bit for bit the same. */
 #define CDL_SEQ_BATCHED 4
 
 typedef struct {

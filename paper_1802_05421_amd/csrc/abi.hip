@@ -1979,6 +1979,41 @@ static cdl_status score_sequence_batched(cdl_ctx *ctx, int32_t n_snap, const cdl
     std::vector<BatchSnap> hs(P);
     std::vector<ChainBuf> chains(P);
     std::vector<SolveWs> solves(P);
+    // Split-K counts for the grouped launches: one count S for the whole group,
+    // the smallest power of two that gives the group at least two workgroups
+    // per CU (the per-snapshot counts fill the chip with one snapshot alone and
+    // multiply the partial sums' traffic when many snapshots share a launch),
+    // clamped per snapshot to what its length and its workspace allow.
+    auto ap_split = [&](int t, int S) {
+        const int64_t n = sn[t].n, ld = pad_n(n);
+        return std::min(cdl::apply_splits_fixed(prec, n, S), apply_splits(prec, ld, kp, n, 2));
+    };
+    auto res_split = [&](int t, int S) {
+        const int64_t n = sn[t].n, ld = pad_n(n);
+        return std::min(cdl::residual_splits_fixed(n, S), residual_splits(ld, kp, n, 2));
+    };
+    constexpr int64_t kGroupWgs = 2 * 256;
+    int Sa = 1, Sr = 1;
+    auto ap_tiles = [&](int S) {
+        int64_t c = 0;
+        for (int t = 0; t < P; ++t) c += cdl::apply_gemm_tiles(pad_n(sn[t].n), kp, ap_split(t, S));
+        return c;
+    };
+    auto res_tiles = [&](int S) {
+        int64_t c = 0;
+        for (int t = 0; t < P; ++t) c += cdl::residual_gemm_tiles(pad_n(sn[t].n), kp, res_split(t, S));
+        return c;
+    };
+    while (Sa < 256 && ap_tiles(Sa) < kGroupWgs && ap_tiles(2 * Sa) > ap_tiles(Sa)) Sa *= 2;
+    while (Sr < 256 && res_tiles(Sr) < kGroupWgs && res_tiles(2 * Sr) > res_tiles(Sr)) Sr *= 2;
+    // a choice pinned on the context (cdl_ctx_force_choice) keeps the
+    // per-snapshot split counts, so that the grouped launches compute exactly
+    // the per-snapshot path's partial sums
+    auto pinned = [&](const char *fam) {
+        auto f = ctx->forced.find(fam);
+        return f != ctx->forced.end() && f->second >= 0 && f->second < 3 ? f->second : -1;
+    };
+    const int pin_ap = pinned("apply"), pin_res = pinned("residual");
     for (int t = 0; t < P; ++t) {
         const int64_t n = sn[t].n, ld = pad_n(n);
         Arena ac(base + L.chain[t]);
@@ -1987,9 +2022,6 @@ static cdl_status score_sequence_batched(cdl_ctx *ctx, int32_t n_snap, const cdl
         solves[t] = plan_solve(aw, n, k, prec);
         const ChainBuf &c = chains[t];
         const SolveWs &w = solves[t];
-        bool tune = false;
-        const int ca = pick_choice(ctx, "apply", prec, ld, kp, 3, false, &tune);
-        const int cr = pick_choice(ctx, "residual", 0, ld, kp, 3, false, &tune);
         BatchSnap &d = hs[t];
         d.n = n;
         d.ld = ld;
@@ -2011,8 +2043,8 @@ static cdl_status score_sequence_batched(cdl_ctx *ctx, int32_t n_snap, const cdl
         d.npart = w.npart;
         d.mpart = w.mpart;
         d.scal = w.scal;
-        d.ap_splits = apply_splits(prec, ld, kp, n, ca);
-        d.res_splits = residual_splits(ld, kp, n, cr);
+        d.ap_splits = pin_ap >= 0 ? apply_splits(prec, ld, kp, n, pin_ap) : ap_split(t, Sa);
+        d.res_splits = pin_res >= 0 ? residual_splits(ld, kp, n, pin_res) : res_split(t, Sr);
     }
     std::vector<BatchPair> hp(NP);
     std::vector<int32_t> hm, m0, m1;
@@ -2059,10 +2091,13 @@ static cdl_status score_sequence_batched(cdl_ctx *ctx, int32_t n_snap, const cdl
     };
     const int tot_sq = fill(0, P, [&](int t) { return square_tiles(prec, hs[t].ld); });
     const int tot_ag = fill(1, P, [&](int t) { return apply_gemm_tiles(hs[t].ld, kp, hs[t].ap_splits); });
-    const int tot_ar = fill(2, P, [&](int t) { return apply_reduce_blocks(hs[t].ld, kp); });
+    // element-wise kernels stride over at most 256 workgroups per snapshot, so
+    // that the launches after every snapshot has converged stay cheap
+    constexpr int kEltWgs = 256;
+    const int tot_ar = fill(2, P, [&](int t) { return apply_reduce_blocks(hs[t].ld, kp, kEltWgs); });
     const int tot_rg = fill(3, P, [&](int t) { return residual_gemm_tiles(hs[t].ld, kp, hs[t].res_splits); });
-    const int tot_rr = fill(4, P, [&](int t) { return (int)(hs[t].ld / 256 * kp); });
-    const int tot_pv = fill(5, P, [&](int t) { return apply_reduce_blocks(hs[t].ld, kp); });
+    const int tot_rr = fill(4, P, [&](int t) { return (int)std::min<int64_t>(hs[t].ld / 256 * kp, kEltWgs); });
+    const int tot_pv = fill(5, P, [&](int t) { return apply_reduce_blocks(hs[t].ld, kp, kEltWgs); });
     const int tot_zh = fill(6, NP, [&](int t) { return (int)hp[t].mpad; });
     const int tot_sc = fill(7, NP, [&](int t) { return score_tiles_2d(hp[t].mpad); });
     const int tot_sr = fill(8, NP, [&](int t) { return (int)((hp[t].m + 63) / 64); });

@@ -59,9 +59,15 @@ hipError_t launch_apply_grouped(int prec, const BatchSnap *snaps, const int *pre
                                 int total_gemm, const int *prefix_red, int total_red, int P,
                                 int64_t kpad, int level, int in, int accumulate, int last,
                                 const int *done, hipStream_t s);
-int apply_reduce_blocks(int64_t ld, int64_t kpad);   // per snapshot (also the prep's)
+// Workgroups of one snapshot's share of the application's update (also the
+// FP16 operand preparation's), at most `cap`; the kernels stride over them.
+int apply_reduce_blocks(int64_t ld, int64_t kpad, int cap = 2048);
 int apply_gemm_tiles(int64_t ld, int64_t kpad, int nsplit);
 int residual_gemm_tiles(int64_t ld, int64_t kpad, int S);
+// Split-K counts S clamped to what a snapshot of n nodes allows (a grouped
+// launch picks one S for all snapshots from the tiles of the whole group).
+int apply_splits_fixed(int prec, int64_t n, int S);
+int residual_splits_fixed(int64_t n, int S);
 // R = Y - deg X + W X, V = dm R (rounded copy into Vlo[0]) and the norm
 // partials, for every unconverged snapshot; skip_gemm: R = Y (initial).
 hipError_t launch_residual_grouped(int prec, const BatchSnap *snaps, const int *prefix_gemm,

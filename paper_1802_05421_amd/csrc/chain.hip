@@ -708,9 +708,16 @@ int apply_gemm_tiles(int64_t ld, int64_t kpad, int nsplit) {
     return (int)(kpad / ap_bm(kpad) * (ld / 256)) * nsplit;
 }
 
-int apply_reduce_blocks(int64_t ld, int64_t kpad) {
+int apply_reduce_blocks(int64_t ld, int64_t kpad, int cap) {
     const int64_t b = cdiv(kpad * ld, 256);
-    return (int)(b < 2048 ? b : 2048);
+    return (int)(b < cap ? b : cap);
+}
+
+int apply_splits_fixed(int prec, int64_t n, int S) {
+    if (prec == 0) return 1;
+    const int64_t kend = (n + 63) / 64 * 64;
+    const int64_t smax = kend / 128 > 0 ? kend / 128 : 1;   // >= 2 k-tiles per split
+    return (int)(S < 1 ? 1 : S > smax ? smax : S);
 }
 
 template <typename T, int BM>

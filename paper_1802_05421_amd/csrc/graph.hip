@@ -197,6 +197,9 @@ __global__ __launch_bounds__(512) void k_gram_dist(const double *Xp, int64_t Tp,
                 out[(m0 + r) * ld + n0 + c] = v;
             }
     if (st) {
+        // the tile's smallest and largest key: waves, then the workgroup, then
+        // one pair of atomics per tile (all tiles update the same two words)
+        __shared__ unsigned long long wmin[GramCore::NT / 64], wmax[GramCore::NT / 64];
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) {
             const unsigned long long a = __shfl_xor(kmin, o), b = __shfl_xor(kmax, o);
@@ -204,6 +207,16 @@ __global__ __launch_bounds__(512) void k_gram_dist(const double *Xp, int64_t Tp,
             kmax = b > kmax ? b : kmax;
         }
         if ((threadIdx.x & 63) == 0) {
+            wmin[threadIdx.x >> 6] = kmin;
+            wmax[threadIdx.x >> 6] = kmax;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int w = 1; w < GramCore::NT / 64; ++w) {
+                kmin = wmin[w] < kmin ? wmin[w] : kmin;
+                kmax = wmax[w] > kmax ? wmax[w] : kmax;
+            }
             if (kmin != ~0ull) atomicMin(&st->kmin, kmin);
             if (kmax != 0ull) atomicMax(&st->kmax, kmax);
         }

@@ -453,6 +453,12 @@ __host__ __device__ inline int64_t residual_split_len(int64_t n, int S) {
 // Split-K count of the FP64 residual product: choice 0 aims at >= 256
 // workgroups, 1 halves that count, 2 doubles it (at least four 16-wide
 // k-tiles per split either way).
+int residual_splits_fixed(int64_t n, int S) {
+    const int64_t kend = (n + 63) / 64 * 64;
+    const int64_t smax = kend / 64 > 0 ? kend / 64 : 1;   // >= 4 k-tiles per split
+    return (int)(S < 1 ? 1 : S > smax ? smax : S);
+}
+
 int residual_splits(int64_t ld, int64_t kpad, int64_t n, int choice) {
     const int64_t base = (kpad / res_bm(kpad)) * (ld / 128);
     const int64_t kend = (n + 63) / 64 * 64;
@@ -783,10 +789,14 @@ __global__ __launch_bounds__(256) void k_residual_reduce_grouped(const BatchSnap
     const int p = group_find(prefix, P, blockIdx.x);
     if (done[p]) return;
     const BatchSnap &d = snaps[p];
-    const int64_t nb = d.ld / 256, lb = blockIdx.x - prefix[p];
-    residual_reduce_block<T>(d.Pres, d.res_splits, d.Yt, d.Xt, d.deg, d.dm, d.ld, d.n, k, kpad,
-                             skip_gemm, d.Rt, d.V64, fused ? (T *)d.Vlo[0] : (T *)nullptr, d.npart,
-                             d.mpart, lb % nb, lb / nb, red, redm);
+    // the snapshot's (node block, column) items, strided over its workgroups
+    const int64_t nb = d.ld / 256, items = nb * kpad, step = prefix[p + 1] - prefix[p];
+    for (int64_t lb = blockIdx.x - prefix[p]; lb < items; lb += step) {
+        residual_reduce_block<T>(d.Pres, d.res_splits, d.Yt, d.Xt, d.deg, d.dm, d.ld, d.n, k, kpad,
+                                 skip_gemm, d.Rt, d.V64, fused ? (T *)d.Vlo[0] : (T *)nullptr,
+                                 d.npart, d.mpart, lb % nb, lb / nb, red, redm);
+        __syncthreads();   // red / redm are rewritten by the next item
+    }
 }
 
 template <int BM>

@@ -52,14 +52,32 @@ def test_batched_equals_per_snapshot_path_and_graph_replays(cdl, prec, mode, dep
     gdev = [torch.from_numpy(g).cuda() for g in seq.gid]
     base = dict(k=k, seed=seed, prec=prec, depth=depth, tol=0.0, max_iter=6, mode=mode, top_k=50)
     print("batched sequence", prec, mode, depth, [len(g) for g in seq.gid], flush=True)
+    # the group's own split counts: the per-snapshot path's results to rounding
     wF, wT, wi = cdl.score_sequence(Xs, gdev, cdl.SeqParams(**base))
     wF, wT = [host(f) for f in wF], [host(t) for t in wT]
     pb = cdl.SeqParams(**base, asynchronous=True, batched=True)
     Fb, Tb, ib = cdl.score_sequence(Xs, gdev, pb)
     assert ib.max_iterations == 6 and ib.pairs == len(Xs) - 1
     for t in range(len(wF)):
-        np.testing.assert_array_equal(host(Fb[t]), wF[t])
-        np.testing.assert_array_equal(host(Tb[t]), wT[t])
+        compare(host(Fb[t]), host(Tb[t]), wF[t], wT[t], 1e-9)
+    # pinned choices: every snapshot keeps its own split counts, and the
+    # grouped launches compute the per-snapshot path's tiles bit for bit
+    cdl.force_choice("apply", 0)
+    cdl.force_choice("residual", 0)
+    try:
+        wF, wT, wi = cdl.score_sequence(Xs, gdev, cdl.SeqParams(**base))
+        wF, wT = [host(f) for f in wF], [host(t) for t in wT]
+        Fb, Tb, ib = cdl.score_sequence(Xs, gdev, pb)
+        for t in range(len(wF)):
+            np.testing.assert_array_equal(host(Fb[t]), wF[t])
+            np.testing.assert_array_equal(host(Tb[t]), wT[t])
+    finally:
+        cdl.force_choice("apply", -1)
+        cdl.force_choice("residual", -1)
+    # graph replays of the group's own counts equal its eager call
+    eF, eT, _ = cdl.score_sequence(Xs, gdev, pb)
+    eF, eT = [host(f) for f in eF], [host(t) for t in eT]
+    sF0 = host(cdl.score_sequence(Xs[:2], gdev[:2], cdl.SeqParams(**base))[0][0])
     pg = cdl.SeqParams(**base, asynchronous=True, batched=True, graph=True)
     ws = torch.empty(cdl.sequence_workspace_bytes(Xs, gdev, pg), dtype=torch.uint8, device="cuda")
     Fs, tops, info = cdl.score_sequence(Xs, gdev, pg, ws=ws)
@@ -69,12 +87,12 @@ def test_batched_equals_per_snapshot_path_and_graph_replays(cdl, prec, mode, dep
             f.fill_(-1.0)
         F2, T2, info = cdl.score_sequence(Xs, gdev, pg, ws=ws, out=(Fs, tops))
         launches.append(info.graph_launches)
-        for t in range(len(wF)):
-            np.testing.assert_array_equal(host(F2[t]), wF[t])
-            np.testing.assert_array_equal(host(T2[t]), wT[t])
+        for t in range(len(eF)):
+            np.testing.assert_array_equal(host(F2[t]), eF[t])
+            np.testing.assert_array_equal(host(T2[t]), eT[t])
         # eager work on the same stream between replays
         Fx, _, _ = cdl.score_sequence(Xs[:2], gdev[:2], cdl.SeqParams(**base))
-        np.testing.assert_array_equal(host(Fx[0]), wF[0])
+        np.testing.assert_array_equal(host(Fx[0]), sF0)
     assert launches == [1, 1, 1]
 
 
