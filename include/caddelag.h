@@ -150,7 +150,7 @@ typedef struct {
 /* CDL_SEQ_BATCHED (with CDL_SEQ_ASYNC; FP32, BF16 or FP16 levels): one pass
  * over the whole sequence with every snapshot resident (the workspace grows
  * with the sum of the snapshots' sizes): graphs, level-0 chains and
- * right-hand sides per snapshot on two streams, then grouped launches over
+ * right-hand sides per snapshot on four streams of the context, then grouped launches over
  * all snapshots for each chain squaring, each step of the refinement (the
  * applications level by level, the FP64 residual product and reduction, the
  * norms) and the embeddings, and over all pairs for the scores.  Convergence

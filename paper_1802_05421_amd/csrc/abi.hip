@@ -52,6 +52,7 @@ struct cdl_ctx {
     hipGraph_t seq_graph = nullptr;
     hipGraphExec_t seq_exec = nullptr;
     hipStream_t side = nullptr;   // second stream of asynchronous sequences (created on first use)
+    hipStream_t extra[2] = {nullptr, nullptr};   // third and fourth (one-pass sequences)
     // Pinned host staging for device-to-host reads (grown on demand): a copy
     // into pageable memory is staged by the runtime one copy at a time.
     void *stage = nullptr;
@@ -688,6 +689,8 @@ cdl_status cdl_ctx_destroy(cdl_ctx *ctx) {
     if (ctx->seq_exec) (void)hipGraphExecDestroy(ctx->seq_exec);
     if (ctx->seq_graph) (void)hipGraphDestroy(ctx->seq_graph);
     if (ctx->side) (void)hipStreamDestroy(ctx->side);
+    for (hipStream_t x : ctx->extra)
+        if (x) (void)hipStreamDestroy(x);
     if (ctx->stage) {
         (void)hipStreamSynchronize(ctx->stream);
         (void)hipHostFree(ctx->stage);
@@ -1804,9 +1807,13 @@ size_t put(Arena &a, size_t bytes) {
 
 struct BatchLayout {
     std::vector<size_t> W, deg, st, chain, solve, Z, score;
-    size_t gws[2] = {0, 0}, maps = 0, snaps = 0, pairs = 0, prefix = 0, flags = 0, ynorm = 0,
-           rel = 0, status = 0, total = 0;
+    size_t gws[4] = {0, 0, 0, 0}, maps = 0, snaps = 0, pairs = 0, prefix = 0, flags = 0,
+           ynorm = 0, rel = 0, status = 0, total = 0;
 };
+// Streams of a one-pass sequence's per-snapshot phase (graphs, level-0
+// chains, right-hand sides): the context's stream, its second stream and
+// two more; each has its own graph workspace.
+constexpr int kSeqStreams = 4;
 constexpr int kBatchTables = 10;   // prefix tables of the grouped launches
 
 BatchLayout batch_layout(int32_t n_snap, const cdl_snapshot *sn, const cdl_seq_params *q) {
@@ -1835,7 +1842,7 @@ BatchLayout batch_layout(int32_t n_snap, const cdl_snapshot *sn, const cdl_seq_p
         plan_score(w, std::min(sn[t - 1].n, sn[t].n), q->k);
         L.score.push_back(put(a, w.off));
     }
-    for (int b = 0; b < 2; ++b) {
+    for (int b = 0; b < kSeqStreams; ++b) {
         Arena g(nullptr);
         plan_graph(g, nmax, Tmax);
         L.gws[b] = put(a, g.off);
@@ -1877,6 +1884,12 @@ size_t seq_bytes(const SeqPlan &p, const cdl_seq_params *q) {
 }
 } // namespace
 
+static void sync_side_streams(cdl_ctx *ctx) {
+    if (ctx->side) (void)hipStreamSynchronize(ctx->side);
+    for (hipStream_t x : ctx->extra)
+        if (x) (void)hipStreamSynchronize(x);
+}
+
 // Runs enqueue(s0, s1) eagerly on the context's stream and its second
 // stream; with use_graph, the second call with the same key is captured into
 // a HIP graph (both streams forked and joined inside the capture) and later
@@ -1891,7 +1904,7 @@ static cdl_status run_sequence(cdl_ctx *ctx, bool use_graph, const std::vector<u
         // eager two-stream enqueue; a later graph call starts its key afresh
         ctx->seq_key.clear();
         if ((st = enqueue(s, ctx->side)) != CDL_OK) {
-            (void)hipStreamSynchronize(ctx->side);
+            sync_side_streams(ctx);
             return st;
         }
     } else if (key == ctx->seq_key && ctx->seq_exec) {
@@ -1945,7 +1958,7 @@ static cdl_status run_sequence(cdl_ctx *ctx, bool use_graph, const std::vector<u
         ctx->seq_graph = nullptr;
         ctx->seq_key = key;
         if ((st = enqueue(s, ctx->side)) != CDL_OK) {
-            (void)hipStreamSynchronize(ctx->side);   // nothing may stay in flight on the side stream
+            sync_side_streams(ctx);   // nothing may stay in flight on the side streams
             return st;
         }
     }
@@ -1953,7 +1966,7 @@ static cdl_status run_sequence(cdl_ctx *ctx, bool use_graph, const std::vector<u
 }
 
 // CDL_SEQ_BATCHED: the snapshots' graphs, level-0 chains and right-hand sides
-// alternate over two streams; then, on the context's stream, grouped
+// rotate over four streams; then, on the context's stream, grouped
 // launches over all snapshots run the squarings (one per level), the
 // initial residuals and every refinement iteration (the applications level
 // by level, the FP64 residual product and its reduction, the norms and the
@@ -2114,27 +2127,31 @@ static cdl_status score_sequence_batched(cdl_ctx *ctx, int32_t n_snap, const cdl
     double *ynorm = (double *)(base + L.ynorm), *rel = (double *)(base + L.rel);
     double *status = (double *)(base + L.status);
     if (!ctx->side) HIPCHK(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
-    hipEvent_t evs[2] = {nullptr, nullptr};
+    for (hipStream_t &x : ctx->extra)
+        if (!x) HIPCHK(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+    // fork (one event on the first stream) and join (one per other stream)
+    hipEvent_t evs[kSeqStreams] = {};
     struct EvGuard {
         hipEvent_t *v;
-        ~EvGuard() { for (int i = 0; i < 2; ++i) if (v[i]) (void)hipEventDestroy(v[i]); }
+        ~EvGuard() { for (int i = 0; i < kSeqStreams; ++i) if (v[i]) (void)hipEventDestroy(v[i]); }
     } ev_guard{evs};
     for (auto &e : evs) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     const int weighted = q->mode == CDL_SCORE_DELTA_A;
 
     auto enqueue = [&](hipStream_t s0, hipStream_t s1) -> cdl_status {
-        hipStream_t ss[2] = {s0, s1};
+        // the two extra streams join a capture through the fork event like s1
+        hipStream_t ss[kSeqStreams] = {s0, s1, ctx->extra[0], ctx->extra[1]};
         cdl_status st = CDL_OK;
         HIPCHK(hipEventRecord(evs[0], s0));
-        HIPCHK(hipStreamWaitEvent(s1, evs[0], 0));
+        for (int b = 1; b < kSeqStreams; ++b) HIPCHK(hipStreamWaitEvent(ss[b], evs[0], 0));
         for (int t = 0; t < P && st == CDL_OK; ++t) {
-            hipStream_t es = ss[t & 1];
+            hipStream_t es = ss[t % kSeqStreams];
             ctx->stream = es;
             const cdl_snapshot &x = sn[t];
             const double *W = hs[t].W, *deg = hs[t].deg;
             double *stats = (double *)(base + L.st[t]);
             st = graph_enqueue(ctx, x.X, x.n, x.T, x.ldx, q->sigma, (double *)W, (double *)deg, stats,
-                               base + L.gws[t & 1]);
+                               base + L.gws[t % kSeqStreams]);
             if (st == CDL_OK) st = chain_enqueue(ctx, W, deg, stats, x.n, prec, depth, base + L.chain[t], false);
             if (st != CDL_OK) break;
             const SolveWs &w = solves[t];
@@ -2146,8 +2163,10 @@ static cdl_status score_sequence_batched(cdl_ctx *ctx, int32_t n_snap, const cdl
                                   CDL_GRAPH_STATS * sizeof(double), hipMemcpyDeviceToDevice, es));
         }
         ctx->stream = s0;
-        HIPCHK(hipEventRecord(evs[1], s1));
-        HIPCHK(hipStreamWaitEvent(s0, evs[1], 0));
+        for (int b = 1; b < kSeqStreams; ++b) {
+            HIPCHK(hipEventRecord(evs[b], ss[b]));
+            HIPCHK(hipStreamWaitEvent(s0, evs[b], 0));
+        }
         if (st != CDL_OK) return st;
         for (int l = 0; l + 1 < depth; ++l)
             { Timed t_(ctx, "square"); HIPCHK(cdl::launch_square_grouped(prec, dsnap, dtable(0), P, tot_sq, l, s0)); }
