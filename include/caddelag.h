@@ -149,8 +149,9 @@ typedef struct {
 #define CDL_SEQ_GRAPH 2
 /* CDL_SEQ_BATCHED (with CDL_SEQ_ASYNC; FP32, BF16 or FP16 levels): one pass
  * over the whole sequence with every snapshot resident (the workspace grows
- * with the sum of the snapshots' sizes): graphs, level-0 chains and
- * right-hand sides per snapshot on four streams of the context, then grouped launches over
+ * with the sum of the snapshots' sizes): grouped launches over all
+ * snapshots for the graphs and level-0 chains, the right-hand sides per
+ * snapshot on four streams of the context, then grouped launches over
  * all snapshots for each chain squaring, each step of the refinement (the
  * applications level by level, the FP64 residual product and reduction, the
  * norms) and the embeddings, and over all pairs for the scores.  Convergence

@@ -502,11 +502,31 @@ class SeqParams:
     batched: bool = False
 
 
+# Host and device int32 copies of global-id tensors, so that repeated calls
+# on the same ids copy nothing.  An entry holds the tensor object itself (its
+# memory cannot be handed to another tensor while cached) and its version
+# counter (an in-place write bumps it and invalidates the entry).
+_gid_cache: dict = {}
+
+
+def _gid_copies(g: torch.Tensor, dev):
+    hit = _gid_cache.get(id(g))
+    if hit is not None and hit[0] is g and hit[1] == g._version and hit[2] == dev:
+        return hit[3], hit[4]
+    if len(_gid_cache) > 4096:
+        _gid_cache.clear()
+    host = g.cpu().to(torch.int32).contiguous()
+    devc = g.to(device=dev, dtype=torch.int32).contiguous()
+    _gid_cache[id(g)] = (g, g._version, dev, host, devc)
+    return host, devc
+
+
 def _seq_args(Xs, gids, p: SeqParams):
     dev = Xs[0].device
     n_snap = len(Xs)
-    gid_host = [g.cpu().to(torch.int32).contiguous() for g in gids]
-    gid_dev = [g.to(device=dev, dtype=torch.int32).contiguous() for g in gids]
+    pairs = [_gid_copies(g, dev) for g in gids]
+    gid_host = [h for h, _ in pairs]
+    gid_dev = [d for _, d in pairs]
     snaps = (L.Snapshot * n_snap)()
     for t, X in enumerate(Xs):
         snaps[t].X = X.data_ptr()

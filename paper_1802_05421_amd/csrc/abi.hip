@@ -1806,13 +1806,12 @@ size_t put(Arena &a, size_t bytes) {
 }
 
 struct BatchLayout {
-    std::vector<size_t> W, deg, st, chain, solve, Z, score;
-    size_t gws[4] = {0, 0, 0, 0}, maps = 0, snaps = 0, pairs = 0, prefix = 0, flags = 0,
+    std::vector<size_t> W, deg, st, chain, solve, Z, score, gws;
+    size_t maps = 0, snaps = 0, pairs = 0, prefix = 0, gsnaps = 0, gprefix = 0, flags = 0,
            ynorm = 0, rel = 0, status = 0, total = 0;
 };
-// Streams of a one-pass sequence's per-snapshot phase (graphs, level-0
-// chains, right-hand sides): the context's stream, its second stream and
-// two more; each has its own graph workspace.
+// Streams of a one-pass sequence's right-hand sides: the context's stream,
+// its second stream and two more.
 constexpr int kSeqStreams = 4;
 constexpr int kBatchTables = 10;   // prefix tables of the grouped launches
 
@@ -1820,11 +1819,9 @@ BatchLayout batch_layout(int32_t n_snap, const cdl_snapshot *sn, const cdl_seq_p
     BatchLayout L;
     Arena a(nullptr);
     const int depth = std::max(q->depth, 1);
-    int64_t nmax = 0, Tmax = 0, ntot = 0;
+    int64_t ntot = 0;
     for (int t = 0; t < n_snap; ++t) {
         const int64_t n = sn[t].n, ld = pad_n(n);
-        nmax = std::max(nmax, n);
-        Tmax = std::max(Tmax, sn[t].T);
         ntot += n;
         L.W.push_back(put(a, (size_t)ld * ld * sizeof(double)));
         L.deg.push_back(put(a, (size_t)ld * sizeof(double)));
@@ -1836,22 +1833,22 @@ BatchLayout batch_layout(int32_t n_snap, const cdl_snapshot *sn, const cdl_seq_p
         plan_solve(w, n, q->k, q->prec);
         L.solve.push_back(put(a, w.off));
         L.Z.push_back(put(a, (size_t)n * q->k * sizeof(double)));
+        Arena g(nullptr);
+        plan_graph(g, n, sn[t].T);
+        L.gws.push_back(put(a, g.off));
     }
     for (int t = 1; t < n_snap; ++t) {
         Arena w(nullptr);
         plan_score(w, std::min(sn[t - 1].n, sn[t].n), q->k);
         L.score.push_back(put(a, w.off));
     }
-    for (int b = 0; b < kSeqStreams; ++b) {
-        Arena g(nullptr);
-        plan_graph(g, nmax, Tmax);
-        L.gws[b] = put(a, g.off);
-    }
     const int64_t kp = pad_k(q->k);
     L.maps = put(a, 2 * (size_t)ntot * sizeof(int32_t));
     L.snaps = put(a, (size_t)n_snap * sizeof(cdl::BatchSnap));
     L.pairs = put(a, (size_t)n_snap * sizeof(cdl::BatchPair));
     L.prefix = put(a, (size_t)kBatchTables * (n_snap + 1) * sizeof(int));
+    L.gsnaps = put(a, (size_t)n_snap * sizeof(cdl::GraphSnap));
+    L.gprefix = put(a, (size_t)cdl::kGraphTables * (n_snap + 1) * sizeof(int));
     L.flags = put(a, 2 * (size_t)n_snap * sizeof(int));
     L.ynorm = put(a, (size_t)n_snap * kp * sizeof(double));
     L.rel = put(a, (size_t)n_snap * sizeof(double));
@@ -1965,8 +1962,10 @@ static cdl_status run_sequence(cdl_ctx *ctx, bool use_graph, const std::vector<u
     return CDL_OK;
 }
 
-// CDL_SEQ_BATCHED: the snapshots' graphs, level-0 chains and right-hand sides
-// rotate over four streams; then, on the context's stream, grouped
+// CDL_SEQ_BATCHED: grouped launches over all snapshots build the graphs
+// (padding, distance Gram, exact median, weights, degrees, statistics) and
+// the level-0 chains; the right-hand sides rotate over four streams; then,
+// on the context's stream, grouped
 // launches over all snapshots run the squarings (one per level), the
 // initial residuals and every refinement iteration (the applications level
 // by level, the FP64 residual product and its reduction, the norms and the
@@ -2122,6 +2121,49 @@ static cdl_status score_sequence_batched(cdl_ctx *ctx, int32_t n_snap, const cdl
     HIPCHK(hipMemcpyAsync(dsnap, hs.data(), hs.size() * sizeof(BatchSnap), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(dpair, hp.data(), hp.size() * sizeof(BatchPair), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(dpre, pre.data(), pre.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    // the graph build and level-0 chains of all snapshots: descriptors and
+    // prefix tables of the grouped launches
+    std::vector<cdl::GraphSnap> hg(P);
+    std::vector<int> gpre((size_t)cdl::kGraphTables * (P + 1), 0), gtot(cdl::kGraphTables, 0);
+    for (int t = 0; t < P; ++t) {
+        const int64_t n = sn[t].n, ld = pad_n(n);
+        Arena ag(base + L.gws[t]);
+        const GraphWs gw = plan_graph(ag, n, sn[t].T);
+        cdl::GraphSnap &g = hg[t];
+        g.X = sn[t].X;
+        g.n = n;
+        g.T = sn[t].T;
+        g.ldx = sn[t].ldx;
+        g.Tp = pad_t(sn[t].T);
+        g.ld = ld;
+        g.Xp = gw.Xp;
+        g.sqn = gw.sqn;
+        g.flags = gw.flags;
+        g.W = (double *)hs[t].W;
+        g.deg = (double *)hs[t].deg;
+        g.stats = (double *)(base + L.st[t]);
+        g.sel = gw.sel;
+        g.buf = gw.selbuf;
+        g.cap = select_buffer_keys(n);
+        g.dpart = gw.dpart;
+        g.dmn = chains[t].dmn;
+        g.dm = chains[t].dm;
+        g.u = chains[t].u;
+        g.level0 = chains[t].levels;
+        g.fro = chains[t].fro;
+        g.fro64 = chains[t].fro64;
+        g.scale = (double)level_scale(prec, n);
+        const bool br = cdl::select_uses_bracket(n, ctx->select_mode == 0);
+        for (int tb = 0; tb < cdl::kGraphTables; ++tb) {
+            int *row = gpre.data() + (size_t)tb * (P + 1);
+            row[t + 1] = row[t] + cdl::graph_table_count(tb, n, ld, br);
+        }
+    }
+    for (int tb = 0; tb < cdl::kGraphTables; ++tb) gtot[tb] = gpre[(size_t)tb * (P + 1) + P];
+    cdl::GraphSnap *dgs = (cdl::GraphSnap *)(base + L.gsnaps);
+    int *dgpre = (int *)(base + L.gprefix);
+    HIPCHK(hipMemcpyAsync(dgs, hg.data(), hg.size() * sizeof(cdl::GraphSnap), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(dgpre, gpre.data(), gpre.size() * sizeof(int), hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
     int *done = (int *)(base + L.flags), *iters = done + P;
     double *ynorm = (double *)(base + L.ynorm), *rel = (double *)(base + L.rel);
@@ -2142,18 +2184,18 @@ static cdl_status score_sequence_batched(cdl_ctx *ctx, int32_t n_snap, const cdl
         // the two extra streams join a capture through the fork event like s1
         hipStream_t ss[kSeqStreams] = {s0, s1, ctx->extra[0], ctx->extra[1]};
         cdl_status st = CDL_OK;
+        // graphs and level-0 chains: grouped launches over all snapshots
+        { Timed t_(ctx, "graph_grouped"); HIPCHK(cdl::launch_graph_grouped(dgs, dgpre, gtot.data(), P, q->sigma, s0)); }
+        { Timed t_(ctx, "chain_level0"); HIPCHK(cdl::launch_chain_level0_grouped(prec, dgs, dgpre, gtot.data(), P, s0)); }
+        // right-hand sides per snapshot over the streams
         HIPCHK(hipEventRecord(evs[0], s0));
         for (int b = 1; b < kSeqStreams; ++b) HIPCHK(hipStreamWaitEvent(ss[b], evs[0], 0));
         for (int t = 0; t < P && st == CDL_OK; ++t) {
             hipStream_t es = ss[t % kSeqStreams];
             ctx->stream = es;
             const cdl_snapshot &x = sn[t];
-            const double *W = hs[t].W, *deg = hs[t].deg;
+            const double *W = hs[t].W;
             double *stats = (double *)(base + L.st[t]);
-            st = graph_enqueue(ctx, x.X, x.n, x.T, x.ldx, q->sigma, (double *)W, (double *)deg, stats,
-                               base + L.gws[t % kSeqStreams]);
-            if (st == CDL_OK) st = chain_enqueue(ctx, W, deg, stats, x.n, prec, depth, base + L.chain[t], false);
-            if (st != CDL_OK) break;
             const SolveWs &w = solves[t];
             const size_t panel = (size_t)kp * hs[t].ld * sizeof(double);
             { Timed t_(ctx, "fill_zero"); HIPCHK(launch_fill_zero(w.Yt, panel, es)); }

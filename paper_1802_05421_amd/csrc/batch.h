@@ -26,6 +26,59 @@ struct BatchSnap {
     int ap_splits, res_splits;
 };
 
+struct SelectState;
+
+// Everything the grouped graph build (padding, distance Gram, median
+// selection, weights, degrees, statistics) and the level-0 chain of one
+// snapshot need.
+struct GraphSnap {
+    const double *X;           // series, n x T, row pitch ldx
+    int64_t n, T, ldx, Tp, ld;
+    double *Xp, *sqn;          // padded series (ld x Tp) and squared row norms
+    int *flags;                // non-finite input flag
+    double *W, *deg, *stats;   // distances, then weights in place; degrees; statistics
+    SelectState *sel;
+    unsigned long long *buf;   // bracket buffer of the selection
+    int64_t cap;               // its capacity (keys)
+    double *dpart;             // degree partials
+    // level 0 of the chain
+    double *dmn, *dm, *u;
+    void *level0;
+    double *fro, *fro64;
+    double scale;              // storage scale of the level
+};
+
+// Prefix tables of the grouped graph build (one per workgroup count):
+enum GraphTable {
+    kGtRows,      // padded rows: ld
+    kGtOne,       // one workgroup per snapshot
+    kGtGram,      // upper-triangle 256 x 128 tiles
+    kGtSample,    // one per snapshot whose selection starts with a sampled bracket
+    kGtBracket,   // min(n, 2048) per such snapshot
+    kGtPass,      // min(n, 2048) per snapshot
+    kGtSym,       // upper 64 x 64 tiles
+    kGtNodes64,   // ceil(n / 64)
+    kGtPrep,      // ceil(ld / 256)
+    kGraphTables
+};
+// Workgroup counts of table `tb` for a snapshot (bracket: its selection
+// starts with the sampled bracket).
+int graph_table_count(int tb, int64_t n, int64_t ld, bool bracket);
+// Whether the stored selection of n keys' matrix starts with a sampled
+// bracket (the bracket must fit the buffer).
+bool select_uses_bracket(int64_t n, bool allowed);
+
+// The graph of every snapshot: padding, Gram (with the key bounds when
+// selecting), the exact lower median (sigma <= 0) or the given sigma,
+// weights, degrees and statistics.  tables: kGraphTables x (P + 1) prefix
+// tables in device memory; totals: their last entries (host).
+hipError_t launch_graph_grouped(const GraphSnap *snaps, const int *tables, const int *totals,
+                                int P, double sigma, hipStream_t s);
+// Level 0 of every snapshot's chain: (cD)^{-1/2}, u and the normalised,
+// deflated, rounded level with its norm partials.
+hipError_t launch_chain_level0_grouped(int prec, const GraphSnap *snaps, const int *tables,
+                                       const int *totals, int P, hipStream_t s);
+
 // One pair of consecutive snapshots for the grouped score kernels.
 struct BatchPair {
     int64_t m, mpad;

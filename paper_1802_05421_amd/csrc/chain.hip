@@ -43,9 +43,9 @@ float level_scale(int prec, int64_t n) {
     return s;
 }
 
-__global__ void k_chain_prep(const double *deg, const double *stats, int64_t n, int64_t ld,
-                             int lazy, double *dmn, double *dm, double *u) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void chain_prep_elem(const double *deg, const double *stats, int64_t n,
+                                                int64_t ld, int lazy, double *dmn, double *dm,
+                                                double *u, int64_t i) {
     if (i >= ld) return;
     if (i < n) {
         const double d = deg[i], vol = stats[0];
@@ -55,6 +55,12 @@ __global__ void k_chain_prep(const double *deg, const double *stats, int64_t n, 
     } else {
         dmn[i] = dm[i] = u[i] = 0.0;
     }
+}
+
+__global__ void k_chain_prep(const double *deg, const double *stats, int64_t n, int64_t ld,
+                             int lazy, double *dmn, double *dm, double *u) {
+    chain_prep_elem(deg, stats, n, ld, lazy, dmn, dm, u,
+                    (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 hipError_t launch_chain_prep(const double *deg, const double *stats, int64_t n, int64_t ld,
@@ -69,11 +75,12 @@ hipError_t launch_chain_prep(const double *deg, const double *stats, int64_t n, 
 // level, so a wave access covers two contiguous row segments.  The mirror is
 // written from the LDS copy of the rounded tile, two adjacent rows per lane.
 // Every element is the expression of k_normalize_rows.
+// Upper tile `id` (after the XCD remap) of the sym_tile<8> order.
 template <typename T>
-__global__ __launch_bounds__(256) void k_normalize(const double *W, int64_t ld, int64_t n,
-                                                   const double *dmn, const double *u, int lazy,
-                                                   double scale, int nt, T *S0,
-                                                   double *fro_part, double *fro64_part) {
+__device__ __forceinline__ void normalize_tile(const double *W, int64_t ld, int64_t n,
+                                               const double *dmn, const double *u, int lazy,
+                                               double scale, int nt, T *S0, double *fro_part,
+                                               double *fro64_part, int id) {
     struct alignas(2 * sizeof(T)) T2 { T a, b; };
     struct alignas(16) D2 { double x, y; };
     // row pitch: a whole number of T2 pairs; 2-byte types get an odd word
@@ -81,8 +88,6 @@ __global__ __launch_bounds__(256) void k_normalize(const double *W, int64_t ld, 
     constexpr int PAD = sizeof(T) == 2 ? 2 : 16 / (int)sizeof(T);
     __shared__ T t[64][64 + PAD];
     __shared__ double red[4];
-    const int total = nt * (nt + 1) / 2;
-    const int id = xcd_remap(blockIdx.x, total);
     int I, J;
     sym_tile<8>(id, nt, I, J);
     const int64_t i0 = (int64_t)I * 64, j0 = (int64_t)J * 64;
@@ -146,6 +151,15 @@ __global__ __launch_bounds__(256) void k_normalize(const double *W, int64_t ld, 
     if (threadIdx.x == 0) fro_part[id] = w * s;
     s64 = block_sum256c(s64, red);
     if (threadIdx.x == 0) fro64_part[id] = w * s64;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_normalize(const double *W, int64_t ld, int64_t n,
+                                                   const double *dmn, const double *u, int lazy,
+                                                   double scale, int nt, T *S0,
+                                                   double *fro_part, double *fro64_part) {
+    normalize_tile<T>(W, ld, n, dmn, u, lazy, scale, nt, S0, fro_part, fro64_part,
+                      xcd_remap(blockIdx.x, nt * (nt + 1) / 2));
 }
 
 hipError_t launch_normalize(int prec, const double *W, int64_t ld, int64_t n,
@@ -895,6 +909,43 @@ hipError_t launch_axpy_v(int prec, const double *T64, int64_t ld, int64_t kpad, 
     case 1: hipLaunchKernelGGL(k_axpy_v<float>, dim3(grid), dim3(256), 0, s, T64, total, ld, V64, (float *)Vout, Xt, dm, inv_vs); break;
     case 2: hipLaunchKernelGGL(k_axpy_v<__bf16>, dim3(grid), dim3(256), 0, s, T64, total, ld, V64, (__bf16 *)Vout, Xt, dm, inv_vs); break;
     case 3: hipLaunchKernelGGL(k_axpy_v<_Float16>, dim3(grid), dim3(256), 0, s, T64, total, ld, V64, (_Float16 *)Vout, Xt, dm, inv_vs); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Level 0 of many snapshots' chains in grouped launches (the per-snapshot
+// kernels' workgroups, found through prefix tables: the same bits).
+
+__global__ __launch_bounds__(256) void k_chain_prep_grouped(const GraphSnap *snaps, const int *prefix,
+                                                            int P) {
+    const int p = group_find(prefix, P, blockIdx.x);
+    const GraphSnap &d = snaps[p];
+    chain_prep_elem(d.deg, d.stats, d.n, d.ld, 0, d.dmn, d.dm, d.u,
+                    (int64_t)(blockIdx.x - prefix[p]) * 256 + threadIdx.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_normalize_grouped(const GraphSnap *snaps, const int *prefix,
+                                                           int P) {
+    const int p = group_find(prefix, P, blockIdx.x);
+    const GraphSnap &d = snaps[p];
+    const int nt = (int)(d.ld / 64);
+    normalize_tile<T>(d.W, d.ld, d.n, d.dmn, d.u, 0, d.scale, nt, (T *)d.level0, d.fro, d.fro64,
+                      xcd_remap(blockIdx.x - prefix[p], prefix[p + 1] - prefix[p]));
+}
+
+hipError_t launch_chain_level0_grouped(int prec, const GraphSnap *snaps, const int *tables,
+                                       const int *totals, int P, hipStream_t s) {
+    auto tb = [&](int t) { return tables + (size_t)t * (P + 1); };
+    hipLaunchKernelGGL(k_chain_prep_grouped, dim3(totals[kGtPrep]), dim3(256), 0, s, snaps, tb(kGtPrep), P);
+    const dim3 g((unsigned)totals[kGtSym]), b(256);
+    switch (prec) {
+    case 0: hipLaunchKernelGGL(k_normalize_grouped<double>, g, b, 0, s, snaps, tb(kGtSym), P); break;
+    case 1: hipLaunchKernelGGL(k_normalize_grouped<float>, g, b, 0, s, snaps, tb(kGtSym), P); break;
+    case 2: hipLaunchKernelGGL(k_normalize_grouped<__bf16>, g, b, 0, s, snaps, tb(kGtSym), P); break;
+    case 3: hipLaunchKernelGGL(k_normalize_grouped<_Float16>, g, b, 0, s, snaps, tb(kGtSym), P); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -24,6 +24,7 @@
 // its tiles, optionally with the weights formed in the epilogue; select by
 // radix digits from the top bit, one sweep over the upper panels per digit;
 // exp_rows for the weights, degrees and Frobenius rows of a panel.
+#include "batch.h"
 #include "common.h"
 #include "gemm.h"
 #include "kernels.h"
@@ -91,9 +92,10 @@ hipError_t launch_copy16(const void *src, void *dst, size_t bytes, hipStream_t s
 }
 
 // One wave per (padded) row.
-__global__ void k_pad_series(const double *X, int64_t n, int64_t T, int64_t ldx,
-                             double *Xp, int64_t Tp, double *sqn, int *flags) {
-    const int64_t i = blockIdx.x;
+// Padded row i of the series and its squared norm (one wave).
+__device__ __forceinline__ void pad_row(const double *X, int64_t n, int64_t T, int64_t ldx,
+                                        double *Xp, int64_t Tp, double *sqn, int *flags,
+                                        int64_t i) {
     const int lane = threadIdx.x;
     double s = 0.0;
     int bad = 0;
@@ -106,6 +108,11 @@ __global__ void k_pad_series(const double *X, int64_t n, int64_t T, int64_t ldx,
     s = wave_sum(s);
     if (lane == 0) sqn[i] = s;
     if (bad) atomicOr(flags, 1);
+}
+
+__global__ void k_pad_series(const double *X, int64_t n, int64_t T, int64_t ldx,
+                             double *Xp, int64_t Tp, double *sqn, int *flags) {
+    pad_row(X, n, T, ldx, Xp, Tp, sqn, flags, blockIdx.x);
 }
 
 hipError_t launch_pad_series(const double *X, int64_t n, int64_t T, int64_t ldx,
@@ -135,15 +142,11 @@ constexpr size_t kGramSmem = GramCore::SMEM;
 // (zero on the diagonal and outside n; sigma = wstats[1]), the expression of
 // the separate exponential kernels, so the values are the same bits.
 template <bool kExp>
-__global__ __launch_bounds__(512) void k_gram_dist(const double *Xp, int64_t Tp,
-                                                   const double *sqn, int64_t n, int64_t ld,
-                                                   double *D2, int ncol, int I0, int pb,
-                                                   int full, int total, SelectState *st,
-                                                   const double *wstats) {
-    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
-    double *smem = (double *)smem_raw;
+__device__ __forceinline__ void gram_tile(const double *Xp, int64_t Tp, const double *sqn,
+                                          int64_t n, int64_t ld, double *D2, int ncol, int I0,
+                                          int pb, int full, int id, SelectState *st,
+                                          const double *wstats, double *smem) {
     int I, J;
-    const int id = xcd_remap(blockIdx.x, total);
     if (full) {
         rect_tile<4>(id, pb, ncol, I, J);
         I += I0;
@@ -223,6 +226,17 @@ __global__ __launch_bounds__(512) void k_gram_dist(const double *Xp, int64_t Tp,
     }
 }
 
+template <bool kExp>
+__global__ __launch_bounds__(512) void k_gram_dist(const double *Xp, int64_t Tp,
+                                                   const double *sqn, int64_t n, int64_t ld,
+                                                   double *D2, int ncol, int I0, int pb,
+                                                   int full, int total, SelectState *st,
+                                                   const double *wstats) {
+    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+    gram_tile<kExp>(Xp, Tp, sqn, n, ld, D2, ncol, I0, pb, full, xcd_remap(blockIdx.x, total), st,
+                    wstats, (double *)smem_raw);
+}
+
 static hipError_t gram_attr() {
     static bool attr = false;
     if (!attr) {
@@ -289,7 +303,7 @@ hipError_t launch_gram_panel(const double *Xp, int64_t Tp, const double *sqn, in
 // a single workgroup sorts them.  Every pass kernel reads the state's mode,
 // so the fixed launch sequence turns into no-ops once the answer is known.
 
-__global__ void k_select_reset(SelectState *st) {
+__device__ __forceinline__ void select_reset_body(SelectState *st) {
     for (int b = threadIdx.x; b < 4096; b += blockDim.x) st->hist[b] = 0;
     if (threadIdx.x == 0) {
         st->kmin = ~0ull;
@@ -301,6 +315,8 @@ __global__ void k_select_reset(SelectState *st) {
         st->nbuf = 0;
     }
 }
+
+__global__ void k_select_reset(SelectState *st) { select_reset_body(st); }
 
 constexpr int kSelSample = 4096;
 constexpr int kSelMargin = 96;    // 3 sqrt(kSelSample / 4): misses in ~0.3% of calls
@@ -319,9 +335,8 @@ __device__ inline unsigned long long sel_mix(unsigned long long z) {
 
 // One workgroup: kSelSample keys at pseudo-random pairs i != j, bitonic sort
 // in LDS, bracket of kSelMargin sample ranks on each side of the target.
-__global__ __launch_bounds__(1024) void k_select_sample(const double *D2, int64_t ld, int64_t n,
-                                                        SelectState *st) {
-    extern __shared__ unsigned long long sk[];
+__device__ __forceinline__ void select_sample_body(const double *D2, int64_t ld, int64_t n,
+                                                   SelectState *st, unsigned long long *sk) {
     if (st->mode == 2) return;
     const int t = threadIdx.x;
     unsigned long long v[kSelSample / 1024];
@@ -358,6 +373,12 @@ __global__ __launch_bounds__(1024) void k_select_sample(const double *D2, int64_
     }
 }
 
+__global__ __launch_bounds__(1024) void k_select_sample(const double *D2, int64_t ld, int64_t n,
+                                                        SelectState *st) {
+    extern __shared__ unsigned long long sk[];
+    select_sample_body(D2, ld, n, st, sk);
+}
+
 // Count the keys below lo; append those in [lo, hi] to buf (at most cap).
 // Appends go to a per-workgroup LDS stage (one LDS atomic each) copied out
 // behind one global atomic at the end; a workgroup holds about
@@ -365,10 +386,11 @@ __global__ __launch_bounds__(1024) void k_select_sample(const double *D2, int64_
 // keys past the stage's end take a global slot each.
 // Rows [row0, row1): row i at D2 + (i - row0) ld (a row panel, or the whole
 // matrix with row0 = 0, row1 = n).
-__global__ __launch_bounds__(256) void k_select_bracket(const double *D2, int64_t ld, int64_t n,
-                                                        int64_t row0, int64_t row1,
-                                                        SelectState *st, unsigned long long *buf,
-                                                        int64_t cap) {
+// Workgroup b of nb.
+__device__ __forceinline__ void select_bracket_body(const double *D2, int64_t ld, int64_t n,
+                                                    int64_t row0, int64_t row1, SelectState *st,
+                                                    unsigned long long *buf, int64_t cap,
+                                                    int64_t b, int64_t nb) {
     constexpr unsigned int kStage = 4096;
     __shared__ unsigned long long sb[kStage];
     __shared__ unsigned int scnt;
@@ -379,7 +401,7 @@ __global__ __launch_bounds__(256) void k_select_bracket(const double *D2, int64_
     if (t == 0) scnt = 0;
     __syncthreads();
     unsigned long long below = 0;
-    for (int64_t i = row0 + blockIdx.x; i < row1; i += gridDim.x) {
+    for (int64_t i = row0 + b; i < row1; i += nb) {
         const unsigned long long *row = (const unsigned long long *)(D2 + (i - row0) * ld);
         for (int64_t j0 = i + 1 + t; j0 < n; j0 += 8 * 256) {
             unsigned long long key[8];   // eight independent loads in flight
@@ -418,9 +440,16 @@ __global__ __launch_bounds__(256) void k_select_bracket(const double *D2, int64_
     if ((t & 63) == 0) spart[t >> 6] = below;
     __syncthreads();
     if (t == 0) {
-        const unsigned long long b = spart[0] + spart[1] + spart[2] + spart[3];
-        if (b) atomicAdd(&st->below, b);
+        const unsigned long long bl = spart[0] + spart[1] + spart[2] + spart[3];
+        if (bl) atomicAdd(&st->below, bl);
     }
+}
+
+__global__ __launch_bounds__(256) void k_select_bracket(const double *D2, int64_t ld, int64_t n,
+                                                        int64_t row0, int64_t row1,
+                                                        SelectState *st, unsigned long long *buf,
+                                                        int64_t cap) {
+    select_bracket_body(D2, ld, n, row0, row1, st, buf, cap, blockIdx.x, gridDim.x);
 }
 
 // The bracket pass for very many keys (streamed panels: billions of keys,
@@ -491,7 +520,7 @@ __global__ __launch_bounds__(256) void k_select_bracket_flush(const double *D2, 
 }
 
 // Switch the radix passes to the buffer when the target lies in the bracket.
-__global__ void k_select_check(SelectState *st, int64_t cap, double *stats) {
+__device__ __forceinline__ void select_check_body(SelectState *st, int64_t cap, double *stats) {
     if (threadIdx.x != 0 || st->mode == 2) return;
     const unsigned long long below = st->below, nb = st->nbuf, rank = st->rank;
     if (nb > (unsigned long long)cap || rank < below || rank >= below + nb) return;   // stay on the matrix
@@ -514,7 +543,11 @@ __global__ void k_select_check(SelectState *st, int64_t cap, double *stats) {
     st->count = 0;
 }
 
-__global__ void k_select_setup(SelectState *st, int64_t n, double *stats) {
+__global__ void k_select_check(SelectState *st, int64_t cap, double *stats) {
+    select_check_body(st, cap, stats);
+}
+
+__device__ __forceinline__ void select_setup_body(SelectState *st, int64_t n, double *stats) {
     if (threadIdx.x != 0) return;
     const unsigned long long N = (unsigned long long)n * (unsigned long long)(n - 1) / 2ull;
     st->rank = (N - 1ull) / 2ull;
@@ -532,6 +565,10 @@ __global__ void k_select_setup(SelectState *st, int64_t n, double *stats) {
     st->mode = 0;
 }
 
+__global__ void k_select_setup(SelectState *st, int64_t n, double *stats) {
+    select_setup_body(st, n, stats);
+}
+
 __device__ inline void sel_digit(const SelectState *st, int &shift, int &width,
                                  unsigned long long &hi_mask) {
     const int bits = st->bits;
@@ -542,10 +579,11 @@ __device__ inline void sel_digit(const SelectState *st, int &shift, int &width,
 
 // Keys of rows [row0, row1): row i at D2 + (i - row0) ld (a row panel, or
 // the whole matrix with row0 = 0, row1 = n).
-__global__ __launch_bounds__(256) void k_select_pass(const double *D2, int64_t ld, int64_t n,
-                                                     int64_t row0, int64_t row1,
-                                                     SelectState *st,
-                                                     const unsigned long long *buf) {
+// Workgroup b of nb.
+__device__ __forceinline__ void select_pass_body(const double *D2, int64_t ld, int64_t n,
+                                                 int64_t row0, int64_t row1, SelectState *st,
+                                                 const unsigned long long *buf, int64_t b,
+                                                 int64_t nb) {
     __shared__ unsigned int h[4096];
     const int mode = st->mode;
     if (mode == 2) return;
@@ -556,7 +594,7 @@ __global__ __launch_bounds__(256) void k_select_pass(const double *D2, int64_t l
     constexpr int kBufBlocks = 256;
     const bool from_buf = st->src == 1;
     const bool few = from_buf && st->nbuf <= (1ull << 24);
-    if (few && (int)blockIdx.x >= kBufBlocks) return;
+    if (few && b >= kBufBlocks) return;
     int shift, width;
     unsigned long long hi_mask;
     sel_digit(st, shift, width, hi_mask);
@@ -577,18 +615,18 @@ __global__ __launch_bounds__(256) void k_select_pass(const double *D2, int64_t l
     };
     // eight independent loads in flight per thread
     if (from_buf) {
-        const int64_t gb = few && (int)gridDim.x > kBufBlocks ? (int64_t)kBufBlocks : (int64_t)gridDim.x;
-        const int64_t nb = (int64_t)st->nbuf, stride = gb * 256;
-        for (int64_t q0 = (int64_t)blockIdx.x * 256 + threadIdx.x; q0 < nb; q0 += 8 * stride) {
+        const int64_t gb = few && nb > kBufBlocks ? (int64_t)kBufBlocks : nb;
+        const int64_t nk = (int64_t)st->nbuf, stride = gb * 256;
+        for (int64_t q0 = b * 256 + threadIdx.x; q0 < nk; q0 += 8 * stride) {
             unsigned long long key[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) key[u] = q0 + u * stride < nb ? buf[q0 + u * stride] : 0ull;
+            for (int u = 0; u < 8; ++u) key[u] = q0 + u * stride < nk ? buf[q0 + u * stride] : 0ull;
 #pragma unroll
             for (int u = 0; u < 8; ++u)
-                if (q0 + u * stride < nb) take(key[u]);
+                if (q0 + u * stride < nk) take(key[u]);
         }
     } else {
-        for (int64_t i = row0 + blockIdx.x; i < row1; i += gridDim.x) {
+        for (int64_t i = row0 + b; i < row1; i += nb) {
             const unsigned long long *row = (const unsigned long long *)(D2 + (i - row0) * ld);
             for (int64_t j0 = i + 1 + threadIdx.x; j0 < n; j0 += 8 * 256) {
                 unsigned long long key[8];
@@ -602,12 +640,19 @@ __global__ __launch_bounds__(256) void k_select_pass(const double *D2, int64_t l
     }
     if (mode == 0) {
         __syncthreads();
-        for (int b = threadIdx.x; b < 4096; b += 256)
-            if (h[b]) atomicAdd(&st->hist[b], (unsigned long long)h[b]);
+        for (int q = threadIdx.x; q < 4096; q += 256)
+            if (h[q]) atomicAdd(&st->hist[q], (unsigned long long)h[q]);
     }
 }
 
-__global__ __launch_bounds__(1024) void k_select_pick(SelectState *st, double *stats) {
+__global__ __launch_bounds__(256) void k_select_pass(const double *D2, int64_t ld, int64_t n,
+                                                     int64_t row0, int64_t row1,
+                                                     SelectState *st,
+                                                     const unsigned long long *buf) {
+    select_pass_body(D2, ld, n, row0, row1, st, buf, blockIdx.x, gridDim.x);
+}
+
+__device__ __forceinline__ void select_pick_body(SelectState *st, double *stats) {
     constexpr int NT = 1024, BPT = 4096 / NT;
     __shared__ unsigned long long part[NT / 64];
     __shared__ unsigned long long keys[kSelCap];
@@ -687,6 +732,10 @@ __global__ __launch_bounds__(1024) void k_select_pick(SelectState *st, double *s
     }
     __syncthreads();
     for (int b = t; b < 4096; b += NT) st->hist[b] = 0;
+}
+
+__global__ __launch_bounds__(1024) void k_select_pick(SelectState *st, double *stats) {
+    select_pick_body(st, stats);
 }
 
 hipError_t launch_select_reset(SelectState *st, hipStream_t s) {
@@ -932,13 +981,13 @@ int sym_tiles64(int64_t ld) {
 // j: every (tile column, node) slot is written by exactly one tile.  Lane =
 // column, so every global access of a wave is one contiguous 512-byte row
 // segment; the four waves take 16 rows each.
-__global__ __launch_bounds__(256) void k_exp_sym(double *W, int64_t ld, int64_t n,
-                                                 const double *stats, int nt, double *part) {
+// Upper tile `id` (after the XCD remap) of the sym_tile<8> order.
+__device__ __forceinline__ void exp_sym_tile(double *W, int64_t ld, int64_t n,
+                                             const double *stats, int nt, double *part, int id) {
     __shared__ double t[64][65];
     __shared__ double cs[4][64];
-    const int total = nt * (nt + 1) / 2;
     int I, J;
-    sym_tile<8>(xcd_remap(blockIdx.x, total), nt, I, J);
+    sym_tile<8>(id, nt, I, J);
     const double sigma = stats[1];
     const double s2 = sigma * sigma;
     const int64_t i0 = (int64_t)I * 64, j0 = (int64_t)J * 64;
@@ -979,6 +1028,11 @@ __global__ __launch_bounds__(256) void k_exp_sym(double *W, int64_t ld, int64_t 
     }
 }
 
+__global__ __launch_bounds__(256) void k_exp_sym(double *W, int64_t ld, int64_t n,
+                                                 const double *stats, int nt, double *part) {
+    exp_sym_tile(W, ld, n, stats, nt, part, xcd_remap(blockIdx.x, nt * (nt + 1) / 2));
+}
+
 __global__ void k_degree_reduce(const double *part, int nt, int64_t ld, int64_t n, double *deg) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -996,8 +1050,7 @@ hipError_t launch_exp_degree(double *W, int64_t ld, int64_t n, const double *sta
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_graph_stats(const double *deg, int64_t n,
-                                                     double *stats) {
+__device__ __forceinline__ void graph_stats_body(const double *deg, int64_t n, double *stats) {
     __shared__ double red[4];
     __shared__ double rmin[256], rmax[256];
     double s = 0.0, lo = INFINITY, hi = -INFINITY;
@@ -1030,6 +1083,11 @@ __global__ __launch_bounds__(256) void k_graph_stats(const double *deg, int64_t 
         stats[2] = a;
         stats[3] = b;
     }
+}
+
+__global__ __launch_bounds__(256) void k_graph_stats(const double *deg, int64_t n,
+                                                     double *stats) {
+    graph_stats_body(deg, n, stats);
 }
 
 hipError_t launch_graph_stats(const double *deg, int64_t n, double *stats, hipStream_t s) {
@@ -1066,6 +1124,186 @@ hipError_t launch_import_weights(const double *Win, int64_t ldw, int64_t n, doub
                                  int64_t ld, double *deg, int *flags, hipStream_t s) {
     hipLaunchKernelGGL(k_import_weights, dim3((unsigned)ld), dim3(256), 0, s, Win, ldw, n, W,
                        ld, deg, flags);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// The graph build of many snapshots in grouped launches: each kernel below
+// runs, for workgroup blockIdx.x, the per-snapshot kernel's workgroup
+// blockIdx.x - prefix[p] of snapshot p (found through the kernel's prefix
+// table), with that snapshot's arguments, so the results are the
+// per-snapshot kernels' bit for bit.
+
+bool select_uses_bracket(int64_t n, bool allowed) {
+    const double N = (double)n * (double)(n - 1) / 2.0;
+    return allowed && N * 2.0 * kSelMargin / kSelSample <= 0.8 * (double)select_buffer_keys(n);
+}
+
+int graph_table_count(int tb, int64_t n, int64_t ld, bool bracket) {
+    const int grid = (int)(n < 2048 ? n : 2048);
+    switch (tb) {
+    case kGtRows: return (int)ld;
+    case kGtOne: return 1;
+    case kGtGram: return rect_upper_tiles(ld);
+    case kGtSample: return bracket ? 1 : 0;
+    case kGtBracket: return bracket ? grid : 0;
+    case kGtPass: return grid;
+    case kGtSym: return sym_tiles64(ld);
+    case kGtNodes64: return (int)cdiv(n, 64);
+    case kGtPrep: return (int)cdiv(ld, 256);
+    default: return 0;
+    }
+}
+
+struct GroupSlot {
+    int p;
+    int64_t b, nb;
+};
+__device__ __forceinline__ GroupSlot group_slot(const int *prefix, int P) {
+    GroupSlot g;
+    g.p = group_find(prefix, P, blockIdx.x);
+    g.b = blockIdx.x - prefix[g.p];
+    g.nb = prefix[g.p + 1] - prefix[g.p];
+    return g;
+}
+
+__global__ __launch_bounds__(256) void k_graph_init_grouped(const GraphSnap *snaps, const int *prefix,
+                                                            int P, int select) {
+    const GroupSlot g = group_slot(prefix, P);
+    const GraphSnap &d = snaps[g.p];
+    if (threadIdx.x < 64) d.flags[threadIdx.x] = 0;
+    if (select) select_reset_body(d.sel);
+}
+
+__global__ __launch_bounds__(64) void k_pad_grouped(const GraphSnap *snaps, const int *prefix, int P) {
+    const GroupSlot g = group_slot(prefix, P);
+    const GraphSnap &d = snaps[g.p];
+    pad_row(d.X, d.n, d.T, d.ldx, d.Xp, d.Tp, d.sqn, d.flags, g.b);
+}
+
+__global__ __launch_bounds__(512) void k_gram_grouped(const GraphSnap *snaps, const int *prefix, int P,
+                                                      int select) {
+    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+    const GroupSlot g = group_slot(prefix, P);
+    const GraphSnap &d = snaps[g.p];
+    gram_tile<false>(d.Xp, d.Tp, d.sqn, d.n, d.ld, d.W, (int)(d.ld / 128), 0, (int)(d.ld / 256), 0,
+                     xcd_remap((int)g.b, (int)g.nb), select ? d.sel : nullptr,
+                     (const double *)nullptr, (double *)smem_raw);
+}
+
+__global__ __launch_bounds__(64) void k_select_setup_grouped(const GraphSnap *snaps, const int *prefix,
+                                                             int P) {
+    const GroupSlot g = group_slot(prefix, P);
+    const GraphSnap &d = snaps[g.p];
+    select_setup_body(d.sel, d.n, d.stats);
+}
+
+__global__ __launch_bounds__(1024) void k_select_sample_grouped(const GraphSnap *snaps, const int *prefix,
+                                                                int P) {
+    extern __shared__ unsigned long long sk[];
+    const GroupSlot g = group_slot(prefix, P);
+    const GraphSnap &d = snaps[g.p];
+    select_sample_body(d.W, d.ld, d.n, d.sel, sk);
+}
+
+__global__ __launch_bounds__(256) void k_select_bracket_grouped(const GraphSnap *snaps, const int *prefix,
+                                                                int P) {
+    const GroupSlot g = group_slot(prefix, P);
+    const GraphSnap &d = snaps[g.p];
+    select_bracket_body(d.W, d.ld, d.n, 0, d.n, d.sel, d.buf, d.cap, g.b, g.nb);
+}
+
+__global__ __launch_bounds__(64) void k_select_check_grouped(const GraphSnap *snaps, const int *prefix,
+                                                             int P) {
+    const GroupSlot g = group_slot(prefix, P);
+    const GraphSnap &d = snaps[g.p];
+    select_check_body(d.sel, d.cap, d.stats);
+}
+
+__global__ __launch_bounds__(256) void k_select_pass_grouped(const GraphSnap *snaps, const int *prefix,
+                                                             int P) {
+    const GroupSlot g = group_slot(prefix, P);
+    const GraphSnap &d = snaps[g.p];
+    select_pass_body(d.W, d.ld, d.n, 0, d.n, d.sel, d.buf, g.b, g.nb);
+}
+
+__global__ __launch_bounds__(1024) void k_select_pick_grouped(const GraphSnap *snaps, const int *prefix,
+                                                              int P) {
+    const GroupSlot g = group_slot(prefix, P);
+    select_pick_body(snaps[g.p].sel, snaps[g.p].stats);
+}
+
+__global__ void k_set_sigma_grouped(const GraphSnap *snaps, const int *prefix, int P, double sigma) {
+    const GroupSlot g = group_slot(prefix, P);
+    if (threadIdx.x == 0) snaps[g.p].stats[1] = sigma;
+}
+
+__global__ __launch_bounds__(256) void k_exp_sym_grouped(const GraphSnap *snaps, const int *prefix, int P) {
+    const GroupSlot g = group_slot(prefix, P);
+    const GraphSnap &d = snaps[g.p];
+    const int nt = (int)(d.ld / 64);
+    exp_sym_tile(d.W, d.ld, d.n, d.stats, nt, d.dpart, xcd_remap((int)g.b, (int)g.nb));
+}
+
+__global__ __launch_bounds__(64) void k_degree_grouped(const GraphSnap *snaps, const int *prefix, int P) {
+    const GroupSlot g = group_slot(prefix, P);
+    const GraphSnap &d = snaps[g.p];
+    const int64_t i = g.b * 64 + threadIdx.x;
+    if (i < d.n) d.deg[i] = ordered_sum(d.dpart + i, d.ld, (int)(d.ld / 64), 0.0);
+}
+
+__global__ __launch_bounds__(256) void k_graph_stats_grouped(const GraphSnap *snaps, const int *prefix,
+                                                             int P) {
+    const GroupSlot g = group_slot(prefix, P);
+    graph_stats_body(snaps[g.p].deg, snaps[g.p].n, snaps[g.p].stats);
+}
+
+hipError_t launch_graph_grouped(const GraphSnap *snaps, const int *tables, const int *totals,
+                                int P, double sigma, hipStream_t s) {
+    auto tb = [&](int t) { return tables + (size_t)t * (P + 1); };
+    hipError_t e = gram_attr();
+    if (e != hipSuccess) return e;
+    static bool attr = false;
+    if (!attr) {
+        e = hipFuncSetAttribute((const void *)k_gram_grouped,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGramSmem);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void *)k_select_sample_grouped,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, kSelSample * 8);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const bool select = sigma <= 0.0;
+    hipLaunchKernelGGL(k_graph_init_grouped, dim3(totals[kGtOne]), dim3(256), 0, s, snaps, tb(kGtOne), P,
+                       select ? 1 : 0);
+    hipLaunchKernelGGL(k_pad_grouped, dim3(totals[kGtRows]), dim3(64), 0, s, snaps, tb(kGtRows), P);
+    hipLaunchKernelGGL(k_gram_grouped, dim3(totals[kGtGram]), dim3(512), kGramSmem, s, snaps,
+                       tb(kGtGram), P, select ? 1 : 0);
+    if (select) {
+        hipLaunchKernelGGL(k_select_setup_grouped, dim3(totals[kGtOne]), dim3(64), 0, s, snaps, tb(kGtOne), P);
+        if (totals[kGtSample] > 0) {
+            hipLaunchKernelGGL(k_select_sample_grouped, dim3(totals[kGtSample]), dim3(1024), kSelSample * 8, s,
+                               snaps, tb(kGtSample), P);
+            hipLaunchKernelGGL(k_select_bracket_grouped, dim3(totals[kGtBracket]), dim3(256), 0, s, snaps,
+                               tb(kGtBracket), P);
+            hipLaunchKernelGGL(k_select_check_grouped, dim3(totals[kGtSample]), dim3(64), 0, s, snaps,
+                               tb(kGtSample), P);
+        }
+        // as in the per-snapshot selection: at most 6 digit passes and the
+        // collect pass, each followed by the pick
+        for (int q = 0; q < 7; ++q) {
+            hipLaunchKernelGGL(k_select_pass_grouped, dim3(totals[kGtPass]), dim3(256), 0, s, snaps,
+                               tb(kGtPass), P);
+            hipLaunchKernelGGL(k_select_pick_grouped, dim3(totals[kGtOne]), dim3(1024), 0, s, snaps,
+                               tb(kGtOne), P);
+        }
+    } else {
+        hipLaunchKernelGGL(k_set_sigma_grouped, dim3(totals[kGtOne]), dim3(64), 0, s, snaps, tb(kGtOne), P,
+                           sigma);
+    }
+    hipLaunchKernelGGL(k_exp_sym_grouped, dim3(totals[kGtSym]), dim3(256), 0, s, snaps, tb(kGtSym), P);
+    hipLaunchKernelGGL(k_degree_grouped, dim3(totals[kGtNodes64]), dim3(64), 0, s, snaps, tb(kGtNodes64), P);
+    hipLaunchKernelGGL(k_graph_stats_grouped, dim3(totals[kGtOne]), dim3(256), 0, s, snaps, tb(kGtOne), P);
     return hipGetLastError();
 }
 

@@ -96,6 +96,34 @@ def test_batched_equals_per_snapshot_path_and_graph_replays(cdl, prec, mode, dep
     assert launches == [1, 1, 1]
 
 
+@pytest.mark.parametrize("case", ["given_sigma", "matrix_select"])
+def test_batched_graph_build_variants_equal_per_snapshot_path(cdl, case):
+    """The grouped graph build with a caller's bandwidth (no selection) and
+    with the selection forced onto the matrix (no sampled bracket): the
+    per-snapshot path's results bit for bit (choices pinned)."""
+    seq = small_sequence()
+    Xs = [dev(X) for X in seq.X]
+    gdev = [torch.from_numpy(g).cuda() for g in seq.gid]
+    base = dict(k=24, seed=gen.grid.PROJ_SEED, prec="fp16", depth=2, tol=0.0, max_iter=3,
+                top_k=50, sigma=8.0 if case == "given_sigma" else 0.0)
+    print("batched graph build", case, flush=True)
+    cdl.force_choice("apply", 0)
+    cdl.force_choice("residual", 0)
+    if case == "matrix_select":
+        cdl.set_select(1)
+    try:
+        wF, wT, _ = cdl.score_sequence(Xs, gdev, cdl.SeqParams(**base))
+        Fb, Tb, _ = cdl.score_sequence(Xs, gdev, cdl.SeqParams(**base, asynchronous=True,
+                                                               batched=True))
+        for t in range(len(wF)):
+            np.testing.assert_array_equal(host(Fb[t]), host(wF[t]))
+            np.testing.assert_array_equal(host(Tb[t]), host(wT[t]))
+    finally:
+        cdl.set_select(0)
+        cdl.force_choice("apply", -1)
+        cdl.force_choice("residual", -1)
+
+
 def seq_oracle(seq, k, seed, idx=None):
     out = {}
     for t in (range(len(seq.X)) if idx is None else idx):
