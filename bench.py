@@ -306,6 +306,9 @@ def main():
         tuned = cdl.autotune_lookup("square", p, n)
         sq[p] = {"frac_of_peak": r["frac"], "achieved_tflops": r["achieved"], "peak_tflops": r["peak"],
                  "avg_ms": r["avg_ms"], "executed_tflop_per_launch": round(float(n) ** 3 / 1e12, 3),
+                 # the symmetric kernel computes the n^3 flops of the upper
+                 # tiles; a dense product of the same matrices would take 2 n^3
+                 "dense_equivalent_tflop_per_launch": round(2.0 * float(n) ** 3 / 1e12, 3),
                  "tuned_variant": None if tuned is None else tuned[0]}
         if p in ("bf16", "fp16"):
             sq[p]["vendor_gemm"] = vendor_gemm(torch, p, n)
@@ -702,7 +705,22 @@ def cpu_baseline(pair, k, seed, gpu=None):
     top = stage("top_k", oracle.top_k, F, 50)
     pair_s = sum(st.values())
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    cpu_model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu_model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    blas = None
+    try:
+        info = np.show_config(mode="dicts")
+        blas = info.get("Build Dependencies", {}).get("blas", {}).get("name")
+    except Exception:
+        pass
     out = {"value": round(1.0 / pair_s, 6), "unit": "pairs/s", "cores": threads, "kind": "oracle",
+           "cpu_model": cpu_model, "blas": blas, "host_cpus": os.cpu_count(),
            "sample": "the whole benchmark pair (both snapshots at n = %d, k = %d, scores of all "
                      "nodes), measured stage by stage" % (pair.X0.shape[0], k),
            "seconds_per_pair": round(pair_s, 2),

@@ -22,6 +22,8 @@ import oracle
 
 pytestmark = pytest.mark.gpu
 
+E_ARG, E_NONFINITE, E_GRAPH, E_NOCONV = 1, 3, 4, 6
+
 
 @pytest.fixture(scope="module")
 def cdl():
@@ -228,3 +230,41 @@ def test_c4_scores_and_top50_match_oracle(c4):
         print("  pair %2d: m=%d e_F %.2e gap %.2e" % (t, Fo.size, ef, gap))
     print("C4: %d pairs, worst e_F %.2e, iterations %d" % (len(seq.X) - 1, worst,
                                                            c4["info"].max_iterations))
+
+
+def test_batched_errors(cdl):
+    """Failure handling of the one-pass mode, every case decided on the host
+    (argument checks before any launch, or the final read-back of graph
+    statistics and residuals), so every kernel exits normally."""
+    seq = small_sequence()
+    Xs = [dev(X) for X in seq.X]
+    gdev = [torch.from_numpy(g).cuda() for g in seq.gid]
+    base = dict(k=16, seed=gen.grid.PROJ_SEED, prec="fp16", depth=2, tol=0.0, max_iter=3,
+                asynchronous=True, batched=True)
+    # arguments: FP64 levels, and the one-pass flag without the asynchronous one
+    for bad in (dict(prec="fp64"), dict(asynchronous=False)):
+        q = dict(base)
+        q.update(bad)
+        with pytest.raises(cdl.CdlError) as e:
+            cdl.score_sequence(Xs, gdev, cdl.SeqParams(**q))
+        assert e.value.status == E_ARG
+    # a non-finite value in one snapshot's series
+    Xn = [x.clone() for x in Xs]
+    Xn[2][5, 3] = float("nan")
+    print("batched errors: non-finite series", flush=True)
+    with pytest.raises(cdl.CdlError) as e:
+        cdl.score_sequence(Xn, gdev, cdl.SeqParams(**base))
+    assert e.value.status == E_NONFINITE
+    # a bandwidth so small that every weight underflows: zero degrees
+    print("batched errors: underflowing weights", flush=True)
+    with pytest.raises(cdl.CdlError) as e:
+        cdl.score_sequence(Xs, gdev, cdl.SeqParams(**dict(base, sigma=1e-3)))
+    assert e.value.status in (E_GRAPH, E_NONFINITE)
+    # a residual target the iteration bound cannot reach
+    print("batched errors: no convergence", flush=True)
+    with pytest.raises(cdl.CdlError) as e:
+        cdl.score_sequence(Xs, gdev, cdl.SeqParams(**dict(base, tol=1e-15, max_iter=1)))
+    assert e.value.status == E_NOCONV
+    # the context still works afterwards
+    F, T, info = cdl.score_sequence(Xs, gdev, cdl.SeqParams(**base))
+    assert info.max_iterations == 3 and all(np.isfinite(host(f)).all() for f in F)
