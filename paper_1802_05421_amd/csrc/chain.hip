@@ -244,15 +244,22 @@ hipError_t launch_normalize_rows(int prec, const double *Wp, int64_t ld, int64_t
 
 // 16-bit levels: 256 x 256 tiles on NW = 8 waves (2 x 4 of 128 x 64) or
 // NW = 4 waves (2 x 2 of 128 x 128); FP32/FP64 levels: one configuration.
-template <typename T, int NW> struct SqCfg;
-template <int NW> struct SqCfg<__bf16, NW> { using Core = DmaCore<MfmaBF16, 256, 256, 2, NW / 2>; static constexpr int TILE = 256; };
-template <int NW> struct SqCfg<_Float16, NW> { using Core = DmaCore<MfmaF16, 256, 256, 2, NW / 2>; static constexpr int TILE = 256; };
-template <int NW> struct SqCfg<float, NW> { using Core = GemmCore<MfmaF32, 128, 128, 32, 2, 2>; static constexpr int TILE = 128; };
-template <int NW> struct SqCfg<double, NW> { using Core = GemmCore<MfmaF64, 128, 128, 16, 2, 2>; static constexpr int TILE = 128; };
+// SH: the MFMA shape of the 16-bit cores (32: 32 x 32 x 16, 16: 16 x 16 x 32).
+template <typename T, int NW, int SH = 32> struct SqCfg;
+template <int NW, int SH> struct SqCfg<__bf16, NW, SH> {
+    using Core = DmaCore<std::conditional_t<SH == 16, MfmaBF16x32, MfmaBF16>, 256, 256, 2, NW / 2>;
+    static constexpr int TILE = 256;
+};
+template <int NW, int SH> struct SqCfg<_Float16, NW, SH> {
+    using Core = DmaCore<std::conditional_t<SH == 16, MfmaF16x32, MfmaF16>, 256, 256, 2, NW / 2>;
+    static constexpr int TILE = 256;
+};
+template <int NW, int SH> struct SqCfg<float, NW, SH> { using Core = GemmCore<MfmaF32, 128, 128, 32, 2, 2>; static constexpr int TILE = 128; };
+template <int NW, int SH> struct SqCfg<double, NW, SH> { using Core = GemmCore<MfmaF64, 128, 128, 16, 2, 2>; static constexpr int TILE = 128; };
 
-template <typename T, int NW> constexpr size_t sq_smem() {
-    using C = typename SqCfg<T, NW>::Core;
-    constexpr int TL = SqCfg<T, NW>::TILE;
+template <typename T, int NW, int SH = 32> constexpr size_t sq_smem() {
+    using C = typename SqCfg<T, NW, SH>::Core;
+    constexpr int TL = SqCfg<T, NW, SH>::TILE;
     constexpr size_t stage = (size_t)TL * (TL + 16 / sizeof(T)) * sizeof(T);
     return C::SMEM > stage ? C::SMEM : stage;
 }
@@ -297,12 +304,12 @@ __device__ inline void square_epilogue(Core &g, const T *A, const T *B, T *S2, i
 // tiles, or the full rounds of 256 workgroups when the last round is split
 // over k below).  The squaring is A = B = S, add = 0.
 // Upper tile `id` of C = A B and its epilogue (one workgroup).
-template <typename T, int NW>
+template <typename T, int NW, int SH = 32>
 __device__ __forceinline__ void square_tile(const T *A, const T *B, T *S2, int64_t ld, int64_t kend, int nt,
                                    int id, float inv_scale, int add, double *fro_part,
                                    char *smem_raw, double *red) {
-    using Core = typename SqCfg<T, NW>::Core;
-    constexpr int TL = SqCfg<T, NW>::TILE;
+    using Core = typename SqCfg<T, NW, SH>::Core;
+    constexpr int TL = SqCfg<T, NW, SH>::TILE;
     int I, J;
     sym_tile<8>(id, nt, I, J);
     const int64_t m0 = (int64_t)I * TL, n0 = (int64_t)J * TL;
@@ -312,16 +319,16 @@ __device__ __forceinline__ void square_tile(const T *A, const T *B, T *S2, int64
                        (T *)smem_raw, red);
 }
 
-template <typename T, int NW>
-__global__ __launch_bounds__((SqCfg<T, NW>::Core::NT)) void k_square(const T *A, const T *B, T *S2, int64_t ld,
+template <typename T, int NW, int SH>
+__global__ __launch_bounds__((SqCfg<T, NW, SH>::Core::NT)) void k_square(const T *A, const T *B, T *S2, int64_t ld,
                                                 int64_t kend, int nt, int count, float inv_scale,
                                                 int add, double *fro_part) {
-    using Core = typename SqCfg<T, NW>::Core;
-    constexpr int TL = SqCfg<T, NW>::TILE;
+    using Core = typename SqCfg<T, NW, SH>::Core;
+    constexpr int TL = SqCfg<T, NW, SH>::TILE;
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
     __shared__ double red[Core::NT / 64];
     const int id = TL == 256 ? round_remap(blockIdx.x, count) : xcd_remap(blockIdx.x, count);
-    square_tile<T, NW>(A, B, S2, ld, kend, nt, id, inv_scale, add, fro_part, smem_raw, red);
+    square_tile<T, NW, SH>(A, B, S2, ld, kend, nt, id, inv_scale, add, fro_part, smem_raw, red);
 }
 
 // Level `level` squared into level + 1 for every snapshot of a sequence:
@@ -346,12 +353,12 @@ __global__ __launch_bounds__((SqCfg<T, 8>::Core::NT)) void k_square_grouped(cons
 // first + b / splits), each split into `splits` k-ranges of ks elements:
 // workgroup b multiplies its range and stores the FP32 accumulators as a
 // partial tile (element e of thread t at P[b * TL^2 + e * NT + t]).
-template <typename T, int NW>
-__global__ __launch_bounds__((SqCfg<T, NW>::Core::NT)) void k_square_part(const T *A, const T *B, int64_t ld,
+template <typename T, int NW, int SH>
+__global__ __launch_bounds__((SqCfg<T, NW, SH>::Core::NT)) void k_square_part(const T *A, const T *B, int64_t ld,
                                                      int64_t kend, int64_t ks, int nt, int first,
                                                      int splits, float *P) {
-    using Core = typename SqCfg<T, NW>::Core;
-    constexpr int TL = SqCfg<T, NW>::TILE;
+    using Core = typename SqCfg<T, NW, SH>::Core;
+    constexpr int TL = SqCfg<T, NW, SH>::TILE;
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
     const int b = blockIdx.x, sp = b % splits;
     int I, J;
@@ -372,13 +379,13 @@ __global__ __launch_bounds__((SqCfg<T, NW>::Core::NT)) void k_square_part(const 
 
 // One workgroup per tile of the split round: the partial tiles summed in
 // split order into the accumulator layout of the core, then the epilogue.
-template <typename T, int NW>
-__global__ __launch_bounds__((SqCfg<T, NW>::Core::NT)) void k_square_tail(const T *A, const T *B, T *S2,
+template <typename T, int NW, int SH>
+__global__ __launch_bounds__((SqCfg<T, NW, SH>::Core::NT)) void k_square_tail(const T *A, const T *B, T *S2,
                                                      int64_t ld, int nt, int first, int splits,
                                                      const float *P, float inv_scale, int add,
                                                      double *fro_part) {
-    using Core = typename SqCfg<T, NW>::Core;
-    constexpr int TL = SqCfg<T, NW>::TILE;
+    using Core = typename SqCfg<T, NW, SH>::Core;
+    constexpr int TL = SqCfg<T, NW, SH>::TILE;
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
     __shared__ double red[Core::NT / 64];
     const int id = first + blockIdx.x;
@@ -443,16 +450,16 @@ size_t square_tail_bytes(int prec, int64_t ld, int64_t n) {
     return (size_t)p.rem * p.splits * 256 * 256 * sizeof(float);
 }
 
-template <typename T, int NW>
+template <typename T, int NW, int SH = 32>
 static hipError_t sq_launch(const void *A, const void *B, void *S2, int64_t ld, int64_t n,
                             float inv_scale, int add, double *fro_part, float *tail, hipStream_t s) {
-    using Cfg = SqCfg<T, NW>;
+    using Cfg = SqCfg<T, NW, SH>;
     constexpr int TL = Cfg::TILE;
-    constexpr size_t smem = sq_smem<T, NW>();
+    constexpr size_t smem = sq_smem<T, NW, SH>();
     static bool attr = false;
     if (!attr) {
-        for (const void *fn : {(const void *)k_square<T, NW>, (const void *)k_square_part<T, NW>,
-                               (const void *)k_square_tail<T, NW>}) {
+        for (const void *fn : {(const void *)k_square<T, NW, SH>, (const void *)k_square_part<T, NW, SH>,
+                               (const void *)k_square_tail<T, NW, SH>}) {
             hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
             if (e != hipSuccess) return e;
         }
@@ -464,36 +471,47 @@ static hipError_t sq_launch(const void *A, const void *B, void *S2, int64_t ld, 
     SqPlan p = square_plan(prec, ld, n);
     if (!tail) p = SqPlan{p.total, p.total, 0, 0, p.kend, 0};
     constexpr int NT = Cfg::Core::NT;
-    hipLaunchKernelGGL((k_square<T, NW>), dim3(p.full), dim3(NT), smem, s, (const T *)A,
+    hipLaunchKernelGGL((k_square<T, NW, SH>), dim3(p.full), dim3(NT), smem, s, (const T *)A,
                        (const T *)B, (T *)S2, ld, p.kend, nt, p.full, inv_scale, add, fro_part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || p.rem == 0) return e;
-    hipLaunchKernelGGL((k_square_part<T, NW>), dim3(p.rem * p.splits), dim3(NT), smem, s,
+    hipLaunchKernelGGL((k_square_part<T, NW, SH>), dim3(p.rem * p.splits), dim3(NT), smem, s,
                        (const T *)A, (const T *)B, ld, p.kend, p.ks, nt, p.full, p.splits, tail);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_square_tail<T, NW>), dim3(p.rem), dim3(NT), smem, s, (const T *)A,
+    hipLaunchKernelGGL((k_square_tail<T, NW, SH>), dim3(p.rem), dim3(NT), smem, s, (const T *)A,
                        (const T *)B, (T *)S2, ld, nt, p.full, p.splits, (const float *)tail,
                        inv_scale, add, fro_part);
     return hipGetLastError();
 }
 
-int square_variants(int prec) { return prec == 2 || prec == 3 ? 4 : 1; }
+int square_variants(int prec) { return prec == 2 || prec == 3 ? 6 : 1; }
 
-// variant (16-bit levels): bit 0 set = no k-split of the last round, bit 1
-// set = the 4-wave core; other types have one variant.
+// (the 4-wave core with 16 x 16 x 32 MFMAs needs more than its 512
+// registers and is not a candidate)
+template <typename T>
+static hipError_t sq_dispatch16(const void *A, const void *B, void *C, int64_t ld, int64_t n,
+                                float inv, int add, double *fro_part, float *t, int variant,
+                                hipStream_t s) {
+    switch (variant >> 1) {
+    case 0: return sq_launch<T, 8, 32>(A, B, C, ld, n, inv, add, fro_part, t, s);
+    case 1: return sq_launch<T, 4, 32>(A, B, C, ld, n, inv, add, fro_part, t, s);
+    default: return sq_launch<T, 8, 16>(A, B, C, ld, n, inv, add, fro_part, t, s);
+    }
+}
+
+// variant (16-bit levels, 0..5): bit 0 set = no k-split of the last round;
+// variant >> 1 = 0: 8-wave core, 32 x 32 x 16 MFMAs; 1: 4-wave core, 32 x 32
+// x 16; 2: 8-wave core, 16 x 16 x 32.  Other types have one variant.
 static hipError_t sq_dispatch(int prec, const void *A, const void *B, void *C, int64_t ld, int64_t n,
                               int add, double *fro_part, float *tail, int variant, hipStream_t s) {
     const float inv = 1.0f / level_scale(prec, n);
     float *t = (variant & 1) ? nullptr : tail;
-    const bool four = (variant & 2) != 0;
     switch (prec) {
     case 0: return sq_launch<double, 8>(A, B, C, ld, n, inv, add, fro_part, nullptr, s);
     case 1: return sq_launch<float, 8>(A, B, C, ld, n, inv, add, fro_part, nullptr, s);
-    case 2: return four ? sq_launch<__bf16, 4>(A, B, C, ld, n, inv, add, fro_part, t, s)
-                        : sq_launch<__bf16, 8>(A, B, C, ld, n, inv, add, fro_part, t, s);
-    case 3: return four ? sq_launch<_Float16, 4>(A, B, C, ld, n, inv, add, fro_part, t, s)
-                        : sq_launch<_Float16, 8>(A, B, C, ld, n, inv, add, fro_part, t, s);
+    case 2: return sq_dispatch16<__bf16>(A, B, C, ld, n, inv, add, fro_part, t, variant, s);
+    case 3: return sq_dispatch16<_Float16>(A, B, C, ld, n, inv, add, fro_part, t, variant, s);
     default: return hipErrorInvalidValue;
     }
 }

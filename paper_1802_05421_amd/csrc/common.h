@@ -56,6 +56,35 @@ struct MfmaF16 {
     __device__ static inline int ccol(int lane) { return lane & 31; }
 };
 
+// The 16 x 16 x 32 forms: half the work and latency of the 32 x 32 x 16
+// instruction, the same per-lane operand layout (8 consecutive reduction
+// elements of one row), four accumulators per lane.
+struct MfmaBF16x32 {
+    using T = __bf16;
+    using Frag = bf16x8;
+    using Acc = float;
+    using AccV = f32x4;
+    static constexpr int M = 16, KI = 32, E = 8, R = 4;
+    __device__ static inline AccV mma(const Frag &a, const Frag &b, const AccV &c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+    __device__ static inline int crow(int lane, int r) { return 4 * (lane >> 4) + r; }
+    __device__ static inline int ccol(int lane) { return lane & 15; }
+};
+
+struct MfmaF16x32 {
+    using T = _Float16;
+    using Frag = f16x8;
+    using Acc = float;
+    using AccV = f32x4;
+    static constexpr int M = 16, KI = 32, E = 8, R = 4;
+    __device__ static inline AccV mma(const Frag &a, const Frag &b, const AccV &c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+    __device__ static inline int crow(int lane, int r) { return 4 * (lane >> 4) + r; }
+    __device__ static inline int ccol(int lane) { return lane & 15; }
+};
+
 struct MfmaF32 {
     using T = float;
     using Frag = float;

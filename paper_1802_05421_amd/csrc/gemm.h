@@ -262,7 +262,7 @@ struct DmaCore {
     static constexpr int NF = WTM + WTN;          // fragment reads per k-step
     static constexpr int NM = WTM * WTN;          // MFMAs per k-step
     static_assert(AI * RPI * NW == BM && BI * RPI * NW == BN, "rows per wave");
-    static_assert(NKK == 4, "four k-steps per stage");
+    static_assert(NKK >= 2 && NKK % 2 == 0, "an even number of k-steps per stage");
 
     AccV acc[WTM][WTN];
 

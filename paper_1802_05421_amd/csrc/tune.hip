@@ -1,8 +1,9 @@
 // Measured tuning of launch configurations (host code).
 //
 // Three kernel families have more than one correct launch configuration:
-//   square    16-bit levels: 256 x 256 tiles on 8 or 4 waves, the last
-//             partial round of workgroups split over k or not (4 candidates)
+//   square    16-bit levels: 256 x 256 tiles on 8 waves (32 x 32 x 16 or
+//             16 x 16 x 32 MFMAs) or on 4 waves (32 x 32 x 16), the last
+//             partial round of workgroups split over k or not (6 candidates)
 //   apply     16-bit and FP32 levels: the split-K count of the chain
 //             application (default, half, double: 3 candidates)
 //   residual  the split-K count of the FP64 residual product (3 candidates)

@@ -1,5 +1,5 @@
 """The measured launch-configuration tuner: a tuning context times every
-candidate of the squaring (4 tile variants), the chain application and the
+candidate of the squaring (6 tile variants), the chain application and the
 FP64 residual product (3 split-K counts each) on first use of a shape, and
 keeps the fastest; every candidate must give the oracle's results within the
 tolerances of the untuned path (the squared level within its rounding bound,
@@ -88,9 +88,9 @@ def test_squaring_tuned_and_every_variant_within_bound(cdl, square_case, prec):
     assert entry is not None
     choice, ncand, ms = entry
     print("square %s n=%d: choice %d of %d, %.3f ms" % (prec, n, choice, ncand, ms), flush=True)
-    assert ncand == 4 and 0 <= choice < 4 and ms > 0
+    assert ncand == 6 and 0 <= choice < 6 and ms > 0
     assert check_level1(square_case, L1, prec, n) <= 1.0
-    for v in range(4):
+    for v in range(6):
         cdl.force_choice("square", v)
         try:
             ratio = check_level1(square_case, level1(cdl, square_case, prec), prec, n)
