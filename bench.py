@@ -158,6 +158,11 @@ def main():
                     help="also time one streamed pair on a G x G grid (e.g. 512: n = 262144)")
     ap.add_argument("--stream-only", action="store_true",
                     help="run only the streamed section (prints its results as one JSON line)")
+    ap.add_argument("--square-only", default="",
+                    help="profiling runs: only two chain builds of depth 2 in this type (fp16/bf16/fp32) "
+                         "on the first snapshot, one squaring each (prints one JSON line)")
+    ap.add_argument("--square-variant", type=int, default=-1,
+                    help="with --square-only: pin the squaring's launch variant (-1: the default)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="profiling runs: exactly 4 plain 1 GiB copies first (the byte counters' reference)")
     args = ap.parse_args()
@@ -186,6 +191,21 @@ def main():
     dev = torch.device("cuda:0")
     X = [torch.from_numpy(pair.X0).to(dev), torch.from_numpy(pair.X1).to(dev)]
     Xpair = list(X)
+    if args.square_only:   # one squaring per chain build, for counters
+        g0 = cdl.build_graph(X[0])
+        if args.square_variant >= 0:
+            cdl.force_choice("square", args.square_variant)
+        for _ in range(2):
+            cdl.build_chain(g0, prec=args.square_only, depth=2, depth_max=6)
+        torch.cuda.synchronize()
+        cdl.timing(reset=True)
+        cdl.set_timing(True)
+        cdl.build_chain(g0, prec=args.square_only, depth=2, depth_max=6)
+        cdl.set_timing(False)
+        r = roofline(cdl.timing(reset=True), "square", n, k, T, args.square_only)
+        print(json.dumps({"square_only": args.square_only, "variant": args.square_variant,
+                          "roofline": r}), flush=True)
+        return
     if args.stream_only:   # the streamed section alone (for kernel traces)
         print(json.dumps({"streamed": streamed_section(args, cdl, gen, torch, dev, Xpair, n, T, k,
                                                        seed, None)}), flush=True)
