@@ -9,6 +9,7 @@ fallback: if the library is missing, importing the package fails.
 from __future__ import annotations
 
 import ctypes as C
+import weakref
 from dataclasses import dataclass, field
 from typing import List, Optional, Sequence
 
@@ -503,21 +504,23 @@ class SeqParams:
 
 
 # Host and device int32 copies of global-id tensors, so that repeated calls
-# on the same ids copy nothing.  An entry holds the tensor object itself (its
-# memory cannot be handed to another tensor while cached) and its version
-# counter (an in-place write bumps it and invalidates the entry).
+# on the same ids copy nothing.  An entry is keyed by the tensor object (a
+# weak reference: the entry goes when the tensor does, so a later tensor at
+# the same address never meets it) and holds its version counter (an
+# in-place write bumps it and invalidates the entry).
 _gid_cache: dict = {}
 
 
 def _gid_copies(g: torch.Tensor, dev):
-    hit = _gid_cache.get(id(g))
-    if hit is not None and hit[0] is g and hit[1] == g._version and hit[2] == dev:
-        return hit[3], hit[4]
-    if len(_gid_cache) > 4096:
-        _gid_cache.clear()
+    key = id(g)
+    hit = _gid_cache.get(key)
+    if hit is not None and hit[0]() is g and hit[1] == g._version and hit[2] == dev:
+        return (g if hit[3] is None else hit[3]), (g if hit[4] is None else hit[4])
     host = g.cpu().to(torch.int32).contiguous()
     devc = g.to(device=dev, dtype=torch.int32).contiguous()
-    _gid_cache[id(g)] = (g, g._version, dev, host, devc)
+    ref = weakref.ref(g, lambda _r, k=key: _gid_cache.pop(k, None))
+    # a copy that is the tensor itself is not held (that would keep it alive)
+    _gid_cache[key] = (ref, g._version, dev, None if host is g else host, None if devc is g else devc)
     return host, devc
 
 

@@ -1741,17 +1741,16 @@ void common_maps(const cdl_snapshot &y, const cdl_snapshot &x, std::vector<int32
     }
 }
 
-// Chain with a fixed number of levels, no host reads (square = false: level 0
-// only; the caller squares, grouped over several chains).
+// Chain with a fixed number of levels, no host reads.
 cdl_status chain_enqueue(cdl_ctx *ctx, const double *W, const double *deg, const double *stats,
-                         int64_t n, int prec, int depth, void *chain, bool square = true) {
+                         int64_t n, int prec, int depth, void *chain) {
     Arena a(chain);
     ChainBuf c = plan_chain(a, n, prec, depth);
     const int64_t ld = pad_n(n);
     hipStream_t s = ctx->stream;
     { Timed t_(ctx, "chain_prep"); HIPCHK(launch_chain_prep(deg, stats, n, ld, 0, c.dmn, c.dm, c.u, s)); }
     { Timed t_(ctx, "normalize"); HIPCHK(launch_normalize(prec, W, ld, n, c.dmn, c.u, 0, c.levels, c.fro, c.fro64, s)); }
-    for (int l = 0; square && l + 1 < depth; ++l) {
+    for (int l = 0; l + 1 < depth; ++l) {
         const cdl_status sq = square_step(ctx, prec, c.levels + c.level_bytes * l, c.levels + c.level_bytes * l,
                                           c.levels + c.level_bytes * (l + 1), ld, n, c, false);
         if (sq != CDL_OK) return sq;

@@ -216,3 +216,25 @@ def test_autotune_table_json_round_trip(L, tmp_path):
     assert L.cdl_autotune_load(str(bad).encode()) == 1
     assert L.cdl_autotune_load(str(tmp_path / "missing.json").encode()) == 1
     assert L.cdl_autotune_clear() == 0
+
+
+def test_sequence_id_cache_follows_the_tensors():
+    """The binding's cached host/device copies of global ids: reused while the
+    tensor is unchanged, refreshed after an in-place write, dropped when the
+    tensor is freed (so a new tensor at a reused address never sees them)."""
+    import gc
+
+    import torch
+
+    from paper_1802_05421_amd import api
+    cpu = torch.device("cpu")
+    g = torch.arange(16, dtype=torch.int64)
+    h, d = api._gid_copies(g, cpu)
+    assert h.dtype == torch.int32 and api._gid_copies(g, cpu)[0] is h
+    g[3] = 99
+    h2, _ = api._gid_copies(g, cpu)
+    assert h2 is not h and int(h2[3]) == 99
+    n = len(api._gid_cache)
+    del g, h, d, h2, _
+    gc.collect()
+    assert len(api._gid_cache) == n - 1
