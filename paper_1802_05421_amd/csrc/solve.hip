@@ -3,10 +3,10 @@
 // over the k columns).
 //
 //   rhs         Y = B^T W^{1/2} Q^T / sqrt(k) with counter-based SplitMix64
-//               signs, one row of Y per wave (lane = neighbour j), FP64
-//               accumulation of EXEC-masked adds, deterministic butterfly
-//               reduction; rhs_pair does the same for two snapshots on one
-//               node set, each sign word and lane mask serving both
+//               signs: per row, the signed sums as an exact int8 MFMA
+//               product of the sign bits with base-256 digits of the scaled
+//               weights; the pair form serves two snapshots on one node set
+//               with each sign word
 //   streamed    the products with W of the streamed solve, one row panel of
 //               W at a time, and the one-level chain's vector steps
 //   residual    R = Y - (deg * X - W X) on FP64 MFMA, per-column partial
@@ -25,15 +25,48 @@
 
 namespace cdl {
 
-// SplitMix64 output function (Steele, Lea & Flood, OOPSLA 2014), split after
-// its first step z ^ (z >> 30): that step is linear over GF(2), so it can be
-// applied to the parts of a key separately and the results XORed.
-__device__ inline uint64_t xorshift30(uint64_t z) { return z ^ (z >> 30); }
-__device__ inline uint64_t splitmix64_mix_tail(uint64_t z) {
-    z = z * 0xbf58476d1ce4e5b9ull;
-    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
-    return z ^ (z >> 31);
-}
+// Right-hand sides on the int8 matrix cores.
+//
+// Column r of row i is y_i[r] = (T - 2 M_r) / sqrt(k): v_j = c_j sqrt(W_ij)
+// (c_j = -1 when i is the tail of edge {i, j}, the end with the higher global
+// id), T = sum_j v_j and M_r = sum_j b_jr v_j, where b_jr is bit r mod 64 of
+// the SplitMix64 sign word of the edge for projection block r / 64 (a set bit
+// negates the sign; Steele, Lea & Flood, OOPSLA 2014, for the mixer).  For a
+// row, M is a (columns x neighbours) 0/1 matrix times the vector v, summed
+// here exactly on v_mfma_i32_16x16x64_i8:
+//   * per chunk of 1024 neighbours and snapshot, v is scaled by a power of two
+//     2^e chosen from the chunk's largest |v| so that V = rint(2^e v) has
+//     |V| <= 2^54, and V is split into seven balanced base-256 digits d_s in
+//     [-128, 127] (V = sum_s d_s 256^s: the bytes of V + 0x80808080808080,
+//     each XOR 0x80);
+//   * the sign bits enter as bytes holding one bit, 2^p with p in 0..7 (p = 7
+//     reads as -128 in int8): bit plane b of a 64-bit word is its byte b, and
+//     MFMA c (c = 0..3) takes for its row m the bit 4 m + c, found in byte
+//     m / 2 at position p = 4 (m & 1) + c, by one AND per four neighbours;
+//   * one MFMA multiplies 16 columns by 16 digit slots (seven digits of each
+//     snapshot and a zero slot) over 64 neighbours; the int32 sums are
+//     exact (|sum| <= 2^22 per chunk and wave) and are scaled into FP64
+//     accumulators after every chunk (times 256^s 2^-e / 2^p, all powers of
+//     two).
+// So the only rounding is V = rint(2^e v) (at most 2^-55 of the chunk's
+// largest |v| per term) and the FP64 sums; T is summed in FP64 from v itself,
+// which also carries non-finite weights into y.
+//
+// A workgroup is one row and NB projection blocks of 64 columns: 4 NB waves,
+// wave (beta, kq) multiplying its block over every fourth 64-neighbour step
+// of a chunk.  Staging, per chunk: thread (beta, q) hashes the sign words of
+// neighbours q + 256 e (e = 0..3) and stores them as 8 bit planes of 4
+// bytes; the digit threads (one per snapshot and q) take the square roots,
+// the chunk maxima and the digits, stored as 7 rows of 4 bytes.  A neighbour
+// sits at the same byte position in the planes and in the digit rows, which
+// is all the contraction needs.  The sign words and digits of chunk c are
+// staged while the MFMAs of chunk c - 1 run from the other LDS buffer; the
+// loads and square roots of chunk c + 1 follow; one barrier per chunk.
+
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kRhsChunk = 1024;
+constexpr int kRhsPitch = kRhsChunk + 64;   // bytes per LDS row (spreads the banks)
 
 static uint64_t splitmix64_mix_host(uint64_t z) {
     z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
@@ -41,353 +74,310 @@ static uint64_t splitmix64_mix_host(uint64_t z) {
     return z ^ (z >> 31);
 }
 
-// acc_q += w on the lanes whose next bit of h (most significant first) is
-// set, for eight bits; h is shifted left by eight.  Doubling h moves its top
-// bit into the carry mask of that lane; the FP64 add then runs with EXEC
-// restricted to the carry mask: two VALU instructions per column instead of
-// the three a per-lane sign insertion needs.  EXEC is saved and restored
-// inside the block, so inactive lanes (loop tails) stay inactive.
-__device__ __forceinline__ void masked_add8(uint32_t &h, double w, double &a0, double &a1,
-                                            double &a2, double &a3, double &a4, double &a5,
-                                            double &a6, double &a7) {
-    uint64_t sv, m0, m1, m2, m3, m4, m5, m6, m7;
-    asm volatile(
-        "s_mov_b64 %[sv], exec\n\t"
-        "v_add_co_u32 %[h], %[m0], %[h], %[h]\n\t"
-        "v_add_co_u32 %[h], %[m1], %[h], %[h]\n\t"
-        "v_add_co_u32 %[h], %[m2], %[h], %[h]\n\t"
-        "v_add_co_u32 %[h], %[m3], %[h], %[h]\n\t"
-        "v_add_co_u32 %[h], %[m4], %[h], %[h]\n\t"
-        "v_add_co_u32 %[h], %[m5], %[h], %[h]\n\t"
-        "v_add_co_u32 %[h], %[m6], %[h], %[h]\n\t"
-        "v_add_co_u32 %[h], %[m7], %[h], %[h]\n\t"
-        "s_and_b64 exec, %[sv], %[m0]\n\t"
-        "v_add_f64 %[a0], %[a0], %[w]\n\t"
-        "s_and_b64 exec, %[sv], %[m1]\n\t"
-        "v_add_f64 %[a1], %[a1], %[w]\n\t"
-        "s_and_b64 exec, %[sv], %[m2]\n\t"
-        "v_add_f64 %[a2], %[a2], %[w]\n\t"
-        "s_and_b64 exec, %[sv], %[m3]\n\t"
-        "v_add_f64 %[a3], %[a3], %[w]\n\t"
-        "s_and_b64 exec, %[sv], %[m4]\n\t"
-        "v_add_f64 %[a4], %[a4], %[w]\n\t"
-        "s_and_b64 exec, %[sv], %[m5]\n\t"
-        "v_add_f64 %[a5], %[a5], %[w]\n\t"
-        "s_and_b64 exec, %[sv], %[m6]\n\t"
-        "v_add_f64 %[a6], %[a6], %[w]\n\t"
-        "s_and_b64 exec, %[sv], %[m7]\n\t"
-        "v_add_f64 %[a7], %[a7], %[w]\n\t"
-        "s_mov_b64 exec, %[sv]"
-        : [h] "+v"(h), [a0] "+v"(a0), [a1] "+v"(a1), [a2] "+v"(a2), [a3] "+v"(a3),
-          [a4] "+v"(a4), [a5] "+v"(a5), [a6] "+v"(a6), [a7] "+v"(a7), [sv] "=&s"(sv),
-          [m0] "=&s"(m0), [m1] "=&s"(m1), [m2] "=&s"(m2), [m3] "=&s"(m3), [m4] "=&s"(m4),
-          [m5] "=&s"(m5), [m6] "=&s"(m6), [m7] "=&s"(m7)
-        : [w] "v"(w)
-        : "scc");
+__device__ __forceinline__ uint64_t rhs_sign_word(uint64_t mseed, uint64_t key) {
+    uint64_t z = mseed ^ key;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
 }
 
-// Row i of Y for one projection block beta (64 columns).  The sign of edge
-// {i, j} in column r is B(e, i) * q_r(e) = c (1 - 2 b), b = bit r of the sign
-// word, c = 1 when i is the head (lower global id) and -1 when it is the
-// tail.  So sum_j s_j w_j = T - 2 M_r with v_j = c_j w_j, T = sum_j v_j and
-// M_r the sum of v_j over the j whose bit is set, all in FP64; the sums'
-// rounding errors stay below 1e-15 sum_j w_j, far below |y| here.
-//
-// A workgroup is 4 waves: 4/P rows, P projection blocks per row.  The P
-// waves of a row share sqrt(W_ij) and the global ids through LDS: per
-// iteration each computes them for its own 64 neighbours, then all P waves
-// sweep the P * 64 neighbours with their own sign words.
-//
-// Rows [row0, row1): row i is read at W + (i - row0) ld (the whole matrix with
-// row0 = 0, row1 = n, or one row panel of it).
-template <int P>
-__global__ __launch_bounds__(256) void k_rhs(const double *W, int64_t ld, int64_t n,
-                                             int64_t row0, int64_t row1,
-                                             const int32_t *gid, int64_t k, uint64_t mseed,
-                                             double inv_sqrt_k, int nb, double *Yt) {
-    constexpr int R = 4 / P;
-    __shared__ double sw[R][P * 64];   // c_j sqrt(W_ij)
-    __shared__ uint2 sz[R][P * 64];    // xorshift30 of the key of {i, j} (beta = 0) XOR the mixed seed
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int rs = wv / P, q = wv % P;
-    // Workgroups are dispatched round-robin over the XCDs: the projection
-    // groups of one row group get ids 8 apart, so they run together on one
-    // XCD and read those rows of W through its L2 once.
-    const int nbg = (nb + P - 1) / P;
-    const int w = blockIdx.x, per = kNumXcd * nbg, l = w % per;
-    const int64_t group = (int64_t)(w / per) * kNumXcd + l % kNumXcd;
-    const int beta_i = (l / kNumXcd) * P + q;
-    const uint64_t beta = (uint64_t)beta_i;
-    const int64_t i = row0 + group * R + rs;
-    const bool row_ok = i < row1, active = row_ok && beta_i < nb;
-    const uint32_t gi = !row_ok ? 0u : (gid ? (uint32_t)gid[i] : (uint32_t)i);
-    // The key beta << 40 | lo << 20 | hi of a pair (ids < 2^20) XOR the mixed
-    // seed in 32-bit halves: low = lo << 20 | hi, high = beta << 8 | lo >> 12
-    // (disjoint bits, so the ORs are XORs and beta enters last).
-    const uint32_t seed_lo = (uint32_t)mseed, seed_hi = (uint32_t)(mseed >> 32);
-    const uint64_t fbeta = xorshift30((uint64_t)((uint32_t)beta_i << 8) << 32);
-    double acc[64];
+// out[b] = byte b of a0, a1, a2, a3 (in that order from the low byte).
+__device__ __forceinline__ void rhs_bytes4(uint32_t a0, uint32_t a1, uint32_t a2, uint32_t a3,
+                                           uint32_t out[4]) {
 #pragma unroll
-    for (int r = 0; r < 64; ++r) acc[r] = 0.0;
-    double tsum = 0.0;
-    const double *row = W + (row_ok ? i - row0 : 0) * ld;
-    for (int64_t j0 = 0; j0 < n; j0 += P * 64) {
-        {   // per neighbour, once for the P projection blocks: the correctly
-            // rounded sqrt(W) (the bare hardware instruction is only an
-            // approximation in FP64), negated when row i is the edge's tail
-            // (gi > gj: every sign flips, so T and M both take -w), and the
-            // key halves; zero beyond n (no contribution whatever the sign)
-            const int64_t j = j0 + q * 64 + lane;
-            double v = 0.0;
-            uint2 z = make_uint2(0u, 0u);
-            if (row_ok && j < n) {
-                const uint32_t gj = gid ? (uint32_t)gid[j] : (uint32_t)j;
-                const double wj = sqrt(row[j]);
-                const uint32_t lo = gi < gj ? gi : gj, hi = gi < gj ? gj : gi;
-                const uint64_t f = xorshift30(((uint64_t)((lo >> 12) ^ seed_hi) << 32) |
-                                              (((lo << 20) | hi) ^ seed_lo));
-                z = make_uint2((uint32_t)f, (uint32_t)(f >> 32));
-                v = gi > gj ? -wj : wj;
-            }
-            sw[rs][q * 64 + lane] = v;
-            sz[rs][q * 64 + lane] = z;
-        }
-        __syncthreads();
-        if (active) {
-#pragma unroll
-            for (int sub = 0; sub < P; ++sub) {
-                const double ws = sw[rs][sub * 64 + lane];
-                const uint2 z = sz[rs][sub * 64 + lane];
-                const uint64_t h = splitmix64_mix_tail((((uint64_t)z.y << 32) | z.x) ^ fbeta);
-                tsum += ws;
-                uint32_t hh = (uint32_t)(h >> 32), hl = (uint32_t)h;
-                masked_add8(hh, ws, acc[63], acc[62], acc[61], acc[60], acc[59], acc[58], acc[57], acc[56]);
-                masked_add8(hh, ws, acc[55], acc[54], acc[53], acc[52], acc[51], acc[50], acc[49], acc[48]);
-                masked_add8(hh, ws, acc[47], acc[46], acc[45], acc[44], acc[43], acc[42], acc[41], acc[40]);
-                masked_add8(hh, ws, acc[39], acc[38], acc[37], acc[36], acc[35], acc[34], acc[33], acc[32]);
-                masked_add8(hl, ws, acc[31], acc[30], acc[29], acc[28], acc[27], acc[26], acc[25], acc[24]);
-                masked_add8(hl, ws, acc[23], acc[22], acc[21], acc[20], acc[19], acc[18], acc[17], acc[16]);
-                masked_add8(hl, ws, acc[15], acc[14], acc[13], acc[12], acc[11], acc[10], acc[9], acc[8]);
-                masked_add8(hl, ws, acc[7], acc[6], acc[5], acc[4], acc[3], acc[2], acc[1], acc[0]);
-            }
-        }
-        __syncthreads();
-    }
-    if (!active) return;
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) tsum += __shfl_xor(tsum, o);
-    // Butterfly transpose-reduction: afterwards lane l holds column l summed
-    // over all 64 lanes.
-#pragma unroll
-    for (int s = 32; s >= 1; s >>= 1) {
-        const bool up = (lane & s) != 0;
-#pragma unroll
-        for (int q2 = 0; q2 < s; ++q2) {
-            const double send = up ? acc[q2] : acc[q2 + s];
-            const double keep = up ? acc[q2 + s] : acc[q2];
-            acc[q2] = keep + __shfl_xor(send, s);
-        }
-    }
-    const int64_t r = (int64_t)beta * 64 + lane;
-    Yt[r * ld + i] = r < k ? (tsum - 2.0 * acc[0]) * inv_sqrt_k : 0.0;
+    for (int b = 0; b < 4; ++b)
+        out[b] = ((a0 >> (8 * b)) & 0xffu) | (((a1 >> (8 * b)) & 0xffu) << 8) |
+                 (((a2 >> (8 * b)) & 0xffu) << 16) | (((a3 >> (8 * b)) & 0xffu) << 24);
 }
 
-// masked_add8 for two sums with the same signs: one lane mask per column
-// serves acc_a (+= wa) and acc_b (+= wb).
-__device__ __forceinline__ void masked_add8x2(uint32_t &h, double wa, double wb, double &a0,
-                                              double &a1, double &a2, double &a3, double &a4,
-                                              double &a5, double &a6, double &a7, double &b0,
-                                              double &b1, double &b2, double &b3, double &b4,
-                                              double &b5, double &b6, double &b7) {
-    uint64_t sv, m0, m1, m2, m3, m4, m5, m6, m7;
-    asm volatile(
-        "s_mov_b64 %[sv], exec\n\t"
-        "v_add_co_u32 %[h], %[m0], %[h], %[h]\n\t"
-        "v_add_co_u32 %[h], %[m1], %[h], %[h]\n\t"
-        "v_add_co_u32 %[h], %[m2], %[h], %[h]\n\t"
-        "v_add_co_u32 %[h], %[m3], %[h], %[h]\n\t"
-        "v_add_co_u32 %[h], %[m4], %[h], %[h]\n\t"
-        "v_add_co_u32 %[h], %[m5], %[h], %[h]\n\t"
-        "v_add_co_u32 %[h], %[m6], %[h], %[h]\n\t"
-        "v_add_co_u32 %[h], %[m7], %[h], %[h]\n\t"
-        "s_and_b64 exec, %[sv], %[m0]\n\t"
-        "v_add_f64 %[a0], %[a0], %[wa]\n\t"
-        "v_add_f64 %[b0], %[b0], %[wb]\n\t"
-        "s_and_b64 exec, %[sv], %[m1]\n\t"
-        "v_add_f64 %[a1], %[a1], %[wa]\n\t"
-        "v_add_f64 %[b1], %[b1], %[wb]\n\t"
-        "s_and_b64 exec, %[sv], %[m2]\n\t"
-        "v_add_f64 %[a2], %[a2], %[wa]\n\t"
-        "v_add_f64 %[b2], %[b2], %[wb]\n\t"
-        "s_and_b64 exec, %[sv], %[m3]\n\t"
-        "v_add_f64 %[a3], %[a3], %[wa]\n\t"
-        "v_add_f64 %[b3], %[b3], %[wb]\n\t"
-        "s_and_b64 exec, %[sv], %[m4]\n\t"
-        "v_add_f64 %[a4], %[a4], %[wa]\n\t"
-        "v_add_f64 %[b4], %[b4], %[wb]\n\t"
-        "s_and_b64 exec, %[sv], %[m5]\n\t"
-        "v_add_f64 %[a5], %[a5], %[wa]\n\t"
-        "v_add_f64 %[b5], %[b5], %[wb]\n\t"
-        "s_and_b64 exec, %[sv], %[m6]\n\t"
-        "v_add_f64 %[a6], %[a6], %[wa]\n\t"
-        "v_add_f64 %[b6], %[b6], %[wb]\n\t"
-        "s_and_b64 exec, %[sv], %[m7]\n\t"
-        "v_add_f64 %[a7], %[a7], %[wa]\n\t"
-        "v_add_f64 %[b7], %[b7], %[wb]\n\t"
-        "s_mov_b64 exec, %[sv]"
-        : [h] "+v"(h), [a0] "+v"(a0), [a1] "+v"(a1), [a2] "+v"(a2), [a3] "+v"(a3),
-          [a4] "+v"(a4), [a5] "+v"(a5), [a6] "+v"(a6), [a7] "+v"(a7), [b0] "+v"(b0),
-          [b1] "+v"(b1), [b2] "+v"(b2), [b3] "+v"(b3), [b4] "+v"(b4), [b5] "+v"(b5),
-          [b6] "+v"(b6), [b7] "+v"(b7), [sv] "=&s"(sv), [m0] "=&s"(m0), [m1] "=&s"(m1),
-          [m2] "=&s"(m2), [m3] "=&s"(m3), [m4] "=&s"(m4), [m5] "=&s"(m5), [m6] "=&s"(m6),
-          [m7] "=&s"(m7)
-        : [wa] "v"(wa), [wb] "v"(wb)
-        : "scc");
+// 2^e for -1022 <= e <= 1023.
+__device__ __forceinline__ double rhs_pow2(int e) { return __hiloint2double((e + 1023) << 20, 0); }
+
+// Scale exponent of a chunk whose largest |v| has high word h: 2^q |v| < 2^54.
+__device__ __forceinline__ int rhs_qexp(uint32_t h) {
+    const int q = 1076 - (int)(h >> 20);
+    return q < -1000 ? -1000 : (q > 1000 ? 1000 : q);
 }
 
-// Rows of Y for two snapshots on one node set (the same global ids, so the
-// same sign words on every edge): Y0 from W0 and Y1 from W1 in one sweep,
-// each word and each lane mask serving both.  A workgroup is one row and 16
-// waves: projection block beta = 4 g + wave / 4 (g the block group), the
-// wave's quarter of it the 16 columns [64 beta + 16 c, 64 beta + 16 c + 16),
-// so that 32 accumulators per lane leave room for four waves per SIMD.
-// Neighbours come in chunks of 512; every thread stages two sign words and
-// one signed square root of the chunk (the stage is the same work for every
-// wave, so the one barrier per chunk finds them together), into one of two
-// LDS buffers, and issues the next chunk's loads before summing this one.
-__global__ __launch_bounds__(1024) void k_rhs_pair(const double *W0, const double *W1, int64_t ld,
-                                                   int64_t n, const int32_t *gid, int64_t k,
-                                                   uint64_t mseed, double inv_sqrt_k, int nb,
-                                                   double *Y0t, double *Y1t) {
-    constexpr int C = 512;
-    __shared__ uint64_t sh[2][4][C];
-    __shared__ double sw[2][2][C];
+template <int NB, int S>
+__global__ __launch_bounds__(256 * NB) void k_rhs(const double *W0, const double *W1, int64_t ld,
+                                                  int64_t n, int64_t row0, int64_t row1,
+                                                  const int32_t *gid, int64_t k, uint64_t mseed,
+                                                  double inv_sqrt_k, int nb, double *Y0t,
+                                                  double *Y1t) {
+    constexpr int NT = 256 * NB;
+    constexpr int DG = (S * 256 + NT - 1) / NT;       // digit groups per thread
+    constexpr int PL = 2 * NB * 8 * kRhsPitch;         // bit planes, two buffers
+    constexpr int DB = 2 * 16 * kRhsPitch;             // digit rows, two buffers
+    static_assert(NB * 4 * S * 64 * 8 <= PL, "reduction buffer must fit the planes");
+    __shared__ __align__(16) unsigned char smem[PL + DB];
+    __shared__ uint32_t wmax[2][S * 4];
+    __shared__ double tred[S][4];
+    unsigned char *const planes = smem, *const digs = smem + PL;
+
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const int bq = wv >> 2, quarter = wv & 3;
-    const int nbg = (nb + 3) / 4;
+    const int nbg = (nb + NB - 1) / NB;
+    // The projection groups of one row take ids kNumXcd apart (one XCD).
     const int w = blockIdx.x, per = kNumXcd * nbg, l = w % per;
-    const int64_t i = (int64_t)(w / per) * kNumXcd + l % kNumXcd;
+    const int64_t i = row0 + (int64_t)(w / per) * kNumXcd + l % kNumXcd;
     const int bgrp = l / kNumXcd;
-    const bool row_ok = i < n, active = row_ok && bgrp * 4 + bq < nb;
-    const uint32_t gi = !row_ok ? 0u : (gid ? (uint32_t)gid[i] : (uint32_t)i);
-    // stage roles: neighbour jj = t % C; the words of blocks 4 g + 2 s and
-    // 4 g + 2 s + 1, and the root of snapshot s, s = t / C
-    const int jj = t & (C - 1), sr = t / C;
-    const uint64_t kb0 = (uint64_t)(bgrp * 4 + 2 * sr) << 40, kb1 = kb0 + (1ull << 40);
-    const double *wrow = (sr == 0 ? W0 : W1) + (row_ok ? i : 0) * ld;
-    double acc0[16], acc1[16];
+    if (i >= row1) return;
+    const uint32_t gi = gid ? (uint32_t)gid[i] : (uint32_t)i;
+    const int64_t wrow = (i - row0) * ld;
+
+    // roles
+    const int q = t & 255, bw = t >> 8;                        // sign words
+    const bool word_on = bgrp * NB + bw < nb;
+    const uint64_t kbeta = (uint64_t)(bgrp * NB + bw) << 40;
+    const int mb = wv >> 2, kq = wv & 3, m16 = lane & 15, g4 = lane >> 4;   // MFMAs
+    const bool mfma_on = bgrp * NB + mb < nb;
+    const int sn = S == 2 ? (m16 >> 3) : 0;                     // snapshot of this lane's slot
+    uint32_t mask[4];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) acc0[q] = acc1[q] = 0.0;
-    double t0 = 0.0, t1 = 0.0;
-    auto load = [&](int64_t j0, uint32_t &g, double &v) {
-        const int64_t j = j0 + jj;
-        g = 0u;
-        v = 0.0;
-        if (row_ok && j < n) {
-            g = gid ? (uint32_t)gid[j] : (uint32_t)j;
-            v = wrow[j];
+    for (int c = 0; c < 4; ++c) mask[c] = 0x01010101u << (4 * (m16 & 1) + c);
+
+    // zero the digit rows once (the unused slots stay zero)
+    for (int o = t * 16; o < DB; o += NT * 16) *(uint4 *)(digs + o) = make_uint4(0, 0, 0, 0);
+
+    uint32_t gn[4];            // global ids of the next chunk's neighbours
+    double vn[DG][4];          // its signed square roots
+    double tp[DG];             // running sums of v
+#pragma unroll
+    for (int d = 0; d < DG; ++d) tp[d] = 0.0;
+
+    auto load_ids = [&](int64_t j0) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t j = j0 + q + 256 * e;
+            gn[e] = j < n ? (gid ? (uint32_t)gid[j] : (uint32_t)j) : 0u;
         }
     };
-    auto word = [&](uint64_t key) -> uint64_t {
-        uint64_t z = mseed ^ key;
-        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
-        z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
-        return z ^ (z >> 31);
-    };
-    uint32_t gj;
-    double wv0;
-    load(0, gj, wv0);
-    int buf = 0;
-    for (int64_t j0 = 0; j0 < n; j0 += C, buf ^= 1) {
-        {   // stage this chunk: zero beyond n (no contribution whatever the sign)
-            const uint32_t lo = gi < gj ? gi : gj, hi = gi < gj ? gj : gi;
-            const uint64_t key = ((uint64_t)lo << 20) | (uint64_t)hi;
-            sh[buf][2 * sr][jj] = word(kb0 | key);
-            sh[buf][2 * sr + 1][jj] = word(kb1 | key);
-            const double r = sqrt(wv0);   // correctly rounded
-            sw[buf][sr][jj] = gi > gj ? -r : r;
+    auto load_w = [&](int64_t j0) {
+#pragma unroll
+        for (int d = 0; d < DG; ++d) {
+            const int gx = t + d * NT;
+            if (gx >= S * 256) continue;
+            const double *Ws = (S == 2 && (gx >> 8)) ? W1 : W0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t j = j0 + q + 256 * e;
+                vn[d][e] = j < n ? Ws[wrow + j] : 0.0;
+            }
         }
-        load(j0 + C, gj, wv0);   // in flight while this chunk is summed
+    };
+    // square roots (correctly rounded), signs, running sums and the chunk
+    // maxima of the loaded weights, into slot `slot`
+    auto roots = [&](int slot) {
+#pragma unroll
+        for (int d = 0; d < DG; ++d) {
+            const int gx = t + d * NT;
+            if (gx >= S * 256) continue;
+            uint32_t h = 0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const double r = sqrt(vn[d][e]);
+                vn[d][e] = gi > gn[e] ? -r : r;
+                tp[d] += vn[d][e];
+                const uint32_t hv = (uint32_t)__double2hiint(r) & 0x7fffffffu;
+                h = h > hv ? h : hv;
+            }
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) {
+                const uint32_t x = (uint32_t)__shfl_xor((int)h, o);
+                h = h > x ? h : x;
+            }
+            if (lane == 0) wmax[slot][gx >> 6] = h;
+        }
+    };
+
+    i32x4 acc[4];
+    double acc64[4][4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        acc[c] = i32x4{0, 0, 0, 0};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc64[c][r] = 0.0;
+    }
+    // the MFMAs of the chunk in buffer pb and their FP64 scaling (qx: the
+    // chunk's scale exponent for this lane's snapshot)
+    auto multiply = [&](int pb, int qx) {
+        if (!mfma_on) return;
+        const unsigned char *pa = planes + ((pb * NB + mb) * 8 + (m16 >> 1)) * kRhsPitch + 16 * g4;
+        const unsigned char *pd = digs + (pb * 16 + m16) * kRhsPitch + 16 * g4;
+#pragma unroll
+        for (int kk = 0; kk < kRhsChunk / 256; ++kk) {
+            const int off = (kk * 4 + kq) * 64;
+            const uint4 a = *(const uint4 *)(pa + off);
+            const i32x4 b = *(const i32x4 *)(pd + off);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const i32x4 ac = i32x4{(int)(a.x & mask[c]), (int)(a.y & mask[c]),
+                                       (int)(a.z & mask[c]), (int)(a.w & mask[c])};
+                acc[c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ac, b, acc[c], 0, 0, 0);
+            }
+        }
+        const int sl = m16 & 7;
+        const double f = sl < 7 ? rhs_pow2(8 * sl - qx) : 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc64[c][r] = fma((double)acc[c][r], f, acc64[c][r]);
+            acc[c] = i32x4{0, 0, 0, 0};
+        }
+    };
+
+    const int64_t nch = cdiv(n, kRhsChunk);
+    load_ids(0);
+    load_w(0);
+    roots(0);
+    __syncthreads();
+    int qprev = 0;
+    for (int64_t ch = 0; ch < nch; ++ch) {
+        const int buf = (int)(ch & 1), slot = buf;
+        int qs[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            uint32_t h = wmax[slot][4 * s];
+#pragma unroll
+            for (int u = 1; u < 4; ++u) h = h > wmax[slot][4 * s + u] ? h : wmax[slot][4 * s + u];
+            qs[s] = rhs_qexp(h);
+        }
+        // digits of this chunk
+#pragma unroll
+        for (int d = 0; d < DG; ++d) {
+            const int gx = t + d * NT;
+            if (gx >= S * 256) continue;
+            const int s = gx >> 8;
+            const double Q = rhs_pow2(S == 2 && s ? qs[S - 1] : qs[0]);
+            uint32_t lo[4], hi[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                // (clamped, so that non-finite weights convert without
+                // overflow; T carries them)
+                const double x = fmin(fmax(rint(vn[d][e] * Q), -0x1p54), 0x1p54);
+                const double xh = floor(x * 0x1p-32);
+                const double xl = fma(xh, -0x1p32, x);
+                const uint64_t u = (((uint64_t)(uint32_t)(int)xh << 32) | (uint32_t)xl) +
+                                   0x80808080808080ull;
+                lo[e] = (uint32_t)u ^ 0x80808080u;
+                hi[e] = (uint32_t)(u >> 32) ^ 0x808080u;
+            }
+            uint32_t o[4];
+            unsigned char *pd = digs + (buf * 16 + 8 * s) * kRhsPitch + 4 * q;
+            rhs_bytes4(lo[0], lo[1], lo[2], lo[3], o);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) *(uint32_t *)(pd + b * kRhsPitch) = o[b];
+            rhs_bytes4(hi[0], hi[1], hi[2], hi[3], o);
+#pragma unroll
+            for (int b = 0; b < 3; ++b) *(uint32_t *)(pd + (4 + b) * kRhsPitch) = o[b];
+        }
+        // sign words of this chunk
+        if (word_on) {
+            uint32_t lo[4], hi[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t a = gi < gn[e] ? gi : gn[e], b = gi < gn[e] ? gn[e] : gi;
+                const uint64_t wd = rhs_sign_word(mseed, kbeta | ((uint64_t)a << 20) | b);
+                lo[e] = (uint32_t)wd;
+                hi[e] = (uint32_t)(wd >> 32);
+            }
+            uint32_t o[4];
+            unsigned char *pp = planes + (buf * NB + bw) * 8 * kRhsPitch + 4 * q;
+            rhs_bytes4(lo[0], lo[1], lo[2], lo[3], o);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) *(uint32_t *)(pp + b * kRhsPitch) = o[b];
+            rhs_bytes4(hi[0], hi[1], hi[2], hi[3], o);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) *(uint32_t *)(pp + (4 + b) * kRhsPitch) = o[b];
+        }
+        const bool more = ch + 1 < nch;
+        if (more) {
+            load_ids((ch + 1) * kRhsChunk);
+            load_w((ch + 1) * kRhsChunk);
+        }
+        if (ch > 0) multiply(buf ^ 1, qprev);
+        qprev = S == 2 && sn ? qs[S - 1] : qs[0];
+        if (more) roots(slot ^ 1);
         __syncthreads();
-        if (active) {
-#pragma unroll 2
-            for (int sub = 0; sub < C / 64; ++sub) {
-                const int q = sub * 64 + lane;
-                const uint64_t hw = sh[buf][bq][q];
-                const double a = sw[buf][0][q], b = sw[buf][1][q];
-                // the quarter's 16 bits, most significant first
-                uint32_t h = (uint32_t)(hw >> (16 * quarter)) << 16;
-                t0 += a;
-                t1 += b;
-                masked_add8x2(h, a, b, acc0[15], acc0[14], acc0[13], acc0[12], acc0[11], acc0[10],
-                              acc0[9], acc0[8], acc1[15], acc1[14], acc1[13], acc1[12], acc1[11],
-                              acc1[10], acc1[9], acc1[8]);
-                masked_add8x2(h, a, b, acc0[7], acc0[6], acc0[5], acc0[4], acc0[3], acc0[2],
-                              acc0[1], acc0[0], acc1[7], acc1[6], acc1[5], acc1[4], acc1[3],
-                              acc1[2], acc1[1], acc1[0]);
+    }
+    multiply((int)((nch - 1) & 1), qprev);
+    __syncthreads();   // the planes now hold the reduction buffer
+
+    // sum each snapshot's seven digit slots (lanes m16 & 7 = 0..6) and undo
+    // the bit scale 2^p, p = 4 (row & 1) + c for accumulator row 4 g4 + r
+    double *red = (double *)smem;   // [NB][4][S][64]
+    if (mfma_on) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                double x = acc64[c][r];
+                x += __shfl_xor(x, 1);
+                x += __shfl_xor(x, 2);
+                x += __shfl_xor(x, 4);
+                const int p = 4 * (r & 1) + c;
+                const double inv = p == 7 ? -0x1p-7 : rhs_pow2(-p);
+                if ((m16 & 7) == 0 && (m16 >> 3) < S)
+                    red[((mb * 4 + kq) * S + sn) * 64 + 16 * g4 + 4 * r + c] = x * inv;
             }
         }
     }
-    if (!active) return;
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-        t0 += __shfl_xor(t0, o);
-        t1 += __shfl_xor(t1, o);
+    for (int d = 0; d < DG; ++d) {
+        const int gx = t + d * NT;
+        if (gx >= S * 256) continue;
+        double x = tp[d];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o);
+        if (lane == 0) tred[gx >> 8][(gx >> 6) & 3] = x;
     }
-    // Butterfly transpose-reduction over each 16-lane group, then across the
-    // groups: lane l ends with column l % 16 summed over all 64 lanes.
-#pragma unroll
-    for (int s = 8; s >= 1; s >>= 1) {
-        const bool up = (lane & s) != 0;
-#pragma unroll
-        for (int q2 = 0; q2 < s; ++q2) {
-            const double s0 = up ? acc0[q2] : acc0[q2 + s], k0 = up ? acc0[q2 + s] : acc0[q2];
-            const double s1 = up ? acc1[q2] : acc1[q2 + s], k1 = up ? acc1[q2 + s] : acc1[q2];
-            acc0[q2] = k0 + __shfl_xor(s0, s);
-            acc1[q2] = k1 + __shfl_xor(s1, s);
+    __syncthreads();
+    if (t < NB * S * 64) {
+        const int b = t / (S * 64), s = (t / 64) % S, r = t & 63;
+        const int beta = bgrp * NB + b;
+        if (beta < nb) {
+            const double *rb = red + (b * 4 * S + s) * 64 + r;
+            const double M = ((rb[0] + rb[S * 64]) + rb[2 * S * 64]) + rb[3 * S * 64];
+            const double T = ((tred[s][0] + tred[s][1]) + tred[s][2]) + tred[s][3];
+            const int64_t col = (int64_t)beta * 64 + r;
+            double *Y = s == 0 ? Y0t : Y1t;
+            Y[col * ld + i] = col < k ? (T - 2.0 * M) * inv_sqrt_k : 0.0;
         }
     }
-    acc0[0] += __shfl_xor(acc0[0], 16);
-    acc1[0] += __shfl_xor(acc1[0], 16);
-    acc0[0] += __shfl_xor(acc0[0], 32);
-    acc1[0] += __shfl_xor(acc1[0], 32);
-    if (lane < 16) {
-        const int64_t r = (int64_t)(bgrp * 4 + bq) * 64 + quarter * 16 + lane;
-        Y0t[r * ld + i] = r < k ? (t0 - 2.0 * acc0[0]) * inv_sqrt_k : 0.0;
-        Y1t[r * ld + i] = r < k ? (t1 - 2.0 * acc1[0]) * inv_sqrt_k : 0.0;
+}
+
+template <int S>
+static hipError_t launch_rhs_k(const double *W0, const double *W1, int64_t ld, int64_t n,
+                               int64_t row0, int64_t row1, const int32_t *gid, int64_t k,
+                               int64_t kpad, uint64_t seed, double *Y0t, double *Y1t,
+                               hipStream_t s) {
+    if (row0 < 0 || row1 > n) return hipErrorInvalidValue;
+    if (row1 <= row0) return hipSuccess;
+    const uint64_t mseed = splitmix64_mix_host(seed);
+    const int nb = (int)(kpad / 64);
+    const int NB = nb >= 3 ? 4 : nb;
+    const int nbg = (nb + NB - 1) / NB;
+    const int64_t rows = cdiv(row1 - row0, kNumXcd) * kNumXcd;
+    const dim3 grid((unsigned)(rows * nbg));
+    const double isk = 1.0 / sqrt((double)k);
+    switch (NB) {
+    case 4: hipLaunchKernelGGL((k_rhs<4, S>), grid, dim3(1024), 0, s, W0, W1, ld, n, row0, row1, gid, k, mseed, isk, nb, Y0t, Y1t); break;
+    case 2: hipLaunchKernelGGL((k_rhs<2, S>), grid, dim3(512), 0, s, W0, W1, ld, n, row0, row1, gid, k, mseed, isk, nb, Y0t, Y1t); break;
+    default: hipLaunchKernelGGL((k_rhs<1, S>), grid, dim3(256), 0, s, W0, W1, ld, n, row0, row1, gid, k, mseed, isk, nb, Y0t, Y1t); break;
     }
+    return hipGetLastError();
 }
 
 hipError_t launch_rhs_pair(const double *W0, const double *W1, int64_t ld, int64_t n,
                            const int32_t *gid, int64_t k, int64_t kpad, uint64_t seed,
                            double *Y0t, double *Y1t, hipStream_t s) {
-    const uint64_t mseed = splitmix64_mix_host(seed);
-    const int nb = (int)(kpad / 64);
-    const int nbg = (nb + 3) / 4;
-    const int64_t rows = cdiv(n, kNumXcd) * kNumXcd;
-    hipLaunchKernelGGL(k_rhs_pair, dim3((unsigned)(rows * nbg)), dim3(1024), 0, s, W0, W1, ld, n,
-                       gid, k, mseed, 1.0 / sqrt((double)k), nb, Y0t, Y1t);
-    return hipGetLastError();
+    return launch_rhs_k<2>(W0, W1, ld, n, 0, n, gid, k, kpad, seed, Y0t, Y1t, s);
 }
 
 hipError_t launch_rhs_rows(const double *W, int64_t ld, int64_t n, int64_t row0, int64_t row1,
                            const int32_t *gid, int64_t k, int64_t kpad, uint64_t seed,
                            double *Yt, hipStream_t s) {
-    if (row0 < 0 || row1 > n) return hipErrorInvalidValue;
-    if (row1 <= row0) return hipSuccess;
-    const uint64_t mseed = splitmix64_mix_host(seed);
-    const int nb = (int)(kpad / 64);
-    const int P = nb >= 4 ? 4 : (nb >= 2 ? 2 : 1);
-    const int nbg = (nb + P - 1) / P;
-    const int64_t groups = cdiv(cdiv(row1 - row0, 4 / P), kNumXcd) * kNumXcd;
-    const dim3 grid((unsigned)(groups * nbg)), blk(256);
-    const double isk = 1.0 / sqrt((double)k);
-    switch (P) {
-    case 4: hipLaunchKernelGGL(k_rhs<4>, grid, blk, 0, s, W, ld, n, row0, row1, gid, k, mseed, isk, nb, Yt); break;
-    case 2: hipLaunchKernelGGL(k_rhs<2>, grid, blk, 0, s, W, ld, n, row0, row1, gid, k, mseed, isk, nb, Yt); break;
-    default: hipLaunchKernelGGL(k_rhs<1>, grid, blk, 0, s, W, ld, n, row0, row1, gid, k, mseed, isk, nb, Yt); break;
-    }
-    return hipGetLastError();
+    return launch_rhs_k<1>(W, nullptr, ld, n, row0, row1, gid, k, kpad, seed, Yt, nullptr, s);
 }
 
 hipError_t launch_rhs(const double *W, int64_t ld, int64_t n, const int32_t *gid, int64_t k,

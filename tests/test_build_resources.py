@@ -12,7 +12,7 @@ import pytest
 
 from paper_1802_05421_amd import _build
 
-HOT = ("k_square", "k_apply_gemm", "k_score", "k_residual_gemm", "k_gram_dist", "k_rhs_pair",
+HOT = ("k_square", "k_apply_gemm", "k_score", "k_residual_gemm", "k_gram_dist", "k_rhs",
        "k_exp_sym", "k_normalize")
 
 
