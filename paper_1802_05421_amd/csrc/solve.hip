@@ -46,8 +46,8 @@ namespace cdl {
 //   * one MFMA multiplies 16 columns by 16 digit slots (seven digits of each
 //     snapshot and a zero slot) over 64 neighbours; the int32 sums are
 //     exact (|sum| <= 2^22 per chunk and wave) and are scaled into FP64
-//     accumulators after every chunk (times 256^s 2^-e / 2^p, all powers of
-//     two).
+//     accumulators (times 256^s 2^-e / 2^p, all powers of two) whenever e
+//     changes and every 256 chunks.
 // So the only rounding is V = rint(2^e v) (at most 2^-55 of the chunk's
 // largest |v| per term) and the FP64 sums; T is summed in FP64 from v itself,
 // which also carries non-finite weights into y.
@@ -81,13 +81,19 @@ __device__ __forceinline__ uint64_t rhs_sign_word(uint64_t mseed, uint64_t key) 
     return z ^ (z >> 31);
 }
 
-// out[b] = byte b of a0, a1, a2, a3 (in that order from the low byte).
+// out[b] = byte b of a0, a1, a2, a3 (in that order from the low byte): a
+// 4 x 4 byte transpose in eight v_perm_b32 (perm(x, y, s) takes result byte
+// t from byte s_t of the 64-bit value x:y, y in the low half).
 __device__ __forceinline__ void rhs_bytes4(uint32_t a0, uint32_t a1, uint32_t a2, uint32_t a3,
                                            uint32_t out[4]) {
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-        out[b] = ((a0 >> (8 * b)) & 0xffu) | (((a1 >> (8 * b)) & 0xffu) << 8) |
-                 (((a2 >> (8 * b)) & 0xffu) << 16) | (((a3 >> (8 * b)) & 0xffu) << 24);
+    const uint32_t l01 = __builtin_amdgcn_perm(a1, a0, 0x05010400u);   // a0.0 a1.0 a0.1 a1.1
+    const uint32_t l23 = __builtin_amdgcn_perm(a3, a2, 0x05010400u);
+    const uint32_t h01 = __builtin_amdgcn_perm(a1, a0, 0x07030602u);   // a0.2 a1.2 a0.3 a1.3
+    const uint32_t h23 = __builtin_amdgcn_perm(a3, a2, 0x07030602u);
+    out[0] = __builtin_amdgcn_perm(l23, l01, 0x05040100u);
+    out[1] = __builtin_amdgcn_perm(l23, l01, 0x07060302u);
+    out[2] = __builtin_amdgcn_perm(h23, h01, 0x05040100u);
+    out[3] = __builtin_amdgcn_perm(h23, h01, 0x07060302u);
 }
 
 // 2^e for -1022 <= e <= 1023.
@@ -145,11 +151,13 @@ __global__ __launch_bounds__(256 * NB) void k_rhs(const double *W0, const double
 #pragma unroll
     for (int d = 0; d < DG; ++d) tp[d] = 0.0;
 
+    // (indices clamped into the row, so that the loads need no branches)
     auto load_ids = [&](int64_t j0) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const int64_t j = j0 + q + 256 * e;
-            gn[e] = j < n ? (gid ? (uint32_t)gid[j] : (uint32_t)j) : 0u;
+            const int64_t j = j0 + q + 256 * e, jc = j < n ? j : n - 1;
+            const uint32_t g = gid ? (uint32_t)gid[jc] : (uint32_t)jc;
+            gn[e] = j < n ? g : 0u;
         }
     };
     auto load_w = [&](int64_t j0) {
@@ -160,8 +168,9 @@ __global__ __launch_bounds__(256 * NB) void k_rhs(const double *W0, const double
             const double *Ws = (S == 2 && (gx >> 8)) ? W1 : W0;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int64_t j = j0 + q + 256 * e;
-                vn[d][e] = j < n ? Ws[wrow + j] : 0.0;
+                const int64_t j = j0 + q + 256 * e, jc = j < n ? j : n - 1;
+                const double x = Ws[wrow + jc];
+                vn[d][e] = j < n ? x : 0.0;
             }
         }
     };
@@ -198,10 +207,32 @@ __global__ __launch_bounds__(256 * NB) void k_rhs(const double *W0, const double
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc64[c][r] = 0.0;
     }
-    // the MFMAs of the chunk in buffer pb and their FP64 scaling (qx: the
-    // chunk's scale exponent for this lane's snapshot)
+    // The integer sums are scaled into FP64 when the scale exponent of this
+    // lane's snapshot changes (in any lane of the wave) and every 256 chunks
+    // (|sum| < 2^30).
+    int qacc = 0, held = 0;
+    auto flush = [&]() {
+        const int sl = m16 & 7;
+        const double f = sl < 7 ? rhs_pow2(8 * sl - qacc) : 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc64[c][r] = fma((double)acc[c][r], f, acc64[c][r]);
+            acc[c] = i32x4{0, 0, 0, 0};
+        }
+        held = 0;
+    };
+    // the MFMAs of the chunk in buffer pb (qx: its scale exponent for this
+    // lane's snapshot)
     auto multiply = [&](int pb, int qx) {
         if (!mfma_on) return;
+        if (held == 0) {
+            qacc = qx;
+        } else if (__any(qx != qacc) || held == 256) {
+            flush();
+            qacc = qx;
+        }
+        ++held;
         const unsigned char *pa = planes + ((pb * NB + mb) * 8 + (m16 >> 1)) * kRhsPitch + 16 * g4;
         const unsigned char *pd = digs + (pb * 16 + m16) * kRhsPitch + 16 * g4;
 #pragma unroll
@@ -215,14 +246,6 @@ __global__ __launch_bounds__(256 * NB) void k_rhs(const double *W0, const double
                                        (int)(a.z & mask[c]), (int)(a.w & mask[c])};
                 acc[c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ac, b, acc[c], 0, 0, 0);
             }
-        }
-        const int sl = m16 & 7;
-        const double f = sl < 7 ? rhs_pow2(8 * sl - qx) : 0.0;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) acc64[c][r] = fma((double)acc[c][r], f, acc64[c][r]);
-            acc[c] = i32x4{0, 0, 0, 0};
         }
     };
 
@@ -301,6 +324,7 @@ __global__ __launch_bounds__(256 * NB) void k_rhs(const double *W0, const double
         __syncthreads();
     }
     multiply((int)((nch - 1) & 1), qprev);
+    if (mfma_on) flush();
     __syncthreads();   // the planes now hold the reduction buffer
 
     // sum each snapshot's seven digit slots (lanes m16 & 7 = 0..6) and undo
