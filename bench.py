@@ -30,7 +30,8 @@ sys.path.insert(0, ROOT)
 METRIC = "graph pairs scored/s at n=16384, mixed vs FP32 at 1e-6 rel err; MFMA % peak"
 PEAK = {  # MI355X published peaks
     "fp64_mfma": 78.6e12, "fp32_mfma": 157.3e12, "bf16_mfma": 2.5e15,
-    "fp64_valu_add": 256 * 4 * 16 * 2.4e9,   # 39.3e12 FP64 adds/s
+    # quarter-rate 32-bit integer multiplies: 16 lanes per SIMD every 4 cycles
+    "int32_mul": 256 * 4 * 16 / 4 * 2.4e9,   # 9.83e12 per second
     "hbm": 8.0e12,
 }
 
@@ -52,10 +53,13 @@ def kernel_model(name, n, k, T, prec):
         return "mfma", 2.0 * n * n * k, "TFLOP/s", PEAK["fp64_mfma"]      # half of n x n x 2k
     if name == "gram_dist":
         return "mfma", float(n) * n * T, "TFLOP/s", PEAK["fp64_mfma"]      # half of n x n x T
-    if name == "rhs":
-        return "alu", float(n) * (n - 1) * k, "TFLOP/s", PEAK["fp64_valu_add"]
-    if name == "rhs_pair":   # both snapshots of the pair
-        return "alu", 2.0 * n * (n - 1) * k, "TFLOP/s", PEAK["fp64_valu_add"]
+    if name in ("rhs", "rhs_pair"):
+        # The signed sums run on the int8 matrix cores; what bounds the kernel
+        # is the VALU's SplitMix64 sign words (one per row, neighbour and 64
+        # projections; the pair's two snapshots share them), whose two 64-bit
+        # products take three quarter-rate 32-bit multiplies each.
+        words = float(n) * n * ((k + 63) // 64)
+        return "alu", 6.0 * words, "Tops/s", PEAK["int32_mul"]
     if name == "apply":
         return "hbm", float(n) * n * esz, "GB/s", PEAK["hbm"]
     if name == "exp_degree":
@@ -112,7 +116,7 @@ def roofline(times, name, n, k, T, prec, traffic=None):
     cnt, ms = times[name]
     avg_s = ms / cnt / 1e3
     bound, amount, unit, peak = m
-    scale = 1e12 if unit == "TFLOP/s" else 1e9
+    scale = 1e12 if unit in ("TFLOP/s", "Tops/s") else 1e9
     achieved = amount / avg_s
     return {"kernel": name, "bound": bound, "achieved": round(achieved / scale, 3),
             "peak": round(peak / scale, 3), "unit": unit, "frac": round(achieved / peak, 4),
