@@ -139,6 +139,126 @@ def load_traffic(kernel):
     return rec["bytes_per_launch"] if sha == rec["source_sha"] else None
 
 
+def sequence_section(args, cdl, gen, torch, dev, seed, DMAX):
+    """Batched uneven sequence: 24 snapshots, n_t ~ U{1024..8192} on a 96 x 96
+    grid, k = 128, 23 consecutive-pair scores over the common global ids:
+    synchronous, two streams with no host reads, a graph replay and the one-pass
+    grouped form."""
+    seqin = gen.make_sequence(G=96, T=120, n_snap=24, stride=30, n_min=1024, n_max=8192,
+                              onsets=(8, 16))
+    Xs = [torch.from_numpy(x).to(dev) for x in seqin.X]
+    gids = [torch.from_numpy(g) for g in seqin.gid]
+    sp = cdl.SeqParams(k=128, seed=seed, prec=args.mixed, depth=0, depth_max=DMAX, tol=1e-8,
+                       max_iter=30, top_k=50)
+    Fs, tops, sinfo = cdl.score_sequence(Xs, gids, sp)        # warm-up (and workspace)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Fs, tops, sinfo = cdl.score_sequence(Xs, gids, sp)
+    torch.cuda.synchronize()
+    ms_seq = time.perf_counter() - t0
+    sequence = {"workload": "24 snapshots, n_t in [1024, 8192] (sum %d), T=120, k=128, %s chain, "
+                            "FP64 residual 1e-8" % (sum(len(g) for g in seqin.gid), args.mixed.upper()),
+                "ms_per_sequence": round(ms_seq * 1e3, 2), "pairs": sinfo.pairs,
+                "pairs_per_s": round(sinfo.pairs / ms_seq, 2),
+                "max_iterations": sinfo.max_iterations,
+                "max_rel_residual": sinfo.max_rel_residual}
+    log("sequence: %d pairs in %.1f ms" % (sinfo.pairs, ms_seq * 1e3))
+    # The same sequence enqueued with no host reads, consecutive snapshots
+    # on two streams, then also captured and replayed as a HIP graph:
+    # every chain at the largest depth the adaptive rule picks over the
+    # snapshots, every solve at the largest iteration count above (two
+    # more per retry); the library rejects the call if any final residual
+    # stays above 1e-8.
+    dfix = 1
+    for Xq in Xs:
+        gb = cdl.build_graph(Xq)
+        dfix = max(dfix, cdl.build_chain(gb, prec=args.mixed, depth=0, depth_max=DMAX).depth)
+        del gb
+    gdev = [g.to(dev) for g in gids]
+    iters, err, replay = sinfo.max_iterations, None, None
+    for attempt in range(3):
+        spa = cdl.SeqParams(k=128, seed=seed, prec=args.mixed, depth=dfix, tol=1e-8,
+                            max_iter=iters, top_k=50, asynchronous=True, graph=True)
+        spe = cdl.SeqParams(k=128, seed=seed, prec=args.mixed, depth=dfix, tol=1e-8,
+                            max_iter=iters, top_k=50, asynchronous=True)
+        try:
+            sws = torch.empty(cdl.sequence_workspace_bytes(Xs, gdev, spa), dtype=torch.uint8,
+                              device=dev)
+            Fa, ta, ainfo = cdl.score_sequence(Xs, gdev, spe, ws=sws, out=None)   # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                Fa, ta, ainfo = cdl.score_sequence(Xs, gdev, spe, ws=sws, out=(Fa, ta))
+            torch.cuda.synchronize()
+            ms_async = (time.perf_counter() - t0) / 3
+            sequence["async_two_streams"] = {
+                "ms_per_sequence": round(ms_async * 1e3, 2),
+                "pairs_per_s": round(ainfo.pairs / ms_async, 2), "chain_depth": dfix,
+                "iterations": iters, "max_rel_residual": ainfo.max_rel_residual}
+            log("sequence, two streams, no host reads: %.1f ms" % (ms_async * 1e3))
+            Fa, ta, ainfo = cdl.score_sequence(Xs, gdev, spa, ws=sws, out=(Fa, ta))   # eager enqueue
+            Fa, ta, ainfo = cdl.score_sequence(Xs, gdev, spa, ws=sws, out=(Fa, ta))   # capture
+            torch.cuda.synchronize()
+            reps = 3
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                Fa, ta, ainfo = cdl.score_sequence(Xs, gdev, spa, ws=sws, out=(Fa, ta))
+            torch.cuda.synchronize()
+            ms_graph = (time.perf_counter() - t0) / reps
+            replay = {"ms_per_sequence": round(ms_graph * 1e3, 2),
+                      "pairs_per_s": round(ainfo.pairs / ms_graph, 2),
+                      "chain_depth": dfix, "iterations": iters,
+                      "graph_launches": ainfo.graph_launches,
+                      "max_rel_residual": ainfo.max_rel_residual}
+            log("sequence as a graph replay: %.1f ms (depth %d, %d iterations)" % (ms_graph * 1e3, dfix, iters))
+            break
+        except cdl.CdlError as e:
+            err = str(e)
+            log("async sequence at depth %d, %d iterations: %s" % (dfix, iters, e))
+            iters += 2
+    sequence["graph_replay"] = replay if replay is not None else {"error": err}
+    sws = None
+    # One pass: every snapshot resident, grouped launches over all
+    # snapshots (squarings, each refinement step) and pairs (scores),
+    # convergence on the device (max_iter only bounds it).
+    pb = cdl.SeqParams(k=128, seed=seed, prec=args.mixed, depth=dfix, tol=1e-8, max_iter=20,
+                       top_k=50, asynchronous=True, batched=True)
+    wsb = torch.empty(cdl.sequence_workspace_bytes(Xs, gdev, pb), dtype=torch.uint8, device=dev)
+    Fb, tb, binfo = cdl.score_sequence(Xs, gdev, pb, ws=wsb)          # warm-up
+    torch.cuda.synchronize()
+    cdl.timing(reset=True)
+    cdl.set_timing(True)
+    Fb, tb, binfo = cdl.score_sequence(Xs, gdev, pb, ws=wsb, out=(Fb, tb))
+    torch.cuda.synchronize()
+    cdl.set_timing(False)
+    kb = {nm: round(v[1], 3) for nm, v in sorted(cdl.timing(reset=True).items(), key=lambda x: -x[1][1])}
+    t0 = time.perf_counter()
+    for _ in range(3):
+        Fb, tb, binfo = cdl.score_sequence(Xs, gdev, pb, ws=wsb, out=(Fb, tb))
+    torch.cuda.synchronize()
+    ms_b = (time.perf_counter() - t0) / 3
+    pbg = cdl.SeqParams(k=128, seed=seed, prec=args.mixed, depth=dfix, tol=1e-8, max_iter=20,
+                        top_k=50, asynchronous=True, batched=True, graph=True)
+    for _ in range(2):   # eager, then captured
+        Fb, tb, binfo = cdl.score_sequence(Xs, gdev, pbg, ws=wsb, out=(Fb, tb))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        Fb, tb, ginfo = cdl.score_sequence(Xs, gdev, pbg, ws=wsb, out=(Fb, tb))
+    torch.cuda.synchronize()
+    ms_bg = (time.perf_counter() - t0) / 3
+    same = all(set(a.tolist()) == set(b.tolist()) for a, b in zip(tb, tops))
+    sequence["batched_one_pass"] = {
+        "ms_per_sequence": round(ms_b * 1e3, 2), "pairs_per_s": round(binfo.pairs / ms_b, 2),
+        "graph_replay_ms": round(ms_bg * 1e3, 2), "graph_launches": ginfo.graph_launches,
+        "chain_depth": dfix, "iterations": binfo.max_iterations,
+        "max_rel_residual": binfo.max_rel_residual, "top50_equal_to_synchronous": bool(same),
+        "kernels_ms": kb}
+    log("sequence, one pass (grouped): %.1f ms, as a graph replay %.1f ms" % (ms_b * 1e3, ms_bg * 1e3))
+    wsb = None
+    return sequence
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -162,6 +282,8 @@ def main():
                     help="also time one streamed pair on a G x G grid (e.g. 512: n = 262144)")
     ap.add_argument("--stream-only", action="store_true",
                     help="run only the streamed section (prints its results as one JSON line)")
+    ap.add_argument("--sequence-only", action="store_true",
+                    help="run only the 24-snapshot sequence section (prints one JSON line)")
     ap.add_argument("--square-only", default="",
                     help="profiling runs: only two chain builds of depth 2 in this type (fp16/bf16/fp32) "
                          "on the first snapshot, one squaring each (prints one JSON line)")
@@ -209,6 +331,10 @@ def main():
         r = roofline(cdl.timing(reset=True), "square", n, k, T, args.square_only)
         print(json.dumps({"square_only": args.square_only, "variant": args.square_variant,
                           "roofline": r}), flush=True)
+        return
+    if args.sequence_only:   # the sequence section alone (for kernel traces)
+        print(json.dumps({"sequence_c4": sequence_section(args, cdl, gen, torch, dev, seed, 6)}),
+              flush=True)
         return
     if args.stream_only:   # the streamed section alone (for kernel traces)
         print(json.dumps({"streamed": streamed_section(args, cdl, gen, torch, dev, Xpair, n, T, k,
@@ -444,122 +570,7 @@ def main():
                  "prec": args.mixed}
     log("amortised sequence pair: %.2f ms" % (ms_amort * 1e3))
 
-    # Batched uneven sequence: 24 snapshots, n_t ~ U{1024..8192} on a 96 x 96
-    # grid, k = 128, 23 consecutive-pair scores over the common global ids.
-    sequence = None
-    if not args.no_sequence:
-        seqin = gen.make_sequence(G=96, T=120, n_snap=24, stride=30, n_min=1024, n_max=8192,
-                               onsets=(8, 16))
-        Xs = [torch.from_numpy(x).to(dev) for x in seqin.X]
-        gids = [torch.from_numpy(g) for g in seqin.gid]
-        sp = cdl.SeqParams(k=128, seed=seed, prec=args.mixed, depth=0, depth_max=DMAX, tol=1e-8,
-                           max_iter=30, top_k=50)
-        Fs, tops, sinfo = cdl.score_sequence(Xs, gids, sp)        # warm-up (and workspace)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        Fs, tops, sinfo = cdl.score_sequence(Xs, gids, sp)
-        torch.cuda.synchronize()
-        ms_seq = time.perf_counter() - t0
-        sequence = {"workload": "24 snapshots, n_t in [1024, 8192] (sum %d), T=120, k=128, %s chain, "
-                                "FP64 residual 1e-8" % (sum(len(g) for g in seqin.gid), args.mixed.upper()),
-                    "ms_per_sequence": round(ms_seq * 1e3, 2), "pairs": sinfo.pairs,
-                    "pairs_per_s": round(sinfo.pairs / ms_seq, 2),
-                    "max_iterations": sinfo.max_iterations,
-                    "max_rel_residual": sinfo.max_rel_residual}
-        log("sequence: %d pairs in %.1f ms" % (sinfo.pairs, ms_seq * 1e3))
-        # The same sequence enqueued with no host reads, consecutive snapshots
-        # on two streams, then also captured and replayed as a HIP graph:
-        # every chain at the largest depth the adaptive rule picks over the
-        # snapshots, every solve at the largest iteration count above (two
-        # more per retry); the library rejects the call if any final residual
-        # stays above 1e-8.
-        dfix = 1
-        for Xq in Xs:
-            gb = cdl.build_graph(Xq)
-            dfix = max(dfix, cdl.build_chain(gb, prec=args.mixed, depth=0, depth_max=DMAX).depth)
-            del gb
-        gdev = [g.to(dev) for g in gids]
-        iters, err, replay = sinfo.max_iterations, None, None
-        for attempt in range(3):
-            spa = cdl.SeqParams(k=128, seed=seed, prec=args.mixed, depth=dfix, tol=1e-8,
-                                max_iter=iters, top_k=50, asynchronous=True, graph=True)
-            spe = cdl.SeqParams(k=128, seed=seed, prec=args.mixed, depth=dfix, tol=1e-8,
-                                max_iter=iters, top_k=50, asynchronous=True)
-            try:
-                sws = torch.empty(cdl.sequence_workspace_bytes(Xs, gdev, spa), dtype=torch.uint8,
-                                  device=dev)
-                Fa, ta, ainfo = cdl.score_sequence(Xs, gdev, spe, ws=sws, out=None)   # warm-up
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                for _ in range(3):
-                    Fa, ta, ainfo = cdl.score_sequence(Xs, gdev, spe, ws=sws, out=(Fa, ta))
-                torch.cuda.synchronize()
-                ms_async = (time.perf_counter() - t0) / 3
-                sequence["async_two_streams"] = {
-                    "ms_per_sequence": round(ms_async * 1e3, 2),
-                    "pairs_per_s": round(ainfo.pairs / ms_async, 2), "chain_depth": dfix,
-                    "iterations": iters, "max_rel_residual": ainfo.max_rel_residual}
-                log("sequence, two streams, no host reads: %.1f ms" % (ms_async * 1e3))
-                Fa, ta, ainfo = cdl.score_sequence(Xs, gdev, spa, ws=sws, out=(Fa, ta))   # eager enqueue
-                Fa, ta, ainfo = cdl.score_sequence(Xs, gdev, spa, ws=sws, out=(Fa, ta))   # capture
-                torch.cuda.synchronize()
-                reps = 3
-                t0 = time.perf_counter()
-                for _ in range(reps):
-                    Fa, ta, ainfo = cdl.score_sequence(Xs, gdev, spa, ws=sws, out=(Fa, ta))
-                torch.cuda.synchronize()
-                ms_graph = (time.perf_counter() - t0) / reps
-                replay = {"ms_per_sequence": round(ms_graph * 1e3, 2),
-                          "pairs_per_s": round(ainfo.pairs / ms_graph, 2),
-                          "chain_depth": dfix, "iterations": iters,
-                          "graph_launches": ainfo.graph_launches,
-                          "max_rel_residual": ainfo.max_rel_residual}
-                log("sequence as a graph replay: %.1f ms (depth %d, %d iterations)" % (ms_graph * 1e3, dfix, iters))
-                break
-            except cdl.CdlError as e:
-                err = str(e)
-                log("async sequence at depth %d, %d iterations: %s" % (dfix, iters, e))
-                iters += 2
-        sequence["graph_replay"] = replay if replay is not None else {"error": err}
-        sws = None
-        # One pass: every snapshot resident, grouped launches over all
-        # snapshots (squarings, each refinement step) and pairs (scores),
-        # convergence on the device (max_iter only bounds it).
-        pb = cdl.SeqParams(k=128, seed=seed, prec=args.mixed, depth=dfix, tol=1e-8, max_iter=20,
-                           top_k=50, asynchronous=True, batched=True)
-        wsb = torch.empty(cdl.sequence_workspace_bytes(Xs, gdev, pb), dtype=torch.uint8, device=dev)
-        Fb, tb, binfo = cdl.score_sequence(Xs, gdev, pb, ws=wsb)          # warm-up
-        torch.cuda.synchronize()
-        cdl.timing(reset=True)
-        cdl.set_timing(True)
-        Fb, tb, binfo = cdl.score_sequence(Xs, gdev, pb, ws=wsb, out=(Fb, tb))
-        torch.cuda.synchronize()
-        cdl.set_timing(False)
-        kb = {nm: round(v[1], 3) for nm, v in sorted(cdl.timing(reset=True).items(), key=lambda x: -x[1][1])}
-        t0 = time.perf_counter()
-        for _ in range(3):
-            Fb, tb, binfo = cdl.score_sequence(Xs, gdev, pb, ws=wsb, out=(Fb, tb))
-        torch.cuda.synchronize()
-        ms_b = (time.perf_counter() - t0) / 3
-        pbg = cdl.SeqParams(k=128, seed=seed, prec=args.mixed, depth=dfix, tol=1e-8, max_iter=20,
-                            top_k=50, asynchronous=True, batched=True, graph=True)
-        for _ in range(2):   # eager, then captured
-            Fb, tb, binfo = cdl.score_sequence(Xs, gdev, pbg, ws=wsb, out=(Fb, tb))
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(3):
-            Fb, tb, ginfo = cdl.score_sequence(Xs, gdev, pbg, ws=wsb, out=(Fb, tb))
-        torch.cuda.synchronize()
-        ms_bg = (time.perf_counter() - t0) / 3
-        same = all(set(a.tolist()) == set(b.tolist()) for a, b in zip(tb, tops))
-        sequence["batched_one_pass"] = {
-            "ms_per_sequence": round(ms_b * 1e3, 2), "pairs_per_s": round(binfo.pairs / ms_b, 2),
-            "graph_replay_ms": round(ms_bg * 1e3, 2), "graph_launches": ginfo.graph_launches,
-            "chain_depth": dfix, "iterations": binfo.max_iterations,
-            "max_rel_residual": binfo.max_rel_residual, "top50_equal_to_synchronous": bool(same),
-            "kernels_ms": kb}
-        log("sequence, one pass (grouped): %.1f ms, as a graph replay %.1f ms" % (ms_b * 1e3, ms_bg * 1e3))
-        wsb = None
+    sequence = None if args.no_sequence else sequence_section(args, cdl, gen, torch, dev, seed, DMAX)
 
     streamed = None
     if not args.no_stream:

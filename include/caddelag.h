@@ -451,9 +451,9 @@ cdl_status cdl_solve_embedding(cdl_ctx *ctx, const double *W, const double *deg,
  * cdl_solve_embedding for each, with the right-hand sides of both made in
  * one sweep over W0 and W1.  The two graphs share the projection on every
  * edge (the same seed and ids give the same signs), so each edge's sign word
- * and each lane mask is made once for both (Algorithm 4 over Algorithm 3's
- * embeddings of G1 and G2).  Results equal two cdl_solve_embedding calls up
- * to the rounding of the right-hand sides' sums (< 1e-15 relative).
+ * is hashed once for both (Algorithm 4 over Algorithm 3's embeddings of G1
+ * and G2).  Results equal two cdl_solve_embedding calls up to the rounding of
+ * the right-hand sides' FP64 sums (< 1e-15 relative).
  *   W0, deg0, stats0, chain0, chain_info0   snapshot 0 as for
  *           cdl_solve_embedding (likewise for snapshot 1; the chains may
  *           differ in type and depth).
@@ -473,6 +473,35 @@ cdl_status cdl_solve_embedding_pair(cdl_ctx *ctx, const double *W0, const double
                                     cdl_solver solver, double tol, int max_iter, double *Z0,
                                     double *Z1, void *ws0, void *ws1, size_t ws_bytes,
                                     cdl_solve_info *info0, cdl_solve_info *info1);
+
+/* ---- right-hand sides alone ------------------------------------------------ */
+
+/* The k right-hand sides of Algorithm 1 for one graph, or for two graphs on
+ * one node set, as cdl_solve_embedding and cdl_solve_embedding_pair make
+ * them: y_i = (1/sqrt(k)) sum_j B(e_ij, i) q(e_ij) sqrt(W_ij), the sign of
+ * edge {i, j} in column r the bit r mod 64 of the SplitMix64 word of
+ * (seed, r / 64, the two global ids), negated at the edge's tail (the end
+ * with the higher id).  The signed sums are exact int8 matrix products of
+ * the sign bits with base-256 digits of the weights' square roots scaled by a
+ * power of two per 1024 neighbours; the only rounding is that scaling (at
+ * most 2^-55 of the largest |sqrt(W_ij)| of those neighbours per term) and
+ * the FP64 sums.
+ *   W0      device, padded n x n FP64 weights (non-negative; a non-finite
+ *           weight makes its row of Y non-finite).
+ *   W1      device, a second padded n x n FP64 weight matrix on the same node
+ *           set (the same ids, so the same signs), or NULL.
+ *   gid     device, n global node ids < 2^20, or NULL for ids 0..n-1.
+ *   n, k, seed  2 <= n <= 2^20, 1 <= k <= 2^20; seed as for
+ *           cdl_solve_embedding.
+ *   Y0, Y1  device outputs, n x k FP64 row-major (row i = y_i); Y1 NULL
+ *           exactly when W1 is NULL.
+ *   ws      device workspace of ws_bytes >= cdl_rhs_workspace_bytes (pair =
+ *           W1 != NULL).
+ * Async.  Errors: CDL_E_ARG, CDL_E_WORKSPACE. */
+cdl_status cdl_rhs_workspace_bytes(int64_t n, int64_t k, int pair, size_t *bytes);
+cdl_status cdl_rhs(cdl_ctx *ctx, const double *W0, const double *W1, const int32_t *gid,
+                   int64_t n, int64_t k, uint64_t seed, double *Y0, double *Y1, void *ws,
+                   size_t ws_bytes);
 
 /* ---- streamed snapshots (graphs larger than device memory) ---------------- */
 

@@ -36,6 +36,7 @@ from .api import (  # noqa: E402,F401
     k_rp,
     level_scale,
     level_scale_for,
+    rhs,
     score_sequence,
     sequence_workspace_bytes,
     set_autotune,

@@ -117,6 +117,8 @@ def load():
         "cdl_solve_embedding_pair": (I, [P, P, P, P, P, C.POINTER(ChainInfo), P, P, P, P,
                                          C.POINTER(ChainInfo), P, i64, i64, u64, I, d, I, P, P,
                                          P, P, sz, C.POINTER(SolveInfo), C.POINTER(SolveInfo)]),
+        "cdl_rhs_workspace_bytes": (I, [i64, i64, I, C.POINTER(sz)]),
+        "cdl_rhs": (I, [P, P, P, P, i64, i64, u64, P, P, P, sz]),
         "cdl_stream_workspace_bytes": (I, [i64, i64, i64, i64, I, C.POINTER(sz)]),
         "cdl_stream_embedding": (I, [P, P, i64, i64, i64, d, P, i64, u64, d, I, i64, I, P, sz,
                                      C.POINTER(ChainInfo), P, P, P, P, sz,

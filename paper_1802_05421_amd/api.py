@@ -372,6 +372,26 @@ def solve_embedding_pair(g0: Graph, chain0: Chain, g1: Graph, chain1: Chain, k: 
     return Z[0], Z[1], i0, i1
 
 
+def rhs(g: Graph, k: int, seed: int, gid: Optional[torch.Tensor] = None,
+        g1: Optional[Graph] = None):
+    """Algorithm 1's right-hand sides Y (n, k) float64 of g, as the solves make
+    them (cdl_rhs); with g1 (the same node set) the pair (Y0, Y1) in one sweep."""
+    dev = g.W.device
+    if g1 is not None and g1.n != g.n:
+        raise ValueError("the two graphs need the same node set")
+    if gid is not None and (gid.dtype != torch.int32 or not gid.is_cuda):
+        raise ValueError("gid must be a CUDA int32 vector")
+    ctx = context(dev.index)
+    need = C.c_size_t()
+    _check(_lib().cdl_rhs_workspace_bytes(g.n, k, int(g1 is not None), C.byref(need)))
+    ws = _ws(need.value, dev)
+    Y0 = torch.empty((g.n, k), dtype=torch.float64, device=dev)
+    Y1 = None if g1 is None else torch.empty((g.n, k), dtype=torch.float64, device=dev)
+    _check(_lib().cdl_rhs(ctx.h, _ptr(g.W), None if g1 is None else _ptr(g1.W), _ptr(gid), g.n, k,
+                          C.c_uint64(seed), _ptr(Y0), _ptr(Y1), _ptr(ws), ws.numel()), ctx.h)
+    return Y0 if g1 is None else (Y0, Y1)
+
+
 def stream_workspace_bytes(n: int, T: int, k: int, panel_rows: int = 0,
                            level: Optional[str] = None) -> int:
     out = C.c_size_t()

@@ -1295,6 +1295,48 @@ cdl_status cdl_solve_embedding_pair(cdl_ctx *ctx, const double *W0, const double
                           tol, max_iter, Z1, w1, info1);
 }
 
+// ---- right-hand sides alone ----------------------------------------------------
+
+cdl_status cdl_rhs_workspace_bytes(int64_t n, int64_t k, int pair, size_t *bytes) {
+    if (n < 2 || n > (1 << 20) || k < 1 || k > ((int64_t)1 << 20) || !bytes) return CDL_E_ARG;
+    Arena a(nullptr);
+    a.take<double>((size_t)pad_k(k) * pad_n(n) * (pair ? 2 : 1));
+    *bytes = a.off;
+    return CDL_OK;
+}
+
+cdl_status cdl_rhs(cdl_ctx *ctx, const double *W0, const double *W1, const int32_t *gid,
+                   int64_t n, int64_t k, uint64_t seed, double *Y0, double *Y1, void *ws,
+                   size_t ws_bytes) {
+    if (!ctx) return CDL_E_ARG;
+    if (n < 2 || n > (1 << 20)) return fail(ctx, CDL_E_ARG, "n must be in [2, 2^20]");
+    if (k < 1 || k > (int64_t)1 << 20) return fail(ctx, CDL_E_ARG, "k must be in [1, 2^20]");
+    if (!W0 || !Y0 || !ws || (W1 == nullptr) != (Y1 == nullptr))
+        return fail(ctx, CDL_E_ARG, "null pointer (W1 and Y1 go together)");
+    if (!aligned(W0, 16) || (W1 && !aligned(W1, 16)) || !aligned(Y0, 8) || (Y1 && !aligned(Y1, 8)) ||
+        !aligned(ws, kAlign))
+        return fail(ctx, CDL_E_ARG, "misaligned pointer");
+    size_t need = 0;
+    cdl_rhs_workspace_bytes(n, k, W1 != nullptr, &need);
+    if (ws_bytes < need) return fail(ctx, CDL_E_WORKSPACE, "right-hand-side workspace too small");
+    const int64_t ld = pad_n(n), kp = pad_k(k);
+    Arena a(ws);
+    double *Yt0 = a.take<double>((size_t)kp * ld);
+    double *Yt1 = W1 ? a.take<double>((size_t)kp * ld) : nullptr;
+    hipStream_t s = ctx->stream;
+    HIPCHK(hipSetDevice(ctx->device));
+    if (W1) {
+        Timed t_(ctx, "rhs_pair");
+        HIPCHK(launch_rhs_pair(W0, W1, ld, n, gid, k, kp, seed, Yt0, Yt1, s));
+    } else {
+        Timed t_(ctx, "rhs");
+        HIPCHK(launch_rhs(W0, ld, n, gid, k, kp, seed, Yt0, s));
+    }
+    HIPCHK(launch_transpose(Yt0, ld, n, k, Y0, s));
+    if (W1) HIPCHK(launch_transpose(Yt1, ld, n, k, Y1, s));
+    return CDL_OK;
+}
+
 // ---- streamed snapshots ---------------------------------------------------------
 
 cdl_status cdl_stream_workspace_bytes(int64_t n, int64_t T, int64_t k, int64_t panel_rows,

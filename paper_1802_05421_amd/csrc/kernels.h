@@ -200,6 +200,9 @@ hipError_t launch_col_norms2(const double *npart, int nparts, int64_t kpad, cons
                              int ntiles, int scaled, double *out, hipStream_t s);
 hipError_t launch_prep_v2(int prec, const double *Rt, const double *dm, int64_t ld, int64_t kpad,
                           const double *scal, double *V64, void *Vlo, hipStream_t s);
+// Z[i][r] = Xt[r][i] for i < n, r < k (Z n x k row-major).
+hipError_t launch_transpose(const double *Xt, int64_t ld, int64_t n, int64_t k, double *Z,
+                            hipStream_t s);
 hipError_t launch_finalize_z2(const double *Xt, int64_t ld, int64_t n, int64_t kpad, int64_t k,
                               double *mean, double *Z, hipStream_t s);
 

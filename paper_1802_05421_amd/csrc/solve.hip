@@ -957,7 +957,7 @@ __global__ __launch_bounds__(256) void k_col_mean(const double *Xt, int64_t ld, 
     if (threadIdx.x == 0) mean[r] = ((red[0] + red[1]) + (red[2] + red[3])) / (double)n;
 }
 
-// Z[i][r] = Xt[r][i] - mean[r] through a 32 x 32 LDS tile.
+// Z[i][r] = Xt[r][i] - mean[r] (mean NULL: no shift) through a 32 x 32 LDS tile.
 __global__ __launch_bounds__(256) void k_transpose_z(const double *Xt, int64_t ld, int64_t n,
                                                      int64_t k, const double *mean, double *Z) {
     __shared__ double t[32][33];
@@ -965,13 +965,20 @@ __global__ __launch_bounds__(256) void k_transpose_z(const double *Xt, int64_t l
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
     for (int q = ty; q < 32; q += 8) {
         const int64_t r = r0 + q, i = i0 + tx;
-        t[q][tx] = (r < k && i < n) ? Xt[r * ld + i] - mean[r] : 0.0;
+        t[q][tx] = (r < k && i < n) ? Xt[r * ld + i] - (mean ? mean[r] : 0.0) : 0.0;
     }
     __syncthreads();
     for (int q = ty; q < 32; q += 8) {
         const int64_t i = i0 + q, r = r0 + tx;
         if (i < n && r < k) Z[i * k + r] = t[tx][q];
     }
+}
+
+hipError_t launch_transpose(const double *Xt, int64_t ld, int64_t n, int64_t k, double *Z,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_transpose_z, dim3((unsigned)cdiv(n, 32), (unsigned)cdiv(k, 32)),
+                       dim3(256), 0, s, Xt, ld, n, k, (const double *)nullptr, Z);
+    return hipGetLastError();
 }
 
 hipError_t launch_finalize_z2(const double *Xt, int64_t ld, int64_t n, int64_t kpad, int64_t k,
