@@ -459,12 +459,17 @@ cdl_status graph_enqueue(cdl_ctx *ctx, const double *X, int64_t n, int64_t T, in
     hipStream_t s = ctx->stream;
     { Timed t_(ctx, "fill_zero"); HIPCHK(launch_fill_zero(w.flags, 256, s)); }
     { Timed t_(ctx, "pad_series"); HIPCHK(launch_pad_series(X, n, T, ldx, w.Xp, ld, Tp, w.sqn, w.flags, s)); }
+    // the median's bracket comes from a sample taken from the series, so that
+    // the Gram's epilogue can count and gather it (no pass over D2 for it)
+    const bool br = sigma <= 0.0 && select_uses_bracket(n, ctx->select_mode == 0);
     if (sigma <= 0.0) { Timed t_(ctx, "select_median"); HIPCHK(launch_select_reset(w.sel, s)); }
-    { Timed t_(ctx, "gram_dist"); HIPCHK(launch_gram_dist(w.Xp, Tp, w.sqn, n, ld, W, sigma > 0.0 ? nullptr : w.sel, s)); }
+    if (br) { Timed t_(ctx, "select_median"); HIPCHK(launch_select_presample(w.Xp, Tp, w.sqn, n, w.sel, w.selbuf, s)); }
+    { Timed t_(ctx, "gram_dist"); HIPCHK(launch_gram_dist(w.Xp, Tp, w.sqn, n, ld, W, sigma > 0.0 ? nullptr : w.sel,
+                                                          br ? w.selbuf : nullptr, select_buffer_keys(n), s)); }
     if (sigma > 0.0)
         { Timed t_(ctx, "set_sigma"); HIPCHK(launch_set_sigma(sigma, stats, s)); }
     else
-        { Timed t_(ctx, "select_median"); HIPCHK(launch_select_median(W, ld, n, w.sel, w.selbuf, ctx->select_mode == 0, stats, s)); }
+        { Timed t_(ctx, "select_median"); HIPCHK(launch_select_median(W, ld, n, w.sel, w.selbuf, br, stats, s)); }
     { Timed t_(ctx, "exp_degree"); HIPCHK(launch_exp_degree(W, ld, n, stats, deg, w.dpart, s)); }
     { Timed t_(ctx, "graph_stats"); HIPCHK(launch_graph_stats(deg, n, stats, s)); }
     return CDL_OK;

@@ -138,14 +138,22 @@ constexpr size_t kGramSmem = GramCore::SMEM;
 // row panel needs a buffer of 256 pb rows only.
 // st != nullptr: also fold the smallest and largest upper-triangle key
 // (i < j) into st->kmin / st->kmax (the median selection starts below their
-// common bit prefix).  kExp: store the weights exp(-D2 / sigma^2) instead
-// (zero on the diagonal and outside n; sigma = wstats[1]), the expression of
-// the separate exponential kernels, so the values are the same bits.
+// common bit prefix); with brbuf as well, the bracket pass of the selection
+// (select_bracket_body) on the tile's upper-triangle keys: count those below
+// st->lo into st->below and append those in [lo, hi] to brbuf (capacity
+// brcap) through an LDS stage in the GEMM's staging memory (a tile with more
+// of them than the stage holds marks the buffer full, which sends the
+// selection to its passes over the matrix: exact either way).  kExp: store the
+// weights exp(-D2 / sigma^2) instead (zero on the diagonal and outside n;
+// sigma = wstats[1]), the expression of the separate exponential kernels, so
+// the values are the same bits.
 template <bool kExp>
 __device__ __forceinline__ void gram_tile(const double *Xp, int64_t Tp, const double *sqn,
                                           int64_t n, int64_t ld, double *D2, int ncol, int I0,
                                           int pb, int full, int id, SelectState *st,
-                                          const double *wstats, double *smem) {
+                                          const double *wstats, double *smem,
+                                          unsigned long long *brbuf = nullptr,
+                                          int64_t brcap = 0) {
     int I, J;
     if (full) {
         rect_tile<4>(id, pb, ncol, I, J);
@@ -158,6 +166,20 @@ __device__ __forceinline__ void gram_tile(const double *Xp, int64_t Tp, const do
     GramCore g;
     g.run(Xp, Tp, Xp, Tp, m0, n0, Tp, smem);
     unsigned long long kmin = ~0ull, kmax = 0ull;
+    // bracket stage: the GEMM's LDS, free once every wave is past its last
+    // fragment read
+    constexpr unsigned int kStage = (unsigned int)(GramCore::SMEM / 8);
+    __shared__ unsigned int scnt;
+    __shared__ unsigned long long sbase, sbel[GramCore::NT / 64];
+    unsigned long long *const stage = (unsigned long long *)smem;
+    unsigned long long blo = 0ull, bhi = 0ull, below = 0ull;
+    unsigned int inside = 0;
+    if (brbuf) {
+        blo = st->lo;
+        bhi = st->hi;
+        if (threadIdx.x == 0) scnt = 0;
+        __syncthreads();
+    }
     // the squared norms of this lane's rows and columns, loaded once (the
     // stores below may alias sqn as far as the compiler knows)
     double sa[GramCore::WTM][MfmaF64::R], sb[GramCore::WTN];
@@ -176,6 +198,8 @@ __device__ __forceinline__ void gram_tile(const double *Xp, int64_t Tp, const do
             const unsigned long long key = (unsigned long long)__double_as_longlong(d);
             kmin = key < kmin ? key : kmin;
             kmax = key > kmax ? key : kmax;
+            below += key < blo ? 1ull : 0ull;
+            inside += (key >= blo && key <= bhi) ? 1u : 0u;
         }
         return d;
     };
@@ -199,6 +223,56 @@ __device__ __forceinline__ void gram_tile(const double *Xp, int64_t Tp, const do
                 }
                 out[(m0 + r) * ld + n0 + c] = v;
             }
+    if (brbuf) {
+        // each thread's place in the stage: a prefix sum over the wave, one
+        // LDS atomic per wave; then its bracket keys again, into the stage
+        const int lane = threadIdx.x & 63;
+        unsigned int incl = inside;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned int x = (unsigned int)__shfl_up((int)incl, o);
+            if (lane >= o) incl += x;
+        }
+        unsigned int wbase = 0;
+        if (lane == 63 && incl > 0) wbase = atomicAdd(&scnt, incl);
+        unsigned int off = (unsigned int)__shfl((int)wbase, 63) + incl - inside;
+#pragma unroll
+        for (int a = 0; a < GramCore::WTM; ++a)
+#pragma unroll
+            for (int b = 0; b < GramCore::WTN; ++b)
+#pragma unroll
+                for (int rr = 0; rr < MfmaF64::R; ++rr) {
+                    const int64_t ia = m0 + GramCore::row_of(a, rr), ib = n0 + GramCore::col_of(b);
+                    double d = sa[a][rr] + sb[b] - 2.0 * g.acc[a][b][rr];
+                    d = d < 0.0 ? 0.0 : d;
+                    const unsigned long long key = (unsigned long long)__double_as_longlong(d);
+                    if (ia < ib && ib < n && key >= blo && key <= bhi) {
+                        if (off < kStage) stage[off] = key;
+                        ++off;
+                    }
+                }
+        // the stage behind one global atomic, the count below
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) below += __shfl_xor(below, o);
+        if (lane == 0) sbel[threadIdx.x >> 6] = below;
+        __syncthreads();
+        const unsigned int c = scnt;
+        if (threadIdx.x == 0) {
+            unsigned long long bl = 0ull;
+#pragma unroll
+            for (int w = 0; w < GramCore::NT / 64; ++w) bl += sbel[w];
+            if (bl) atomicAdd(&st->below, bl);
+            // a full stage: mark the buffer full (the passes then take the matrix)
+            sbase = c > kStage ? atomicAdd(&st->nbuf, (unsigned long long)brcap + 1ull)
+                               : (c > 0 ? atomicAdd(&st->nbuf, (unsigned long long)c) : 0ull);
+        }
+        __syncthreads();
+        if (c <= kStage) {
+            const unsigned long long base = sbase;
+            for (unsigned int q = threadIdx.x; q < c; q += GramCore::NT)
+                if (base + q < (unsigned long long)brcap) brbuf[base + q] = stage[q];
+        }
+    }
     if (st) {
         // the tile's smallest and largest key: waves, then the workgroup, then
         // one pair of atomics per tile (all tiles update the same two words)
@@ -231,10 +305,11 @@ __global__ __launch_bounds__(512) void k_gram_dist(const double *Xp, int64_t Tp,
                                                    const double *sqn, int64_t n, int64_t ld,
                                                    double *D2, int ncol, int I0, int pb,
                                                    int full, int total, SelectState *st,
-                                                   const double *wstats) {
+                                                   const double *wstats,
+                                                   unsigned long long *brbuf, int64_t brcap) {
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
     gram_tile<kExp>(Xp, Tp, sqn, n, ld, D2, ncol, I0, pb, full, xcd_remap(blockIdx.x, total), st,
-                    wstats, (double *)smem_raw);
+                    wstats, (double *)smem_raw, brbuf, brcap);
 }
 
 static hipError_t gram_attr() {
@@ -253,13 +328,16 @@ static hipError_t gram_attr() {
 }
 
 hipError_t launch_gram_dist(const double *Xp, int64_t Tp, const double *sqn, int64_t n,
-                            int64_t ld, double *D2, SelectState *st, hipStream_t s) {
+                            int64_t ld, double *D2, SelectState *st, unsigned long long *brbuf,
+                            int64_t brcap, hipStream_t s) {
+    if (brbuf && !st) return hipErrorInvalidValue;
     hipError_t e = gram_attr();
     if (e != hipSuccess) return e;
     const int ncol = (int)(ld / 128);
     const int total = rect_upper_tiles(ld);
     hipLaunchKernelGGL(k_gram_dist<false>, dim3(total), dim3(512), kGramSmem, s, Xp, Tp, sqn, n,
-                       ld, D2, ncol, 0, (int)(ld / 256), 0, total, st, (const double *)nullptr);
+                       ld, D2, ncol, 0, (int)(ld / 256), 0, total, st, (const double *)nullptr,
+                       brbuf, brcap);
     return hipGetLastError();
 }
 
@@ -281,11 +359,13 @@ hipError_t launch_gram_panel(const double *Xp, int64_t Tp, const double *sqn, in
     if (wstats)
         hipLaunchKernelGGL(k_gram_dist<true>, dim3((unsigned)total), dim3(512), kGramSmem, s, Xp,
                            Tp, sqn, n, ld, D2p, ncol, I0, pb, 1, (int)total,
-                           (SelectState *)nullptr, wstats);
+                           (SelectState *)nullptr, wstats, (unsigned long long *)nullptr,
+                           (int64_t)0);
     else
         hipLaunchKernelGGL(k_gram_dist<false>, dim3((unsigned)total), dim3(512), kGramSmem, s, Xp,
                            Tp, sqn, n, ld, D2p, ncol, I0, pb, full ? 1 : 0, (int)total,
-                           (SelectState *)nullptr, (const double *)nullptr);
+                           (SelectState *)nullptr, (const double *)nullptr,
+                           (unsigned long long *)nullptr, (int64_t)0);
     return hipGetLastError();
 }
 
@@ -294,8 +374,10 @@ hipError_t launch_gram_panel(const double *Xp, int64_t Tp, const double *sqn, in
 // D2_ij (i < j).  D2 >= 0, so its IEEE bit pattern orders like its value.
 // First a bracket: a sorted sample of kSelSample keys gives [lo, hi] around
 // the target quantile (three standard deviations of the sample quantile on
-// each side); one pass over the matrix counts the keys below lo and appends
-// those in [lo, hi] to a buffer.  If the target rank falls inside the bracket
+// each side); the keys below lo are counted and those in [lo, hi] appended to
+// a buffer, by the Gram's epilogue for a single stored snapshot (its sample
+// taken from the series beforehand), else by one pass over the matrix (its
+// sample taken from the matrix).  If the target rank falls inside the bracket
 // the radix passes below run over the buffer, else over the matrix (the
 // result is exact either way).  Radix passes of 12-bit digits start below the
 // common prefix of the bracket (or of the smallest and largest key); as soon
@@ -333,6 +415,19 @@ __device__ inline unsigned long long sel_mix(unsigned long long z) {
     return z ^ (z >> 31);
 }
 
+// Sample pair u of the bracket: a pseudo-random pair i != j.
+__device__ inline void sel_pair(unsigned long long u, int64_t n, int64_t &a, int64_t &b) {
+    const unsigned long long h = sel_mix(0x5851f42d4c957f2dull + u);
+    const int64_t i = (int64_t)((h & 0xffffffffull) % (unsigned long long)n);
+    int64_t j = (int64_t)((h >> 32) % (unsigned long long)(n - 1));
+    if (j >= i) ++j;   // j != i
+    a = i < j ? i : j;
+    b = i < j ? j : i;
+}
+
+__device__ __forceinline__ void select_sort_bracket(int64_t n, SelectState *st,
+                                                    unsigned long long *sk);
+
 // One workgroup: kSelSample keys at pseudo-random pairs i != j, bitonic sort
 // in LDS, bracket of kSelMargin sample ranks on each side of the target.
 __device__ __forceinline__ void select_sample_body(const double *D2, int64_t ld, int64_t n,
@@ -342,16 +437,21 @@ __device__ __forceinline__ void select_sample_body(const double *D2, int64_t ld,
     unsigned long long v[kSelSample / 1024];
 #pragma unroll
     for (int u = 0; u < kSelSample / 1024; ++u) {   // independent loads in flight together
-        const unsigned long long h = sel_mix(0x5851f42d4c957f2dull + (unsigned long long)(t + 1024 * u));
-        int64_t i = (int64_t)((h & 0xffffffffull) % (unsigned long long)n);
-        int64_t j = (int64_t)((h >> 32) % (unsigned long long)(n - 1));
-        if (j >= i) ++j;   // j != i
-        const int64_t a = i < j ? i : j, b = i < j ? j : i;
+        int64_t a, b;
+        sel_pair((unsigned long long)(t + 1024 * u), n, a, b);
         v[u] = (unsigned long long)__double_as_longlong(D2[a * ld + b]);
     }
 #pragma unroll
     for (int u = 0; u < kSelSample / 1024; ++u) sk[t + 1024 * u] = v[u];
     __syncthreads();
+    select_sort_bracket(n, st, sk);
+}
+
+// Sort the kSelSample keys in sk (LDS, 1024 threads) and set the bracket
+// [lo, hi] of kSelMargin sample ranks on each side of the target rank.
+__device__ __forceinline__ void select_sort_bracket(int64_t n, SelectState *st,
+                                                    unsigned long long *sk) {
+    const int t = threadIdx.x;
     for (int size = 2; size <= kSelSample; size <<= 1)
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
             for (int q = t; q < kSelSample / 2; q += 1024) {
@@ -373,10 +473,37 @@ __device__ __forceinline__ void select_sample_body(const double *D2, int64_t ld,
     }
 }
 
-__global__ __launch_bounds__(1024) void k_select_sample(const double *D2, int64_t ld, int64_t n,
-                                                        SelectState *st) {
+// The same sample pairs' keys from the padded series, before the Gram: one
+// wave per pair, D2 = sq_a + sq_b - 2 x_a.x_b with the dot product summed
+// over the lanes (another order than the Gram's: an estimate of the quantile,
+// which is all the bracket needs; the counts against it are exact).
+__global__ __launch_bounds__(256) void k_select_sample_keys(const double *Xp, int64_t Tp,
+                                                            const double *sqn, int64_t n,
+                                                            unsigned long long *keys) {
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6), nwave = gridDim.x * 4;
+    for (int u = wave; u < kSelSample; u += nwave) {
+        int64_t a, b;
+        sel_pair((unsigned long long)u, n, a, b);
+        const double *xa = Xp + a * Tp, *xb = Xp + b * Tp;
+        double dot = 0.0;
+        for (int64_t q = lane; q < Tp; q += 64) dot += xa[q] * xb[q];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) dot += __shfl_xor(dot, o);
+        if (lane == 0) {
+            double d = sqn[a] + sqn[b] - 2.0 * dot;
+            d = d < 0.0 ? 0.0 : d;
+            keys[u] = (unsigned long long)__double_as_longlong(d);
+        }
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_select_sort_bracket(const unsigned long long *keys,
+                                                              int64_t n, SelectState *st) {
     extern __shared__ unsigned long long sk[];
-    select_sample_body(D2, ld, n, st, sk);
+    for (int u = threadIdx.x; u < kSelSample; u += 1024) sk[u] = keys[u];
+    __syncthreads();
+    select_sort_bracket(n, st, sk);
 }
 
 // Count the keys below lo; append those in [lo, hi] to buf (at most cap).
@@ -443,13 +570,6 @@ __device__ __forceinline__ void select_bracket_body(const double *D2, int64_t ld
         const unsigned long long bl = spart[0] + spart[1] + spart[2] + spart[3];
         if (bl) atomicAdd(&st->below, bl);
     }
-}
-
-__global__ __launch_bounds__(256) void k_select_bracket(const double *D2, int64_t ld, int64_t n,
-                                                        int64_t row0, int64_t row1,
-                                                        SelectState *st, unsigned long long *buf,
-                                                        int64_t cap) {
-    select_bracket_body(D2, ld, n, row0, row1, st, buf, cap, blockIdx.x, gridDim.x);
 }
 
 // The bracket pass for very many keys (streamed panels: billions of keys,
@@ -743,29 +863,30 @@ hipError_t launch_select_reset(SelectState *st, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_select_median(const double *D2, int64_t ld, int64_t n, SelectState *st,
-                                unsigned long long *buf, bool bracket, double *stats,
-                                hipStream_t s) {
+hipError_t launch_select_presample(const double *Xp, int64_t Tp, const double *sqn, int64_t n,
+                                   SelectState *st, unsigned long long *buf, hipStream_t s) {
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_select_sample,
+        hipError_t e = hipFuncSetAttribute((const void *)k_select_sort_bracket,
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
                                            kSelSample * 8);
         if (e != hipSuccess) return e;
         attr = true;
     }
+    if (select_buffer_keys(n) < kSelSample) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_select_sample_keys, dim3(64), dim3(256), 0, s, Xp, Tp, sqn, n, buf);
+    hipLaunchKernelGGL(k_select_sort_bracket, dim3(1), dim3(1024), kSelSample * 8, s, buf, n, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_median(const double *D2, int64_t ld, int64_t n, SelectState *st,
+                                unsigned long long *buf, bool gathered, double *stats,
+                                hipStream_t s) {
     hipLaunchKernelGGL(k_select_setup, dim3(1), dim3(64), 0, s, st, n, stats);
     const int grid = (int)(n < 2048 ? n : 2048);
     const int64_t cap = select_buffer_keys(n);
-    // the bracket holds about 2 kSelMargin / kSelSample of the N keys: skip it
-    // when that would not fit the buffer
-    const double N = (double)n * (double)(n - 1) / 2.0;
-    if (bracket && N * 2.0 * kSelMargin / kSelSample <= 0.8 * (double)cap) {
-        hipLaunchKernelGGL(k_select_sample, dim3(1), dim3(1024), kSelSample * 8, s, D2, ld, n, st);
-        hipLaunchKernelGGL(k_select_bracket, dim3(grid), dim3(256), 0, s, D2, ld, n, (int64_t)0, n,
-                           st, buf, cap);
+    if (gathered)   // the Gram's epilogue counted and gathered the bracket
         hipLaunchKernelGGL(k_select_check, dim3(1), dim3(64), 0, s, st, cap, stats);
-    }
     // at most 6 digit passes resolve 64 bits; the collect pass is one more
     for (int p = 0; p < 7; ++p) {
         hipLaunchKernelGGL(k_select_pass, dim3(grid), dim3(256), 0, s, D2, ld, n, (int64_t)0, n,

@@ -38,9 +38,12 @@ hipError_t launch_pad_series(const double *X, int64_t n, int64_t T, int64_t ldx,
                              double *Xp, int64_t rows, int64_t Tp, double *sqn,
                              int *flags, hipStream_t s);
 // st != nullptr: also record min/max upper-triangle keys for the selection
-// (st must have been reset with launch_select_reset).
+// (st must have been reset with launch_select_reset); brbuf != nullptr (with
+// st, after launch_select_presample): also count the upper-triangle keys
+// below the bracket and gather those inside it into brbuf (brcap keys).
 hipError_t launch_gram_dist(const double *Xp, int64_t Tp, const double *sqn, int64_t n,
-                            int64_t ld, double *D2, SelectState *st, hipStream_t s);
+                            int64_t ld, double *D2, SelectState *st, unsigned long long *brbuf,
+                            int64_t brcap, hipStream_t s);
 // Row panel [row0, row0 + rows) of the same tiles (row0 and rows multiples of
 // 256): the upper-triangle cover only (full = false) or every tile of the
 // rows (full = true), row i stored at D2p + (i - row0) ld.  wstats != nullptr
@@ -79,10 +82,16 @@ hipError_t launch_select_buffer_pass(SelectState *st, const unsigned long long *
 hipError_t launch_exp_rows(double *Wp, int64_t ld, int64_t n, int64_t row0, int64_t rows,
                            const double *stats, double *deg, const double *dinv, double *fro,
                            hipStream_t s);
-// buf: select_buffer_keys(n) words of scratch; bracket = false: radix
-// passes over the matrix only.
+// The bracket of the median selection from a sample of pair distances taken
+// from the padded series (buf: select_buffer_keys(n) words of scratch, its
+// first 4096 words used); call before launch_gram_dist with brbuf = buf.
+hipError_t launch_select_presample(const double *Xp, int64_t Tp, const double *sqn, int64_t n,
+                                   SelectState *st, unsigned long long *buf, hipStream_t s);
+// The exact lower median after the Gram: gathered = the Gram gathered the
+// bracket into buf (radix passes over it when it holds the target rank),
+// else radix passes over the matrix only.
 hipError_t launch_select_median(const double *D2, int64_t ld, int64_t n,
-                                SelectState *st, unsigned long long *buf, bool bracket,
+                                SelectState *st, unsigned long long *buf, bool gathered,
                                 double *stats, hipStream_t s);
 hipError_t launch_set_sigma(double sigma, double *stats, hipStream_t s);
 // part: (ld / 64) x ld doubles of degree partials.
