@@ -2200,6 +2200,7 @@ static cdl_status score_sequence_batched(cdl_ctx *ctx, int32_t n_snap, const cdl
         g.fro64 = chains[t].fro64;
         g.scale = (double)level_scale(prec, n);
         const bool br = cdl::select_uses_bracket(n, ctx->select_mode == 0);
+        g.bracket = br ? 1 : 0;
         for (int tb = 0; tb < cdl::kGraphTables; ++tb) {
             int *row = gpre.data() + (size_t)tb * (P + 1);
             row[t + 1] = row[t] + cdl::graph_table_count(tb, n, ld, br);

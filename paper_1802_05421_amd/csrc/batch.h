@@ -40,6 +40,7 @@ struct GraphSnap {
     SelectState *sel;
     unsigned long long *buf;   // bracket buffer of the selection
     int64_t cap;               // its capacity (keys)
+    int bracket;               // the selection starts with a sampled bracket
     double *dpart;             // degree partials
     // level 0 of the chain
     double *dmn, *dm, *u;
@@ -54,7 +55,7 @@ enum GraphTable {
     kGtOne,       // one workgroup per snapshot
     kGtGram,      // upper-triangle 256 x 128 tiles
     kGtSample,    // one per snapshot whose selection starts with a sampled bracket
-    kGtBracket,   // min(n, 2048) per such snapshot
+    kGtKeys,      // 16 per such snapshot (its sample's keys from the series)
     kGtPass,      // min(n, 2048) per snapshot
     kGtSym,       // upper 64 x 64 tiles
     kGtNodes64,   // ceil(n / 64)

@@ -139,9 +139,9 @@ constexpr size_t kGramSmem = GramCore::SMEM;
 // st != nullptr: also fold the smallest and largest upper-triangle key
 // (i < j) into st->kmin / st->kmax (the median selection starts below their
 // common bit prefix); with brbuf as well, the bracket pass of the selection
-// (select_bracket_body) on the tile's upper-triangle keys: count those below
-// st->lo into st->below and append those in [lo, hi] to brbuf (capacity
-// brcap) through an LDS stage in the GEMM's staging memory (a tile with more
+// on the tile's upper-triangle keys: count those below st->lo into st->below
+// and append those in [lo, hi] to brbuf (capacity brcap) through an LDS
+// stage in the GEMM's staging memory (a tile with more
 // of them than the stage holds marks the buffer full, which sends the
 // selection to its passes over the matrix: exact either way).  kExp: store the
 // weights exp(-D2 / sigma^2) instead (zero on the diagonal and outside n;
@@ -374,10 +374,10 @@ hipError_t launch_gram_panel(const double *Xp, int64_t Tp, const double *sqn, in
 // D2_ij (i < j).  D2 >= 0, so its IEEE bit pattern orders like its value.
 // First a bracket: a sorted sample of kSelSample keys gives [lo, hi] around
 // the target quantile (three standard deviations of the sample quantile on
-// each side); the keys below lo are counted and those in [lo, hi] appended to
-// a buffer, by the Gram's epilogue for a single stored snapshot (its sample
-// taken from the series beforehand), else by one pass over the matrix (its
-// sample taken from the matrix).  If the target rank falls inside the bracket
+// each side), the sample's keys taken from the series before the Gram; the
+// keys below lo are counted and those in [lo, hi] appended to a buffer, by
+// the Gram's epilogue for stored snapshots, by one sweep over the recomputed
+// upper panels for streamed ones.  If the target rank falls inside the bracket
 // the radix passes below run over the buffer, else over the matrix (the
 // result is exact either way).  Radix passes of 12-bit digits start below the
 // common prefix of the bracket (or of the smallest and largest key); as soon
@@ -425,28 +425,6 @@ __device__ inline void sel_pair(unsigned long long u, int64_t n, int64_t &a, int
     b = i < j ? j : i;
 }
 
-__device__ __forceinline__ void select_sort_bracket(int64_t n, SelectState *st,
-                                                    unsigned long long *sk);
-
-// One workgroup: kSelSample keys at pseudo-random pairs i != j, bitonic sort
-// in LDS, bracket of kSelMargin sample ranks on each side of the target.
-__device__ __forceinline__ void select_sample_body(const double *D2, int64_t ld, int64_t n,
-                                                   SelectState *st, unsigned long long *sk) {
-    if (st->mode == 2) return;
-    const int t = threadIdx.x;
-    unsigned long long v[kSelSample / 1024];
-#pragma unroll
-    for (int u = 0; u < kSelSample / 1024; ++u) {   // independent loads in flight together
-        int64_t a, b;
-        sel_pair((unsigned long long)(t + 1024 * u), n, a, b);
-        v[u] = (unsigned long long)__double_as_longlong(D2[a * ld + b]);
-    }
-#pragma unroll
-    for (int u = 0; u < kSelSample / 1024; ++u) sk[t + 1024 * u] = v[u];
-    __syncthreads();
-    select_sort_bracket(n, st, sk);
-}
-
 // Sort the kSelSample keys in sk (LDS, 1024 threads) and set the bracket
 // [lo, hi] of kSelMargin sample ranks on each side of the target rank.
 __device__ __forceinline__ void select_sort_bracket(int64_t n, SelectState *st,
@@ -477,11 +455,11 @@ __device__ __forceinline__ void select_sort_bracket(int64_t n, SelectState *st,
 // wave per pair, D2 = sq_a + sq_b - 2 x_a.x_b with the dot product summed
 // over the lanes (another order than the Gram's: an estimate of the quantile,
 // which is all the bracket needs; the counts against it are exact).
-__global__ __launch_bounds__(256) void k_select_sample_keys(const double *Xp, int64_t Tp,
-                                                            const double *sqn, int64_t n,
-                                                            unsigned long long *keys) {
+__device__ __forceinline__ void select_sample_keys_body(const double *Xp, int64_t Tp,
+                                                        const double *sqn, int64_t n,
+                                                        unsigned long long *keys, int wave,
+                                                        int nwave) {
     const int lane = threadIdx.x & 63;
-    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6), nwave = gridDim.x * 4;
     for (int u = wave; u < kSelSample; u += nwave) {
         int64_t a, b;
         sel_pair((unsigned long long)u, n, a, b);
@@ -498,78 +476,24 @@ __global__ __launch_bounds__(256) void k_select_sample_keys(const double *Xp, in
     }
 }
 
-__global__ __launch_bounds__(1024) void k_select_sort_bracket(const unsigned long long *keys,
-                                                              int64_t n, SelectState *st) {
-    extern __shared__ unsigned long long sk[];
+__global__ __launch_bounds__(256) void k_select_sample_keys(const double *Xp, int64_t Tp,
+                                                            const double *sqn, int64_t n,
+                                                            unsigned long long *keys) {
+    select_sample_keys_body(Xp, Tp, sqn, n, keys, blockIdx.x * 4 + (threadIdx.x >> 6),
+                            gridDim.x * 4);
+}
+
+__device__ __forceinline__ void select_sort_keys(const unsigned long long *keys, int64_t n,
+                                                 SelectState *st, unsigned long long *sk) {
     for (int u = threadIdx.x; u < kSelSample; u += 1024) sk[u] = keys[u];
     __syncthreads();
     select_sort_bracket(n, st, sk);
 }
 
-// Count the keys below lo; append those in [lo, hi] to buf (at most cap).
-// Appends go to a per-workgroup LDS stage (one LDS atomic each) copied out
-// behind one global atomic at the end; a workgroup holds about
-// N / 2048 * 2 kSelMargin / kSelSample ~ 3000 bracket keys for n = 16384, and
-// keys past the stage's end take a global slot each.
-// Rows [row0, row1): row i at D2 + (i - row0) ld (a row panel, or the whole
-// matrix with row0 = 0, row1 = n).
-// Workgroup b of nb.
-__device__ __forceinline__ void select_bracket_body(const double *D2, int64_t ld, int64_t n,
-                                                    int64_t row0, int64_t row1, SelectState *st,
-                                                    unsigned long long *buf, int64_t cap,
-                                                    int64_t b, int64_t nb) {
-    constexpr unsigned int kStage = 4096;
-    __shared__ unsigned long long sb[kStage];
-    __shared__ unsigned int scnt;
-    __shared__ unsigned long long sbase, spart[4];
-    if (st->mode == 2) return;
-    const unsigned long long lo = st->lo, hi = st->hi;
-    const int t = threadIdx.x;
-    if (t == 0) scnt = 0;
-    __syncthreads();
-    unsigned long long below = 0;
-    for (int64_t i = row0 + b; i < row1; i += nb) {
-        const unsigned long long *row = (const unsigned long long *)(D2 + (i - row0) * ld);
-        for (int64_t j0 = i + 1 + t; j0 < n; j0 += 8 * 256) {
-            unsigned long long key[8];   // eight independent loads in flight
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int64_t j = j0 + 256 * u;
-                key[u] = j < n ? row[j] : ~0ull;   // ~0: above every bracket
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                if (key[u] < lo) {
-                    ++below;
-                } else if (key[u] <= hi && key[u] != ~0ull) {
-                    const unsigned int q = atomicAdd(&scnt, 1u);
-                    if (q < kStage) {
-                        sb[q] = key[u];
-                    } else {
-                        const unsigned long long g = atomicAdd(&st->nbuf, 1ull);
-                        if (g < (unsigned long long)cap) buf[g] = key[u];
-                    }
-                }
-            }
-        }
-    }
-    __syncthreads();
-    const unsigned int c = scnt < kStage ? scnt : kStage;
-    if (t == 0 && c > 0) sbase = atomicAdd(&st->nbuf, (unsigned long long)c);
-    __syncthreads();
-    if (c > 0) {
-        const unsigned long long base = sbase;
-        for (unsigned int q = t; q < c; q += 256)
-            if (base + q < (unsigned long long)cap) buf[base + q] = sb[q];
-    }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) below += __shfl_xor(below, o);
-    if ((t & 63) == 0) spart[t >> 6] = below;
-    __syncthreads();
-    if (t == 0) {
-        const unsigned long long bl = spart[0] + spart[1] + spart[2] + spart[3];
-        if (bl) atomicAdd(&st->below, bl);
-    }
+__global__ __launch_bounds__(1024) void k_select_sort_bracket(const unsigned long long *keys,
+                                                              int64_t n, SelectState *st) {
+    extern __shared__ unsigned long long sk[];
+    select_sort_keys(keys, n, st, sk);
 }
 
 // The bracket pass for very many keys (streamed panels: billions of keys,
@@ -1267,7 +1191,7 @@ int graph_table_count(int tb, int64_t n, int64_t ld, bool bracket) {
     case kGtOne: return 1;
     case kGtGram: return rect_upper_tiles(ld);
     case kGtSample: return bracket ? 1 : 0;
-    case kGtBracket: return bracket ? grid : 0;
+    case kGtKeys: return bracket ? 16 : 0;
     case kGtPass: return grid;
     case kGtSym: return sym_tiles64(ld);
     case kGtNodes64: return (int)cdiv(n, 64);
@@ -1302,6 +1226,22 @@ __global__ __launch_bounds__(64) void k_pad_grouped(const GraphSnap *snaps, cons
     pad_row(d.X, d.n, d.T, d.ldx, d.Xp, d.Tp, d.sqn, d.flags, g.b);
 }
 
+__global__ __launch_bounds__(256) void k_select_keys_grouped(const GraphSnap *snaps, const int *prefix,
+                                                             int P) {
+    const GroupSlot g = group_slot(prefix, P);
+    const GraphSnap &d = snaps[g.p];
+    select_sample_keys_body(d.Xp, d.Tp, d.sqn, d.n, d.buf, (int)g.b * 4 + (threadIdx.x >> 6),
+                            (int)g.nb * 4);
+}
+
+__global__ __launch_bounds__(1024) void k_select_sort_grouped(const GraphSnap *snaps, const int *prefix,
+                                                              int P) {
+    extern __shared__ unsigned long long sk[];
+    const GroupSlot g = group_slot(prefix, P);
+    const GraphSnap &d = snaps[g.p];
+    select_sort_keys(d.buf, d.n, d.sel, sk);
+}
+
 __global__ __launch_bounds__(512) void k_gram_grouped(const GraphSnap *snaps, const int *prefix, int P,
                                                       int select) {
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
@@ -1309,7 +1249,8 @@ __global__ __launch_bounds__(512) void k_gram_grouped(const GraphSnap *snaps, co
     const GraphSnap &d = snaps[g.p];
     gram_tile<false>(d.Xp, d.Tp, d.sqn, d.n, d.ld, d.W, (int)(d.ld / 128), 0, (int)(d.ld / 256), 0,
                      xcd_remap((int)g.b, (int)g.nb), select ? d.sel : nullptr,
-                     (const double *)nullptr, (double *)smem_raw);
+                     (const double *)nullptr, (double *)smem_raw,
+                     select && d.bracket ? d.buf : nullptr, d.cap);
 }
 
 __global__ __launch_bounds__(64) void k_select_setup_grouped(const GraphSnap *snaps, const int *prefix,
@@ -1317,21 +1258,6 @@ __global__ __launch_bounds__(64) void k_select_setup_grouped(const GraphSnap *sn
     const GroupSlot g = group_slot(prefix, P);
     const GraphSnap &d = snaps[g.p];
     select_setup_body(d.sel, d.n, d.stats);
-}
-
-__global__ __launch_bounds__(1024) void k_select_sample_grouped(const GraphSnap *snaps, const int *prefix,
-                                                                int P) {
-    extern __shared__ unsigned long long sk[];
-    const GroupSlot g = group_slot(prefix, P);
-    const GraphSnap &d = snaps[g.p];
-    select_sample_body(d.W, d.ld, d.n, d.sel, sk);
-}
-
-__global__ __launch_bounds__(256) void k_select_bracket_grouped(const GraphSnap *snaps, const int *prefix,
-                                                                int P) {
-    const GroupSlot g = group_slot(prefix, P);
-    const GraphSnap &d = snaps[g.p];
-    select_bracket_body(d.W, d.ld, d.n, 0, d.n, d.sel, d.buf, d.cap, g.b, g.nb);
 }
 
 __global__ __launch_bounds__(64) void k_select_check_grouped(const GraphSnap *snaps, const int *prefix,
@@ -1389,7 +1315,7 @@ hipError_t launch_graph_grouped(const GraphSnap *snaps, const int *tables, const
         e = hipFuncSetAttribute((const void *)k_gram_grouped,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGramSmem);
         if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void *)k_select_sample_grouped,
+            e = hipFuncSetAttribute((const void *)k_select_sort_grouped,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, kSelSample * 8);
         if (e != hipSuccess) return e;
         attr = true;
@@ -1398,18 +1324,20 @@ hipError_t launch_graph_grouped(const GraphSnap *snaps, const int *tables, const
     hipLaunchKernelGGL(k_graph_init_grouped, dim3(totals[kGtOne]), dim3(256), 0, s, snaps, tb(kGtOne), P,
                        select ? 1 : 0);
     hipLaunchKernelGGL(k_pad_grouped, dim3(totals[kGtRows]), dim3(64), 0, s, snaps, tb(kGtRows), P);
+    // the brackets from samples of the series; the Gram counts and gathers them
+    if (select && totals[kGtSample] > 0) {
+        hipLaunchKernelGGL(k_select_keys_grouped, dim3(totals[kGtKeys]), dim3(256), 0, s, snaps,
+                           tb(kGtKeys), P);
+        hipLaunchKernelGGL(k_select_sort_grouped, dim3(totals[kGtSample]), dim3(1024), kSelSample * 8, s,
+                           snaps, tb(kGtSample), P);
+    }
     hipLaunchKernelGGL(k_gram_grouped, dim3(totals[kGtGram]), dim3(512), kGramSmem, s, snaps,
                        tb(kGtGram), P, select ? 1 : 0);
     if (select) {
         hipLaunchKernelGGL(k_select_setup_grouped, dim3(totals[kGtOne]), dim3(64), 0, s, snaps, tb(kGtOne), P);
-        if (totals[kGtSample] > 0) {
-            hipLaunchKernelGGL(k_select_sample_grouped, dim3(totals[kGtSample]), dim3(1024), kSelSample * 8, s,
-                               snaps, tb(kGtSample), P);
-            hipLaunchKernelGGL(k_select_bracket_grouped, dim3(totals[kGtBracket]), dim3(256), 0, s, snaps,
-                               tb(kGtBracket), P);
+        if (totals[kGtSample] > 0)
             hipLaunchKernelGGL(k_select_check_grouped, dim3(totals[kGtSample]), dim3(64), 0, s, snaps,
                                tb(kGtSample), P);
-        }
         // as in the per-snapshot selection: at most 6 digit passes and the
         // collect pass, each followed by the pick
         for (int q = 0; q < 7; ++q) {
