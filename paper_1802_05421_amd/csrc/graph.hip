@@ -879,10 +879,8 @@ __global__ __launch_bounds__(1024) void k_select_sample_x(const double *Xp, int6
     extern __shared__ unsigned long long sk[];
     const int t = threadIdx.x;
     for (int u = 0; u < kStreamSample / 1024; ++u) {
-        const unsigned long long h = sel_mix(0x5851f42d4c957f2dull + (unsigned long long)(t + 1024 * u));
-        int64_t i = (int64_t)((h & 0xffffffffull) % (unsigned long long)n);
-        int64_t j = (int64_t)((h >> 32) % (unsigned long long)(n - 1));
-        if (j >= i) ++j;   // j != i
+        int64_t i, j;
+        sel_pair((unsigned long long)(t + 1024 * u), n, i, j);
         const double *xa = Xp + i * Tp, *xb = Xp + j * Tp;
         double dot = 0.0;
         for (int64_t q = 0; q < Tp; ++q) dot += xa[q] * xb[q];
