@@ -141,9 +141,10 @@ constexpr size_t kGramSmem = GramCore::SMEM;
 // common bit prefix); with brbuf as well, the bracket pass of the selection
 // on the tile's upper-triangle keys: count those below st->lo into st->below
 // and append those in [lo, hi] to brbuf (capacity brcap) through an LDS
-// stage in the GEMM's staging memory (a tile with more
-// of them than the stage holds marks the buffer full, which sends the
-// selection to its passes over the matrix: exact either way).  kExp: store the
+// stage in the GEMM's staging memory, one segment per wave filled at ballot
+// positions (a wave with more of them than its segment holds marks the
+// buffer full, which sends the selection to its passes over the matrix:
+// exact either way).  kExp: store the
 // weights exp(-D2 / sigma^2) instead (zero on the diagonal and outside n;
 // sigma = wstats[1]), the expression of the separate exponential kernels, so
 // the values are the same bits.
@@ -167,17 +168,17 @@ __device__ __forceinline__ void gram_tile(const double *Xp, int64_t Tp, const do
     g.run(Xp, Tp, Xp, Tp, m0, n0, Tp, smem);
     unsigned long long kmin = ~0ull, kmax = 0ull;
     // bracket stage: the GEMM's LDS, free once every wave is past its last
-    // fragment read
-    constexpr unsigned int kStage = (unsigned int)(GramCore::SMEM / 8);
-    __shared__ unsigned int scnt;
-    __shared__ unsigned long long sbase, sbel[GramCore::NT / 64];
-    unsigned long long *const stage = (unsigned long long *)smem;
-    unsigned long long blo = 0ull, bhi = 0ull, below = 0ull;
-    unsigned int inside = 0;
+    // fragment read; each wave appends to its own segment of it
+    constexpr unsigned int kSeg = (unsigned int)(GramCore::SMEM / 8 / (GramCore::NT / 64));
+    __shared__ unsigned long long sbel[GramCore::NT / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    unsigned long long *const seg = (unsigned long long *)smem + wid * kSeg;
+    const unsigned long long ltmask = (1ull << lane) - 1ull;
+    unsigned long long blo = 0ull, bhi = 0ull;
+    unsigned int below = 0, wcount = 0;   // wcount: the wave's bracket keys so far (every lane)
     if (brbuf) {
         blo = st->lo;
         bhi = st->hi;
-        if (threadIdx.x == 0) scnt = 0;
         __syncthreads();
     }
     // the squared norms of this lane's rows and columns, loaded once (the
@@ -189,19 +190,18 @@ __device__ __forceinline__ void gram_tile(const double *Xp, int64_t Tp, const do
         for (int rr = 0; rr < MfmaF64::R; ++rr) sa[a][rr] = sqn[m0 + GramCore::row_of(a, rr)];
 #pragma unroll
     for (int b = 0; b < GramCore::WTN; ++b) sb[b] = sqn[n0 + GramCore::col_of(b)];
-    auto f = [&](int r, int c, double acc, double sqa, double sqb) -> double {
+    // D2 of element (r, c) (zero outside n and on the diagonal), without
+    // branches; upper: an upper-triangle pair inside n, whose key d2 is
+    auto f = [&](int r, int c, double acc, double sqa, double sqb, bool &upper,
+                 unsigned long long &key) -> double {
         const int64_t a = m0 + r, b = n0 + c;
-        if (a >= n || b >= n || a == b) return 0.0;
         double d = sqa + sqb - 2.0 * acc;
         d = d < 0.0 ? 0.0 : d;
-        if (a < b) {
-            const unsigned long long key = (unsigned long long)__double_as_longlong(d);
-            kmin = key < kmin ? key : kmin;
-            kmax = key > kmax ? key : kmax;
-            below += key < blo ? 1ull : 0ull;
-            inside += (key >= blo && key <= bhi) ? 1u : 0u;
-        }
-        return d;
+        upper = a < b && b < n;
+        key = (unsigned long long)__double_as_longlong(d);
+        kmin = upper && key < kmin ? key : kmin;
+        kmax = upper && key > kmax ? key : kmax;
+        return (a < n && b < n && a != b) ? d : 0.0;
     };
     double s2 = 0.0;
     if (kExp) {
@@ -216,7 +216,17 @@ __device__ __forceinline__ void gram_tile(const double *Xp, int64_t Tp, const do
 #pragma unroll
             for (int rr = 0; rr < MfmaF64::R; ++rr) {
                 const int r = GramCore::row_of(a, rr), c = GramCore::col_of(b);
-                double v = f(r, c, g.acc[a][b][rr], sa[a][rr], sb[b]);
+                bool upper;
+                unsigned long long key;
+                double v = f(r, c, g.acc[a][b][rr], sa[a][rr], sb[b], upper, key);
+                if (brbuf) {   // count below; append inside at the wave's ballot positions
+                    below += upper && key < blo ? 1u : 0u;
+                    const bool in = upper && key >= blo && key <= bhi;
+                    const unsigned long long m = __ballot(in);
+                    const unsigned int pos = wcount + (unsigned int)__popcll(m & ltmask);
+                    if (in && pos < kSeg) seg[pos] = key;
+                    wcount += (unsigned int)__popcll(m);
+                }
                 if (kExp) {
                     const int64_t ia = m0 + r, ib = n0 + c;
                     v = (ia < n && ib < n && ia != ib) ? exp(-v / s2) : 0.0;
@@ -224,53 +234,27 @@ __device__ __forceinline__ void gram_tile(const double *Xp, int64_t Tp, const do
                 out[(m0 + r) * ld + n0 + c] = v;
             }
     if (brbuf) {
-        // each thread's place in the stage: a prefix sum over the wave, one
-        // LDS atomic per wave; then its bracket keys again, into the stage
-        const int lane = threadIdx.x & 63;
-        unsigned int incl = inside;
+        // each wave's segment behind one global atomic (a full segment marks
+        // the buffer full: the passes then take the matrix); the count below
+        // behind one atomic per tile
+        unsigned long long base = 0ull;
+        if (lane == 0 && wcount > 0)
+            base = atomicAdd(&st->nbuf, wcount > kSeg ? (unsigned long long)brcap + 1ull
+                                                      : (unsigned long long)wcount);
+        base = __shfl(base, 0);
+        if (wcount <= kSeg)
+            for (unsigned int q = lane; q < wcount; q += 64)
+                if (base + q < (unsigned long long)brcap) brbuf[base + q] = seg[q];
+        unsigned long long bw = below;
 #pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const unsigned int x = (unsigned int)__shfl_up((int)incl, o);
-            if (lane >= o) incl += x;
-        }
-        unsigned int wbase = 0;
-        if (lane == 63 && incl > 0) wbase = atomicAdd(&scnt, incl);
-        unsigned int off = (unsigned int)__shfl((int)wbase, 63) + incl - inside;
-#pragma unroll
-        for (int a = 0; a < GramCore::WTM; ++a)
-#pragma unroll
-            for (int b = 0; b < GramCore::WTN; ++b)
-#pragma unroll
-                for (int rr = 0; rr < MfmaF64::R; ++rr) {
-                    const int64_t ia = m0 + GramCore::row_of(a, rr), ib = n0 + GramCore::col_of(b);
-                    double d = sa[a][rr] + sb[b] - 2.0 * g.acc[a][b][rr];
-                    d = d < 0.0 ? 0.0 : d;
-                    const unsigned long long key = (unsigned long long)__double_as_longlong(d);
-                    if (ia < ib && ib < n && key >= blo && key <= bhi) {
-                        if (off < kStage) stage[off] = key;
-                        ++off;
-                    }
-                }
-        // the stage behind one global atomic, the count below
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) below += __shfl_xor(below, o);
-        if (lane == 0) sbel[threadIdx.x >> 6] = below;
+        for (int o = 32; o >= 1; o >>= 1) bw += __shfl_xor(bw, o);
+        if (lane == 0) sbel[wid] = bw;
         __syncthreads();
-        const unsigned int c = scnt;
         if (threadIdx.x == 0) {
             unsigned long long bl = 0ull;
 #pragma unroll
             for (int w = 0; w < GramCore::NT / 64; ++w) bl += sbel[w];
             if (bl) atomicAdd(&st->below, bl);
-            // a full stage: mark the buffer full (the passes then take the matrix)
-            sbase = c > kStage ? atomicAdd(&st->nbuf, (unsigned long long)brcap + 1ull)
-                               : (c > 0 ? atomicAdd(&st->nbuf, (unsigned long long)c) : 0ull);
-        }
-        __syncthreads();
-        if (c <= kStage) {
-            const unsigned long long base = sbase;
-            for (unsigned int q = threadIdx.x; q < c; q += GramCore::NT)
-                if (base + q < (unsigned long long)brcap) brbuf[base + q] = stage[q];
         }
     }
     if (st) {
