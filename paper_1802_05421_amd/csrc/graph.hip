@@ -190,18 +190,23 @@ __device__ __forceinline__ void gram_tile(const double *Xp, int64_t Tp, const do
         for (int rr = 0; rr < MfmaF64::R; ++rr) sa[a][rr] = sqn[m0 + GramCore::row_of(a, rr)];
 #pragma unroll
     for (int b = 0; b < GramCore::WTN; ++b) sb[b] = sqn[n0 + GramCore::col_of(b)];
-    // D2 of element (r, c) (zero outside n and on the diagonal), without
-    // branches; upper: an upper-triangle pair inside n, whose key d2 is
+    // D2 of element (r, c) (zero outside n and on the diagonal); upper: an
+    // upper-triangle pair inside n, whose key is set
     auto f = [&](int r, int c, double acc, double sqa, double sqb, bool &upper,
                  unsigned long long &key) -> double {
         const int64_t a = m0 + r, b = n0 + c;
+        upper = false;
+        key = 0ull;
+        if (a >= n || b >= n || a == b) return 0.0;
         double d = sqa + sqb - 2.0 * acc;
         d = d < 0.0 ? 0.0 : d;
-        upper = a < b && b < n;
-        key = (unsigned long long)__double_as_longlong(d);
-        kmin = upper && key < kmin ? key : kmin;
-        kmax = upper && key > kmax ? key : kmax;
-        return (a < n && b < n && a != b) ? d : 0.0;
+        if (a < b) {
+            key = (unsigned long long)__double_as_longlong(d);
+            kmin = key < kmin ? key : kmin;
+            kmax = key > kmax ? key : kmax;
+            upper = true;
+        }
+        return d;
     };
     double s2 = 0.0;
     if (kExp) {
