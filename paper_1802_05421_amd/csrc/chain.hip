@@ -379,6 +379,8 @@ __global__ __launch_bounds__((SqCfg<T, NW, SH>::Core::NT)) void k_square_part(co
 
 // One workgroup per tile of the split round: the partial tiles summed in
 // split order into the accumulator layout of the core, then the epilogue.
+// Loads go out sixteen elements by four splits at a time, so a thread has
+// 64 in flight instead of one round trip per element and split.
 template <typename T, int NW, int SH>
 __global__ __launch_bounds__((SqCfg<T, NW, SH>::Core::NT)) void k_square_tail(const T *A, const T *B, T *S2,
                                                      int64_t ld, int nt, int first, int splits,
@@ -386,24 +388,41 @@ __global__ __launch_bounds__((SqCfg<T, NW, SH>::Core::NT)) void k_square_tail(co
                                                      double *fro_part) {
     using Core = typename SqCfg<T, NW, SH>::Core;
     constexpr int TL = SqCfg<T, NW, SH>::TILE;
+    constexpr int R = Core::MF::R, E = Core::WTM * Core::WTN * R;
+    constexpr int G = 16, SB = 4;   // elements per group, splits per batch
+    static_assert(E % G == 0, "accumulator count");
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
     __shared__ double red[Core::NT / 64];
     const int id = first + blockIdx.x;
     int I, J;
     sym_tile<8>(id, nt, I, J);
     Core g;
-    const float *Pt = P + (size_t)blockIdx.x * splits * TL * TL;
-    int e = 0;
+    const float *Pt = P + (size_t)blockIdx.x * splits * TL * TL + threadIdx.x;
 #pragma unroll
-    for (int i = 0; i < Core::WTM; ++i)
+    for (int e0 = 0; e0 < E; e0 += G) {
+        float v[G];
 #pragma unroll
-        for (int j = 0; j < Core::WTN; ++j)
+        for (int q = 0; q < G; ++q) v[q] = 0.f;
+        for (int sp0 = 0; sp0 < splits; sp0 += SB) {
+            float w[SB][G];
 #pragma unroll
-            for (int r = 0; r < Core::MF::R; ++r, ++e) {
-                float v = 0.f;
-                for (int sp = 0; sp < splits; ++sp) v += Pt[(size_t)sp * TL * TL + (size_t)e * Core::NT + threadIdx.x];
-                g.acc[i][j][r] = v;
-            }
+            for (int u = 0; u < SB; ++u)
+                if (sp0 + u < splits)
+#pragma unroll
+                    for (int q = 0; q < G; ++q)
+                        w[u][q] = Pt[(size_t)(sp0 + u) * TL * TL + (size_t)(e0 + q) * Core::NT];
+#pragma unroll
+            for (int u = 0; u < SB; ++u)
+                if (sp0 + u < splits)
+#pragma unroll
+                    for (int q = 0; q < G; ++q) v[q] += w[u][q];
+        }
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            const int e = e0 + q, r = e % R, ij = e / R;
+            g.acc[ij / Core::WTN][ij % Core::WTN][r] = v[q];
+        }
+    }
     square_epilogue<T>(g, A, B, S2, ld, (int64_t)I * TL, (int64_t)J * TL, I != J, inv_scale, add,
                        fro_part + id, (T *)smem_raw, red);
 }

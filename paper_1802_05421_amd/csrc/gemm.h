@@ -1,15 +1,19 @@
-// Generic LDS-tiled MFMA core for C = A * B^T (both operands row-major along
-// the reduction index k), used by every dense contraction of the path:
-// kernel-distance Gram, chain squarings, chain application, FP64 residual
-// and the score Gram.  Callers supply padded operands (K a multiple of BK,
-// tile rows inside the allocation), so the core has no bounds checks.
+// Generic LDS-tiled MFMA core for C = A * B^T (A row-major along the
+// reduction index k; B row-major along k, or with BT = true row-major along
+// n, i.e. element (n, k) at B[k * ldb + n]), used by every dense contraction
+// of the path: kernel-distance Gram, chain squarings, chain application,
+// FP64 residual and the score Gram.  BT reads a k-tile of B as BK rows of BN
+// contiguous elements (1 KB segments for 128 doubles) instead of BN rows of
+// BK; for a symmetric B both forms multiply the same values in the same
+// order.  Callers supply padded operands (K a multiple of BK, tile rows
+// inside the allocation), so the core has no bounds checks.
 #pragma once
 
 #include "common.h"
 
 namespace cdl {
 
-template <class Mf, int BM, int BN, int BK, int WM, int WN>
+template <class Mf, int BM, int BN, int BK, int WM, int WN, bool BT = false>
 struct GemmCore {
     using T = typename Mf::T;
     using Frag = typename Mf::Frag;
@@ -24,9 +28,14 @@ struct GemmCore {
     static constexpr int B_CH = BN * CPR / NT;
     static constexpr int WTM = BM / WM / Mf::M;
     static constexpr int WTN = BN / WN / Mf::M;
-    static constexpr int STAGE = (BM + BN) * LDSK;      // elements per LDS stage
+    // BT: B's k-tile as BK rows of BN (+ pad: consecutive k rows start 32
+    // banks apart, so the four k rows of a fragment read hit disjoint banks)
+    static constexpr int LDSN = BN + 16;
+    static constexpr int CPN = BN / CE;                 // chunks per B^T tile row
+    static constexpr int STAGE = BM * LDSK + (BT ? BK * LDSN : BN * LDSK);   // elements per stage
     static constexpr size_t SMEM = 2 * (size_t)STAGE * sizeof(T);
     static_assert(BM * CPR % NT == 0 && BN * CPR % NT == 0, "tile/thread mismatch");
+    static_assert(!BT || (Mf::E == 1 && BN % CE == 0), "B^T tiles need one k per fragment");
     static_assert(WTM >= 1 && WTN >= 1, "wave tile too small");
     static_assert(BK % Mf::KI == 0 && BK % CE == 0, "bad BK");
 
@@ -52,8 +61,13 @@ struct GemmCore {
         }
 #pragma unroll
         for (int c = 0; c < B_CH; ++c) {
-            int ch = tid + c * NT, row = ch / CPR, kc = ch % CPR;
-            rb[c] = *(const uint4 *)(B + (n0 + row) * ldb + k0 + kc * CE);
+            if (BT) {
+                int ch = tid + c * NT, row = ch / CPN, nc = ch % CPN;
+                rb[c] = *(const uint4 *)(B + (k0 + row) * ldb + n0 + nc * CE);
+            } else {
+                int ch = tid + c * NT, row = ch / CPR, kc = ch % CPR;
+                rb[c] = *(const uint4 *)(B + (n0 + row) * ldb + k0 + kc * CE);
+            }
         }
     }
 
@@ -67,8 +81,13 @@ struct GemmCore {
         }
 #pragma unroll
         for (int c = 0; c < B_CH; ++c) {
-            int ch = tid + c * NT, row = ch / CPR, kc = ch % CPR;
-            *(uint4 *)(sB + row * LDSK + kc * CE) = rb[c];
+            if (BT) {
+                int ch = tid + c * NT, row = ch / CPN, nc = ch % CPN;
+                *(uint4 *)(sB + row * LDSN + nc * CE) = rb[c];
+            } else {
+                int ch = tid + c * NT, row = ch / CPR, kc = ch % CPR;
+                *(uint4 *)(sB + row * LDSK + kc * CE) = rb[c];
+            }
         }
     }
 
@@ -76,7 +95,7 @@ struct GemmCore {
         const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
         const int wm = wid % WM, wn = wid / WM;
         const T *sA = s + (wm * WTM * Mf::M) * LDSK;
-        const T *sB = s + BM * LDSK + (wn * WTN * Mf::M) * LDSK;
+        const T *sB = s + BM * LDSK + (wn * WTN * Mf::M) * (BT ? 1 : LDSK);
         const int fr = lane % Mf::M, fk = Mf::E * (lane / Mf::M);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += Mf::KI) {
@@ -86,7 +105,8 @@ struct GemmCore {
                 a[i] = *(const Frag *)(sA + (i * Mf::M + fr) * LDSK + kk + fk);
 #pragma unroll
             for (int j = 0; j < WTN; ++j)
-                b[j] = *(const Frag *)(sB + (j * Mf::M + fr) * LDSK + kk + fk);
+                b[j] = BT ? *(const Frag *)(sB + (kk + fk) * LDSN + j * Mf::M + fr)
+                          : *(const Frag *)(sB + (j * Mf::M + fr) * LDSK + kk + fk);
 #pragma unroll
             for (int i = 0; i < WTM; ++i)
 #pragma unroll

@@ -1010,13 +1010,16 @@ int sym_tiles64(int64_t ld) {
 
 // One 64 x 64 tile (I <= J) per workgroup.  part[J][i] receives the sum of
 // row i over the tile's columns and, for I < J, part[I][j] the sum of column
-// j: every (tile column, node) slot is written by exactly one tile.  Lane =
-// column, so every global access of a wave is one contiguous 512-byte row
-// segment; the four waves take 16 rows each.
+// j: every (tile column, node) slot is written by exactly one tile.  A lane
+// takes two adjacent columns of every other row (16-byte loads and stores),
+// so a wave access covers two contiguous 512-byte row segments; the four
+// waves take 16 rows each.  The mirror is written from the LDS copy, two
+// adjacent rows per lane.
 // Upper tile `id` (after the XCD remap) of the sym_tile<8> order.
 __device__ __forceinline__ void exp_sym_tile(double *W, int64_t ld, int64_t n,
                                              const double *stats, int nt, double *part, int id) {
-    __shared__ double t[64][65];
+    struct alignas(16) D2 { double x, y; };
+    __shared__ double t[64][66];   // even pitch: 16-byte rows of pairs
     __shared__ double cs[4][64];
     int I, J;
     sym_tile<8>(id, nt, I, J);
@@ -1024,21 +1027,31 @@ __device__ __forceinline__ void exp_sym_tile(double *W, int64_t ld, int64_t n,
     const double s2 = sigma * sigma;
     const int64_t i0 = (int64_t)I * 64, j0 = (int64_t)J * 64;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t j = j0 + lane;
-    double csum = 0.0;
-    double d2[16];   // all sixteen row loads in flight before the first exp
+    const int cp = lane & 31, h = lane >> 5;
+    const int64_t ja = j0 + 2 * cp;   // this lane's columns ja, ja + 1
+    double c0 = 0.0, c1 = 0.0;
+    D2 d2[8];   // all eight row loads in flight before the first exp
 #pragma unroll
-    for (int rr = 0; rr < 16; ++rr) d2[rr] = W[(i0 + wv * 16 + rr) * ld + j];
+    for (int rr = 0; rr < 8; ++rr) d2[rr] = *(const D2 *)(W + (i0 + wv * 16 + 2 * rr + h) * ld + ja);
 #pragma unroll
-    for (int rr = 0; rr < 16; ++rr) {
-        const int r = wv * 16 + rr;
+    for (int rr = 0; rr < 8; ++rr) {
+        const int r = wv * 16 + 2 * rr + h;
         const int64_t i = i0 + r;
-        const double v = (i < n && j < n && i != j) ? exp(-d2[rr] / s2) : 0.0;
-        W[i * ld + j] = v;
-        t[r][lane] = v;
-        csum += v;
+        D2 v;
+        v.x = (i < n && ja < n && i != ja) ? exp(-d2[rr].x / s2) : 0.0;
+        v.y = (i < n && ja + 1 < n && i != ja + 1) ? exp(-d2[rr].y / s2) : 0.0;
+        *(D2 *)(W + i * ld + ja) = v;
+        *(D2 *)&t[r][2 * cp] = v;
+        c0 += v.x;
+        c1 += v.y;
     }
-    cs[wv][lane] = csum;
+    // this wave's column sums: the two halves hold the even and odd rows
+    c0 += __shfl_xor(c0, 32);
+    c1 += __shfl_xor(c1, 32);
+    if (h == 0) {
+        cs[wv][2 * cp] = c0;
+        cs[wv][2 * cp + 1] = c1;
+    }
     __syncthreads();
     {   // row sums: thread (row r, quarter q) over 16 columns
         const int r = threadIdx.x >> 2, q = threadIdx.x & 3;
@@ -1054,9 +1067,10 @@ __device__ __forceinline__ void exp_sym_tile(double *W, int64_t ld, int64_t n,
         part[(int64_t)I * ld + j0 + threadIdx.x] =
             (cs[0][threadIdx.x] + cs[1][threadIdx.x]) + (cs[2][threadIdx.x] + cs[3][threadIdx.x]);
 #pragma unroll 4
-    for (int cc = 0; cc < 16; ++cc) {   // mirror: row j0 + c gets column c of the tile
-        const int c = wv * 16 + cc;
-        W[(j0 + c) * ld + i0 + lane] = t[lane][c];
+    for (int cc = 0; cc < 8; ++cc) {   // mirror: row j0 + c gets column c of the tile
+        const int c = wv * 16 + 2 * cc + h;
+        const D2 m{t[2 * cp][c], t[2 * cp + 1][c]};
+        *(D2 *)(W + (j0 + c) * ld + i0 + 2 * cp) = m;
     }
 }
 

@@ -414,18 +414,20 @@ hipError_t launch_rhs(const double *W, int64_t ld, int64_t n, const int32_t *gid
 // P[s][r][i] = sum_{j in split s} Xt[r][j] W[i][j] followed by a reduction
 // that forms R, the next preconditioner operand and the column-norm partials.
 
-template <int BM> struct ResCfg {
+// BT: W is the whole symmetric matrix, read along its rows as W^T (k-tiles of
+// 16 rows x 128 contiguous columns); row panels are read as they are.
+template <int BM, bool BT = false> struct ResCfg {
     static constexpr int WM = BM / 64, WN = 8 / (BM / 64);
-    using Core = GemmCore<MfmaF64, BM, 128, 16, WM, WN>;
+    using Core = GemmCore<MfmaF64, BM, 128, 16, WM, WN, BT>;
 };
 
 // W may be a row panel: its row q holds node row0 + q, whose products land in
 // column row0 + q of the partials (row0 = 0 for the whole matrix).
-template <int BM>
+template <int BM, bool BT>
 __device__ __forceinline__ void residual_gemm_tile(const double *Xt, const double *W, int64_t ld,
                                           int64_t kend, int64_t ks, int mt, int nt, double *P,
                                           int64_t kpad, int64_t row0, int id, char *smem_raw) {
-    using Core = typename ResCfg<BM>::Core;
+    using Core = typename ResCfg<BM, BT>::Core;
     double *smem = (double *)smem_raw;
     // split-major order: the WGs of one split stream the same K range
     const int split = id / (mt * nt);
@@ -435,7 +437,7 @@ __device__ __forceinline__ void residual_gemm_tile(const double *Xt, const doubl
     const int64_t k0 = (int64_t)split * ks;
     const int64_t kk = k0 < kend ? (kend - k0 < ks ? kend - k0 : ks) : 0;
     Core g;
-    g.run(Xt + k0, ld, W + k0, ld, m0, n0, kk, smem);
+    g.run(Xt + k0, ld, BT ? W + k0 * ld : W + k0, ld, m0, n0, kk, smem);
     double *Ps = P + (int64_t)split * kpad * ld + row0;
 #pragma unroll
     for (int a = 0; a < Core::WTM; ++a)
@@ -446,14 +448,14 @@ __device__ __forceinline__ void residual_gemm_tile(const double *Xt, const doubl
                 Ps[(m0 + Core::row_of(a, rr)) * ld + n0 + Core::col_of(b)] = g.acc[a][b][rr];
 }
 
-template <int BM>
+template <int BM, bool BT>
 __global__ __launch_bounds__(512) void k_residual_gemm(const double *Xt, const double *W,
                                                        int64_t ld, int64_t kend, int64_t ks,
                                                        int mt, int nt, int S, double *P,
                                                        int64_t kpad, int64_t row0) {
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
     const int id = xcd_remap(blockIdx.x, mt * nt * S);
-    residual_gemm_tile<BM>(Xt, W, ld, kend, ks, mt, nt, P, kpad, row0, id, smem_raw);
+    residual_gemm_tile<BM, BT>(Xt, W, ld, kend, ks, mt, nt, P, kpad, row0, id, smem_raw);
 }
 
 static int res_bm(int64_t kpad) { return kpad % 256 == 0 ? 256 : (kpad % 128 == 0 ? 128 : 64); }
@@ -488,10 +490,10 @@ int residual_splits(int64_t ld, int64_t kpad, int64_t n, int choice) {
 template <int BM>
 static hipError_t resg_launch(const double *Xt, const double *W, int64_t ld, int64_t n,
                               int64_t kpad, int S, double *P, hipStream_t s) {
-    using Core = typename ResCfg<BM>::Core;
+    using Core = typename ResCfg<BM, true>::Core;
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_residual_gemm<BM>,
+        hipError_t e = hipFuncSetAttribute((const void *)k_residual_gemm<BM, true>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)Core::SMEM);
         if (e != hipSuccess) return e;
@@ -500,7 +502,7 @@ static hipError_t resg_launch(const double *Xt, const double *W, int64_t ld, int
     const int mt = (int)(kpad / BM), nt = (int)(ld / 128);
     const int64_t kend = (n + 63) / 64 * 64;
     const int64_t ks = (cdiv(kend, S) + 15) / 16 * 16;
-    hipLaunchKernelGGL(k_residual_gemm<BM>, dim3(mt * nt * S), dim3(512), Core::SMEM, s, Xt, W,
+    hipLaunchKernelGGL((k_residual_gemm<BM, true>), dim3(mt * nt * S), dim3(512), Core::SMEM, s, Xt, W,
                        ld, kend, ks, mt, nt, S, P, kpad, (int64_t)0);
     return hipGetLastError();
 }
@@ -509,10 +511,10 @@ template <int BM>
 static hipError_t panel_launch(const double *Vt, const double *Wp, int64_t ld, int64_t n,
                                int64_t kpad, int64_t row0, int64_t rows, double *Prod,
                                hipStream_t s) {
-    using Core = typename ResCfg<BM>::Core;
+    using Core = typename ResCfg<BM, false>::Core;
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_residual_gemm<BM>,
+        hipError_t e = hipFuncSetAttribute((const void *)k_residual_gemm<BM, false>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)Core::SMEM);
         if (e != hipSuccess) return e;
@@ -521,7 +523,7 @@ static hipError_t panel_launch(const double *Vt, const double *Wp, int64_t ld, i
     const int mt = (int)(kpad / BM), nt = (int)(rows / 128);
     const int64_t kend = (n + 63) / 64 * 64;
     const int64_t ks = (kend + 15) / 16 * 16;
-    hipLaunchKernelGGL(k_residual_gemm<BM>, dim3(mt * nt), dim3(512), Core::SMEM, s, Vt, Wp, ld,
+    hipLaunchKernelGGL((k_residual_gemm<BM, false>), dim3(mt * nt), dim3(512), Core::SMEM, s, Vt, Wp, ld,
                        kend, ks, mt, nt, 1, Prod, kpad, row0);
     return hipGetLastError();
 }
@@ -790,7 +792,7 @@ __global__ __launch_bounds__(512) void k_residual_gemm_grouped(const BatchSnap *
     const BatchSnap &d = snaps[p];
     const int mt = (int)(kpad / BM), nt = (int)(d.ld / 128);
     const int id = xcd_remap(blockIdx.x - prefix[p], prefix[p + 1] - prefix[p]);
-    residual_gemm_tile<BM>(d.Xt, d.W, d.ld, (d.n + 63) / 64 * 64, residual_split_len(d.n, d.res_splits),
+    residual_gemm_tile<BM, true>(d.Xt, d.W, d.ld, (d.n + 63) / 64 * 64, residual_split_len(d.n, d.res_splits),
                            mt, nt, d.Pres, kpad, 0, id, smem_raw);
 }
 
@@ -816,7 +818,7 @@ __global__ __launch_bounds__(256) void k_residual_reduce_grouped(const BatchSnap
 template <int BM>
 static hipError_t resg_grouped_launch(const BatchSnap *snaps, const int *prefix, int total, int P,
                                       int64_t kpad, const int *done, hipStream_t s) {
-    using Core = typename ResCfg<BM>::Core;
+    using Core = typename ResCfg<BM, true>::Core;
     static bool attr = false;
     if (!attr) {
         hipError_t e = hipFuncSetAttribute((const void *)k_residual_gemm_grouped<BM>,
