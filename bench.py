@@ -91,6 +91,52 @@ def vendor_gemm(torch, p, n, reps=5):
             "flop_per_launch": 2.0 * float(n) ** 3}
 
 
+def vendor_gemm_residual(torch, W, k, reps=5):
+    """The vendor library's FP64 GEMM of the residual product's shape: a k x m
+    operand times the m x m weight matrix (torch.matmul, the padded matrix of
+    the timed step's first snapshot), timed with events: the attainable mark
+    for the FP64 residual on the same box."""
+    m = W.shape[0]
+    g = torch.Generator(device="cuda:0").manual_seed(6)
+    xt = torch.rand(k, m, device="cuda:0", dtype=torch.float64, generator=g)
+    c = torch.matmul(xt, W)                                      # warm-up (algorithm choice)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        c = torch.matmul(xt, W)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    tf = 2.0 * k * float(m) ** 2 / (ms * 1e-3) / 1e12
+    del xt, c
+    return {"ms": round(ms, 4), "achieved_tflops": round(tf, 1), "frac_of_peak": round(tf / (PEAK["fp64_mfma"] / 1e12), 4),
+            "shape": [k, m, m]}
+
+
+def vendor_gemm_apply(torch, p, m, k, reps=10):
+    """The vendor library's 16-bit GEMM of one chain application's shape (an
+    m x m level times an m x k operand, and the transposed orientation k x m
+    times m x m; torch.matmul), timed with events."""
+    dt = torch.bfloat16 if p == "bf16" else torch.float16
+    g = torch.Generator(device="cuda:0").manual_seed(7)
+    a = torch.rand(m, m, device="cuda:0", dtype=dt, generator=g)
+    x = torch.rand(m, k, device="cuda:0", dtype=dt, generator=g)
+    xt = x.t().contiguous()
+    out = {}
+    for name, f in (("level_x_operand", lambda: torch.matmul(a, x)),
+                    ("operand_t_x_level", lambda: torch.matmul(xt, a))):
+        c = f()                                                  # warm-up (algorithm choice)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            c = f()
+        e1.record()
+        e1.synchronize()
+        out[name + "_ms"] = round(e0.elapsed_time(e1) / reps, 4)
+    del a, x, xt, c
+    return out
+
+
 def copy_bandwidth(cdl, torch, reps):
     """GB/s of cdl.device_copy over 1 GiB (read + write bytes / event time)."""
     src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
@@ -576,6 +622,14 @@ def main():
 
     # dominant kernel of the mixed step, timed live over the timed steps
     roof = roofline(times_mixed, dom, n, k, T, args.mixed, load_traffic(dom))
+    if dom == "residual":
+        roof["vendor_gemm"] = vendor_gemm_residual(torch, graphs[0].W, (k + 63) // 64 * 64)
+    # one chain application of the mixed type against the vendor GEMM of its shape
+    apply_ref = None
+    if args.mixed in ("fp16", "bf16"):
+        tuned_apply = cdl.autotune_lookup("apply", args.mixed, n, k)
+        apply_ref = {"tuned_ms": None if tuned_apply is None else round(tuned_apply[2], 4),
+                     "vendor": vendor_gemm_apply(torch, args.mixed, m, (k + 63) // 64 * 64)}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -612,6 +666,7 @@ def main():
         "streamed": streamed,
         "cpu_baseline": cpu,
         "autotune": autotune_report(cdl, precs, n, k),
+        "apply_vs_vendor": apply_ref,
     }
     print(json.dumps(out), flush=True)
 
