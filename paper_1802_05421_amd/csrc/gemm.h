@@ -29,7 +29,8 @@ struct GemmCore {
     static constexpr int WTM = BM / WM / Mf::M;
     static constexpr int WTN = BN / WN / Mf::M;
     // BT: B's k-tile as BK rows of BN (+ pad: consecutive k rows start 32
-    // banks apart, so the four k rows of a fragment read hit disjoint banks)
+    // banks apart, so the two k rows that one half-wave of a fragment read
+    // takes, 16 consecutive doubles each, cover the 64 banks once)
     static constexpr int LDSN = BN + 16;
     static constexpr int CPN = BN / CE;                 // chunks per B^T tile row
     static constexpr int STAGE = BM * LDSK + (BT ? BK * LDSN : BN * LDSK);   // elements per stage
