@@ -126,8 +126,13 @@ hipError_t launch_pad_series(const double *X, int64_t n, int64_t T, int64_t ldx,
 // ---------------------------------------------------------------------------
 // Squared distances from the Gram matrix of the series (FP64 MFMA).
 
-// 256 x 128 tiles (each wave 64 x 64: 16 MFMAs per 8 fragment reads), BK 16.
-using GramCore = GemmCore<MfmaF64, 256, 128, 16, 4, 2>;
+// The cover is made of 256 x 128 tiles; each is computed as two 128 x 128
+// halves by two workgroups of four waves (each wave 64 x 64: 16 MFMAs per 8
+// fragment reads), BK 16.  A half takes 74 KB of LDS, so two workgroups fit
+// on a CU and one's epilogue (distances, median bracket, stores) runs beside
+// the other's MFMAs.
+using GramCore = GemmCore<MfmaF64, 128, 128, 16, 2, 2>;
+constexpr int kGramWgPerTile = 2;
 constexpr size_t kGramSmem = GramCore::SMEM;
 
 
@@ -155,14 +160,16 @@ __device__ __forceinline__ void gram_tile(const double *Xp, int64_t Tp, const do
                                           const double *wstats, double *smem,
                                           unsigned long long *brbuf = nullptr,
                                           int64_t brcap = 0) {
+    // workgroup id: half id & 1 (rows 128 (id & 1) ..) of tile id >> 1
+    const int tile = id >> 1, half = id & 1;
     int I, J;
     if (full) {
-        rect_tile<4>(id, pb, ncol, I, J);
+        rect_tile<4>(tile, pb, ncol, I, J);
         I += I0;
     } else {
-        upper_band_tile<4>(id, I0, pb, ncol, I, J);
+        upper_band_tile<4>(tile, I0, pb, ncol, I, J);
     }
-    const int64_t m0 = (int64_t)I * 256, n0 = (int64_t)J * 128;
+    const int64_t m0 = (int64_t)I * 256 + 128 * half, n0 = (int64_t)J * 128;
     double *const out = D2 - (int64_t)I0 * 256 * ld;
     GramCore g;
     g.run(Xp, Tp, Xp, Tp, m0, n0, Tp, smem);
@@ -290,7 +297,7 @@ __device__ __forceinline__ void gram_tile(const double *Xp, int64_t Tp, const do
 }
 
 template <bool kExp>
-__global__ __launch_bounds__(512) void k_gram_dist(const double *Xp, int64_t Tp,
+__global__ __launch_bounds__(GramCore::NT, 2) void k_gram_dist(const double *Xp, int64_t Tp,
                                                    const double *sqn, int64_t n, int64_t ld,
                                                    double *D2, int ncol, int I0, int pb,
                                                    int full, int total, SelectState *st,
@@ -323,8 +330,8 @@ hipError_t launch_gram_dist(const double *Xp, int64_t Tp, const double *sqn, int
     hipError_t e = gram_attr();
     if (e != hipSuccess) return e;
     const int ncol = (int)(ld / 128);
-    const int total = rect_upper_tiles(ld);
-    hipLaunchKernelGGL(k_gram_dist<false>, dim3(total), dim3(512), kGramSmem, s, Xp, Tp, sqn, n,
+    const int total = kGramWgPerTile * rect_upper_tiles(ld);
+    hipLaunchKernelGGL(k_gram_dist<false>, dim3(total), dim3(GramCore::NT), kGramSmem, s, Xp, Tp, sqn, n,
                        ld, D2, ncol, 0, (int)(ld / 256), 0, total, st, (const double *)nullptr,
                        brbuf, brcap);
     return hipGetLastError();
@@ -342,16 +349,16 @@ hipError_t launch_gram_panel(const double *Xp, int64_t Tp, const double *sqn, in
     if (wstats && !full) return hipErrorInvalidValue;
     hipError_t e = gram_attr();
     if (e != hipSuccess) return e;
-    const int64_t total = gram_panel_tiles(ld, row0, rows, full);
+    const int64_t total = kGramWgPerTile * gram_panel_tiles(ld, row0, rows, full);
     if (total <= 0 || total > INT32_MAX) return hipErrorInvalidValue;
     const int ncol = (int)(ld / 128), I0 = (int)(row0 / 256), pb = (int)(rows / 256);
     if (wstats)
-        hipLaunchKernelGGL(k_gram_dist<true>, dim3((unsigned)total), dim3(512), kGramSmem, s, Xp,
+        hipLaunchKernelGGL(k_gram_dist<true>, dim3((unsigned)total), dim3(GramCore::NT), kGramSmem, s, Xp,
                            Tp, sqn, n, ld, D2p, ncol, I0, pb, 1, (int)total,
                            (SelectState *)nullptr, wstats, (unsigned long long *)nullptr,
                            (int64_t)0);
     else
-        hipLaunchKernelGGL(k_gram_dist<false>, dim3((unsigned)total), dim3(512), kGramSmem, s, Xp,
+        hipLaunchKernelGGL(k_gram_dist<false>, dim3((unsigned)total), dim3(GramCore::NT), kGramSmem, s, Xp,
                            Tp, sqn, n, ld, D2p, ncol, I0, pb, full ? 1 : 0, (int)total,
                            (SelectState *)nullptr, (const double *)nullptr,
                            (unsigned long long *)nullptr, (int64_t)0);
@@ -1190,7 +1197,7 @@ int graph_table_count(int tb, int64_t n, int64_t ld, bool bracket) {
     switch (tb) {
     case kGtRows: return (int)ld;
     case kGtOne: return 1;
-    case kGtGram: return rect_upper_tiles(ld);
+    case kGtGram: return kGramWgPerTile * rect_upper_tiles(ld);
     case kGtSample: return bracket ? 1 : 0;
     case kGtKeys: return bracket ? 16 : 0;
     case kGtPass: return grid;
@@ -1243,7 +1250,7 @@ __global__ __launch_bounds__(1024) void k_select_sort_grouped(const GraphSnap *s
     select_sort_keys(d.buf, d.n, d.sel, sk);
 }
 
-__global__ __launch_bounds__(512) void k_gram_grouped(const GraphSnap *snaps, const int *prefix, int P,
+__global__ __launch_bounds__(GramCore::NT, 2) void k_gram_grouped(const GraphSnap *snaps, const int *prefix, int P,
                                                       int select) {
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
     const GroupSlot g = group_slot(prefix, P);
@@ -1332,7 +1339,7 @@ hipError_t launch_graph_grouped(const GraphSnap *snaps, const int *tables, const
         hipLaunchKernelGGL(k_select_sort_grouped, dim3(totals[kGtSample]), dim3(1024), kSelSample * 8, s,
                            snaps, tb(kGtSample), P);
     }
-    hipLaunchKernelGGL(k_gram_grouped, dim3(totals[kGtGram]), dim3(512), kGramSmem, s, snaps,
+    hipLaunchKernelGGL(k_gram_grouped, dim3(totals[kGtGram]), dim3(GramCore::NT), kGramSmem, s, snaps,
                        tb(kGtGram), P, select ? 1 : 0);
     if (select) {
         hipLaunchKernelGGL(k_select_setup_grouped, dim3(totals[kGtOne]), dim3(64), 0, s, snaps, tb(kGtOne), P);
