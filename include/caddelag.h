@@ -234,9 +234,11 @@ cdl_status cdl_timing_reset(cdl_ctx *ctx);
 /* Three kernel families have several correct launch configurations, which
  * give the same results up to the rounding order of their sums:
  *   "square"    16-bit levels (cdl_build_chain, cdl_chain_densify): 256 x 256
- *               tiles on 8 waves (choices 0, 1) or 4 waves (2, 3), the last
- *               partial round of workgroups split over the reduction
- *               (0, 2) or not (1, 3); other level types: one choice;
+ *               tiles on 8 waves with 32 x 32 x 16 MFMAs (choices 0, 1), 4
+ *               waves with 32 x 32 x 16 (2, 3) or 8 waves with 16 x 16 x 32
+ *               (4, 5); the last partial round of workgroups split over the
+ *               reduction (even choices) or not (odd); other level types:
+ *               one choice;
  *   "apply"     the chain application (cdl_solve_embedding*), BF16/FP16/FP32
  *               levels: the split-K count, the default (0), half (1) or
  *               twice (2) it; FP64 levels: one choice;
